@@ -1,0 +1,827 @@
+/*
+ * FP64 CPU oracle for the FAS multigrid Poisson solve on quadtree/octree box
+ * grids (Teunissen & Ebert, "Afivo", §2-§3).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow reference that the
+ * GPU library is checked against.  It shares no code with the GPU library,
+ * and only tests, the smoke check and the CPU-baseline leg of the benchmark
+ * may load it.
+ *
+ * Data model (paper §2.1): every box holds n^D cells plus one stored ghost
+ * layer, so each field of a box is an (n+2)^D array indexed 1..n in the
+ * interior and 0 / n+1 in the ghost layer (1-based, as the paper numbers
+ * cells).  Boxes of the tree have n = N; below the root (level 1) extra coarse
+ * grids of N/2, N/4, ..., 2 cells per side are added (paper §3.2, V-cycle).
+ *
+ * Steps, each following the paper:
+ *   fill_gc      side ghost cells: same-level copy, Dirichlet, or the default
+ *                refinement-boundary scheme (paper §2.4 and §3.3)
+ *   half_sweep   Gauss-Seidel red-black on one colour (paper §3.1)
+ *   vcycle       the FAS V-cycle (paper §3.2, eqs. residual, coarse-rhs,
+ *                coarse-corr)
+ *   fmg          the FMG cycle without an initial guess (paper §3.2)
+ *   restriction  averaging over the 2^D children (paper §2.5)
+ *   prolongation 2-1-1 interpolation (paper §2.5)
+ *
+ * Readings where the paper is silent (each also listed in the design notes):
+ *   - red cells are those whose 1-based global index sum is even;
+ *   - side ghosts are refreshed before every half sweep;
+ *   - a Dirichlet ghost is 2 b - u1 (linear through the face value b);
+ *   - Dirichlet values of non-leaf boxes are the means of their children's
+ *     face values;
+ *   - the copy v'_H includes side ghosts filled right after restriction;
+ *   - the stop test uses the max-norm of the composite leaf residual relative
+ *     to that of the zero initial guess.
+ *
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC
+ */
+#include <math.h>
+#include <omp.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_MAXLEV 40
+
+typedef struct {
+    int dim, N;
+    int lmin, lmax;
+    int nbox;
+    int *lev, *ix, *iy, *iz, *n, *parent, *leaf;
+    int *child;  /* [nbox*8], octant bits x | y<<1 | z<<2, -1 if none */
+    int *nbr;    /* [nbox*6]: >=0 same-level box, -1 physical, -2 refinement boundary */
+    int64_t *off;   /* offset of each box's padded array */
+    int64_t *bcoff; /* [nbox*6] offset into bc store, -1 if side not physical */
+    int64_t ntot, nbc;
+    double *u, *rho, *uold, *res, *bc;
+    int nleaf_in;
+    int *leaf_box; /* box id of input leaf i */
+    /* per level lists, level l stored at index l - lmin */
+    int *lvl_first[OR_MAXLEV];
+    int lvl_cnt[OR_MAXLEV];
+    int *lvl_store;
+} otree;
+
+/* ------------------------------------------------------------------------ */
+/* hash map (level, i, j, k) -> box id                                       */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    uint64_t *key;
+    int *val;
+    int64_t cap;
+} ohash;
+
+static uint64_t okey(int l, int i, int j, int k) {
+    return ((uint64_t)(l + 8) << 57) | ((uint64_t)i << 38) | ((uint64_t)j << 19) | (uint64_t)k;
+}
+static uint64_t omix(uint64_t x) {
+    x ^= x >> 33; x *= 0xff51afd7ed558ccdULL; x ^= x >> 33; x *= 0xc4ceb9fe1a85ec53ULL; x ^= x >> 33;
+    return x;
+}
+static int oh_init(ohash *h, int64_t n) {
+    h->cap = 16;
+    while (h->cap < 2 * n + 16) h->cap *= 2;
+    h->key = (uint64_t *)malloc(sizeof(uint64_t) * h->cap);
+    h->val = (int *)malloc(sizeof(int) * h->cap);
+    if (!h->key || !h->val) return -1;
+    for (int64_t i = 0; i < h->cap; i++) h->key[i] = 0;
+    return 0;
+}
+static int oh_get(const ohash *h, uint64_t k) {
+    int64_t p = (int64_t)(omix(k) & (uint64_t)(h->cap - 1));
+    while (h->key[p]) {
+        if (h->key[p] == k) return h->val[p];
+        p = (p + 1) & (h->cap - 1);
+    }
+    return -1;
+}
+static int oh_put(ohash *h, uint64_t k, int v) { /* returns existing value or -1 when inserted */
+    int64_t p = (int64_t)(omix(k) & (uint64_t)(h->cap - 1));
+    while (h->key[p]) {
+        if (h->key[p] == k) return h->val[p];
+        p = (p + 1) & (h->cap - 1);
+    }
+    h->key[p] = k;
+    h->val[p] = v;
+    return -1;
+}
+static void oh_free(ohash *h) { free(h->key); free(h->val); }
+
+/* ------------------------------------------------------------------------ */
+/* small helpers                                                             */
+/* ------------------------------------------------------------------------ */
+static int or_np(const otree *t, int b) { return t->n[b] + 2; }
+/* padded index, 1-based interior */
+static int64_t PI(const otree *t, int b, int i, int j, int k) {
+    int m = t->n[b] + 2;
+    return t->off[b] + i + (int64_t)m * (j + (int64_t)m * k);
+}
+static double level_h(const otree *t, int l) { return 1.0 / ((double)t->N * ldexp(1.0, l - 1)); }
+static int lvl_count(const otree *t, int l) { return t->lvl_cnt[l - t->lmin]; }
+static int lvl_box(const otree *t, int l, int m) { return t->lvl_first[l - t->lmin][m]; }
+
+/* offset (0-based, in parent cells) of box b inside its parent along axis d */
+static int child_offset(const otree *t, int b, int d) {
+    if (t->lev[b] <= 1) return 0; /* root and coarse grids cover their parent fully */
+    int id = d == 0 ? t->ix[b] : (d == 1 ? t->iy[b] : t->iz[b]);
+    return ((id - 1) & 1) * (t->n[b] / 2);
+}
+
+static char or_errbuf[512];
+static void seterr(char *err, int errlen, const char *msg) {
+    snprintf(or_errbuf, sizeof(or_errbuf), "%s", msg);
+    if (err && errlen > 0) snprintf(err, (size_t)errlen, "%s", msg);
+}
+
+/* ------------------------------------------------------------------------ */
+/* tree construction from a leaf list                                        */
+/* ------------------------------------------------------------------------ */
+void or_tree_free(void *p);
+
+void *or_tree_new(int dim, int N, int64_t n_leaves, const int32_t *level, const int32_t *idx,
+                  char *err, int errlen) {
+    if (dim != 2 && dim != 3) { seterr(err, errlen, "dim must be 2 or 3"); return NULL; }
+    if (N < 2 || (N & (N - 1))) { seterr(err, errlen, "N must be a power of two >= 2"); return NULL; }
+    if (n_leaves <= 0) { seterr(err, errlen, "no leaves"); return NULL; }
+    int lg = 0;
+    while ((2 << lg) < N) lg++; /* N = 2^(lg+1) */
+    otree *t = (otree *)calloc(1, sizeof(otree));
+    t->dim = dim;
+    t->N = N;
+    t->lmin = 1 - lg;
+    t->lmax = 1;
+    ohash h;
+    int64_t cap = n_leaves * 2 + 64;
+    if (oh_init(&h, cap) != 0) { free(t); seterr(err, errlen, "out of memory"); return NULL; }
+    /* provisional arrays */
+    int *L = (int *)malloc(sizeof(int) * cap), *I = (int *)malloc(sizeof(int) * cap),
+        *J = (int *)malloc(sizeof(int) * cap), *K = (int *)malloc(sizeof(int) * cap),
+        *isleaf = (int *)malloc(sizeof(int) * cap);
+    int nb = 0;
+    for (int64_t q = 0; q < n_leaves; q++) {
+        int l = level[q], i = idx[3 * q], j = idx[3 * q + 1], k = dim == 3 ? idx[3 * q + 2] : 1;
+        if (l < 1 || l > 18) { seterr(err, errlen, "leaf level out of range [1,18]"); goto fail; }
+        int n1 = 1 << (l - 1);
+        if (i < 1 || i > n1 || j < 1 || j > n1 || k < 1 || k > (dim == 3 ? n1 : 1)) {
+            seterr(err, errlen, "leaf spatial index out of range"); goto fail;
+        }
+        if (oh_put(&h, okey(l, i, j, k), nb) >= 0) { seterr(err, errlen, "duplicate leaf"); goto fail; }
+        L[nb] = l; I[nb] = i; J[nb] = j; K[nb] = k; isleaf[nb] = 1;
+        nb++;
+        if (l > t->lmax) t->lmax = l;
+    }
+    /* ancestors */
+    for (int q = 0; q < (int)n_leaves; q++) {
+        int l = L[q], i = I[q], j = J[q], k = K[q];
+        while (l > 1) {
+            l--; i = (i + 1) / 2; j = (j + 1) / 2; k = dim == 3 ? (k + 1) / 2 : 1;
+            if (nb >= cap) {
+                cap *= 2;
+                L = realloc(L, sizeof(int) * cap); I = realloc(I, sizeof(int) * cap);
+                J = realloc(J, sizeof(int) * cap); K = realloc(K, sizeof(int) * cap);
+                isleaf = realloc(isleaf, sizeof(int) * cap);
+                ohash h2; oh_init(&h2, cap);
+                for (int64_t p = 0; p < h.cap; p++) if (h.key[p]) oh_put(&h2, h.key[p], h.val[p]);
+                oh_free(&h); h = h2;
+            }
+            int ex = oh_put(&h, okey(l, i, j, k), nb);
+            if (ex >= 0) {
+                if (isleaf[ex]) { seterr(err, errlen, "a leaf overlaps a finer leaf"); goto fail; }
+                break;
+            }
+            L[nb] = l; I[nb] = i; J[nb] = j; K[nb] = k; isleaf[nb] = 0;
+            nb++;
+        }
+    }
+    /* final numbering: coarse grids first (levels lmin..0), then tree boxes in
+       the provisional order, grouped by level */
+    int ncoarse = 1 - t->lmin;
+    t->nbox = nb + ncoarse;
+    int B = t->nbox;
+    t->lev = malloc(sizeof(int) * B); t->ix = malloc(sizeof(int) * B); t->iy = malloc(sizeof(int) * B);
+    t->iz = malloc(sizeof(int) * B); t->n = malloc(sizeof(int) * B); t->parent = malloc(sizeof(int) * B);
+    t->leaf = malloc(sizeof(int) * B); t->child = malloc(sizeof(int) * B * 8);
+    t->nbr = malloc(sizeof(int) * B * 6); t->off = malloc(sizeof(int64_t) * B);
+    t->bcoff = malloc(sizeof(int64_t) * B * 6);
+    int *newid = malloc(sizeof(int) * nb);
+    int pos = 0;
+    for (int l = t->lmin; l <= 0; l++) {
+        t->lev[pos] = l; t->ix[pos] = t->iy[pos] = t->iz[pos] = 1;
+        t->n[pos] = N >> (1 - l); t->leaf[pos] = 0;
+        pos++;
+    }
+    for (int l = 1; l <= t->lmax; l++)
+        for (int q = 0; q < nb; q++)
+            if (L[q] == l) {
+                newid[q] = pos;
+                t->lev[pos] = l; t->ix[pos] = I[q]; t->iy[pos] = J[q]; t->iz[pos] = K[q];
+                t->n[pos] = N; t->leaf[pos] = isleaf[q];
+                pos++;
+            }
+    for (int64_t p = 0; p < h.cap; p++) if (h.key[p]) h.val[p] = newid[h.val[p]];
+    t->nleaf_in = (int)n_leaves;
+    t->leaf_box = malloc(sizeof(int) * n_leaves);
+    for (int q = 0; q < (int)n_leaves; q++) t->leaf_box[q] = newid[q];
+    free(newid);
+    /* parents / children */
+    int nch = 1 << dim;
+    for (int b = 0; b < B; b++) {
+        for (int c = 0; c < 8; c++) t->child[8 * b + c] = -1;
+        t->parent[b] = -1;
+    }
+    for (int b = 0; b < B; b++) {
+        int l = t->lev[b];
+        if (l <= 1) {
+            t->parent[b] = l > t->lmin ? (l - 1 - t->lmin) : -1; /* coarse grid box ids are l - lmin */
+            if (t->parent[b] >= 0) t->child[8 * t->parent[b]] = b;
+            continue;
+        }
+        int pi = (t->ix[b] + 1) / 2, pj = (t->iy[b] + 1) / 2, pk = dim == 3 ? (t->iz[b] + 1) / 2 : 1;
+        int p = oh_get(&h, okey(l - 1, pi, pj, pk));
+        t->parent[b] = p;
+        int oc = ((t->ix[b] - 1) & 1) | (((t->iy[b] - 1) & 1) << 1) | (dim == 3 ? (((t->iz[b] - 1) & 1) << 2) : 0);
+        t->child[8 * p + oc] = b;
+    }
+    for (int b = 0; b < B; b++) {
+        if (t->lev[b] < 1 || t->leaf[b]) continue;
+        for (int c = 0; c < nch; c++)
+            if (t->child[8 * b + c] < 0) { seterr(err, errlen, "leaves do not tile the domain (missing child)"); goto fail2; }
+    }
+    /* neighbours */
+    for (int b = 0; b < B; b++) {
+        int l = t->lev[b];
+        for (int s = 0; s < 6; s++) t->nbr[6 * b + s] = -1;
+        if (l < 1) continue;
+        int n1 = 1 << (l - 1);
+        for (int s = 0; s < 2 * dim; s++) {
+            int d = s / 2, dir = (s % 2) ? 1 : -1;
+            int q[3] = {t->ix[b], t->iy[b], t->iz[b]};
+            q[d] += dir;
+            if (q[d] < 1 || q[d] > n1) { t->nbr[6 * b + s] = -1; continue; }
+            int nb2 = oh_get(&h, okey(l, q[0], q[1], q[2]));
+            if (nb2 >= 0) { t->nbr[6 * b + s] = nb2; continue; }
+            t->nbr[6 * b + s] = -2;
+            /* 2:1 balance: the parent's neighbour must exist */
+            int p = t->parent[b];
+            int pq[3] = {t->ix[p], t->iy[p], t->iz[p]};
+            pq[d] += dir;
+            if (oh_get(&h, okey(l - 1, pq[0], pq[1], pq[2])) < 0) {
+                seterr(err, errlen, "grid violates 2:1 balance across a box side"); goto fail2;
+            }
+        }
+    }
+    /* level lists */
+    t->lvl_store = malloc(sizeof(int) * B);
+    pos = 0;
+    for (int l = t->lmin; l <= t->lmax; l++) {
+        t->lvl_first[l - t->lmin] = t->lvl_store + pos;
+        int c = 0;
+        for (int b = 0; b < B; b++) if (t->lev[b] == l) t->lvl_store[pos + c++] = b;
+        t->lvl_cnt[l - t->lmin] = c;
+        pos += c;
+    }
+    /* storage */
+    int64_t o = 0;
+    for (int b = 0; b < B; b++) {
+        t->off[b] = o;
+        int64_t m = t->n[b] + 2;
+        o += dim == 3 ? m * m * m : m * m;
+    }
+    t->ntot = o;
+    int64_t ob = 0;
+    for (int b = 0; b < B; b++)
+        for (int s = 0; s < 6; s++) {
+            t->bcoff[6 * b + s] = -1;
+            if (s < 2 * dim && t->nbr[6 * b + s] == -1) {
+                t->bcoff[6 * b + s] = ob;
+                ob += dim == 3 ? (int64_t)t->n[b] * t->n[b] : t->n[b];
+            }
+        }
+    t->nbc = ob;
+    t->u = calloc(o, sizeof(double)); t->rho = calloc(o, sizeof(double));
+    t->uold = calloc(o, sizeof(double)); t->res = calloc(o, sizeof(double));
+    t->bc = calloc(ob > 0 ? ob : 1, sizeof(double));
+    free(L); free(I); free(J); free(K); free(isleaf); oh_free(&h);
+    return t;
+fail2:
+    free(L); free(I); free(J); free(K); free(isleaf); oh_free(&h);
+    or_tree_free(t);
+    return NULL;
+fail:
+    free(L); free(I); free(J); free(K); free(isleaf); oh_free(&h); free(t);
+    return NULL;
+}
+
+void or_tree_free(void *p) {
+    otree *t = (otree *)p;
+    if (!t) return;
+    free(t->lev); free(t->ix); free(t->iy); free(t->iz); free(t->n); free(t->parent);
+    free(t->leaf); free(t->child); free(t->nbr); free(t->off); free(t->bcoff);
+    free(t->leaf_box); free(t->lvl_store);
+    free(t->u); free(t->rho); free(t->uold); free(t->res); free(t->bc);
+    free(t);
+}
+
+const char *or_last_error(void) { return or_errbuf; }
+
+/* info: [nbox, lmin, lmax, n_leaf_in, dim, N] */
+void or_tree_info(void *p, int64_t *out) {
+    otree *t = (otree *)p;
+    out[0] = t->nbox; out[1] = t->lmin; out[2] = t->lmax; out[3] = t->nleaf_in;
+    out[4] = t->dim; out[5] = t->N;
+}
+
+/* per box: [level, ix, iy, iz, n, parent, leaf, nbr0..nbr5] */
+void or_box_info(void *p, int b, int32_t *out) {
+    otree *t = (otree *)p;
+    out[0] = t->lev[b]; out[1] = t->ix[b]; out[2] = t->iy[b]; out[3] = t->iz[b];
+    out[4] = t->n[b]; out[5] = t->parent[b]; out[6] = t->leaf[b];
+    for (int s = 0; s < 6; s++) out[7 + s] = t->nbr[6 * b + s];
+}
+
+void or_leaf_boxes(void *p, int32_t *out) {
+    otree *t = (otree *)p;
+    for (int q = 0; q < t->nleaf_in; q++) out[q] = t->leaf_box[q];
+}
+
+/* ------------------------------------------------------------------------ */
+/* field access helpers                                                      */
+/* ------------------------------------------------------------------------ */
+static double *fld(otree *t, int which) {
+    switch (which) {
+    case 0: return t->u;
+    case 1: return t->rho;
+    case 2: return t->uold;
+    default: return t->res;
+    }
+}
+
+/* Loop over the interior cells of box b, 1-based (i, j, k); k == 1 in 2D. */
+#define FOR_CELLS(t, b, i, j, k)                                  \
+    for (int k = 1; k <= ((t)->dim == 3 ? (t)->n[b] : 1); k++)      \
+        for (int j = 1; j <= (t)->n[b]; j++)                        \
+            for (int i = 1; i <= (t)->n[b]; i++)
+/* padded index allowing k = 1 in 2D */
+static int64_t PX(const otree *t, int b, int i, int j, int k) {
+    return t->dim == 3 ? PI(t, b, i, j, k) : PI(t, b, i, j, 0);
+}
+
+/* copy interior of leaf-ordered input array into field */
+static void load_leaf_field(otree *t, double *f, const double *src) {
+    int N = t->N, D = t->dim;
+    int64_t nc = D == 3 ? (int64_t)N * N * N : (int64_t)N * N;
+#pragma omp parallel for schedule(static)
+    for (int q = 0; q < t->nleaf_in; q++) {
+        int b = t->leaf_box[q];
+        const double *s = src + nc * q;
+        int64_t m = 0;
+        FOR_CELLS(t, b, i, j, k) f[PX(t, b, i, j, k)] = s[m++];
+    }
+}
+static void store_leaf_field(otree *t, const double *f, double *dst) {
+    int N = t->N, D = t->dim;
+    int64_t nc = D == 3 ? (int64_t)N * N * N : (int64_t)N * N;
+#pragma omp parallel for schedule(static)
+    for (int q = 0; q < t->nleaf_in; q++) {
+        int b = t->leaf_box[q];
+        double *s = dst + nc * q;
+        int64_t m = 0;
+        FOR_CELLS(t, b, i, j, k) s[m++] = f[PX(t, b, i, j, k)];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* boundary values                                                           */
+/* ------------------------------------------------------------------------ */
+/* bc layout of the input: [n_leaves][2D][N^(D-1)], tangential axes in
+   increasing order, first fastest.  Values of non-leaf boxes are the means
+   of the 2^(D-1) child face values that cover each coarse face. */
+static void set_bc(otree *t, const double *bc_leaf) {
+    int N = t->N, D = t->dim;
+    int64_t nf = D == 3 ? (int64_t)N * N : N;
+    for (int64_t i = 0; i < t->nbc; i++) t->bc[i] = 0.0;
+    for (int q = 0; q < t->nleaf_in; q++) {
+        int b = t->leaf_box[q];
+        for (int s = 0; s < 2 * D; s++) {
+            int64_t o = t->bcoff[6 * b + s];
+            if (o < 0) continue;
+            for (int64_t m = 0; m < nf; m++) t->bc[o + m] = bc_leaf[(q * 2 * D + s) * nf + m];
+        }
+    }
+    /* from fine to coarse */
+    for (int l = t->lmax - 1; l >= t->lmin; l--) {
+        for (int m = 0; m < lvl_count(t, l); m++) {
+            int b = lvl_box(t, l, m);
+            if (t->leaf[b]) continue;
+            int n = t->n[b];
+            for (int s = 0; s < 2 * D; s++) {
+                int64_t o = t->bcoff[6 * b + s];
+                if (o < 0) continue;
+                int d = s / 2, hi = s % 2;
+                int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2; /* tangential axes */
+                int na = n, nc2 = D == 3 ? n : 1;
+                for (int c = 0; c < nc2; c++)
+                    for (int a = 0; a < na; a++) {
+                        /* find the child box covering coarse face cell (a, c) */
+                        double sum = 0.0;
+                        int cnt = 0;
+                        for (int oc = 0; oc < 8; oc++) {
+                            int ch = t->child[8 * b + oc];
+                            if (ch < 0) continue;
+                            int bits[3] = {oc & 1, (oc >> 1) & 1, (oc >> 2) & 1};
+                            if (t->lev[ch] >= 2 && bits[d] != hi) continue;
+                            int nc_ = t->n[ch];
+                            int offa = child_offset(t, ch, t1), offc = D == 3 ? child_offset(t, ch, t2) : 0;
+                            if (a < offa || a >= offa + nc_ / 2) continue;
+                            if (D == 3 && (c < offc || c >= offc + nc_ / 2)) continue;
+                            int64_t oc_ = t->bcoff[6 * ch + s];
+                            int fa = 2 * (a - offa), fc = 2 * (c - offc);
+                            int nc3 = D == 3 ? 2 : 1;
+                            for (int dc = 0; dc < nc3; dc++)
+                                for (int da = 0; da < 2; da++) {
+                                    sum += t->bc[oc_ + (fa + da) + (int64_t)nc_ * (fc + dc)];
+                                    cnt++;
+                                }
+                        }
+                        t->bc[o + a + (int64_t)n * c] = sum / cnt;
+                    }
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* ghost cells (paper §2.4, §3.3)                                            */
+/* ------------------------------------------------------------------------ */
+/* Fill the side ghosts of every box at level l for field f.  homog != 0
+   uses zero Dirichlet values. */
+static void fill_gc(otree *t, int l, double *f, int homog) {
+    int D = t->dim;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int m = 0; m < lvl_count(t, l); m++) {
+        int b = lvl_box(t, l, m);
+        int n = t->n[b];
+        for (int s = 0; s < 2 * D; s++) {
+            int d = s / 2, hi = s % 2;
+            int nb = t->nbr[6 * b + s];
+            int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+            int nc2 = D == 3 ? n : 1;
+            for (int c = 1; c <= nc2; c++)
+                for (int a = 1; a <= n; a++) {
+                    /* ghost position g, face cell c1, inner cell c2 (1-based) */
+                    int g[3], c1[3], c2[3];
+                    g[t1] = c1[t1] = c2[t1] = a;
+                    g[t2] = c1[t2] = c2[t2] = (D == 3 ? c : 1);
+                    g[d] = hi ? n + 1 : 0;
+                    c1[d] = hi ? n : 1;
+                    c2[d] = hi ? n - 1 : 2;
+                    int64_t ig = PX(t, b, g[0], g[1], g[2]);
+                    double u1 = f[PX(t, b, c1[0], c1[1], c1[2])];
+                    if (nb >= 0) {
+                        int q[3] = {c1[0], c1[1], c1[2]};
+                        q[d] = hi ? 1 : n;
+                        f[ig] = f[PX(t, nb, q[0], q[1], q[2])];
+                    } else if (nb == -1) {
+                        double bv = homog ? 0.0 : t->bc[t->bcoff[6 * b + s] + (a - 1) + (int64_t)n * ((D == 3 ? c : 1) - 1)];
+                        f[ig] = 2.0 * bv - u1;
+                    } else {
+                        /* refinement boundary: coarse value from the parent's neighbour */
+                        int p = t->parent[b];
+                        int cb = t->nbr[6 * p + s];
+                        int qc[3];
+                        qc[d] = hi ? 1 : n;
+                        qc[t1] = child_offset(t, b, t1) + (a + 1) / 2;
+                        qc[t2] = D == 3 ? child_offset(t, b, t2) + (c + 1) / 2 : 1;
+                        double uH = f[PX(t, cb, qc[0], qc[1], qc[2])];
+                        double u2 = f[PX(t, b, c2[0], c2[1], c2[2])];
+                        int p1[3] = {c1[0], c1[1], c1[2]};
+                        p1[t1] = (a % 2) ? a + 1 : a - 1; /* partner inside the same coarse cell */
+                        double u1p = f[PX(t, b, p1[0], p1[1], p1[2])];
+                        if (D == 2) {
+                            f[ig] = 0.5 * uH + u1 - 0.25 * (u1p + u2);
+                        } else {
+                            int p2[3] = {c1[0], c1[1], c1[2]};
+                            p2[t2] = (c % 2) ? c + 1 : c - 1;
+                            double u1pp = f[PX(t, b, p2[0], p2[1], p2[2])];
+                            f[ig] = 0.5 * uH + 1.25 * u1 - 0.25 * (u2 + u1p + u1pp);
+                        }
+                    }
+                }
+        }
+    }
+}
+
+/* sum of the 2D side neighbours of cell (i,j,k) (ghosts included) */
+static double nb_sum(const otree *t, const double *f, int b, int i, int j, int k) {
+    if (t->dim == 2)
+        return (f[PX(t, b, i - 1, j, k)] + f[PX(t, b, i + 1, j, k)]) +
+               (f[PX(t, b, i, j - 1, k)] + f[PX(t, b, i, j + 1, k)]);
+    return (f[PI(t, b, i - 1, j, k)] + f[PI(t, b, i + 1, j, k)]) +
+           (f[PI(t, b, i, j - 1, k)] + f[PI(t, b, i, j + 1, k)]) +
+           (f[PI(t, b, i, j, k - 1)] + f[PI(t, b, i, j, k + 1)]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* smoother (paper §3.1)                                                     */
+/* ------------------------------------------------------------------------ */
+/* colour 0 = red: 1-based index sum even (within a box this equals the
+   parity of the global index sum because box offsets are even) */
+static void half_sweep(otree *t, int l, int colour, int homog) {
+    fill_gc(t, l, t->u, homog);
+    double h = level_h(t, l), h2 = h * h;
+    double twoD = 2.0 * t->dim;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int m = 0; m < lvl_count(t, l); m++) {
+        int b = lvl_box(t, l, m);
+        FOR_CELLS(t, b, i, j, k) {
+            int par = (i + j + (t->dim == 3 ? k : 0)) & 1;
+            if (par != colour) continue;
+            int64_t c = PX(t, b, i, j, k);
+            t->u[c] = (nb_sum(t, t->u, b, i, j, k) - h2 * t->rho[c]) / twoD;
+        }
+    }
+}
+static void gsrb(otree *t, int l, int nsweep, int homog) {
+    for (int s = 0; s < nsweep; s++) {
+        half_sweep(t, l, 0, homog);
+        half_sweep(t, l, 1, homog);
+    }
+}
+
+/* r = rho - L u on the given box (ghosts must be filled) */
+static void box_residual(otree *t, int b, double *out) {
+    double h = level_h(t, t->lev[b]), ih2 = 1.0 / (h * h);
+    double twoD = 2.0 * t->dim;
+    FOR_CELLS(t, b, i, j, k) {
+        int64_t c = PX(t, b, i, j, k);
+        out[c] = t->rho[c] - (nb_sum(t, t->u, b, i, j, k) - twoD * t->u[c]) * ih2;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* restriction / prolongation (paper §2.5)                                   */
+/* ------------------------------------------------------------------------ */
+/* parent cells covered by box b <- mean of its 2^D cells, for field src -> dst */
+static void restrict_box(otree *t, int b, const double *src, double *dst) {
+    int p = t->parent[b], D = t->dim, n = t->n[b];
+    int o0 = child_offset(t, b, 0), o1 = child_offset(t, b, 1), o2 = D == 3 ? child_offset(t, b, 2) : 0;
+    int nk = D == 3 ? n / 2 : 1;
+    double w = D == 3 ? 0.125 : 0.25;
+    for (int K = 1; K <= nk; K++)
+        for (int J = 1; J <= n / 2; J++)
+            for (int I = 1; I <= n / 2; I++) {
+                double s = 0.0;
+                int nkk = D == 3 ? 2 : 1;
+                for (int dk = 0; dk < nkk; dk++)
+                    for (int dj = 0; dj < 2; dj++)
+                        for (int di = 0; di < 2; di++)
+                            s += src[PX(t, b, 2 * I - 1 + di, 2 * J - 1 + dj, D == 3 ? 2 * K - 1 + dk : 1)];
+                dst[PX(t, p, o0 + I, o1 + J, D == 3 ? o2 + K : 1)] = w * s;
+            }
+}
+
+/* u_b += P211(delta) where delta = u - uold of the parent, ghosts included */
+static void prolong_correct_box(otree *t, int b) {
+    int p = t->parent[b], D = t->dim;
+    int o0 = child_offset(t, b, 0), o1 = child_offset(t, b, 1), o2 = D == 3 ? child_offset(t, b, 2) : 0;
+    FOR_CELLS(t, b, i, j, k) {
+        int P[3] = {o0 + (i + 1) / 2, o1 + (j + 1) / 2, D == 3 ? o2 + (k + 1) / 2 : 1};
+        int s[3] = {(i & 1) ? -1 : 1, (j & 1) ? -1 : 1, (k & 1) ? -1 : 1};
+#define DEL(a, bb, cc) (t->u[PX(t, p, a, bb, cc)] - t->uold[PX(t, p, a, bb, cc)])
+        double v;
+        if (D == 2) {
+            v = 0.5 * DEL(P[0], P[1], 1) + 0.25 * DEL(P[0] + s[0], P[1], 1) + 0.25 * DEL(P[0], P[1] + s[1], 1);
+        } else {
+            v = 0.25 * (DEL(P[0], P[1], P[2]) + DEL(P[0] + s[0], P[1], P[2]) +
+                        DEL(P[0], P[1] + s[1], P[2]) + DEL(P[0], P[1], P[2] + s[2]));
+        }
+#undef DEL
+        t->u[PX(t, b, i, j, k)] += v;
+    }
+}
+
+static void copy_box_padded(otree *t, int b, const double *src, double *dst) {
+    int64_t m = or_np(t, b), sz = t->dim == 3 ? m * m * m : m * m;
+    memcpy(dst + t->off[b], src + t->off[b], sizeof(double) * sz);
+}
+
+/* ------------------------------------------------------------------------ */
+/* cycles (paper §3.2)                                                       */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int cycle;      /* 0: V-cycles only, 1: one FMG cycle then V-cycles */
+    int n_down, n_up, n_base;
+    double tol;     /* stop when max|r| <= tol * max|r0| */
+    int max_cycles;
+    int fixed_cycles; /* > 0: run exactly this many V-cycles, no stop test */
+    int use_guess;
+    int homog;      /* zero Dirichlet values */
+} or_opts;
+
+typedef struct {
+    int status;     /* 0 converged, 1 not converged */
+    int cycles;     /* V-cycles run (FMG not counted) */
+    double r0_max, r0_l2, r_max, r_l2;
+    double hist_max[128];
+    double hist_l2[128];
+} or_stats;
+
+static void vcycle(otree *t, int top, const or_opts *o) {
+    int homog = o->homog;
+    for (int l = top; l > t->lmin; l--) {
+        gsrb(t, l, o->n_down, homog);
+        fill_gc(t, l, t->u, homog);
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int m = 0; m < lvl_count(t, l); m++) {
+            int b = lvl_box(t, l, m);
+            box_residual(t, b, t->res);
+            restrict_box(t, b, t->u, t->u);
+            restrict_box(t, b, t->res, t->res);
+        }
+        fill_gc(t, l - 1, t->u, homog);
+        double H = level_h(t, l - 1), iH2 = 1.0 / (H * H), twoD = 2.0 * t->dim;
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int m = 0; m < lvl_count(t, l - 1); m++) {
+            int b = lvl_box(t, l - 1, m);
+            copy_box_padded(t, b, t->u, t->uold);
+            if (t->leaf[b]) continue;
+            FOR_CELLS(t, b, i, j, k) {
+                int64_t c = PX(t, b, i, j, k);
+                t->rho[c] = t->res[c] + (nb_sum(t, t->u, b, i, j, k) - twoD * t->u[c]) * iH2;
+            }
+        }
+    }
+    gsrb(t, t->lmin, o->n_base, homog);
+    for (int l = t->lmin + 1; l <= top; l++) {
+        fill_gc(t, l - 1, t->u, homog);
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int m = 0; m < lvl_count(t, l); m++) prolong_correct_box(t, lvl_box(t, l, m));
+        gsrb(t, l, o->n_up, homog);
+    }
+}
+
+/* restrict u into all parents, fill ghosts, composite residual on leaves.
+   Returns max|r| and sqrt(sum r^2 h^D). */
+static void finalize(otree *t, int homog, double *rmax, double *rl2) {
+    for (int l = t->lmax; l > t->lmin; l--) {
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int m = 0; m < lvl_count(t, l); m++) restrict_box(t, lvl_box(t, l, m), t->u, t->u);
+    }
+    double mx = 0.0, s2 = 0.0;
+    for (int l = 1; l <= t->lmax; l++) {
+        fill_gc(t, l, t->u, homog);
+        double h = level_h(t, l), hD = t->dim == 3 ? h * h * h : h * h;
+        double lmx = 0.0, ls2 = 0.0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(max : lmx) reduction(+ : ls2)
+        for (int m = 0; m < lvl_count(t, l); m++) {
+            int b = lvl_box(t, l, m);
+            if (!t->leaf[b]) continue;
+            box_residual(t, b, t->res);
+            FOR_CELLS(t, b, i, j, k) {
+                double r = t->res[PX(t, b, i, j, k)];
+                if (fabs(r) > lmx) lmx = fabs(r);
+                ls2 += r * r;
+            }
+        }
+        if (lmx > mx) mx = lmx;
+        s2 += ls2 * hD;
+    }
+    *rmax = mx;
+    *rl2 = sqrt(s2);
+}
+
+static void fmg(otree *t, const or_opts *o) {
+    int homog = o->homog;
+    memset(t->u, 0, sizeof(double) * t->ntot);
+    for (int l = t->lmax; l > t->lmin; l--) {
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int m = 0; m < lvl_count(t, l); m++) restrict_box(t, lvl_box(t, l, m), t->rho, t->rho);
+    }
+    for (int l = t->lmin; l <= t->lmax; l++) {
+        fill_gc(t, l, t->u, homog);
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int m = 0; m < lvl_count(t, l); m++) copy_box_padded(t, lvl_box(t, l, m), t->u, t->uold);
+        if (l > t->lmin) {
+            fill_gc(t, l - 1, t->u, homog);
+#pragma omp parallel for schedule(dynamic, 16)
+            for (int m = 0; m < lvl_count(t, l); m++) prolong_correct_box(t, lvl_box(t, l, m));
+        }
+        if (l == t->lmin) gsrb(t, l, o->n_base, homog);
+        else vcycle(t, l, o);
+    }
+}
+
+static int load_inputs(otree *t, const double *rho_leaf, const double *bc_leaf, const double *u_leaf,
+                       int use_guess) {
+    memset(t->u, 0, sizeof(double) * t->ntot);
+    memset(t->rho, 0, sizeof(double) * t->ntot);
+    memset(t->uold, 0, sizeof(double) * t->ntot);
+    memset(t->res, 0, sizeof(double) * t->ntot);
+    load_leaf_field(t, t->rho, rho_leaf);
+    if (bc_leaf) set_bc(t, bc_leaf);
+    else for (int64_t i = 0; i < t->nbc; i++) t->bc[i] = 0.0;
+    if (use_guess && u_leaf) load_leaf_field(t, t->u, u_leaf);
+    return 0;
+}
+
+/* Solve lap_h u = rho.  rho_leaf: [n_leaves][N^D]; bc_leaf: [n_leaves][2D][N^(D-1)]
+   (NULL = zero); u_leaf: in (guess if use_guess) / out. */
+int or_solve(void *p, const double *rho_leaf, const double *bc_leaf, double *u_leaf,
+             const or_opts *o, or_stats *st) {
+    otree *t = (otree *)p;
+    memset(st, 0, sizeof(*st));
+    load_inputs(t, rho_leaf, bc_leaf, u_leaf, o->use_guess);
+    double r0m, r0l;
+    finalize(t, o->homog, &r0m, &r0l);
+    st->r0_max = r0m; st->r0_l2 = r0l;
+    st->r_max = r0m; st->r_l2 = r0l;
+    if (!isfinite(r0m)) { st->status = -5; return -5; }
+    if (o->cycle == 1 && !o->use_guess) {
+        fmg(t, o);
+        finalize(t, o->homog, &st->r_max, &st->r_l2);
+    }
+    int conv = 0;
+    if (o->fixed_cycles <= 0 && st->r_max <= o->tol * r0m) conv = 1;
+    int nmax = o->fixed_cycles > 0 ? o->fixed_cycles : o->max_cycles;
+    while (!conv && st->cycles < nmax) {
+        vcycle(t, t->lmax, o);
+        finalize(t, o->homog, &st->r_max, &st->r_l2);
+        if (st->cycles < 128) { st->hist_max[st->cycles] = st->r_max; st->hist_l2[st->cycles] = st->r_l2; }
+        st->cycles++;
+        if (!isfinite(st->r_max)) { st->status = -5; store_leaf_field(t, t->u, u_leaf); return -5; }
+        if (o->fixed_cycles <= 0 && st->r_max <= o->tol * r0m) conv = 1;
+    }
+    store_leaf_field(t, t->u, u_leaf);
+    st->status = (o->fixed_cycles > 0 || conv) ? 0 : 1;
+    return st->status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* entry points used by the pins                                             */
+/* ------------------------------------------------------------------------ */
+
+/* Composite operator on leaves: out = L u (homog = zero Dirichlet values) or
+   out = L u + boundary part.  Parents get the restriction of u first. */
+void or_apply_L(void *p, const double *u_leaf, const double *bc_leaf, double *out_leaf, int homog) {
+    otree *t = (otree *)p;
+    int nleaf = t->nleaf_in, N = t->N, D = t->dim;
+    int64_t nc = D == 3 ? (int64_t)N * N * N : (int64_t)N * N;
+    double *zero = calloc((size_t)nleaf * nc, sizeof(double));
+    load_inputs(t, zero, bc_leaf, u_leaf, 1);
+    free(zero);
+    double a, bq;
+    finalize(t, homog, &a, &bq); /* res = rho - L u = -L u */
+    store_leaf_field(t, t->res, out_leaf);
+    for (int64_t i = 0; i < (int64_t)nleaf * nc; i++) out_leaf[i] = -out_leaf[i];
+}
+
+/* Load a state: u on leaves (restricted into parents), rho, bc. */
+void or_load(void *p, const double *rho_leaf, const double *bc_leaf, const double *u_leaf) {
+    otree *t = (otree *)p;
+    load_inputs(t, rho_leaf, bc_leaf, u_leaf, u_leaf != NULL);
+    double a, b;
+    finalize(t, 0, &a, &b);
+}
+void or_fill_gc(void *p, int l, int which, int homog) { otree *t = (otree *)p; fill_gc(t, l, fld(t, which), homog); }
+void or_half_sweep(void *p, int l, int colour, int homog) { half_sweep((otree *)p, l, colour, homog); }
+void or_vcycle(void *p, const or_opts *o) { otree *t = (otree *)p; vcycle(t, t->lmax, o); }
+void or_fmg(void *p, const or_opts *o) { fmg((otree *)p, o); }
+void or_finalize(void *p, int homog, double *out2) { finalize((otree *)p, homog, out2, out2 + 1); }
+void or_restrict_level(void *p, int l, int which) {
+    otree *t = (otree *)p;
+    double *f = fld(t, which);
+    for (int m = 0; m < lvl_count(t, l); m++) restrict_box(t, lvl_box(t, l, m), f, f);
+}
+/* u_old <- u on every box of level l (incl. ghosts) */
+void or_copy_uold(void *p, int l) {
+    otree *t = (otree *)p;
+    for (int m = 0; m < lvl_count(t, l); m++) copy_box_padded(t, lvl_box(t, l, m), t->u, t->uold);
+}
+void or_prolong_level(void *p, int l) {
+    otree *t = (otree *)p;
+    for (int m = 0; m < lvl_count(t, l); m++) prolong_correct_box(t, lvl_box(t, l, m));
+}
+/* padded box array of a field: (n+2)^D values, x fastest */
+void or_get_box(void *p, int b, int which, double *out) {
+    otree *t = (otree *)p;
+    int64_t m = or_np(t, b), sz = t->dim == 3 ? m * m * m : m * m;
+    memcpy(out, fld(t, which) + t->off[b], sizeof(double) * sz);
+}
+void or_set_box(void *p, int b, int which, const double *in) {
+    otree *t = (otree *)p;
+    int64_t m = or_np(t, b), sz = t->dim == 3 ? m * m * m : m * m;
+    memcpy(fld(t, which) + t->off[b], in, sizeof(double) * sz);
+}
+void or_get_leaf_field(void *p, int which, double *out) { otree *t = (otree *)p; store_leaf_field(t, fld(t, which), out); }
+/* Dirichlet values in use for box b side s (n^(D-1) values); returns 0 if the
+   side is not physical */
+int or_get_bc(void *p, int b, int s, double *out) {
+    otree *t = (otree *)p;
+    int64_t o = t->bcoff[6 * b + s];
+    if (o < 0) return 0;
+    int64_t nf = t->dim == 3 ? (int64_t)t->n[b] * t->n[b] : t->n[b];
+    memcpy(out, t->bc + o, sizeof(double) * nf);
+    return 1;
+}
+int or_num_threads(void) { return omp_get_max_threads(); }

@@ -1,0 +1,408 @@
+"""Seeded synthetic inputs for the multigrid Poisson solve.
+
+This module only produces inputs: leaf lists of quadtree/octree grids and
+analytic fields sampled on them.  It holds none of the solver's arithmetic
+(no ghost cells, no stencils, no cycles), so the FP64 oracle and the HIP
+path can both consume what it returns without sharing any solver code.
+
+Conventions (shared by every consumer):
+
+* Domain [0,1]^D covered by one root box at level 1.  A box at level l has
+  N^D cells of size h_l = 1 / (N * 2^(l-1)) and a 1-based spatial index
+  (i, j[, k]); its children have indices (2i-1 .. 2i, ...)  (paper §2.1).
+* A grid is given by its leaves: ``level`` int32 [n], ``idx`` int32 [n, 3]
+  (third column 1 in 2D).
+* Cell fields per leaf are float64 [n, N^D], x fastest.
+* Dirichlet values per leaf are float64 [n, 2D, N^(D-1)] at the face
+  centres of the box sides ordered (-x, +x, -y, +y, -z, +z); on each side the
+  tangential axes are taken in increasing axis order, the first fastest.
+  Only sides on the physical boundary are meaningful; the rest are zero.
+* Sign convention: the solver solves lap_h(u) = rho, so a manufactured
+  solution u gives rho = lap(u) sampled at cell centres (paper §4.1 uses the
+  same form of the Poisson equation).
+
+Refinement follows the flag rules of paper §2.3: a box is refined when any of
+its cells is flagged, boxes whose cells lie within N_buf = 2 cells of a
+flagged cell (diagonal neighbours included) are refined too, and coarser
+neighbours are refined to keep 2:1 balance (diagonal neighbours included).
+The flag criterion is the form used in paper §4.1, |lap u| h^2 > threshold.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+BOX_N_DEFAULT = 8
+
+
+# ----------------------------------------------------------------------------
+# analytic sources
+# ----------------------------------------------------------------------------
+
+
+@dataclasses.dataclass
+class GaussMix:
+    """u(x) = sum_k amp_k * exp(-|x - c_k|^2 / sigma_k^2)."""
+
+    centres: np.ndarray  # [K, D]
+    sigmas: np.ndarray  # [K]
+    amps: np.ndarray  # [K]
+
+    @property
+    def dim(self) -> int:
+        return self.centres.shape[1]
+
+    def value(self, x: np.ndarray) -> np.ndarray:
+        """x: [..., D] -> [...]"""
+        out = np.zeros(x.shape[:-1])
+        for c, s, a in zip(self.centres, self.sigmas, self.amps):
+            r2 = np.sum((x - c) ** 2, axis=-1)
+            out += a * np.exp(-r2 / (s * s))
+        return out
+
+    def laplacian(self, x: np.ndarray) -> np.ndarray:
+        """Analytic Laplacian: (4 r^2 / s^4 - 2 D / s^2) * g for each term."""
+        d = x.shape[-1]
+        out = np.zeros(x.shape[:-1])
+        for c, s, a in zip(self.centres, self.sigmas, self.amps):
+            r2 = np.sum((x - c) ** 2, axis=-1)
+            g = a * np.exp(-r2 / (s * s))
+            out += g * (4.0 * r2 / s**4 - 2.0 * d / s**2)
+        return out
+
+
+def gauss_mix_seeded(dim, n, seed, lo=0.1, hi=0.9, sigma_range=(0.05, 0.05),
+                     log_sigma=False):
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(lo, hi, size=(n, dim))
+    s0, s1 = sigma_range
+    if log_sigma:
+        sig = np.exp(rng.uniform(math.log(s0), math.log(s1), size=n))
+    else:
+        sig = rng.uniform(s0, s1, size=n)
+    return GaussMix(centres, sig, np.ones(n))
+
+
+# ----------------------------------------------------------------------------
+# grid geometry helpers (pure index arithmetic)
+# ----------------------------------------------------------------------------
+
+
+def box_h(level, n_cells=BOX_N_DEFAULT):
+    return 1.0 / (n_cells * 2.0 ** (np.asarray(level, dtype=np.float64) - 1.0))
+
+
+def cell_centres(dim, N, level, idx):
+    """Cell centres of the given boxes: [n, N^D, D] (x fastest)."""
+    level = np.asarray(level)
+    idx = np.asarray(idx)
+    h = box_h(level, N)  # [n]
+    loc = (np.arange(N) + 0.5)
+    grids = np.meshgrid(*([loc] * dim), indexing="ij")  # grid[d][i0, i1, ...]
+    # x fastest: flatten with axis order (z, y, x)
+    offs = []
+    for d in range(dim):
+        g = np.transpose(grids[d], axes=list(range(dim))[::-1]).reshape(-1)
+        offs.append(g)
+    offs = np.stack(offs, axis=-1)  # [N^D, D]
+    origin = (idx[:, :dim] - 1).astype(np.float64) * N * h[:, None]  # [n, D]
+    return origin[:, None, :] + offs[None, :, :] * h[:, None, None]
+
+
+def face_centres(dim, N, level, idx, side):
+    """Face centres of side `side` of each box: [n, N^(D-1), D]."""
+    level = np.asarray(level)
+    idx = np.asarray(idx)
+    h = box_h(level, N)
+    axis, hi = side // 2, side % 2
+    tang = [d for d in range(dim) if d != axis]
+    loc = np.arange(N) + 0.5
+    if dim == 2:
+        t = [loc]
+    else:
+        a, b = np.meshgrid(loc, loc, indexing="ij")
+        t = [np.transpose(a).reshape(-1), np.transpose(b).reshape(-1)]
+    n = len(level)
+    out = np.zeros((n, N ** (dim - 1), dim))
+    origin = (idx[:, :dim] - 1).astype(np.float64) * N * h[:, None]
+    for m, d in enumerate(tang):
+        out[:, :, d] = origin[:, d:d + 1] + t[m][None, :] * h[:, None]
+    out[:, :, axis] = origin[:, axis:axis + 1] + (N * h[:, None] if hi else 0.0)
+    return out
+
+
+def physical_side_mask(dim, level, idx):
+    """[n, 2D] bool: side lies on the boundary of [0,1]^D."""
+    level = np.asarray(level)
+    idx = np.asarray(idx)
+    nmax = 2 ** (level - 1)
+    m = np.zeros((len(level), 2 * dim), dtype=bool)
+    for d in range(dim):
+        m[:, 2 * d] = idx[:, d] == 1
+        m[:, 2 * d + 1] = idx[:, d] == nmax
+    return m
+
+
+# ----------------------------------------------------------------------------
+# leaf lists
+# ----------------------------------------------------------------------------
+
+
+def uniform_leaves(dim, level):
+    n1 = 2 ** (level - 1)
+    r = np.arange(1, n1 + 1, dtype=np.int32)
+    if dim == 2:
+        j, i = np.meshgrid(r, r, indexing="ij")
+        idx = np.stack([i.ravel(), j.ravel(), np.ones(i.size, np.int32)], 1)
+    else:
+        k, j, i = np.meshgrid(r, r, r, indexing="ij")
+        idx = np.stack([i.ravel(), j.ravel(), k.ravel()], 1)
+    lev = np.full(len(idx), level, dtype=np.int32)
+    return lev, idx.astype(np.int32)
+
+
+def _neighbour_offsets(dim):
+    rng = [-1, 0, 1]
+    if dim == 2:
+        return [(a, b, 0) for b in rng for a in rng if (a, b) != (0, 0)]
+    return [(a, b, c) for c in rng for b in rng for a in rng if (a, b, c) != (0, 0, 0)]
+
+
+class _LeafSet:
+    """Mutable set of leaves keyed by (level, i, j, k); used only to build
+    input grids."""
+
+    def __init__(self, dim):
+        self.dim = dim
+        self.leaves = {(1, 1, 1, 1)}
+
+    def covering_leaf(self, level, i, j, k):
+        """The leaf covering box position (level, i, j, k), or None if that
+        position is refined further (or outside the domain)."""
+        n1 = 2 ** (level - 1)
+        if not (1 <= i <= n1 and 1 <= j <= n1 and (self.dim == 2 or 1 <= k <= n1)):
+            return None
+        l, a, b, c = level, i, j, k
+        while l >= 1:
+            if (l, a, b, c) in self.leaves:
+                return (l, a, b, c)
+            l -= 1
+            a, b = (a + 1) // 2, (b + 1) // 2
+            c = (c + 1) // 2 if self.dim == 3 else 1
+        return None
+
+    def refine(self, key):
+        l, i, j, k = key
+        self.leaves.remove(key)
+        ks = (0, 1) if self.dim == 3 else (0,)
+        for dk in ks:
+            for dj in (0, 1):
+                for di in (0, 1):
+                    kk = 2 * k - 1 + dk if self.dim == 3 else 1
+                    self.leaves.add((l + 1, 2 * i - 1 + di, 2 * j - 1 + dj, kk))
+
+    def arrays(self):
+        keys = sorted(self.leaves)
+        lev = np.array([k[0] for k in keys], dtype=np.int32)
+        idx = np.array([k[1:] for k in keys], dtype=np.int32).reshape(-1, 3)
+        return lev, idx
+
+
+def adaptive_leaves(dim, N, flag_fn, lmax, n_buf=2):
+    """Refine from the root until stable.
+
+    flag_fn(level, idx[n,3]) -> bool [n, N^D] cell flags for the given boxes.
+    A box is refined when any cell is flagged (and its level < lmax); same-level
+    neighbours whose cells lie within n_buf cells of a flagged cell are refined
+    too; coarser neighbours (diagonals included) are refined for 2:1 balance.
+    """
+    ls = _LeafSet(dim)
+    offs = _neighbour_offsets(dim)
+    evaluated = set()
+    while True:
+        cand = sorted(k for k in ls.leaves if k[0] < lmax and k not in evaluated)
+        flagged = set()
+        if cand:
+            lev = np.array([k[0] for k in cand], dtype=np.int32)
+            idx = np.array([k[1:] for k in cand], dtype=np.int32)
+            cf = flag_fn(lev, idx).reshape((len(cand),) + (N,) * dim)  # [n, (z,) y, x]
+            for key in cand:
+                evaluated.add(key)
+            for m, key in enumerate(cand):
+                f = cf[m]
+                if not f.any():
+                    continue
+                flagged.add(key)
+                # buffer: which neighbour directions contain a cell within
+                # n_buf cells of a flagged cell
+                for o in offs:
+                    sl = []
+                    for d in range(dim):
+                        od = o[d]
+                        if od == -1:
+                            sl.append(slice(0, n_buf))
+                        elif od == 1:
+                            sl.append(slice(N - n_buf, N))
+                        else:
+                            sl.append(slice(0, N))
+                    sl = tuple(sl[::-1])  # array axes are (z,) y, x
+                    if f[sl].any():
+                        l, i, j, k = key
+                        nb = (l, i + o[0], j + o[1], k + o[2] if dim == 3 else 1)
+                        if nb in ls.leaves:
+                            flagged.add(nb)
+        flagged = {k for k in flagged if k[0] < lmax}
+        if not flagged:
+            break
+        # 2:1 balance: coarser neighbours of a box to be refined get refined
+        work = list(flagged)
+        while work:
+            key = work.pop()
+            l, i, j, k = key
+            for o in offs:
+                nb = ls.covering_leaf(l, i + o[0], j + o[1], (k + o[2]) if dim == 3 else 1)
+                if nb is not None and nb[0] < l and nb not in flagged:
+                    flagged.add(nb)
+                    work.append(nb)
+        for key in sorted(flagged):
+            ls.refine(key)
+    return ls.arrays()
+
+
+def laplacian_flag(mix: GaussMix, N, threshold):
+    def fn(level, idx):
+        xc = cell_centres(mix.dim, N, level, idx)
+        h = box_h(level, N)
+        return np.abs(mix.laplacian(xc)) * (h[:, None] ** 2) > threshold
+    return fn
+
+
+# ----------------------------------------------------------------------------
+# workloads
+# ----------------------------------------------------------------------------
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    dim: int
+    N: int
+    level: np.ndarray  # int32 [n]
+    idx: np.ndarray  # int32 [n, 3]
+    rho: np.ndarray  # float64 [n, N^D]
+    bc: np.ndarray  # float64 [n, 2D, N^(D-1)]
+    u_exact: np.ndarray | None = None  # float64 [n, N^D] analytic at centres
+    mix: GaussMix | None = None
+
+    @property
+    def n_leaves(self):
+        return len(self.level)
+
+    @property
+    def n_unknowns(self):
+        return len(self.level) * self.N ** self.dim
+
+    @property
+    def lmax(self):
+        return int(self.level.max())
+
+
+def sample_workload(name, dim, N, level, idx, mix: GaussMix | None, bc_from_mix=True,
+                    rho_const=None, with_exact=True):
+    """Sample rho = lap(u) at cell centres and Dirichlet values u at physical
+    face centres.  rho_const overrides rho with a constant (EX4-style)."""
+    level = np.asarray(level, dtype=np.int32)
+    idx = np.asarray(idx, dtype=np.int32)
+    n = len(level)
+    nf = N ** (dim - 1)
+    bc = np.zeros((n, 2 * dim, nf))
+    if rho_const is not None:
+        rho = np.full((n, N ** dim), float(rho_const))
+        u_ex = None
+    else:
+        xc = cell_centres(dim, N, level, idx)
+        rho = mix.laplacian(xc)
+        u_ex = mix.value(xc) if with_exact else None
+        if bc_from_mix:
+            phys = physical_side_mask(dim, level, idx)
+            for s in range(2 * dim):
+                sel = np.nonzero(phys[:, s])[0]
+                if len(sel):
+                    fc = face_centres(dim, N, level[sel], idx[sel], s)
+                    bc[sel, s, :] = mix.value(fc)
+    return Workload(name, dim, N, level, idx, np.ascontiguousarray(rho), bc, u_ex, mix)
+
+
+def config1(N=BOX_N_DEFAULT):
+    """2D, uniform 128^2 (levels 1..5 with 8^2 boxes), u = exp(-|x-x0|^2/0.01),
+    x0 = (0.5, 0.5), zero Dirichlet values."""
+    lmax = 1 + int(round(math.log2(128 // N)))
+    lev, idx = uniform_leaves(2, lmax)
+    mix = GaussMix(np.array([[0.5, 0.5]]), np.array([0.1]), np.array([1.0]))
+    return sample_workload("c1_2d_uniform_128", 2, N, lev, idx, mix, bc_from_mix=False)
+
+
+def config2(N=BOX_N_DEFAULT, res=256, seed=2):
+    """3D, uniform res^3, two Gaussians sigma = 0.05 with seeded centres in
+    [0.1, 0.9]^3, Dirichlet values from the analytic solution."""
+    lmax = 1 + int(round(math.log2(res // N)))
+    lev, idx = uniform_leaves(3, lmax)
+    mix = gauss_mix_seeded(3, 2, seed, 0.1, 0.9, (0.05, 0.05))
+    return sample_workload(f"c2_3d_uniform_{res}", 3, N, lev, idx, mix)
+
+
+def config3(N=BOX_N_DEFAULT, lmax=8, threshold=1e-4, seed=3, n_src=4,
+            sigma_range=(0.01, 0.05)):
+    """3D adaptive octree refined where |lap u| h^2 > threshold around n_src
+    seeded Gaussians (sigma log-uniform in sigma_range)."""
+    mix = gauss_mix_seeded(3, n_src, seed, 0.1, 0.9, sigma_range, log_sigma=True)
+    lev, idx = adaptive_leaves(3, N, laplacian_flag(mix, N, threshold), lmax)
+    return sample_workload(f"c3_3d_adaptive_l{lmax}", 3, N, lev, idx, mix)
+
+
+def adaptive_small(dim, N, lmax, threshold, seed, n_src=2, sigma_range=(0.03, 0.08),
+                   name=None):
+    """Small adaptive grid for tests: Gaussians in [0.1, 0.9]^D."""
+    mix = gauss_mix_seeded(dim, n_src, seed, 0.1, 0.9, sigma_range, log_sigma=True)
+    lev, idx = adaptive_leaves(dim, N, laplacian_flag(mix, N, threshold), lmax)
+    return sample_workload(name or f"adaptive_{dim}d_l{lmax}_s{seed}", dim, N, lev, idx, mix)
+
+
+def uniform_const_rhs(dim, N, res, value=1.0):
+    """The paper's scaling problem (§4.2): lap(phi) = 1, phi = 0 on the
+    boundary, uniform res^D."""
+    lmax = 1 + int(round(math.log2(res // N)))
+    lev, idx = uniform_leaves(dim, lmax)
+    return sample_workload(f"ex4_{dim}d_uniform_{res}", dim, N, lev, idx, None,
+                           bc_from_mix=False, rho_const=value)
+
+
+def random_fields(dim, N, level, idx, seed):
+    """Seeded random rho and Dirichlet values (no analytic solution)."""
+    rng = np.random.default_rng(seed)
+    n = len(level)
+    rho = rng.standard_normal((n, N ** dim))
+    bc = rng.standard_normal((n, 2 * dim, N ** (dim - 1)))
+    bc *= physical_side_mask(dim, level, idx)[:, :, None]
+    return Workload(f"random_{dim}d_s{seed}", dim, N, np.asarray(level, np.int32),
+                    np.asarray(idx, np.int32), rho, bc)
+
+
+def ball_flag(dim, N, centre, radius):
+    """Flag the cells that intersect the ball |x - centre| <= radius."""
+    p = np.asarray(centre, dtype=np.float64)[:dim]
+
+    def fn(level, idx):
+        xc = cell_centres(dim, N, level, idx)
+        h = box_h(level, N)
+        return np.linalg.norm(xc - p, axis=-1) < radius + 0.5 * math.sqrt(dim) * h[:, None]
+    return fn
+
+
+def ball_leaves(dim, N, lmax, centre, radius=0.0, n_buf=0):
+    """Grid refined to lmax around a ball (small grids with refinement
+    boundaries at several levels, used by tests)."""
+    return adaptive_leaves(dim, N, ball_flag(dim, N, centre, radius), lmax, n_buf=n_buf)
