@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Benchmark of the FAS multigrid Poisson solve on one MI355X.
+
+One step = one complete solve of the uniform 256^3 octree workload (8^3-cell
+boxes, 37,449 boxes, 16,777,216 unknowns, Dirichlet values from two seeded
+Gaussians): one FMG cycle, then V(2,2) cycles until the max-norm of the
+composite residual has dropped by 1e-10.  Inputs are resident in HBM before
+the timed region starts.
+
+Prints one JSON line: throughput in unknowns/s, the roofline of the dominant
+kernel (the finest-level red-black half sweep) measured with HIP events on
+the solve's stream during the timed steps, and the FP64 CPU oracle timed on
+the host cores on the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("afmg_kernels.hip", "afmg_kernels.h", "afmg_internal.h"):
+        with open(os.path.join(ROOT, "paper_1701_04329_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(kernel_tag):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, or None if it is missing or was taken on
+    other kernel sources."""
+    path = os.path.join(PROFILES, f"{kernel_tag}_counters.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_hash = re.search(r"kernel source hash:\s*`?([0-9a-f]{16})", txt)
+    m_bytes = re.search(r"HBM bytes per launch \(calibrated\):\s*([0-9.eE+]+)", txt)
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+def make_workload(name):
+    from paper_1701_04329_amd import workloads as W
+    if name == "c2":
+        return W.config2(), dict(cycle="FMG", tol=1e-10)
+    if name == "c1":
+        return W.config1(), dict(cycle="V", tol=1e-10)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(w, solve_kw, budget_s=30.0):
+    """Time the oracle on the host cores: the same workload and stop rule."""
+    from oracle import oracle as O
+    t = O.Tree(w.dim, w.N, w.level, w.idx)
+    kw = dict(solve_kw)
+    t0 = time.perf_counter()
+    _, st = t.solve(w.rho, w.bc, **kw)
+    dt = time.perf_counter() - t0
+    return {
+        "value": w.n_unknowns / dt,
+        "unit": "unknowns/s",
+        "cores": O.num_threads(),
+        "kind": "oracle",
+        "sample": f"one full solve of the benchmark workload ({w.n_unknowns} unknowns, "
+                  f"{'FMG + ' if kw.get('cycle') == 'FMG' else ''}{st['cycles']} V-cycles to "
+                  f"{kw.get('tol', 1e-10):g}), FP64, OpenMP over boxes, {dt:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device copy (for HBM counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solve is not "
+              "distributed across GPUs", file=sys.stderr)
+        return 2
+
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 2
+    dev = torch.device("cuda", 0)
+
+    if args.copy_calibration:
+        n = (1 << 30) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
+        return 0
+
+    from paper_1701_04329_amd import afmg as A
+
+    w, solve_kw = make_workload(args.workload)
+    tree = A.Tree(w.dim, w.level, w.idx)
+    rho = tree.leaf_to_boxes(torch.tensor(w.rho, device=dev))
+    bc = tree.bc_rows(torch.tensor(w.bc, device=dev)) if tree.n_bfaces else None
+    u = torch.zeros((tree.n_boxes, tree.cells_per_box), dtype=torch.float64, device=dev)
+    opts = A.make_opts(**solve_kw)
+    ws = torch.empty(tree.workspace_bytes(opts), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step(profile):
+        # the FMG cycle starts from zero by definition; V-cycles restart from
+        # zero because u is zeroed before each step
+        if solve_kw["cycle"] != "FMG":
+            u.zero_()
+        return A.solve(tree, rho, bc, u, workspace=ws, stream=stream, profile=profile, **solve_kw)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    prof_ms = np.zeros(4)
+    prof_n = np.zeros(4, dtype=np.int64)
+    cycles = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, st = step(True)
+        prof_ms += np.array(st["prof_ms"])
+        prof_n += np.array(st["prof_n"], dtype=np.int64)
+        cycles.append(st["cycles"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    value = w.n_unknowns / (ms * 1e-3)
+
+    # dominant kernel: finest-level half sweep.  Algorithmic bytes per cell
+    # of the level: read the other colour (8 B / 2), read rho of the updated
+    # colour (8 B / 2), write the updated colour (8 B / 2) = 12 B.
+    n_fine = tree.n_leaves * tree.cells_per_box if args.workload in ("c2", "c1") else None
+    bytes_per_launch = 12.0 * n_fine
+    avg_ms = prof_ms[0] / max(prof_n[0], 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = committed_traffic(f"k_gsrb_{w.name}")
+    roofline = {
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "kernel": "k_gsrb (finest level, one half sweep)",
+        "algorithmic_bytes_per_launch": bytes_per_launch,
+        "avg_launch_ms": round(avg_ms, 5),
+        "launches_timed": int(prof_n[0]),
+    }
+    out = {
+        "metric": "Poisson unknowns/s to 1e-10 residual reduction (FP64 vs mixed); HBM % of peak",
+        "value": value,
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": w.name,
+            "dim": w.dim,
+            "box": f"{w.N}^{w.dim}",
+            "unknowns": int(w.n_unknowns),
+            "boxes": int(tree.n_boxes),
+            "cycle": "FMG + V(2,2)" if solve_kw["cycle"] == "FMG" else "V(2,2)",
+            "tol": solve_kw["tol"],
+            "v_cycles": int(np.median(cycles)),
+            "precision": "fp64",
+        },
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, solve_kw)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

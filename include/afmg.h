@@ -1,0 +1,176 @@
+/*
+ * afmg — FAS geometric multigrid for Poisson's equation on quadtree (2D) and
+ * octree (3D) box grids, on one AMD MI355X (gfx950).
+ *
+ * The method is the one of Teunissen & Ebert, "Afivo: a framework for
+ * quadtree/octree AMR with shared-memory parallelization and geometric
+ * multigrid methods" (Comput. Phys. Commun.), sections 2 and 3:
+ *   - grid of boxes of N^D cells, one root box covering [0,1]^D at level 1,
+ *     children of box (i,j[,k]) at (2i-1..2i, ...) one level finer (§2.1);
+ *   - Gauss-Seidel red-black smoothing (§3.1), FAS V-cycle and FMG cycle with
+ *     averaging restriction and 2-1-1 prolongation (§2.5, §3.2, eqs.
+ *     residual, coarse-rhs, coarse-corr);
+ *   - side ghost cells: copy from a same-level neighbour, Dirichlet values
+ *     through g = 2 b - u1, and the default conservative scheme at refinement
+ *     boundaries (§2.4, §3.3);
+ *   - extra coarse grids of N/2, ..., 2 cells below the root (§3.2).
+ * The operator is the 5-point (2D) / 7-point (3D) Laplacian: the library
+ * solves lap_h(u) = rho with Dirichlet boundary values.
+ *
+ * Conventions
+ *   - All entry points return an afmg_status; nothing is thrown or exits.
+ *     afmg_last_error() returns a thread-local message for the last failure.
+ *   - Box ids: after afmg_tree_create the library numbers boxes level by
+ *     level (level 1 first) and in Morton order within a level.
+ *     afmg_tree_leaf_boxes maps the caller's leaf order to box ids.
+ *   - Cell fields are device arrays of doubles laid out [n_boxes][N^D] in
+ *     box-id order, x fastest within a box, no ghost cells.
+ *   - Dirichlet values are a device array [n_bfaces][N^(D-1)]: one row per
+ *     physical-boundary side of a LEAF box, rows ordered as
+ *     afmg_tree_bfaces lists them; within a row the tangential axes are
+ *     taken in increasing order, the first fastest; values sit at the face
+ *     centres.  Values for coarser boxes are derived by averaging.
+ *   - Every device operation is enqueued on the caller's HIP stream.
+ *   - A tree may be used by one stream at a time.
+ */
+#ifndef AFMG_H
+#define AFMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct afmg_tree afmg_tree;
+
+typedef enum {
+    AFMG_OK = 0,
+    AFMG_NOT_CONVERGED = 1,  /* max_cycles reached before tol; stats filled */
+    AFMG_ERR_ARG = -1,       /* bad argument (null, misaligned, size, range) */
+    AFMG_ERR_TREE = -2,      /* leaves overlap, leave gaps, or break 2:1 balance */
+    AFMG_ERR_HIP = -3,       /* a HIP call or kernel failed */
+    AFMG_ERR_OOM = -4,       /* host or device allocation failed */
+    AFMG_ERR_NONFINITE = -5, /* a residual norm became NaN or Inf */
+    AFMG_ERR_DIVERGED = -6   /* residual grew for 3 consecutive cycles */
+} afmg_status;
+
+typedef enum { AFMG_CYCLE_V = 0, AFMG_CYCLE_FMG_V = 1 } afmg_cycle;
+typedef enum { AFMG_FP64 = 0, AFMG_MIXED = 1 } afmg_precision;
+
+#define AFMG_HIST 128
+
+typedef struct {
+    int cycle;        /* AFMG_CYCLE_V: V-cycles from the initial guess;
+                         AFMG_CYCLE_FMG_V: one FMG cycle from zero, then V-cycles */
+    int n_down;       /* smoothing steps before restriction (paper default 2) */
+    int n_up;         /* smoothing steps after correction (default 2) */
+    int n_base;       /* relaxation steps on the coarsest grid (default 4) */
+    double tol;       /* stop when max|r| <= tol * max|r0| (default 1e-10);
+                         r0 is the composite residual of u = 0 */
+    int max_cycles;   /* cap on V-cycles (default 100) */
+    int fixed_cycles; /* > 0: run exactly this many V-cycles, no stop test */
+    int use_guess;    /* 1: u holds the initial guess on leaf boxes (V only) */
+    int precision;    /* AFMG_FP64 (default) or AFMG_MIXED */
+    int profile;      /* 1: time the finest-level kernels with HIP events
+                         (stats.prof_*); adds one event pair per launch */
+} afmg_opts;
+
+/* kernel classes timed when opts.profile is set (finest level only) */
+enum {
+    AFMG_PROF_GSRB = 0,      /* one red or black half sweep */
+    AFMG_PROF_RESID = 1,     /* residual + restriction */
+    AFMG_PROF_PROLONG = 2,   /* prolongation + correction */
+    AFMG_PROF_FINAL = 3,     /* restriction of u + composite leaf residual */
+    AFMG_PROF_KINDS = 4
+};
+
+typedef struct {
+    int status;       /* final afmg_status of the solve */
+    int cycles;       /* V-cycles run (the FMG cycle is not counted) */
+    double r0_max, r0_l2;  /* residual norms of the initial guess (u = 0
+                              unless opts.use_guess) */
+    double r_max, r_l2;    /* residual norms on return */
+    double hist_max[AFMG_HIST]; /* max|r| after each V-cycle */
+    double hist_l2[AFMG_HIST];  /* sqrt(sum r^2 h^D) after each V-cycle */
+    double t_ms;      /* device time from first kernel to last norm */
+    double prof_ms[AFMG_PROF_KINDS]; /* summed kernel time per class */
+    int prof_n[AFMG_PROF_KINDS];     /* launches per class */
+} afmg_stats;
+
+typedef struct {
+    int dim, box_n;
+    int64_t n_boxes, n_leaves, n_bfaces;
+    int lmin, lmax;   /* lmin < 1: coarse grids below the root */
+    int64_t cells_per_box;
+    int64_t n_unknowns;  /* leaf cells */
+} afmg_tree_desc;
+
+typedef struct {
+    int level;
+    int idx[3];       /* 1-based spatial index (idx[2] = 1 in 2D) */
+    int parent;       /* box id, -1 for the root */
+    int leaf;
+    int nbr[6];       /* per side (-x,+x,-y,+y,-z,+z): >= 0 same-level box,
+                         -1 physical boundary, <= -2 refinement boundary with
+                         the coarser leaf box -nbr-2 */
+} afmg_box_desc;
+
+/* Fill opts with the paper's defaults (V(2,2), N_base = 4, tol 1e-10,
+   100 cycles, FP64). */
+void afmg_default_opts(afmg_opts *opts);
+
+/*
+ * Build a tree from its leaves (paper §2.1-§2.3).  level[i] >= 1 and the
+ * 1-based spatial index idx[3*i .. 3*i+2] (third entry ignored in 2D) name
+ * leaf i.  The leaves must tile [0,1]^D exactly and neighbouring leaves
+ * (across a side) may differ by at most one level.  Host-only: no device
+ * work happens here.  dim in {2,3}; box_n = 8.  On success *out owns the
+ * tree (free with afmg_tree_destroy).  Errors: AFMG_ERR_ARG, AFMG_ERR_TREE,
+ * AFMG_ERR_OOM.
+ */
+int afmg_tree_create(int dim, int box_n, int64_t n_leaves, const int32_t *level,
+                     const int32_t *idx, afmg_tree **out);
+
+void afmg_tree_destroy(afmg_tree *tree);
+
+int afmg_tree_info(const afmg_tree *tree, afmg_tree_desc *out);
+
+/* box id of each input leaf: out[n_leaves] (host array) */
+int afmg_tree_leaf_boxes(const afmg_tree *tree, int32_t *out);
+
+/* (box id, side) of each Dirichlet row: out[2*n_bfaces] (host array) */
+int afmg_tree_bfaces(const afmg_tree *tree, int32_t *out);
+
+int afmg_tree_box(const afmg_tree *tree, int64_t box, afmg_box_desc *out);
+
+/* Device workspace bytes afmg_solve needs for these options. */
+int afmg_workspace_bytes(const afmg_tree *tree, const afmg_opts *opts, size_t *bytes);
+
+/*
+ * Solve lap_h(u) = rho (paper §3, eq. mg-discr-equation) on the tree.
+ *   stream     hipStream_t to enqueue on (NULL = default stream)
+ *   rho        device [n_boxes][N^D]; only leaf boxes are read
+ *   bc         device [n_bfaces][N^(D-1)] Dirichlet values, or NULL for zero
+ *   u          device [n_boxes][N^D]; in: initial guess on leaf boxes if
+ *              opts->use_guess, out: solution on leaf boxes and its
+ *              restriction on parent boxes
+ *   workspace  device, >= afmg_workspace_bytes, 256-byte aligned; the
+ *              caller owns it; contents are scratch
+ * Arrays must be 8-byte aligned and must not overlap.  The call
+ * synchronises the stream once per V-cycle to read the residual norm.
+ * Returns AFMG_OK, AFMG_NOT_CONVERGED (stats filled), or an error.
+ */
+int afmg_solve(afmg_tree *tree, void *stream, const double *rho, const double *bc, double *u,
+               void *workspace, size_t workspace_bytes, const afmg_opts *opts,
+               afmg_stats *stats);
+
+/* Message for the last failing call on this thread. */
+const char *afmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AFMG_H */

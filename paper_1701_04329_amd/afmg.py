@@ -1,0 +1,287 @@
+"""Python binding of the afmg C-ABI (include/afmg.h).
+
+Argument marshalling only: every step of the solve runs in the HIP library
+(libafmg.so next to this file).  Device memory and streams come from PyTorch.
+There is no fallback: if the library is missing the import of this module's
+entry points raises.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libafmg.so")
+
+AFMG_OK = 0
+AFMG_NOT_CONVERGED = 1
+AFMG_ERR_ARG = -1
+AFMG_ERR_TREE = -2
+AFMG_ERR_HIP = -3
+AFMG_ERR_OOM = -4
+AFMG_ERR_NONFINITE = -5
+AFMG_ERR_DIVERGED = -6
+AFMG_HIST = 128
+
+CYCLES = {"V": 0, "FMG": 1}
+PRECISIONS = {"fp64": 0, "mixed": 1}
+
+
+class Opts(C.Structure):
+    _fields_ = [
+        ("cycle", C.c_int),
+        ("n_down", C.c_int),
+        ("n_up", C.c_int),
+        ("n_base", C.c_int),
+        ("tol", C.c_double),
+        ("max_cycles", C.c_int),
+        ("fixed_cycles", C.c_int),
+        ("use_guess", C.c_int),
+        ("precision", C.c_int),
+        ("profile", C.c_int),
+    ]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("status", C.c_int),
+        ("cycles", C.c_int),
+        ("r0_max", C.c_double),
+        ("r0_l2", C.c_double),
+        ("r_max", C.c_double),
+        ("r_l2", C.c_double),
+        ("hist_max", C.c_double * AFMG_HIST),
+        ("hist_l2", C.c_double * AFMG_HIST),
+        ("t_ms", C.c_double),
+        ("prof_ms", C.c_double * 4),
+        ("prof_n", C.c_int * 4),
+    ]
+
+    def to_dict(self):
+        n = min(self.cycles, AFMG_HIST)
+        return dict(status=self.status, cycles=self.cycles, r0_max=self.r0_max, r0_l2=self.r0_l2,
+                    r_max=self.r_max, r_l2=self.r_l2, hist_max=np.array(self.hist_max[:n]),
+                    hist_l2=np.array(self.hist_l2[:n]), t_ms=self.t_ms,
+                    prof_ms=list(self.prof_ms), prof_n=list(self.prof_n))
+
+
+class TreeDesc(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int),
+        ("box_n", C.c_int),
+        ("n_boxes", C.c_int64),
+        ("n_leaves", C.c_int64),
+        ("n_bfaces", C.c_int64),
+        ("lmin", C.c_int),
+        ("lmax", C.c_int),
+        ("cells_per_box", C.c_int64),
+        ("n_unknowns", C.c_int64),
+    ]
+
+
+class BoxDesc(C.Structure):
+    _fields_ = [
+        ("level", C.c_int),
+        ("idx", C.c_int * 3),
+        ("parent", C.c_int),
+        ("leaf", C.c_int),
+        ("nbr", C.c_int * 6),
+    ]
+
+
+EXPORTS = [
+    "afmg_default_opts", "afmg_tree_create", "afmg_tree_destroy", "afmg_tree_info",
+    "afmg_tree_leaf_boxes", "afmg_tree_bfaces", "afmg_tree_box", "afmg_workspace_bytes",
+    "afmg_solve", "afmg_last_error",
+]
+
+_lib = None
+
+
+class AfmgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"afmg error {code}: {msg}")
+        self.code = code
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        # PyTorch bundles its own HIP runtime.  Load it first so that the
+        # library binds to that same runtime (matched by soname); two HIP
+        # runtimes in one process cannot share the device.
+        import torch  # noqa: F401
+        L = C.CDLL(LIB_PATH)
+        vp, i32p, i64 = C.c_void_p, C.POINTER(C.c_int32), C.c_int64
+        L.afmg_default_opts.argtypes = [C.POINTER(Opts)]
+        L.afmg_default_opts.restype = None
+        L.afmg_tree_create.argtypes = [C.c_int, C.c_int, i64, i32p, i32p, C.POINTER(vp)]
+        L.afmg_tree_destroy.argtypes = [vp]
+        L.afmg_tree_destroy.restype = None
+        L.afmg_tree_info.argtypes = [vp, C.POINTER(TreeDesc)]
+        L.afmg_tree_leaf_boxes.argtypes = [vp, i32p]
+        L.afmg_tree_bfaces.argtypes = [vp, i32p]
+        L.afmg_tree_box.argtypes = [vp, i64, C.POINTER(BoxDesc)]
+        L.afmg_workspace_bytes.argtypes = [vp, C.POINTER(Opts), C.POINTER(C.c_size_t)]
+        L.afmg_solve.argtypes = [vp, vp, vp, vp, vp, vp, C.c_size_t, C.POINTER(Opts), C.POINTER(Stats)]
+        L.afmg_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def last_error():
+    return lib().afmg_last_error().decode()
+
+
+def _check(rc, allow=(AFMG_OK,)):
+    if rc not in allow:
+        raise AfmgError(rc, last_error())
+    return rc
+
+
+def make_opts(cycle="V", n_down=2, n_up=2, n_base=4, tol=1e-10, max_cycles=100, fixed_cycles=0,
+              use_guess=False, precision="fp64", profile=False):
+    o = Opts()
+    lib().afmg_default_opts(C.byref(o))
+    o.cycle = CYCLES[cycle]
+    o.n_down, o.n_up, o.n_base = n_down, n_up, n_base
+    o.tol = tol
+    o.max_cycles = max_cycles
+    o.fixed_cycles = fixed_cycles
+    o.use_guess = 1 if use_guess else 0
+    o.precision = PRECISIONS[precision]
+    o.profile = 1 if profile else 0
+    return o
+
+
+class Tree:
+    """A quadtree/octree of 8^D-cell boxes built from its leaves."""
+
+    def __init__(self, dim, level, idx, box_n=8):
+        L = lib()
+        level = np.ascontiguousarray(level, dtype=np.int32)
+        idx = np.ascontiguousarray(idx, dtype=np.int32).reshape(-1, 3)
+        if len(level) != len(idx):
+            raise ValueError("level and idx lengths differ")
+        h = C.c_void_p()
+        _check(L.afmg_tree_create(dim, box_n, len(level), level.ctypes.data_as(C.POINTER(C.c_int32)),
+                                  idx.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(h)))
+        self._h = h
+        d = TreeDesc()
+        _check(L.afmg_tree_info(h, C.byref(d)))
+        self.dim, self.box_n = d.dim, d.box_n
+        self.n_boxes, self.n_leaves, self.n_bfaces = d.n_boxes, d.n_leaves, d.n_bfaces
+        self.lmin, self.lmax = d.lmin, d.lmax
+        self.cells_per_box = d.cells_per_box
+        self.n_unknowns = d.n_unknowns
+        self.leaf_boxes = np.zeros(self.n_leaves, np.int32)
+        _check(L.afmg_tree_leaf_boxes(h, self.leaf_boxes.ctypes.data_as(C.POINTER(C.c_int32))))
+        bf = np.zeros(2 * max(1, self.n_bfaces), np.int32)
+        _check(L.afmg_tree_bfaces(h, bf.ctypes.data_as(C.POINTER(C.c_int32))))
+        self.bfaces = bf[: 2 * self.n_bfaces].reshape(-1, 2)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().afmg_tree_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def box(self, b):
+        d = BoxDesc()
+        _check(lib().afmg_tree_box(self._h, b, C.byref(d)))
+        return dict(level=d.level, idx=tuple(d.idx), parent=d.parent, leaf=bool(d.leaf), nbr=tuple(d.nbr))
+
+    def workspace_bytes(self, opts=None):
+        n = C.c_size_t()
+        _check(lib().afmg_workspace_bytes(self._h, C.byref(opts) if opts is not None else None, C.byref(n)))
+        return n.value
+
+    # ---- marshalling between the caller's leaf order and box order ---------
+    def leaf_to_boxes(self, leaf_field):
+        """[n_leaves, N^D] (leaf order) -> [n_boxes, N^D] (box order, zero on
+        parents); works for numpy arrays and torch tensors."""
+        if hasattr(leaf_field, "new_zeros"):
+            import torch
+            out = leaf_field.new_zeros((self.n_boxes, self.cells_per_box))
+            out[torch.as_tensor(self.leaf_boxes, device=leaf_field.device).long()] = leaf_field.reshape(
+                self.n_leaves, -1)
+            return out
+        out = np.zeros((self.n_boxes, self.cells_per_box), dtype=leaf_field.dtype)
+        out[self.leaf_boxes] = leaf_field.reshape(self.n_leaves, -1)
+        return out
+
+    def boxes_to_leaf(self, box_field):
+        if hasattr(box_field, "new_zeros"):
+            import torch
+            return box_field.reshape(self.n_boxes, -1)[torch.as_tensor(self.leaf_boxes, device=box_field.device).long()]
+        return box_field.reshape(self.n_boxes, -1)[self.leaf_boxes]
+
+    def bc_rows(self, bc_leaf):
+        """Dirichlet values [n_leaves, 2D, N^(D-1)] (leaf order) -> the rows
+        [n_bfaces, N^(D-1)] the library reads."""
+        box_to_leaf = np.full(self.n_boxes, -1, np.int64)
+        box_to_leaf[self.leaf_boxes] = np.arange(self.n_leaves)
+        q = box_to_leaf[self.bfaces[:, 0]]
+        s = self.bfaces[:, 1]
+        if hasattr(bc_leaf, "new_zeros"):
+            import torch
+            dev = bc_leaf.device
+            return bc_leaf[torch.as_tensor(q, device=dev), torch.as_tensor(s, device=dev)].contiguous()
+        return np.ascontiguousarray(bc_leaf[q, s])
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def solve(tree: Tree, rho, bc=None, u=None, *, cycle="V", tol=1e-10, max_cycles=100, fixed_cycles=0,
+          n_down=2, n_up=2, n_base=4, precision="fp64", workspace=None, stream=None, check=True,
+          profile=False):
+    """Solve lap_h(u) = rho on `tree`.
+
+    rho, u: torch float64 CUDA tensors [n_boxes, N^D] in box order; bc:
+    [n_bfaces, N^(D-1)] Dirichlet rows or None (zero).  u (if given) is the
+    initial guess and is overwritten; otherwise a new tensor is returned.
+    Returns (u, stats dict)."""
+    import torch
+
+    dev = rho.device
+    if dev.type != "cuda":
+        raise ValueError("rho must be a device tensor")
+    shape = (tree.n_boxes, tree.cells_per_box)
+    if rho.dtype != torch.float64 or tuple(rho.shape) != shape or not rho.is_contiguous():
+        raise ValueError(f"rho must be contiguous float64 {shape}")
+    use_guess = u is not None
+    if u is None:
+        u = torch.empty(shape, dtype=torch.float64, device=dev)
+    elif u.dtype != torch.float64 or tuple(u.shape) != shape or not u.is_contiguous():
+        raise ValueError(f"u must be contiguous float64 {shape}")
+    if bc is not None:
+        if bc.dtype != torch.float64 or bc.numel() != tree.n_bfaces * tree.box_n ** (tree.dim - 1):
+            raise ValueError("bc has the wrong dtype or size")
+        bc = bc.contiguous()
+    opts = make_opts(cycle, n_down, n_up, n_base, tol, max_cycles, fixed_cycles, use_guess, precision,
+                     profile)
+    nbytes = tree.workspace_bytes(opts)
+    if workspace is None or workspace.numel() * workspace.element_size() < nbytes:
+        workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    st = Stats()
+    with torch.cuda.device(dev):
+        rc = lib().afmg_solve(tree.handle, C.c_void_p(stream.cuda_stream), _ptr(rho), _ptr(bc), _ptr(u),
+                              _ptr(workspace), nbytes, C.byref(opts), C.byref(st))
+    if check:
+        _check(rc, allow=(AFMG_OK, AFMG_NOT_CONVERGED))
+    d = st.to_dict()
+    d["rc"] = rc
+    return u, d

@@ -1,0 +1,50 @@
+// Internal declarations shared by the host tree, the scheduler and the
+// kernels of the afmg library.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "afmg.h"
+
+namespace afmg {
+
+// Per-box topology as the kernels read it (64 bytes, one cache line).
+struct BoxInfo {
+    int32_t nbr[6];    // >= 0 same-level box, -1 physical, <= -2 coarse box -v-2
+    int32_t bcoff[6];  // Dirichlet row of a physical side, else -1
+    int32_t parent;    // parent box id, -1 for the root
+    int32_t flags;     // bit 0 leaf; bits 1..3 position inside the parent (x,y,z)
+    int32_t level;
+    int32_t pad;
+};
+static_assert(sizeof(BoxInfo) == 64, "BoxInfo must be 64 bytes");
+
+constexpr int FLAG_LEAF = 1;
+inline int oct_bit(int flags, int axis) { return (flags >> (1 + axis)) & 1; }
+
+// Host tree (built from leaves, immutable afterwards).
+struct HostTree {
+    int dim = 0, N = 0, lmin = 1, lmax = 1;
+    int64_t n_boxes = 0, n_leaves = 0;
+    int64_t n_bfaces_leaf = 0;   // Dirichlet rows supplied by the caller
+    int64_t n_bfaces_all = 0;    // plus rows derived for parent boxes
+    std::vector<BoxInfo> info;
+    std::vector<int32_t> ix, iy, iz;  // spatial index per box
+    std::vector<int64_t> lvl_off;     // box range of level l: [lvl_off[l], lvl_off[l+1]), l = 0..lmax+1 (0 unused)
+    std::vector<int32_t> leaf_box;    // box id of input leaf q
+    std::vector<int32_t> bface_box, bface_side;  // per Dirichlet row (leaf rows first)
+    // parent rows to derive, per level (fine to coarse order is by level)
+    int64_t level_begin(int l) const { return lvl_off[l]; }
+    int64_t level_count(int l) const { return lvl_off[l + 1] - lvl_off[l]; }
+    int64_t n_below_lmax() const { return lvl_off[lmax]; }  // boxes at levels < lmax
+};
+
+// Returns AFMG_OK or an error with msg filled.
+int build_tree(int dim, int N, int64_t n_leaves, const int32_t *level, const int32_t *idx,
+               HostTree &t, std::string &msg);
+
+void set_error(const std::string &msg);
+
+}  // namespace afmg

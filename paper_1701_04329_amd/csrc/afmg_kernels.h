@@ -1,0 +1,59 @@
+// Launch interface between the cycle scheduler and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "afmg_internal.h"
+
+namespace afmg {
+
+// Arguments of a kernel over one level (a contiguous box-id range).
+template <typename T>
+struct LevelArgs {
+    const BoxInfo *info;
+    T *u;               // [n_boxes][N^D]
+    const T *rho_user;  // caller's right-hand side (read on leaf boxes)
+    T *rho_w;           // right-hand side of parent boxes (FAS / restricted)
+    T *uold;            // copy v'_H (boxes of levels < lmax)
+    const T *bc;        // Dirichlet rows (leaf rows, then derived rows)
+    int64_t b0;         // first box of the range
+    int nb;             // number of boxes
+    int homog;          // 1: zero Dirichlet values
+    T h2, ih2;          // h^2 and 1/h^2 of the level
+};
+
+enum class Op { GSRB, RESID_RESTRICT, COARSE_RHS, PROLONG, RESTRICT_RHO };
+
+enum { COARSE_V_FROM_2 = 0, COARSE_V_TOP1 = 1, COARSE_FMG = 2 };
+
+// Arguments of the one-workgroup kernel for levels <= 1 (root box = box 0).
+template <typename T>
+struct CoarseArgs {
+    const BoxInfo *info;
+    T *u;
+    const T *rho_user;
+    T *rho_w;
+    T *uold;            // may be null when the tree has one level
+    const double *bc;
+    int mode;
+    int homog;
+    int n_down, n_up, n_base;
+};
+
+template <int D, int N, typename T>
+void launch_level(Op op, const LevelArgs<T> &a, int colour, hipStream_t st);
+template <int D, int N, typename T>
+void launch_final(const LevelArgs<T> &a, double *partial, int64_t part0, double hD, hipStream_t st);
+template <int D, int N>
+int final_wgs(int64_t nb);
+void launch_reduce(const double *partial, int64_t n, double *out, hipStream_t st);
+template <int D, int N, typename T>
+void launch_coarse(const CoarseArgs<T> &a, hipStream_t st);
+template <int D, int N>
+void launch_bc_derive(const BoxInfo *info, int64_t b0, int64_t nb, double *bc, hipStream_t st);
+template <typename T>
+void launch_copy(const T *src, T *dst, int64_t n, hipStream_t st);
+template <typename T>
+void launch_fill(T *dst, int64_t n, T v, hipStream_t st);
+
+}  // namespace afmg

@@ -1,0 +1,860 @@
+// HIP kernels (gfx950) of the FAS multigrid Poisson solve on box grids.
+//
+// Every kernel works on a contiguous range of box ids (one level).  A box's
+// N^D cells are staged in LDS together with the side ghosts it needs; the
+// ghosts are computed on the fly from the neighbouring boxes (paper §2.4,
+// §3.3), so no ghost layer is ever stored in HBM.  Workgroups are 256 threads
+// (four wave64); in 3D one box per workgroup, in 2D eight boxes.  Workgroup
+// ids are remapped so that each of the eight XCDs processes a contiguous run
+// of boxes: Morton-ordered siblings and neighbours then share one L2.
+#include <hip/hip_runtime.h>
+
+#include "afmg_internal.h"
+#include "afmg_kernels.h"
+
+namespace afmg {
+
+template <int D, int N>
+struct Geo {
+    static constexpr int C = D == 3 ? N * N * N : N * N;  // cells per box
+    static constexpr int F = D == 3 ? N * N : N;          // cells per side
+    static constexpr int P = N + 2;
+    static constexpr int PC = D == 3 ? P * P * P : P * P;  // padded cells
+    static constexpr int HALF = C / 2;
+    static constexpr int BPW = HALF >= 256 ? 1 : 256 / HALF;  // boxes per workgroup
+    static constexpr int TPB = 256 / BPW;                     // threads per box
+    static constexpr int NG = 2 * D * F;                      // side ghosts per box
+    static constexpr int H = N / 2;                           // parent cells per axis under a box
+    static constexpr int HC = D == 3 ? H * H * H : H * H;
+    static constexpr int HF = D == 3 ? H * H : H;
+    static constexpr int Q = H + 2;
+    static constexpr int QC = D == 3 ? Q * Q * Q : Q * Q;
+};
+
+template <int D, int N>
+__device__ __forceinline__ int padi(int i, int j, int k) {
+    constexpr int P = N + 2;
+    return D == 3 ? (i + 1) + P * ((j + 1) + P * (k + 1)) : (i + 1) + P * (j + 1);
+}
+template <int D, int N>
+__device__ __forceinline__ int offi(int i, int j, int k) {
+    return D == 3 ? i + N * (j + N * k) : i + N * j;
+}
+template <int D, int N>
+__device__ __forceinline__ void decode(int c, int &i, int &j, int &k) {
+    i = c % N;
+    j = (c / N) % N;
+    k = D == 3 ? c / (N * N) : 0;
+}
+__device__ __forceinline__ int obit(int flags, int axis) { return (flags >> (1 + axis)) & 1; }
+
+// Contiguous run of workgroup ids per XCD (workgroups are dispatched to the
+// eight XCDs round-robin).  Bijective on [0, G).
+__device__ __forceinline__ int xcd_remap(int w, int G) {
+    const int q = G >> 3, r = G & 7;
+    const int x = w & 7, p = w >> 3;
+    return x < r ? x * (q + 1) + p : r * (q + 1) + (x - r) * q + p;
+}
+
+// ---------------------------------------------------------------------------
+// ghost cells
+// ---------------------------------------------------------------------------
+
+// Side ghosts of box bi for field u whose interior is staged in s (padded).
+// Same-level neighbour: copy of its face layer.  Physical side: 2 b - u1
+// (b = 0 when homog).  Refinement boundary (paper §3.3, default scheme):
+//   2D  g = 1/2 uH + u1 - 1/4 (u1' + u2)
+//   3D  g = 1/2 uH + 5/4 u1 - 1/4 (u2 + u1' + u1'')
+// uH: cell of the coarser neighbour box containing the ghost centre; u2: next
+// cell inward; u1', u1'': tangential partners of u1 inside one coarse cell.
+template <int D, int N, typename T>
+__device__ void fill_ghosts(T *s, const BoxInfo &bi, const T *__restrict__ u,
+                            const T *__restrict__ bc, int homog, int t, int nt) {
+    using G = Geo<D, N>;
+    for (int g = t; g < G::NG; g += nt) {
+        const int side = g / G::F, m = g - side * G::F;
+        const int d = side >> 1, hi = side & 1;
+        const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+        const int a = m % N, c = D == 3 ? m / N : 0;
+        int x[3];
+        x[t1] = a;
+        x[t2] = c;
+        x[d] = hi ? N - 1 : 0;
+        const T u1 = s[padi<D, N>(x[0], x[1], x[2])];
+        const int v = bi.nbr[side];
+        T val;
+        if (v >= 0) {
+            int y[3] = {x[0], x[1], x[2]};
+            y[d] = hi ? 0 : N - 1;
+            val = u[(size_t)v * G::C + offi<D, N>(y[0], y[1], y[2])];
+        } else if (v == -1) {
+            const T bv = homog ? T(0) : bc[(size_t)bi.bcoff[side] * G::F + m];
+            val = T(2) * bv - u1;
+        } else {
+            const int cb = -v - 2;
+            int q[3];
+            q[d] = hi ? 0 : N - 1;
+            q[t1] = obit(bi.flags, t1) * (N / 2) + (a >> 1);
+            q[t2] = D == 3 ? obit(bi.flags, t2) * (N / 2) + (c >> 1) : 0;
+            const T uH = u[(size_t)cb * G::C + offi<D, N>(q[0], q[1], q[2])];
+            int x2[3] = {x[0], x[1], x[2]};
+            x2[d] = hi ? N - 2 : 1;
+            const T u2 = s[padi<D, N>(x2[0], x2[1], x2[2])];
+            int p1[3] = {x[0], x[1], x[2]};
+            p1[t1] ^= 1;
+            const T u1p = s[padi<D, N>(p1[0], p1[1], p1[2])];
+            if (D == 2) {
+                val = T(0.5) * uH + u1 - T(0.25) * (u1p + u2);
+            } else {
+                int p2[3] = {x[0], x[1], x[2]};
+                p2[t2] ^= 1;
+                const T u1pp = s[padi<D, N>(p2[0], p2[1], p2[2])];
+                val = T(0.5) * uH + T(1.25) * u1 - T(0.25) * ((u2 + u1p) + u1pp);
+            }
+        }
+        int gx[3] = {x[0], x[1], x[2]};
+        gx[d] = hi ? N : -1;
+        s[padi<D, N>(gx[0], gx[1], gx[2])] = val;
+    }
+}
+
+// Ghost of the correction delta = u - uold of box p on side `side` next to
+// its face cell x: the ghost formulas are linear, so the ghost of the
+// difference is the difference of the ghosts; Dirichlet values cancel.
+template <int D, int N, typename T>
+__device__ T delta_ghost(const BoxInfo &pi, int64_t p, int side, const int x[3],
+                         const T *__restrict__ u, const T *__restrict__ uold) {
+    using G = Geo<D, N>;
+    const int d = side >> 1, hi = side & 1;
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    const size_t pb = (size_t)p * G::C;
+    const int v = pi.nbr[side];
+    auto del = [&](size_t base, int i, int j, int k) {
+        const size_t o = base + offi<D, N>(i, j, k);
+        return u[o] - uold[o];
+    };
+    if (v >= 0) {
+        int y[3] = {x[0], x[1], x[2]};
+        y[d] = hi ? 0 : N - 1;
+        return del((size_t)v * G::C, y[0], y[1], y[2]);
+    }
+    const T d1 = del(pb, x[0], x[1], x[2]);
+    if (v == -1) return -d1;
+    const int cb = -v - 2;
+    int q[3];
+    q[d] = hi ? 0 : N - 1;
+    q[t1] = obit(pi.flags, t1) * (N / 2) + (x[t1] >> 1);
+    q[t2] = D == 3 ? obit(pi.flags, t2) * (N / 2) + (x[t2] >> 1) : 0;
+    const T dH = del((size_t)cb * G::C, q[0], q[1], q[2]);
+    int x2[3] = {x[0], x[1], x[2]};
+    x2[d] = hi ? N - 2 : 1;
+    int p1[3] = {x[0], x[1], x[2]};
+    p1[t1] ^= 1;
+    const T d2 = del(pb, x2[0], x2[1], x2[2]);
+    const T d1p = del(pb, p1[0], p1[1], p1[2]);
+    if (D == 2) return T(0.5) * dH + d1 - T(0.25) * (d1p + d2);
+    int p2[3] = {x[0], x[1], x[2]};
+    p2[t2] ^= 1;
+    const T d1pp = del(pb, p2[0], p2[1], p2[2]);
+    return T(0.5) * dH + T(1.25) * d1 - T(0.25) * ((d2 + d1p) + d1pp);
+}
+
+template <int D, int N, typename T>
+__device__ __forceinline__ T nb_sum(const T *s, int i, int j, int k) {
+    if (D == 2)
+        return (s[padi<D, N>(i - 1, j, k)] + s[padi<D, N>(i + 1, j, k)]) +
+               (s[padi<D, N>(i, j - 1, k)] + s[padi<D, N>(i, j + 1, k)]);
+    return (s[padi<D, N>(i - 1, j, k)] + s[padi<D, N>(i + 1, j, k)]) +
+           (s[padi<D, N>(i, j - 1, k)] + s[padi<D, N>(i, j + 1, k)]) +
+           (s[padi<D, N>(i, j, k - 1)] + s[padi<D, N>(i, j, k + 1)]);
+}
+
+// Workgroup -> box slot of this thread.
+template <int D, int N>
+struct Slot {
+    int64_t b;   // box id (clamped to a valid box)
+    bool valid;  // false for the padding slots of the last workgroup
+    int slot, t; // slot in the workgroup, thread in the slot
+};
+template <int D, int N>
+__device__ __forceinline__ Slot<D, N> slot_of(int64_t b0, int nb) {
+    using G = Geo<D, N>;
+    Slot<D, N> r;
+    const int w = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    r.slot = (int)threadIdx.x / G::TPB;
+    r.t = (int)threadIdx.x % G::TPB;
+    const int bl = w * G::BPW + r.slot;
+    r.valid = bl < nb;
+    r.b = b0 + (r.valid ? bl : 0);
+    return r;
+}
+
+template <int D, int N, typename T>
+__device__ __forceinline__ void stage_interior(T *s, const T *__restrict__ ub, int t) {
+    using G = Geo<D, N>;
+    for (int c = t; c < G::C; c += G::TPB) {
+        int i, j, k;
+        decode<D, N>(c, i, j, k);
+        s[padi<D, N>(i, j, k)] = ub[c];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Gauss-Seidel red-black half sweep (paper §3.1)
+// ---------------------------------------------------------------------------
+// Red cells: 1-based index sum even, i.e. (i0 + j0 + k0 + D) even for 0-based
+// indices (box offsets are multiples of N, which is even).
+template <int D, int N, typename T>
+__global__ __launch_bounds__(256) void k_gsrb(LevelArgs<T> a, int colour) {
+    using G = Geo<D, N>;
+    __shared__ T sm[G::BPW * G::PC];
+    const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb);
+    T *s = sm + sl.slot * G::PC;
+    const BoxInfo bi = a.info[sl.b];
+    T *ub = a.u + (size_t)sl.b * G::C;
+    if (sl.valid) stage_interior<D, N, T>(s, ub, sl.t);
+    __syncthreads();
+    if (sl.valid) fill_ghosts<D, N, T>(s, bi, a.u, a.bc, a.homog, sl.t, G::TPB);
+    __syncthreads();
+    if (!sl.valid) return;
+    const T *rb = ((bi.flags & FLAG_LEAF) ? a.rho_user : a.rho_w) + (size_t)sl.b * G::C;
+    constexpr int HN = N / 2;
+    const int t = sl.t;
+    int i, j, k;
+    if (D == 3) {
+        k = t / (N * HN);
+        j = (t / HN) % N;
+    } else {
+        k = 0;
+        j = t / HN;
+    }
+    i = 2 * (t % HN) + ((colour + D + j + k) & 1);
+    const int c = offi<D, N>(i, j, k);
+    const T sum = nb_sum<D, N, T>(s, i, j, k);
+    ub[c] = (sum - a.h2 * rb[c]) / T(2 * D);
+}
+
+// ---------------------------------------------------------------------------
+// residual (eq. residual) and restriction by averaging (paper §2.5)
+// ---------------------------------------------------------------------------
+// For every box of level l: r = rho - L u; the box's octant of its parent
+// receives mean(u) in u and mean(r) in rho_w (the restricted residual, which
+// k_coarse_rhs then turns into the FAS right-hand side).
+template <int D, int N, typename T>
+__device__ __forceinline__ void restrict_octant(const T *s, T *__restrict__ dst, const BoxInfo &bi,
+                                                int t, int nt, bool padded) {
+    using G = Geo<D, N>;
+    const T w = D == 3 ? T(0.125) : T(0.25);
+    for (int pc = t; pc < G::HC; pc += nt) {
+        const int I = pc % G::H, J = (pc / G::H) % G::H, K = D == 3 ? pc / (G::H * G::H) : 0;
+        T acc = T(0);
+        for (int dk = 0; dk < (D == 3 ? 2 : 1); dk++)
+            for (int dj = 0; dj < 2; dj++)
+                for (int di = 0; di < 2; di++) {
+                    const int i = 2 * I + di, j = 2 * J + dj, k = D == 3 ? 2 * K + dk : 0;
+                    acc += padded ? s[padi<D, N>(i, j, k)] : s[offi<D, N>(i, j, k)];
+                }
+        const int X = obit(bi.flags, 0) * G::H + I, Y = obit(bi.flags, 1) * G::H + J,
+                  Z = D == 3 ? obit(bi.flags, 2) * G::H + K : 0;
+        dst[(size_t)bi.parent * G::C + offi<D, N>(X, Y, Z)] = w * acc;
+    }
+}
+
+template <int D, int N, typename T>
+__global__ __launch_bounds__(256) void k_resid_restrict(LevelArgs<T> a) {
+    using G = Geo<D, N>;
+    __shared__ T sm[G::BPW * G::PC];
+    __shared__ T rs[G::BPW * G::C];
+    const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb);
+    T *s = sm + sl.slot * G::PC;
+    T *r = rs + sl.slot * G::C;
+    const BoxInfo bi = a.info[sl.b];
+    const T *ub = a.u + (size_t)sl.b * G::C;
+    if (sl.valid) stage_interior<D, N, T>(s, ub, sl.t);
+    __syncthreads();
+    if (sl.valid) fill_ghosts<D, N, T>(s, bi, a.u, a.bc, a.homog, sl.t, G::TPB);
+    __syncthreads();
+    if (sl.valid) {
+        const T *rb = ((bi.flags & FLAG_LEAF) ? a.rho_user : a.rho_w) + (size_t)sl.b * G::C;
+        for (int c = sl.t; c < G::C; c += G::TPB) {
+            int i, j, k;
+            decode<D, N>(c, i, j, k);
+            r[c] = rb[c] - (nb_sum<D, N, T>(s, i, j, k) - T(2 * D) * s[padi<D, N>(i, j, k)]) * a.ih2;
+        }
+    }
+    __syncthreads();
+    if (!sl.valid) return;
+    restrict_octant<D, N, T>(s, a.u, bi, sl.t, G::TPB, true);
+    restrict_octant<D, N, T>(r, a.rho_w, bi, sl.t, G::TPB, false);
+}
+
+// ---------------------------------------------------------------------------
+// FAS coarse right-hand side (eq. coarse-rhs) and the copy v'_H
+// ---------------------------------------------------------------------------
+// Boxes of level l-1: uold <- u; on parents rho_w <- rbar + L_H u (rho_w
+// holds rbar = the restricted residual).
+template <int D, int N, typename T>
+__global__ __launch_bounds__(256) void k_coarse_rhs(LevelArgs<T> a) {
+    using G = Geo<D, N>;
+    __shared__ T sm[G::BPW * G::PC];
+    const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb);
+    T *s = sm + sl.slot * G::PC;
+    const BoxInfo bi = a.info[sl.b];
+    const T *ub = a.u + (size_t)sl.b * G::C;
+    const bool parent = !(bi.flags & FLAG_LEAF);
+    if (sl.valid) {
+        T *ob = a.uold + (size_t)sl.b * G::C;
+        for (int c = sl.t; c < G::C; c += G::TPB) {
+            int i, j, k;
+            decode<D, N>(c, i, j, k);
+            const T v = ub[c];
+            ob[c] = v;
+            s[padi<D, N>(i, j, k)] = v;
+        }
+    }
+    __syncthreads();
+    if (sl.valid && parent) fill_ghosts<D, N, T>(s, bi, a.u, a.bc, a.homog, sl.t, G::TPB);
+    __syncthreads();
+    if (!sl.valid || !parent) return;
+    T *rw = a.rho_w + (size_t)sl.b * G::C;
+    for (int c = sl.t; c < G::C; c += G::TPB) {
+        int i, j, k;
+        decode<D, N>(c, i, j, k);
+        rw[c] = rw[c] + (nb_sum<D, N, T>(s, i, j, k) - T(2 * D) * s[padi<D, N>(i, j, k)]) * a.ih2;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// coarse-grid correction (eq. coarse-corr) with 2-1-1 prolongation (§2.5)
+// ---------------------------------------------------------------------------
+// Boxes of level l: u += P(delta), delta = u - uold of the parent (level
+// l-1).  The parent's octant under the box plus a one-cell face halo is
+// staged; halo cells outside the parent come from delta_ghost.
+//   2D: 1/2 d(P) + 1/4 d(P + sx ex) + 1/4 d(P + sy ey)
+//   3D: 1/4 [d(P) + d(P + sx ex) + d(P + sy ey) + d(P + sz ez)]
+// with s = -1 for a fine cell in the lower half of its parent cell.
+template <int D, int N>
+__device__ __forceinline__ int qpad(int I, int J, int K) {
+    constexpr int Q = N / 2 + 2;
+    return D == 3 ? (I + 1) + Q * ((J + 1) + Q * (K + 1)) : (I + 1) + Q * (J + 1);
+}
+
+template <int D, int N, typename T>
+__global__ __launch_bounds__(256) void k_prolong(LevelArgs<T> a) {
+    using G = Geo<D, N>;
+    __shared__ T qs[G::BPW * G::QC];
+    const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb);
+    T *q = qs + sl.slot * G::QC;
+    const BoxInfo bi = a.info[sl.b];
+    if (sl.valid) {
+        const int64_t p = bi.parent;
+        const BoxInfo pi = a.info[p];
+        const int o[3] = {obit(bi.flags, 0) * G::H, obit(bi.flags, 1) * G::H,
+                          D == 3 ? obit(bi.flags, 2) * G::H : 0};
+        const size_t pb = (size_t)p * G::C;
+        // octant interior
+        for (int pc = sl.t; pc < G::HC; pc += G::TPB) {
+            const int I = pc % G::H, J = (pc / G::H) % G::H, K = D == 3 ? pc / (G::H * G::H) : 0;
+            const size_t oo = pb + offi<D, N>(o[0] + I, o[1] + J, o[2] + K);
+            q[qpad<D, N>(I, J, K)] = a.u[oo] - a.uold[oo];
+        }
+        // face halos
+        for (int hc = sl.t; hc < 2 * D * G::HF; hc += G::TPB) {
+            const int side = hc / G::HF, m = hc % G::HF;
+            const int d = side >> 1, hi = side & 1;
+            const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+            int L[3];
+            L[t1] = m % G::H;
+            L[t2] = D == 3 ? m / G::H : 0;
+            L[d] = hi ? G::H : -1;
+            int X[3] = {o[0] + L[0], o[1] + L[1], o[2] + L[2]};
+            if (D == 2) X[2] = 0;
+            T val;
+            if (X[d] >= 0 && X[d] < N) {
+                const size_t oo = pb + offi<D, N>(X[0], X[1], X[2]);
+                val = a.u[oo] - a.uold[oo];
+            } else {
+                int x[3] = {X[0], X[1], X[2]};
+                x[d] = hi ? N - 1 : 0;
+                val = delta_ghost<D, N, T>(pi, p, 2 * d + hi, x, a.u, a.uold);
+            }
+            q[qpad<D, N>(L[0], L[1], L[2])] = val;
+        }
+    }
+    __syncthreads();
+    if (!sl.valid) return;
+    T *ub = a.u + (size_t)sl.b * G::C;
+    for (int c = sl.t; c < G::C; c += G::TPB) {
+        int i, j, k;
+        decode<D, N>(c, i, j, k);
+        const int I = i >> 1, J = j >> 1, K = k >> 1;
+        const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
+        T v;
+        if (D == 2) {
+            v = T(0.5) * q[qpad<D, N>(I, J, 0)] + T(0.25) * q[qpad<D, N>(I + sx, J, 0)] +
+                T(0.25) * q[qpad<D, N>(I, J + sy, 0)];
+        } else {
+            v = T(0.25) * (((q[qpad<D, N>(I, J, K)] + q[qpad<D, N>(I + sx, J, K)]) +
+                            q[qpad<D, N>(I, J + sy, K)]) +
+                           q[qpad<D, N>(I, J, K + sz)]);
+        }
+        ub[c] = ub[c] + v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// end of a cycle: restriction of u and the composite leaf residual
+// ---------------------------------------------------------------------------
+// Boxes of level l: the octant of the parent receives mean(u) (l >= 2); on
+// leaves r = rho - L u, and the workgroup writes (max |r|, sum r^2 h^D) to
+// partial[part0 + workgroup].
+template <int D, int N, typename T>
+__global__ __launch_bounds__(256) void k_final(LevelArgs<T> a, double *partial, int64_t part0,
+                                               double hD) {
+    using G = Geo<D, N>;
+    __shared__ T sm[G::BPW * G::PC];
+    __shared__ double red_m[256], red_s[256];
+    const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb);
+    T *s = sm + sl.slot * G::PC;
+    const BoxInfo bi = a.info[sl.b];
+    const T *ub = a.u + (size_t)sl.b * G::C;
+    const bool leaf = bi.flags & FLAG_LEAF;
+    if (sl.valid) stage_interior<D, N, T>(s, ub, sl.t);
+    __syncthreads();
+    if (sl.valid && leaf) fill_ghosts<D, N, T>(s, bi, a.u, a.bc, a.homog, sl.t, G::TPB);
+    __syncthreads();
+    double mx = 0.0, ss = 0.0;
+    if (sl.valid) {
+        if (bi.parent >= 0) restrict_octant<D, N, T>(s, a.u, bi, sl.t, G::TPB, true);
+        if (leaf) {
+            const T *rb = a.rho_user + (size_t)sl.b * G::C;
+            for (int c = sl.t; c < G::C; c += G::TPB) {
+                int i, j, k;
+                decode<D, N>(c, i, j, k);
+                const double r = (double)(rb[c] - (nb_sum<D, N, T>(s, i, j, k) -
+                                                   T(2 * D) * s[padi<D, N>(i, j, k)]) * a.ih2);
+                mx = fmax(mx, fabs(r));
+                ss += r * r;
+            }
+        }
+    }
+    red_m[threadIdx.x] = mx;
+    red_s[threadIdx.x] = ss;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red_m[threadIdx.x] = fmax(red_m[threadIdx.x], red_m[threadIdx.x + w]);
+            red_s[threadIdx.x] += red_s[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * (part0 + blockIdx.x) + 0] = red_m[0];
+        partial[2 * (part0 + blockIdx.x) + 1] = red_s[0] * hD;
+    }
+}
+
+// One workgroup: out[0] = max over partial maxima, out[1] = sqrt(sum of
+// partial sums); fixed reduction order.
+__global__ __launch_bounds__(256) void k_reduce(const double *partial, int64_t n, double *out) {
+    __shared__ double rm[256], rsum[256];
+    double mx = 0.0, ss = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        mx = fmax(mx, partial[2 * i]);
+        ss += partial[2 * i + 1];
+    }
+    rm[threadIdx.x] = mx;
+    rsum[threadIdx.x] = ss;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            rm[threadIdx.x] = fmax(rm[threadIdx.x], rm[threadIdx.x + w]);
+            rsum[threadIdx.x] += rsum[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        // propagate NaN: fmax drops NaN operands, the sum keeps them
+        const double s = rsum[0];
+        out[0] = (s == s) ? rm[0] : s;
+        out[1] = sqrt(s);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// small helpers: restriction of rho (FMG), copies, Dirichlet rows of parents
+// ---------------------------------------------------------------------------
+template <int D, int N, typename T>
+__global__ __launch_bounds__(256) void k_restrict_rho(LevelArgs<T> a) {
+    using G = Geo<D, N>;
+    const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb);
+    if (!sl.valid) return;
+    const BoxInfo bi = a.info[sl.b];
+    const T *rb = ((bi.flags & FLAG_LEAF) ? a.rho_user : a.rho_w) + (size_t)sl.b * G::C;
+    restrict_octant<D, N, T>(rb, a.rho_w, bi, sl.t, G::TPB, false);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_copy(const T *__restrict__ src, T *__restrict__ dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        dst[i] = src[i];
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill(T *__restrict__ dst, int64_t n, T v) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        dst[i] = v;
+}
+
+// Boxes of level l (children): each physical side writes the covered part of
+// its parent's Dirichlet row as means of 2^(D-1) child face values.
+template <int D, int N>
+__global__ __launch_bounds__(256) void k_bc_derive(const BoxInfo *__restrict__ info, int64_t b0,
+                                                   int nb, double *bc) {
+    using G = Geo<D, N>;
+    const int64_t bl = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t work = (int64_t)nb * 2 * D * G::HF;
+    if (bl >= work) return;
+    const int64_t b = b0 + bl / (2 * D * G::HF);
+    const int rem = (int)(bl % (2 * D * G::HF));
+    const int side = rem / G::HF, m = rem % G::HF;
+    const BoxInfo bi = info[b];
+    if (bi.nbr[side] != -1 || bi.parent < 0) return;
+    const BoxInfo pi = info[bi.parent];
+    const int d = side >> 1;
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    const int A = m % G::H, Cc = D == 3 ? m / G::H : 0;
+    const double *cr = bc + (size_t)bi.bcoff[side] * G::F;
+    double acc = 0.0;
+    for (int dc = 0; dc < (D == 3 ? 2 : 1); dc++)
+        for (int da = 0; da < 2; da++) acc += cr[(2 * A + da) + N * (2 * Cc + dc)];
+    const int pa = obit(bi.flags, t1) * G::H + A;
+    const int pc = D == 3 ? obit(bi.flags, t2) * G::H + Cc : 0;
+    bc[(size_t)pi.bcoff[side] * G::F + pa + N * pc] = acc * (D == 3 ? 0.25 : 0.5);
+}
+
+// ---------------------------------------------------------------------------
+// levels <= 1: the root box and the coarse grids below it, one workgroup
+// ---------------------------------------------------------------------------
+// The grids of N, N/2, ..., 2 cells per side (levels 1, 0, ..., lmin) are
+// single boxes with Dirichlet sides only; they live in LDS with a stored ghost
+// layer, in FP64 for every precision of the caller's arrays.
+template <int D, int N>
+struct CoarseGeo {
+    static constexpr int lg(int n) { return n <= 1 ? 0 : 1 + lg(n / 2); }
+    static constexpr int NL = lg(N);  // grids of N, N/2, ..., 2 cells
+    static constexpr int n(int li) { return N >> li; }
+    static constexpr int psz(int li) { return D == 3 ? (n(li) + 2) * (n(li) + 2) * (n(li) + 2) : (n(li) + 2) * (n(li) + 2); }
+    static constexpr int poff(int li) { return li == 0 ? 0 : poff(li - 1) + psz(li - 1); }
+    static constexpr int PTOT = poff(NL);
+    static constexpr int fsz(int li) { return D == 3 ? n(li) * n(li) : n(li); }
+    static constexpr int boff(int li) { return li == 0 ? 0 : boff(li - 1) + 2 * D * fsz(li - 1); }
+    static constexpr int BTOT = boff(NL);
+};
+
+template <int D, int N>
+struct CoarseState {
+    using CG = CoarseGeo<D, N>;
+    double *u, *rho, *uold, *res, *bc;
+    int n_down, n_up, n_base;
+
+    __device__ int pidx(int li, int i, int j, int k) const {
+        const int m = CG::n(li) + 2;
+        return CG::poff(li) + (D == 3 ? (i + 1) + m * ((j + 1) + m * (k + 1)) : (i + 1) + m * (j + 1));
+    }
+    __device__ static double hlev(int li) { return (double)(1 << li) / (double)N; }
+
+    __device__ void fill(double *f, int li) const {
+        const int n = CG::n(li), F = CG::fsz(li);
+        for (int g = threadIdx.x; g < 2 * D * F; g += blockDim.x) {
+            const int side = g / F, m = g % F;
+            const int d = side >> 1, hi = side & 1;
+            const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+            int x[3];
+            x[t1] = m % n;
+            x[t2] = D == 3 ? m / n : 0;
+            x[d] = hi ? n - 1 : 0;
+            const double u1 = f[pidx(li, x[0], x[1], x[2])];
+            const double bv = bc[CG::boff(li) + side * F + m];
+            x[d] = hi ? n : -1;
+            f[pidx(li, x[0], x[1], x[2])] = 2.0 * bv - u1;
+        }
+        __syncthreads();
+    }
+    __device__ double nbs(const double *f, int li, int i, int j, int k) const {
+        if (D == 2)
+            return (f[pidx(li, i - 1, j, k)] + f[pidx(li, i + 1, j, k)]) +
+                   (f[pidx(li, i, j - 1, k)] + f[pidx(li, i, j + 1, k)]);
+        return (f[pidx(li, i - 1, j, k)] + f[pidx(li, i + 1, j, k)]) +
+               (f[pidx(li, i, j - 1, k)] + f[pidx(li, i, j + 1, k)]) +
+               (f[pidx(li, i, j, k - 1)] + f[pidx(li, i, j, k + 1)]);
+    }
+    __device__ void cell(int li, int c, int &i, int &j, int &k) const {
+        const int n = CG::n(li);
+        i = c % n;
+        j = (c / n) % n;
+        k = D == 3 ? c / (n * n) : 0;
+    }
+    __device__ int ncell(int li) const { return D == 3 ? CG::n(li) * CG::n(li) * CG::n(li) : CG::n(li) * CG::n(li); }
+
+    __device__ void half(int li, int colour) const {
+        fill(u, li);
+        const double h = hlev(li), h2 = h * h;
+        for (int c = threadIdx.x; c < ncell(li); c += blockDim.x) {
+            int i, j, k;
+            cell(li, c, i, j, k);
+            if (((i + j + k + D) & 1) != colour) continue;
+            const int p = pidx(li, i, j, k);
+            u[p] = (nbs(u, li, i, j, k) - h2 * rho[p]) / double(2 * D);
+        }
+        __syncthreads();
+    }
+    __device__ void gsrb(int li, int nsweep) const {
+        for (int q = 0; q < nsweep; q++) {
+            half(li, 0);
+            half(li, 1);
+        }
+    }
+    // res = rho - L u (ghosts of u must be filled)
+    __device__ void residual(int li) const {
+        const double h = hlev(li), ih2 = 1.0 / (h * h);
+        for (int c = threadIdx.x; c < ncell(li); c += blockDim.x) {
+            int i, j, k;
+            cell(li, c, i, j, k);
+            const int p = pidx(li, i, j, k);
+            res[p] = rho[p] - (nbs(u, li, i, j, k) - double(2 * D) * u[p]) * ih2;
+        }
+        __syncthreads();
+    }
+    // f at li+1 <- mean of f at li
+    __device__ void restrict_to_coarser(double *f, int li) const {
+        const int nc = CG::n(li + 1);
+        const int cells = D == 3 ? nc * nc * nc : nc * nc;
+        const double w = D == 3 ? 0.125 : 0.25;
+        for (int c = threadIdx.x; c < cells; c += blockDim.x) {
+            const int I = c % nc, J = (c / nc) % nc, K = D == 3 ? c / (nc * nc) : 0;
+            double acc = 0.0;
+            for (int dk = 0; dk < (D == 3 ? 2 : 1); dk++)
+                for (int dj = 0; dj < 2; dj++)
+                    for (int di = 0; di < 2; di++)
+                        acc += f[pidx(li, 2 * I + di, 2 * J + dj, D == 3 ? 2 * K + dk : 0)];
+            f[pidx(li + 1, I, J, K)] = w * acc;
+        }
+        __syncthreads();
+    }
+    __device__ void copy_uold(int li) const {
+        for (int p = threadIdx.x; p < CG::psz(li); p += blockDim.x) uold[CG::poff(li) + p] = u[CG::poff(li) + p];
+        __syncthreads();
+    }
+    // rho <- res + L u (ghosts filled)
+    __device__ void coarse_rhs(int li) const {
+        const double h = hlev(li), ih2 = 1.0 / (h * h);
+        for (int c = threadIdx.x; c < ncell(li); c += blockDim.x) {
+            int i, j, k;
+            cell(li, c, i, j, k);
+            const int p = pidx(li, i, j, k);
+            rho[p] = res[p] + (nbs(u, li, i, j, k) - double(2 * D) * u[p]) * ih2;
+        }
+        __syncthreads();
+    }
+    // u(li) += P211(u - uold at li+1, ghosts included)
+    __device__ void prolong(int li) const {
+        for (int c = threadIdx.x; c < ncell(li); c += blockDim.x) {
+            int i, j, k;
+            cell(li, c, i, j, k);
+            const int I = i >> 1, J = j >> 1, K = k >> 1;
+            const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
+            auto del = [&](int a, int b, int cc) {
+                const int p = pidx(li + 1, a, b, cc);
+                return u[p] - uold[p];
+            };
+            double v;
+            if (D == 2)
+                v = 0.5 * del(I, J, 0) + 0.25 * del(I + sx, J, 0) + 0.25 * del(I, J + sy, 0);
+            else
+                v = 0.25 * (((del(I, J, K) + del(I + sx, J, K)) + del(I, J + sy, K)) + del(I, J, K + sz));
+            const int p = pidx(li, i, j, k);
+            u[p] = u[p] + v;
+        }
+        __syncthreads();
+    }
+    // FAS V-cycle over grids top..NL-1 (paper §3.2)
+    __device__ void vcycle(int top) const {
+        for (int li = top; li < CG::NL - 1; li++) {
+            gsrb(li, n_down);
+            fill(u, li);
+            residual(li);
+            restrict_to_coarser(u, li);
+            restrict_to_coarser(res, li);
+            fill(u, li + 1);
+            copy_uold(li + 1);
+            coarse_rhs(li + 1);
+        }
+        gsrb(CG::NL - 1, n_base);
+        for (int li = CG::NL - 2; li >= top; li--) {
+            fill(u, li + 1);
+            prolong(li);
+            gsrb(li, n_up);
+        }
+    }
+};
+
+template <int D, int N, typename T>
+__global__ __launch_bounds__(256) void k_coarse(CoarseArgs<T> a) {
+    using CG = CoarseGeo<D, N>;
+    using G = Geo<D, N>;
+    __shared__ double f_u[CG::PTOT], f_rho[CG::PTOT], f_uold[CG::PTOT], f_res[CG::PTOT], f_bc[CG::BTOT];
+    CoarseState<D, N> st{f_u, f_rho, f_uold, f_res, f_bc, a.n_down, a.n_up, a.n_base};
+    const BoxInfo ri = a.info[0];  // the root is box 0
+    const bool root_leaf = ri.flags & FLAG_LEAF;
+    // Dirichlet values: root rows, then means down to the 2^D grid
+    for (int g = threadIdx.x; g < 2 * D * G::F; g += blockDim.x) {
+        const int side = g / G::F, m = g % G::F;
+        f_bc[side * G::F + m] = a.homog ? 0.0 : a.bc[(size_t)ri.bcoff[side] * G::F + m];
+    }
+    __syncthreads();
+    for (int li = 1; li < CG::NL; li++) {
+        const int n = CG::n(li), F = CG::fsz(li), Ff = CG::fsz(li - 1), nf = CG::n(li - 1);
+        for (int g = threadIdx.x; g < 2 * D * F; g += blockDim.x) {
+            const int side = g / F, m = g % F;
+            const int A = m % n, Cc = D == 3 ? m / n : 0;
+            double acc = 0.0;
+            for (int dc = 0; dc < (D == 3 ? 2 : 1); dc++)
+                for (int da = 0; da < 2; da++)
+                    acc += f_bc[CG::boff(li - 1) + side * Ff + (2 * A + da) + nf * (2 * Cc + dc)];
+            f_bc[CG::boff(li) + side * F + m] = acc * (D == 3 ? 0.25 : 0.5);
+        }
+        __syncthreads();
+    }
+    for (int p = threadIdx.x; p < CG::PTOT; p += blockDim.x) {
+        f_u[p] = 0.0;
+        f_rho[p] = 0.0;
+        f_uold[p] = 0.0;
+        f_res[p] = 0.0;
+    }
+    __syncthreads();
+    const T *rho_root = root_leaf ? a.rho_user : a.rho_w;
+    // stage level 1 (the root box) from global memory
+    for (int c = threadIdx.x; c < G::C; c += blockDim.x) {
+        int i, j, k;
+        decode<D, N>(c, i, j, k);
+        const int p = st.pidx(0, i, j, k);
+        if (a.mode != COARSE_FMG) f_u[p] = (double)a.u[c];
+        if (a.mode == COARSE_V_FROM_2) f_res[p] = (double)a.rho_w[c];
+        else f_rho[p] = (double)rho_root[c];
+    }
+    __syncthreads();
+    if (a.mode == COARSE_V_FROM_2) {
+        // level 1 right after restriction from level 2: ghosts, copy v'_H,
+        // FAS right-hand side, then the V-cycle from level 1
+        st.fill(f_u, 0);
+        st.copy_uold(0);
+        st.coarse_rhs(0);
+        st.vcycle(0);
+    } else if (a.mode == COARSE_V_TOP1) {
+        st.vcycle(0);
+    } else {
+        // FMG from a zero guess: rho restricted down, then for l = lmin..1:
+        // store v', correct from the coarser grid, V-cycle from l
+        for (int li = 0; li < CG::NL - 1; li++) st.restrict_to_coarser(f_rho, li);
+        for (int li = CG::NL - 1; li >= 0; li--) {
+            st.fill(f_u, li);
+            st.copy_uold(li);
+            if (li < CG::NL - 1) {
+                st.fill(f_u, li + 1);
+                st.prolong(li);
+            }
+            st.vcycle(li);
+        }
+    }
+    for (int c = threadIdx.x; c < G::C; c += blockDim.x) {
+        int i, j, k;
+        decode<D, N>(c, i, j, k);
+        const int p = st.pidx(0, i, j, k);
+        a.u[c] = (T)f_u[p];
+        if (a.uold && a.mode != COARSE_V_TOP1) a.uold[c] = (T)f_uold[p];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <int D, int N>
+static inline int wg_count(int64_t nb) {
+    using G = Geo<D, N>;
+    return (int)((nb + G::BPW - 1) / G::BPW);
+}
+
+#define AFMG_LAUNCH(kernel, grid, stream, ...)                                     \
+    do {                                                                           \
+        if ((grid) > 0) hipLaunchKernelGGL(kernel, dim3(grid), dim3(256), 0, stream, __VA_ARGS__); \
+    } while (0)
+
+template <int D, int N, typename T>
+void launch_level(Op op, const LevelArgs<T> &a, int colour, hipStream_t st) {
+    const int g = wg_count<D, N>(a.nb);
+    switch (op) {
+    case Op::GSRB: AFMG_LAUNCH((k_gsrb<D, N, T>), g, st, a, colour); break;
+    case Op::RESID_RESTRICT: AFMG_LAUNCH((k_resid_restrict<D, N, T>), g, st, a); break;
+    case Op::COARSE_RHS: AFMG_LAUNCH((k_coarse_rhs<D, N, T>), g, st, a); break;
+    case Op::PROLONG: AFMG_LAUNCH((k_prolong<D, N, T>), g, st, a); break;
+    case Op::RESTRICT_RHO: AFMG_LAUNCH((k_restrict_rho<D, N, T>), g, st, a); break;
+    }
+}
+
+template <int D, int N, typename T>
+void launch_final(const LevelArgs<T> &a, double *partial, int64_t part0, double hD, hipStream_t st) {
+    const int g = wg_count<D, N>(a.nb);
+    AFMG_LAUNCH((k_final<D, N, T>), g, st, a, partial, part0, hD);
+}
+
+template <int D, int N>
+int final_wgs(int64_t nb) { return wg_count<D, N>(nb); }
+
+void launch_reduce(const double *partial, int64_t n, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, partial, n, out);
+}
+
+template <int D, int N, typename T>
+void launch_coarse(const CoarseArgs<T> &a, hipStream_t st) {
+    hipLaunchKernelGGL((k_coarse<D, N, T>), dim3(1), dim3(256), 0, st, a);
+}
+
+template <int D, int N>
+void launch_bc_derive(const BoxInfo *info, int64_t b0, int64_t nb, double *bc, hipStream_t st) {
+    using G = Geo<D, N>;
+    const int64_t work = nb * 2 * D * G::HF;
+    const int g = (int)((work + 255) / 256);
+    AFMG_LAUNCH((k_bc_derive<D, N>), g, st, info, b0, (int)nb, bc);
+}
+
+template <typename T>
+void launch_copy(const T *src, T *dst, int64_t n, hipStream_t st) {
+    if (n <= 0) return;
+    int64_t g = (n + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_copy<T>, dim3((unsigned)g), dim3(256), 0, st, src, dst, n);
+}
+template <typename T>
+void launch_fill(T *dst, int64_t n, T v, hipStream_t st) {
+    if (n <= 0) return;
+    int64_t g = (n + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)g), dim3(256), 0, st, dst, n, v);
+}
+
+#define AFMG_INST(D, N, T)                                                                 \
+    template void launch_level<D, N, T>(Op, const LevelArgs<T> &, int, hipStream_t);        \
+    template void launch_final<D, N, T>(const LevelArgs<T> &, double *, int64_t, double,    \
+                                        hipStream_t);                                      \
+    template void launch_coarse<D, N, T>(const CoarseArgs<T> &, hipStream_t);
+
+AFMG_INST(2, 8, double)
+AFMG_INST(3, 8, double)
+template int final_wgs<2, 8>(int64_t);
+template int final_wgs<3, 8>(int64_t);
+template void launch_bc_derive<2, 8>(const BoxInfo *, int64_t, int64_t, double *, hipStream_t);
+template void launch_bc_derive<3, 8>(const BoxInfo *, int64_t, int64_t, double *, hipStream_t);
+template void launch_copy<double>(const double *, double *, int64_t, hipStream_t);
+template void launch_fill<double>(double *, int64_t, double, hipStream_t);
+
+}  // namespace afmg

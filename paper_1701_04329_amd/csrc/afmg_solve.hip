@@ -1,0 +1,463 @@
+// Cycle scheduler and C-ABI of the afmg library.
+//
+// The scheduler issues the kernels of one FAS V-cycle level by level (paper
+// §3.2): smoothing, residual + restriction, FAS right-hand side and the copy
+// v'_H, the one-workgroup kernel for the root box and the coarse grids below
+// it, then prolongation + correction and smoothing on the way up.  After
+// each cycle the composite leaf residual is reduced on the device and its
+// max-norm is read back for the stop test.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "afmg.h"
+#include "afmg_internal.h"
+#include "afmg_kernels.h"
+
+using namespace afmg;
+
+namespace {
+thread_local std::string g_err;
+}
+
+void afmg::set_error(const std::string &m) { g_err = m; }
+extern "C" const char *afmg_last_error(void) { return g_err.c_str(); }
+
+struct afmg_tree {
+    HostTree h;
+    int device = -1;
+    BoxInfo *d_info = nullptr;
+    double *h_norm = nullptr;        // pinned host copy of the two norms
+    std::vector<int64_t> part_off;   // first k_final partial of each level
+    int64_t n_parts = 0;
+    std::vector<hipEvent_t> events;  // event pairs for opts.profile
+};
+
+namespace {
+
+constexpr int BOX_N = 8;
+
+int fail(int code, const std::string &msg) {
+    set_error(msg);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(AFMG_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int64_t cells_per_box(int dim) { return dim == 3 ? BOX_N * BOX_N * BOX_N : BOX_N * BOX_N; }
+int64_t cells_per_face(int dim) { return dim == 3 ? BOX_N * BOX_N : BOX_N; }
+double level_h(int l) { return 1.0 / ((double)BOX_N * std::ldexp(1.0, l - 1)); }
+
+struct WsLayout {
+    size_t rho_w, uold, bc, partial, norm, total;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+WsLayout ws_layout(const afmg_tree *t) {
+    const HostTree &h = t->h;
+    const size_t C = (size_t)cells_per_box(h.dim), F = (size_t)cells_per_face(h.dim);
+    const size_t nlt = (size_t)h.n_below_lmax();
+    WsLayout L{};
+    size_t off = 0;
+    L.rho_w = off; off = align256(off + nlt * C * sizeof(double));
+    L.uold = off; off = align256(off + nlt * C * sizeof(double));
+    L.bc = off; off = align256(off + (size_t)std::max<int64_t>(1, h.n_bfaces_all) * F * sizeof(double));
+    L.partial = off; off = align256(off + (size_t)std::max<int64_t>(1, t->n_parts) * 2 * sizeof(double));
+    L.norm = off; off = align256(off + 2 * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+template <int D>
+int64_t final_wgs_d(int64_t nb) { return final_wgs<D, BOX_N>(nb); }
+
+bool root_is_leaf(const HostTree &h) { return h.info[0].flags & FLAG_LEAF; }
+
+void compute_partials(afmg_tree *t) {
+    const HostTree &h = t->h;
+    t->part_off.assign((size_t)h.lmax + 2, 0);
+    int64_t n = 0;
+    for (int l = h.lmax; l >= 1; l--) {
+        t->part_off[(size_t)l] = n;
+        if (l >= 2 || root_is_leaf(h))
+            n += h.dim == 3 ? final_wgs_d<3>(h.level_count(l)) : final_wgs_d<2>(h.level_count(l));
+    }
+    t->n_parts = n;
+}
+
+int bind_device(afmg_tree *t) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (t->device >= 0) {
+        if (dev != t->device) return fail(AFMG_ERR_ARG, "tree was first used on another device");
+        return AFMG_OK;
+    }
+    const HostTree &h = t->h;
+    e = hipMalloc(&t->d_info, sizeof(BoxInfo) * (size_t)h.n_boxes);
+    if (e != hipSuccess) return fail(AFMG_ERR_OOM, "hipMalloc of the box table failed");
+    e = hipMemcpy(t->d_info, h.info.data(), sizeof(BoxInfo) * (size_t)h.n_boxes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "upload of the box table");
+    e = hipHostMalloc(&t->h_norm, 2 * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) return fail(AFMG_ERR_OOM, "hipHostMalloc failed");
+    t->device = dev;
+    return AFMG_OK;
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+int check_opts(const afmg_opts *o) {
+    if (!o) return fail(AFMG_ERR_ARG, "opts is null");
+    if (o->cycle != AFMG_CYCLE_V && o->cycle != AFMG_CYCLE_FMG_V) return fail(AFMG_ERR_ARG, "bad cycle");
+    if (o->n_down < 0 || o->n_up < 0 || o->n_base < 1 || o->n_down > 64 || o->n_up > 64 || o->n_base > 1024)
+        return fail(AFMG_ERR_ARG, "smoothing counts out of range");
+    if (!(o->tol >= 0.0) || o->max_cycles < 0 || o->max_cycles > 100000 || o->fixed_cycles < 0 ||
+        o->fixed_cycles > 100000)
+        return fail(AFMG_ERR_ARG, "tol / max_cycles / fixed_cycles out of range");
+    if (o->precision != AFMG_FP64) return fail(AFMG_ERR_ARG, "precision not supported by this entry point");
+    return AFMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the FP64 solve
+// ---------------------------------------------------------------------------
+constexpr int PROF_PAIRS = 64;
+
+template <int D>
+struct Solver {
+    afmg_tree *t;
+    const HostTree &h;
+    hipStream_t st;
+    const afmg_opts &o;
+    LevelArgs<double> base;
+    double *partial, *norm;
+    afmg_stats *stats = nullptr;
+    std::vector<std::pair<int, int>> pending;  // (kernel class, event pair)
+
+    Solver(afmg_tree *t_, hipStream_t s, const afmg_opts &o_) : t(t_), h(t_->h), st(s), o(o_) {}
+
+    // Bracket a finest-level launch with an event pair when profiling.
+    template <class Fn>
+    void timed(int kind, int l, Fn fn) {
+        const int pair = (int)pending.size();
+        if (!o.profile || l != h.lmax || pair >= PROF_PAIRS) {
+            fn();
+            return;
+        }
+        (void)hipEventRecord(t->events[(size_t)(2 * pair)], st);
+        fn();
+        (void)hipEventRecord(t->events[(size_t)(2 * pair + 1)], st);
+        pending.emplace_back(kind, pair);
+    }
+    // after a stream synchronisation: add the timed launches to the stats
+    void collect() {
+        for (const auto &p : pending) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, t->events[(size_t)(2 * p.second)],
+                                    t->events[(size_t)(2 * p.second + 1)]) == hipSuccess) {
+                stats->prof_ms[p.first] += ms;
+                stats->prof_n[p.first] += 1;
+            }
+        }
+        pending.clear();
+    }
+
+    LevelArgs<double> lev(int l) const {
+        LevelArgs<double> a = base;
+        a.b0 = h.lvl_off[(size_t)l];
+        a.nb = (int)h.level_count(l);
+        const double hh = level_h(l);
+        a.h2 = hh * hh;
+        a.ih2 = 1.0 / (hh * hh);
+        return a;
+    }
+    void level(Op op, int l, int colour = 0) {
+        const int kind = op == Op::GSRB ? AFMG_PROF_GSRB
+                         : op == Op::RESID_RESTRICT ? AFMG_PROF_RESID
+                         : op == Op::PROLONG ? AFMG_PROF_PROLONG : -1;
+        if (kind < 0) {
+            launch_level<D, BOX_N, double>(op, lev(l), colour, st);
+            return;
+        }
+        timed(kind, l, [&] { launch_level<D, BOX_N, double>(op, lev(l), colour, st); });
+    }
+    void gsrb(int l, int n) {
+        for (int q = 0; q < n; q++) {
+            level(Op::GSRB, l, 0);
+            level(Op::GSRB, l, 1);
+        }
+    }
+    void coarse(int mode) {
+        CoarseArgs<double> c{base.info, base.u, base.rho_user, base.rho_w, base.uold, base.bc, mode, 0,
+                             o.n_down, o.n_up, o.n_base};
+        if (h.lmax == 1) c.uold = nullptr;
+        launch_coarse<D, BOX_N, double>(c, st);
+    }
+    void vcycle(int top) {
+        for (int l = top; l >= 2; l--) {
+            gsrb(l, o.n_down);
+            level(Op::RESID_RESTRICT, l);
+            if (l - 1 >= 2) level(Op::COARSE_RHS, l - 1);
+        }
+        coarse(top >= 2 ? COARSE_V_FROM_2 : COARSE_V_TOP1);
+        for (int l = 2; l <= top; l++) {
+            level(Op::PROLONG, l);
+            gsrb(l, o.n_up);
+        }
+    }
+    void fmg() {
+        launch_fill<double>(base.u, h.n_boxes * cells_per_box(D), 0.0, st);
+        for (int l = h.lmax; l >= 2; l--) level(Op::RESTRICT_RHO, l);
+        coarse(COARSE_FMG);
+        const int64_t C = cells_per_box(D);
+        for (int l = 2; l <= h.lmax; l++) {
+            if (l < h.lmax)
+                launch_copy<double>(base.u + h.lvl_off[(size_t)l] * C, base.uold + h.lvl_off[(size_t)l] * C,
+                                    h.level_count(l) * C, st);
+            level(Op::PROLONG, l);
+            vcycle(l);
+        }
+    }
+    // restriction of u into parents and the composite leaf residual norms
+    int finalize(double &rmax, double &rl2) {
+        for (int l = h.lmax; l >= 1; l--) {
+            if (l == 1 && !root_is_leaf(h)) continue;
+            const double hh = level_h(l);
+            const double hD = D == 3 ? hh * hh * hh : hh * hh;
+            timed(AFMG_PROF_FINAL, l, [&] {
+                launch_final<D, BOX_N, double>(lev(l), partial, t->part_off[(size_t)l], hD, st);
+            });
+        }
+        launch_reduce(partial, t->n_parts, norm, st);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        e = hipMemcpyAsync(t->h_norm, norm, 2 * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) return hip_fail(e, "norm readback");
+        e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+        collect();
+        rmax = t->h_norm[0];
+        rl2 = t->h_norm[1];
+        return AFMG_OK;
+    }
+};
+
+template <int D>
+int solve_fp64(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, double *u,
+               char *ws, const afmg_opts &o, afmg_stats &S) {
+    const HostTree &h = t->h;
+    const WsLayout L = ws_layout(t);
+    Solver<D> s(t, st, o);
+    double *rho_w = (double *)(ws + L.rho_w);
+    double *uold = (double *)(ws + L.uold);
+    double *bc_w = (double *)(ws + L.bc);
+    s.stats = &S;
+    if (o.profile && t->events.empty()) {
+        t->events.resize(2 * PROF_PAIRS);
+        for (auto &ev : t->events)
+            if (hipEventCreate(&ev) != hipSuccess) return fail(AFMG_ERR_HIP, "hipEventCreate failed");
+    }
+    s.partial = (double *)(ws + L.partial);
+    s.norm = (double *)(ws + L.norm);
+    s.base = LevelArgs<double>{t->d_info, u, rho, rho_w, uold, bc_w, 0, 0, 0, 0.0, 0.0};
+    const int64_t F = cells_per_face(D), C = cells_per_box(D);
+
+    hipEvent_t ev0, ev1;
+    (void)hipEventCreate(&ev0);
+    (void)hipEventCreate(&ev1);
+    (void)hipEventRecord(ev0, st);
+    // Dirichlet rows: caller's leaf rows, then parent rows from fine to coarse
+    if (h.n_bfaces_leaf > 0) {
+        if (bc) {
+            hipError_t e = hipMemcpyAsync(bc_w, bc, (size_t)(h.n_bfaces_leaf * F) * sizeof(double),
+                                          hipMemcpyDeviceToDevice, st);
+            if (e != hipSuccess) return hip_fail(e, "copy of Dirichlet values");
+        } else {
+            launch_fill<double>(bc_w, h.n_bfaces_leaf * F, 0.0, st);
+        }
+    }
+    for (int l = h.lmax; l >= 2; l--)
+        launch_bc_derive<D, BOX_N>(t->d_info, h.lvl_off[(size_t)l], h.level_count(l), bc_w, st);
+    if (!o.use_guess || o.cycle == AFMG_CYCLE_FMG_V) launch_fill<double>(u, h.n_boxes * C, 0.0, st);
+
+    int rc = s.finalize(S.r0_max, S.r0_l2);
+    if (rc != AFMG_OK) return rc;
+    S.r_max = S.r0_max;
+    S.r_l2 = S.r0_l2;
+    int status = AFMG_OK;
+    if (!std::isfinite(S.r0_max)) {
+        status = AFMG_ERR_NONFINITE;
+    } else {
+        if (o.cycle == AFMG_CYCLE_FMG_V) {
+            s.fmg();
+            rc = s.finalize(S.r_max, S.r_l2);
+            if (rc != AFMG_OK) return rc;
+        }
+        const bool fixed = o.fixed_cycles > 0;
+        const int nmax = fixed ? o.fixed_cycles : o.max_cycles;
+        bool conv = !fixed && S.r_max <= o.tol * S.r0_max;
+        int grow = 0;
+        double prev = S.r_max;
+        while (!conv && S.cycles < nmax) {
+            s.vcycle(h.lmax);
+            rc = s.finalize(S.r_max, S.r_l2);
+            if (rc != AFMG_OK) return rc;
+            if (S.cycles < AFMG_HIST) {
+                S.hist_max[S.cycles] = S.r_max;
+                S.hist_l2[S.cycles] = S.r_l2;
+            }
+            S.cycles++;
+            if (!std::isfinite(S.r_max)) { status = AFMG_ERR_NONFINITE; break; }
+            if (!fixed) {
+                grow = S.r_max > prev ? grow + 1 : 0;
+                if (grow >= 3) { status = AFMG_ERR_DIVERGED; break; }
+                conv = S.r_max <= o.tol * S.r0_max;
+            }
+            prev = S.r_max;
+        }
+        if (status == AFMG_OK && !fixed && !conv) status = AFMG_NOT_CONVERGED;
+    }
+    (void)hipEventRecord(ev1, st);
+    (void)hipEventSynchronize(ev1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ev0, ev1);
+    S.t_ms = ms;
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "solve");
+    S.status = status;
+    if (status == AFMG_ERR_NONFINITE) set_error("residual norm is not finite");
+    if (status == AFMG_ERR_DIVERGED) set_error("residual grew for 3 consecutive cycles");
+    if (status == AFMG_NOT_CONVERGED) set_error("max_cycles reached before the tolerance");
+    return status;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C-ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void afmg_default_opts(afmg_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->cycle = AFMG_CYCLE_V;
+    o->n_down = 2;
+    o->n_up = 2;
+    o->n_base = 4;
+    o->tol = 1e-10;
+    o->max_cycles = 100;
+    o->fixed_cycles = 0;
+    o->use_guess = 0;
+    o->precision = AFMG_FP64;
+}
+
+int afmg_tree_create(int dim, int box_n, int64_t n_leaves, const int32_t *level, const int32_t *idx,
+                     afmg_tree **out) {
+    if (!out) return fail(AFMG_ERR_ARG, "out is null");
+    *out = nullptr;
+    afmg_tree *t = nullptr;
+    try {
+        t = new afmg_tree();
+        std::string msg;
+        int rc = build_tree(dim, box_n, n_leaves, level, idx, t->h, msg);
+        if (rc != AFMG_OK) {
+            delete t;
+            return fail(rc, msg);
+        }
+        compute_partials(t);
+    } catch (const std::bad_alloc &) {
+        delete t;
+        return fail(AFMG_ERR_OOM, "host allocation failed");
+    }
+    *out = t;
+    return AFMG_OK;
+}
+
+void afmg_tree_destroy(afmg_tree *t) {
+    if (!t) return;
+    if (t->d_info) (void)hipFree(t->d_info);
+    if (t->h_norm) (void)hipHostFree(t->h_norm);
+    for (auto ev : t->events) (void)hipEventDestroy(ev);
+    delete t;
+}
+
+int afmg_tree_info(const afmg_tree *t, afmg_tree_desc *out) {
+    if (!t || !out) return fail(AFMG_ERR_ARG, "null argument");
+    const HostTree &h = t->h;
+    out->dim = h.dim;
+    out->box_n = h.N;
+    out->n_boxes = h.n_boxes;
+    out->n_leaves = h.n_leaves;
+    out->n_bfaces = h.n_bfaces_leaf;
+    out->lmin = h.lmin;
+    out->lmax = h.lmax;
+    out->cells_per_box = cells_per_box(h.dim);
+    out->n_unknowns = h.n_leaves * cells_per_box(h.dim);
+    return AFMG_OK;
+}
+
+int afmg_tree_leaf_boxes(const afmg_tree *t, int32_t *out) {
+    if (!t || !out) return fail(AFMG_ERR_ARG, "null argument");
+    std::memcpy(out, t->h.leaf_box.data(), sizeof(int32_t) * t->h.leaf_box.size());
+    return AFMG_OK;
+}
+
+int afmg_tree_bfaces(const afmg_tree *t, int32_t *out) {
+    if (!t || !out) return fail(AFMG_ERR_ARG, "null argument");
+    for (int64_t f = 0; f < t->h.n_bfaces_leaf; f++) {
+        out[2 * f] = t->h.bface_box[(size_t)f];
+        out[2 * f + 1] = t->h.bface_side[(size_t)f];
+    }
+    return AFMG_OK;
+}
+
+int afmg_tree_box(const afmg_tree *t, int64_t b, afmg_box_desc *out) {
+    if (!t || !out) return fail(AFMG_ERR_ARG, "null argument");
+    if (b < 0 || b >= t->h.n_boxes) return fail(AFMG_ERR_ARG, "box id out of range");
+    const BoxInfo &bi = t->h.info[(size_t)b];
+    out->level = bi.level;
+    out->idx[0] = t->h.ix[(size_t)b];
+    out->idx[1] = t->h.iy[(size_t)b];
+    out->idx[2] = t->h.iz[(size_t)b];
+    out->parent = bi.parent;
+    out->leaf = bi.flags & FLAG_LEAF;
+    for (int s = 0; s < 6; s++) out->nbr[s] = s < 2 * t->h.dim ? bi.nbr[s] : -1;
+    return AFMG_OK;
+}
+
+int afmg_workspace_bytes(const afmg_tree *t, const afmg_opts *o, size_t *bytes) {
+    if (!t || !bytes) return fail(AFMG_ERR_ARG, "null argument");
+    if (o) {
+        int rc = check_opts(o);
+        if (rc != AFMG_OK) return rc;
+    }
+    *bytes = ws_layout(t).total;
+    return AFMG_OK;
+}
+
+int afmg_solve(afmg_tree *t, void *stream, const double *rho, const double *bc, double *u,
+               void *workspace, size_t workspace_bytes, const afmg_opts *opts, afmg_stats *stats) {
+    if (!t || !rho || !u || !workspace || !stats) return fail(AFMG_ERR_ARG, "null argument");
+    int rc = check_opts(opts);
+    if (rc != AFMG_OK) return rc;
+    if (!aligned(rho, 8) || !aligned(u, 8) || (bc && !aligned(bc, 8)) || !aligned(workspace, 256))
+        return fail(AFMG_ERR_ARG, "misaligned array");
+    const WsLayout L = ws_layout(t);
+    if (workspace_bytes < L.total) return fail(AFMG_ERR_ARG, "workspace too small");
+    std::memset(stats, 0, sizeof(*stats));
+    rc = bind_device(t);
+    if (rc != AFMG_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (t->h.dim == 3) return solve_fp64<3>(t, st, rho, bc, u, (char *)workspace, *opts, *stats);
+    return solve_fp64<2>(t, st, rho, bc, u, (char *)workspace, *opts, *stats);
+}
+
+}  // extern "C"

@@ -1,0 +1,193 @@
+// Host-side tree construction from a leaf list (paper §2.1-§2.3): ancestors,
+// completeness and 2:1 checks, Morton order per level (§2.3), neighbour and
+// parent tables, and the numbering of Dirichlet rows.
+#include <algorithm>
+#include <unordered_map>
+
+#include "afmg_internal.h"
+
+namespace afmg {
+
+namespace {
+
+struct Key {
+    int l, i, j, k;
+    bool operator==(const Key &o) const { return l == o.l && i == o.i && j == o.j && k == o.k; }
+};
+struct KeyHash {
+    size_t operator()(const Key &a) const {
+        uint64_t x = (uint64_t)(uint32_t)a.l * 0x9E3779B97F4A7C15ULL;
+        x ^= (uint64_t)(uint32_t)a.i + 0x632BE59BD9B4E019ULL + (x << 6) + (x >> 2);
+        x ^= (uint64_t)(uint32_t)a.j + 0x8CB92BA72F3D8DD7ULL + (x << 6) + (x >> 2);
+        x ^= (uint64_t)(uint32_t)a.k + 0xA24BAED4963EE407ULL + (x << 6) + (x >> 2);
+        return (size_t)x;
+    }
+};
+
+// Morton key of a 0-based spatial index (up to 21 bits per axis)
+uint64_t spread3(uint64_t v) {
+    v &= 0x1fffff;
+    v = (v | v << 32) & 0x1f00000000ffffULL;
+    v = (v | v << 16) & 0x1f0000ff0000ffULL;
+    v = (v | v << 8) & 0x100f00f00f00f00fULL;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+    v = (v | v << 2) & 0x1249249249249249ULL;
+    return v;
+}
+uint64_t spread2(uint64_t v) {
+    v &= 0xffffffff;
+    v = (v | v << 16) & 0x0000ffff0000ffffULL;
+    v = (v | v << 8) & 0x00ff00ff00ff00ffULL;
+    v = (v | v << 4) & 0x0f0f0f0f0f0f0f0fULL;
+    v = (v | v << 2) & 0x3333333333333333ULL;
+    v = (v | v << 1) & 0x5555555555555555ULL;
+    return v;
+}
+uint64_t morton(int dim, int i, int j, int k) {
+    if (dim == 2) return spread2((uint64_t)(i - 1)) | (spread2((uint64_t)(j - 1)) << 1);
+    return spread3((uint64_t)(i - 1)) | (spread3((uint64_t)(j - 1)) << 1) |
+           (spread3((uint64_t)(k - 1)) << 2);
+}
+
+}  // namespace
+
+int build_tree(int dim, int N, int64_t n_leaves, const int32_t *level, const int32_t *idx,
+               HostTree &t, std::string &msg) {
+    if (dim != 2 && dim != 3) { msg = "dim must be 2 or 3"; return AFMG_ERR_ARG; }
+    if (N != 8) { msg = "box_n must be 8"; return AFMG_ERR_ARG; }
+    if (n_leaves <= 0 || !level || !idx) { msg = "empty or null leaf list"; return AFMG_ERR_ARG; }
+    if (n_leaves > (int64_t)1 << 28) { msg = "too many leaves"; return AFMG_ERR_ARG; }
+    const int max_level = dim == 3 ? 17 : 20;  // keeps box counts and indices in int32
+    struct Box { Key key; bool leaf; int64_t input; };
+    std::vector<Box> boxes;
+    std::unordered_map<Key, int64_t, KeyHash> map;
+    boxes.reserve((size_t)(n_leaves * 8 / 7 + 16));
+    map.reserve((size_t)(n_leaves * 8 / 7 + 16));
+    for (int64_t q = 0; q < n_leaves; q++) {
+        Key k{level[q], idx[3 * q], idx[3 * q + 1], dim == 3 ? idx[3 * q + 2] : 1};
+        if (k.l < 1 || k.l > max_level) { msg = "leaf level out of range"; return AFMG_ERR_ARG; }
+        int n1 = 1 << (k.l - 1);
+        if (k.i < 1 || k.i > n1 || k.j < 1 || k.j > n1 || k.k < 1 || k.k > (dim == 3 ? n1 : 1)) {
+            msg = "leaf spatial index out of range";
+            return AFMG_ERR_ARG;
+        }
+        auto ins = map.emplace(k, (int64_t)boxes.size());
+        if (!ins.second) { msg = "duplicate leaf"; return AFMG_ERR_TREE; }
+        boxes.push_back({k, true, q});
+    }
+    for (int64_t q = 0; q < n_leaves; q++) {
+        Key k = boxes[(size_t)q].key;
+        while (k.l > 1) {
+            Key p{k.l - 1, (k.i + 1) / 2, (k.j + 1) / 2, dim == 3 ? (k.k + 1) / 2 : 1};
+            auto it = map.find(p);
+            if (it != map.end()) {
+                if (boxes[(size_t)it->second].leaf) { msg = "a leaf overlaps finer leaves"; return AFMG_ERR_TREE; }
+                break;
+            }
+            map.emplace(p, (int64_t)boxes.size());
+            boxes.push_back({p, false, -1});
+            k = p;
+        }
+    }
+    // every refined box has all 2^D children
+    const int nch = 1 << dim;
+    for (const Box &b : boxes) {
+        if (b.leaf) continue;
+        for (int c = 0; c < nch; c++) {
+            Key ch{b.key.l + 1, 2 * b.key.i - 1 + (c & 1), 2 * b.key.j - 1 + ((c >> 1) & 1),
+                   dim == 3 ? 2 * b.key.k - 1 + ((c >> 2) & 1) : 1};
+            if (!map.count(ch)) { msg = "leaves do not tile the domain"; return AFMG_ERR_TREE; }
+        }
+    }
+    // order: level, then Morton index
+    std::vector<int64_t> order(boxes.size());
+    for (size_t m = 0; m < order.size(); m++) order[m] = (int64_t)m;
+    std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+        const Key &x = boxes[(size_t)a].key, &y = boxes[(size_t)b].key;
+        if (x.l != y.l) return x.l < y.l;
+        return morton(dim, x.i, x.j, x.k) < morton(dim, y.i, y.j, y.k);
+    });
+    const int64_t nb = (int64_t)boxes.size();
+    if (nb >= ((int64_t)1 << 30)) { msg = "too many boxes"; return AFMG_ERR_ARG; }
+    std::vector<int64_t> newid(boxes.size());
+    for (int64_t m = 0; m < nb; m++) newid[(size_t)order[(size_t)m]] = m;
+    t.dim = dim;
+    t.N = N;
+    t.n_boxes = nb;
+    t.n_leaves = n_leaves;
+    int lg = 0;
+    while ((1 << (lg + 1)) < N) lg++;  // N = 2^(lg+1)
+    t.lmin = 1 - lg;
+    t.lmax = 1;
+    t.info.assign((size_t)nb, BoxInfo{});
+    t.ix.resize((size_t)nb);
+    t.iy.resize((size_t)nb);
+    t.iz.resize((size_t)nb);
+    for (int64_t m = 0; m < nb; m++) {
+        const Box &b = boxes[(size_t)order[(size_t)m]];
+        t.ix[(size_t)m] = b.key.i;
+        t.iy[(size_t)m] = b.key.j;
+        t.iz[(size_t)m] = b.key.k;
+        BoxInfo &bi = t.info[(size_t)m];
+        bi.level = b.key.l;
+        bi.flags = (b.leaf ? FLAG_LEAF : 0) | (((b.key.i - 1) & 1) << 1) | (((b.key.j - 1) & 1) << 2) |
+                   (dim == 3 ? (((b.key.k - 1) & 1) << 3) : 0);
+        if (b.key.l > t.lmax) t.lmax = b.key.l;
+        for (int s = 0; s < 6; s++) { bi.nbr[s] = -1; bi.bcoff[s] = -1; }
+        bi.parent = -1;
+    }
+    t.lvl_off.assign((size_t)t.lmax + 2, 0);
+    for (int64_t m = 0; m < nb; m++) t.lvl_off[(size_t)t.info[(size_t)m].level + 1]++;
+    // prefix sums: lvl_off[l] = first box of level l (level 1 starts at 0)
+    t.lvl_off[0] = 0;
+    for (int l = 1; l <= t.lmax + 1; l++) t.lvl_off[(size_t)l] += t.lvl_off[(size_t)l - 1];
+    t.leaf_box.resize((size_t)n_leaves);
+    for (int64_t m = 0; m < nb; m++) {
+        const Box &b = boxes[(size_t)order[(size_t)m]];
+        if (b.leaf) t.leaf_box[(size_t)b.input] = (int32_t)m;
+    }
+    // parents, neighbours, 2:1 balance
+    for (int64_t m = 0; m < nb; m++) {
+        BoxInfo &bi = t.info[(size_t)m];
+        const Key key{bi.level, t.ix[(size_t)m], t.iy[(size_t)m], t.iz[(size_t)m]};
+        if (key.l > 1) {
+            Key p{key.l - 1, (key.i + 1) / 2, (key.j + 1) / 2, dim == 3 ? (key.k + 1) / 2 : 1};
+            bi.parent = (int32_t)newid[(size_t)map.at(p)];
+        }
+        const int n1 = 1 << (key.l - 1);
+        for (int s = 0; s < 2 * dim; s++) {
+            int d = s / 2, dir = (s & 1) ? 1 : -1;
+            int q[3] = {key.i, key.j, key.k};
+            q[d] += dir;
+            if (q[d] < 1 || q[d] > n1) { bi.nbr[s] = -1; continue; }
+            auto it = map.find(Key{key.l, q[0], q[1], q[2]});
+            if (it != map.end()) { bi.nbr[s] = (int32_t)newid[(size_t)it->second]; continue; }
+            int pq[3] = {(key.i + 1) / 2, (key.j + 1) / 2, dim == 3 ? (key.k + 1) / 2 : 1};
+            pq[d] += dir;
+            auto itp = map.find(Key{key.l - 1, pq[0], pq[1], pq[2]});
+            if (itp == map.end()) { msg = "grid is not 2:1 balanced across a box side"; return AFMG_ERR_TREE; }
+            bi.nbr[s] = -2 - (int32_t)newid[(size_t)itp->second];
+        }
+    }
+    // Dirichlet rows: leaf sides first (box order, side order), then parents
+    t.bface_box.clear();
+    t.bface_side.clear();
+    for (int pass = 0; pass < 2; pass++) {
+        for (int64_t m = 0; m < nb; m++) {
+            BoxInfo &bi = t.info[(size_t)m];
+            bool leaf = bi.flags & FLAG_LEAF;
+            if ((pass == 0) != leaf) continue;
+            for (int s = 0; s < 2 * dim; s++) {
+                if (bi.nbr[s] != -1) continue;
+                bi.bcoff[s] = (int32_t)t.bface_box.size();
+                t.bface_box.push_back((int32_t)m);
+                t.bface_side.push_back(s);
+            }
+        }
+        if (pass == 0) t.n_bfaces_leaf = (int64_t)t.bface_box.size();
+    }
+    t.n_bfaces_all = (int64_t)t.bface_box.size();
+    return AFMG_OK;
+}
+
+}  // namespace afmg
