@@ -8,12 +8,13 @@
 namespace afmg {
 
 // Arguments of a kernel over one level (a contiguous box-id range).
+// Cell arrays are colour-split inside each box (see afmg_kernels.hip).
 template <typename T>
 struct LevelArgs {
     const BoxInfo *info;
     T *u;               // [n_boxes][N^D]
-    const T *rho_user;  // caller's right-hand side (read on leaf boxes)
-    T *rho_w;           // right-hand side of parent boxes (FAS / restricted)
+    T *rho;             // [n_boxes][N^D]: caller's rho on leaves, FAS /
+                        // restricted right-hand side on parents
     T *uold;            // copy v'_H (boxes of levels < lmax)
     const T *bc;        // Dirichlet rows (leaf rows, then derived rows)
     int64_t b0;         // first box of the range
@@ -31,8 +32,7 @@ template <typename T>
 struct CoarseArgs {
     const BoxInfo *info;
     T *u;
-    const T *rho_user;
-    T *rho_w;
+    T *rho;
     T *uold;            // may be null when the tree has one level
     const double *bc;
     int mode;
@@ -49,6 +49,11 @@ int final_wgs(int64_t nb);
 void launch_reduce(const double *partial, int64_t n, double *out, hipStream_t st);
 template <int D, int N, typename T>
 void launch_coarse(const CoarseArgs<T> &a, hipStream_t st);
+template <int D, int N, typename T>
+void launch_permute(const BoxInfo *info, T *f, int64_t b0, int64_t nb, int to_split, int leaves_only,
+                    hipStream_t st);
+template <int D, int N, typename T>
+void launch_load_rho(const BoxInfo *info, const T *src, T *dst, int64_t nb, hipStream_t st);
 template <int D, int N>
 void launch_bc_derive(const BoxInfo *info, int64_t b0, int64_t nb, double *bc, hipStream_t st);
 template <typename T>

@@ -1,12 +1,17 @@
 // HIP kernels (gfx950) of the FAS multigrid Poisson solve on box grids.
 //
-// Every kernel works on a contiguous range of box ids (one level).  A box's
-// N^D cells are staged in LDS together with the side ghosts it needs; the
-// ghosts are computed on the fly from the neighbouring boxes (paper §2.4,
-// §3.3), so no ghost layer is ever stored in HBM.  Workgroups are 256 threads
-// (four wave64); in 3D one box per workgroup, in 2D eight boxes.  Workgroup
-// ids are remapped so that each of the eight XCDs processes a contiguous run
-// of boxes: Morton-ordered siblings and neighbours then share one L2.
+// Storage: every box holds its N^D cells colour-split, red cells (1-based
+// index sum even, paper §3.1) first, then black; within a colour z, y, x
+// (x fastest, every other cell).  A red-black half sweep therefore reads the
+// other colour and the right-hand side of its own colour and writes its own
+// colour, each as one contiguous run per box.  The caller's arrays keep the
+// natural x-fastest order; k_permute converts at the solve boundary.
+//
+// No ghost layer is stored: side ghosts (paper §2.4, §3.3) are computed on
+// the fly from the neighbouring boxes.  Workgroups are 256 threads (four
+// wave64); in 3D one box per workgroup, in 2D eight boxes.  Workgroup ids are
+// remapped so that each of the eight XCDs processes a contiguous run of boxes:
+// Morton-ordered siblings and neighbours then share one L2.
 #include <hip/hip_runtime.h>
 
 #include "afmg_internal.h"
@@ -21,9 +26,11 @@ struct Geo {
     static constexpr int P = N + 2;
     static constexpr int PC = D == 3 ? P * P * P : P * P;  // padded cells
     static constexpr int HALF = C / 2;
+    static constexpr int HN = N / 2;
     static constexpr int BPW = HALF >= 256 ? 1 : 256 / HALF;  // boxes per workgroup
     static constexpr int TPB = 256 / BPW;                     // threads per box
     static constexpr int NG = 2 * D * F;                      // side ghosts per box
+    static constexpr int NJ = (NG + TPB - 1) / TPB;           // ghosts per thread
     static constexpr int H = N / 2;                           // parent cells per axis under a box
     static constexpr int HC = D == 3 ? H * H * H : H * H;
     static constexpr int HF = D == 3 ? H * H : H;
@@ -31,20 +38,36 @@ struct Geo {
     static constexpr int QC = D == 3 ? Q * Q * Q : Q * Q;
 };
 
+// padded LDS index (natural order, ghost layer at -1 and N)
 template <int D, int N>
 __device__ __forceinline__ int padi(int i, int j, int k) {
     constexpr int P = N + 2;
     return D == 3 ? (i + 1) + P * ((j + 1) + P * (k + 1)) : (i + 1) + P * (j + 1);
 }
-template <int D, int N>
-__device__ __forceinline__ int offi(int i, int j, int k) {
-    return D == 3 ? i + N * (j + N * k) : i + N * j;
+// colour of a cell: 0 red, 1 black (0-based local indices; box offsets are even)
+template <int D>
+__device__ __forceinline__ int colour_of(int i, int j, int k) {
+    return (i + j + (D == 3 ? k : 0) + D) & 1;
 }
+// position of a cell inside its colour
 template <int D, int N>
-__device__ __forceinline__ void decode(int c, int &i, int &j, int &k) {
-    i = c % N;
-    j = (c / N) % N;
-    k = D == 3 ? c / (N * N) : 0;
+__device__ __forceinline__ int in_colour(int i, int j, int k) {
+    constexpr int HN = N / 2;
+    return (D == 3 ? (k * N + j) * HN : j * HN) + (i >> 1);
+}
+// storage position of a cell in a box
+template <int D, int N>
+__device__ __forceinline__ int cpos(int i, int j, int k) {
+    return colour_of<D>(i, j, k) * Geo<D, N>::HALF + in_colour<D, N>(i, j, k);
+}
+// cell of storage position e
+template <int D, int N>
+__device__ __forceinline__ void cell_of(int e, int &i, int &j, int &k) {
+    using G = Geo<D, N>;
+    const int c = e / G::HALF, r = e % G::HALF;
+    j = (r / G::HN) % N;
+    k = D == 3 ? r / (N * G::HN) : 0;
+    i = 2 * (r % G::HN) + ((c + D + j + k) & 1);
 }
 __device__ __forceinline__ int obit(int flags, int axis) { return (flags >> (1 + axis)) & 1; }
 
@@ -56,120 +79,6 @@ __device__ __forceinline__ int xcd_remap(int w, int G) {
     return x < r ? x * (q + 1) + p : r * (q + 1) + (x - r) * q + p;
 }
 
-// ---------------------------------------------------------------------------
-// ghost cells
-// ---------------------------------------------------------------------------
-
-// Side ghosts of box bi for field u whose interior is staged in s (padded).
-// Same-level neighbour: copy of its face layer.  Physical side: 2 b - u1
-// (b = 0 when homog).  Refinement boundary (paper §3.3, default scheme):
-//   2D  g = 1/2 uH + u1 - 1/4 (u1' + u2)
-//   3D  g = 1/2 uH + 5/4 u1 - 1/4 (u2 + u1' + u1'')
-// uH: cell of the coarser neighbour box containing the ghost centre; u2: next
-// cell inward; u1', u1'': tangential partners of u1 inside one coarse cell.
-template <int D, int N, typename T>
-__device__ void fill_ghosts(T *s, const BoxInfo &bi, const T *__restrict__ u,
-                            const T *__restrict__ bc, int homog, int t, int nt) {
-    using G = Geo<D, N>;
-    for (int g = t; g < G::NG; g += nt) {
-        const int side = g / G::F, m = g - side * G::F;
-        const int d = side >> 1, hi = side & 1;
-        const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-        const int a = m % N, c = D == 3 ? m / N : 0;
-        int x[3];
-        x[t1] = a;
-        x[t2] = c;
-        x[d] = hi ? N - 1 : 0;
-        const T u1 = s[padi<D, N>(x[0], x[1], x[2])];
-        const int v = bi.nbr[side];
-        T val;
-        if (v >= 0) {
-            int y[3] = {x[0], x[1], x[2]};
-            y[d] = hi ? 0 : N - 1;
-            val = u[(size_t)v * G::C + offi<D, N>(y[0], y[1], y[2])];
-        } else if (v == -1) {
-            const T bv = homog ? T(0) : bc[(size_t)bi.bcoff[side] * G::F + m];
-            val = T(2) * bv - u1;
-        } else {
-            const int cb = -v - 2;
-            int q[3];
-            q[d] = hi ? 0 : N - 1;
-            q[t1] = obit(bi.flags, t1) * (N / 2) + (a >> 1);
-            q[t2] = D == 3 ? obit(bi.flags, t2) * (N / 2) + (c >> 1) : 0;
-            const T uH = u[(size_t)cb * G::C + offi<D, N>(q[0], q[1], q[2])];
-            int x2[3] = {x[0], x[1], x[2]};
-            x2[d] = hi ? N - 2 : 1;
-            const T u2 = s[padi<D, N>(x2[0], x2[1], x2[2])];
-            int p1[3] = {x[0], x[1], x[2]};
-            p1[t1] ^= 1;
-            const T u1p = s[padi<D, N>(p1[0], p1[1], p1[2])];
-            if (D == 2) {
-                val = T(0.5) * uH + u1 - T(0.25) * (u1p + u2);
-            } else {
-                int p2[3] = {x[0], x[1], x[2]};
-                p2[t2] ^= 1;
-                const T u1pp = s[padi<D, N>(p2[0], p2[1], p2[2])];
-                val = T(0.5) * uH + T(1.25) * u1 - T(0.25) * ((u2 + u1p) + u1pp);
-            }
-        }
-        int gx[3] = {x[0], x[1], x[2]};
-        gx[d] = hi ? N : -1;
-        s[padi<D, N>(gx[0], gx[1], gx[2])] = val;
-    }
-}
-
-// Ghost of the correction delta = u - uold of box p on side `side` next to
-// its face cell x: the ghost formulas are linear, so the ghost of the
-// difference is the difference of the ghosts; Dirichlet values cancel.
-template <int D, int N, typename T>
-__device__ T delta_ghost(const BoxInfo &pi, int64_t p, int side, const int x[3],
-                         const T *__restrict__ u, const T *__restrict__ uold) {
-    using G = Geo<D, N>;
-    const int d = side >> 1, hi = side & 1;
-    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-    const size_t pb = (size_t)p * G::C;
-    const int v = pi.nbr[side];
-    auto del = [&](size_t base, int i, int j, int k) {
-        const size_t o = base + offi<D, N>(i, j, k);
-        return u[o] - uold[o];
-    };
-    if (v >= 0) {
-        int y[3] = {x[0], x[1], x[2]};
-        y[d] = hi ? 0 : N - 1;
-        return del((size_t)v * G::C, y[0], y[1], y[2]);
-    }
-    const T d1 = del(pb, x[0], x[1], x[2]);
-    if (v == -1) return -d1;
-    const int cb = -v - 2;
-    int q[3];
-    q[d] = hi ? 0 : N - 1;
-    q[t1] = obit(pi.flags, t1) * (N / 2) + (x[t1] >> 1);
-    q[t2] = D == 3 ? obit(pi.flags, t2) * (N / 2) + (x[t2] >> 1) : 0;
-    const T dH = del((size_t)cb * G::C, q[0], q[1], q[2]);
-    int x2[3] = {x[0], x[1], x[2]};
-    x2[d] = hi ? N - 2 : 1;
-    int p1[3] = {x[0], x[1], x[2]};
-    p1[t1] ^= 1;
-    const T d2 = del(pb, x2[0], x2[1], x2[2]);
-    const T d1p = del(pb, p1[0], p1[1], p1[2]);
-    if (D == 2) return T(0.5) * dH + d1 - T(0.25) * (d1p + d2);
-    int p2[3] = {x[0], x[1], x[2]};
-    p2[t2] ^= 1;
-    const T d1pp = del(pb, p2[0], p2[1], p2[2]);
-    return T(0.5) * dH + T(1.25) * d1 - T(0.25) * ((d2 + d1p) + d1pp);
-}
-
-template <int D, int N, typename T>
-__device__ __forceinline__ T nb_sum(const T *s, int i, int j, int k) {
-    if (D == 2)
-        return (s[padi<D, N>(i - 1, j, k)] + s[padi<D, N>(i + 1, j, k)]) +
-               (s[padi<D, N>(i, j - 1, k)] + s[padi<D, N>(i, j + 1, k)]);
-    return (s[padi<D, N>(i - 1, j, k)] + s[padi<D, N>(i + 1, j, k)]) +
-           (s[padi<D, N>(i, j - 1, k)] + s[padi<D, N>(i, j + 1, k)]) +
-           (s[padi<D, N>(i, j, k - 1)] + s[padi<D, N>(i, j, k + 1)]);
-}
-
-// Workgroup -> box slot of this thread.
 template <int D, int N>
 struct Slot {
     int64_t b;   // box id (clamped to a valid box)
@@ -189,77 +98,266 @@ __device__ __forceinline__ Slot<D, N> slot_of(int64_t b0, int nb) {
     return r;
 }
 
-template <int D, int N, typename T>
-__device__ __forceinline__ void stage_interior(T *s, const T *__restrict__ ub, int t) {
+// ---------------------------------------------------------------------------
+// side ghosts (paper §2.4, §3.3)
+// ---------------------------------------------------------------------------
+// A ghost next to face cell x on side S is
+//   same-level neighbour v:  its face cell across the side
+//   physical side:           2 b - u1          (b = 0 when homog)
+//   refinement boundary:     2D 1/2 uH + u1 - 1/4 (u1' + u2)
+//                            3D 1/2 uH + 5/4 u1 - 1/4 (u2 + u1' + u1'')
+// uH: cell of the coarser neighbour box containing the ghost centre; u2: next
+// cell inward; u1', u1'': tangential partners of u1 inside one coarse cell.
+// The global operand (neighbour cell, b or uH) is fetched first ("raw"), the
+// formula is finished once the box interior is in LDS.
+template <int S>
+struct SideOf {
+    static constexpr int d = S >> 1, hi = S & 1;
+    static constexpr int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+};
+
+template <int D, int N, int S>
+__device__ __forceinline__ void face_cell(int m, int x[3]) {
+    using SD = SideOf<S>;
+    x[SD::t1] = m % N;
+    x[SD::t2] = D == 3 ? m / N : 0;
+    x[SD::d] = SD::hi ? N - 1 : 0;
+}
+
+// raw operand of the ghost on side S next to face cell m of box bi
+template <int D, int N, int S, typename T>
+__device__ __forceinline__ T ghost_raw(const BoxInfo *__restrict__ bi, int m, const T *__restrict__ u,
+                                       const T *__restrict__ bc, int homog, int &v) {
+    using SD = SideOf<S>;
     using G = Geo<D, N>;
-    for (int c = t; c < G::C; c += G::TPB) {
-        int i, j, k;
-        decode<D, N>(c, i, j, k);
-        s[padi<D, N>(i, j, k)] = ub[c];
+    int x[3];
+    face_cell<D, N, S>(m, x);
+    v = bi->nbr[S];
+    if (v >= 0) {
+        x[SD::d] = SD::hi ? 0 : N - 1;
+        return u[(size_t)v * G::C + cpos<D, N>(x[0], x[1], x[2])];
     }
+    if (v == -1) return homog ? T(0) : bc[(size_t)bi->bcoff[S] * G::F + m];
+    const int flags = bi->flags;
+    int q[3];
+    q[SD::d] = SD::hi ? 0 : N - 1;
+    q[SD::t1] = obit(flags, SD::t1) * G::H + (x[SD::t1] >> 1);
+    q[SD::t2] = D == 3 ? obit(flags, SD::t2) * G::H + (x[SD::t2] >> 1) : 0;
+    return u[(size_t)(-v - 2) * G::C + cpos<D, N>(q[0], q[1], q[2])];
+}
+
+// finish the ghost from its raw operand; s is the padded box in LDS
+template <int D, int N, int S, typename T>
+__device__ __forceinline__ T ghost_finish(const T *s, int m, T raw, int v) {
+    using SD = SideOf<S>;
+    if (v >= 0) return raw;
+    int x[3];
+    face_cell<D, N, S>(m, x);
+    const T u1 = s[padi<D, N>(x[0], x[1], x[2])];
+    if (v == -1) return T(2) * raw - u1;
+    int y[3] = {x[0], x[1], x[2]};
+    y[SD::d] = SD::hi ? N - 2 : 1;
+    const T u2 = s[padi<D, N>(y[0], y[1], y[2])];
+    int p[3] = {x[0], x[1], x[2]};
+    p[SD::t1] ^= 1;
+    const T u1p = s[padi<D, N>(p[0], p[1], p[2])];
+    if (D == 2) return T(0.5) * raw + u1 - T(0.25) * (u1p + u2);
+    int r[3] = {x[0], x[1], x[2]};
+    r[SD::t2] ^= 1;
+    const T u1pp = s[padi<D, N>(r[0], r[1], r[2])];
+    return T(0.5) * raw + T(1.25) * u1 - T(0.25) * ((u2 + u1p) + u1pp);
+}
+
+template <int D, int N, int S>
+__device__ __forceinline__ int ghost_slot(int m) {
+    using SD = SideOf<S>;
+    int x[3];
+    face_cell<D, N, S>(m, x);
+    x[SD::d] = SD::hi ? N : -1;
+    return padi<D, N>(x[0], x[1], x[2]);
+}
+
+#define AFMG_SIDE_SWITCH(side, CALL) \
+    switch (side) {                  \
+    case 0: CALL(0); break;          \
+    case 1: CALL(1); break;          \
+    case 2: CALL(2); break;          \
+    case 3: CALL(3); break;          \
+    case 4: CALL(4); break;          \
+    default: CALL(5); break;         \
+    }
+
+// Staging of one box with its ghosts in two phases around a barrier:
+// begin() loads the interior into the padded LDS box and fetches the raw
+// ghost operands; after __syncthreads, end() writes the ghost slots; one more
+// __syncthreads and the box is ready.
+template <int D, int N, typename T>
+struct Stager {
+    using G = Geo<D, N>;
+    T raw[G::NJ];
+    int v[G::NJ];
+
+    __device__ void begin(T *s, const BoxInfo *__restrict__ bi, const T *__restrict__ ub,
+                          const T *__restrict__ u, const T *__restrict__ bc, int homog, int t, bool ghosts) {
+        for (int e = t; e < G::C; e += G::TPB) {
+            int i, j, k;
+            cell_of<D, N>(e, i, j, k);
+            s[padi<D, N>(i, j, k)] = ub[e];
+        }
+        if (!ghosts) return;
+#pragma unroll
+        for (int q = 0; q < G::NJ; q++) {
+            const int g = t + q * G::TPB;
+            if (g < G::NG) {
+                const int side = g / G::F, m = g % G::F;
+#define AFMG_RAW(S) raw[q] = ghost_raw<D, N, S, T>(bi, m, u, bc, homog, v[q])
+                AFMG_SIDE_SWITCH(side, AFMG_RAW)
+#undef AFMG_RAW
+            }
+        }
+    }
+    __device__ void end(T *s, int t) {
+#pragma unroll
+        for (int q = 0; q < G::NJ; q++) {
+            const int g = t + q * G::TPB;
+            if (g < G::NG) {
+                const int side = g / G::F, m = g % G::F;
+#define AFMG_FIN(S) s[ghost_slot<D, N, S>(m)] = ghost_finish<D, N, S, T>(s, m, raw[q], v[q])
+                AFMG_SIDE_SWITCH(side, AFMG_FIN)
+#undef AFMG_FIN
+            }
+        }
+    }
+};
+
+template <int D, int N, typename T>
+__device__ __forceinline__ T nb_sum(const T *s, int i, int j, int k) {
+    if (D == 2)
+        return (s[padi<D, N>(i - 1, j, k)] + s[padi<D, N>(i + 1, j, k)]) +
+               (s[padi<D, N>(i, j - 1, k)] + s[padi<D, N>(i, j + 1, k)]);
+    return (s[padi<D, N>(i - 1, j, k)] + s[padi<D, N>(i + 1, j, k)]) +
+           (s[padi<D, N>(i, j - 1, k)] + s[padi<D, N>(i, j + 1, k)]) +
+           (s[padi<D, N>(i, j, k - 1)] + s[padi<D, N>(i, j, k + 1)]);
 }
 
 // ---------------------------------------------------------------------------
 // Gauss-Seidel red-black half sweep (paper §3.1)
 // ---------------------------------------------------------------------------
-// Red cells: 1-based index sum even, i.e. (i0 + j0 + k0 + D) even for 0-based
-// indices (box offsets are multiples of N, which is even).
+// Thread t of a box updates cell `colour*HALF + t`.  Only the other colour is
+// staged in LDS; each thread fetches the ghosts of its own cell (at most one
+// per axis) and, next to Dirichlet or refinement sides, its own old value.
 template <int D, int N, typename T>
 __global__ __launch_bounds__(256) void k_gsrb(LevelArgs<T> a, int colour) {
     using G = Geo<D, N>;
-    __shared__ T sm[G::BPW * G::PC];
+    __shared__ T so[G::BPW * G::HALF];
     const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb);
-    T *s = sm + sl.slot * G::PC;
-    const BoxInfo bi = a.info[sl.b];
-    T *ub = a.u + (size_t)sl.b * G::C;
-    if (sl.valid) stage_interior<D, N, T>(s, ub, sl.t);
-    __syncthreads();
-    if (sl.valid) fill_ghosts<D, N, T>(s, bi, a.u, a.bc, a.homog, sl.t, G::TPB);
+    T *s = so + sl.slot * G::HALF;
+    const int64_t b = sl.b;
+    const BoxInfo *bi = a.info + b;
+    T *ub = a.u + (size_t)b * G::C;
+    const int e = colour * G::HALF + sl.t;
+    int c[3];
+    cell_of<D, N>(e, c[0], c[1], c[2]);
+    T rho_c = T(0), own = T(0);
+    T graw[3] = {T(0), T(0), T(0)};
+    int gv[3] = {0, 0, 0};
+    if (sl.valid) {
+        s[sl.t] = ub[(1 - colour) * G::HALF + sl.t];
+        rho_c = a.rho[(size_t)b * G::C + e];
+        bool need_own = false;
+#pragma unroll
+        for (int d = 0; d < D; d++) {
+            if (c[d] == 0 || c[d] == N - 1) {
+                const int m = D == 3 ? c[d == 0 ? 1 : 0] + N * c[d == 2 ? 1 : 2] : c[d == 0 ? 1 : 0];
+                const bool hi = c[d] == N - 1;
+#define AFMG_GR(S) graw[d] = ghost_raw<D, N, S, T>(bi, m, a.u, a.bc, a.homog, gv[d])
+                if (d == 0) { if (hi) AFMG_GR(1); else AFMG_GR(0); }
+                else if (d == 1) { if (hi) AFMG_GR(3); else AFMG_GR(2); }
+                else { if (hi) AFMG_GR(5); else AFMG_GR(4); }
+#undef AFMG_GR
+                need_own |= gv[d] < 0;
+            }
+        }
+        if (need_own) own = ub[e];
+    }
     __syncthreads();
     if (!sl.valid) return;
-    const T *rb = ((bi.flags & FLAG_LEAF) ? a.rho_user : a.rho_w) + (size_t)sl.b * G::C;
-    constexpr int HN = N / 2;
-    const int t = sl.t;
-    int i, j, k;
-    if (D == 3) {
-        k = t / (N * HN);
-        j = (t / HN) % N;
-    } else {
-        k = 0;
-        j = t / HN;
+    auto oth = [&](int i, int j, int k) { return s[in_colour<D, N>(i, j, k)]; };
+    T lo[3], hi[3];
+#pragma unroll
+    for (int d = 0; d < D; d++) {
+        const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+        // neighbours inside the box
+        int m1[3] = {c[0], c[1], c[2]}, p1[3] = {c[0], c[1], c[2]};
+        m1[d] -= 1;
+        p1[d] += 1;
+        lo[d] = c[d] > 0 ? oth(m1[0], m1[1], m1[2]) : T(0);
+        hi[d] = c[d] < N - 1 ? oth(p1[0], p1[1], p1[2]) : T(0);
+        if (c[d] == 0 || c[d] == N - 1) {
+            const bool h = c[d] == N - 1;
+            T g;
+            if (gv[d] >= 0) {
+                g = graw[d];
+            } else if (gv[d] == -1) {
+                g = T(2) * graw[d] - own;
+            } else {
+                int y[3] = {c[0], c[1], c[2]};
+                y[d] += h ? -1 : 1;
+                int q1[3] = {c[0], c[1], c[2]};
+                q1[t1] ^= 1;
+                const T u2 = oth(y[0], y[1], y[2]);
+                const T u1p = oth(q1[0], q1[1], q1[2]);
+                if (D == 2) {
+                    g = T(0.5) * graw[d] + own - T(0.25) * (u1p + u2);
+                } else {
+                    int q2[3] = {c[0], c[1], c[2]};
+                    q2[t2] ^= 1;
+                    const T u1pp = oth(q2[0], q2[1], q2[2]);
+                    g = T(0.5) * graw[d] + T(1.25) * own - T(0.25) * ((u2 + u1p) + u1pp);
+                }
+            }
+            if (h) hi[d] = g;
+            else lo[d] = g;
+        }
     }
-    i = 2 * (t % HN) + ((colour + D + j + k) & 1);
-    const int c = offi<D, N>(i, j, k);
-    const T sum = nb_sum<D, N, T>(s, i, j, k);
-    ub[c] = (sum - a.h2 * rb[c]) / T(2 * D);
+    const T sum = D == 3 ? ((lo[0] + hi[0]) + (lo[1] + hi[1])) + (lo[2] + hi[2])
+                         : (lo[0] + hi[0]) + (lo[1] + hi[1]);
+    ub[e] = (sum - a.h2 * rho_c) / T(2 * D);
 }
 
 // ---------------------------------------------------------------------------
 // residual (eq. residual) and restriction by averaging (paper §2.5)
 // ---------------------------------------------------------------------------
-// For every box of level l: r = rho - L u; the box's octant of its parent
-// receives mean(u) in u and mean(r) in rho_w (the restricted residual, which
-// k_coarse_rhs then turns into the FAS right-hand side).
-template <int D, int N, typename T>
-__device__ __forceinline__ void restrict_octant(const T *s, T *__restrict__ dst, const BoxInfo &bi,
-                                                int t, int nt, bool padded) {
+// The octant of box bi's parent receives the mean of each 2^D block of src
+// (src in LDS, padded or plain natural order).
+template <int D, int N, typename T, bool PADDED>
+__device__ __forceinline__ void restrict_octant(const T *s, T *__restrict__ dst, const BoxInfo *__restrict__ bi,
+                                                int t) {
     using G = Geo<D, N>;
     const T w = D == 3 ? T(0.125) : T(0.25);
-    for (int pc = t; pc < G::HC; pc += nt) {
+    const int flags = bi->flags;
+    const int64_t p = bi->parent;
+    for (int pc = t; pc < G::HC; pc += G::TPB) {
         const int I = pc % G::H, J = (pc / G::H) % G::H, K = D == 3 ? pc / (G::H * G::H) : 0;
         T acc = T(0);
+#pragma unroll
         for (int dk = 0; dk < (D == 3 ? 2 : 1); dk++)
+#pragma unroll
             for (int dj = 0; dj < 2; dj++)
+#pragma unroll
                 for (int di = 0; di < 2; di++) {
                     const int i = 2 * I + di, j = 2 * J + dj, k = D == 3 ? 2 * K + dk : 0;
-                    acc += padded ? s[padi<D, N>(i, j, k)] : s[offi<D, N>(i, j, k)];
+                    acc += PADDED ? s[padi<D, N>(i, j, k)] : s[D == 3 ? i + N * (j + N * k) : i + N * j];
                 }
-        const int X = obit(bi.flags, 0) * G::H + I, Y = obit(bi.flags, 1) * G::H + J,
-                  Z = D == 3 ? obit(bi.flags, 2) * G::H + K : 0;
-        dst[(size_t)bi.parent * G::C + offi<D, N>(X, Y, Z)] = w * acc;
+        const int X = obit(flags, 0) * G::H + I, Y = obit(flags, 1) * G::H + J,
+                  Z = D == 3 ? obit(flags, 2) * G::H + K : 0;
+        dst[(size_t)p * G::C + cpos<D, N>(X, Y, Z)] = w * acc;
     }
 }
 
+// Boxes of level l: r = rho - L u; the parent's octant receives mean(u) in u
+// and mean(r) in rho (the restricted residual, turned into the FAS
+// right-hand side by k_coarse_rhs).
 template <int D, int N, typename T>
 __global__ __launch_bounds__(256) void k_resid_restrict(LevelArgs<T> a) {
     using G = Geo<D, N>;
@@ -268,59 +366,54 @@ __global__ __launch_bounds__(256) void k_resid_restrict(LevelArgs<T> a) {
     const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb);
     T *s = sm + sl.slot * G::PC;
     T *r = rs + sl.slot * G::C;
-    const BoxInfo bi = a.info[sl.b];
-    const T *ub = a.u + (size_t)sl.b * G::C;
-    if (sl.valid) stage_interior<D, N, T>(s, ub, sl.t);
+    const BoxInfo *bi = a.info + sl.b;
+    const size_t bo = (size_t)sl.b * G::C;
+    Stager<D, N, T> st;
+    if (sl.valid) st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, true);
     __syncthreads();
-    if (sl.valid) fill_ghosts<D, N, T>(s, bi, a.u, a.bc, a.homog, sl.t, G::TPB);
+    if (sl.valid) st.end(s, sl.t);
     __syncthreads();
     if (sl.valid) {
-        const T *rb = ((bi.flags & FLAG_LEAF) ? a.rho_user : a.rho_w) + (size_t)sl.b * G::C;
-        for (int c = sl.t; c < G::C; c += G::TPB) {
+        for (int e = sl.t; e < G::C; e += G::TPB) {
             int i, j, k;
-            decode<D, N>(c, i, j, k);
-            r[c] = rb[c] - (nb_sum<D, N, T>(s, i, j, k) - T(2 * D) * s[padi<D, N>(i, j, k)]) * a.ih2;
+            cell_of<D, N>(e, i, j, k);
+            r[D == 3 ? i + N * (j + N * k) : i + N * j] =
+                a.rho[bo + e] - (nb_sum<D, N, T>(s, i, j, k) - T(2 * D) * s[padi<D, N>(i, j, k)]) * a.ih2;
         }
     }
     __syncthreads();
     if (!sl.valid) return;
-    restrict_octant<D, N, T>(s, a.u, bi, sl.t, G::TPB, true);
-    restrict_octant<D, N, T>(r, a.rho_w, bi, sl.t, G::TPB, false);
+    restrict_octant<D, N, T, true>(s, a.u, bi, sl.t);
+    restrict_octant<D, N, T, false>(r, a.rho, bi, sl.t);
 }
 
 // ---------------------------------------------------------------------------
 // FAS coarse right-hand side (eq. coarse-rhs) and the copy v'_H
 // ---------------------------------------------------------------------------
-// Boxes of level l-1: uold <- u; on parents rho_w <- rbar + L_H u (rho_w
-// holds rbar = the restricted residual).
+// Boxes of level l-1: uold <- u; on parents rho <- rbar + L_H u (rho holds
+// rbar, the restricted residual).
 template <int D, int N, typename T>
 __global__ __launch_bounds__(256) void k_coarse_rhs(LevelArgs<T> a) {
     using G = Geo<D, N>;
     __shared__ T sm[G::BPW * G::PC];
     const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb);
     T *s = sm + sl.slot * G::PC;
-    const BoxInfo bi = a.info[sl.b];
-    const T *ub = a.u + (size_t)sl.b * G::C;
-    const bool parent = !(bi.flags & FLAG_LEAF);
+    const BoxInfo *bi = a.info + sl.b;
+    const size_t bo = (size_t)sl.b * G::C;
+    const bool parent = !(bi->flags & FLAG_LEAF);
+    Stager<D, N, T> st;
     if (sl.valid) {
-        T *ob = a.uold + (size_t)sl.b * G::C;
-        for (int c = sl.t; c < G::C; c += G::TPB) {
-            int i, j, k;
-            decode<D, N>(c, i, j, k);
-            const T v = ub[c];
-            ob[c] = v;
-            s[padi<D, N>(i, j, k)] = v;
-        }
+        for (int e = sl.t; e < G::C; e += G::TPB) a.uold[bo + e] = a.u[bo + e];
+        st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, parent);
     }
     __syncthreads();
-    if (sl.valid && parent) fill_ghosts<D, N, T>(s, bi, a.u, a.bc, a.homog, sl.t, G::TPB);
+    if (sl.valid && parent) st.end(s, sl.t);
     __syncthreads();
     if (!sl.valid || !parent) return;
-    T *rw = a.rho_w + (size_t)sl.b * G::C;
-    for (int c = sl.t; c < G::C; c += G::TPB) {
+    for (int e = sl.t; e < G::C; e += G::TPB) {
         int i, j, k;
-        decode<D, N>(c, i, j, k);
-        rw[c] = rw[c] + (nb_sum<D, N, T>(s, i, j, k) - T(2 * D) * s[padi<D, N>(i, j, k)]) * a.ih2;
+        cell_of<D, N>(e, i, j, k);
+        a.rho[bo + e] = a.rho[bo + e] + (nb_sum<D, N, T>(s, i, j, k) - T(2 * D) * s[padi<D, N>(i, j, k)]) * a.ih2;
     }
 }
 
@@ -329,7 +422,9 @@ __global__ __launch_bounds__(256) void k_coarse_rhs(LevelArgs<T> a) {
 // ---------------------------------------------------------------------------
 // Boxes of level l: u += P(delta), delta = u - uold of the parent (level
 // l-1).  The parent's octant under the box plus a one-cell face halo is
-// staged; halo cells outside the parent come from delta_ghost.
+// staged; halo cells outside the parent are ghosts of delta.  The ghost
+// formulas are linear, so the ghost of delta is the formula applied to
+// deltas, and Dirichlet values cancel (2b - u1 minus 2b - u1_old).
 //   2D: 1/2 d(P) + 1/4 d(P + sx ex) + 1/4 d(P + sy ey)
 //   3D: 1/4 [d(P) + d(P + sx ex) + d(P + sy ey) + d(P + sz ez)]
 // with s = -1 for a fine cell in the lower half of its parent cell.
@@ -339,54 +434,104 @@ __device__ __forceinline__ int qpad(int I, int J, int K) {
     return D == 3 ? (I + 1) + Q * ((J + 1) + Q * (K + 1)) : (I + 1) + Q * (J + 1);
 }
 
+template <int D, int N, int S, typename T>
+__device__ __forceinline__ T delta_ghost(const BoxInfo *__restrict__ pi, int64_t p, const int x[3],
+                                         const T *__restrict__ u, const T *__restrict__ uold) {
+    using SD = SideOf<S>;
+    using G = Geo<D, N>;
+    auto del = [&](int64_t box, int i, int j, int k) {
+        const size_t o = (size_t)box * G::C + cpos<D, N>(i, j, k);
+        return u[o] - uold[o];
+    };
+    const int v = pi->nbr[S];
+    if (v >= 0) {
+        int y[3] = {x[0], x[1], x[2]};
+        y[SD::d] = SD::hi ? 0 : N - 1;
+        return del(v, y[0], y[1], y[2]);
+    }
+    const T d1 = del(p, x[0], x[1], x[2]);
+    if (v == -1) return -d1;
+    const int flags = pi->flags;
+    int q[3];
+    q[SD::d] = SD::hi ? 0 : N - 1;
+    q[SD::t1] = obit(flags, SD::t1) * G::H + (x[SD::t1] >> 1);
+    q[SD::t2] = D == 3 ? obit(flags, SD::t2) * G::H + (x[SD::t2] >> 1) : 0;
+    const T dH = del(-v - 2, q[0], q[1], q[2]);
+    int y[3] = {x[0], x[1], x[2]};
+    y[SD::d] = SD::hi ? N - 2 : 1;
+    int p1[3] = {x[0], x[1], x[2]};
+    p1[SD::t1] ^= 1;
+    const T d2 = del(p, y[0], y[1], y[2]);
+    const T d1p = del(p, p1[0], p1[1], p1[2]);
+    if (D == 2) return T(0.5) * dH + d1 - T(0.25) * (d1p + d2);
+    int p2[3] = {x[0], x[1], x[2]};
+    p2[SD::t2] ^= 1;
+    const T d1pp = del(p, p2[0], p2[1], p2[2]);
+    return T(0.5) * dH + T(1.25) * d1 - T(0.25) * ((d2 + d1p) + d1pp);
+}
+
+// halo cell m of side S of the octant (o = octant origin in parent cells)
+template <int D, int N, int S, typename T>
+__device__ __forceinline__ void prolong_halo(T *q, int m, const int o[3], const BoxInfo *__restrict__ pi,
+                                             int64_t p, const T *__restrict__ u, const T *__restrict__ uold) {
+    using SD = SideOf<S>;
+    using G = Geo<D, N>;
+    int L[3];
+    L[SD::t1] = m % G::H;
+    L[SD::t2] = D == 3 ? m / G::H : 0;
+    L[SD::d] = SD::hi ? G::H : -1;
+    int X[3] = {o[0] + L[0], o[1] + L[1], D == 3 ? o[2] + L[2] : 0};
+    T val;
+    if (X[SD::d] >= 0 && X[SD::d] < N) {
+        const size_t oo = (size_t)p * G::C + cpos<D, N>(X[0], X[1], X[2]);
+        val = u[oo] - uold[oo];
+    } else {
+        X[SD::d] = SD::hi ? N - 1 : 0;
+        val = delta_ghost<D, N, S, T>(pi, p, X, u, uold);
+    }
+    q[qpad<D, N>(L[0], L[1], L[2])] = val;
+}
+
 template <int D, int N, typename T>
 __global__ __launch_bounds__(256) void k_prolong(LevelArgs<T> a) {
     using G = Geo<D, N>;
     __shared__ T qs[G::BPW * G::QC];
     const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb);
     T *q = qs + sl.slot * G::QC;
-    const BoxInfo bi = a.info[sl.b];
+    const BoxInfo *bi = a.info + sl.b;
+    const size_t bo = (size_t)sl.b * G::C;
+    T ucell[(G::C + G::TPB - 1) / G::TPB];
     if (sl.valid) {
-        const int64_t p = bi.parent;
-        const BoxInfo pi = a.info[p];
-        const int o[3] = {obit(bi.flags, 0) * G::H, obit(bi.flags, 1) * G::H,
-                          D == 3 ? obit(bi.flags, 2) * G::H : 0};
-        const size_t pb = (size_t)p * G::C;
-        // octant interior
+        // own cells first: their loads overlap with the parent's
+#pragma unroll
+        for (int r = 0; r < (G::C + G::TPB - 1) / G::TPB; r++) {
+            const int e = sl.t + r * G::TPB;
+            if (e < G::C) ucell[r] = a.u[bo + e];
+        }
+        const int flags = bi->flags;
+        const int64_t p = bi->parent;
+        const BoxInfo *pi = a.info + p;
+        const int o[3] = {obit(flags, 0) * G::H, obit(flags, 1) * G::H, D == 3 ? obit(flags, 2) * G::H : 0};
         for (int pc = sl.t; pc < G::HC; pc += G::TPB) {
             const int I = pc % G::H, J = (pc / G::H) % G::H, K = D == 3 ? pc / (G::H * G::H) : 0;
-            const size_t oo = pb + offi<D, N>(o[0] + I, o[1] + J, o[2] + K);
+            const size_t oo = (size_t)p * G::C + cpos<D, N>(o[0] + I, o[1] + J, o[2] + K);
             q[qpad<D, N>(I, J, K)] = a.u[oo] - a.uold[oo];
         }
-        // face halos
         for (int hc = sl.t; hc < 2 * D * G::HF; hc += G::TPB) {
             const int side = hc / G::HF, m = hc % G::HF;
-            const int d = side >> 1, hi = side & 1;
-            const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-            int L[3];
-            L[t1] = m % G::H;
-            L[t2] = D == 3 ? m / G::H : 0;
-            L[d] = hi ? G::H : -1;
-            int X[3] = {o[0] + L[0], o[1] + L[1], o[2] + L[2]};
-            if (D == 2) X[2] = 0;
-            T val;
-            if (X[d] >= 0 && X[d] < N) {
-                const size_t oo = pb + offi<D, N>(X[0], X[1], X[2]);
-                val = a.u[oo] - a.uold[oo];
-            } else {
-                int x[3] = {X[0], X[1], X[2]};
-                x[d] = hi ? N - 1 : 0;
-                val = delta_ghost<D, N, T>(pi, p, 2 * d + hi, x, a.u, a.uold);
-            }
-            q[qpad<D, N>(L[0], L[1], L[2])] = val;
+#define AFMG_HALO(S) prolong_halo<D, N, S, T>(q, m, o, pi, p, a.u, a.uold)
+            AFMG_SIDE_SWITCH(side, AFMG_HALO)
+#undef AFMG_HALO
         }
     }
     __syncthreads();
     if (!sl.valid) return;
-    T *ub = a.u + (size_t)sl.b * G::C;
-    for (int c = sl.t; c < G::C; c += G::TPB) {
+#pragma unroll
+    for (int r = 0; r < (G::C + G::TPB - 1) / G::TPB; r++) {
+        const int e = sl.t + r * G::TPB;
+        if (e >= G::C) break;
         int i, j, k;
-        decode<D, N>(c, i, j, k);
+        cell_of<D, N>(e, i, j, k);
         const int I = i >> 1, J = j >> 1, K = k >> 1;
         const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
         T v;
@@ -394,11 +539,10 @@ __global__ __launch_bounds__(256) void k_prolong(LevelArgs<T> a) {
             v = T(0.5) * q[qpad<D, N>(I, J, 0)] + T(0.25) * q[qpad<D, N>(I + sx, J, 0)] +
                 T(0.25) * q[qpad<D, N>(I, J + sy, 0)];
         } else {
-            v = T(0.25) * (((q[qpad<D, N>(I, J, K)] + q[qpad<D, N>(I + sx, J, K)]) +
-                            q[qpad<D, N>(I, J + sy, K)]) +
+            v = T(0.25) * (((q[qpad<D, N>(I, J, K)] + q[qpad<D, N>(I + sx, J, K)]) + q[qpad<D, N>(I, J + sy, K)]) +
                            q[qpad<D, N>(I, J, K + sz)]);
         }
-        ub[c] = ub[c] + v;
+        a.u[bo + e] = ucell[r] + v;
     }
 }
 
@@ -409,30 +553,29 @@ __global__ __launch_bounds__(256) void k_prolong(LevelArgs<T> a) {
 // leaves r = rho - L u, and the workgroup writes (max |r|, sum r^2 h^D) to
 // partial[part0 + workgroup].
 template <int D, int N, typename T>
-__global__ __launch_bounds__(256) void k_final(LevelArgs<T> a, double *partial, int64_t part0,
-                                               double hD) {
+__global__ __launch_bounds__(256) void k_final(LevelArgs<T> a, double *partial, int64_t part0, double hD) {
     using G = Geo<D, N>;
     __shared__ T sm[G::BPW * G::PC];
     __shared__ double red_m[256], red_s[256];
     const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb);
     T *s = sm + sl.slot * G::PC;
-    const BoxInfo bi = a.info[sl.b];
-    const T *ub = a.u + (size_t)sl.b * G::C;
-    const bool leaf = bi.flags & FLAG_LEAF;
-    if (sl.valid) stage_interior<D, N, T>(s, ub, sl.t);
+    const BoxInfo *bi = a.info + sl.b;
+    const size_t bo = (size_t)sl.b * G::C;
+    const bool leaf = bi->flags & FLAG_LEAF;
+    Stager<D, N, T> st;
+    if (sl.valid) st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, leaf);
     __syncthreads();
-    if (sl.valid && leaf) fill_ghosts<D, N, T>(s, bi, a.u, a.bc, a.homog, sl.t, G::TPB);
+    if (sl.valid && leaf) st.end(s, sl.t);
     __syncthreads();
     double mx = 0.0, ss = 0.0;
     if (sl.valid) {
-        if (bi.parent >= 0) restrict_octant<D, N, T>(s, a.u, bi, sl.t, G::TPB, true);
+        if (bi->parent >= 0) restrict_octant<D, N, T, true>(s, a.u, bi, sl.t);
         if (leaf) {
-            const T *rb = a.rho_user + (size_t)sl.b * G::C;
-            for (int c = sl.t; c < G::C; c += G::TPB) {
+            for (int e = sl.t; e < G::C; e += G::TPB) {
                 int i, j, k;
-                decode<D, N>(c, i, j, k);
-                const double r = (double)(rb[c] - (nb_sum<D, N, T>(s, i, j, k) -
-                                                   T(2 * D) * s[padi<D, N>(i, j, k)]) * a.ih2);
+                cell_of<D, N>(e, i, j, k);
+                const double r = (double)(a.rho[bo + e] - (nb_sum<D, N, T>(s, i, j, k) -
+                                                          T(2 * D) * s[padi<D, N>(i, j, k)]) * a.ih2);
                 mx = fmax(mx, fabs(r));
                 ss += r * r;
             }
@@ -454,19 +597,27 @@ __global__ __launch_bounds__(256) void k_final(LevelArgs<T> a, double *partial, 
     }
 }
 
-// One workgroup: out[0] = max over partial maxima, out[1] = sqrt(sum of
-// partial sums); fixed reduction order.
-__global__ __launch_bounds__(256) void k_reduce(const double *partial, int64_t n, double *out) {
-    __shared__ double rm[256], rsum[256];
-    double mx = 0.0, ss = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 256) {
-        mx = fmax(mx, partial[2 * i]);
-        ss += partial[2 * i + 1];
+// One workgroup of 1024 threads: out[0] = max of the partial maxima, out[1] =
+// sqrt of the sum of the partial sums; the reduction order is fixed.
+__global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ partial, int64_t n, double *out) {
+    __shared__ double rm[1024], rsum[1024];
+    double mx[4] = {0.0, 0.0, 0.0, 0.0}, ss[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t i = threadIdx.x;
+    for (; i + 3 * 1024 < n; i += 4 * 1024) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            mx[q] = fmax(mx[q], partial[2 * (i + q * 1024)]);
+            ss[q] += partial[2 * (i + q * 1024) + 1];
+        }
     }
-    rm[threadIdx.x] = mx;
-    rsum[threadIdx.x] = ss;
+    for (; i < n; i += 1024) {
+        mx[0] = fmax(mx[0], partial[2 * i]);
+        ss[0] += partial[2 * i + 1];
+    }
+    rm[threadIdx.x] = fmax(fmax(mx[0], mx[1]), fmax(mx[2], mx[3]));
+    rsum[threadIdx.x] = (ss[0] + ss[1]) + (ss[2] + ss[3]);
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (int w = 512; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) {
             rm[threadIdx.x] = fmax(rm[threadIdx.x], rm[threadIdx.x + w]);
             rsum[threadIdx.x] += rsum[threadIdx.x + w];
@@ -474,7 +625,7 @@ __global__ __launch_bounds__(256) void k_reduce(const double *partial, int64_t n
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        // propagate NaN: fmax drops NaN operands, the sum keeps them
+        // fmax drops NaN operands; the sum keeps them
         const double s = rsum[0];
         out[0] = (s == s) ? rm[0] : s;
         out[1] = sqrt(s);
@@ -482,16 +633,66 @@ __global__ __launch_bounds__(256) void k_reduce(const double *partial, int64_t n
 }
 
 // ---------------------------------------------------------------------------
-// small helpers: restriction of rho (FMG), copies, Dirichlet rows of parents
+// small helpers
 // ---------------------------------------------------------------------------
+// FMG: the parent's octant of rho receives the mean of the box's rho.
 template <int D, int N, typename T>
 __global__ __launch_bounds__(256) void k_restrict_rho(LevelArgs<T> a) {
     using G = Geo<D, N>;
+    __shared__ T sm[G::BPW * G::C];
     const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb);
-    if (!sl.valid) return;
-    const BoxInfo bi = a.info[sl.b];
-    const T *rb = ((bi.flags & FLAG_LEAF) ? a.rho_user : a.rho_w) + (size_t)sl.b * G::C;
-    restrict_octant<D, N, T>(rb, a.rho_w, bi, sl.t, G::TPB, false);
+    T *s = sm + sl.slot * G::C;
+    const BoxInfo *bi = a.info + sl.b;
+    const size_t bo = (size_t)sl.b * G::C;
+    if (sl.valid) {
+        for (int e = sl.t; e < G::C; e += G::TPB) {
+            int i, j, k;
+            cell_of<D, N>(e, i, j, k);
+            s[D == 3 ? i + N * (j + N * k) : i + N * j] = a.rho[bo + e];
+        }
+    }
+    __syncthreads();
+    if (sl.valid) restrict_octant<D, N, T, false>(s, a.rho, bi, sl.t);
+}
+
+// In-place conversion of whole boxes between the caller's order (x fastest)
+// and the colour-split storage.  to_split = 1: natural -> split.  Only boxes
+// whose leaf flag matches `which` (0 all, 1 leaves) are converted.
+template <int D, int N, typename T>
+__global__ __launch_bounds__(256) void k_permute(const BoxInfo *__restrict__ info, T *f, int64_t b0, int nb,
+                                                 int to_split, int which) {
+    using G = Geo<D, N>;
+    __shared__ T sm[G::BPW * G::C];
+    const Slot<D, N> sl = slot_of<D, N>(b0, nb);
+    T *s = sm + sl.slot * G::C;
+    const bool go = sl.valid && (which == 0 || (info[sl.b].flags & FLAG_LEAF));
+    T *fb = f + (size_t)sl.b * G::C;
+    if (go)
+        for (int e = sl.t; e < G::C; e += G::TPB) s[e] = fb[e];
+    __syncthreads();
+    if (!go) return;
+    for (int e = sl.t; e < G::C; e += G::TPB) {
+        int i, j, k;
+        cell_of<D, N>(e, i, j, k);
+        const int n = D == 3 ? i + N * (j + N * k) : i + N * j;
+        if (to_split) fb[e] = s[n];
+        else fb[n] = s[e];
+    }
+}
+
+// Copy of the caller's rho on leaf boxes into the colour-split working rho.
+template <int D, int N, typename T>
+__global__ __launch_bounds__(256) void k_load_rho(const BoxInfo *__restrict__ info, const T *__restrict__ src,
+                                                  T *__restrict__ dst, int nb) {
+    using G = Geo<D, N>;
+    const Slot<D, N> sl = slot_of<D, N>(0, nb);
+    if (!sl.valid || !(info[sl.b].flags & FLAG_LEAF)) return;
+    const size_t bo = (size_t)sl.b * G::C;
+    for (int e = sl.t; e < G::C; e += G::TPB) {
+        int i, j, k;
+        cell_of<D, N>(e, i, j, k);
+        dst[bo + e] = src[bo + (D == 3 ? i + N * (j + N * k) : i + N * j)];
+    }
 }
 
 template <typename T>
@@ -506,10 +707,11 @@ __global__ __launch_bounds__(256) void k_fill(T *__restrict__ dst, int64_t n, T 
 }
 
 // Boxes of level l (children): each physical side writes the covered part of
-// its parent's Dirichlet row as means of 2^(D-1) child face values.
+// its parent's Dirichlet row as means of 2^(D-1) child face values (the rows
+// are in face order, tangential axes increasing, first fastest).
 template <int D, int N>
-__global__ __launch_bounds__(256) void k_bc_derive(const BoxInfo *__restrict__ info, int64_t b0,
-                                                   int nb, double *bc) {
+__global__ __launch_bounds__(256) void k_bc_derive(const BoxInfo *__restrict__ info, int64_t b0, int nb,
+                                                   double *bc) {
     using G = Geo<D, N>;
     const int64_t bl = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t work = (int64_t)nb * 2 * D * G::HF;
@@ -517,19 +719,19 @@ __global__ __launch_bounds__(256) void k_bc_derive(const BoxInfo *__restrict__ i
     const int64_t b = b0 + bl / (2 * D * G::HF);
     const int rem = (int)(bl % (2 * D * G::HF));
     const int side = rem / G::HF, m = rem % G::HF;
-    const BoxInfo bi = info[b];
-    if (bi.nbr[side] != -1 || bi.parent < 0) return;
-    const BoxInfo pi = info[bi.parent];
+    const BoxInfo *bi = info + b;
+    if (bi->nbr[side] != -1 || bi->parent < 0) return;
+    const BoxInfo *pi = info + bi->parent;
     const int d = side >> 1;
     const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
     const int A = m % G::H, Cc = D == 3 ? m / G::H : 0;
-    const double *cr = bc + (size_t)bi.bcoff[side] * G::F;
+    const double *cr = bc + (size_t)bi->bcoff[side] * G::F;
     double acc = 0.0;
     for (int dc = 0; dc < (D == 3 ? 2 : 1); dc++)
         for (int da = 0; da < 2; da++) acc += cr[(2 * A + da) + N * (2 * Cc + dc)];
-    const int pa = obit(bi.flags, t1) * G::H + A;
-    const int pc = D == 3 ? obit(bi.flags, t2) * G::H + Cc : 0;
-    bc[(size_t)pi.bcoff[side] * G::F + pa + N * pc] = acc * (D == 3 ? 0.25 : 0.5);
+    const int pa = obit(bi->flags, t1) * G::H + A;
+    const int pc = D == 3 ? obit(bi->flags, t2) * G::H + Cc : 0;
+    bc[(size_t)pi->bcoff[side] * G::F + pa + N * pc] = acc * (D == 3 ? 0.25 : 0.5);
 }
 
 // ---------------------------------------------------------------------------
@@ -543,7 +745,9 @@ struct CoarseGeo {
     static constexpr int lg(int n) { return n <= 1 ? 0 : 1 + lg(n / 2); }
     static constexpr int NL = lg(N);  // grids of N, N/2, ..., 2 cells
     static constexpr int n(int li) { return N >> li; }
-    static constexpr int psz(int li) { return D == 3 ? (n(li) + 2) * (n(li) + 2) * (n(li) + 2) : (n(li) + 2) * (n(li) + 2); }
+    static constexpr int psz(int li) {
+        return D == 3 ? (n(li) + 2) * (n(li) + 2) * (n(li) + 2) : (n(li) + 2) * (n(li) + 2);
+    }
     static constexpr int poff(int li) { return li == 0 ? 0 : poff(li - 1) + psz(li - 1); }
     static constexpr int PTOT = poff(NL);
     static constexpr int fsz(int li) { return D == 3 ? n(li) * n(li) : n(li); }
@@ -563,20 +767,26 @@ struct CoarseState {
     }
     __device__ static double hlev(int li) { return (double)(1 << li) / (double)N; }
 
+    template <int S>
+    __device__ void fill_side(double *f, int li, int m) const {
+        using SD = SideOf<S>;
+        const int n = CG::n(li);
+        int x[3];
+        x[SD::t1] = m % n;
+        x[SD::t2] = D == 3 ? m / n : 0;
+        x[SD::d] = SD::hi ? n - 1 : 0;
+        const double u1 = f[pidx(li, x[0], x[1], x[2])];
+        const double bv = bc[CG::boff(li) + S * CG::fsz(li) + m];
+        x[SD::d] = SD::hi ? n : -1;
+        f[pidx(li, x[0], x[1], x[2])] = 2.0 * bv - u1;
+    }
     __device__ void fill(double *f, int li) const {
-        const int n = CG::n(li), F = CG::fsz(li);
+        const int F = CG::fsz(li);
         for (int g = threadIdx.x; g < 2 * D * F; g += blockDim.x) {
             const int side = g / F, m = g % F;
-            const int d = side >> 1, hi = side & 1;
-            const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-            int x[3];
-            x[t1] = m % n;
-            x[t2] = D == 3 ? m / n : 0;
-            x[d] = hi ? n - 1 : 0;
-            const double u1 = f[pidx(li, x[0], x[1], x[2])];
-            const double bv = bc[CG::boff(li) + side * F + m];
-            x[d] = hi ? n : -1;
-            f[pidx(li, x[0], x[1], x[2])] = 2.0 * bv - u1;
+#define AFMG_CF(S) fill_side<S>(f, li, m)
+            AFMG_SIDE_SWITCH(side, AFMG_CF)
+#undef AFMG_CF
         }
         __syncthreads();
     }
@@ -594,7 +804,9 @@ struct CoarseState {
         j = (c / n) % n;
         k = D == 3 ? c / (n * n) : 0;
     }
-    __device__ int ncell(int li) const { return D == 3 ? CG::n(li) * CG::n(li) * CG::n(li) : CG::n(li) * CG::n(li); }
+    __device__ int ncell(int li) const {
+        return D == 3 ? CG::n(li) * CG::n(li) * CG::n(li) : CG::n(li) * CG::n(li);
+    }
 
     __device__ void half(int li, int colour) const {
         fill(u, li);
@@ -704,12 +916,11 @@ __global__ __launch_bounds__(256) void k_coarse(CoarseArgs<T> a) {
     using G = Geo<D, N>;
     __shared__ double f_u[CG::PTOT], f_rho[CG::PTOT], f_uold[CG::PTOT], f_res[CG::PTOT], f_bc[CG::BTOT];
     CoarseState<D, N> st{f_u, f_rho, f_uold, f_res, f_bc, a.n_down, a.n_up, a.n_base};
-    const BoxInfo ri = a.info[0];  // the root is box 0
-    const bool root_leaf = ri.flags & FLAG_LEAF;
+    const BoxInfo *ri = a.info;  // the root is box 0
     // Dirichlet values: root rows, then means down to the 2^D grid
     for (int g = threadIdx.x; g < 2 * D * G::F; g += blockDim.x) {
         const int side = g / G::F, m = g % G::F;
-        f_bc[side * G::F + m] = a.homog ? 0.0 : a.bc[(size_t)ri.bcoff[side] * G::F + m];
+        f_bc[side * G::F + m] = a.homog ? 0.0 : a.bc[(size_t)ri->bcoff[side] * G::F + m];
     }
     __syncthreads();
     for (int li = 1; li < CG::NL; li++) {
@@ -732,15 +943,14 @@ __global__ __launch_bounds__(256) void k_coarse(CoarseArgs<T> a) {
         f_res[p] = 0.0;
     }
     __syncthreads();
-    const T *rho_root = root_leaf ? a.rho_user : a.rho_w;
-    // stage level 1 (the root box) from global memory
-    for (int c = threadIdx.x; c < G::C; c += blockDim.x) {
+    // stage level 1 (the root box) from global memory (colour-split)
+    for (int e = threadIdx.x; e < G::C; e += blockDim.x) {
         int i, j, k;
-        decode<D, N>(c, i, j, k);
+        cell_of<D, N>(e, i, j, k);
         const int p = st.pidx(0, i, j, k);
-        if (a.mode != COARSE_FMG) f_u[p] = (double)a.u[c];
-        if (a.mode == COARSE_V_FROM_2) f_res[p] = (double)a.rho_w[c];
-        else f_rho[p] = (double)rho_root[c];
+        if (a.mode != COARSE_FMG) f_u[p] = (double)a.u[e];
+        if (a.mode == COARSE_V_FROM_2) f_res[p] = (double)a.rho[e];
+        else f_rho[p] = (double)a.rho[e];
     }
     __syncthreads();
     if (a.mode == COARSE_V_FROM_2) {
@@ -766,12 +976,12 @@ __global__ __launch_bounds__(256) void k_coarse(CoarseArgs<T> a) {
             st.vcycle(li);
         }
     }
-    for (int c = threadIdx.x; c < G::C; c += blockDim.x) {
+    for (int e = threadIdx.x; e < G::C; e += blockDim.x) {
         int i, j, k;
-        decode<D, N>(c, i, j, k);
+        cell_of<D, N>(e, i, j, k);
         const int p = st.pidx(0, i, j, k);
-        a.u[c] = (T)f_u[p];
-        if (a.uold && a.mode != COARSE_V_TOP1) a.uold[c] = (T)f_uold[p];
+        a.u[e] = (T)f_u[p];
+        if (a.uold && a.mode != COARSE_V_TOP1) a.uold[e] = (T)f_uold[p];
     }
 }
 
@@ -784,8 +994,8 @@ static inline int wg_count(int64_t nb) {
     return (int)((nb + G::BPW - 1) / G::BPW);
 }
 
-#define AFMG_LAUNCH(kernel, grid, stream, ...)                                     \
-    do {                                                                           \
+#define AFMG_LAUNCH(kernel, grid, stream, ...)                                                      \
+    do {                                                                                            \
         if ((grid) > 0) hipLaunchKernelGGL(kernel, dim3(grid), dim3(256), 0, stream, __VA_ARGS__); \
     } while (0)
 
@@ -811,12 +1021,25 @@ template <int D, int N>
 int final_wgs(int64_t nb) { return wg_count<D, N>(nb); }
 
 void launch_reduce(const double *partial, int64_t n, double *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, partial, n, out);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, partial, n, out);
 }
 
 template <int D, int N, typename T>
 void launch_coarse(const CoarseArgs<T> &a, hipStream_t st) {
     hipLaunchKernelGGL((k_coarse<D, N, T>), dim3(1), dim3(256), 0, st, a);
+}
+
+template <int D, int N, typename T>
+void launch_permute(const BoxInfo *info, T *f, int64_t b0, int64_t nb, int to_split, int leaves_only,
+                    hipStream_t st) {
+    const int g = wg_count<D, N>(nb);
+    AFMG_LAUNCH((k_permute<D, N, T>), g, st, info, f, b0, (int)nb, to_split, leaves_only);
+}
+
+template <int D, int N, typename T>
+void launch_load_rho(const BoxInfo *info, const T *src, T *dst, int64_t nb, hipStream_t st) {
+    const int g = wg_count<D, N>(nb);
+    AFMG_LAUNCH((k_load_rho<D, N, T>), g, st, info, src, dst, (int)nb);
 }
 
 template <int D, int N>
@@ -842,11 +1065,12 @@ void launch_fill(T *dst, int64_t n, T v, hipStream_t st) {
     hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)g), dim3(256), 0, st, dst, n, v);
 }
 
-#define AFMG_INST(D, N, T)                                                                 \
-    template void launch_level<D, N, T>(Op, const LevelArgs<T> &, int, hipStream_t);        \
-    template void launch_final<D, N, T>(const LevelArgs<T> &, double *, int64_t, double,    \
-                                        hipStream_t);                                      \
-    template void launch_coarse<D, N, T>(const CoarseArgs<T> &, hipStream_t);
+#define AFMG_INST(D, N, T)                                                                              \
+    template void launch_level<D, N, T>(Op, const LevelArgs<T> &, int, hipStream_t);                     \
+    template void launch_final<D, N, T>(const LevelArgs<T> &, double *, int64_t, double, hipStream_t);  \
+    template void launch_coarse<D, N, T>(const CoarseArgs<T> &, hipStream_t);                           \
+    template void launch_permute<D, N, T>(const BoxInfo *, T *, int64_t, int64_t, int, int, hipStream_t); \
+    template void launch_load_rho<D, N, T>(const BoxInfo *, const T *, T *, int64_t, hipStream_t);
 
 AFMG_INST(2, 8, double)
 AFMG_INST(3, 8, double)

@@ -53,7 +53,7 @@ int64_t cells_per_face(int dim) { return dim == 3 ? BOX_N * BOX_N : BOX_N; }
 double level_h(int l) { return 1.0 / ((double)BOX_N * std::ldexp(1.0, l - 1)); }
 
 struct WsLayout {
-    size_t rho_w, uold, bc, partial, norm, total;
+    size_t rho, uold, bc, partial, norm, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -64,7 +64,7 @@ WsLayout ws_layout(const afmg_tree *t) {
     const size_t nlt = (size_t)h.n_below_lmax();
     WsLayout L{};
     size_t off = 0;
-    L.rho_w = off; off = align256(off + nlt * C * sizeof(double));
+    L.rho = off; off = align256(off + (size_t)h.n_boxes * C * sizeof(double));
     L.uold = off; off = align256(off + nlt * C * sizeof(double));
     L.bc = off; off = align256(off + (size_t)std::max<int64_t>(1, h.n_bfaces_all) * F * sizeof(double));
     L.partial = off; off = align256(off + (size_t)std::max<int64_t>(1, t->n_parts) * 2 * sizeof(double));
@@ -193,7 +193,7 @@ struct Solver {
         }
     }
     void coarse(int mode) {
-        CoarseArgs<double> c{base.info, base.u, base.rho_user, base.rho_w, base.uold, base.bc, mode, 0,
+        CoarseArgs<double> c{base.info, base.u, base.rho, base.uold, base.bc, mode, 0,
                              o.n_down, o.n_up, o.n_base};
         if (h.lmax == 1) c.uold = nullptr;
         launch_coarse<D, BOX_N, double>(c, st);
@@ -253,7 +253,7 @@ int solve_fp64(afmg_tree *t, hipStream_t st, const double *rho, const double *bc
     const HostTree &h = t->h;
     const WsLayout L = ws_layout(t);
     Solver<D> s(t, st, o);
-    double *rho_w = (double *)(ws + L.rho_w);
+    double *rho_i = (double *)(ws + L.rho);
     double *uold = (double *)(ws + L.uold);
     double *bc_w = (double *)(ws + L.bc);
     s.stats = &S;
@@ -264,7 +264,7 @@ int solve_fp64(afmg_tree *t, hipStream_t st, const double *rho, const double *bc
     }
     s.partial = (double *)(ws + L.partial);
     s.norm = (double *)(ws + L.norm);
-    s.base = LevelArgs<double>{t->d_info, u, rho, rho_w, uold, bc_w, 0, 0, 0, 0.0, 0.0};
+    s.base = LevelArgs<double>{t->d_info, u, rho_i, uold, bc_w, 0, 0, 0, 0.0, 0.0};
     const int64_t F = cells_per_face(D), C = cells_per_box(D);
 
     hipEvent_t ev0, ev1;
@@ -283,7 +283,11 @@ int solve_fp64(afmg_tree *t, hipStream_t st, const double *rho, const double *bc
     }
     for (int l = h.lmax; l >= 2; l--)
         launch_bc_derive<D, BOX_N>(t->d_info, h.lvl_off[(size_t)l], h.level_count(l), bc_w, st);
+    // working copies in the colour-split box layout: rho of the leaves, and
+    // u in place (a zero guess needs no conversion)
+    launch_load_rho<D, BOX_N, double>(t->d_info, rho, rho_i, h.n_boxes, st);
     if (!o.use_guess || o.cycle == AFMG_CYCLE_FMG_V) launch_fill<double>(u, h.n_boxes * C, 0.0, st);
+    else launch_permute<D, BOX_N, double>(t->d_info, u, 0, h.n_boxes, 1, 0, st);
 
     int rc = s.finalize(S.r0_max, S.r0_l2);
     if (rc != AFMG_OK) return rc;
@@ -322,6 +326,7 @@ int solve_fp64(afmg_tree *t, hipStream_t st, const double *rho, const double *bc
         }
         if (status == AFMG_OK && !fixed && !conv) status = AFMG_NOT_CONVERGED;
     }
+    launch_permute<D, BOX_N, double>(t->d_info, u, 0, h.n_boxes, 0, 0, st);
     (void)hipEventRecord(ev1, st);
     (void)hipEventSynchronize(ev1);
     float ms = 0.f;

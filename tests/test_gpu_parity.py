@@ -63,7 +63,11 @@ def check_pair(w, **kw):
             ratio = so["r_max"] / (tol * so["r0_max"])
             assert abs(sg["cycles"] - so["cycles"]) == 1 and 0.99 < ratio < 1.01, (sg, so)
     np.testing.assert_allclose(sg["r0_max"], so["r0_max"], rtol=1e-12)
-    np.testing.assert_allclose(sg["r_max"], so["r_max"], rtol=1e-6, atol=1e-14 * so["r0_max"])
+    # final residuals sit at the rounding floor (about eps * 2D/h^2 * |u|), so
+    # compare them on the scale of the stop test: they must agree to 1% of
+    # tol * r0 for the two stop decisions to agree
+    tol = kw.get("tol", 1e-10)
+    np.testing.assert_allclose(sg["r_max"], so["r_max"], rtol=1e-6, atol=1e-2 * tol * so["r0_max"])
     return ug, sg, uo, so
 
 
