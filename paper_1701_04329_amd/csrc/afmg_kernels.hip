@@ -9,7 +9,8 @@
 //
 // No ghost layer is stored: side ghosts (paper §2.4, §3.3) are computed on
 // the fly from the neighbouring boxes.  Workgroups are 256 threads (four
-// wave64); in 3D one box per workgroup, in 2D eight boxes.  Workgroup ids are
+// wave64) and one thread owns one x-row of a box, so a workgroup holds four
+// boxes in 3D (one wave per box) and 32 in 2D.  Workgroup ids are
 // remapped so that each of the eight XCDs processes a contiguous run of boxes:
 // Morton-ordered siblings and neighbours then share one L2.
 #include <hip/hip_runtime.h>
@@ -27,10 +28,8 @@ struct Geo {
     static constexpr int PC = D == 3 ? P * P * P : P * P;  // padded cells
     static constexpr int HALF = C / 2;
     static constexpr int HN = N / 2;
-    static constexpr int BPW = HALF >= 256 ? 1 : 256 / HALF;  // boxes per workgroup
-    static constexpr int TPB = 256 / BPW;                     // threads per box
-    static constexpr int NG = 2 * D * F;                      // side ghosts per box
-    static constexpr int NJ = (NG + TPB - 1) / TPB;           // ghosts per thread
+    static constexpr int TPB = F;          // threads per box: one per row (j, k) of x-cells
+    static constexpr int BPW = 256 / TPB;  // boxes per workgroup
     static constexpr int H = N / 2;                           // parent cells per axis under a box
     static constexpr int HC = D == 3 ? H * H * H : H * H;
     static constexpr int HF = D == 3 ? H * H : H;
@@ -70,6 +69,13 @@ __device__ __forceinline__ void cell_of(int e, int &i, int &j, int &k) {
     i = 2 * (r % G::HN) + ((c + D + j + k) & 1);
 }
 __device__ __forceinline__ int obit(int flags, int axis) { return (flags >> (1 + axis)) & 1; }
+
+// row r of a box: cells (0..N-1, j, k)
+template <int D, int N>
+__device__ __forceinline__ void row_of(int r, int &j, int &k) {
+    j = r % N;
+    k = D == 3 ? r / N : 0;
+}
 
 // Contiguous run of workgroup ids per XCD (workgroups are dispatched to the
 // eight XCDs round-robin).  Bijective on [0, G).
@@ -190,42 +196,48 @@ __device__ __forceinline__ int ghost_slot(int m) {
 // Staging of one box with its ghosts in two phases around a barrier:
 // begin() loads the interior into the padded LDS box and fetches the raw
 // ghost operands; after __syncthreads, end() writes the ghost slots; one more
-// __syncthreads and the box is ready.
+// __syncthreads and the box is ready.  Thread t of the box owns row t (both
+// colours) and face cell t of every side (a side has F == TPB cells).
 template <int D, int N, typename T>
 struct Stager {
     using G = Geo<D, N>;
-    T raw[G::NJ];
-    int v[G::NJ];
+    T raw[6];
+    int v[6];
 
     __device__ void begin(T *s, const BoxInfo *__restrict__ bi, const T *__restrict__ ub,
                           const T *__restrict__ u, const T *__restrict__ bc, int homog, int t, bool ghosts) {
-        for (int e = t; e < G::C; e += G::TPB) {
-            int i, j, k;
-            cell_of<D, N>(e, i, j, k);
-            s[padi<D, N>(i, j, k)] = ub[e];
-        }
-        if (!ghosts) return;
+        int j, k;
+        row_of<D, N>(t, j, k);
+        T rowv[2][G::HN];
 #pragma unroll
-        for (int q = 0; q < G::NJ; q++) {
-            const int g = t + q * G::TPB;
-            if (g < G::NG) {
-                const int side = g / G::F, m = g % G::F;
-#define AFMG_RAW(S) raw[q] = ghost_raw<D, N, S, T>(bi, m, u, bc, homog, v[q])
-                AFMG_SIDE_SWITCH(side, AFMG_RAW)
-#undef AFMG_RAW
+        for (int c = 0; c < 2; c++)
+#pragma unroll
+            for (int m = 0; m < G::HN; m++) rowv[c][m] = ub[c * G::HALF + t * G::HN + m];
+        if (ghosts) {
+            raw[0] = ghost_raw<D, N, 0, T>(bi, t, u, bc, homog, v[0]);
+            raw[1] = ghost_raw<D, N, 1, T>(bi, t, u, bc, homog, v[1]);
+            raw[2] = ghost_raw<D, N, 2, T>(bi, t, u, bc, homog, v[2]);
+            raw[3] = ghost_raw<D, N, 3, T>(bi, t, u, bc, homog, v[3]);
+            if (D == 3) {
+                raw[4] = ghost_raw<D, N, 4, T>(bi, t, u, bc, homog, v[4]);
+                raw[5] = ghost_raw<D, N, 5, T>(bi, t, u, bc, homog, v[5]);
             }
+        }
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+            const int p = (c + D + j + k) & 1;
+#pragma unroll
+            for (int m = 0; m < G::HN; m++) s[padi<D, N>(2 * m + p, j, k)] = rowv[c][m];
         }
     }
     __device__ void end(T *s, int t) {
-#pragma unroll
-        for (int q = 0; q < G::NJ; q++) {
-            const int g = t + q * G::TPB;
-            if (g < G::NG) {
-                const int side = g / G::F, m = g % G::F;
-#define AFMG_FIN(S) s[ghost_slot<D, N, S>(m)] = ghost_finish<D, N, S, T>(s, m, raw[q], v[q])
-                AFMG_SIDE_SWITCH(side, AFMG_FIN)
-#undef AFMG_FIN
-            }
+        s[ghost_slot<D, N, 0>(t)] = ghost_finish<D, N, 0, T>(s, t, raw[0], v[0]);
+        s[ghost_slot<D, N, 1>(t)] = ghost_finish<D, N, 1, T>(s, t, raw[1], v[1]);
+        s[ghost_slot<D, N, 2>(t)] = ghost_finish<D, N, 2, T>(s, t, raw[2], v[2]);
+        s[ghost_slot<D, N, 3>(t)] = ghost_finish<D, N, 3, T>(s, t, raw[3], v[3]);
+        if (D == 3) {
+            s[ghost_slot<D, N, 4>(t)] = ghost_finish<D, N, 4, T>(s, t, raw[4], v[4]);
+            s[ghost_slot<D, N, 5>(t)] = ghost_finish<D, N, 5, T>(s, t, raw[5], v[5]);
         }
     }
 };
@@ -243,86 +255,108 @@ __device__ __forceinline__ T nb_sum(const T *s, int i, int j, int k) {
 // ---------------------------------------------------------------------------
 // Gauss-Seidel red-black half sweep (paper §3.1)
 // ---------------------------------------------------------------------------
-// Thread t of a box updates cell `colour*HALF + t`.  Only the other colour is
-// staged in LDS; each thread fetches the ghosts of its own cell (at most one
-// per axis) and, next to Dirichlet or refinement sides, its own old value.
+// Thread t of a box updates the N/2 cells of `colour` in row t.  Only the
+// other colour is staged in LDS; the thread fetches the ghosts of its own cells
+// (one x ghost at the row end, a y / z ghost per cell on the box faces) and,
+// next to Dirichlet or refinement sides, the old values of its cells, which
+// those ghost formulas use.
+
+// ghost of side S next to own cell (i, j, k), other colour in s
+template <int D, int N, int S, typename T>
+__device__ __forceinline__ T gs_finish(const T *s, T raw, int v, T own, int i, int j, int k) {
+    using SD = SideOf<S>;
+    if (v >= 0) return raw;
+    if (v == -1) return T(2) * raw - own;
+    int y[3] = {i, j, k};
+    y[SD::d] += SD::hi ? -1 : 1;
+    int p1[3] = {i, j, k};
+    p1[SD::t1] ^= 1;
+    const T u2 = s[in_colour<D, N>(y[0], y[1], y[2])];
+    const T u1p = s[in_colour<D, N>(p1[0], p1[1], p1[2])];
+    if (D == 2) return T(0.5) * raw + own - T(0.25) * (u1p + u2);
+    int p2[3] = {i, j, k};
+    p2[SD::t2] ^= 1;
+    const T u1pp = s[in_colour<D, N>(p2[0], p2[1], p2[2])];
+    return T(0.5) * raw + T(1.25) * own - T(0.25) * ((u2 + u1p) + u1pp);
+}
+
 template <int D, int N, typename T>
 __global__ __launch_bounds__(256) void k_gsrb(LevelArgs<T> a, int colour) {
     using G = Geo<D, N>;
+    constexpr int HN = G::HN;
     __shared__ T so[G::BPW * G::HALF];
     const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb);
     T *s = so + sl.slot * G::HALF;
-    const int64_t b = sl.b;
-    const BoxInfo *bi = a.info + b;
-    T *ub = a.u + (size_t)b * G::C;
-    const int e = colour * G::HALF + sl.t;
-    int c[3];
-    cell_of<D, N>(e, c[0], c[1], c[2]);
-    T rho_c = T(0), own = T(0);
-    T graw[3] = {T(0), T(0), T(0)};
-    int gv[3] = {0, 0, 0};
-    if (sl.valid) {
-        s[sl.t] = ub[(1 - colour) * G::HALF + sl.t];
-        rho_c = a.rho[(size_t)b * G::C + e];
-        bool need_own = false;
+    const BoxInfo *bi = a.info + sl.b;
+    T *ub = a.u + (size_t)sl.b * G::C;
+    const int r = sl.t;
+    int j, k;
+    row_of<D, N>(r, j, k);
+    const int p = (colour + D + j + k) & 1;  // x parity of the updated cells in this row
+    const int own0 = colour * G::HALF + r * HN;
+    T rr[HN], ow[HN], gy[HN], gz[HN];
+    T gx = T(0);
+    int vx = 0, vy = 0, vz = 0;
 #pragma unroll
-        for (int d = 0; d < D; d++) {
-            if (c[d] == 0 || c[d] == N - 1) {
-                const int m = D == 3 ? c[d == 0 ? 1 : 0] + N * c[d == 2 ? 1 : 2] : c[d == 0 ? 1 : 0];
-                const bool hi = c[d] == N - 1;
-#define AFMG_GR(S) graw[d] = ghost_raw<D, N, S, T>(bi, m, a.u, a.bc, a.homog, gv[d])
-                if (d == 0) { if (hi) AFMG_GR(1); else AFMG_GR(0); }
-                else if (d == 1) { if (hi) AFMG_GR(3); else AFMG_GR(2); }
-                else { if (hi) AFMG_GR(5); else AFMG_GR(4); }
-#undef AFMG_GR
-                need_own |= gv[d] < 0;
+    for (int m = 0; m < HN; m++) {
+        ow[m] = T(0);
+        gy[m] = T(0);
+        gz[m] = T(0);
+    }
+    if (sl.valid) {
+        T ot[HN];
+        const int oth0 = (1 - colour) * G::HALF + r * HN;
+#pragma unroll
+        for (int m = 0; m < HN; m++) ot[m] = ub[oth0 + m];
+        const T *rb = a.rho + (size_t)sl.b * G::C + own0;
+#pragma unroll
+        for (int m = 0; m < HN; m++) rr[m] = rb[m];
+        // x ghost of the row end cell (side 0 when the row starts with this colour)
+        if (p == 0) gx = ghost_raw<D, N, 0, T>(bi, r, a.u, a.bc, a.homog, vx);
+        else gx = ghost_raw<D, N, 1, T>(bi, r, a.u, a.bc, a.homog, vx);
+        bool need_own = vx < 0;
+        if (j == 0 || j == N - 1) {
+#pragma unroll
+            for (int m = 0; m < HN; m++) {
+                const int fm = (2 * m + p) + (D == 3 ? N * k : 0);
+                if (j == 0) gy[m] = ghost_raw<D, N, 2, T>(bi, fm, a.u, a.bc, a.homog, vy);
+                else gy[m] = ghost_raw<D, N, 3, T>(bi, fm, a.u, a.bc, a.homog, vy);
             }
+            need_own |= vy < 0;
         }
-        if (need_own) own = ub[e];
+        if (D == 3 && (k == 0 || k == N - 1)) {
+#pragma unroll
+            for (int m = 0; m < HN; m++) {
+                const int fm = (2 * m + p) + N * j;
+                if (k == 0) gz[m] = ghost_raw<D, N, 4, T>(bi, fm, a.u, a.bc, a.homog, vz);
+                else gz[m] = ghost_raw<D, N, 5, T>(bi, fm, a.u, a.bc, a.homog, vz);
+            }
+            need_own |= vz < 0;
+        }
+        if (need_own) {
+#pragma unroll
+            for (int m = 0; m < HN; m++) ow[m] = ub[own0 + m];
+        }
+#pragma unroll
+        for (int m = 0; m < HN; m++) s[r * HN + m] = ot[m];
     }
     __syncthreads();
     if (!sl.valid) return;
-    auto oth = [&](int i, int j, int k) { return s[in_colour<D, N>(i, j, k)]; };
-    T lo[3], hi[3];
 #pragma unroll
-    for (int d = 0; d < D; d++) {
-        const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-        // neighbours inside the box
-        int m1[3] = {c[0], c[1], c[2]}, p1[3] = {c[0], c[1], c[2]};
-        m1[d] -= 1;
-        p1[d] += 1;
-        lo[d] = c[d] > 0 ? oth(m1[0], m1[1], m1[2]) : T(0);
-        hi[d] = c[d] < N - 1 ? oth(p1[0], p1[1], p1[2]) : T(0);
-        if (c[d] == 0 || c[d] == N - 1) {
-            const bool h = c[d] == N - 1;
-            T g;
-            if (gv[d] >= 0) {
-                g = graw[d];
-            } else if (gv[d] == -1) {
-                g = T(2) * graw[d] - own;
-            } else {
-                int y[3] = {c[0], c[1], c[2]};
-                y[d] += h ? -1 : 1;
-                int q1[3] = {c[0], c[1], c[2]};
-                q1[t1] ^= 1;
-                const T u2 = oth(y[0], y[1], y[2]);
-                const T u1p = oth(q1[0], q1[1], q1[2]);
-                if (D == 2) {
-                    g = T(0.5) * graw[d] + own - T(0.25) * (u1p + u2);
-                } else {
-                    int q2[3] = {c[0], c[1], c[2]};
-                    q2[t2] ^= 1;
-                    const T u1pp = oth(q2[0], q2[1], q2[2]);
-                    g = T(0.5) * graw[d] + T(1.25) * own - T(0.25) * ((u2 + u1p) + u1pp);
-                }
-            }
-            if (h) hi[d] = g;
-            else lo[d] = g;
+    for (int m = 0; m < HN; m++) {
+        const int i = 2 * m + p;
+        const T xm = i > 0 ? s[in_colour<D, N>(i - 1, j, k)] : gs_finish<D, N, 0, T>(s, gx, vx, ow[m], i, j, k);
+        const T xp = i < N - 1 ? s[in_colour<D, N>(i + 1, j, k)] : gs_finish<D, N, 1, T>(s, gx, vx, ow[m], i, j, k);
+        const T ym = j > 0 ? s[in_colour<D, N>(i, j - 1, k)] : gs_finish<D, N, 2, T>(s, gy[m], vy, ow[m], i, j, k);
+        const T yp = j < N - 1 ? s[in_colour<D, N>(i, j + 1, k)] : gs_finish<D, N, 3, T>(s, gy[m], vy, ow[m], i, j, k);
+        T sum = (xm + xp) + (ym + yp);
+        if (D == 3) {
+            const T zm = k > 0 ? s[in_colour<D, N>(i, j, k - 1)] : gs_finish<D, N, 4, T>(s, gz[m], vz, ow[m], i, j, k);
+            const T zp = k < N - 1 ? s[in_colour<D, N>(i, j, k + 1)] : gs_finish<D, N, 5, T>(s, gz[m], vz, ow[m], i, j, k);
+            sum = sum + (zm + zp);
         }
+        ub[own0 + m] = (sum - a.h2 * rr[m]) / T(2 * D);
     }
-    const T sum = D == 3 ? ((lo[0] + hi[0]) + (lo[1] + hi[1])) + (lo[2] + hi[2])
-                         : (lo[0] + hi[0]) + (lo[1] + hi[1]);
-    ub[e] = (sum - a.h2 * rho_c) / T(2 * D);
 }
 
 // ---------------------------------------------------------------------------
@@ -362,10 +396,8 @@ template <int D, int N, typename T>
 __global__ __launch_bounds__(256) void k_resid_restrict(LevelArgs<T> a) {
     using G = Geo<D, N>;
     __shared__ T sm[G::BPW * G::PC];
-    __shared__ T rs[G::BPW * G::C];
     const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb);
     T *s = sm + sl.slot * G::PC;
-    T *r = rs + sl.slot * G::C;
     const BoxInfo *bi = a.info + sl.b;
     const size_t bo = (size_t)sl.b * G::C;
     Stager<D, N, T> st;
@@ -373,18 +405,28 @@ __global__ __launch_bounds__(256) void k_resid_restrict(LevelArgs<T> a) {
     __syncthreads();
     if (sl.valid) st.end(s, sl.t);
     __syncthreads();
-    if (sl.valid) {
-        for (int e = sl.t; e < G::C; e += G::TPB) {
-            int i, j, k;
-            cell_of<D, N>(e, i, j, k);
-            r[D == 3 ? i + N * (j + N * k) : i + N * j] =
-                a.rho[bo + e] - (nb_sum<D, N, T>(s, i, j, k) - T(2 * D) * s[padi<D, N>(i, j, k)]) * a.ih2;
-        }
-    }
-    __syncthreads();
     if (!sl.valid) return;
-    restrict_octant<D, N, T, true>(s, a.u, bi, sl.t);
-    restrict_octant<D, N, T, false>(r, a.rho, bi, sl.t);
+    // each thread: one 2^D block = one parent cell; residuals in registers
+    const T w = D == 3 ? T(0.125) : T(0.25);
+    const int flags = bi->flags;
+    const int64_t p = bi->parent;
+    for (int pc = sl.t; pc < G::HC; pc += G::TPB) {
+        const int I = pc % G::H, J = (pc / G::H) % G::H, K = D == 3 ? pc / (G::H * G::H) : 0;
+        T su = T(0), sr = T(0);
+        for (int dk = 0; dk < (D == 3 ? 2 : 1); dk++)
+            for (int dj = 0; dj < 2; dj++)
+                for (int di = 0; di < 2; di++) {
+                    const int i = 2 * I + di, j = 2 * J + dj, k = D == 3 ? 2 * K + dk : 0;
+                    const T uc = s[padi<D, N>(i, j, k)];
+                    su += uc;
+                    sr += a.rho[bo + cpos<D, N>(i, j, k)] - (nb_sum<D, N, T>(s, i, j, k) - T(2 * D) * uc) * a.ih2;
+                }
+        const int X = obit(flags, 0) * G::H + I, Y = obit(flags, 1) * G::H + J,
+                  Z = D == 3 ? obit(flags, 2) * G::H + K : 0;
+        const size_t o = (size_t)p * G::C + cpos<D, N>(X, Y, Z);
+        a.u[o] = w * su;
+        a.rho[o] = w * sr;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -434,60 +476,84 @@ __device__ __forceinline__ int qpad(int I, int J, int K) {
     return D == 3 ? (I + 1) + Q * ((J + 1) + Q * (K + 1)) : (I + 1) + Q * (J + 1);
 }
 
-template <int D, int N, int S, typename T>
-__device__ __forceinline__ T delta_ghost(const BoxInfo *__restrict__ pi, int64_t p, const int x[3],
-                                         const T *__restrict__ u, const T *__restrict__ uold) {
+// Halo cell m of side S of the octant (o = octant origin in parent cells).
+// Phase 1 stores what needs no LDS data (delta inside the parent or in a
+// same-level neighbour) and returns, for the other halo cells, the side type
+// v and the global operand (delta of the coarser cell uH for a refinement
+// side).  Phase 2 (after a barrier) finishes those from the staged octant.
+template <int D, int N, int S>
+__device__ __forceinline__ void halo_cell(int m, const int o[3], int L[3], int X[3]) {
     using SD = SideOf<S>;
     using G = Geo<D, N>;
-    auto del = [&](int64_t box, int i, int j, int k) {
-        const size_t o = (size_t)box * G::C + cpos<D, N>(i, j, k);
-        return u[o] - uold[o];
-    };
-    const int v = pi->nbr[S];
-    if (v >= 0) {
-        int y[3] = {x[0], x[1], x[2]};
-        y[SD::d] = SD::hi ? 0 : N - 1;
-        return del(v, y[0], y[1], y[2]);
-    }
-    const T d1 = del(p, x[0], x[1], x[2]);
-    if (v == -1) return -d1;
-    const int flags = pi->flags;
-    int q[3];
-    q[SD::d] = SD::hi ? 0 : N - 1;
-    q[SD::t1] = obit(flags, SD::t1) * G::H + (x[SD::t1] >> 1);
-    q[SD::t2] = D == 3 ? obit(flags, SD::t2) * G::H + (x[SD::t2] >> 1) : 0;
-    const T dH = del(-v - 2, q[0], q[1], q[2]);
-    int y[3] = {x[0], x[1], x[2]};
-    y[SD::d] = SD::hi ? N - 2 : 1;
-    int p1[3] = {x[0], x[1], x[2]};
-    p1[SD::t1] ^= 1;
-    const T d2 = del(p, y[0], y[1], y[2]);
-    const T d1p = del(p, p1[0], p1[1], p1[2]);
-    if (D == 2) return T(0.5) * dH + d1 - T(0.25) * (d1p + d2);
-    int p2[3] = {x[0], x[1], x[2]};
-    p2[SD::t2] ^= 1;
-    const T d1pp = del(p, p2[0], p2[1], p2[2]);
-    return T(0.5) * dH + T(1.25) * d1 - T(0.25) * ((d2 + d1p) + d1pp);
-}
-
-// halo cell m of side S of the octant (o = octant origin in parent cells)
-template <int D, int N, int S, typename T>
-__device__ __forceinline__ void prolong_halo(T *q, int m, const int o[3], const BoxInfo *__restrict__ pi,
-                                             int64_t p, const T *__restrict__ u, const T *__restrict__ uold) {
-    using SD = SideOf<S>;
-    using G = Geo<D, N>;
-    int L[3];
     L[SD::t1] = m % G::H;
     L[SD::t2] = D == 3 ? m / G::H : 0;
     L[SD::d] = SD::hi ? G::H : -1;
-    int X[3] = {o[0] + L[0], o[1] + L[1], D == 3 ? o[2] + L[2] : 0};
-    T val;
+    X[0] = o[0] + L[0];
+    X[1] = o[1] + L[1];
+    X[2] = D == 3 ? o[2] + L[2] : 0;
+}
+
+template <int D, int N, int S, typename T>
+__device__ __forceinline__ T halo_phase1(T *q, int m, const int o[3], const BoxInfo *__restrict__ pi, int64_t p,
+                                         const T *__restrict__ u, const T *__restrict__ uold, int &v) {
+    using SD = SideOf<S>;
+    using G = Geo<D, N>;
+    int L[3], X[3];
+    halo_cell<D, N, S>(m, o, L, X);
+    int64_t box = p;
     if (X[SD::d] >= 0 && X[SD::d] < N) {
-        const size_t oo = (size_t)p * G::C + cpos<D, N>(X[0], X[1], X[2]);
-        val = u[oo] - uold[oo];
+        v = 0;  // inside the parent
     } else {
-        X[SD::d] = SD::hi ? N - 1 : 0;
-        val = delta_ghost<D, N, S, T>(pi, p, X, u, uold);
+        v = pi->nbr[S];
+        if (v >= 0) {
+            box = v;
+            X[SD::d] = SD::hi ? 0 : N - 1;
+        } else if (v == -1) {
+            return T(0);
+        } else {
+            const int flags = pi->flags;
+            box = -v - 2;
+            const int x1 = X[SD::t1], x2 = X[SD::t2];
+            X[SD::d] = SD::hi ? 0 : N - 1;
+            X[SD::t1] = obit(flags, SD::t1) * G::H + (x1 >> 1);
+            X[SD::t2] = D == 3 ? obit(flags, SD::t2) * G::H + (x2 >> 1) : 0;
+        }
+    }
+    const size_t oo = (size_t)box * G::C + cpos<D, N>(X[0], X[1], X[2]);
+    const T d = u[oo] - uold[oo];
+    if (v >= 0) q[qpad<D, N>(L[0], L[1], L[2])] = d;
+    return d;
+}
+
+// Dirichlet: ghost of delta = -delta(face cell) (the values b cancel);
+// refinement side: the default scheme applied to deltas.
+template <int D, int N, int S, typename T>
+__device__ __forceinline__ void halo_phase2(T *q, int m, const int o[3], T raw, int v) {
+    using SD = SideOf<S>;
+    if (v >= 0) return;
+    int L[3], X[3];
+    halo_cell<D, N, S>(m, o, L, X);
+    int f[3] = {L[0], L[1], L[2]};
+    f[SD::d] = SD::hi ? L[SD::d] - 1 : 0;  // face cell inside the octant
+    const T d1 = q[qpad<D, N>(f[0], f[1], f[2])];
+    T val;
+    if (v == -1) {
+        val = -d1;
+    } else {
+        int y[3] = {f[0], f[1], f[2]};
+        y[SD::d] += SD::hi ? -1 : 1;
+        int p1[3] = {f[0], f[1], f[2]};
+        p1[SD::t1] ^= 1;  // octant origins are even: partners stay in the octant
+        const T d2 = q[qpad<D, N>(y[0], y[1], y[2])];
+        const T d1p = q[qpad<D, N>(p1[0], p1[1], p1[2])];
+        if (D == 2) {
+            val = T(0.5) * raw + d1 - T(0.25) * (d1p + d2);
+        } else {
+            int p2[3] = {f[0], f[1], f[2]};
+            p2[SD::t2] ^= 1;
+            const T d1pp = q[qpad<D, N>(p2[0], p2[1], p2[2])];
+            val = T(0.5) * raw + T(1.25) * d1 - T(0.25) * ((d2 + d1p) + d1pp);
+        }
     }
     q[qpad<D, N>(L[0], L[1], L[2])] = val;
 }
@@ -495,41 +561,53 @@ __device__ __forceinline__ void prolong_halo(T *q, int m, const int o[3], const 
 template <int D, int N, typename T>
 __global__ __launch_bounds__(256) void k_prolong(LevelArgs<T> a) {
     using G = Geo<D, N>;
+    constexpr int NH = (2 * D * G::HF + G::TPB - 1) / G::TPB;  // halo cells per thread
     __shared__ T qs[G::BPW * G::QC];
     const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb);
     T *q = qs + sl.slot * G::QC;
     const BoxInfo *bi = a.info + sl.b;
     const size_t bo = (size_t)sl.b * G::C;
-    T ucell[(G::C + G::TPB - 1) / G::TPB];
+    const int flags = bi->flags;
+    const int o[3] = {obit(flags, 0) * G::H, obit(flags, 1) * G::H, D == 3 ? obit(flags, 2) * G::H : 0};
+    T raw[NH];
+    int hv[NH];
     if (sl.valid) {
-        // own cells first: their loads overlap with the parent's
-#pragma unroll
-        for (int r = 0; r < (G::C + G::TPB - 1) / G::TPB; r++) {
-            const int e = sl.t + r * G::TPB;
-            if (e < G::C) ucell[r] = a.u[bo + e];
-        }
-        const int flags = bi->flags;
         const int64_t p = bi->parent;
         const BoxInfo *pi = a.info + p;
-        const int o[3] = {obit(flags, 0) * G::H, obit(flags, 1) * G::H, D == 3 ? obit(flags, 2) * G::H : 0};
         for (int pc = sl.t; pc < G::HC; pc += G::TPB) {
             const int I = pc % G::H, J = (pc / G::H) % G::H, K = D == 3 ? pc / (G::H * G::H) : 0;
             const size_t oo = (size_t)p * G::C + cpos<D, N>(o[0] + I, o[1] + J, o[2] + K);
             q[qpad<D, N>(I, J, K)] = a.u[oo] - a.uold[oo];
         }
-        for (int hc = sl.t; hc < 2 * D * G::HF; hc += G::TPB) {
-            const int side = hc / G::HF, m = hc % G::HF;
-#define AFMG_HALO(S) prolong_halo<D, N, S, T>(q, m, o, pi, p, a.u, a.uold)
-            AFMG_SIDE_SWITCH(side, AFMG_HALO)
-#undef AFMG_HALO
+#pragma unroll
+        for (int h = 0; h < NH; h++) {
+            const int hc = sl.t + h * G::TPB;
+            hv[h] = 0;
+            raw[h] = T(0);
+            if (hc < 2 * D * G::HF) {
+                const int side = hc / G::HF, m = hc % G::HF;
+#define AFMG_H1(S) raw[h] = halo_phase1<D, N, S, T>(q, m, o, pi, p, a.u, a.uold, hv[h])
+                AFMG_SIDE_SWITCH(side, AFMG_H1)
+#undef AFMG_H1
+            }
+        }
+    }
+    __syncthreads();
+    if (sl.valid) {
+#pragma unroll
+        for (int h = 0; h < NH; h++) {
+            const int hc = sl.t + h * G::TPB;
+            if (hc < 2 * D * G::HF && hv[h] < 0) {
+                const int side = hc / G::HF, m = hc % G::HF;
+#define AFMG_H2(S) halo_phase2<D, N, S, T>(q, m, o, raw[h], hv[h])
+                AFMG_SIDE_SWITCH(side, AFMG_H2)
+#undef AFMG_H2
+            }
         }
     }
     __syncthreads();
     if (!sl.valid) return;
-#pragma unroll
-    for (int r = 0; r < (G::C + G::TPB - 1) / G::TPB; r++) {
-        const int e = sl.t + r * G::TPB;
-        if (e >= G::C) break;
+    for (int e = sl.t; e < G::C; e += G::TPB) {
         int i, j, k;
         cell_of<D, N>(e, i, j, k);
         const int I = i >> 1, J = j >> 1, K = k >> 1;
@@ -542,7 +620,7 @@ __global__ __launch_bounds__(256) void k_prolong(LevelArgs<T> a) {
             v = T(0.25) * (((q[qpad<D, N>(I, J, K)] + q[qpad<D, N>(I + sx, J, K)]) + q[qpad<D, N>(I, J + sy, K)]) +
                            q[qpad<D, N>(I, J, K + sz)]);
         }
-        a.u[bo + e] = ucell[r] + v;
+        a.u[bo + e] = a.u[bo + e] + v;
     }
 }
 
