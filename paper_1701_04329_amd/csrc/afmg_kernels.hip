@@ -85,6 +85,14 @@ __device__ __forceinline__ int xcd_remap(int w, int G) {
     return x < r ? x * (q + 1) + p : r * (q + 1) + (x - r) * q + p;
 }
 
+// Box record of box b.  With one box per wave (3D) the id is made
+// wave-uniform so that the record arrives through one scalar load.
+template <int D, int N>
+__device__ __forceinline__ BoxInfo load_box(const BoxInfo *__restrict__ info, int64_t b) {
+    if (Geo<D, N>::TPB == 64) return info[__builtin_amdgcn_readfirstlane((int)b)];
+    return info[b];
+}
+
 template <int D, int N>
 struct Slot {
     int64_t b;   // box id (clamped to a valid box)
@@ -98,7 +106,8 @@ __device__ __forceinline__ Slot<D, N> slot_of(int64_t b0, int nb) {
     const int w = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     r.slot = (int)threadIdx.x / G::TPB;
     r.t = (int)threadIdx.x % G::TPB;
-    const int bl = w * G::BPW + r.slot;
+    int bl = w * G::BPW + r.slot;
+    if (G::TPB == 64) bl = __builtin_amdgcn_readfirstlane(bl);  // one box per wave
     r.valid = bl < nb;
     r.b = b0 + (r.valid ? bl : 0);
     return r;
@@ -130,26 +139,30 @@ __device__ __forceinline__ void face_cell(int m, int x[3]) {
     x[SD::d] = SD::hi ? N - 1 : 0;
 }
 
-// raw operand of the ghost on side S next to face cell m of box bi
+// raw operand of the ghost on side S next to face cell m of box bi.  The
+// address is selected without branches (one load per ghost, so the loads of a
+// thread stay in flight together); a homogeneous Dirichlet side loads a
+// harmless in-range value and returns 0.
 template <int D, int N, int S, typename T>
-__device__ __forceinline__ T ghost_raw(const BoxInfo *__restrict__ bi, int m, const T *__restrict__ u,
+__device__ __forceinline__ T ghost_raw(const BoxInfo &bi, int m, const T *__restrict__ u,
                                        const T *__restrict__ bc, int homog, int &v) {
     using SD = SideOf<S>;
     using G = Geo<D, N>;
     int x[3];
     face_cell<D, N, S>(m, x);
-    v = bi->nbr[S];
-    if (v >= 0) {
-        x[SD::d] = SD::hi ? 0 : N - 1;
-        return u[(size_t)v * G::C + cpos<D, N>(x[0], x[1], x[2])];
-    }
-    if (v == -1) return homog ? T(0) : bc[(size_t)bi->bcoff[S] * G::F + m];
-    const int flags = bi->flags;
+    v = bi.nbr[S];
+    const bool cf = v <= -2, dir = v == -1;
+    const int flags = bi.flags;
     int q[3];
     q[SD::d] = SD::hi ? 0 : N - 1;
-    q[SD::t1] = obit(flags, SD::t1) * G::H + (x[SD::t1] >> 1);
-    q[SD::t2] = D == 3 ? obit(flags, SD::t2) * G::H + (x[SD::t2] >> 1) : 0;
-    return u[(size_t)(-v - 2) * G::C + cpos<D, N>(q[0], q[1], q[2])];
+    q[SD::t1] = cf ? obit(flags, SD::t1) * G::H + (x[SD::t1] >> 1) : x[SD::t1];
+    q[SD::t2] = D == 3 ? (cf ? obit(flags, SD::t2) * G::H + (x[SD::t2] >> 1) : x[SD::t2]) : 0;
+    const int64_t box = v >= 0 ? (int64_t)v : (cf ? (int64_t)(-v - 2) : (int64_t)0);
+    const size_t iu = (size_t)box * G::C + cpos<D, N>(q[0], q[1], q[2]);
+    const bool from_bc = dir && !homog;
+    const size_t ib = from_bc ? (size_t)bi.bcoff[S] * G::F + m : 0;
+    const T val = from_bc ? bc[ib] : u[iu];
+    return (dir && homog) ? T(0) : val;
 }
 
 // finish the ghost from its raw operand; s is the padded box in LDS
@@ -204,7 +217,7 @@ struct Stager {
     T raw[6];
     int v[6];
 
-    __device__ void begin(T *s, const BoxInfo *__restrict__ bi, const T *__restrict__ ub,
+    __device__ void begin(T *s, const BoxInfo &bi, const T *__restrict__ ub,
                           const T *__restrict__ u, const T *__restrict__ bc, int homog, int t, bool ghosts) {
         int j, k;
         row_of<D, N>(t, j, k);
@@ -262,6 +275,18 @@ __device__ __forceinline__ T nb_sum(const T *s, int i, int j, int k) {
 // those ghost formulas use.
 
 // ghost of side S next to own cell (i, j, k), other colour in s
+// LDS slot of an other-colour cell: x-pair index major, row minor, so that the
+// threads of a wave (consecutive rows) touch consecutive words.  In 2D a
+// box's block is padded by one word so that the eight boxes of a wave do not
+// share banks.
+template <int D, int N>
+__device__ __forceinline__ int oslot(int i, int j, int k) {
+    constexpr int TPB = Geo<D, N>::TPB;
+    return (i >> 1) * TPB + (D == 3 ? k * N + j : j);
+}
+template <int D, int N>
+constexpr int oblock() { return Geo<D, N>::HALF + (D == 3 ? 0 : 1); }
+
 template <int D, int N, int S, typename T>
 __device__ __forceinline__ T gs_finish(const T *s, T raw, int v, T own, int i, int j, int k) {
     using SD = SideOf<S>;
@@ -271,12 +296,12 @@ __device__ __forceinline__ T gs_finish(const T *s, T raw, int v, T own, int i, i
     y[SD::d] += SD::hi ? -1 : 1;
     int p1[3] = {i, j, k};
     p1[SD::t1] ^= 1;
-    const T u2 = s[in_colour<D, N>(y[0], y[1], y[2])];
-    const T u1p = s[in_colour<D, N>(p1[0], p1[1], p1[2])];
+    const T u2 = s[oslot<D, N>(y[0], y[1], y[2])];
+    const T u1p = s[oslot<D, N>(p1[0], p1[1], p1[2])];
     if (D == 2) return T(0.5) * raw + own - T(0.25) * (u1p + u2);
     int p2[3] = {i, j, k};
     p2[SD::t2] ^= 1;
-    const T u1pp = s[in_colour<D, N>(p2[0], p2[1], p2[2])];
+    const T u1pp = s[oslot<D, N>(p2[0], p2[1], p2[2])];
     return T(0.5) * raw + T(1.25) * own - T(0.25) * ((u2 + u1p) + u1pp);
 }
 
@@ -284,10 +309,10 @@ template <int D, int N, typename T>
 __global__ __launch_bounds__(256) void k_gsrb(LevelArgs<T> a, int colour) {
     using G = Geo<D, N>;
     constexpr int HN = G::HN;
-    __shared__ T so[G::BPW * G::HALF];
+    __shared__ T so[G::BPW * oblock<D, N>()];
     const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb);
-    T *s = so + sl.slot * G::HALF;
-    const BoxInfo *bi = a.info + sl.b;
+    T *s = so + sl.slot * oblock<D, N>();
+    const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     T *ub = a.u + (size_t)sl.b * G::C;
     const int r = sl.t;
     int j, k;
@@ -338,21 +363,21 @@ __global__ __launch_bounds__(256) void k_gsrb(LevelArgs<T> a, int colour) {
             for (int m = 0; m < HN; m++) ow[m] = ub[own0 + m];
         }
 #pragma unroll
-        for (int m = 0; m < HN; m++) s[r * HN + m] = ot[m];
+        for (int m = 0; m < HN; m++) s[m * G::TPB + r] = ot[m];
     }
     __syncthreads();
     if (!sl.valid) return;
 #pragma unroll
     for (int m = 0; m < HN; m++) {
         const int i = 2 * m + p;
-        const T xm = i > 0 ? s[in_colour<D, N>(i - 1, j, k)] : gs_finish<D, N, 0, T>(s, gx, vx, ow[m], i, j, k);
-        const T xp = i < N - 1 ? s[in_colour<D, N>(i + 1, j, k)] : gs_finish<D, N, 1, T>(s, gx, vx, ow[m], i, j, k);
-        const T ym = j > 0 ? s[in_colour<D, N>(i, j - 1, k)] : gs_finish<D, N, 2, T>(s, gy[m], vy, ow[m], i, j, k);
-        const T yp = j < N - 1 ? s[in_colour<D, N>(i, j + 1, k)] : gs_finish<D, N, 3, T>(s, gy[m], vy, ow[m], i, j, k);
+        const T xm = i > 0 ? s[oslot<D, N>(i - 1, j, k)] : gs_finish<D, N, 0, T>(s, gx, vx, ow[m], i, j, k);
+        const T xp = i < N - 1 ? s[oslot<D, N>(i + 1, j, k)] : gs_finish<D, N, 1, T>(s, gx, vx, ow[m], i, j, k);
+        const T ym = j > 0 ? s[oslot<D, N>(i, j - 1, k)] : gs_finish<D, N, 2, T>(s, gy[m], vy, ow[m], i, j, k);
+        const T yp = j < N - 1 ? s[oslot<D, N>(i, j + 1, k)] : gs_finish<D, N, 3, T>(s, gy[m], vy, ow[m], i, j, k);
         T sum = (xm + xp) + (ym + yp);
         if (D == 3) {
-            const T zm = k > 0 ? s[in_colour<D, N>(i, j, k - 1)] : gs_finish<D, N, 4, T>(s, gz[m], vz, ow[m], i, j, k);
-            const T zp = k < N - 1 ? s[in_colour<D, N>(i, j, k + 1)] : gs_finish<D, N, 5, T>(s, gz[m], vz, ow[m], i, j, k);
+            const T zm = k > 0 ? s[oslot<D, N>(i, j, k - 1)] : gs_finish<D, N, 4, T>(s, gz[m], vz, ow[m], i, j, k);
+            const T zp = k < N - 1 ? s[oslot<D, N>(i, j, k + 1)] : gs_finish<D, N, 5, T>(s, gz[m], vz, ow[m], i, j, k);
             sum = sum + (zm + zp);
         }
         ub[own0 + m] = (sum - a.h2 * rr[m]) / T(2 * D);
@@ -365,12 +390,12 @@ __global__ __launch_bounds__(256) void k_gsrb(LevelArgs<T> a, int colour) {
 // The octant of box bi's parent receives the mean of each 2^D block of src
 // (src in LDS, padded or plain natural order).
 template <int D, int N, typename T, bool PADDED>
-__device__ __forceinline__ void restrict_octant(const T *s, T *__restrict__ dst, const BoxInfo *__restrict__ bi,
+__device__ __forceinline__ void restrict_octant(const T *s, T *__restrict__ dst, const BoxInfo &bi,
                                                 int t) {
     using G = Geo<D, N>;
     const T w = D == 3 ? T(0.125) : T(0.25);
-    const int flags = bi->flags;
-    const int64_t p = bi->parent;
+    const int flags = bi.flags;
+    const int64_t p = bi.parent;
     for (int pc = t; pc < G::HC; pc += G::TPB) {
         const int I = pc % G::H, J = (pc / G::H) % G::H, K = D == 3 ? pc / (G::H * G::H) : 0;
         T acc = T(0);
@@ -398,7 +423,7 @@ __global__ __launch_bounds__(256) void k_resid_restrict(LevelArgs<T> a) {
     __shared__ T sm[G::BPW * G::PC];
     const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb);
     T *s = sm + sl.slot * G::PC;
-    const BoxInfo *bi = a.info + sl.b;
+    const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
     Stager<D, N, T> st;
     if (sl.valid) st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, true);
@@ -408,8 +433,8 @@ __global__ __launch_bounds__(256) void k_resid_restrict(LevelArgs<T> a) {
     if (!sl.valid) return;
     // each thread: one 2^D block = one parent cell; residuals in registers
     const T w = D == 3 ? T(0.125) : T(0.25);
-    const int flags = bi->flags;
-    const int64_t p = bi->parent;
+    const int flags = bi.flags;
+    const int64_t p = bi.parent;
     for (int pc = sl.t; pc < G::HC; pc += G::TPB) {
         const int I = pc % G::H, J = (pc / G::H) % G::H, K = D == 3 ? pc / (G::H * G::H) : 0;
         T su = T(0), sr = T(0);
@@ -440,9 +465,9 @@ __global__ __launch_bounds__(256) void k_coarse_rhs(LevelArgs<T> a) {
     __shared__ T sm[G::BPW * G::PC];
     const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb);
     T *s = sm + sl.slot * G::PC;
-    const BoxInfo *bi = a.info + sl.b;
+    const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
-    const bool parent = !(bi->flags & FLAG_LEAF);
+    const bool parent = !(bi.flags & FLAG_LEAF);
     Stager<D, N, T> st;
     if (sl.valid) {
         for (int e = sl.t; e < G::C; e += G::TPB) a.uold[bo + e] = a.u[bo + e];
@@ -494,31 +519,23 @@ __device__ __forceinline__ void halo_cell(int m, const int o[3], int L[3], int X
 }
 
 template <int D, int N, int S, typename T>
-__device__ __forceinline__ T halo_phase1(T *q, int m, const int o[3], const BoxInfo *__restrict__ pi, int64_t p,
+__device__ __forceinline__ T halo_phase1(T *q, int m, const int o[3], const BoxInfo &pi, int64_t p,
                                          const T *__restrict__ u, const T *__restrict__ uold, int &v) {
     using SD = SideOf<S>;
     using G = Geo<D, N>;
     int L[3], X[3];
     halo_cell<D, N, S>(m, o, L, X);
-    int64_t box = p;
-    if (X[SD::d] >= 0 && X[SD::d] < N) {
-        v = 0;  // inside the parent
-    } else {
-        v = pi->nbr[S];
-        if (v >= 0) {
-            box = v;
-            X[SD::d] = SD::hi ? 0 : N - 1;
-        } else if (v == -1) {
-            return T(0);
-        } else {
-            const int flags = pi->flags;
-            box = -v - 2;
-            const int x1 = X[SD::t1], x2 = X[SD::t2];
-            X[SD::d] = SD::hi ? 0 : N - 1;
-            X[SD::t1] = obit(flags, SD::t1) * G::H + (x1 >> 1);
-            X[SD::t2] = D == 3 ? obit(flags, SD::t2) * G::H + (x2 >> 1) : 0;
-        }
-    }
+    const bool inside = X[SD::d] >= 0 && X[SD::d] < N;
+    const int nb = pi.nbr[S];
+    v = inside ? 0 : nb;
+    const bool cf = v <= -2;
+    const int flags = pi.flags;
+    const int x1 = X[SD::t1], x2 = X[SD::t2];
+    if (!inside) X[SD::d] = SD::hi ? 0 : N - 1;
+    X[SD::t1] = cf ? obit(flags, SD::t1) * G::H + (x1 >> 1) : x1;
+    X[SD::t2] = D == 3 ? (cf ? obit(flags, SD::t2) * G::H + (x2 >> 1) : x2) : 0;
+    // a Dirichlet side reads the parent's own (in-range) cell and ignores it
+    const int64_t box = inside ? p : (v >= 0 ? (int64_t)v : (cf ? (int64_t)(-v - 2) : p));
     const size_t oo = (size_t)box * G::C + cpos<D, N>(X[0], X[1], X[2]);
     const T d = u[oo] - uold[oo];
     if (v >= 0) q[qpad<D, N>(L[0], L[1], L[2])] = d;
@@ -565,15 +582,15 @@ __global__ __launch_bounds__(256) void k_prolong(LevelArgs<T> a) {
     __shared__ T qs[G::BPW * G::QC];
     const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb);
     T *q = qs + sl.slot * G::QC;
-    const BoxInfo *bi = a.info + sl.b;
+    const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
-    const int flags = bi->flags;
+    const int flags = bi.flags;
     const int o[3] = {obit(flags, 0) * G::H, obit(flags, 1) * G::H, D == 3 ? obit(flags, 2) * G::H : 0};
     T raw[NH];
     int hv[NH];
     if (sl.valid) {
-        const int64_t p = bi->parent;
-        const BoxInfo *pi = a.info + p;
+        const int64_t p = bi.parent;
+        const BoxInfo pi = load_box<D, N>(a.info, p);
         for (int pc = sl.t; pc < G::HC; pc += G::TPB) {
             const int I = pc % G::H, J = (pc / G::H) % G::H, K = D == 3 ? pc / (G::H * G::H) : 0;
             const size_t oo = (size_t)p * G::C + cpos<D, N>(o[0] + I, o[1] + J, o[2] + K);
@@ -637,9 +654,9 @@ __global__ __launch_bounds__(256) void k_final(LevelArgs<T> a, double *partial, 
     __shared__ double red_m[256], red_s[256];
     const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb);
     T *s = sm + sl.slot * G::PC;
-    const BoxInfo *bi = a.info + sl.b;
+    const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
-    const bool leaf = bi->flags & FLAG_LEAF;
+    const bool leaf = bi.flags & FLAG_LEAF;
     Stager<D, N, T> st;
     if (sl.valid) st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, leaf);
     __syncthreads();
@@ -647,7 +664,7 @@ __global__ __launch_bounds__(256) void k_final(LevelArgs<T> a, double *partial, 
     __syncthreads();
     double mx = 0.0, ss = 0.0;
     if (sl.valid) {
-        if (bi->parent >= 0) restrict_octant<D, N, T, true>(s, a.u, bi, sl.t);
+        if (bi.parent >= 0) restrict_octant<D, N, T, true>(s, a.u, bi, sl.t);
         if (leaf) {
             for (int e = sl.t; e < G::C; e += G::TPB) {
                 int i, j, k;
@@ -720,7 +737,7 @@ __global__ __launch_bounds__(256) void k_restrict_rho(LevelArgs<T> a) {
     __shared__ T sm[G::BPW * G::C];
     const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb);
     T *s = sm + sl.slot * G::C;
-    const BoxInfo *bi = a.info + sl.b;
+    const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
     if (sl.valid) {
         for (int e = sl.t; e < G::C; e += G::TPB) {
