@@ -43,7 +43,10 @@ struct CoarseArgs {
 template <int D, int N, typename T>
 void launch_level(Op op, const LevelArgs<T> &a, int colour, hipStream_t st);
 template <int D, int N, typename T>
-void launch_final(const LevelArgs<T> &a, double *partial, int64_t part0, double hD, hipStream_t st);
+void launch_final(const LevelArgs<T> &a, double *partial, int64_t part0, double hD, float *rout,
+                  hipStream_t st);
+template <int D, int N>
+void launch_ir_update(const BoxInfo *info, double *u, const float *e, int64_t nb, hipStream_t st);
 template <int D, int N>
 int final_wgs(int64_t nb);
 void launch_reduce(const double *partial, int64_t n, double *out, hipStream_t st);

@@ -646,9 +646,12 @@ __global__ __launch_bounds__(256) void k_prolong(LevelArgs<T> a) {
 // ---------------------------------------------------------------------------
 // Boxes of level l: the octant of the parent receives mean(u) (l >= 2); on
 // leaves r = rho - L u, and the workgroup writes (max |r|, sum r^2 h^D) to
-// partial[part0 + workgroup].
+// partial[part0 + workgroup].  With rout set, the leaf residual is also
+// stored there rounded to FP32: the right-hand side of the correction solve
+// of the mixed-precision refinement.
 template <int D, int N, typename T>
-__global__ __launch_bounds__(256) void k_final(LevelArgs<T> a, double *partial, int64_t part0, double hD) {
+__global__ __launch_bounds__(256) void k_final(LevelArgs<T> a, double *partial, int64_t part0, double hD,
+                                               float *__restrict__ rout) {
     using G = Geo<D, N>;
     __shared__ T sm[G::BPW * G::PC];
     __shared__ double red_m[256], red_s[256];
@@ -671,6 +674,7 @@ __global__ __launch_bounds__(256) void k_final(LevelArgs<T> a, double *partial, 
                 cell_of<D, N>(e, i, j, k);
                 const double r = (double)(a.rho[bo + e] - (nb_sum<D, N, T>(s, i, j, k) -
                                                           T(2 * D) * s[padi<D, N>(i, j, k)]) * a.ih2);
+                if (rout) rout[bo + e] = (float)r;
                 mx = fmax(mx, fabs(r));
                 ss += r * r;
             }
@@ -773,6 +777,17 @@ __global__ __launch_bounds__(256) void k_permute(const BoxInfo *__restrict__ inf
         if (to_split) fb[e] = s[n];
         else fb[n] = s[e];
     }
+}
+
+// Mixed-precision refinement: u += e on the leaf boxes (e in FP32).
+template <int D, int N>
+__global__ __launch_bounds__(256) void k_ir_update(const BoxInfo *__restrict__ info, double *__restrict__ u,
+                                                   const float *__restrict__ e, int nb) {
+    using G = Geo<D, N>;
+    const Slot<D, N> sl = slot_of<D, N>(0, nb);
+    if (!sl.valid || !(load_box<D, N>(info, sl.b).flags & FLAG_LEAF)) return;
+    const size_t bo = (size_t)sl.b * G::C;
+    for (int c = sl.t; c < G::C; c += G::TPB) u[bo + c] = u[bo + c] + (double)e[bo + c];
 }
 
 // Copy of the caller's rho on leaf boxes into the colour-split working rho.
@@ -1107,9 +1122,16 @@ void launch_level(Op op, const LevelArgs<T> &a, int colour, hipStream_t st) {
 }
 
 template <int D, int N, typename T>
-void launch_final(const LevelArgs<T> &a, double *partial, int64_t part0, double hD, hipStream_t st) {
+void launch_final(const LevelArgs<T> &a, double *partial, int64_t part0, double hD, float *rout,
+                  hipStream_t st) {
     const int g = wg_count<D, N>(a.nb);
-    AFMG_LAUNCH((k_final<D, N, T>), g, st, a, partial, part0, hD);
+    AFMG_LAUNCH((k_final<D, N, T>), g, st, a, partial, part0, hD, rout);
+}
+
+template <int D, int N>
+void launch_ir_update(const BoxInfo *info, double *u, const float *e, int64_t nb, hipStream_t st) {
+    const int g = wg_count<D, N>(nb);
+    AFMG_LAUNCH((k_ir_update<D, N>), g, st, info, u, e, (int)nb);
 }
 
 template <int D, int N>
@@ -1162,13 +1184,20 @@ void launch_fill(T *dst, int64_t n, T v, hipStream_t st) {
 
 #define AFMG_INST(D, N, T)                                                                              \
     template void launch_level<D, N, T>(Op, const LevelArgs<T> &, int, hipStream_t);                     \
-    template void launch_final<D, N, T>(const LevelArgs<T> &, double *, int64_t, double, hipStream_t);  \
+    template void launch_final<D, N, T>(const LevelArgs<T> &, double *, int64_t, double, float *,     \
+                                        hipStream_t);                                                 \
     template void launch_coarse<D, N, T>(const CoarseArgs<T> &, hipStream_t);                           \
     template void launch_permute<D, N, T>(const BoxInfo *, T *, int64_t, int64_t, int, int, hipStream_t); \
     template void launch_load_rho<D, N, T>(const BoxInfo *, const T *, T *, int64_t, hipStream_t);
 
 AFMG_INST(2, 8, double)
 AFMG_INST(3, 8, double)
+AFMG_INST(2, 8, float)
+AFMG_INST(3, 8, float)
+template void launch_ir_update<2, 8>(const BoxInfo *, double *, const float *, int64_t, hipStream_t);
+template void launch_ir_update<3, 8>(const BoxInfo *, double *, const float *, int64_t, hipStream_t);
+template void launch_copy<float>(const float *, float *, int64_t, hipStream_t);
+template void launch_fill<float>(float *, int64_t, float, hipStream_t);
 template int final_wgs<2, 8>(int64_t);
 template int final_wgs<3, 8>(int64_t);
 template void launch_bc_derive<2, 8>(const BoxInfo *, int64_t, int64_t, double *, hipStream_t);

@@ -53,22 +53,27 @@ int64_t cells_per_face(int dim) { return dim == 3 ? BOX_N * BOX_N : BOX_N; }
 double level_h(int l) { return 1.0 / ((double)BOX_N * std::ldexp(1.0, l - 1)); }
 
 struct WsLayout {
-    size_t rho, uold, bc, partial, norm, total;
+    // FP64: rho, uold; mixed: rho (FP64 leaf rho), e, rho_e, uold_e (FP32)
+    size_t rho, uold, bc, partial, norm, e, rho_e, uold_e, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-WsLayout ws_layout(const afmg_tree *t) {
+WsLayout ws_layout(const afmg_tree *t, int precision) {
     const HostTree &h = t->h;
     const size_t C = (size_t)cells_per_box(h.dim), F = (size_t)cells_per_face(h.dim);
-    const size_t nlt = (size_t)h.n_below_lmax();
+    const size_t nlt = (size_t)h.n_below_lmax(), nb = (size_t)h.n_boxes;
+    const bool mixed = precision == AFMG_MIXED;
     WsLayout L{};
     size_t off = 0;
-    L.rho = off; off = align256(off + (size_t)h.n_boxes * C * sizeof(double));
-    L.uold = off; off = align256(off + nlt * C * sizeof(double));
+    L.rho = off; off = align256(off + nb * C * sizeof(double));
+    L.uold = off; off = align256(off + (mixed ? 0 : nlt * C * sizeof(double)));
     L.bc = off; off = align256(off + (size_t)std::max<int64_t>(1, h.n_bfaces_all) * F * sizeof(double));
     L.partial = off; off = align256(off + (size_t)std::max<int64_t>(1, t->n_parts) * 2 * sizeof(double));
     L.norm = off; off = align256(off + 2 * sizeof(double));
+    L.e = off; off = align256(off + (mixed ? nb * C * sizeof(float) : 0));
+    L.rho_e = off; off = align256(off + (mixed ? nb * C * sizeof(float) : 0));
+    L.uold_e = off; off = align256(off + (mixed ? nlt * C * sizeof(float) : 0));
     L.total = off;
     return L;
 }
@@ -119,33 +124,28 @@ int check_opts(const afmg_opts *o) {
     if (!(o->tol >= 0.0) || o->max_cycles < 0 || o->max_cycles > 100000 || o->fixed_cycles < 0 ||
         o->fixed_cycles > 100000)
         return fail(AFMG_ERR_ARG, "tol / max_cycles / fixed_cycles out of range");
-    if (o->precision != AFMG_FP64) return fail(AFMG_ERR_ARG, "precision not supported by this entry point");
+    if (o->precision != AFMG_FP64 && o->precision != AFMG_MIXED) return fail(AFMG_ERR_ARG, "bad precision");
     return AFMG_OK;
 }
 
 // ---------------------------------------------------------------------------
-// the FP64 solve
+// kernel timing for opts.profile
 // ---------------------------------------------------------------------------
 constexpr int PROF_PAIRS = 64;
 
-template <int D>
-struct Solver {
+struct Prof {
     afmg_tree *t;
-    const HostTree &h;
     hipStream_t st;
-    const afmg_opts &o;
-    LevelArgs<double> base;
-    double *partial, *norm;
-    afmg_stats *stats = nullptr;
+    bool on;
+    int lmax;
+    afmg_stats *stats;
     std::vector<std::pair<int, int>> pending;  // (kernel class, event pair)
-
-    Solver(afmg_tree *t_, hipStream_t s, const afmg_opts &o_) : t(t_), h(t_->h), st(s), o(o_) {}
 
     // Bracket a finest-level launch with an event pair when profiling.
     template <class Fn>
     void timed(int kind, int l, Fn fn) {
         const int pair = (int)pending.size();
-        if (!o.profile || l != h.lmax || pair >= PROF_PAIRS) {
+        if (!on || kind < 0 || l != lmax || pair >= PROF_PAIRS) {
             fn();
             return;
         }
@@ -166,25 +166,34 @@ struct Solver {
         }
         pending.clear();
     }
+};
 
-    LevelArgs<double> lev(int l) const {
-        LevelArgs<double> a = base;
+// ---------------------------------------------------------------------------
+// the FAS cycles (paper §3.2) on arrays of type T
+// ---------------------------------------------------------------------------
+template <int D, typename T>
+struct Cycler {
+    const HostTree &h;
+    hipStream_t st;
+    const afmg_opts &o;
+    Prof &prof;
+    LevelArgs<T> base;
+    const double *bc64;  // Dirichlet rows for the coarse kernel (null when homogeneous)
+
+    LevelArgs<T> lev(int l) const {
+        LevelArgs<T> a = base;
         a.b0 = h.lvl_off[(size_t)l];
         a.nb = (int)h.level_count(l);
         const double hh = level_h(l);
-        a.h2 = hh * hh;
-        a.ih2 = 1.0 / (hh * hh);
+        a.h2 = (T)(hh * hh);
+        a.ih2 = (T)(1.0 / (hh * hh));
         return a;
     }
     void level(Op op, int l, int colour = 0) {
         const int kind = op == Op::GSRB ? AFMG_PROF_GSRB
                          : op == Op::RESID_RESTRICT ? AFMG_PROF_RESID
                          : op == Op::PROLONG ? AFMG_PROF_PROLONG : -1;
-        if (kind < 0) {
-            launch_level<D, BOX_N, double>(op, lev(l), colour, st);
-            return;
-        }
-        timed(kind, l, [&] { launch_level<D, BOX_N, double>(op, lev(l), colour, st); });
+        prof.timed(kind, l, [&] { launch_level<D, BOX_N, T>(op, lev(l), colour, st); });
     }
     void gsrb(int l, int n) {
         for (int q = 0; q < n; q++) {
@@ -193,11 +202,13 @@ struct Solver {
         }
     }
     void coarse(int mode) {
-        CoarseArgs<double> c{base.info, base.u, base.rho, base.uold, base.bc, mode, 0,
-                             o.n_down, o.n_up, o.n_base};
+        CoarseArgs<T> c{base.info, base.u, base.rho, base.uold, bc64, mode, base.homog,
+                        o.n_down, o.n_up, o.n_base};
         if (h.lmax == 1) c.uold = nullptr;
-        launch_coarse<D, BOX_N, double>(c, st);
+        launch_coarse<D, BOX_N, T>(c, st);
     }
+    // V-cycle from level top: levels >= 2 box by box, levels <= 1 in the
+    // one-workgroup kernel
     void vcycle(int top) {
         for (int l = top; l >= 2; l--) {
             gsrb(l, o.n_down);
@@ -210,27 +221,53 @@ struct Solver {
             gsrb(l, o.n_up);
         }
     }
+    // FMG from a zero guess: restrict rho down, then per level store v',
+    // correct from the coarser level and run a V-cycle from it
     void fmg() {
-        launch_fill<double>(base.u, h.n_boxes * cells_per_box(D), 0.0, st);
+        launch_fill<T>(base.u, h.n_boxes * cells_per_box(D), T(0), st);
         for (int l = h.lmax; l >= 2; l--) level(Op::RESTRICT_RHO, l);
         coarse(COARSE_FMG);
         const int64_t C = cells_per_box(D);
         for (int l = 2; l <= h.lmax; l++) {
             if (l < h.lmax)
-                launch_copy<double>(base.u + h.lvl_off[(size_t)l] * C, base.uold + h.lvl_off[(size_t)l] * C,
-                                    h.level_count(l) * C, st);
+                launch_copy<T>(base.u + h.lvl_off[(size_t)l] * C, base.uold + h.lvl_off[(size_t)l] * C,
+                               h.level_count(l) * C, st);
             level(Op::PROLONG, l);
             vcycle(l);
         }
     }
-    // restriction of u into parents and the composite leaf residual norms
-    int finalize(double &rmax, double &rl2) {
+};
+
+// ---------------------------------------------------------------------------
+// the solve
+// ---------------------------------------------------------------------------
+template <int D>
+struct Solver {
+    afmg_tree *t;
+    const HostTree &h;
+    hipStream_t st;
+    const afmg_opts &o;
+    Prof prof;
+    LevelArgs<double> base;  // FP64 state: u, rho, uold (FP64 path), Dirichlet rows
+    double *partial, *norm;
+
+    Solver(afmg_tree *t_, hipStream_t s, const afmg_opts &o_, afmg_stats *S)
+        : t(t_), h(t_->h), st(s), o(o_), prof{t_, s, o_.profile != 0, t_->h.lmax, S, {}} {}
+
+    // Restriction of u into parents and the composite leaf residual (FP64);
+    // rout receives the FP32 leaf residual for the mixed refinement.
+    int finalize(double &rmax, double &rl2, float *rout) {
         for (int l = h.lmax; l >= 1; l--) {
             if (l == 1 && !root_is_leaf(h)) continue;
             const double hh = level_h(l);
             const double hD = D == 3 ? hh * hh * hh : hh * hh;
-            timed(AFMG_PROF_FINAL, l, [&] {
-                launch_final<D, BOX_N, double>(lev(l), partial, t->part_off[(size_t)l], hD, st);
+            LevelArgs<double> a = base;
+            a.b0 = h.lvl_off[(size_t)l];
+            a.nb = (int)h.level_count(l);
+            a.h2 = hh * hh;
+            a.ih2 = 1.0 / (hh * hh);
+            prof.timed(AFMG_PROF_FINAL, l, [&] {
+                launch_final<D, BOX_N, double>(a, partial, t->part_off[(size_t)l], hD, rout, st);
             });
         }
         launch_reduce(partial, t->n_parts, norm, st);
@@ -240,31 +277,59 @@ struct Solver {
         if (e != hipSuccess) return hip_fail(e, "norm readback");
         e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(e, "stream synchronize");
-        collect();
+        prof.collect();
         rmax = t->h_norm[0];
         rl2 = t->h_norm[1];
         return AFMG_OK;
     }
 };
 
+// Outer loop shared by both precisions: `step` runs one cycle (or one
+// refinement step) and leaves the FP64 residual norms in S.r_max / S.r_l2.
+template <class Step>
+int iterate(const afmg_opts &o, afmg_stats &S, Step step) {
+    const bool fixed = o.fixed_cycles > 0;
+    const int nmax = fixed ? o.fixed_cycles : o.max_cycles;
+    bool conv = !fixed && S.r_max <= o.tol * S.r0_max;
+    int grow = 0;
+    double prev = S.r_max;
+    while (!conv && S.cycles < nmax) {
+        const int rc = step(S.cycles);
+        if (rc != AFMG_OK) return rc;
+        if (S.cycles < AFMG_HIST) {
+            S.hist_max[S.cycles] = S.r_max;
+            S.hist_l2[S.cycles] = S.r_l2;
+        }
+        S.cycles++;
+        if (!std::isfinite(S.r_max)) return AFMG_ERR_NONFINITE;
+        if (!fixed) {
+            grow = S.r_max > prev ? grow + 1 : 0;
+            if (grow >= 3) return AFMG_ERR_DIVERGED;
+            conv = S.r_max <= o.tol * S.r0_max;
+        }
+        prev = S.r_max;
+    }
+    return (!fixed && !conv) ? AFMG_NOT_CONVERGED : AFMG_OK;
+}
+
 template <int D>
-int solve_fp64(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, double *u,
-               char *ws, const afmg_opts &o, afmg_stats &S) {
+int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, double *u, char *ws,
+          const afmg_opts &o, afmg_stats &S) {
     const HostTree &h = t->h;
-    const WsLayout L = ws_layout(t);
-    Solver<D> s(t, st, o);
-    double *rho_i = (double *)(ws + L.rho);
-    double *uold = (double *)(ws + L.uold);
-    double *bc_w = (double *)(ws + L.bc);
-    s.stats = &S;
+    const bool mixed = o.precision == AFMG_MIXED;
+    const WsLayout L = ws_layout(t, o.precision);
+    Solver<D> s(t, st, o, &S);
     if (o.profile && t->events.empty()) {
         t->events.resize(2 * PROF_PAIRS);
         for (auto &ev : t->events)
             if (hipEventCreate(&ev) != hipSuccess) return fail(AFMG_ERR_HIP, "hipEventCreate failed");
     }
+    double *rho_i = (double *)(ws + L.rho);
+    double *bc_w = (double *)(ws + L.bc);
     s.partial = (double *)(ws + L.partial);
     s.norm = (double *)(ws + L.norm);
-    s.base = LevelArgs<double>{t->d_info, u, rho_i, uold, bc_w, 0, 0, 0, 0.0, 0.0};
+    s.base = LevelArgs<double>{t->d_info, u, rho_i, mixed ? nullptr : (double *)(ws + L.uold), bc_w, 0, 0, 0,
+                               0.0, 0.0};
     const int64_t F = cells_per_face(D), C = cells_per_box(D);
 
     hipEvent_t ev0, ev1;
@@ -286,46 +351,49 @@ int solve_fp64(afmg_tree *t, hipStream_t st, const double *rho, const double *bc
     // working copies in the colour-split box layout: rho of the leaves, and
     // u in place (a zero guess needs no conversion)
     launch_load_rho<D, BOX_N, double>(t->d_info, rho, rho_i, h.n_boxes, st);
-    if (!o.use_guess || o.cycle == AFMG_CYCLE_FMG_V) launch_fill<double>(u, h.n_boxes * C, 0.0, st);
+    const bool guess = o.use_guess && (mixed || o.cycle == AFMG_CYCLE_V);
+    if (!guess) launch_fill<double>(u, h.n_boxes * C, 0.0, st);
     else launch_permute<D, BOX_N, double>(t->d_info, u, 0, h.n_boxes, 1, 0, st);
 
-    int rc = s.finalize(S.r0_max, S.r0_l2);
+    float *e32 = mixed ? (float *)(ws + L.e) : nullptr;
+    float *rho32 = mixed ? (float *)(ws + L.rho_e) : nullptr;
+    int rc = s.finalize(S.r0_max, S.r0_l2, rho32);
     if (rc != AFMG_OK) return rc;
     S.r_max = S.r0_max;
     S.r_l2 = S.r0_l2;
     int status = AFMG_OK;
     if (!std::isfinite(S.r0_max)) {
         status = AFMG_ERR_NONFINITE;
-    } else {
+    } else if (!mixed) {
+        Cycler<D, double> cy{h, st, o, s.prof, s.base, bc_w};
         if (o.cycle == AFMG_CYCLE_FMG_V) {
-            s.fmg();
-            rc = s.finalize(S.r_max, S.r_l2);
+            cy.fmg();
+            rc = s.finalize(S.r_max, S.r_l2, nullptr);
             if (rc != AFMG_OK) return rc;
         }
-        const bool fixed = o.fixed_cycles > 0;
-        const int nmax = fixed ? o.fixed_cycles : o.max_cycles;
-        bool conv = !fixed && S.r_max <= o.tol * S.r0_max;
-        int grow = 0;
-        double prev = S.r_max;
-        while (!conv && S.cycles < nmax) {
-            s.vcycle(h.lmax);
-            rc = s.finalize(S.r_max, S.r_l2);
-            if (rc != AFMG_OK) return rc;
-            if (S.cycles < AFMG_HIST) {
-                S.hist_max[S.cycles] = S.r_max;
-                S.hist_l2[S.cycles] = S.r_l2;
+        status = iterate(o, S, [&](int) {
+            cy.vcycle(h.lmax);
+            return s.finalize(S.r_max, S.r_l2, nullptr);
+        });
+    } else {
+        // FP32 V-cycles inside FP64 iterative refinement: solve L e = r with
+        // homogeneous Dirichlet values in FP32 (coarsest grids in FP64),
+        // u += e on the leaves, new FP64 residual
+        LevelArgs<float> b32{t->d_info, e32, rho32, (float *)(ws + L.uold_e), nullptr, 0, 0, 1, 0.f, 0.f};
+        Cycler<D, float> cy{h, st, o, s.prof, b32, nullptr};
+        status = iterate(o, S, [&](int k) {
+            if (k == 0 && o.cycle == AFMG_CYCLE_FMG_V) {
+                cy.fmg();
+            } else {
+                launch_fill<float>(e32, h.n_boxes * C, 0.f, st);
+                cy.vcycle(h.lmax);
             }
-            S.cycles++;
-            if (!std::isfinite(S.r_max)) { status = AFMG_ERR_NONFINITE; break; }
-            if (!fixed) {
-                grow = S.r_max > prev ? grow + 1 : 0;
-                if (grow >= 3) { status = AFMG_ERR_DIVERGED; break; }
-                conv = S.r_max <= o.tol * S.r0_max;
-            }
-            prev = S.r_max;
-        }
-        if (status == AFMG_OK && !fixed && !conv) status = AFMG_NOT_CONVERGED;
+            launch_ir_update<D, BOX_N>(t->d_info, u, e32, h.n_boxes, st);
+            return s.finalize(S.r_max, S.r_l2, rho32);
+        });
+        if (status < 0 && status != AFMG_ERR_NONFINITE && status != AFMG_ERR_DIVERGED) return status;
     }
+    if (!mixed && status < 0 && status != AFMG_ERR_NONFINITE && status != AFMG_ERR_DIVERGED) return status;
     launch_permute<D, BOX_N, double>(t->d_info, u, 0, h.n_boxes, 0, 0, st);
     (void)hipEventRecord(ev1, st);
     (void)hipEventSynchronize(ev1);
@@ -444,7 +512,7 @@ int afmg_workspace_bytes(const afmg_tree *t, const afmg_opts *o, size_t *bytes) 
         int rc = check_opts(o);
         if (rc != AFMG_OK) return rc;
     }
-    *bytes = ws_layout(t).total;
+    *bytes = ws_layout(t, o ? o->precision : AFMG_FP64).total;
     return AFMG_OK;
 }
 
@@ -455,14 +523,14 @@ int afmg_solve(afmg_tree *t, void *stream, const double *rho, const double *bc, 
     if (rc != AFMG_OK) return rc;
     if (!aligned(rho, 8) || !aligned(u, 8) || (bc && !aligned(bc, 8)) || !aligned(workspace, 256))
         return fail(AFMG_ERR_ARG, "misaligned array");
-    const WsLayout L = ws_layout(t);
+    const WsLayout L = ws_layout(t, opts->precision);
     if (workspace_bytes < L.total) return fail(AFMG_ERR_ARG, "workspace too small");
     std::memset(stats, 0, sizeof(*stats));
     rc = bind_device(t);
     if (rc != AFMG_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
-    if (t->h.dim == 3) return solve_fp64<3>(t, st, rho, bc, u, (char *)workspace, *opts, *stats);
-    return solve_fp64<2>(t, st, rho, bc, u, (char *)workspace, *opts, *stats);
+    if (t->h.dim == 3) return solve<3>(t, st, rho, bc, u, (char *)workspace, *opts, *stats);
+    return solve<2>(t, st, rho, bc, u, (char *)workspace, *opts, *stats);
 }
 
 }  // extern "C"
