@@ -64,15 +64,16 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(w, solve_kw, budget_s=30.0):
-    """Time the oracle on the host cores: the same workload and stop rule."""
+def cpu_baseline(w, solve_kw):
+    """Time the oracle on the host cores: the same workload and stop rule.
+    Returns the baseline record and the oracle's solution (leaf order)."""
     from oracle import oracle as O
     t = O.Tree(w.dim, w.N, w.level, w.idx)
     kw = dict(solve_kw)
     t0 = time.perf_counter()
-    _, st = t.solve(w.rho, w.bc, **kw)
+    u, st = t.solve(w.rho, w.bc, **kw)
     dt = time.perf_counter() - t0
-    return {
+    return u, {
         "value": w.n_unknowns / dt,
         "unit": "unknowns/s",
         "cores": O.num_threads(),
@@ -126,34 +127,43 @@ def main():
     ws = torch.empty(tree.workspace_bytes(opts), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream(dev)
 
-    def step(profile):
-        # the FMG cycle starts from zero by definition; V-cycles restart from
-        # zero because u is zeroed before each step
-        if solve_kw["cycle"] != "FMG":
-            u.zero_()
-        return A.solve(tree, rho, bc, u, workspace=ws, stream=stream, profile=profile, **solve_kw)
+    def timed_steps(precision):
+        """warmup + exactly `steps` timed solves; returns ms/step, the
+        summed event timings of the finest-level kernels and the last stats."""
+        kw = dict(solve_kw, precision=precision)
+        ws_p = ws if tree.workspace_bytes(A.make_opts(**kw)) <= ws.numel() else torch.empty(
+            tree.workspace_bytes(A.make_opts(**kw)), dtype=torch.uint8, device=dev)
 
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    prof_ms = np.zeros(4)
-    prof_n = np.zeros(4, dtype=np.int64)
-    cycles = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        _, st = step(True)
-        prof_ms += np.array(st["prof_ms"])
-        prof_n += np.array(st["prof_n"], dtype=np.int64)
-        cycles.append(st["cycles"])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
+        def one(profile):
+            # every step starts from u = 0 (the library zeroes u itself)
+            return A.solve(tree, rho, bc, u, workspace=ws_p, stream=stream, profile=profile,
+                           use_guess=False, **kw)
+
+        for _ in range(args.warmup):
+            one(False)
+        torch.cuda.synchronize()
+        prof_ms = np.zeros(4)
+        prof_n = np.zeros(4, dtype=np.int64)
+        cycles = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, st = one(True)
+            prof_ms += np.array(st["prof_ms"])
+            prof_n += np.array(st["prof_n"], dtype=np.int64)
+            cycles.append(st["cycles"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        return (t1 - t0) * 1e3 / args.steps, prof_ms, prof_n, st, cycles
+
+    # FP64: the headline step
+    ms, prof_ms, prof_n, st64, cycles = timed_steps("fp64")
+    u64 = tree.boxes_to_leaf(u).cpu().numpy()
     value = w.n_unknowns / (ms * 1e-3)
 
     # dominant kernel: finest-level half sweep.  Algorithmic bytes per cell
-    # of the level: read the other colour (8 B / 2), read rho of the updated
-    # colour (8 B / 2), write the updated colour (8 B / 2) = 12 B.
-    n_fine = tree.n_leaves * tree.cells_per_box if args.workload in ("c2", "c1") else None
+    # of the level: read the other colour (s / 2), read rho of the updated
+    # colour (s / 2), write the updated colour (s / 2) = 1.5 s, s = 8 B.
+    n_fine = tree.n_leaves * tree.cells_per_box
     bytes_per_launch = 12.0 * n_fine
     avg_ms = prof_ms[0] / max(prof_n[0], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
@@ -165,11 +175,28 @@ def main():
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": traffic,
-        "kernel": "k_gsrb (finest level, one half sweep)",
+        "kernel": "k_gsrb<3,8,double> (finest level, one half sweep)",
         "algorithmic_bytes_per_launch": bytes_per_launch,
         "avg_launch_ms": round(avg_ms, 5),
         "launches_timed": int(prof_n[0]),
     }
+
+    # mixed: FP32 V-cycles inside FP64 refinement, same workload and stop rule
+    ms_m, prof_m, prof_nm, stm, cycles_m = timed_steps("mixed")
+    umx = tree.boxes_to_leaf(u).cpu().numpy()
+    avg_m = prof_m[0] / max(prof_nm[0], 1)
+    mixed = {
+        "value": w.n_unknowns / (ms_m * 1e-3),
+        "unit": "unknowns/s",
+        "ms_per_step": ms_m,
+        "outer_iterations": int(np.median(cycles_m)),
+        "final_residual_ratio": stm["r_max"] / stm["r0_max"],
+        "rel_l2_vs_gpu_fp64": float(np.linalg.norm(umx - u64) / np.linalg.norm(u64)),
+        "dominant_kernel": "k_gsrb<3,8,float> (finest level, one half sweep)",
+        "dominant_achieved_GBs": round(6.0 * n_fine / (avg_m * 1e-3) / 1e9, 1) if prof_nm[0] else None,
+        "dominant_avg_launch_ms": round(avg_m, 5),
+    }
+
     out = {
         "metric": "Poisson unknowns/s to 1e-10 residual reduction (FP64 vs mixed); HBM % of peak",
         "value": value,
@@ -192,12 +219,17 @@ def main():
             "cycle": "FMG + V(2,2)" if solve_kw["cycle"] == "FMG" else "V(2,2)",
             "tol": solve_kw["tol"],
             "v_cycles": int(np.median(cycles)),
+            "final_residual_ratio": st64["r_max"] / st64["r0_max"],
             "precision": "fp64",
         },
         "roofline": roofline,
+        "mixed": mixed,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, solve_kw)
+        uo, out["cpu_baseline"] = cpu_baseline(w, solve_kw)
+        nrm = np.linalg.norm(uo)
+        out["config"]["rel_l2_vs_oracle"] = float(np.linalg.norm(u64 - uo) / nrm)
+        out["mixed"]["rel_l2_vs_oracle"] = float(np.linalg.norm(umx - uo) / nrm)
     print(json.dumps(out), flush=True)
     return 0
 

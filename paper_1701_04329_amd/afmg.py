@@ -245,13 +245,13 @@ def _ptr(t):
 
 def solve(tree: Tree, rho, bc=None, u=None, *, cycle="V", tol=1e-10, max_cycles=100, fixed_cycles=0,
           n_down=2, n_up=2, n_base=4, precision="fp64", workspace=None, stream=None, check=True,
-          profile=False):
+          profile=False, use_guess=None):
     """Solve lap_h(u) = rho on `tree`.
 
     rho, u: torch float64 CUDA tensors [n_boxes, N^D] in box order; bc:
     [n_bfaces, N^(D-1)] Dirichlet rows or None (zero).  u (if given) is the
-    initial guess and is overwritten; otherwise a new tensor is returned.
-    Returns (u, stats dict)."""
+    initial guess (unless use_guess=False) and is overwritten; otherwise a
+    new tensor is returned.  Returns (u, stats dict)."""
     import torch
 
     dev = rho.device
@@ -260,7 +260,8 @@ def solve(tree: Tree, rho, bc=None, u=None, *, cycle="V", tol=1e-10, max_cycles=
     shape = (tree.n_boxes, tree.cells_per_box)
     if rho.dtype != torch.float64 or tuple(rho.shape) != shape or not rho.is_contiguous():
         raise ValueError(f"rho must be contiguous float64 {shape}")
-    use_guess = u is not None
+    if use_guess is None:
+        use_guess = u is not None
     if u is None:
         u = torch.empty(shape, dtype=torch.float64, device=dev)
     elif u.dtype != torch.float64 or tuple(u.shape) != shape or not u.is_contiguous():
