@@ -825,3 +825,104 @@ int or_get_bc(void *p, int b, int s, double *out) {
     return 1;
 }
 int or_num_threads(void) { return omp_get_max_threads(); }
+
+/* ------------------------------------------------------------------------ */
+/* sparse assembly of the composite operator (for the adjoint oracle)        */
+/* ------------------------------------------------------------------------ */
+/* Row of leaf cell c: (sum over its 2D sides of u_nb - 2D u_c) / h^2 with the
+   neighbour value of each side written out as a combination of leaf cells:
+     same-level leaf cell      -> that cell
+     same-level refined cell   -> mean of its 2^D children (leaf cells, 2:1)
+     physical side (b = 0)     -> -u_c
+     refinement boundary       -> 1/2 u_H + k1 u_c - 1/4 (u_c2 + partners),
+                                  k1 = 1 (2D), 5/4 (3D)
+   This is the same operator as fill_gc + the stencil (homogeneous values).
+   Unknowns are numbered q * N^D + (x-fastest cell) in the caller's leaf
+   order.  Call with rows == NULL to get the number of entries. */
+static int64_t leaf_unknown(const otree *t, const int *leaf_of_box, int b, int i, int j, int k) {
+    int q = leaf_of_box[b];
+    int N = t->N;
+    int64_t cell = t->dim == 3 ? (i - 1) + (int64_t)N * ((j - 1) + (int64_t)N * (k - 1)) : (i - 1) + (int64_t)N * (j - 1);
+    return (int64_t)q * (t->dim == 3 ? (int64_t)N * N * N : (int64_t)N * N) + cell;
+}
+
+int64_t or_assemble_L(void *p, int32_t *rows, int32_t *cols, double *vals) {
+    otree *t = (otree *)p;
+    int D = t->dim, N = t->N;
+    int *leaf_of_box = malloc(sizeof(int) * t->nbox);
+    for (int b = 0; b < t->nbox; b++) leaf_of_box[b] = -1;
+    for (int q = 0; q < t->nleaf_in; q++) leaf_of_box[t->leaf_box[q]] = q;
+    int64_t n = 0;
+#define PUT(r, c, v)                                   \
+    do {                                               \
+        if (rows) { rows[n] = (int32_t)(r); cols[n] = (int32_t)(c); vals[n] = (v); } \
+        n++;                                           \
+    } while (0)
+    for (int qq = 0; qq < t->nleaf_in; qq++) {
+        int b = t->leaf_box[qq];
+        double h = level_h(t, t->lev[b]), ih2 = 1.0 / (h * h);
+        FOR_CELLS(t, b, i, j, k) {
+            int64_t row = leaf_unknown(t, leaf_of_box, b, i, j, D == 3 ? k : 1);
+            double diag = -2.0 * D * ih2;
+            int c[3] = {i, j, D == 3 ? k : 1};
+            for (int s = 0; s < 2 * D; s++) {
+                int d = s / 2, hi = s % 2;
+                int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+                int x[3] = {c[0], c[1], c[2]};
+                x[d] += hi ? 1 : -1;
+                if (x[d] >= 1 && x[d] <= N) { /* inside the box */
+                    PUT(row, leaf_unknown(t, leaf_of_box, b, x[0], x[1], x[2]), ih2);
+                    continue;
+                }
+                if (c[d] != (hi ? N : 1)) continue;
+                int nb = t->nbr[6 * b + s];
+                if (nb >= 0) {
+                    int y[3] = {c[0], c[1], c[2]};
+                    y[d] = hi ? 1 : N;
+                    if (t->leaf[nb]) {
+                        PUT(row, leaf_unknown(t, leaf_of_box, nb, y[0], y[1], y[2]), ih2);
+                    } else {
+                        /* refined neighbour: mean of the 2^D children of cell y */
+                        double w = ih2 / (D == 3 ? 8.0 : 4.0);
+                        for (int oc = 0; oc < (1 << D); oc++) {
+                            int f[3];
+                            f[0] = 2 * y[0] - 1 + (oc & 1);
+                            f[1] = 2 * y[1] - 1 + ((oc >> 1) & 1);
+                            f[2] = D == 3 ? 2 * y[2] - 1 + ((oc >> 2) & 1) : 1;
+                            int bits = ((f[0] - 1) / N) | (((f[1] - 1) / N) << 1) | (D == 3 ? (((f[2] - 1) / N) << 2) : 0);
+                            int ch = t->child[8 * nb + bits];
+                            PUT(row, leaf_unknown(t, leaf_of_box, ch, (f[0] - 1) % N + 1, (f[1] - 1) % N + 1,
+                                                  D == 3 ? (f[2] - 1) % N + 1 : 1), w);
+                        }
+                    }
+                } else if (nb == -1) {
+                    diag -= ih2;
+                } else {
+                    int par = t->parent[b];
+                    int cb = t->nbr[6 * par + s];
+                    int qc[3];
+                    qc[d] = hi ? 1 : N;
+                    qc[t1] = child_offset(t, b, t1) + (c[t1] + 1) / 2;
+                    qc[t2] = D == 3 ? child_offset(t, b, t2) + (c[t2] + 1) / 2 : 1;
+                    PUT(row, leaf_unknown(t, leaf_of_box, cb, qc[0], qc[1], qc[2]), 0.5 * ih2);
+                    diag += (D == 3 ? 1.25 : 1.0) * ih2;
+                    int y[3] = {c[0], c[1], c[2]};
+                    y[d] = hi ? N - 1 : 2;
+                    PUT(row, leaf_unknown(t, leaf_of_box, b, y[0], y[1], y[2]), -0.25 * ih2);
+                    int p1[3] = {c[0], c[1], c[2]};
+                    p1[t1] = (c[t1] % 2) ? c[t1] + 1 : c[t1] - 1;
+                    PUT(row, leaf_unknown(t, leaf_of_box, b, p1[0], p1[1], p1[2]), -0.25 * ih2);
+                    if (D == 3) {
+                        int p2[3] = {c[0], c[1], c[2]};
+                        p2[t2] = (c[t2] % 2) ? c[t2] + 1 : c[t2] - 1;
+                        PUT(row, leaf_unknown(t, leaf_of_box, b, p2[0], p2[1], p2[2]), -0.25 * ih2);
+                    }
+                }
+            }
+            PUT(row, row, diag);
+        }
+    }
+#undef PUT
+    free(leaf_of_box);
+    return n;
+}

@@ -92,6 +92,8 @@ def lib():
         L.or_get_bc.argtypes = [vp, C.c_int, C.c_int, dp]
         L.or_get_bc.restype = C.c_int
         L.or_num_threads.restype = C.c_int
+        L.or_assemble_L.argtypes = [vp, i32p, i32p, dp]
+        L.or_assemble_L.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -239,6 +241,55 @@ class Tree:
         out = np.zeros(n ** (self.dim - 1))
         ok = lib().or_get_bc(self.h, b, side, _dp(out))
         return out if ok else None
+
+
+def _assemble(tree):
+    L = lib()
+    nnz = L.or_assemble_L(tree.h, None, None, None)
+    r = np.zeros(nnz, np.int32)
+    c = np.zeros(nnz, np.int32)
+    v = np.zeros(nnz)
+    L.or_assemble_L(tree.h, r.ctypes.data_as(C.POINTER(C.c_int32)), c.ctypes.data_as(C.POINTER(C.c_int32)),
+                    _dp(v))
+    return r, c, v
+
+
+def assemble_L(tree):
+    """Sparse matrix (scipy CSR) of the homogeneous composite operator on the
+    leaf unknowns, numbered q * N^D + cell in the caller's leaf order."""
+    import scipy.sparse as sp
+    r, c, v = _assemble(tree)
+    n = tree.n_leaves * tree.cells_per_box
+    return sp.csr_matrix((v, (r, c)), shape=(n, n))
+
+
+def adjoint(tree, ubar):
+    """lambda = L^-T ubar on the leaf unknowns (sparse direct solve), and the
+    gradient with respect to the Dirichlet values, -2 lambda / h^2 on the leaf
+    cells next to each physical side, as [n_leaves, 2D, N^(D-1)] (zero on
+    non-physical sides).  The derivation: u = L^-1 (rho - B b) with
+    (B b)_c = sum over the Dirichlet sides of c of 2 b / h^2."""
+    import scipy.sparse.linalg as spla
+    A = assemble_L(tree)
+    lam = spla.spsolve(A.T.tocsc(), np.ascontiguousarray(ubar, dtype=np.float64).ravel())
+    return lam.reshape(tree.n_leaves, -1), boundary_gradient(tree, lam)
+
+
+def boundary_gradient(tree, lam):
+    dim, N = tree.dim, tree.N
+    lam = np.asarray(lam).reshape((tree.n_leaves,) + (N,) * dim)
+    h = 1.0 / (N * 2.0 ** (tree.level.astype(np.float64) - 1))
+    out = np.zeros((tree.n_leaves, 2 * dim, N ** (dim - 1)))
+    nmax = 2 ** (tree.level - 1)
+    for s in range(2 * dim):
+        d, hi = s // 2, s % 2
+        phys = (tree.idx[:, d] == (nmax if hi else 1))
+        ax = dim - 1 - d
+        sl = [slice(None)] * (dim + 1)
+        sl[1 + ax] = N - 1 if hi else 0
+        face = lam[tuple(sl)].reshape(tree.n_leaves, -1)
+        out[:, s, :] = np.where(phys[:, None], -2.0 * face / (h[:, None] ** 2), 0.0)
+    return out
 
 
 def num_threads():

@@ -687,3 +687,80 @@ def test_gauss_seidel_property_across_boxes(case):
         assert v == pytest.approx((sum(nbs) - h * h * rhos[G]) / (2 * dim), rel=1e-13, abs=1e-13)
         nchk += 1
     assert nchk > 0
+
+
+# ----------------------------------------------------------------------------
+# sparse assembly and the adjoint
+# ----------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_sparse_assembly_equals_dense_and_stencil(case):
+    """The oracle's sparse assembly equals the independent dense assembly and
+    its own ghost-cell stencil (apply_L)."""
+    dim, N, lev, idx = tiny_trees()[case]
+    t = O.Tree(dim, N, lev, idx)
+    A = O.assemble_L(t).toarray()
+    Ad, _ = dense_ref.assemble(dim, N, lev, idx)
+    np.testing.assert_allclose(A, Ad, rtol=1e-13, atol=1e-13 * np.abs(Ad).max())
+    rng = np.random.default_rng(700 + case)
+    x = rng.standard_normal((len(lev), N ** dim))
+    np.testing.assert_allclose(A @ x.ravel(), t.apply_L(x).ravel(), rtol=1e-12,
+                               atol=1e-12 * np.abs(A).max() * np.abs(x).max())
+
+
+def test_sparse_assembly_matches_stencil_on_larger_adaptive_grid():
+    w = W.adaptive_small(3, 8, 5, 1e-3, 6, n_src=2, sigma_range=(0.04, 0.08))
+    t = O.Tree(3, 8, w.level, w.idx)
+    A = O.assemble_L(t)
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal((w.n_leaves, 512))
+    y = t.apply_L(x).ravel()
+    np.testing.assert_allclose(A @ x.ravel(), y, rtol=1e-12, atol=1e-12 * np.abs(y).max())
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_adjoint_gradient_by_finite_differences(case):
+    """l(rho, b) = sum (u* - ut)^2 with u* the discrete solution: central
+    differences are exact for a quadratic loss, so the adjoint gradient
+    (lambda = L^-T 2 (u* - ut)) must match them to rounding, for rho and for
+    the Dirichlet values, along random and single-cell directions."""
+    dim, N, lev, idx = tiny_trees()[case]
+    rng = np.random.default_rng(800 + case)
+    n = len(lev)
+    rho = rng.standard_normal((n, N ** dim))
+    phys = W.physical_side_mask(dim, lev, idx)[:, :, None]
+    bc = rng.standard_normal((n, 2 * dim, N ** (dim - 1))) * phys
+    ut = rng.standard_normal((n, N ** dim))
+    A, g = dense_ref.assemble(dim, N, lev, idx, bc)
+
+    def loss(r, b):
+        _, gb = dense_ref.assemble(dim, N, lev, idx, b)
+        u = np.linalg.solve(A, r.ravel() - gb)
+        return np.sum((u - ut.ravel()) ** 2)
+
+    t = O.Tree(dim, N, lev, idx)
+    u = np.linalg.solve(A, rho.ravel() - g)
+    lam, gbc = O.adjoint(t, 2.0 * (u - ut.ravel()))
+    for trial in range(3):
+        dr = rng.standard_normal(rho.shape) if trial < 2 else np.zeros_like(rho)
+        if trial == 2:
+            dr.ravel()[rng.integers(dr.size)] = 1.0
+        db = rng.standard_normal(bc.shape) * phys
+        eps = 1e-3
+        fd_r = (loss(rho + eps * dr, bc) - loss(rho - eps * dr, bc)) / (2 * eps)
+        fd_b = (loss(rho, bc + eps * db) - loss(rho, bc - eps * db)) / (2 * eps)
+        assert np.sum(lam * dr) == pytest.approx(fd_r, rel=1e-7, abs=1e-9)
+        assert np.sum(gbc * db) == pytest.approx(fd_b, rel=1e-7, abs=1e-9)
+
+
+def test_composite_operator_is_nonsymmetric_at_refinement_boundaries():
+    """On adaptive grids the default refinement-boundary ghost makes L
+    non-symmetric (so the adjoint needs L^T); on uniform grids L is
+    symmetric."""
+    dim, N, lev, idx = tiny_trees()[0]
+    A = O.assemble_L(O.Tree(dim, N, lev, idx))
+    assert abs(A - A.T).max() > 0.1 * abs(A).max()
+    lev_u, idx_u = W.uniform_leaves(3, 3)
+    Au = O.assemble_L(O.Tree(3, 4, lev_u, idx_u))
+    assert abs(Au - Au.T).max() == 0.0
