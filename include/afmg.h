@@ -166,6 +166,49 @@ int afmg_solve(afmg_tree *tree, void *stream, const double *rho, const double *b
                void *workspace, size_t workspace_bytes, const afmg_opts *opts,
                afmg_stats *stats);
 
+/* Operators of afmg_apply (homogeneous Dirichlet values). */
+typedef enum { AFMG_OP_L = 0, AFMG_OP_LT = 1 } afmg_op;
+
+/* Device workspace bytes afmg_apply and afmg_adjoint need. */
+int afmg_adjoint_workspace_bytes(const afmg_tree *tree, const afmg_opts *opts, size_t *bytes);
+
+/*
+ * y = L x or y = L^T x on the leaf cells, where L is the composite operator of
+ * the solve with zero Dirichlet values: the 5/7-point Laplacian with the side
+ * ghosts of §2.4 and §3.3 written out, the value of a refined same-level
+ * neighbour being the mean of its children (§2.5).  On adaptive grids the
+ * refinement-boundary ghost makes L non-symmetric.  x, y: device
+ * [n_boxes][N^D] in the layout of afmg_solve; only leaf boxes of x are read,
+ * parent boxes of y are set to zero.  Errors: AFMG_ERR_ARG, AFMG_ERR_HIP.
+ */
+int afmg_apply(afmg_tree *tree, void *stream, int op, const double *x, double *y, void *workspace,
+               size_t workspace_bytes);
+
+/*
+ * Adjoint of the solve.  With u* = L^-1 (rho - B b) the converged solution
+ * ((B b)_c = sum over the Dirichlet sides of c of 2 b / h^2), a loss l(u*) and
+ * u_bar = dl/du* on the leaf cells:
+ *   rho_bar = dl/drho = lambda,  lambda = L^-T u_bar;
+ *   bc_bar  = dl/db   = -2 lambda_c / h^2 for each Dirichlet row entry, c the
+ *             leaf cell next to that face (zero for non-leaf values, which the
+ *             converged solution does not depend on).
+ * On grids whose leaves all lie on one level L is symmetric and lambda is one
+ * more multigrid solve (V-cycles, zero Dirichlet values).  Otherwise lambda
+ * comes from BiCGSTAB on L^T, right-preconditioned by one V-cycle of L scaled
+ * by the cell volumes.  opts: tol (relative max-norm of u_bar - L^T lambda),
+ * max_cycles (iterations), n_down/n_up/n_base of the V-cycle; stats.cycles
+ * counts V-cycles or BiCGSTAB iterations, stats.r_max is the final residual.
+ *   u_bar    device [n_boxes][N^D]; entries on parent boxes (where u* is the
+ *            restriction of the leaves) reach the leaves through the
+ *            transposed restriction
+ *   rho_bar  device [n_boxes][N^D] out (parents zero)
+ *   bc_bar   device [n_bfaces][N^(D-1)] out, or NULL
+ *   workspace >= afmg_adjoint_workspace_bytes
+ * Returns AFMG_OK, AFMG_NOT_CONVERGED, or an error.
+ */
+int afmg_adjoint(afmg_tree *tree, void *stream, const double *u_bar, double *rho_bar, double *bc_bar,
+                 void *workspace, size_t workspace_bytes, const afmg_opts *opts, afmg_stats *stats);
+
 /* Message for the last failing call on this thread. */
 const char *afmg_last_error(void);
 

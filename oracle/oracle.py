@@ -271,7 +271,9 @@ def adjoint(tree, ubar):
     (B b)_c = sum over the Dirichlet sides of c of 2 b / h^2."""
     import scipy.sparse.linalg as spla
     A = assemble_L(tree)
-    lam = spla.spsolve(A.T.tocsc(), np.ascontiguousarray(ubar, dtype=np.float64).ravel())
+    # minimum-degree ordering on A + A^T keeps the fill of 3D grids small
+    lu = spla.splu(A.T.tocsc(), permc_spec="MMD_AT_PLUS_A")
+    lam = lu.solve(np.ascontiguousarray(ubar, dtype=np.float64).ravel())
     return lam.reshape(tree.n_leaves, -1), boundary_gradient(tree, lam)
 
 

@@ -95,8 +95,9 @@ class BoxDesc(C.Structure):
 EXPORTS = [
     "afmg_default_opts", "afmg_tree_create", "afmg_tree_destroy", "afmg_tree_info",
     "afmg_tree_leaf_boxes", "afmg_tree_bfaces", "afmg_tree_box", "afmg_workspace_bytes",
-    "afmg_solve", "afmg_last_error",
+    "afmg_solve", "afmg_last_error", "afmg_adjoint_workspace_bytes", "afmg_apply", "afmg_adjoint",
 ]
+OPS = {"L": 0, "LT": 1}
 
 _lib = None
 
@@ -130,6 +131,9 @@ def lib():
         L.afmg_workspace_bytes.argtypes = [vp, C.POINTER(Opts), C.POINTER(C.c_size_t)]
         L.afmg_solve.argtypes = [vp, vp, vp, vp, vp, vp, C.c_size_t, C.POINTER(Opts), C.POINTER(Stats)]
         L.afmg_last_error.restype = C.c_char_p
+        L.afmg_adjoint_workspace_bytes.argtypes = [vp, C.POINTER(Opts), C.POINTER(C.c_size_t)]
+        L.afmg_apply.argtypes = [vp, vp, C.c_int, vp, vp, vp, C.c_size_t]
+        L.afmg_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, C.c_size_t, C.POINTER(Opts), C.POINTER(Stats)]
         _lib = L
     return _lib
 
@@ -199,6 +203,12 @@ class Tree:
         d = BoxDesc()
         _check(lib().afmg_tree_box(self._h, b, C.byref(d)))
         return dict(level=d.level, idx=tuple(d.idx), parent=d.parent, leaf=bool(d.leaf), nbr=tuple(d.nbr))
+
+    def adjoint_workspace_bytes(self, opts=None):
+        n = C.c_size_t()
+        _check(lib().afmg_adjoint_workspace_bytes(self._h, C.byref(opts) if opts is not None else None,
+                                                  C.byref(n)))
+        return n.value
 
     def workspace_bytes(self, opts=None):
         n = C.c_size_t()
@@ -286,3 +296,96 @@ def solve(tree: Tree, rho, bc=None, u=None, *, cycle="V", tol=1e-10, max_cycles=
     d = st.to_dict()
     d["rc"] = rc
     return u, d
+
+
+def _check_field(tree, t, name):
+    import torch
+    shape = (tree.n_boxes, tree.cells_per_box)
+    if t.device.type != "cuda" or t.dtype != torch.float64 or tuple(t.shape) != shape or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 device tensor {shape}")
+
+
+def apply(tree: Tree, x, op="L", workspace=None, stream=None):
+    """y = L x (op "L") or L^T x (op "LT") on the leaf cells, zero Dirichlet
+    values; x, y: float64 device tensors [n_boxes, N^D]."""
+    import torch
+    _check_field(tree, x, "x")
+    y = torch.empty_like(x)
+    nbytes = tree.adjoint_workspace_bytes()
+    if workspace is None or workspace.numel() * workspace.element_size() < nbytes:
+        workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=x.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(x.device)
+    with torch.cuda.device(x.device):
+        _check(lib().afmg_apply(tree.handle, C.c_void_p(stream.cuda_stream), OPS[op], _ptr(x), _ptr(y),
+                                _ptr(workspace), nbytes))
+    return y
+
+
+def adjoint(tree: Tree, u_bar, *, tol=1e-10, max_cycles=200, n_down=2, n_up=2, n_base=4, workspace=None,
+            stream=None, check=True):
+    """Gradients of a loss with respect to rho and the Dirichlet rows given
+    u_bar = dloss/du (float64 device [n_boxes, N^D]).  Returns (rho_bar,
+    bc_bar, stats)."""
+    import torch
+    _check_field(tree, u_bar, "u_bar")
+    dev = u_bar.device
+    rho_bar = torch.empty_like(u_bar)
+    bc_bar = torch.zeros((max(tree.n_bfaces, 1), tree.box_n ** (tree.dim - 1)), dtype=torch.float64, device=dev)
+    opts = make_opts("V", n_down, n_up, n_base, tol, max_cycles, 0, False, "fp64")
+    nbytes = tree.adjoint_workspace_bytes(opts)
+    if workspace is None or workspace.numel() * workspace.element_size() < nbytes:
+        workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    st = Stats()
+    with torch.cuda.device(dev):
+        rc = lib().afmg_adjoint(tree.handle, C.c_void_p(stream.cuda_stream), _ptr(u_bar.contiguous()),
+                                _ptr(rho_bar), _ptr(bc_bar) if tree.n_bfaces else None, _ptr(workspace), nbytes,
+                                C.byref(opts), C.byref(st))
+    if check:
+        _check(rc, allow=(AFMG_OK, AFMG_NOT_CONVERGED))
+    d = st.to_dict()
+    d["rc"] = rc
+    return rho_bar, bc_bar[: tree.n_bfaces], d
+
+
+def _autograd_function():
+    import torch
+
+    class PoissonSolve(torch.autograd.Function):
+        """u = L^-1 (rho - B b): forward = afmg_solve, backward = afmg_adjoint."""
+
+        @staticmethod
+        def forward(ctx, rho, bc, tree, opts):
+            u, st = solve(tree, rho.detach().contiguous(), None if bc is None else bc.detach().contiguous(),
+                          **opts)
+            ctx.tree = tree
+            ctx.opts = opts
+            ctx.has_bc = bc is not None
+            ctx.stats = st
+            return u
+
+        @staticmethod
+        def backward(ctx, u_bar):
+            o = ctx.opts
+            rho_bar, bc_bar, _ = adjoint(ctx.tree, u_bar.contiguous(), tol=o.get("tol", 1e-10),
+                                         max_cycles=max(o.get("max_cycles", 100), 200),
+                                         n_down=o.get("n_down", 2), n_up=o.get("n_up", 2),
+                                         n_base=o.get("n_base", 4))
+            return rho_bar, (bc_bar if ctx.has_bc else None), None, None
+
+    return PoissonSolve
+
+
+_PS = None
+
+
+def poisson_solve(tree: Tree, rho, bc=None, **opts):
+    """Differentiable solve: gradients flow to rho (leaf boxes) and to the
+    Dirichlet rows bc through the adjoint (one more multigrid solve on
+    uniform grids, preconditioned BiCGSTAB on L^T otherwise)."""
+    global _PS
+    if _PS is None:
+        _PS = _autograd_function()
+    return _PS.apply(rho, bc, tree, opts)

@@ -22,6 +22,8 @@ struct BoxInfo {
 static_assert(sizeof(BoxInfo) == 64, "BoxInfo must be 64 bytes");
 
 constexpr int FLAG_LEAF = 1;
+// bits 4..9: the same-level neighbour on side s is refined (a parent box)
+constexpr int FLAG_NBR_REFINED = 1 << 4;
 inline int oct_bit(int flags, int axis) { return (flags >> (1 + axis)) & 1; }
 
 // Host tree (built from leaves, immutable afterwards).
@@ -34,6 +36,8 @@ struct HostTree {
     std::vector<int32_t> ix, iy, iz;  // spatial index per box
     std::vector<int64_t> lvl_off;     // box range of level l: [lvl_off[l], lvl_off[l+1]), l = 0..lmax+1 (0 unused)
     std::vector<int32_t> leaf_box;    // box id of input leaf q
+    std::vector<int32_t> child;       // [n_boxes][8] child ids (octant bits x|y<<1|z<<2), -1 if none
+    bool uniform = true;              // all leaves on one level (the operator is symmetric)
     std::vector<int32_t> bface_box, bface_side;  // per Dirichlet row (leaf rows first)
     // parent rows to derive, per level (fine to coarse order is by level)
     int64_t level_begin(int l) const { return lvl_off[l]; }

@@ -59,6 +59,27 @@ template <int D, int N, typename T>
 void launch_load_rho(const BoxInfo *info, const T *src, T *dst, int64_t nb, hipStream_t st);
 template <int D, int N>
 void launch_bc_derive(const BoxInfo *info, int64_t b0, int64_t nb, double *bc, hipStream_t st);
+// adjoint support (FP64)
+constexpr int DOT_WGS = 1024;  // fixed grid of k_dot: deterministic sums
+template <int D, int N>
+void launch_apply_lt(const BoxInfo *info, const int *child, const double *y, double *out, int64_t nb,
+                     hipStream_t st);
+template <int D, int N>
+void launch_apply_l(const BoxInfo *info, const double *x, double *out, int64_t nb, hipStream_t st);
+template <int D, int N>
+void launch_restrict_field(const BoxInfo *info, double *f, int64_t b0, int64_t nb, hipStream_t st);
+template <int D, int N>
+void launch_push_down(const BoxInfo *info, double *f, int64_t b0, int64_t nb, hipStream_t st);
+template <int D, int N>
+void launch_scale_leaves(const BoxInfo *info, double *dst, const double *src, int pw, int64_t nb, hipStream_t st);
+template <int D, int N>
+void launch_store_leaves(const BoxInfo *info, const double *src, double *dst, int64_t nb, hipStream_t st);
+template <int D, int N>
+void launch_bc_grad(const BoxInfo *info, const double *lam, double *bc_bar, int64_t nb, hipStream_t st);
+// out[0] = max |a|, out[1] = sum a b (partial: DOT_WGS pairs)
+void launch_dot(const double *a, const double *b, int64_t n, double *partial, double *out, hipStream_t st);
+void launch_lc3(double *out, double a, const double *x, double b, const double *y, double c, const double *z,
+                int64_t n, hipStream_t st);
 template <typename T>
 void launch_copy(const T *src, T *dst, int64_t n, hipStream_t st);
 template <typename T>

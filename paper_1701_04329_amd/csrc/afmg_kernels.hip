@@ -698,7 +698,8 @@ __global__ __launch_bounds__(256) void k_final(LevelArgs<T> a, double *partial, 
 
 // One workgroup of 1024 threads: out[0] = max of the partial maxima, out[1] =
 // sqrt of the sum of the partial sums; the reduction order is fixed.
-__global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ partial, int64_t n, double *out) {
+__global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ partial, int64_t n, double *out,
+                                                 int root) {
     __shared__ double rm[1024], rsum[1024];
     double mx[4] = {0.0, 0.0, 0.0, 0.0}, ss[4] = {0.0, 0.0, 0.0, 0.0};
     int64_t i = threadIdx.x;
@@ -727,7 +728,7 @@ __global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ part
         // fmax drops NaN operands; the sum keeps them
         const double s = rsum[0];
         out[0] = (s == s) ? rm[0] : s;
-        out[1] = sqrt(s);
+        out[1] = root ? sqrt(s) : s;
     }
 }
 
@@ -1096,6 +1097,325 @@ __global__ __launch_bounds__(256) void k_coarse(CoarseArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
+// the composite operator and its transpose on leaf cells (adjoint)
+// ---------------------------------------------------------------------------
+// With homogeneous Dirichlet values the composite operator L is a sparse
+// matrix on the leaf cells; its rows are the stencil with the ghost formulas
+// written out (paper §2.4, §3.3).  On adaptive grids L is not symmetric: the
+// refinement-boundary ghost couples a fine face cell to the coarse cell
+// (1/2 uH / h^2) while the coarse cell sees the fine cells through the mean of
+// their parent (1/2^D / H^2), and the fine ghost also involves the partner and
+// the next inner cell.  k_apply_lt gathers, for every leaf cell c, the entries
+// L_rc y_r of all rows r that reference c:
+//   - in-box and same-level leaf neighbours: y_r / h^2, and -2D y_c / h^2;
+//   - a refined same-level neighbour: the 2^(D-1) fine face cells next to c
+//     reference c as their uH: 1/2 / (h/2)^2 = 2 / h^2 each;
+//   - a physical side: -y_c / h^2 (ghost -u_c);
+//   - a refinement side, c on the face layer: k1 y_c / h^2 (k1 = 1 in 2D, 5/4
+//     in 3D), -1/4 y / h^2 for each tangential partner (their ghosts use c),
+//     and the coarse cell R next to c's parent cell: y_R / (2^D (2h)^2);
+//   - a refinement side, c on the second layer: -1/4 y_f / h^2 for the face
+//     cell f in front (its ghost uses c as the inner cell) and y_R / (2^D (2h)^2).
+
+__device__ __forceinline__ double level_ih2(int N, int level) {
+    const double h = 1.0 / ((double)N * ldexp(1.0, level - 1));
+    return 1.0 / (h * h);
+}
+
+template <int D, int N, int S>
+__device__ __forceinline__ void coarse_cell(int flags, const int c[3], int q[3]) {
+    using SD = SideOf<S>;
+    q[SD::d] = SD::hi ? 0 : N - 1;
+    q[SD::t1] = obit(flags, SD::t1) * (N / 2) + (c[SD::t1] >> 1);
+    q[SD::t2] = D == 3 ? obit(flags, SD::t2) * (N / 2) + (c[SD::t2] >> 1) : 0;
+}
+
+// contribution to (L^T y)_c across side S, c on the face layer of S
+template <int D, int N, int S>
+__device__ double lt_face(const BoxInfo &bi, const int c[3], const double *s, const double *__restrict__ y,
+                          const int *__restrict__ child, double ih2) {
+    using SD = SideOf<S>;
+    using G = Geo<D, N>;
+    const int v = bi.nbr[S];
+    const double yc = s[padi<D, N>(c[0], c[1], c[2])];
+    if (v == -1) return -ih2 * yc;
+    if (v >= 0) {
+        if (!(bi.flags & (FLAG_NBR_REFINED << S))) {
+            int o[3] = {c[0], c[1], c[2]};
+            o[SD::d] = SD::hi ? 0 : N - 1;
+            return ih2 * y[(size_t)v * G::C + cpos<D, N>(o[0], o[1], o[2])];
+        }
+        double acc = 0.0;
+        for (int sub = 0; sub < (D == 3 ? 4 : 2); sub++) {
+            int f[3], bit[3];
+            const int g1 = 2 * c[SD::t1] + (sub & 1);
+            bit[SD::t1] = g1 / N;
+            f[SD::t1] = g1 % N;
+            if (D == 3) {
+                const int g2 = 2 * c[SD::t2] + (sub >> 1);
+                bit[SD::t2] = g2 / N;
+                f[SD::t2] = g2 % N;
+            } else {
+                bit[SD::t2] = 0;
+                f[SD::t2] = 0;
+            }
+            bit[SD::d] = SD::hi ? 0 : 1;
+            f[SD::d] = SD::hi ? 0 : N - 1;
+            const int oc = bit[0] | (bit[1] << 1) | (D == 3 ? bit[2] << 2 : 0);
+            const int ch = child[(size_t)v * 8 + oc];
+            acc += y[(size_t)ch * G::C + cpos<D, N>(f[0], f[1], f[2])];
+        }
+        return 2.0 * ih2 * acc;
+    }
+    int q[3];
+    coarse_cell<D, N, S>(bi.flags, c, q);
+    const double yR = y[(size_t)(-v - 2) * G::C + cpos<D, N>(q[0], q[1], q[2])];
+    int p1[3] = {c[0], c[1], c[2]};
+    p1[SD::t1] ^= 1;
+    double part = s[padi<D, N>(p1[0], p1[1], p1[2])];
+    if (D == 3) {
+        int p2[3] = {c[0], c[1], c[2]};
+        p2[SD::t2] ^= 1;
+        part += s[padi<D, N>(p2[0], p2[1], p2[2])];
+    }
+    const double k1 = D == 3 ? 1.25 : 1.0;
+    return k1 * ih2 * yc - 0.25 * ih2 * part + ih2 / (4.0 * (1 << D)) * yR;
+}
+
+// contribution across side S for c on the second layer of a refinement side
+template <int D, int N, int S>
+__device__ double lt_layer1(const BoxInfo &bi, const int c[3], const double *s, const double *__restrict__ y,
+                            double ih2) {
+    using SD = SideOf<S>;
+    using G = Geo<D, N>;
+    const int v = bi.nbr[S];
+    if (v > -2) return 0.0;
+    int f[3] = {c[0], c[1], c[2]};
+    f[SD::d] = SD::hi ? N - 1 : 0;
+    int q[3];
+    coarse_cell<D, N, S>(bi.flags, c, q);
+    const double yR = y[(size_t)(-v - 2) * G::C + cpos<D, N>(q[0], q[1], q[2])];
+    return -0.25 * ih2 * s[padi<D, N>(f[0], f[1], f[2])] + ih2 / (4.0 * (1 << D)) * yR;
+}
+
+// out = L^T y on leaf boxes (zero on parents); one launch for all boxes
+template <int D, int N>
+__global__ __launch_bounds__(256) void k_apply_lt(const BoxInfo *__restrict__ info, const int *__restrict__ child,
+                                                  const double *__restrict__ y, double *__restrict__ out, int nb) {
+    using G = Geo<D, N>;
+    __shared__ double sm[G::BPW * G::PC];
+    const Slot<D, N> sl = slot_of<D, N>(0, nb);
+    double *s = sm + sl.slot * G::PC;
+    const BoxInfo bi = load_box<D, N>(info, sl.b);
+    const bool leaf = bi.flags & FLAG_LEAF;
+    const size_t bo = (size_t)sl.b * G::C;
+    Stager<D, N, double> st;
+    if (sl.valid && leaf) st.begin(s, bi, y + bo, y, nullptr, 1, sl.t, false);
+    __syncthreads();
+    if (!sl.valid) return;
+    int j, k;
+    row_of<D, N>(sl.t, j, k);
+    if (!leaf) {
+        for (int i = 0; i < N; i++) out[bo + cpos<D, N>(i, j, k)] = 0.0;
+        return;
+    }
+    const double ih2 = level_ih2(N, bi.level);
+    for (int i = 0; i < N; i++) {
+        const int c[3] = {i, j, k};
+        const double yc = s[padi<D, N>(i, j, k)];
+        double nbs = 0.0;
+        if (i > 0) nbs += s[padi<D, N>(i - 1, j, k)];
+        if (i < N - 1) nbs += s[padi<D, N>(i + 1, j, k)];
+        if (j > 0) nbs += s[padi<D, N>(i, j - 1, k)];
+        if (j < N - 1) nbs += s[padi<D, N>(i, j + 1, k)];
+        if (D == 3) {
+            if (k > 0) nbs += s[padi<D, N>(i, j, k - 1)];
+            if (k < N - 1) nbs += s[padi<D, N>(i, j, k + 1)];
+        }
+        double acc = ih2 * (nbs - 2.0 * D * yc);
+        if (i == 0) acc += lt_face<D, N, 0>(bi, c, s, y, child, ih2);
+        if (i == N - 1) acc += lt_face<D, N, 1>(bi, c, s, y, child, ih2);
+        if (i == 1) acc += lt_layer1<D, N, 0>(bi, c, s, y, ih2);
+        if (i == N - 2) acc += lt_layer1<D, N, 1>(bi, c, s, y, ih2);
+        if (j == 0) acc += lt_face<D, N, 2>(bi, c, s, y, child, ih2);
+        if (j == N - 1) acc += lt_face<D, N, 3>(bi, c, s, y, child, ih2);
+        if (j == 1) acc += lt_layer1<D, N, 2>(bi, c, s, y, ih2);
+        if (j == N - 2) acc += lt_layer1<D, N, 3>(bi, c, s, y, ih2);
+        if (D == 3) {
+            if (k == 0) acc += lt_face<D, N, 4>(bi, c, s, y, child, ih2);
+            if (k == N - 1) acc += lt_face<D, N, 5>(bi, c, s, y, child, ih2);
+            if (k == 1) acc += lt_layer1<D, N, 4>(bi, c, s, y, ih2);
+            if (k == N - 2) acc += lt_layer1<D, N, 5>(bi, c, s, y, ih2);
+        }
+        out[bo + cpos<D, N>(i, j, k)] = acc;
+    }
+}
+
+// out = L x on leaf boxes (zero on parents), homogeneous Dirichlet values; x
+// must hold the restriction of its leaf values on parent boxes
+template <int D, int N>
+__global__ __launch_bounds__(256) void k_apply_l(const BoxInfo *__restrict__ info, const double *__restrict__ x,
+                                                 double *__restrict__ out, int nb) {
+    using G = Geo<D, N>;
+    __shared__ double sm[G::BPW * G::PC];
+    const Slot<D, N> sl = slot_of<D, N>(0, nb);
+    double *s = sm + sl.slot * G::PC;
+    const BoxInfo bi = load_box<D, N>(info, sl.b);
+    const bool leaf = bi.flags & FLAG_LEAF;
+    const size_t bo = (size_t)sl.b * G::C;
+    Stager<D, N, double> st;
+    if (sl.valid && leaf) st.begin(s, bi, x + bo, x, nullptr, 1, sl.t, true);
+    __syncthreads();
+    if (sl.valid && leaf) st.end(s, sl.t);
+    __syncthreads();
+    if (!sl.valid) return;
+    const double ih2 = level_ih2(N, bi.level);
+    for (int e = sl.t; e < G::C; e += G::TPB) {
+        int i, j, k;
+        cell_of<D, N>(e, i, j, k);
+        out[bo + e] = leaf ? (nb_sum<D, N, double>(s, i, j, k) - 2.0 * D * s[padi<D, N>(i, j, k)]) * ih2 : 0.0;
+    }
+}
+
+// restriction of field f into the parents of the boxes of one level
+template <int D, int N>
+__global__ __launch_bounds__(256) void k_restrict_field(const BoxInfo *__restrict__ info, double *f, int64_t b0,
+                                                        int nb) {
+    using G = Geo<D, N>;
+    __shared__ double sm[G::BPW * G::C];
+    const Slot<D, N> sl = slot_of<D, N>(b0, nb);
+    double *s = sm + sl.slot * G::C;
+    const BoxInfo bi = load_box<D, N>(info, sl.b);
+    const size_t bo = (size_t)sl.b * G::C;
+    if (sl.valid) {
+        for (int e = sl.t; e < G::C; e += G::TPB) {
+            int i, j, k;
+            cell_of<D, N>(e, i, j, k);
+            s[D == 3 ? i + N * (j + N * k) : i + N * j] = f[bo + e];
+        }
+    }
+    __syncthreads();
+    if (sl.valid) restrict_octant<D, N, double, false>(s, f, bi, sl.t);
+}
+
+// transpose of the restriction for the boxes of one level: each cell adds
+// 1/2^D of its parent cell (run from coarse to fine, so that values on parent
+// boxes reach the leaves)
+template <int D, int N>
+__global__ __launch_bounds__(256) void k_push_down(const BoxInfo *__restrict__ info, double *f, int64_t b0,
+                                                   int nb) {
+    using G = Geo<D, N>;
+    const Slot<D, N> sl = slot_of<D, N>(b0, nb);
+    if (!sl.valid) return;
+    const BoxInfo bi = load_box<D, N>(info, sl.b);
+    if (bi.parent < 0) return;
+    const size_t bo = (size_t)sl.b * G::C, po = (size_t)bi.parent * G::C;
+    const double w = D == 3 ? 0.125 : 0.25;
+    for (int e = sl.t; e < G::C; e += G::TPB) {
+        int i, j, k;
+        cell_of<D, N>(e, i, j, k);
+        const int X = obit(bi.flags, 0) * G::H + (i >> 1), Y = obit(bi.flags, 1) * G::H + (j >> 1),
+                  Z = D == 3 ? obit(bi.flags, 2) * G::H + (k >> 1) : 0;
+        f[bo + e] += w * f[po + cpos<D, N>(X, Y, Z)];
+    }
+}
+
+// per-workgroup (max |a|, sum a b) over n elements with a fixed grid, in a
+// fixed order; reduced by k_reduce
+__global__ __launch_bounds__(256) void k_dot(const double *__restrict__ a, const double *__restrict__ b,
+                                             int64_t n, double *__restrict__ partial) {
+    __shared__ double rm[256], rs[256];
+    double mx = 0.0, ss = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        mx = fmax(mx, fabs(a[i]));
+        ss += a[i] * b[i];
+    }
+    rm[threadIdx.x] = mx;
+    rs[threadIdx.x] = ss;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            rm[threadIdx.x] = fmax(rm[threadIdx.x], rm[threadIdx.x + w]);
+            rs[threadIdx.x] += rs[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = rm[0];
+        partial[2 * blockIdx.x + 1] = rs[0];
+    }
+}
+
+// out = a x + b y + c z (y, z may be null)
+__global__ __launch_bounds__(256) void k_lc3(double *out, double a, const double *x, double b, const double *y,
+                                             double c, const double *z, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        double v = a * x[i];
+        if (y) v += b * y[i];
+        if (z) v += c * z[i];
+        out[i] = v;
+    }
+}
+
+// dst = (h^D)^pw src on leaf boxes (pw in {-1, 0, 1}), 0 on parent boxes
+template <int D, int N>
+__global__ __launch_bounds__(256) void k_scale_leaves(const BoxInfo *__restrict__ info, double *dst,
+                                                      const double *src, int pw, int nb) {
+    using G = Geo<D, N>;
+    const Slot<D, N> sl = slot_of<D, N>(0, nb);
+    if (!sl.valid) return;
+    const BoxInfo bi = load_box<D, N>(info, sl.b);
+    const bool leaf = bi.flags & FLAG_LEAF;
+    const double h = 1.0 / ((double)N * ldexp(1.0, bi.level - 1));
+    const double hD = D == 3 ? h * h * h : h * h;
+    const double f = pw > 0 ? hD : (pw < 0 ? 1.0 / hD : 1.0);
+    const size_t bo = (size_t)sl.b * G::C;
+    for (int e = sl.t; e < G::C; e += G::TPB) dst[bo + e] = leaf ? f * src[bo + e] : 0.0;
+}
+
+// natural-order copy of the leaf boxes of src (colour-split) into dst; parent
+// boxes of dst are zeroed
+template <int D, int N>
+__global__ __launch_bounds__(256) void k_store_leaves(const BoxInfo *__restrict__ info,
+                                                      const double *__restrict__ src, double *__restrict__ dst,
+                                                      int nb) {
+    using G = Geo<D, N>;
+    const Slot<D, N> sl = slot_of<D, N>(0, nb);
+    if (!sl.valid) return;
+    const bool leaf = load_box<D, N>(info, sl.b).flags & FLAG_LEAF;
+    const size_t bo = (size_t)sl.b * G::C;
+    for (int e = sl.t; e < G::C; e += G::TPB) {
+        int i, j, k;
+        cell_of<D, N>(e, i, j, k);
+        dst[bo + (D == 3 ? i + N * (j + N * k) : i + N * j)] = leaf ? src[bo + e] : 0.0;
+    }
+}
+
+// gradient with respect to the Dirichlet rows of the leaves:
+// d loss / d b_f = -2 lambda_c(f) / h^2 (the boundary part of the rhs is
+// 2 b / h^2 per Dirichlet side of a cell)
+template <int D, int N>
+__global__ __launch_bounds__(256) void k_bc_grad(const BoxInfo *__restrict__ info, const double *__restrict__ lam,
+                                                 double *__restrict__ bc_bar, int nb) {
+    using G = Geo<D, N>;
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= (int64_t)nb * 2 * D * G::F) return;
+    const int64_t b = g / (2 * D * G::F);
+    const int rem = (int)(g % (2 * D * G::F));
+    const int side = rem / G::F, m = rem % G::F;
+    const BoxInfo *bi = info + b;
+    if (!(bi->flags & FLAG_LEAF) || bi->nbr[side] != -1) return;
+    const int d = side >> 1, hi = side & 1;
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    int x[3];
+    x[t1] = m % N;
+    x[t2] = D == 3 ? m / N : 0;
+    x[d] = hi ? N - 1 : 0;
+    const double ih2 = level_ih2(N, bi->level);
+    bc_bar[(size_t)bi->bcoff[side] * G::F + m] = -2.0 * ih2 * lam[(size_t)b * G::C + cpos<D, N>(x[0], x[1], x[2])];
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 template <int D, int N>
@@ -1138,7 +1458,7 @@ template <int D, int N>
 int final_wgs(int64_t nb) { return wg_count<D, N>(nb); }
 
 void launch_reduce(const double *partial, int64_t n, double *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, partial, n, out);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, partial, n, out, 1);
 }
 
 template <int D, int N, typename T>
@@ -1181,6 +1501,70 @@ void launch_fill(T *dst, int64_t n, T v, hipStream_t st) {
     if (g > 65536) g = 65536;
     hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)g), dim3(256), 0, st, dst, n, v);
 }
+
+template <int D, int N>
+void launch_apply_lt(const BoxInfo *info, const int *child, const double *y, double *out, int64_t nb,
+                     hipStream_t st) {
+    const int g = wg_count<D, N>(nb);
+    AFMG_LAUNCH((k_apply_lt<D, N>), g, st, info, child, y, out, (int)nb);
+}
+template <int D, int N>
+void launch_apply_l(const BoxInfo *info, const double *x, double *out, int64_t nb, hipStream_t st) {
+    const int g = wg_count<D, N>(nb);
+    AFMG_LAUNCH((k_apply_l<D, N>), g, st, info, x, out, (int)nb);
+}
+template <int D, int N>
+void launch_restrict_field(const BoxInfo *info, double *f, int64_t b0, int64_t nb, hipStream_t st) {
+    const int g = wg_count<D, N>(nb);
+    AFMG_LAUNCH((k_restrict_field<D, N>), g, st, info, f, b0, (int)nb);
+}
+template <int D, int N>
+void launch_push_down(const BoxInfo *info, double *f, int64_t b0, int64_t nb, hipStream_t st) {
+    const int g = wg_count<D, N>(nb);
+    AFMG_LAUNCH((k_push_down<D, N>), g, st, info, f, b0, (int)nb);
+}
+template <int D, int N>
+void launch_scale_leaves(const BoxInfo *info, double *dst, const double *src, int pw, int64_t nb, hipStream_t st) {
+    const int g = wg_count<D, N>(nb);
+    AFMG_LAUNCH((k_scale_leaves<D, N>), g, st, info, dst, src, pw, (int)nb);
+}
+template <int D, int N>
+void launch_store_leaves(const BoxInfo *info, const double *src, double *dst, int64_t nb, hipStream_t st) {
+    const int g = wg_count<D, N>(nb);
+    AFMG_LAUNCH((k_store_leaves<D, N>), g, st, info, src, dst, (int)nb);
+}
+template <int D, int N>
+void launch_bc_grad(const BoxInfo *info, const double *lam, double *bc_bar, int64_t nb, hipStream_t st) {
+    using G = Geo<D, N>;
+    const int64_t work = nb * 2 * D * G::F;
+    const int g = (int)((work + 255) / 256);
+    AFMG_LAUNCH((k_bc_grad<D, N>), g, st, info, lam, bc_bar, (int)nb);
+}
+void launch_dot(const double *a, const double *b, int64_t n, double *partial, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_dot, dim3(DOT_WGS), dim3(256), 0, st, a, b, n, partial);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, partial, (int64_t)DOT_WGS, out, 0);
+}
+void launch_lc3(double *out, double a, const double *x, double b, const double *y, double c, const double *z,
+                int64_t n, hipStream_t st) {
+    int64_t g = (n + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_lc3, dim3((unsigned)g), dim3(256), 0, st, out, a, x, b, y, c, z, n);
+}
+
+#define AFMG_ADJ_INST(D, N)                                                                          \
+    template void launch_apply_lt<D, N>(const BoxInfo *, const int *, const double *, double *, int64_t, \
+                                        hipStream_t);                                                \
+    template void launch_apply_l<D, N>(const BoxInfo *, const double *, double *, int64_t, hipStream_t); \
+    template void launch_restrict_field<D, N>(const BoxInfo *, double *, int64_t, int64_t, hipStream_t);   \
+    template void launch_push_down<D, N>(const BoxInfo *, double *, int64_t, int64_t, hipStream_t);        \
+    template void launch_scale_leaves<D, N>(const BoxInfo *, double *, const double *, int, int64_t,       \
+                                            hipStream_t);                                             \
+    template void launch_store_leaves<D, N>(const BoxInfo *, const double *, double *, int64_t,            \
+                                            hipStream_t);                                             \
+    template void launch_bc_grad<D, N>(const BoxInfo *, const double *, double *, int64_t, hipStream_t);
+
+AFMG_ADJ_INST(2, 8)
+AFMG_ADJ_INST(3, 8)
 
 #define AFMG_INST(D, N, T)                                                                              \
     template void launch_level<D, N, T>(Op, const LevelArgs<T> &, int, hipStream_t);                     \

@@ -29,6 +29,7 @@ struct afmg_tree {
     HostTree h;
     int device = -1;
     BoxInfo *d_info = nullptr;
+    int32_t *d_child = nullptr;      // [n_boxes][8] child ids (adjoint)
     double *h_norm = nullptr;        // pinned host copy of the two norms
     std::vector<int64_t> part_off;   // first k_final partial of each level
     int64_t n_parts = 0;
@@ -108,6 +109,10 @@ int bind_device(afmg_tree *t) {
     if (e != hipSuccess) return fail(AFMG_ERR_OOM, "hipMalloc of the box table failed");
     e = hipMemcpy(t->d_info, h.info.data(), sizeof(BoxInfo) * (size_t)h.n_boxes, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "upload of the box table");
+    e = hipMalloc(&t->d_child, sizeof(int32_t) * 8 * (size_t)h.n_boxes);
+    if (e != hipSuccess) return fail(AFMG_ERR_OOM, "hipMalloc of the child table failed");
+    e = hipMemcpy(t->d_child, h.child.data(), sizeof(int32_t) * 8 * (size_t)h.n_boxes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "upload of the child table");
     e = hipHostMalloc(&t->h_norm, 2 * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) return fail(AFMG_ERR_OOM, "hipHostMalloc failed");
     t->device = dev;
@@ -411,6 +416,208 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
     return status;
 }
 
+// ---------------------------------------------------------------------------
+// operator application and the adjoint solve
+// ---------------------------------------------------------------------------
+struct AdjLayout {
+    // Krylov vectors and preconditioner arrays, each [n_boxes][N^D] FP64
+    enum { X, R, RH, P, V, SV, T, PH, SH, B, PU, PRHO, NVEC };
+    size_t vec[NVEC];
+    size_t puold, bc, partial, norm, total;
+};
+
+AdjLayout adj_layout(const afmg_tree *t) {
+    const HostTree &h = t->h;
+    const size_t C = (size_t)cells_per_box(h.dim), F = (size_t)cells_per_face(h.dim);
+    const size_t nb = (size_t)h.n_boxes, nlt = (size_t)h.n_below_lmax();
+    AdjLayout L{};
+    size_t off = 0;
+    for (int v = 0; v < AdjLayout::NVEC; v++) {
+        L.vec[v] = off;
+        off = align256(off + nb * C * sizeof(double));
+    }
+    L.puold = off; off = align256(off + nlt * C * sizeof(double));
+    L.bc = off; off = align256(off + (size_t)std::max<int64_t>(1, h.n_bfaces_all) * F * sizeof(double));
+    const size_t np = (size_t)std::max<int64_t>(t->n_parts, DOT_WGS);
+    L.partial = off; off = align256(off + np * 2 * sizeof(double));
+    L.norm = off; off = align256(off + 2 * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+template <int D>
+struct Adj {
+    afmg_tree *t;
+    const HostTree &h;
+    hipStream_t st;
+    char *ws;
+    AdjLayout L;
+    int64_t n;  // values per field
+    double *partial, *norm;
+
+    double *vec(int v) const { return (double *)(ws + L.vec[v]); }
+
+    // (max |a|, sum a b) over all cells; synchronises the stream
+    int dot(const double *a, const double *b, double &mx, double &sum) {
+        launch_dot(a, b, n, partial, norm, st);
+        hipError_t e = hipMemcpyAsync(t->h_norm, norm, 2 * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "dot product");
+        mx = t->h_norm[0];
+        sum = t->h_norm[1];
+        return AFMG_OK;
+    }
+    void apply_lt(const double *y, double *out) {
+        launch_apply_lt<D, BOX_N>(t->d_info, t->d_child, y, out, h.n_boxes, st);
+    }
+    // x must be zero on parents; its restriction is written there first
+    void apply_l(double *x, double *out) {
+        for (int l = h.lmax; l >= 2; l--)
+            launch_restrict_field<D, BOX_N>(t->d_info, x, h.lvl_off[(size_t)l], h.level_count(l), st);
+        launch_apply_l<D, BOX_N>(t->d_info, x, out, h.n_boxes, st);
+    }
+};
+
+template <int D>
+int apply_op(afmg_tree *t, hipStream_t st, int op, const double *x, double *y, char *ws) {
+    const HostTree &h = t->h;
+    Adj<D> A{t, h, st, ws, adj_layout(t), h.n_boxes * cells_per_box(D), nullptr, nullptr};
+    double *X = A.vec(AdjLayout::X), *Y = A.vec(AdjLayout::R);
+    launch_fill<double>(X, A.n, 0.0, st);
+    launch_load_rho<D, BOX_N, double>(t->d_info, x, X, h.n_boxes, st);
+    if (op == AFMG_OP_L) A.apply_l(X, Y);
+    else A.apply_lt(X, Y);
+    launch_store_leaves<D, BOX_N>(t->d_info, Y, y, h.n_boxes, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "operator application");
+    return AFMG_OK;
+}
+
+// lambda = L^-T ubar on the leaf cells; rho_bar = lambda, bc_bar = -2 lambda / h^2
+// on the leaf cells next to the Dirichlet rows.
+template <int D>
+int adjoint(afmg_tree *t, hipStream_t st, const double *ubar, double *rho_bar, double *bc_bar, char *ws,
+            const afmg_opts &o, afmg_stats &S) {
+    const HostTree &h = t->h;
+    Adj<D> A{t, h, st, ws, adj_layout(t), h.n_boxes * cells_per_box(D), nullptr, nullptr};
+    A.partial = (double *)(ws + A.L.partial);
+    A.norm = (double *)(ws + A.L.norm);
+    double *X = A.vec(AdjLayout::X), *B = A.vec(AdjLayout::B);
+    double *bcz = (double *)(ws + A.L.bc);
+    const int64_t n = A.n, F = cells_per_face(D);
+    hipEvent_t ev0, ev1;
+    (void)hipEventCreate(&ev0);
+    (void)hipEventCreate(&ev1);
+    (void)hipEventRecord(ev0, st);
+    // u_bar in the working layout; values on parent boxes (the restriction of
+    // the leaves) are pushed to the leaves through the transposed restriction
+    launch_copy<double>(ubar, B, n, st);
+    launch_permute<D, BOX_N, double>(t->d_info, B, 0, h.n_boxes, 1, 0, st);
+    for (int l = 2; l <= h.lmax; l++)
+        launch_push_down<D, BOX_N>(t->d_info, B, h.lvl_off[(size_t)l], h.level_count(l), st);
+    launch_scale_leaves<D, BOX_N>(t->d_info, B, B, 0, h.n_boxes, st);
+    launch_fill<double>(bcz, std::max<int64_t>(1, h.n_bfaces_all) * F, 0.0, st);
+    launch_fill<double>(X, n, 0.0, st);
+    Solver<D> s(t, st, o, &S);
+    s.partial = A.partial;
+    s.norm = A.norm;
+    int status = AFMG_OK, rc;
+    if (h.uniform) {
+        // the operator is symmetric: lambda solves L lambda = ubar with zero
+        // Dirichlet values, one more multigrid solve
+        s.base = LevelArgs<double>{t->d_info, X, B, (double *)(ws + A.L.puold), bcz, 0, 0, 1, 0.0, 0.0};
+        Cycler<D, double> cy{h, st, o, s.prof, s.base, nullptr};
+        rc = s.finalize(S.r0_max, S.r0_l2, nullptr);
+        if (rc != AFMG_OK) return rc;
+        S.r_max = S.r0_max;
+        S.r_l2 = S.r0_l2;
+        status = iterate(o, S, [&](int) {
+            cy.vcycle(h.lmax);
+            return s.finalize(S.r_max, S.r_l2, nullptr);
+        });
+    } else {
+        // L^T = V L* V^-1 with V = diag(h^D) and L* close to L away from
+        // refinement boundaries, so M = V Vcycle(V^-1 .) approximates L^-T:
+        // BiCGSTAB on L^T lambda = ubar, right-preconditioned with M
+        double *R = A.vec(AdjLayout::R), *RH = A.vec(AdjLayout::RH), *P = A.vec(AdjLayout::P);
+        double *Vv = A.vec(AdjLayout::V), *SV = A.vec(AdjLayout::SV), *T = A.vec(AdjLayout::T);
+        double *PH = A.vec(AdjLayout::PH), *SH = A.vec(AdjLayout::SH);
+        double *PU = A.vec(AdjLayout::PU), *PRHO = A.vec(AdjLayout::PRHO);
+        LevelArgs<double> pb{t->d_info, PU, PRHO, (double *)(ws + A.L.puold), bcz, 0, 0, 1, 0.0, 0.0};
+        Cycler<D, double> cy{h, st, o, s.prof, pb, nullptr};
+        auto precond = [&](const double *in, double *out) {
+            launch_scale_leaves<D, BOX_N>(t->d_info, PRHO, in, -1, h.n_boxes, st);
+            launch_fill<double>(PU, n, 0.0, st);
+            cy.vcycle(h.lmax);
+            launch_scale_leaves<D, BOX_N>(t->d_info, out, PU, +1, h.n_boxes, st);
+        };
+        launch_copy<double>(B, R, n, st);
+        launch_copy<double>(B, RH, n, st);
+        launch_fill<double>(P, n, 0.0, st);
+        launch_fill<double>(Vv, n, 0.0, st);
+        double mx, sum;
+        if ((rc = A.dot(R, R, mx, sum)) != AFMG_OK) return rc;
+        S.r0_max = mx;
+        S.r0_l2 = std::sqrt(sum);
+        S.r_max = mx;
+        S.r_l2 = S.r0_l2;
+        double rho_old = 1.0, alpha = 1.0, omega = 1.0;
+        status = iterate(o, S, [&](int) -> int {
+            double rho_new, dummy;
+            int q;
+            if ((q = A.dot(RH, R, dummy, rho_new)) != AFMG_OK) return q;
+            if (rho_new == 0.0) return fail(AFMG_ERR_DIVERGED, "BiCGSTAB breakdown (rho = 0)");
+            const double beta = (rho_new / rho_old) * (alpha / omega);
+            launch_lc3(P, 1.0, R, beta, P, -beta * omega, Vv, n, st);
+            precond(P, PH);
+            A.apply_lt(PH, Vv);
+            double rv;
+            if ((q = A.dot(RH, Vv, dummy, rv)) != AFMG_OK) return q;
+            if (rv == 0.0) return fail(AFMG_ERR_DIVERGED, "BiCGSTAB breakdown (r.v = 0)");
+            alpha = rho_new / rv;
+            launch_lc3(SV, 1.0, R, -alpha, Vv, 0.0, nullptr, n, st);
+            precond(SV, SH);
+            A.apply_lt(SH, T);
+            double tt, ts;
+            if ((q = A.dot(T, T, dummy, tt)) != AFMG_OK) return q;
+            if ((q = A.dot(T, SV, dummy, ts)) != AFMG_OK) return q;
+            omega = tt > 0.0 ? ts / tt : 0.0;
+            launch_lc3(X, 1.0, X, alpha, PH, omega, SH, n, st);
+            launch_lc3(R, 1.0, SV, -omega, T, 0.0, nullptr, n, st);
+            double rs;
+            if ((q = A.dot(R, R, S.r_max, rs)) != AFMG_OK) return q;
+            S.r_l2 = std::sqrt(rs);
+            rho_old = rho_new;
+            if (omega == 0.0) return fail(AFMG_ERR_DIVERGED, "BiCGSTAB breakdown (omega = 0)");
+            return AFMG_OK;
+        });
+        if (status < 0 && status != AFMG_ERR_NONFINITE && status != AFMG_ERR_DIVERGED) return status;
+        // true residual of the result
+        A.apply_lt(X, T);
+        launch_lc3(T, 1.0, B, -1.0, T, 0.0, nullptr, n, st);
+        double tmx, tsum;
+        if ((rc = A.dot(T, T, tmx, tsum)) != AFMG_OK) return rc;
+        S.r_max = tmx;
+        S.r_l2 = std::sqrt(tsum);
+    }
+    if (status < 0 && status != AFMG_ERR_NONFINITE && status != AFMG_ERR_DIVERGED) return status;
+    launch_store_leaves<D, BOX_N>(t->d_info, X, rho_bar, h.n_boxes, st);
+    if (bc_bar && h.n_bfaces_leaf > 0) launch_bc_grad<D, BOX_N>(t->d_info, X, bc_bar, h.n_boxes, st);
+    (void)hipEventRecord(ev1, st);
+    (void)hipEventSynchronize(ev1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ev0, ev1);
+    S.t_ms = ms;
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "adjoint");
+    S.status = status;
+    if (status == AFMG_NOT_CONVERGED) set_error("max_cycles reached before the tolerance");
+    if (status == AFMG_ERR_NONFINITE) set_error("residual norm is not finite");
+    return status;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -457,6 +664,7 @@ int afmg_tree_create(int dim, int box_n, int64_t n_leaves, const int32_t *level,
 void afmg_tree_destroy(afmg_tree *t) {
     if (!t) return;
     if (t->d_info) (void)hipFree(t->d_info);
+    if (t->d_child) (void)hipFree(t->d_child);
     if (t->h_norm) (void)hipHostFree(t->h_norm);
     for (auto ev : t->events) (void)hipEventDestroy(ev);
     delete t;
@@ -514,6 +722,45 @@ int afmg_workspace_bytes(const afmg_tree *t, const afmg_opts *o, size_t *bytes) 
     }
     *bytes = ws_layout(t, o ? o->precision : AFMG_FP64).total;
     return AFMG_OK;
+}
+
+int afmg_adjoint_workspace_bytes(const afmg_tree *t, const afmg_opts *o, size_t *bytes) {
+    if (!t || !bytes) return fail(AFMG_ERR_ARG, "null argument");
+    if (o) {
+        int rc = check_opts(o);
+        if (rc != AFMG_OK) return rc;
+    }
+    *bytes = adj_layout(t).total;
+    return AFMG_OK;
+}
+
+int afmg_apply(afmg_tree *t, void *stream, int op, const double *x, double *y, void *workspace,
+               size_t workspace_bytes) {
+    if (!t || !x || !y || !workspace) return fail(AFMG_ERR_ARG, "null argument");
+    if (op != AFMG_OP_L && op != AFMG_OP_LT) return fail(AFMG_ERR_ARG, "bad operator");
+    if (!aligned(x, 8) || !aligned(y, 8) || !aligned(workspace, 256)) return fail(AFMG_ERR_ARG, "misaligned array");
+    if (workspace_bytes < adj_layout(t).total) return fail(AFMG_ERR_ARG, "workspace too small");
+    int rc = bind_device(t);
+    if (rc != AFMG_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (t->h.dim == 3) return apply_op<3>(t, st, op, x, y, (char *)workspace);
+    return apply_op<2>(t, st, op, x, y, (char *)workspace);
+}
+
+int afmg_adjoint(afmg_tree *t, void *stream, const double *u_bar, double *rho_bar, double *bc_bar,
+                 void *workspace, size_t workspace_bytes, const afmg_opts *opts, afmg_stats *stats) {
+    if (!t || !u_bar || !rho_bar || !workspace || !stats) return fail(AFMG_ERR_ARG, "null argument");
+    int rc = check_opts(opts);
+    if (rc != AFMG_OK) return rc;
+    if (!aligned(u_bar, 8) || !aligned(rho_bar, 8) || (bc_bar && !aligned(bc_bar, 8)) || !aligned(workspace, 256))
+        return fail(AFMG_ERR_ARG, "misaligned array");
+    if (workspace_bytes < adj_layout(t).total) return fail(AFMG_ERR_ARG, "workspace too small");
+    std::memset(stats, 0, sizeof(*stats));
+    rc = bind_device(t);
+    if (rc != AFMG_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (t->h.dim == 3) return adjoint<3>(t, st, u_bar, rho_bar, bc_bar, (char *)workspace, *opts, *stats);
+    return adjoint<2>(t, st, u_bar, rho_bar, bc_bar, (char *)workspace, *opts, *stats);
 }
 
 int afmg_solve(afmg_tree *t, void *stream, const double *rho, const double *bc, double *u,

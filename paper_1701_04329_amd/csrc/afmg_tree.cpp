@@ -169,6 +169,23 @@ int build_tree(int dim, int N, int64_t n_leaves, const int32_t *level, const int
             bi.nbr[s] = -2 - (int32_t)newid[(size_t)itp->second];
         }
     }
+    // children, refined same-level neighbours, uniformity
+    t.child.assign((size_t)nb * 8, -1);
+    for (int64_t m = 0; m < nb; m++) {
+        const BoxInfo &bi = t.info[(size_t)m];
+        if (bi.parent >= 0) {
+            const int oc = ((bi.flags >> 1) & 1) | (((bi.flags >> 2) & 1) << 1) | (((bi.flags >> 3) & 1) << 2);
+            t.child[(size_t)bi.parent * 8 + oc] = (int32_t)m;
+        }
+    }
+    for (int64_t m = 0; m < nb; m++) {
+        BoxInfo &bi = t.info[(size_t)m];
+        if ((bi.flags & FLAG_LEAF) && bi.level != t.lmax) t.uniform = false;
+        for (int s = 0; s < 2 * dim; s++) {
+            const int v = bi.nbr[s];
+            if (v >= 0 && !(t.info[(size_t)v].flags & FLAG_LEAF)) bi.flags |= FLAG_NBR_REFINED << s;
+        }
+    }
     // Dirichlet rows: leaf sides first (box order, side order), then parents
     t.bface_box.clear();
     t.bface_side.clear();
