@@ -44,6 +44,7 @@ extern "C" {
 #endif
 
 typedef struct afmg_tree afmg_tree;
+typedef struct afmg_batch afmg_batch;
 
 typedef enum {
     AFMG_OK = 0,
@@ -75,6 +76,9 @@ typedef struct {
     int precision;    /* AFMG_FP64 (default) or AFMG_MIXED */
     int profile;      /* 1: time the finest-level kernels with HIP events
                          (stats.prof_*); adds one event pair per launch */
+    int graph;        /* 1: record the repeated cycle (V-cycle, refinement
+                         update, residual) once as a HIP graph and replay it;
+                         ignored while profiling.  Results are identical. */
 } afmg_opts;
 
 /* kernel classes timed when opts.profile is set (finest level only) */
@@ -208,6 +212,54 @@ int afmg_apply(afmg_tree *tree, void *stream, int op, const double *x, double *y
  */
 int afmg_adjoint(afmg_tree *tree, void *stream, const double *u_bar, double *rho_bar, double *bc_bar,
                  void *workspace, size_t workspace_bytes, const afmg_opts *opts, afmg_stats *stats);
+
+/*
+ * Batches: many independent trees of one dimension solved together.
+ *
+ * The paper parallelises the loops over the boxes of one level (§2.6).  A
+ * batch extends each such loop over the boxes of that level of every tree:
+ * the boxes of all trees form one list ordered by level, then tree, then
+ * Morton index, and every kernel of the cycle (§3.2) runs once per level for
+ * all trees.  Each tree still follows exactly the iteration afmg_solve runs on
+ * it alone (same kernels and arithmetic, its own stop test): trees that have
+ * stopped are masked out of later cycles, and an FMG step at level l involves
+ * only trees that reach level l.  The solution of each tree is therefore
+ * identical to its afmg_solve result.
+ */
+typedef struct {
+    int dim, box_n, n_trees;
+    int lmax;            /* finest level over all trees */
+    int64_t n_boxes;     /* sum of the trees' n_boxes (the caller's layout) */
+    int64_t n_bfaces;    /* sum of the trees' n_bfaces */
+    int64_t n_unknowns;  /* sum of the trees' leaf cells */
+} afmg_batch_desc;
+
+/*
+ * Group n_trees >= 1 trees of the same dim and box_n.  Their topology is
+ * copied: the trees may be destroyed afterwards.  Host-only.  Errors:
+ * AFMG_ERR_ARG (null, empty, mixed dimensions), AFMG_ERR_OOM.
+ */
+int afmg_batch_create(afmg_tree *const *trees, int n_trees, afmg_batch **out);
+
+void afmg_batch_destroy(afmg_batch *batch);
+
+int afmg_batch_info(const afmg_batch *batch, afmg_batch_desc *out);
+
+/* Device workspace bytes afmg_batch_solve needs for these options. */
+int afmg_batch_workspace_bytes(const afmg_batch *batch, const afmg_opts *opts, size_t *bytes);
+
+/*
+ * afmg_solve on every tree of the batch.  rho, u: device arrays holding the
+ * trees' [n_boxes][N^D] arrays one after the other, in the order the trees
+ * were given (each in its own box-id order, as afmg_solve takes it); bc:
+ * likewise the trees' Dirichlet rows one after the other, or NULL for zero.
+ * stats: host array of n_trees records, one per tree (t_ms is the time of the
+ * whole batch).  Returns AFMG_OK when every tree converged, the first error of
+ * a tree (in tree order) if any tree failed, else AFMG_NOT_CONVERGED.
+ */
+int afmg_batch_solve(afmg_batch *batch, void *stream, const double *rho, const double *bc, double *u,
+                     void *workspace, size_t workspace_bytes, const afmg_opts *opts,
+                     afmg_stats *stats);
 
 /* Message for the last failing call on this thread. */
 const char *afmg_last_error(void);

@@ -42,6 +42,7 @@ class Opts(C.Structure):
         ("use_guess", C.c_int),
         ("precision", C.c_int),
         ("profile", C.c_int),
+        ("graph", C.c_int),
     ]
 
 
@@ -82,6 +83,18 @@ class TreeDesc(C.Structure):
     ]
 
 
+class BatchDesc(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int),
+        ("box_n", C.c_int),
+        ("n_trees", C.c_int),
+        ("lmax", C.c_int),
+        ("n_boxes", C.c_int64),
+        ("n_bfaces", C.c_int64),
+        ("n_unknowns", C.c_int64),
+    ]
+
+
 class BoxDesc(C.Structure):
     _fields_ = [
         ("level", C.c_int),
@@ -96,6 +109,8 @@ EXPORTS = [
     "afmg_default_opts", "afmg_tree_create", "afmg_tree_destroy", "afmg_tree_info",
     "afmg_tree_leaf_boxes", "afmg_tree_bfaces", "afmg_tree_box", "afmg_workspace_bytes",
     "afmg_solve", "afmg_last_error", "afmg_adjoint_workspace_bytes", "afmg_apply", "afmg_adjoint",
+    "afmg_batch_create", "afmg_batch_destroy", "afmg_batch_info", "afmg_batch_workspace_bytes",
+    "afmg_batch_solve",
 ]
 OPS = {"L": 0, "LT": 1}
 
@@ -134,6 +149,12 @@ def lib():
         L.afmg_adjoint_workspace_bytes.argtypes = [vp, C.POINTER(Opts), C.POINTER(C.c_size_t)]
         L.afmg_apply.argtypes = [vp, vp, C.c_int, vp, vp, vp, C.c_size_t]
         L.afmg_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, C.c_size_t, C.POINTER(Opts), C.POINTER(Stats)]
+        L.afmg_batch_create.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(vp)]
+        L.afmg_batch_destroy.argtypes = [vp]
+        L.afmg_batch_destroy.restype = None
+        L.afmg_batch_info.argtypes = [vp, C.POINTER(BatchDesc)]
+        L.afmg_batch_workspace_bytes.argtypes = [vp, C.POINTER(Opts), C.POINTER(C.c_size_t)]
+        L.afmg_batch_solve.argtypes = [vp, vp, vp, vp, vp, vp, C.c_size_t, C.POINTER(Opts), C.POINTER(Stats)]
         _lib = L
     return _lib
 
@@ -149,7 +170,7 @@ def _check(rc, allow=(AFMG_OK,)):
 
 
 def make_opts(cycle="V", n_down=2, n_up=2, n_base=4, tol=1e-10, max_cycles=100, fixed_cycles=0,
-              use_guess=False, precision="fp64", profile=False):
+              use_guess=False, precision="fp64", profile=False, graph=False):
     o = Opts()
     lib().afmg_default_opts(C.byref(o))
     o.cycle = CYCLES[cycle]
@@ -160,6 +181,7 @@ def make_opts(cycle="V", n_down=2, n_up=2, n_base=4, tol=1e-10, max_cycles=100, 
     o.use_guess = 1 if use_guess else 0
     o.precision = PRECISIONS[precision]
     o.profile = 1 if profile else 0
+    o.graph = 1 if graph else 0
     return o
 
 
@@ -255,7 +277,7 @@ def _ptr(t):
 
 def solve(tree: Tree, rho, bc=None, u=None, *, cycle="V", tol=1e-10, max_cycles=100, fixed_cycles=0,
           n_down=2, n_up=2, n_base=4, precision="fp64", workspace=None, stream=None, check=True,
-          profile=False, use_guess=None):
+          profile=False, use_guess=None, graph=False):
     """Solve lap_h(u) = rho on `tree`.
 
     rho, u: torch float64 CUDA tensors [n_boxes, N^D] in box order; bc:
@@ -281,7 +303,7 @@ def solve(tree: Tree, rho, bc=None, u=None, *, cycle="V", tol=1e-10, max_cycles=
             raise ValueError("bc has the wrong dtype or size")
         bc = bc.contiguous()
     opts = make_opts(cycle, n_down, n_up, n_base, tol, max_cycles, fixed_cycles, use_guess, precision,
-                     profile)
+                     profile, graph)
     nbytes = tree.workspace_bytes(opts)
     if workspace is None or workspace.numel() * workspace.element_size() < nbytes:
         workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
@@ -296,6 +318,102 @@ def solve(tree: Tree, rho, bc=None, u=None, *, cycle="V", tol=1e-10, max_cycles=
     d = st.to_dict()
     d["rc"] = rc
     return u, d
+
+
+class Batch:
+    """Independent trees of one dimension solved together (afmg_batch_*).
+
+    Fields are the trees' [n_boxes, N^D] arrays one after the other (each in
+    its tree's box order); `concat` and `split` convert from / to lists."""
+
+    def __init__(self, trees):
+        trees = list(trees)
+        if not trees:
+            raise ValueError("empty batch")
+        L = lib()
+        arr = (C.c_void_p * len(trees))(*[t.handle for t in trees])
+        h = C.c_void_p()
+        _check(L.afmg_batch_create(arr, len(trees), C.byref(h)))
+        self._h = h
+        d = BatchDesc()
+        _check(L.afmg_batch_info(h, C.byref(d)))
+        self.dim, self.box_n, self.n_trees, self.lmax = d.dim, d.box_n, d.n_trees, d.lmax
+        self.n_boxes, self.n_bfaces, self.n_unknowns = d.n_boxes, d.n_bfaces, d.n_unknowns
+        self.cells_per_box = trees[0].cells_per_box
+        self.box_counts = [t.n_boxes for t in trees]
+        self.bface_counts = [t.n_bfaces for t in trees]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().afmg_batch_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def workspace_bytes(self, opts=None):
+        n = C.c_size_t()
+        _check(lib().afmg_batch_workspace_bytes(self._h, C.byref(opts) if opts is not None else None,
+                                                C.byref(n)))
+        return n.value
+
+    def concat(self, fields):
+        import torch
+        return torch.cat([f.reshape(n, -1) for f, n in zip(fields, self.box_counts)]).contiguous()
+
+    def concat_bc(self, rows):
+        import torch
+        parts = [r.reshape(n, -1) for r, n in zip(rows, self.bface_counts) if n > 0]
+        return torch.cat(parts).contiguous() if parts else None
+
+    def split(self, field):
+        return list(field.reshape(self.n_boxes, -1).split(self.box_counts))
+
+
+def solve_batch(batch: Batch, rho, bc=None, u=None, *, cycle="V", tol=1e-10, max_cycles=100, fixed_cycles=0,
+                n_down=2, n_up=2, n_base=4, precision="fp64", workspace=None, stream=None, check=True,
+                profile=False, use_guess=None, graph=False):
+    """afmg_solve on every tree of the batch.  rho, u: float64 device tensors
+    [batch.n_boxes, N^D] (the trees' arrays one after the other); bc: the
+    trees' Dirichlet rows one after the other, or None.  Returns (u, list of
+    per-tree stats dicts)."""
+    import torch
+
+    dev = rho.device
+    shape = (batch.n_boxes, batch.cells_per_box)
+    if dev.type != "cuda" or rho.dtype != torch.float64 or tuple(rho.shape) != shape or not rho.is_contiguous():
+        raise ValueError(f"rho must be a contiguous float64 device tensor {shape}")
+    if use_guess is None:
+        use_guess = u is not None
+    if u is None:
+        u = torch.empty(shape, dtype=torch.float64, device=dev)
+    elif u.dtype != torch.float64 or tuple(u.shape) != shape or not u.is_contiguous():
+        raise ValueError(f"u must be contiguous float64 {shape}")
+    if bc is not None:
+        if bc.dtype != torch.float64 or bc.numel() != batch.n_bfaces * batch.box_n ** (batch.dim - 1):
+            raise ValueError("bc has the wrong dtype or size")
+        bc = bc.contiguous()
+    opts = make_opts(cycle, n_down, n_up, n_base, tol, max_cycles, fixed_cycles, use_guess, precision,
+                     profile, graph)
+    nbytes = batch.workspace_bytes(opts)
+    if workspace is None or workspace.numel() * workspace.element_size() < nbytes:
+        workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    sts = (Stats * batch.n_trees)()
+    with torch.cuda.device(dev):
+        rc = lib().afmg_batch_solve(batch.handle, C.c_void_p(stream.cuda_stream), _ptr(rho), _ptr(bc), _ptr(u),
+                                    _ptr(workspace), nbytes, C.byref(opts), sts)
+    if check:
+        _check(rc, allow=(AFMG_OK, AFMG_NOT_CONVERGED))
+    out = []
+    for s in sts:
+        d = s.to_dict()
+        d["rc"] = rc
+        out.append(d)
+    return u, out
 
 
 def _check_field(tree, t, name):

@@ -21,13 +21,16 @@ struct LevelArgs {
     int nb;             // number of boxes
     int homog;          // 1: zero Dirichlet values
     T h2, ih2;          // h^2 and 1/h^2 of the level
+    const int *active;  // forest: per-tree flag, boxes of trees at 0 are left
+                        // untouched; null: every box is processed
 };
 
 enum class Op { GSRB, RESID_RESTRICT, COARSE_RHS, PROLONG, RESTRICT_RHO };
 
 enum { COARSE_V_FROM_2 = 0, COARSE_V_TOP1 = 1, COARSE_FMG = 2 };
 
-// Arguments of the one-workgroup kernel for levels <= 1 (root box = box 0).
+// Arguments of the kernel for levels <= 1: one workgroup per tree, whose
+// root is box `tree` (the roots come first in the box order).
 template <typename T>
 struct CoarseArgs {
     const BoxInfo *info;
@@ -38,6 +41,7 @@ struct CoarseArgs {
     int mode;
     int homog;
     int n_down, n_up, n_base;
+    const int *active;  // per-tree flag as in LevelArgs (null: all trees)
 };
 
 template <int D, int N, typename T>
@@ -46,17 +50,31 @@ template <int D, int N, typename T>
 void launch_final(const LevelArgs<T> &a, double *partial, int64_t part0, double hD, float *rout,
                   hipStream_t st);
 template <int D, int N>
-void launch_ir_update(const BoxInfo *info, double *u, const float *e, int64_t nb, hipStream_t st);
+void launch_ir_update(const BoxInfo *info, double *u, const float *e, int64_t nb, const int *active,
+                      hipStream_t st);
 template <int D, int N>
 int final_wgs(int64_t nb);
 void launch_reduce(const double *partial, int64_t n, double *out, hipStream_t st);
+// forests: per-tree (max, L2) of the per-box partials of each tree's leaf boxes
+void launch_reduce_trees(const double *partial, const int64_t *ptr, const int32_t *boxes, const int *active,
+                         double *out, int n_trees, hipStream_t st);
+// out[t] = base[t] (1 if base is null) and tree_lmax[t] >= l
+void launch_level_mask(const int *base, const int32_t *tree_lmax, int l, int *out, int n_trees, hipStream_t st);
 template <int D, int N, typename T>
-void launch_coarse(const CoarseArgs<T> &a, hipStream_t st);
+void launch_coarse(const CoarseArgs<T> &a, int n_trees, hipStream_t st);
 template <int D, int N, typename T>
 void launch_permute(const BoxInfo *info, T *f, int64_t b0, int64_t nb, int to_split, int leaves_only,
                     hipStream_t st);
+// caller's boxes (natural order; box map[b], or b if map is null) -> working
+// boxes (colour-split); leaves_only skips parents
 template <int D, int N, typename T>
-void launch_load_rho(const BoxInfo *info, const T *src, T *dst, int64_t nb, hipStream_t st);
+void launch_load_rho(const BoxInfo *info, const int32_t *map, const T *src, T *dst, int64_t nb, int leaves_only,
+                     hipStream_t st);
+// working box b -> caller's box map[b]
+template <int D, int N, typename T>
+void launch_store_boxes(const int32_t *map, const T *src, T *dst, int64_t nb, hipStream_t st);
+// dst row r (F values) <- src row map[r]
+void launch_gather_rows(const int32_t *map, const double *src, double *dst, int64_t n_rows, int F, hipStream_t st);
 template <int D, int N>
 void launch_bc_derive(const BoxInfo *info, int64_t b0, int64_t nb, double *bc, hipStream_t st);
 // adjoint support (FP64)

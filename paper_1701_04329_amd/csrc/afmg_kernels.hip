@@ -113,6 +113,15 @@ __device__ __forceinline__ Slot<D, N> slot_of(int64_t b0, int nb) {
     return r;
 }
 
+// Slot of a level kernel.  In a forest, boxes of trees whose mask entry is 0
+// are treated like padding slots: they are read but never written.
+template <int D, int N, typename T>
+__device__ __forceinline__ Slot<D, N> slot_of(const LevelArgs<T> &a) {
+    Slot<D, N> r = slot_of<D, N>(a.b0, a.nb);
+    if (a.active) r.valid = r.valid && a.active[load_box<D, N>(a.info, r.b).tree] != 0;
+    return r;
+}
+
 // ---------------------------------------------------------------------------
 // side ghosts (paper §2.4, §3.3)
 // ---------------------------------------------------------------------------
@@ -310,7 +319,7 @@ __global__ __launch_bounds__(256) void k_gsrb(LevelArgs<T> a, int colour) {
     using G = Geo<D, N>;
     constexpr int HN = G::HN;
     __shared__ T so[G::BPW * oblock<D, N>()];
-    const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb);
+    const Slot<D, N> sl = slot_of<D, N>(a);
     T *s = so + sl.slot * oblock<D, N>();
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     T *ub = a.u + (size_t)sl.b * G::C;
@@ -421,7 +430,7 @@ template <int D, int N, typename T>
 __global__ __launch_bounds__(256) void k_resid_restrict(LevelArgs<T> a) {
     using G = Geo<D, N>;
     __shared__ T sm[G::BPW * G::PC];
-    const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb);
+    const Slot<D, N> sl = slot_of<D, N>(a);
     T *s = sm + sl.slot * G::PC;
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
@@ -463,7 +472,7 @@ template <int D, int N, typename T>
 __global__ __launch_bounds__(256) void k_coarse_rhs(LevelArgs<T> a) {
     using G = Geo<D, N>;
     __shared__ T sm[G::BPW * G::PC];
-    const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb);
+    const Slot<D, N> sl = slot_of<D, N>(a);
     T *s = sm + sl.slot * G::PC;
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
@@ -580,7 +589,7 @@ __global__ __launch_bounds__(256) void k_prolong(LevelArgs<T> a) {
     using G = Geo<D, N>;
     constexpr int NH = (2 * D * G::HF + G::TPB - 1) / G::TPB;  // halo cells per thread
     __shared__ T qs[G::BPW * G::QC];
-    const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb);
+    const Slot<D, N> sl = slot_of<D, N>(a);
     T *q = qs + sl.slot * G::QC;
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
@@ -645,17 +654,18 @@ __global__ __launch_bounds__(256) void k_prolong(LevelArgs<T> a) {
 // end of a cycle: restriction of u and the composite leaf residual
 // ---------------------------------------------------------------------------
 // Boxes of level l: the octant of the parent receives mean(u) (l >= 2); on
-// leaves r = rho - L u, and the workgroup writes (max |r|, sum r^2 h^D) to
-// partial[part0 + workgroup].  With rout set, the leaf residual is also
-// stored there rounded to FP32: the right-hand side of the correction solve
-// of the mixed-precision refinement.
+// leaves r = rho - L u, and (max |r|, sum r^2 h^D) goes to partial: per
+// workgroup at partial[part0 + workgroup], or, with part0 < 0 (forests), per
+// leaf box at partial[box].  With rout set, the leaf residual is also stored
+// there rounded to FP32: the right-hand side of the correction solve of the
+// mixed-precision refinement.
 template <int D, int N, typename T>
 __global__ __launch_bounds__(256) void k_final(LevelArgs<T> a, double *partial, int64_t part0, double hD,
                                                float *__restrict__ rout) {
     using G = Geo<D, N>;
     __shared__ T sm[G::BPW * G::PC];
     __shared__ double red_m[256], red_s[256];
-    const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb);
+    const Slot<D, N> sl = slot_of<D, N>(a);
     T *s = sm + sl.slot * G::PC;
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
@@ -683,6 +693,21 @@ __global__ __launch_bounds__(256) void k_final(LevelArgs<T> a, double *partial, 
     red_m[threadIdx.x] = mx;
     red_s[threadIdx.x] = ss;
     __syncthreads();
+    if (part0 < 0) {
+        // per box: reduce the TPB threads of each slot
+        for (int w = G::TPB / 2; w > 0; w >>= 1) {
+            if (sl.t < w) {
+                red_m[threadIdx.x] = fmax(red_m[threadIdx.x], red_m[threadIdx.x + w]);
+                red_s[threadIdx.x] += red_s[threadIdx.x + w];
+            }
+            __syncthreads();
+        }
+        if (sl.valid && leaf && sl.t == 0) {
+            partial[2 * sl.b + 0] = red_m[threadIdx.x];
+            partial[2 * sl.b + 1] = red_s[threadIdx.x] * hD;
+        }
+        return;
+    }
     for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) {
             red_m[threadIdx.x] = fmax(red_m[threadIdx.x], red_m[threadIdx.x + w]);
@@ -732,6 +757,47 @@ __global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ part
     }
 }
 
+// One workgroup per tree of a forest: (max, sqrt of sum) of the per-box
+// partials of the tree's leaf boxes, in a fixed order; trees whose mask entry
+// is 0 are skipped.
+__global__ __launch_bounds__(256) void k_reduce_trees(const double *__restrict__ partial,
+                                                      const int64_t *__restrict__ ptr,
+                                                      const int32_t *__restrict__ boxes,
+                                                      const int *__restrict__ active, double *out) {
+    __shared__ double rm[256], rsum[256];
+    const int tr = blockIdx.x;
+    if (active && !active[tr]) return;
+    double mx = 0.0, ss = 0.0;
+    for (int64_t i = ptr[tr] + threadIdx.x; i < ptr[tr + 1]; i += 256) {
+        const int64_t b = boxes[i];
+        mx = fmax(mx, partial[2 * b]);
+        ss += partial[2 * b + 1];
+    }
+    rm[threadIdx.x] = mx;
+    rsum[threadIdx.x] = ss;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            rm[threadIdx.x] = fmax(rm[threadIdx.x], rm[threadIdx.x + w]);
+            rsum[threadIdx.x] += rsum[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double s = rsum[0];
+        out[2 * tr + 0] = (s == s) ? rm[0] : s;
+        out[2 * tr + 1] = sqrt(s);
+    }
+}
+
+// Mask of the trees that take part in an FMG step at level l: out[t] =
+// base[t] (1 when base is null) and the tree reaches level l.
+__global__ __launch_bounds__(256) void k_level_mask(const int *__restrict__ base, const int32_t *__restrict__ tree_lmax,
+                                                    int l, int *__restrict__ out, int n) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t < n) out[t] = ((base ? base[t] : 1) != 0 && tree_lmax[t] >= l) ? 1 : 0;
+}
+
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
@@ -740,7 +806,7 @@ template <int D, int N, typename T>
 __global__ __launch_bounds__(256) void k_restrict_rho(LevelArgs<T> a) {
     using G = Geo<D, N>;
     __shared__ T sm[G::BPW * G::C];
-    const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb);
+    const Slot<D, N> sl = slot_of<D, N>(a);
     T *s = sm + sl.slot * G::C;
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
@@ -783,27 +849,58 @@ __global__ __launch_bounds__(256) void k_permute(const BoxInfo *__restrict__ inf
 // Mixed-precision refinement: u += e on the leaf boxes (e in FP32).
 template <int D, int N>
 __global__ __launch_bounds__(256) void k_ir_update(const BoxInfo *__restrict__ info, double *__restrict__ u,
-                                                   const float *__restrict__ e, int nb) {
+                                                   const float *__restrict__ e, int nb, const int *active) {
     using G = Geo<D, N>;
     const Slot<D, N> sl = slot_of<D, N>(0, nb);
-    if (!sl.valid || !(load_box<D, N>(info, sl.b).flags & FLAG_LEAF)) return;
+    if (!sl.valid) return;
+    const BoxInfo bi = load_box<D, N>(info, sl.b);
+    if (!(bi.flags & FLAG_LEAF) || (active && !active[bi.tree])) return;
     const size_t bo = (size_t)sl.b * G::C;
     for (int c = sl.t; c < G::C; c += G::TPB) u[bo + c] = u[bo + c] + (double)e[bo + c];
 }
 
-// Copy of the caller's rho on leaf boxes into the colour-split working rho.
+// Copy of the caller's boxes (natural order) into the colour-split working
+// layout: box b receives the caller's box map[b] (b itself when map is null);
+// leaves_only skips parent boxes.
 template <int D, int N, typename T>
-__global__ __launch_bounds__(256) void k_load_rho(const BoxInfo *__restrict__ info, const T *__restrict__ src,
-                                                  T *__restrict__ dst, int nb) {
+__global__ __launch_bounds__(256) void k_load_rho(const BoxInfo *__restrict__ info, const int32_t *__restrict__ map,
+                                                  const T *__restrict__ src, T *__restrict__ dst, int nb,
+                                                  int leaves_only) {
     using G = Geo<D, N>;
     const Slot<D, N> sl = slot_of<D, N>(0, nb);
-    if (!sl.valid || !(info[sl.b].flags & FLAG_LEAF)) return;
+    if (!sl.valid || (leaves_only && !(info[sl.b].flags & FLAG_LEAF))) return;
     const size_t bo = (size_t)sl.b * G::C;
+    const size_t so = (size_t)(map ? map[sl.b] : sl.b) * G::C;
     for (int e = sl.t; e < G::C; e += G::TPB) {
         int i, j, k;
         cell_of<D, N>(e, i, j, k);
-        dst[bo + e] = src[bo + (D == 3 ? i + N * (j + N * k) : i + N * j)];
+        dst[bo + e] = src[so + (D == 3 ? i + N * (j + N * k) : i + N * j)];
     }
+}
+
+// Inverse of k_load_rho for whole boxes: the caller's box map[b] (natural
+// order) receives working box b (colour-split).
+template <int D, int N, typename T>
+__global__ __launch_bounds__(256) void k_store_boxes(const int32_t *__restrict__ map, const T *__restrict__ src,
+                                                     T *__restrict__ dst, int nb) {
+    using G = Geo<D, N>;
+    const Slot<D, N> sl = slot_of<D, N>(0, nb);
+    if (!sl.valid) return;
+    const size_t bo = (size_t)sl.b * G::C;
+    const size_t dof = (size_t)map[sl.b] * G::C;
+    for (int e = sl.t; e < G::C; e += G::TPB) {
+        int i, j, k;
+        cell_of<D, N>(e, i, j, k);
+        dst[dof + (D == 3 ? i + N * (j + N * k) : i + N * j)] = src[bo + e];
+    }
+}
+
+// Rows of F values: dst row r receives src row map[r].
+__global__ __launch_bounds__(256) void k_gather_rows(const int32_t *__restrict__ map, const double *__restrict__ src,
+                                                     double *__restrict__ dst, int64_t n_rows, int F) {
+    const int64_t n = n_rows * F;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        dst[i] = src[(int64_t)map[i / F] * F + i % F];
 }
 
 template <typename T>
@@ -1027,7 +1124,16 @@ __global__ __launch_bounds__(256) void k_coarse(CoarseArgs<T> a) {
     using G = Geo<D, N>;
     __shared__ double f_u[CG::PTOT], f_rho[CG::PTOT], f_uold[CG::PTOT], f_res[CG::PTOT], f_bc[CG::BTOT];
     CoarseState<D, N> st{f_u, f_rho, f_uold, f_res, f_bc, a.n_down, a.n_up, a.n_base};
-    const BoxInfo *ri = a.info;  // the root is box 0
+    // one workgroup per tree; the roots are boxes 0 .. n_trees-1
+    const int64_t root = blockIdx.x;
+    const BoxInfo *ri = a.info + root;
+    if (a.active && !a.active[ri->tree]) return;
+    // a V-cycle reaching level 2 starts here after a restriction, unless the
+    // tree is its root box alone
+    const int mode = (a.mode == COARSE_V_FROM_2 && (ri->flags & FLAG_LEAF)) ? COARSE_V_TOP1 : a.mode;
+    T *gu = a.u + root * G::C;
+    const T *grho = a.rho + root * G::C;
+    T *guold = a.uold ? a.uold + root * G::C : nullptr;
     // Dirichlet values: root rows, then means down to the 2^D grid
     for (int g = threadIdx.x; g < 2 * D * G::F; g += blockDim.x) {
         const int side = g / G::F, m = g % G::F;
@@ -1059,19 +1165,19 @@ __global__ __launch_bounds__(256) void k_coarse(CoarseArgs<T> a) {
         int i, j, k;
         cell_of<D, N>(e, i, j, k);
         const int p = st.pidx(0, i, j, k);
-        if (a.mode != COARSE_FMG) f_u[p] = (double)a.u[e];
-        if (a.mode == COARSE_V_FROM_2) f_res[p] = (double)a.rho[e];
-        else f_rho[p] = (double)a.rho[e];
+        if (mode != COARSE_FMG) f_u[p] = (double)gu[e];
+        if (mode == COARSE_V_FROM_2) f_res[p] = (double)grho[e];
+        else f_rho[p] = (double)grho[e];
     }
     __syncthreads();
-    if (a.mode == COARSE_V_FROM_2) {
+    if (mode == COARSE_V_FROM_2) {
         // level 1 right after restriction from level 2: ghosts, copy v'_H,
         // FAS right-hand side, then the V-cycle from level 1
         st.fill(f_u, 0);
         st.copy_uold(0);
         st.coarse_rhs(0);
         st.vcycle(0);
-    } else if (a.mode == COARSE_V_TOP1) {
+    } else if (mode == COARSE_V_TOP1) {
         st.vcycle(0);
     } else {
         // FMG from a zero guess: rho restricted down, then for l = lmin..1:
@@ -1091,8 +1197,8 @@ __global__ __launch_bounds__(256) void k_coarse(CoarseArgs<T> a) {
         int i, j, k;
         cell_of<D, N>(e, i, j, k);
         const int p = st.pidx(0, i, j, k);
-        a.u[e] = (T)f_u[p];
-        if (a.uold && a.mode != COARSE_V_TOP1) a.uold[e] = (T)f_uold[p];
+        gu[e] = (T)f_u[p];
+        if (guold && mode != COARSE_V_TOP1) guold[e] = (T)f_uold[p];
     }
 }
 
@@ -1449,9 +1555,10 @@ void launch_final(const LevelArgs<T> &a, double *partial, int64_t part0, double 
 }
 
 template <int D, int N>
-void launch_ir_update(const BoxInfo *info, double *u, const float *e, int64_t nb, hipStream_t st) {
+void launch_ir_update(const BoxInfo *info, double *u, const float *e, int64_t nb, const int *active,
+                      hipStream_t st) {
     const int g = wg_count<D, N>(nb);
-    AFMG_LAUNCH((k_ir_update<D, N>), g, st, info, u, e, (int)nb);
+    AFMG_LAUNCH((k_ir_update<D, N>), g, st, info, u, e, (int)nb, active);
 }
 
 template <int D, int N>
@@ -1461,9 +1568,19 @@ void launch_reduce(const double *partial, int64_t n, double *out, hipStream_t st
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, partial, n, out, 1);
 }
 
+void launch_reduce_trees(const double *partial, const int64_t *ptr, const int32_t *boxes, const int *active,
+                         double *out, int n_trees, hipStream_t st) {
+    AFMG_LAUNCH(k_reduce_trees, n_trees, st, partial, ptr, boxes, active, out);
+}
+
+void launch_level_mask(const int *base, const int32_t *tree_lmax, int l, int *out, int n_trees, hipStream_t st) {
+    const int g = (n_trees + 255) / 256;
+    AFMG_LAUNCH(k_level_mask, g, st, base, tree_lmax, l, out, n_trees);
+}
+
 template <int D, int N, typename T>
-void launch_coarse(const CoarseArgs<T> &a, hipStream_t st) {
-    hipLaunchKernelGGL((k_coarse<D, N, T>), dim3(1), dim3(256), 0, st, a);
+void launch_coarse(const CoarseArgs<T> &a, int n_trees, hipStream_t st) {
+    AFMG_LAUNCH((k_coarse<D, N, T>), n_trees, st, a);
 }
 
 template <int D, int N, typename T>
@@ -1474,9 +1591,23 @@ void launch_permute(const BoxInfo *info, T *f, int64_t b0, int64_t nb, int to_sp
 }
 
 template <int D, int N, typename T>
-void launch_load_rho(const BoxInfo *info, const T *src, T *dst, int64_t nb, hipStream_t st) {
+void launch_load_rho(const BoxInfo *info, const int32_t *map, const T *src, T *dst, int64_t nb, int leaves_only,
+                     hipStream_t st) {
     const int g = wg_count<D, N>(nb);
-    AFMG_LAUNCH((k_load_rho<D, N, T>), g, st, info, src, dst, (int)nb);
+    AFMG_LAUNCH((k_load_rho<D, N, T>), g, st, info, map, src, dst, (int)nb, leaves_only);
+}
+
+template <int D, int N, typename T>
+void launch_store_boxes(const int32_t *map, const T *src, T *dst, int64_t nb, hipStream_t st) {
+    const int g = wg_count<D, N>(nb);
+    AFMG_LAUNCH((k_store_boxes<D, N, T>), g, st, map, src, dst, (int)nb);
+}
+
+void launch_gather_rows(const int32_t *map, const double *src, double *dst, int64_t n_rows, int F,
+                        hipStream_t st) {
+    int64_t g = (n_rows * F + 255) / 256;
+    if (g > 65536) g = 65536;
+    AFMG_LAUNCH(k_gather_rows, (int)g, st, map, src, dst, n_rows, F);
 }
 
 template <int D, int N>
@@ -1570,16 +1701,18 @@ AFMG_ADJ_INST(3, 8)
     template void launch_level<D, N, T>(Op, const LevelArgs<T> &, int, hipStream_t);                     \
     template void launch_final<D, N, T>(const LevelArgs<T> &, double *, int64_t, double, float *,     \
                                         hipStream_t);                                                 \
-    template void launch_coarse<D, N, T>(const CoarseArgs<T> &, hipStream_t);                           \
+    template void launch_coarse<D, N, T>(const CoarseArgs<T> &, int, hipStream_t);                      \
     template void launch_permute<D, N, T>(const BoxInfo *, T *, int64_t, int64_t, int, int, hipStream_t); \
-    template void launch_load_rho<D, N, T>(const BoxInfo *, const T *, T *, int64_t, hipStream_t);
+    template void launch_load_rho<D, N, T>(const BoxInfo *, const int32_t *, const T *, T *, int64_t, int, \
+                                           hipStream_t);                                              \
+    template void launch_store_boxes<D, N, T>(const int32_t *, const T *, T *, int64_t, hipStream_t);
 
 AFMG_INST(2, 8, double)
 AFMG_INST(3, 8, double)
 AFMG_INST(2, 8, float)
 AFMG_INST(3, 8, float)
-template void launch_ir_update<2, 8>(const BoxInfo *, double *, const float *, int64_t, hipStream_t);
-template void launch_ir_update<3, 8>(const BoxInfo *, double *, const float *, int64_t, hipStream_t);
+template void launch_ir_update<2, 8>(const BoxInfo *, double *, const float *, int64_t, const int *, hipStream_t);
+template void launch_ir_update<3, 8>(const BoxInfo *, double *, const float *, int64_t, const int *, hipStream_t);
 template void launch_copy<float>(const float *, float *, int64_t, hipStream_t);
 template void launch_fill<float>(float *, int64_t, float, hipStream_t);
 template int final_wgs<2, 8>(int64_t);

@@ -2,12 +2,18 @@
 //
 // The scheduler issues the kernels of one FAS V-cycle level by level (paper
 // §3.2): smoothing, residual + restriction, FAS right-hand side and the copy
-// v'_H, the one-workgroup kernel for the root box and the coarse grids below
-// it, then prolongation + correction and smoothing on the way up.  After
-// each cycle the composite leaf residual is reduced on the device and its
-// max-norm is read back for the stop test.
+// v'_H, the kernel for the root box and the coarse grids below it, then
+// prolongation + correction and smoothing on the way up.  After each cycle the
+// composite leaf residual is reduced on the device and its max-norm is read
+// back for the stop test.
+//
+// A batch is a forest: the boxes of all its trees in one list (level, tree,
+// Morton), so every launch covers one level of every tree.  Each tree keeps
+// its own stop test; a per-tree mask on the device removes stopped trees from
+// later cycles, so each tree runs exactly the iteration it would run alone.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -25,15 +31,51 @@ thread_local std::string g_err;
 void afmg::set_error(const std::string &m) { g_err = m; }
 extern "C" const char *afmg_last_error(void) { return g_err.c_str(); }
 
+namespace {
+// The repeated cycle recorded as a HIP graph (opts.graph), with the
+// arguments it was recorded for.
+struct Recorded {
+    hipStream_t cap = nullptr;  // private stream, used only for recording
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<uintptr_t> key;
+
+    void drop() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        key.clear();
+    }
+};
+}  // namespace
+
 struct afmg_tree {
     HostTree h;
     int device = -1;
     BoxInfo *d_info = nullptr;
     int32_t *d_child = nullptr;      // [n_boxes][8] child ids (adjoint)
-    double *h_norm = nullptr;        // pinned host copy of the two norms
-    std::vector<int64_t> part_off;   // first k_final partial of each level
+    double *h_norm = nullptr;        // pinned host copy of (max, L2) per tree
+    std::vector<int64_t> part_off;   // first k_final partial of each level (one tree)
     int64_t n_parts = 0;
     std::vector<hipEvent_t> events;  // event pairs for opts.profile
+    Recorded rec;
+    // forests (batches): per-tree mask and tables, and the caller's layout
+    bool forest = false;
+    int *h_active = nullptr;              // pinned per-tree mask
+    int *d_active = nullptr;              // mask of the trees still iterating
+    int *d_mask = nullptr;                // mask of one FMG step
+    int32_t *d_tree_lmax = nullptr;
+    int64_t *d_tree_leaf_ptr = nullptr;
+    int32_t *d_tree_leaf_box = nullptr;
+    std::vector<int32_t> box_map;         // caller's box of each working box
+    std::vector<int32_t> row_map;         // caller's Dirichlet row of each leaf row
+    int32_t *d_box_map = nullptr, *d_row_map = nullptr;
+    int64_t user_boxes = 0, user_rows = 0, user_unknowns = 0;
+};
+
+struct afmg_batch {
+    afmg_tree f;
 };
 
 namespace {
@@ -54,8 +96,9 @@ int64_t cells_per_face(int dim) { return dim == 3 ? BOX_N * BOX_N : BOX_N; }
 double level_h(int l) { return 1.0 / ((double)BOX_N * std::ldexp(1.0, l - 1)); }
 
 struct WsLayout {
-    // FP64: rho, uold; mixed: rho (FP64 leaf rho), e, rho_e, uold_e (FP32)
-    size_t rho, uold, bc, partial, norm, e, rho_e, uold_e, total;
+    // FP64: rho, uold; mixed: rho (FP64 leaf rho), e, rho_e, uold_e (FP32);
+    // forests also hold the working u
+    size_t rho, uold, bc, partial, norm, e, rho_e, uold_e, u, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -65,16 +108,18 @@ WsLayout ws_layout(const afmg_tree *t, int precision) {
     const size_t C = (size_t)cells_per_box(h.dim), F = (size_t)cells_per_face(h.dim);
     const size_t nlt = (size_t)h.n_below_lmax(), nb = (size_t)h.n_boxes;
     const bool mixed = precision == AFMG_MIXED;
+    const size_t np = t->forest ? nb : (size_t)std::max<int64_t>(1, t->n_parts);
     WsLayout L{};
     size_t off = 0;
     L.rho = off; off = align256(off + nb * C * sizeof(double));
     L.uold = off; off = align256(off + (mixed ? 0 : nlt * C * sizeof(double)));
     L.bc = off; off = align256(off + (size_t)std::max<int64_t>(1, h.n_bfaces_all) * F * sizeof(double));
-    L.partial = off; off = align256(off + (size_t)std::max<int64_t>(1, t->n_parts) * 2 * sizeof(double));
-    L.norm = off; off = align256(off + 2 * sizeof(double));
+    L.partial = off; off = align256(off + np * 2 * sizeof(double));
+    L.norm = off; off = align256(off + (size_t)h.n_trees * 2 * sizeof(double));
     L.e = off; off = align256(off + (mixed ? nb * C * sizeof(float) : 0));
     L.rho_e = off; off = align256(off + (mixed ? nb * C * sizeof(float) : 0));
     L.uold_e = off; off = align256(off + (mixed ? nlt * C * sizeof(float) : 0));
+    L.u = off; off = align256(off + (t->forest ? nb * C * sizeof(double) : 0));
     L.total = off;
     return L;
 }
@@ -96,6 +141,17 @@ void compute_partials(afmg_tree *t) {
     t->n_parts = n;
 }
 
+template <class V>
+int upload(V *&dst, const std::vector<V> &src, const char *what) {
+    const size_t bytes = sizeof(V) * std::max<size_t>(1, src.size());
+    hipError_t e = hipMalloc(&dst, bytes);
+    if (e != hipSuccess) return fail(AFMG_ERR_OOM, std::string("hipMalloc of ") + what + " failed");
+    if (src.empty()) return AFMG_OK;
+    e = hipMemcpy(dst, src.data(), sizeof(V) * src.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, what);
+    return AFMG_OK;
+}
+
 int bind_device(afmg_tree *t) {
     int dev = -1;
     hipError_t e = hipGetDevice(&dev);
@@ -105,18 +161,37 @@ int bind_device(afmg_tree *t) {
         return AFMG_OK;
     }
     const HostTree &h = t->h;
-    e = hipMalloc(&t->d_info, sizeof(BoxInfo) * (size_t)h.n_boxes);
-    if (e != hipSuccess) return fail(AFMG_ERR_OOM, "hipMalloc of the box table failed");
-    e = hipMemcpy(t->d_info, h.info.data(), sizeof(BoxInfo) * (size_t)h.n_boxes, hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "upload of the box table");
-    e = hipMalloc(&t->d_child, sizeof(int32_t) * 8 * (size_t)h.n_boxes);
-    if (e != hipSuccess) return fail(AFMG_ERR_OOM, "hipMalloc of the child table failed");
-    e = hipMemcpy(t->d_child, h.child.data(), sizeof(int32_t) * 8 * (size_t)h.n_boxes, hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "upload of the child table");
-    e = hipHostMalloc(&t->h_norm, 2 * sizeof(double), hipHostMallocDefault);
+    int rc;
+    if ((rc = upload(t->d_info, h.info, "the box table")) != AFMG_OK) return rc;
+    if ((rc = upload(t->d_child, h.child, "the child table")) != AFMG_OK) return rc;
+    e = hipHostMalloc(&t->h_norm, 2 * sizeof(double) * (size_t)h.n_trees, hipHostMallocDefault);
     if (e != hipSuccess) return fail(AFMG_ERR_OOM, "hipHostMalloc failed");
+    if (t->forest) {
+        e = hipHostMalloc(&t->h_active, sizeof(int) * (size_t)h.n_trees, hipHostMallocDefault);
+        if (e != hipSuccess) return fail(AFMG_ERR_OOM, "hipHostMalloc failed");
+        const std::vector<int> ones((size_t)h.n_trees, 1);
+        if ((rc = upload(t->d_active, ones, "the tree mask")) != AFMG_OK) return rc;
+        if ((rc = upload(t->d_mask, ones, "the tree mask")) != AFMG_OK) return rc;
+        if ((rc = upload(t->d_tree_lmax, h.tree_lmax, "the tree levels")) != AFMG_OK) return rc;
+        if ((rc = upload(t->d_tree_leaf_ptr, h.tree_leaf_ptr, "the tree leaf lists")) != AFMG_OK) return rc;
+        if ((rc = upload(t->d_tree_leaf_box, h.tree_leaf_box, "the tree leaf lists")) != AFMG_OK) return rc;
+        if ((rc = upload(t->d_box_map, t->box_map, "the box map")) != AFMG_OK) return rc;
+        if ((rc = upload(t->d_row_map, t->row_map, "the row map")) != AFMG_OK) return rc;
+    }
     t->device = dev;
     return AFMG_OK;
+}
+
+void release(afmg_tree *t) {
+    t->rec.drop();
+    if (t->rec.cap) (void)hipStreamDestroy(t->rec.cap);
+    for (void *p : {(void *)t->d_info, (void *)t->d_child, (void *)t->d_active, (void *)t->d_mask,
+                    (void *)t->d_tree_lmax, (void *)t->d_tree_leaf_ptr, (void *)t->d_tree_leaf_box,
+                    (void *)t->d_box_map, (void *)t->d_row_map})
+        if (p) (void)hipFree(p);
+    if (t->h_norm) (void)hipHostFree(t->h_norm);
+    if (t->h_active) (void)hipHostFree(t->h_active);
+    for (auto ev : t->events) (void)hipEventDestroy(ev);
 }
 
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
@@ -184,6 +259,7 @@ struct Cycler {
     Prof &prof;
     LevelArgs<T> base;
     const double *bc64;  // Dirichlet rows for the coarse kernel (null when homogeneous)
+    afmg_tree *t;        // forests: tree levels and the FMG step mask
 
     LevelArgs<T> lev(int l) const {
         LevelArgs<T> a = base;
@@ -206,14 +282,16 @@ struct Cycler {
             level(Op::GSRB, l, 1);
         }
     }
+    // one workgroup per tree; a tree that is its root box alone takes the
+    // top-level-1 path inside the kernel
     void coarse(int mode) {
         CoarseArgs<T> c{base.info, base.u, base.rho, base.uold, bc64, mode, base.homog,
-                        o.n_down, o.n_up, o.n_base};
+                        o.n_down, o.n_up, o.n_base, base.active};
         if (h.lmax == 1) c.uold = nullptr;
-        launch_coarse<D, BOX_N, T>(c, st);
+        launch_coarse<D, BOX_N, T>(c, h.n_trees, st);
     }
     // V-cycle from level top: levels >= 2 box by box, levels <= 1 in the
-    // one-workgroup kernel
+    // coarse kernel
     void vcycle(int top) {
         for (int l = top; l >= 2; l--) {
             gsrb(l, o.n_down);
@@ -227,19 +305,26 @@ struct Cycler {
         }
     }
     // FMG from a zero guess: restrict rho down, then per level store v',
-    // correct from the coarser level and run a V-cycle from it
+    // correct from the coarser level and run a V-cycle from it.  In a forest
+    // the step at level l involves only the trees that reach level l.
     void fmg() {
         launch_fill<T>(base.u, h.n_boxes * cells_per_box(D), T(0), st);
         for (int l = h.lmax; l >= 2; l--) level(Op::RESTRICT_RHO, l);
         coarse(COARSE_FMG);
         const int64_t C = cells_per_box(D);
+        const LevelArgs<T> saved = base;
         for (int l = 2; l <= h.lmax; l++) {
+            if (saved.active) {
+                launch_level_mask(saved.active, t->d_tree_lmax, l, t->d_mask, h.n_trees, st);
+                base.active = t->d_mask;
+            }
             if (l < h.lmax)
                 launch_copy<T>(base.u + h.lvl_off[(size_t)l] * C, base.uold + h.lvl_off[(size_t)l] * C,
                                h.level_count(l) * C, st);
             level(Op::PROLONG, l);
             vcycle(l);
         }
+        base = saved;
     }
 };
 
@@ -259,11 +344,12 @@ struct Solver {
     Solver(afmg_tree *t_, hipStream_t s, const afmg_opts &o_, afmg_stats *S)
         : t(t_), h(t_->h), st(s), o(o_), prof{t_, s, o_.profile != 0, t_->h.lmax, S, {}} {}
 
-    // Restriction of u into parents and the composite leaf residual (FP64);
-    // rout receives the FP32 leaf residual for the mixed refinement.
-    int finalize(double &rmax, double &rl2, float *rout) {
+    // Restriction of u into parents and the composite leaf residual (FP64),
+    // reduced to (max, L2) per tree in norm; rout receives the FP32 leaf
+    // residual for the mixed refinement.
+    void finalize_launch(float *rout, hipStream_t s) {
         for (int l = h.lmax; l >= 1; l--) {
-            if (l == 1 && !root_is_leaf(h)) continue;
+            if (l == 1 && !t->forest && !root_is_leaf(h)) continue;
             const double hh = level_h(l);
             const double hD = D == 3 ? hh * hh * hh : hh * hh;
             LevelArgs<double> a = base;
@@ -272,25 +358,81 @@ struct Solver {
             a.h2 = hh * hh;
             a.ih2 = 1.0 / (hh * hh);
             prof.timed(AFMG_PROF_FINAL, l, [&] {
-                launch_final<D, BOX_N, double>(a, partial, t->part_off[(size_t)l], hD, rout, st);
+                launch_final<D, BOX_N, double>(a, partial, t->forest ? -1 : t->part_off[(size_t)l], hD, rout, s);
             });
         }
-        launch_reduce(partial, t->n_parts, norm, st);
+        if (t->forest)
+            launch_reduce_trees(partial, t->d_tree_leaf_ptr, t->d_tree_leaf_box, base.active, norm, h.n_trees, s);
+        else
+            launch_reduce(partial, t->n_parts, norm, s);
+    }
+    // norms to t->h_norm; synchronises the stream
+    int read_norms() {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "kernel launch");
-        e = hipMemcpyAsync(t->h_norm, norm, 2 * sizeof(double), hipMemcpyDeviceToHost, st);
+        e = hipMemcpyAsync(t->h_norm, norm, 2 * sizeof(double) * (size_t)h.n_trees, hipMemcpyDeviceToHost, st);
         if (e != hipSuccess) return hip_fail(e, "norm readback");
         e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(e, "stream synchronize");
         prof.collect();
+        return AFMG_OK;
+    }
+    int finalize(float *rout) {
+        finalize_launch(rout, st);
+        return read_norms();
+    }
+    // single tree: the two norms
+    int finalize(double &rmax, double &rl2, float *rout) {
+        const int rc = finalize(rout);
         rmax = t->h_norm[0];
         rl2 = t->h_norm[1];
+        return rc;
+    }
+    // Enqueue the launches of fn(stream) on st, through the recorded graph
+    // when opts.graph is set (recorded on first use or when key changes).
+    template <class Fn>
+    int run(const std::vector<uintptr_t> &key, Fn fn) {
+        if (!o.graph || o.profile) {
+            fn(st);
+            return AFMG_OK;
+        }
+        Recorded &r = t->rec;
+        hipError_t e;
+        if (!r.exec || r.key != key) {
+            r.drop();
+            if (!r.cap) {
+                e = hipStreamCreateWithFlags(&r.cap, hipStreamNonBlocking);
+                if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+            }
+            e = hipStreamBeginCapture(r.cap, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+            fn(r.cap);
+            e = hipStreamEndCapture(r.cap, &r.graph);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+            e = hipGraphInstantiate(&r.exec, r.graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                r.drop();
+                return hip_fail(e, "hipGraphInstantiate");
+            }
+            r.key = key;
+        }
+        e = hipGraphLaunch(r.exec, st);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+        return AFMG_OK;
+    }
+    // per-tree mask of the next launches (forests); h_active is rewritten
+    // only after the stream has synchronised
+    int upload_mask() {
+        if (!t->forest) return AFMG_OK;
+        hipError_t e = hipMemcpyAsync(t->d_active, t->h_active, sizeof(int) * (size_t)h.n_trees,
+                                      hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, "mask upload");
         return AFMG_OK;
     }
 };
 
-// Outer loop shared by both precisions: `step` runs one cycle (or one
-// refinement step) and leaves the FP64 residual norms in S.r_max / S.r_l2.
+// Outer loop of the adjoint solve: `step` runs one iteration and leaves the
+// residual norms in S.r_max / S.r_l2.
 template <class Step>
 int iterate(const afmg_opts &o, afmg_stats &S, Step step) {
     const bool fixed = o.fixed_cycles > 0;
@@ -317,13 +459,97 @@ int iterate(const afmg_opts &o, afmg_stats &S, Step step) {
     return (!fixed && !conv) ? AFMG_NOT_CONVERGED : AFMG_OK;
 }
 
+// Stop rule of one tree: cycles until max|r| <= tol max|r0|, max_cycles,
+// a non-finite norm or 3 consecutive growths; exactly fixed_cycles if set.
+struct Track {
+    bool done = false, conv = false;
+    int grow = 0;
+    double prev = 0.0;
+};
+
+// Outer loop of the solve over the trees of t: `step(k)` runs cycle k on the
+// trees whose mask entry is set and leaves their norms in t->h_norm.
+template <int D, class Step>
+int iterate_trees(Solver<D> &s, afmg_stats *S, std::vector<Track> &tr, Step step) {
+    afmg_tree *t = s.t;
+    const afmg_opts &o = s.o;
+    const int n = t->h.n_trees;
+    const bool fixed = o.fixed_cycles > 0;
+    const int nmax = fixed ? o.fixed_cycles : o.max_cycles;
+    for (int i = 0; i < n; i++) {
+        tr[(size_t)i].prev = S[i].r_max;
+        if (S[i].status != AFMG_OK) tr[(size_t)i].done = true;
+        tr[(size_t)i].conv = !fixed && S[i].r_max <= o.tol * S[i].r0_max;
+        if (tr[(size_t)i].conv) tr[(size_t)i].done = true;
+    }
+    for (int k = 0;; k++) {
+        bool any = false;
+        for (int i = 0; i < n; i++) {
+            Track &q = tr[(size_t)i];
+            if (!q.done && S[i].cycles >= nmax) q.done = true;
+            if (t->forest) t->h_active[i] = q.done ? 0 : 1;
+            any |= !q.done;
+        }
+        if (!any) break;
+        int rc = s.upload_mask();
+        if (rc == AFMG_OK) rc = step(k);
+        if (rc != AFMG_OK) return rc;
+        for (int i = 0; i < n; i++) {
+            Track &q = tr[(size_t)i];
+            if (q.done) continue;
+            afmg_stats &x = S[i];
+            x.r_max = t->h_norm[2 * i];
+            x.r_l2 = t->h_norm[2 * i + 1];
+            if (x.cycles < AFMG_HIST) {
+                x.hist_max[x.cycles] = x.r_max;
+                x.hist_l2[x.cycles] = x.r_l2;
+            }
+            x.cycles++;
+            if (!std::isfinite(x.r_max)) {
+                x.status = AFMG_ERR_NONFINITE;
+                q.done = true;
+                continue;
+            }
+            if (!fixed) {
+                q.grow = x.r_max > q.prev ? q.grow + 1 : 0;
+                if (q.grow >= 3) {
+                    x.status = AFMG_ERR_DIVERGED;
+                    q.done = true;
+                    continue;
+                }
+                q.conv = x.r_max <= o.tol * x.r0_max;
+                if (q.conv) q.done = true;
+            }
+            q.prev = x.r_max;
+        }
+    }
+    for (int i = 0; i < n; i++)
+        if (S[i].status == AFMG_OK && !fixed && !tr[(size_t)i].conv) S[i].status = AFMG_NOT_CONVERGED;
+    return AFMG_OK;
+}
+
+// norms of the trees marked in t->h_active (all trees for one tree) from
+// t->h_norm into the stats
+void take_norms(const afmg_tree *t, afmg_stats *S, bool initial) {
+    for (int i = 0; i < t->h.n_trees; i++) {
+        if (t->forest && !t->h_active[i]) continue;
+        if (initial) {
+            S[i].r0_max = t->h_norm[2 * i];
+            S[i].r0_l2 = t->h_norm[2 * i + 1];
+        }
+        S[i].r_max = t->h_norm[2 * i];
+        S[i].r_l2 = t->h_norm[2 * i + 1];
+    }
+}
+
 template <int D>
 int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, double *u, char *ws,
-          const afmg_opts &o, afmg_stats &S) {
+          const afmg_opts &o, afmg_stats *S) {
     const HostTree &h = t->h;
+    const int n = h.n_trees;
     const bool mixed = o.precision == AFMG_MIXED;
     const WsLayout L = ws_layout(t, o.precision);
-    Solver<D> s(t, st, o, &S);
+    Solver<D> s(t, st, o, &S[0]);
     if (o.profile && t->events.empty()) {
         t->events.resize(2 * PROF_PAIRS);
         for (auto &ev : t->events)
@@ -331,10 +557,11 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
     }
     double *rho_i = (double *)(ws + L.rho);
     double *bc_w = (double *)(ws + L.bc);
+    double *uw = t->forest ? (double *)(ws + L.u) : u;  // working u (colour-split)
     s.partial = (double *)(ws + L.partial);
     s.norm = (double *)(ws + L.norm);
-    s.base = LevelArgs<double>{t->d_info, u, rho_i, mixed ? nullptr : (double *)(ws + L.uold), bc_w, 0, 0, 0,
-                               0.0, 0.0};
+    s.base = LevelArgs<double>{t->d_info, uw, rho_i, mixed ? nullptr : (double *)(ws + L.uold), bc_w, 0, 0, 0,
+                               0.0, 0.0, t->d_active};
     const int64_t F = cells_per_face(D), C = cells_per_box(D);
 
     hipEvent_t ev0, ev1;
@@ -343,73 +570,113 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
     (void)hipEventRecord(ev0, st);
     // Dirichlet rows: caller's leaf rows, then parent rows from fine to coarse
     if (h.n_bfaces_leaf > 0) {
-        if (bc) {
+        if (!bc) {
+            launch_fill<double>(bc_w, h.n_bfaces_leaf * F, 0.0, st);
+        } else if (t->forest) {
+            launch_gather_rows(t->d_row_map, bc, bc_w, h.n_bfaces_leaf, (int)F, st);
+        } else {
             hipError_t e = hipMemcpyAsync(bc_w, bc, (size_t)(h.n_bfaces_leaf * F) * sizeof(double),
                                           hipMemcpyDeviceToDevice, st);
             if (e != hipSuccess) return hip_fail(e, "copy of Dirichlet values");
-        } else {
-            launch_fill<double>(bc_w, h.n_bfaces_leaf * F, 0.0, st);
         }
     }
     for (int l = h.lmax; l >= 2; l--)
         launch_bc_derive<D, BOX_N>(t->d_info, h.lvl_off[(size_t)l], h.level_count(l), bc_w, st);
     // working copies in the colour-split box layout: rho of the leaves, and
-    // u in place (a zero guess needs no conversion)
-    launch_load_rho<D, BOX_N, double>(t->d_info, rho, rho_i, h.n_boxes, st);
+    // u (in place for one tree; a zero guess needs no conversion)
+    const int32_t *map = t->forest ? t->d_box_map : nullptr;
+    launch_load_rho<D, BOX_N, double>(t->d_info, map, rho, rho_i, h.n_boxes, 1, st);
     const bool guess = o.use_guess && (mixed || o.cycle == AFMG_CYCLE_V);
-    if (!guess) launch_fill<double>(u, h.n_boxes * C, 0.0, st);
+    if (!guess) launch_fill<double>(uw, h.n_boxes * C, 0.0, st);
+    else if (t->forest) launch_load_rho<D, BOX_N, double>(t->d_info, map, u, uw, h.n_boxes, 0, st);
     else launch_permute<D, BOX_N, double>(t->d_info, u, 0, h.n_boxes, 1, 0, st);
 
     float *e32 = mixed ? (float *)(ws + L.e) : nullptr;
     float *rho32 = mixed ? (float *)(ws + L.rho_e) : nullptr;
-    int rc = s.finalize(S.r0_max, S.r0_l2, rho32);
+    // initial residual of every tree
+    if (t->forest)
+        for (int i = 0; i < n; i++) t->h_active[i] = 1;
+    int rc = s.upload_mask();
+    if (rc == AFMG_OK) rc = s.finalize(rho32);
     if (rc != AFMG_OK) return rc;
-    S.r_max = S.r0_max;
-    S.r_l2 = S.r0_l2;
-    int status = AFMG_OK;
-    if (!std::isfinite(S.r0_max)) {
-        status = AFMG_ERR_NONFINITE;
+    take_norms(t, S, true);
+    bool any = false;
+    for (int i = 0; i < n; i++) {
+        if (!std::isfinite(S[i].r0_max)) S[i].status = AFMG_ERR_NONFINITE;
+        any |= S[i].status == AFMG_OK;
+        if (t->forest) t->h_active[i] = S[i].status == AFMG_OK;
+    }
+    std::vector<Track> tr((size_t)n);
+    const uintptr_t wsk = (uintptr_t)ws, uk = (uintptr_t)uw;
+    const std::vector<uintptr_t> key{(uintptr_t)o.precision, wsk, uk, (uintptr_t)o.n_down, (uintptr_t)o.n_up,
+                                     (uintptr_t)o.n_base};
+    if (!any) {
+        // nothing to iterate
     } else if (!mixed) {
-        Cycler<D, double> cy{h, st, o, s.prof, s.base, bc_w};
+        Cycler<D, double> cy{h, st, o, s.prof, s.base, bc_w, t};
         if (o.cycle == AFMG_CYCLE_FMG_V) {
-            cy.fmg();
-            rc = s.finalize(S.r_max, S.r_l2, nullptr);
+            rc = s.upload_mask();
             if (rc != AFMG_OK) return rc;
+            cy.fmg();
+            if ((rc = s.finalize(nullptr)) != AFMG_OK) return rc;
+            take_norms(t, S, false);
         }
-        status = iterate(o, S, [&](int) {
-            cy.vcycle(h.lmax);
-            return s.finalize(S.r_max, S.r_l2, nullptr);
+        rc = iterate_trees(s, S, tr, [&](int) {
+            const int q = s.run(key, [&](hipStream_t cs) {
+                Cycler<D, double> c2 = cy;
+                c2.st = cs;
+                c2.vcycle(h.lmax);
+                s.finalize_launch(nullptr, cs);
+            });
+            return q != AFMG_OK ? q : s.read_norms();
         });
     } else {
         // FP32 V-cycles inside FP64 iterative refinement: solve L e = r with
         // homogeneous Dirichlet values in FP32 (coarsest grids in FP64),
         // u += e on the leaves, new FP64 residual
-        LevelArgs<float> b32{t->d_info, e32, rho32, (float *)(ws + L.uold_e), nullptr, 0, 0, 1, 0.f, 0.f};
-        Cycler<D, float> cy{h, st, o, s.prof, b32, nullptr};
-        status = iterate(o, S, [&](int k) {
-            if (k == 0 && o.cycle == AFMG_CYCLE_FMG_V) {
-                cy.fmg();
+        LevelArgs<float> b32{t->d_info, e32, rho32, (float *)(ws + L.uold_e), nullptr, 0, 0, 1, 0.f, 0.f,
+                             t->d_active};
+        Cycler<D, float> cy{h, st, o, s.prof, b32, nullptr, t};
+        auto refine = [&](hipStream_t cs, bool first_fmg) {
+            Cycler<D, float> c2 = cy;
+            c2.st = cs;
+            if (first_fmg) {
+                c2.fmg();
             } else {
-                launch_fill<float>(e32, h.n_boxes * C, 0.f, st);
-                cy.vcycle(h.lmax);
+                launch_fill<float>(e32, h.n_boxes * C, 0.f, cs);
+                c2.vcycle(h.lmax);
             }
-            launch_ir_update<D, BOX_N>(t->d_info, u, e32, h.n_boxes, st);
-            return s.finalize(S.r_max, S.r_l2, rho32);
+            launch_ir_update<D, BOX_N>(t->d_info, uw, e32, h.n_boxes, t->d_active, cs);
+            s.finalize_launch(rho32, cs);
+        };
+        rc = iterate_trees(s, S, tr, [&](int k) {
+            int q;
+            if (k == 0 && o.cycle == AFMG_CYCLE_FMG_V) {
+                refine(st, true);
+                q = AFMG_OK;
+            } else {
+                q = s.run(key, [&](hipStream_t cs) { refine(cs, false); });
+            }
+            return q != AFMG_OK ? q : s.read_norms();
         });
-        if (status < 0 && status != AFMG_ERR_NONFINITE && status != AFMG_ERR_DIVERGED) return status;
     }
-    if (!mixed && status < 0 && status != AFMG_ERR_NONFINITE && status != AFMG_ERR_DIVERGED) return status;
-    launch_permute<D, BOX_N, double>(t->d_info, u, 0, h.n_boxes, 0, 0, st);
+    if (rc != AFMG_OK) return rc;
+    if (t->forest) launch_store_boxes<D, BOX_N, double>(t->d_box_map, uw, u, h.n_boxes, st);
+    else launch_permute<D, BOX_N, double>(t->d_info, u, 0, h.n_boxes, 0, 0, st);
     (void)hipEventRecord(ev1, st);
     (void)hipEventSynchronize(ev1);
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, ev0, ev1);
-    S.t_ms = ms;
     (void)hipEventDestroy(ev0);
     (void)hipEventDestroy(ev1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "solve");
-    S.status = status;
+    int status = AFMG_OK;
+    for (int i = 0; i < n; i++) {
+        S[i].t_ms = ms;
+        if (S[i].status < 0 && status >= 0) status = S[i].status;
+        if (S[i].status == AFMG_NOT_CONVERGED && status == AFMG_OK) status = AFMG_NOT_CONVERGED;
+    }
     if (status == AFMG_ERR_NONFINITE) set_error("residual norm is not finite");
     if (status == AFMG_ERR_DIVERGED) set_error("residual grew for 3 consecutive cycles");
     if (status == AFMG_NOT_CONVERGED) set_error("max_cycles reached before the tolerance");
@@ -484,7 +751,7 @@ int apply_op(afmg_tree *t, hipStream_t st, int op, const double *x, double *y, c
     Adj<D> A{t, h, st, ws, adj_layout(t), h.n_boxes * cells_per_box(D), nullptr, nullptr};
     double *X = A.vec(AdjLayout::X), *Y = A.vec(AdjLayout::R);
     launch_fill<double>(X, A.n, 0.0, st);
-    launch_load_rho<D, BOX_N, double>(t->d_info, x, X, h.n_boxes, st);
+    launch_load_rho<D, BOX_N, double>(t->d_info, nullptr, x, X, h.n_boxes, 1, st);
     if (op == AFMG_OP_L) A.apply_l(X, Y);
     else A.apply_lt(X, Y);
     launch_store_leaves<D, BOX_N>(t->d_info, Y, y, h.n_boxes, st);
@@ -637,6 +904,8 @@ void afmg_default_opts(afmg_opts *o) {
     o->fixed_cycles = 0;
     o->use_guess = 0;
     o->precision = AFMG_FP64;
+    o->profile = 0;
+    o->graph = 0;
 }
 
 int afmg_tree_create(int dim, int box_n, int64_t n_leaves, const int32_t *level, const int32_t *idx,
@@ -647,7 +916,8 @@ int afmg_tree_create(int dim, int box_n, int64_t n_leaves, const int32_t *level,
     try {
         t = new afmg_tree();
         std::string msg;
-        int rc = build_tree(dim, box_n, n_leaves, level, idx, t->h, msg);
+        const int64_t off[2] = {0, n_leaves};
+        int rc = build_tree(dim, box_n, 1, off, level, idx, t->h, msg);
         if (rc != AFMG_OK) {
             delete t;
             return fail(rc, msg);
@@ -663,10 +933,7 @@ int afmg_tree_create(int dim, int box_n, int64_t n_leaves, const int32_t *level,
 
 void afmg_tree_destroy(afmg_tree *t) {
     if (!t) return;
-    if (t->d_info) (void)hipFree(t->d_info);
-    if (t->d_child) (void)hipFree(t->d_child);
-    if (t->h_norm) (void)hipHostFree(t->h_norm);
-    for (auto ev : t->events) (void)hipEventDestroy(ev);
+    release(t);
     delete t;
 }
 
@@ -776,8 +1043,139 @@ int afmg_solve(afmg_tree *t, void *stream, const double *rho, const double *bc, 
     rc = bind_device(t);
     if (rc != AFMG_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
-    if (t->h.dim == 3) return solve<3>(t, st, rho, bc, u, (char *)workspace, *opts, *stats);
-    return solve<2>(t, st, rho, bc, u, (char *)workspace, *opts, *stats);
+    if (t->h.dim == 3) return solve<3>(t, st, rho, bc, u, (char *)workspace, *opts, stats);
+    return solve<2>(t, st, rho, bc, u, (char *)workspace, *opts, stats);
+}
+
+int afmg_batch_create(afmg_tree *const *trees, int n_trees, afmg_batch **out) {
+    if (!out) return fail(AFMG_ERR_ARG, "out is null");
+    *out = nullptr;
+    if (!trees || n_trees < 1) return fail(AFMG_ERR_ARG, "empty batch");
+    for (int i = 0; i < n_trees; i++) {
+        if (!trees[i]) return fail(AFMG_ERR_ARG, "null tree");
+        if (trees[i]->forest) return fail(AFMG_ERR_ARG, "not a tree");
+        if (trees[i]->h.dim != trees[0]->h.dim || trees[i]->h.N != trees[0]->h.N)
+            return fail(AFMG_ERR_ARG, "trees of one batch must share dim and box_n");
+    }
+    afmg_batch *b = nullptr;
+    try {
+        b = new afmg_batch();
+        afmg_tree &f = b->f;
+        const int dim = trees[0]->h.dim;
+        // the trees' leaves, each tree in its own input order
+        std::vector<int64_t> off((size_t)n_trees + 1, 0), box_base((size_t)n_trees), row_base((size_t)n_trees);
+        for (int i = 0; i < n_trees; i++) {
+            const HostTree &h = trees[i]->h;
+            off[(size_t)i + 1] = off[(size_t)i] + h.n_leaves;
+            box_base[(size_t)i] = f.user_boxes;
+            row_base[(size_t)i] = f.user_rows;
+            f.user_boxes += h.n_boxes;
+            f.user_rows += h.n_bfaces_leaf;
+            f.user_unknowns += h.n_leaves * cells_per_box(dim);
+        }
+        if (f.user_boxes >= ((int64_t)1 << 30) || f.user_rows >= ((int64_t)1 << 31)) {
+            delete b;
+            return fail(AFMG_ERR_ARG, "batch too large");
+        }
+        std::vector<int32_t> level((size_t)off[(size_t)n_trees]), idx(3 * (size_t)off[(size_t)n_trees]);
+        for (int i = 0; i < n_trees; i++) {
+            const HostTree &h = trees[i]->h;
+            for (int64_t q = 0; q < h.n_leaves; q++) {
+                const size_t m = (size_t)h.leaf_box[(size_t)q], g = (size_t)(off[(size_t)i] + q);
+                level[g] = h.info[m].level;
+                idx[3 * g] = h.ix[m];
+                idx[3 * g + 1] = h.iy[m];
+                idx[3 * g + 2] = h.iz[m];
+            }
+        }
+        std::string msg;
+        int rc = build_tree(dim, trees[0]->h.N, n_trees, off.data(), level.data(), idx.data(), f.h, msg);
+        if (rc != AFMG_OK) {
+            delete b;
+            return fail(rc, msg);
+        }
+        f.forest = true;
+        // caller's box of each working box: inside one tree the working order
+        // is the tree's own order, level by level
+        const HostTree &fh = f.h;
+        f.box_map.assign((size_t)fh.n_boxes, 0);
+        std::vector<int64_t> seen((size_t)n_trees, 0);
+        int cur_level = 0;
+        for (int64_t m = 0; m < fh.n_boxes; m++) {
+            const BoxInfo &bi = fh.info[(size_t)m];
+            if (bi.level != cur_level) {
+                std::fill(seen.begin(), seen.end(), 0);
+                cur_level = bi.level;
+            }
+            const HostTree &h = trees[bi.tree]->h;
+            const int64_t local = h.lvl_off[(size_t)bi.level] + seen[(size_t)bi.tree]++;
+            if (local >= h.lvl_off[(size_t)bi.level + 1] || h.ix[(size_t)local] != fh.ix[(size_t)m] ||
+                h.iy[(size_t)local] != fh.iy[(size_t)m] || h.iz[(size_t)local] != fh.iz[(size_t)m]) {
+                delete b;
+                return fail(AFMG_ERR_TREE, "inconsistent box order in a batch");
+            }
+            f.box_map[(size_t)m] = (int32_t)(box_base[(size_t)bi.tree] + local);
+        }
+        f.row_map.assign((size_t)fh.n_bfaces_leaf, 0);
+        for (int64_t r = 0; r < fh.n_bfaces_leaf; r++) {
+            const int32_t m = fh.bface_box[(size_t)r];
+            const int tr = fh.info[(size_t)m].tree;
+            const int64_t local = f.box_map[(size_t)m] - box_base[(size_t)tr];
+            const int32_t row = trees[tr]->h.info[(size_t)local].bcoff[fh.bface_side[(size_t)r]];
+            f.row_map[(size_t)r] = (int32_t)(row_base[(size_t)tr] + row);
+        }
+    } catch (const std::bad_alloc &) {
+        delete b;
+        return fail(AFMG_ERR_OOM, "host allocation failed");
+    }
+    *out = b;
+    return AFMG_OK;
+}
+
+void afmg_batch_destroy(afmg_batch *b) {
+    if (!b) return;
+    release(&b->f);
+    delete b;
+}
+
+int afmg_batch_info(const afmg_batch *b, afmg_batch_desc *out) {
+    if (!b || !out) return fail(AFMG_ERR_ARG, "null argument");
+    const HostTree &h = b->f.h;
+    out->dim = h.dim;
+    out->box_n = h.N;
+    out->n_trees = h.n_trees;
+    out->lmax = h.lmax;
+    out->n_boxes = b->f.user_boxes;
+    out->n_bfaces = b->f.user_rows;
+    out->n_unknowns = b->f.user_unknowns;
+    return AFMG_OK;
+}
+
+int afmg_batch_workspace_bytes(const afmg_batch *b, const afmg_opts *o, size_t *bytes) {
+    if (!b || !bytes) return fail(AFMG_ERR_ARG, "null argument");
+    if (o) {
+        int rc = check_opts(o);
+        if (rc != AFMG_OK) return rc;
+    }
+    *bytes = ws_layout(&b->f, o ? o->precision : AFMG_FP64).total;
+    return AFMG_OK;
+}
+
+int afmg_batch_solve(afmg_batch *b, void *stream, const double *rho, const double *bc, double *u,
+                     void *workspace, size_t workspace_bytes, const afmg_opts *opts, afmg_stats *stats) {
+    if (!b || !rho || !u || !workspace || !stats) return fail(AFMG_ERR_ARG, "null argument");
+    int rc = check_opts(opts);
+    if (rc != AFMG_OK) return rc;
+    if (!aligned(rho, 8) || !aligned(u, 8) || (bc && !aligned(bc, 8)) || !aligned(workspace, 256))
+        return fail(AFMG_ERR_ARG, "misaligned array");
+    afmg_tree *f = &b->f;
+    if (workspace_bytes < ws_layout(f, opts->precision).total) return fail(AFMG_ERR_ARG, "workspace too small");
+    std::memset(stats, 0, sizeof(afmg_stats) * (size_t)f->h.n_trees);
+    rc = bind_device(f);
+    if (rc != AFMG_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (f->h.dim == 3) return solve<3>(f, st, rho, bc, u, (char *)workspace, *opts, stats);
+    return solve<2>(f, st, rho, bc, u, (char *)workspace, *opts, stats);
 }
 
 }  // extern "C"

@@ -1,6 +1,12 @@
-// Host-side tree construction from a leaf list (paper §2.1-§2.3): ancestors,
-// completeness and 2:1 checks, Morton order per level (§2.3), neighbour and
-// parent tables, and the numbering of Dirichlet rows.
+// Host-side construction of a tree, or a forest of independent trees, from
+// leaf lists (paper §2.1-§2.3): ancestors, completeness and 2:1 checks, Morton
+// order per level (§2.3), neighbour / parent / child tables, and the
+// numbering of Dirichlet rows.
+//
+// Box numbering: by level over the whole forest, then by tree, then Morton
+// index.  The boxes of one level of all trees form one contiguous range, the
+// roots (level 1) are boxes 0 .. n_trees-1, and inside one tree the relative
+// order of its boxes is the order the tree has on its own.
 #include <algorithm>
 #include <unordered_map>
 
@@ -11,12 +17,13 @@ namespace afmg {
 namespace {
 
 struct Key {
-    int l, i, j, k;
-    bool operator==(const Key &o) const { return l == o.l && i == o.i && j == o.j && k == o.k; }
+    int tr, l, i, j, k;
+    bool operator==(const Key &o) const { return tr == o.tr && l == o.l && i == o.i && j == o.j && k == o.k; }
 };
 struct KeyHash {
     size_t operator()(const Key &a) const {
         uint64_t x = (uint64_t)(uint32_t)a.l * 0x9E3779B97F4A7C15ULL;
+        x ^= (uint64_t)(uint32_t)a.tr + 0xD6E8FEB86659FD93ULL + (x << 6) + (x >> 2);
         x ^= (uint64_t)(uint32_t)a.i + 0x632BE59BD9B4E019ULL + (x << 6) + (x >> 2);
         x ^= (uint64_t)(uint32_t)a.j + 0x8CB92BA72F3D8DD7ULL + (x << 6) + (x >> 2);
         x ^= (uint64_t)(uint32_t)a.k + 0xA24BAED4963EE407ULL + (x << 6) + (x >> 2);
@@ -51,11 +58,15 @@ uint64_t morton(int dim, int i, int j, int k) {
 
 }  // namespace
 
-int build_tree(int dim, int N, int64_t n_leaves, const int32_t *level, const int32_t *idx,
+int build_tree(int dim, int N, int n_trees, const int64_t *tree_off, const int32_t *level, const int32_t *idx,
                HostTree &t, std::string &msg) {
     if (dim != 2 && dim != 3) { msg = "dim must be 2 or 3"; return AFMG_ERR_ARG; }
     if (N != 8) { msg = "box_n must be 8"; return AFMG_ERR_ARG; }
-    if (n_leaves <= 0 || !level || !idx) { msg = "empty or null leaf list"; return AFMG_ERR_ARG; }
+    if (n_trees <= 0 || !tree_off || !level || !idx) { msg = "empty or null leaf list"; return AFMG_ERR_ARG; }
+    if (tree_off[0] != 0) { msg = "leaf offsets must start at 0"; return AFMG_ERR_ARG; }
+    for (int tr = 0; tr < n_trees; tr++)
+        if (tree_off[tr + 1] <= tree_off[tr]) { msg = "empty or null leaf list"; return AFMG_ERR_ARG; }
+    const int64_t n_leaves = tree_off[n_trees];
     if (n_leaves > (int64_t)1 << 28) { msg = "too many leaves"; return AFMG_ERR_ARG; }
     const int max_level = dim == 3 ? 17 : 20;  // keeps box counts and indices in int32
     struct Box { Key key; bool leaf; int64_t input; };
@@ -63,22 +74,24 @@ int build_tree(int dim, int N, int64_t n_leaves, const int32_t *level, const int
     std::unordered_map<Key, int64_t, KeyHash> map;
     boxes.reserve((size_t)(n_leaves * 8 / 7 + 16));
     map.reserve((size_t)(n_leaves * 8 / 7 + 16));
-    for (int64_t q = 0; q < n_leaves; q++) {
-        Key k{level[q], idx[3 * q], idx[3 * q + 1], dim == 3 ? idx[3 * q + 2] : 1};
-        if (k.l < 1 || k.l > max_level) { msg = "leaf level out of range"; return AFMG_ERR_ARG; }
-        int n1 = 1 << (k.l - 1);
-        if (k.i < 1 || k.i > n1 || k.j < 1 || k.j > n1 || k.k < 1 || k.k > (dim == 3 ? n1 : 1)) {
-            msg = "leaf spatial index out of range";
-            return AFMG_ERR_ARG;
+    for (int tr = 0; tr < n_trees; tr++) {
+        for (int64_t q = tree_off[tr]; q < tree_off[tr + 1]; q++) {
+            Key k{tr, level[q], idx[3 * q], idx[3 * q + 1], dim == 3 ? idx[3 * q + 2] : 1};
+            if (k.l < 1 || k.l > max_level) { msg = "leaf level out of range"; return AFMG_ERR_ARG; }
+            int n1 = 1 << (k.l - 1);
+            if (k.i < 1 || k.i > n1 || k.j < 1 || k.j > n1 || k.k < 1 || k.k > (dim == 3 ? n1 : 1)) {
+                msg = "leaf spatial index out of range";
+                return AFMG_ERR_ARG;
+            }
+            auto ins = map.emplace(k, (int64_t)boxes.size());
+            if (!ins.second) { msg = "duplicate leaf"; return AFMG_ERR_TREE; }
+            boxes.push_back({k, true, q});
         }
-        auto ins = map.emplace(k, (int64_t)boxes.size());
-        if (!ins.second) { msg = "duplicate leaf"; return AFMG_ERR_TREE; }
-        boxes.push_back({k, true, q});
     }
     for (int64_t q = 0; q < n_leaves; q++) {
         Key k = boxes[(size_t)q].key;
         while (k.l > 1) {
-            Key p{k.l - 1, (k.i + 1) / 2, (k.j + 1) / 2, dim == 3 ? (k.k + 1) / 2 : 1};
+            Key p{k.tr, k.l - 1, (k.i + 1) / 2, (k.j + 1) / 2, dim == 3 ? (k.k + 1) / 2 : 1};
             auto it = map.find(p);
             if (it != map.end()) {
                 if (boxes[(size_t)it->second].leaf) { msg = "a leaf overlaps finer leaves"; return AFMG_ERR_TREE; }
@@ -94,17 +107,18 @@ int build_tree(int dim, int N, int64_t n_leaves, const int32_t *level, const int
     for (const Box &b : boxes) {
         if (b.leaf) continue;
         for (int c = 0; c < nch; c++) {
-            Key ch{b.key.l + 1, 2 * b.key.i - 1 + (c & 1), 2 * b.key.j - 1 + ((c >> 1) & 1),
+            Key ch{b.key.tr, b.key.l + 1, 2 * b.key.i - 1 + (c & 1), 2 * b.key.j - 1 + ((c >> 1) & 1),
                    dim == 3 ? 2 * b.key.k - 1 + ((c >> 2) & 1) : 1};
             if (!map.count(ch)) { msg = "leaves do not tile the domain"; return AFMG_ERR_TREE; }
         }
     }
-    // order: level, then Morton index
+    // order: level, tree, Morton index
     std::vector<int64_t> order(boxes.size());
     for (size_t m = 0; m < order.size(); m++) order[m] = (int64_t)m;
     std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
         const Key &x = boxes[(size_t)a].key, &y = boxes[(size_t)b].key;
         if (x.l != y.l) return x.l < y.l;
+        if (x.tr != y.tr) return x.tr < y.tr;
         return morton(dim, x.i, x.j, x.k) < morton(dim, y.i, y.j, y.k);
     });
     const int64_t nb = (int64_t)boxes.size();
@@ -113,12 +127,14 @@ int build_tree(int dim, int N, int64_t n_leaves, const int32_t *level, const int
     for (int64_t m = 0; m < nb; m++) newid[(size_t)order[(size_t)m]] = m;
     t.dim = dim;
     t.N = N;
+    t.n_trees = n_trees;
     t.n_boxes = nb;
     t.n_leaves = n_leaves;
     int lg = 0;
     while ((1 << (lg + 1)) < N) lg++;  // N = 2^(lg+1)
     t.lmin = 1 - lg;
     t.lmax = 1;
+    t.tree_lmax.assign((size_t)n_trees, 1);
     t.info.assign((size_t)nb, BoxInfo{});
     t.ix.resize((size_t)nb);
     t.iy.resize((size_t)nb);
@@ -130,9 +146,11 @@ int build_tree(int dim, int N, int64_t n_leaves, const int32_t *level, const int
         t.iz[(size_t)m] = b.key.k;
         BoxInfo &bi = t.info[(size_t)m];
         bi.level = b.key.l;
+        bi.tree = b.key.tr;
         bi.flags = (b.leaf ? FLAG_LEAF : 0) | (((b.key.i - 1) & 1) << 1) | (((b.key.j - 1) & 1) << 2) |
                    (dim == 3 ? (((b.key.k - 1) & 1) << 3) : 0);
         if (b.key.l > t.lmax) t.lmax = b.key.l;
+        if (b.key.l > t.tree_lmax[(size_t)b.key.tr]) t.tree_lmax[(size_t)b.key.tr] = b.key.l;
         for (int s = 0; s < 6; s++) { bi.nbr[s] = -1; bi.bcoff[s] = -1; }
         bi.parent = -1;
     }
@@ -149,9 +167,9 @@ int build_tree(int dim, int N, int64_t n_leaves, const int32_t *level, const int
     // parents, neighbours, 2:1 balance
     for (int64_t m = 0; m < nb; m++) {
         BoxInfo &bi = t.info[(size_t)m];
-        const Key key{bi.level, t.ix[(size_t)m], t.iy[(size_t)m], t.iz[(size_t)m]};
+        const Key key{bi.tree, bi.level, t.ix[(size_t)m], t.iy[(size_t)m], t.iz[(size_t)m]};
         if (key.l > 1) {
-            Key p{key.l - 1, (key.i + 1) / 2, (key.j + 1) / 2, dim == 3 ? (key.k + 1) / 2 : 1};
+            Key p{key.tr, key.l - 1, (key.i + 1) / 2, (key.j + 1) / 2, dim == 3 ? (key.k + 1) / 2 : 1};
             bi.parent = (int32_t)newid[(size_t)map.at(p)];
         }
         const int n1 = 1 << (key.l - 1);
@@ -160,11 +178,11 @@ int build_tree(int dim, int N, int64_t n_leaves, const int32_t *level, const int
             int q[3] = {key.i, key.j, key.k};
             q[d] += dir;
             if (q[d] < 1 || q[d] > n1) { bi.nbr[s] = -1; continue; }
-            auto it = map.find(Key{key.l, q[0], q[1], q[2]});
+            auto it = map.find(Key{key.tr, key.l, q[0], q[1], q[2]});
             if (it != map.end()) { bi.nbr[s] = (int32_t)newid[(size_t)it->second]; continue; }
             int pq[3] = {(key.i + 1) / 2, (key.j + 1) / 2, dim == 3 ? (key.k + 1) / 2 : 1};
             pq[d] += dir;
-            auto itp = map.find(Key{key.l - 1, pq[0], pq[1], pq[2]});
+            auto itp = map.find(Key{key.tr, key.l - 1, pq[0], pq[1], pq[2]});
             if (itp == map.end()) { msg = "grid is not 2:1 balanced across a box side"; return AFMG_ERR_TREE; }
             bi.nbr[s] = -2 - (int32_t)newid[(size_t)itp->second];
         }
@@ -178,13 +196,26 @@ int build_tree(int dim, int N, int64_t n_leaves, const int32_t *level, const int
             t.child[(size_t)bi.parent * 8 + oc] = (int32_t)m;
         }
     }
+    t.uniform = true;
     for (int64_t m = 0; m < nb; m++) {
         BoxInfo &bi = t.info[(size_t)m];
-        if ((bi.flags & FLAG_LEAF) && bi.level != t.lmax) t.uniform = false;
+        if ((bi.flags & FLAG_LEAF) && bi.level != t.tree_lmax[(size_t)bi.tree]) t.uniform = false;
         for (int s = 0; s < 2 * dim; s++) {
             const int v = bi.nbr[s];
             if (v >= 0 && !(t.info[(size_t)v].flags & FLAG_LEAF)) bi.flags |= FLAG_NBR_REFINED << s;
         }
+    }
+    // leaf boxes of each tree, in box order (per-tree residual norms)
+    t.tree_leaf_ptr.assign((size_t)n_trees + 1, 0);
+    for (int64_t m = 0; m < nb; m++)
+        if (t.info[(size_t)m].flags & FLAG_LEAF) t.tree_leaf_ptr[(size_t)t.info[(size_t)m].tree + 1]++;
+    for (int tr = 0; tr < n_trees; tr++) t.tree_leaf_ptr[(size_t)tr + 1] += t.tree_leaf_ptr[(size_t)tr];
+    t.tree_leaf_box.assign((size_t)n_leaves, 0);
+    {
+        std::vector<int64_t> next(t.tree_leaf_ptr.begin(), t.tree_leaf_ptr.end() - 1);
+        for (int64_t m = 0; m < nb; m++)
+            if (t.info[(size_t)m].flags & FLAG_LEAF)
+                t.tree_leaf_box[(size_t)next[(size_t)t.info[(size_t)m].tree]++] = (int32_t)m;
     }
     // Dirichlet rows: leaf sides first (box order, side order), then parents
     t.bface_box.clear();

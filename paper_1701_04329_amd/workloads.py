@@ -391,6 +391,101 @@ def random_fields(dim, N, level, idx, seed):
                     np.asarray(idx, np.int32), rho, bc)
 
 
+def _morton_key(dim, i, j, k):
+    key, bit = 0, 0
+    a, b, c = i - 1, j - 1, k - 1
+    while a or b or c:
+        key |= (a & 1) << bit | (b & 1) << (bit + 1)
+        if dim == 3:
+            key |= (c & 1) << (bit + 2)
+        a, b, c = a >> 1, b >> 1, c >> 1
+        bit += dim
+    return key
+
+
+def greedy_leaves(dim, N, mix: GaussMix, target_boxes, max_level=None):
+    """Refine one leaf at a time, the leaf with the largest max |lap u| h^2
+    first (ties: coarser level, then lower Morton key), until the tree holds
+    at least target_boxes boxes (parents and leaves, levels >= 1).  Before a
+    leaf is refined its coarser neighbours (diagonals included) are refined,
+    recursively, so the grid stays 2:1 balanced."""
+    import heapq
+
+    ls = _LeafSet(dim)
+    offs = _neighbour_offsets(dim)
+    max_level = max_level or (12 if dim == 3 else 16)
+    heap = []
+    n_boxes = 1
+
+    def push(keys):
+        lev = np.array([k[0] for k in keys], dtype=np.int32)
+        idx = np.array([k[1:] for k in keys], dtype=np.int32)
+        h = box_h(lev, N)
+        score = (np.abs(mix.laplacian(cell_centres(dim, N, lev, idx))) * (h[:, None] ** 2)).max(axis=1)
+        for key, sc in zip(keys, score):
+            heapq.heappush(heap, (-float(sc), key[0], _morton_key(dim, *key[1:]), key))
+
+    def children(key):
+        l, i, j, k = key
+        out = []
+        for dk in ((0, 1) if dim == 3 else (0,)):
+            for dj in (0, 1):
+                for di in (0, 1):
+                    out.append((l + 1, 2 * i - 1 + di, 2 * j - 1 + dj, 2 * k - 1 + dk if dim == 3 else 1))
+        return out
+
+    def refine(key):
+        nonlocal n_boxes
+        l, i, j, k = key
+        for o in offs:
+            nb = ls.covering_leaf(l, i + o[0], j + o[1], (k + o[2]) if dim == 3 else 1)
+            if nb is not None and nb[0] < l:
+                refine(nb)
+        ls.refine(key)
+        n_boxes += 2 ** dim
+        push(children(key))
+
+    push([(1, 1, 1, 1)])
+    while n_boxes < target_boxes and heap:
+        _, _, _, key = heapq.heappop(heap)
+        if key in ls.leaves and key[0] < max_level:
+            refine(key)
+    return ls.arrays()
+
+
+def config4_tree(j, N=BOX_N_DEFAULT, box_range=(64, 8192), seed_base=4000):
+    """Tree j of the batch workload: D = 2 for even j, 3 for odd j; 1-3
+    Gaussians with centres in [0.25, 0.75]^D and sigma log-uniform in
+    [0.02, 0.1]; a box target log-uniform in box_range; zero Dirichlet
+    values.  All draws come from one generator seeded with seed_base + j."""
+    dim = 2 if j % 2 == 0 else 3
+    rng = np.random.default_rng(seed_base + j)
+    n_src = int(rng.integers(1, 4))
+    centres = rng.uniform(0.25, 0.75, size=(n_src, dim))
+    sig = np.exp(rng.uniform(math.log(0.02), math.log(0.1), size=n_src))
+    target = int(round(math.exp(rng.uniform(math.log(box_range[0]), math.log(box_range[1])))))
+    mix = GaussMix(centres, sig, np.ones(n_src))
+    lev, idx = greedy_leaves(dim, N, mix, target)
+    w = sample_workload(f"c4_tree{j}_{dim}d", dim, N, lev, idx, mix, bc_from_mix=False)
+    return w
+
+
+def _config4_one(args):
+    return config4_tree(*args)
+
+
+def config4(n_trees=256, N=BOX_N_DEFAULT, box_range=(64, 8192), seed_base=4000, workers=1):
+    """The batch workload: n_trees independent trees (config4_tree), built
+    in `workers` fresh processes when workers > 1."""
+    args = [(j, N, box_range, seed_base) for j in range(n_trees)]
+    if workers <= 1:
+        return [_config4_one(a) for a in args]
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_config4_one, args, chunksize=4))
+
+
 def ball_flag(dim, N, centre, radius):
     """Flag the cells that intersect the ball |x - centre| <= radius."""
     p = np.asarray(centre, dtype=np.float64)[:dim]

@@ -149,3 +149,42 @@ def test_workspace_and_argument_checks_without_device():
     assert rc == A.AFMG_ERR_ARG
     rc = L.afmg_solve(t.handle, None, fake, None, fake, fake, 16, C.byref(o), C.byref(st))
     assert rc == A.AFMG_ERR_ARG and "workspace" in A.last_error()
+
+
+def test_batch_create_sums_and_validation():
+    trees = [A.Tree(3, *W.uniform_leaves(3, 2)), A.Tree(3, *W.ball_leaves(3, 8, 4, (0.3, 0.6, 0.4), 0.0, 1)),
+             A.Tree(3, *W.uniform_leaves(3, 1))]
+    b = A.Batch(trees)
+    assert b.n_trees == 3 and b.dim == 3 and b.box_n == 8
+    assert b.n_boxes == sum(t.n_boxes for t in trees)
+    assert b.n_bfaces == sum(t.n_bfaces for t in trees)
+    assert b.n_unknowns == sum(t.n_unknowns for t in trees)
+    assert b.lmax == max(t.lmax for t in trees)
+    # the workspace holds the working u besides what one solve needs
+    assert b.workspace_bytes() > sum(t.workspace_bytes() for t in trees)
+    # the trees' topology was copied: the batch outlives them
+    del trees
+    assert b.workspace_bytes() > 0
+    with pytest.raises(A.AfmgError) as e:
+        A.Batch([A.Tree(2, *W.uniform_leaves(2, 2)), A.Tree(3, *W.uniform_leaves(3, 2))])
+    assert e.value.code == A.AFMG_ERR_ARG
+    L = A.lib()
+    h = C.c_void_p()
+    assert L.afmg_batch_create(None, 1, C.byref(h)) == A.AFMG_ERR_ARG
+    arr = (C.c_void_p * 1)(None)
+    assert L.afmg_batch_create(arr, 1, C.byref(h)) == A.AFMG_ERR_ARG
+    assert L.afmg_batch_create(arr, 0, C.byref(h)) == A.AFMG_ERR_ARG
+
+
+def test_batch_workload_generator():
+    """The batch trees: seeded, deterministic, sizes near their box target,
+    D alternating, valid trees (the library accepts them)."""
+    for j in (0, 1, 6, 7):
+        w = W.config4_tree(j)
+        w2 = W.config4_tree(j)
+        assert np.array_equal(w.level, w2.level) and np.array_equal(w.rho, w2.rho)
+        assert w.dim == (2 if j % 2 == 0 else 3)
+        assert not w.bc.any()
+        t = A.Tree(w.dim, w.level, w.idx)
+        assert t.n_boxes >= 64
+        assert t.n_boxes <= 8192 + 2 ** w.dim * 64
