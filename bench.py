@@ -84,6 +84,100 @@ def cpu_baseline(w, solve_kw):
     }
 
 
+def batch_bench(args, A, torch, dev, stream):
+    """The batch workload: independent trees of 64-8192 boxes, D alternating
+    2/3, 1-3 Gaussian sources, zero Dirichlet values.  One step solves every
+    tree (FMG, then V-cycles until each tree's own residual dropped by 1e-10):
+    one batch per dimension, one after the other on the stream."""
+    from oracle import oracle as O
+    from paper_1701_04329_amd import workloads as W
+
+    workers = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    ws = W.config4(args.batch_trees, workers=workers)
+    gen_s = time.perf_counter() - t0
+    groups = []
+    for dim in (2, 3):
+        sub = [w for w in ws if w.dim == dim]
+        if not sub:
+            continue
+        trees = [A.Tree(w.dim, w.level, w.idx) for w in sub]
+        b = A.Batch(trees)
+        rho = b.concat([t.leaf_to_boxes(torch.tensor(w.rho, device=dev)) for t, w in zip(trees, sub)])
+        u = torch.zeros_like(rho)
+        groups.append(dict(dim=dim, sub=sub, trees=trees, b=b, rho=rho, u=u, work={}))
+    n_unk = sum(g["b"].n_unknowns for g in groups)
+
+    def step(precision, graph=True):
+        sts = []
+        for g in groups:
+            key = precision
+            if key not in g["work"]:
+                nb = g["b"].workspace_bytes(A.make_opts(precision=precision))
+                g["work"][key] = torch.empty(nb, dtype=torch.uint8, device=dev)
+            _, st = A.solve_batch(g["b"], g["rho"], None, g["u"], cycle="FMG", tol=1e-10, precision=precision,
+                                  workspace=g["work"][key], stream=stream, use_guess=False, graph=graph)
+            sts.append(st)
+        return sts
+
+    res = {}
+    sols = {}
+    for precision in ("fp64", "mixed"):
+        for _ in range(args.warmup):
+            step(precision)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            sts = step(precision)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        cyc = [s["cycles"] for st in sts for s in st]
+        res[precision] = {"value": n_unk / (ms * 1e-3), "unit": "unknowns/s", "ms_per_step": ms,
+                          "cycles_min": int(min(cyc)), "cycles_max": int(max(cyc)),
+                          "cycles_median": float(np.median(cyc)),
+                          "all_converged": bool(all(s["status"] == 0 for st in sts for s in st))}
+        sols[precision] = [[t.boxes_to_leaf(x).cpu().numpy() for t, x in zip(g["trees"], g["b"].split(g["u"]))]
+                           for g in groups]
+    # per-tree error of the mixed solution against the FP64 one
+    errs = [float(np.linalg.norm(m - f) / np.linalg.norm(f))
+            for gm, gf in zip(sols["mixed"], sols["fp64"]) for m, f in zip(gm, gf)]
+    # the same trees solved one at a time (one pass, mixed, graph replay)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g in groups:
+        for t, w in zip(g["trees"], g["sub"]):
+            r = t.leaf_to_boxes(torch.tensor(w.rho, device=dev))
+            A.solve(t, r, None, None, cycle="FMG", tol=1e-10, precision="mixed", stream=stream, graph=True)
+    torch.cuda.synchronize()
+    unbatched_ms = (time.perf_counter() - t0) * 1e3
+    # oracle check of the smallest tree of each dimension
+    oracle = {}
+    for gi, g in enumerate(groups):
+        q = int(np.argmin([w.n_unknowns for w in g["sub"]]))
+        w = g["sub"][q]
+        uo, _ = O.Tree(w.dim, w.N, w.level, w.idx).solve(w.rho, w.bc, cycle="FMG", tol=1e-10)
+        nrm = np.linalg.norm(uo)
+        oracle[w.name] = {"fp64": float(np.linalg.norm(sols["fp64"][gi][q] - uo) / nrm),
+                          "mixed": float(np.linalg.norm(sols["mixed"][gi][q] - uo) / nrm)}
+    return {
+        "workload": f"c4_batch_{args.batch_trees}_trees",
+        "trees": len(ws),
+        "unknowns": int(n_unk),
+        "boxes": int(sum(g["b"].n_boxes for g in groups)),
+        "per_dim": {f"{g['dim']}d": {"trees": len(g["sub"]), "unknowns": int(g["b"].n_unknowns),
+                                     "boxes": int(g["b"].n_boxes), "lmax": g["b"].lmax} for g in groups},
+        "fp64": res["fp64"],
+        "mixed": res["mixed"],
+        "mixed_vs_fp64_rel_l2_max": max(errs),
+        "mixed_vs_fp64_rel_l2_median": float(np.median(errs)),
+        "unbatched_mixed_ms": unbatched_ms,
+        "oracle_rel_l2_smallest_trees": oracle,
+        "generation_s": round(gen_s, 1),
+        "note": "one step = every tree solved (FMG, then V(2,2) until its own residual dropped by 1e-10), "
+                "one batch launch sequence per dimension, cycles replayed from recorded HIP graphs",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +185,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2", choices=["c2", "c1"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-tree batch workload")
+    ap.add_argument("--batch-trees", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -127,9 +223,10 @@ def main():
     ws = torch.empty(tree.workspace_bytes(opts), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream(dev)
 
-    def timed_steps(precision):
+    def timed_steps(precision, graph=False):
         """warmup + exactly `steps` timed solves; returns ms/step, the
-        summed event timings of the finest-level kernels and the last stats."""
+        summed event timings of the finest-level kernels (without graph
+        replay) and the last stats."""
         kw = dict(solve_kw, precision=precision)
         ws_p = ws if tree.workspace_bytes(A.make_opts(**kw)) <= ws.numel() else torch.empty(
             tree.workspace_bytes(A.make_opts(**kw)), dtype=torch.uint8, device=dev)
@@ -137,7 +234,7 @@ def main():
         def one(profile):
             # every step starts from u = 0 (the library zeroes u itself)
             return A.solve(tree, rho, bc, u, workspace=ws_p, stream=stream, profile=profile,
-                           use_guess=False, **kw)
+                           use_guess=False, graph=graph, **kw)
 
         for _ in range(args.warmup):
             one(False)
@@ -147,7 +244,7 @@ def main():
         cycles = []
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            _, st = one(True)
+            _, st = one(not graph)
             prof_ms += np.array(st["prof_ms"])
             prof_n += np.array(st["prof_n"], dtype=np.int64)
             cycles.append(st["cycles"])
@@ -197,6 +294,13 @@ def main():
         "dominant_avg_launch_ms": round(avg_m, 5),
     }
 
+    # the repeated cycle replayed from a recorded HIP graph (no per-kernel events)
+    ms_g, _, _, _, _ = timed_steps("fp64", graph=True)
+    ms_gm, _, _, _, _ = timed_steps("mixed", graph=True)
+    mixed["graph_ms_per_step"] = ms_gm
+    graph = {"fp64_ms_per_step": ms_g, "mixed_ms_per_step": ms_gm,
+             "fp64_value": w.n_unknowns / (ms_g * 1e-3), "mixed_value": w.n_unknowns / (ms_gm * 1e-3)}
+
     out = {
         "metric": "Poisson unknowns/s to 1e-10 residual reduction (FP64 vs mixed); HBM % of peak",
         "value": value,
@@ -224,7 +328,10 @@ def main():
         },
         "roofline": roofline,
         "mixed": mixed,
+        "graph": graph,
     }
+    if not args.no_batch:
+        out["batch"] = batch_bench(args, A, torch, dev, stream)
     if not args.no_cpu_baseline:
         uo, out["cpu_baseline"] = cpu_baseline(w, solve_kw)
         nrm = np.linalg.norm(uo)
