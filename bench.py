@@ -120,6 +120,24 @@ def batch_bench(args, A, torch, dev, stream):
             sts.append(st)
         return sts
 
+    def timed(precision):
+        for _ in range(args.warmup):
+            step(precision)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            sts = step(precision)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / args.steps, sts
+
+    untuned = None
+    if not args.no_autotune:
+        untuned = {f"{p}_ms_per_step": timed(p)[0] for p in ("fp64", "mixed")}
+        t0 = time.perf_counter()
+        for g in groups:
+            g["b"].autotune(dev, stream)
+        untuned["autotune_s"] = round(time.perf_counter() - t0, 3)
+
     res = {}
     sols = {}
     for precision in ("fp64", "mixed"):
@@ -171,6 +189,7 @@ def batch_bench(args, A, torch, dev, stream):
         "mixed_vs_fp64_rel_l2_max": max(errs),
         "mixed_vs_fp64_rel_l2_median": float(np.median(errs)),
         "unbatched_mixed_ms": unbatched_ms,
+        "untuned": untuned,
         "oracle_rel_l2_smallest_trees": oracle,
         "generation_s": round(gen_s, 1),
         "note": "one step = every tree solved (FMG, then V(2,2) until its own residual dropped by 1e-10), "
@@ -187,6 +206,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-tree batch workload")
     ap.add_argument("--batch-trees", type=int, default=256)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -251,6 +271,17 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         return (t1 - t0) * 1e3 / args.steps, prof_ms, prof_n, st, cycles
+
+    # launch shapes: untuned time first, then the autotuner (setup, untimed)
+    tune = None
+    if not args.no_autotune:
+        ms_untuned, _, _, _, _ = timed_steps("fp64", graph=True)
+        ms_untuned_m, _, _, _, _ = timed_steps("mixed", graph=True)
+        t0 = time.perf_counter()
+        shapes = tree.autotune(dev, stream)
+        tune = {"untuned_fp64_graph_ms_per_step": ms_untuned, "untuned_mixed_graph_ms_per_step": ms_untuned_m,
+                "autotune_s": round(time.perf_counter() - t0, 3),
+                "shapes": {f"{p}/{k}": [f"{wg}{'' if nr else 'x'}" for wg, nr in v] for (p, k), v in shapes.items()}}
 
     # FP64: the headline step
     ms, prof_ms, prof_n, st64, cycles = timed_steps("fp64")
@@ -329,6 +360,7 @@ def main():
         "roofline": roofline,
         "mixed": mixed,
         "graph": graph,
+        "autotune": tune,
     }
     if not args.no_batch:
         out["batch"] = batch_bench(args, A, torch, dev, stream)

@@ -261,6 +261,51 @@ int afmg_batch_solve(afmg_batch *batch, void *stream, const double *rho, const d
                      void *workspace, size_t workspace_bytes, const afmg_opts *opts,
                      afmg_stats *stats);
 
+/*
+ * Launch shapes and the autotuner.
+ *
+ * The per-level kernels of the cycle run in workgroups of 64, 128 or 256
+ * threads, one thread per x-row of a box (N^(D-1) threads per box, so 1, 2
+ * or 4 boxes per workgroup in 3D and 8, 16 or 32 in 2D), and either hand each
+ * of the eight XCDs a contiguous run of boxes (siblings and neighbours share
+ * that XCD's L2) or take boxes in launch order.  The shape is chosen per
+ * kernel class, level and precision; every shape computes bitwise the same
+ * values.  The default is 256 threads with XCD runs.
+ */
+typedef enum {
+    AFMG_K_GSRB = 0,       /* red-black half sweep (§3.1) */
+    AFMG_K_RESID = 1,      /* residual + restriction (eq. residual, §2.5) */
+    AFMG_K_COARSE_RHS = 2, /* FAS right-hand side and the copy v' (eq. coarse-rhs) */
+    AFMG_K_PROLONG = 3,    /* prolongation + correction (eq. coarse-corr) */
+    AFMG_K_FINAL = 4,      /* restriction of u + composite leaf residual (FP64 only) */
+    AFMG_K_KINDS = 5
+} afmg_kernel_kind;
+
+/* Device workspace bytes afmg_tree_autotune needs (scratch, 256-aligned). */
+int afmg_autotune_workspace_bytes(const afmg_tree *tree, size_t *bytes);
+
+/*
+ * Time every shape of every kernel class on every level of the tree, for
+ * FP64 and FP32 arrays, on zero-filled scratch arrays in workspace, and keep
+ * the fastest for later solves (the default unless another is at least 3%
+ * faster).  Synchronises the stream.  Errors: AFMG_ERR_ARG, AFMG_ERR_HIP.
+ */
+int afmg_tree_autotune(afmg_tree *tree, void *stream, void *workspace, size_t workspace_bytes);
+
+/* Shape of kernel class `kind` on level `level` (1 .. lmax) for precision 0
+   (FP64 arrays) or 1 (FP32 arrays of the mixed refinement). */
+int afmg_tree_shape(const afmg_tree *tree, int precision, int kind, int level, int *wg, int *no_remap);
+
+/* Set a shape; -1 for precision, kind or level selects all of them.
+   wg in {64, 128, 256}, no_remap in {0, 1}.  Errors: AFMG_ERR_ARG. */
+int afmg_tree_set_shape(afmg_tree *tree, int precision, int kind, int level, int wg, int no_remap);
+
+/* The same for a batch (its levels are those of the whole batch). */
+int afmg_batch_autotune_workspace_bytes(const afmg_batch *batch, size_t *bytes);
+int afmg_batch_autotune(afmg_batch *batch, void *stream, void *workspace, size_t workspace_bytes);
+int afmg_batch_shape(const afmg_batch *batch, int precision, int kind, int level, int *wg, int *no_remap);
+int afmg_batch_set_shape(afmg_batch *batch, int precision, int kind, int level, int wg, int no_remap);
+
 /* Message for the last failing call on this thread. */
 const char *afmg_last_error(void);
 

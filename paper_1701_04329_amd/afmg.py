@@ -110,8 +110,11 @@ EXPORTS = [
     "afmg_tree_leaf_boxes", "afmg_tree_bfaces", "afmg_tree_box", "afmg_workspace_bytes",
     "afmg_solve", "afmg_last_error", "afmg_adjoint_workspace_bytes", "afmg_apply", "afmg_adjoint",
     "afmg_batch_create", "afmg_batch_destroy", "afmg_batch_info", "afmg_batch_workspace_bytes",
-    "afmg_batch_solve",
+    "afmg_batch_solve", "afmg_autotune_workspace_bytes", "afmg_tree_autotune", "afmg_tree_shape",
+    "afmg_tree_set_shape", "afmg_batch_autotune_workspace_bytes", "afmg_batch_autotune", "afmg_batch_shape",
+    "afmg_batch_set_shape",
 ]
+KINDS = {"gsrb": 0, "resid": 1, "coarse_rhs": 2, "prolong": 3, "final": 4}
 OPS = {"L": 0, "LT": 1}
 
 _lib = None
@@ -155,6 +158,13 @@ def lib():
         L.afmg_batch_info.argtypes = [vp, C.POINTER(BatchDesc)]
         L.afmg_batch_workspace_bytes.argtypes = [vp, C.POINTER(Opts), C.POINTER(C.c_size_t)]
         L.afmg_batch_solve.argtypes = [vp, vp, vp, vp, vp, vp, C.c_size_t, C.POINTER(Opts), C.POINTER(Stats)]
+        ip = C.POINTER(C.c_int)
+        for pre in ("tree", "batch"):
+            getattr(L, f"afmg_{pre}_autotune").argtypes = [vp, vp, vp, C.c_size_t]
+            getattr(L, f"afmg_{pre}_shape").argtypes = [vp, C.c_int, C.c_int, C.c_int, ip, ip]
+            getattr(L, f"afmg_{pre}_set_shape").argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
+        L.afmg_autotune_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+        L.afmg_batch_autotune_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
         _lib = L
     return _lib
 
@@ -185,7 +195,48 @@ def make_opts(cycle="V", n_down=2, n_up=2, n_base=4, tol=1e-10, max_cycles=100, 
     return o
 
 
-class Tree:
+class _Shapes:
+    """Launch shapes and the autotuner (shared by Tree and Batch)."""
+
+    _pre = "tree"
+
+    def shape(self, precision, kind, level):
+        """(workgroup size, no_remap) of a kernel class on a level."""
+        wg, nr = C.c_int(), C.c_int()
+        _check(getattr(lib(), f"afmg_{self._pre}_shape")(self._h, PRECISIONS.get(precision, precision),
+                                                          KINDS.get(kind, kind), level, C.byref(wg), C.byref(nr)))
+        return wg.value, nr.value
+
+    def shapes(self):
+        out = {}
+        for p in ("fp64", "mixed"):
+            for k in KINDS:
+                if k == "final" and p == "mixed":
+                    continue
+                out[(p, k)] = [self.shape(p, k, l) for l in range(1, self.lmax + 1)]
+        return out
+
+    def set_shape(self, wg, no_remap=0, precision=-1, kind=-1, level=-1):
+        _check(getattr(lib(), f"afmg_{self._pre}_set_shape")(self._h, PRECISIONS.get(precision, precision),
+                                                              KINDS.get(kind, kind), level, wg, no_remap))
+
+    def autotune(self, device=None, stream=None):
+        """Time every launch shape on this grid and keep the fastest."""
+        import torch
+        dev = device or torch.device("cuda", 0)
+        n = C.c_size_t()
+        _check(getattr(lib(), f"afmg_{'' if self._pre == 'tree' else 'batch_'}autotune_workspace_bytes")(
+            self._h, C.byref(n)))
+        ws = torch.empty(max(n.value, 256), dtype=torch.uint8, device=dev)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        with torch.cuda.device(dev):
+            _check(getattr(lib(), f"afmg_{self._pre}_autotune")(self._h, C.c_void_p(stream.cuda_stream),
+                                                                 C.c_void_p(ws.data_ptr()), n.value))
+        return self.shapes()
+
+
+class Tree(_Shapes):
     """A quadtree/octree of 8^D-cell boxes built from its leaves."""
 
     def __init__(self, dim, level, idx, box_n=8):
@@ -320,11 +371,13 @@ def solve(tree: Tree, rho, bc=None, u=None, *, cycle="V", tol=1e-10, max_cycles=
     return u, d
 
 
-class Batch:
+class Batch(_Shapes):
     """Independent trees of one dimension solved together (afmg_batch_*).
 
     Fields are the trees' [n_boxes, N^D] arrays one after the other (each in
     its tree's box order); `concat` and `split` convert from / to lists."""
+
+    _pre = "batch"
 
     def __init__(self, trees):
         trees = list(trees)

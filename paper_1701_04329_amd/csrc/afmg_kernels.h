@@ -23,6 +23,7 @@ struct LevelArgs {
     T h2, ih2;          // h^2 and 1/h^2 of the level
     const int *active;  // forest: per-tree flag, boxes of trees at 0 are left
                         // untouched; null: every box is processed
+    int no_remap;       // 1: workgroups take boxes in launch order (no XCD remap)
 };
 
 enum class Op { GSRB, RESID_RESTRICT, COARSE_RHS, PROLONG, RESTRICT_RHO };
@@ -44,16 +45,18 @@ struct CoarseArgs {
     const int *active;  // per-tree flag as in LevelArgs (null: all trees)
 };
 
+// wg: workgroup size of the launch (64, 128 or 256 threads; W / N^(D-1)
+// boxes per workgroup); every size gives bitwise the same results
 template <int D, int N, typename T>
-void launch_level(Op op, const LevelArgs<T> &a, int colour, hipStream_t st);
+void launch_level(Op op, const LevelArgs<T> &a, int colour, int wg, hipStream_t st);
 template <int D, int N, typename T>
-void launch_final(const LevelArgs<T> &a, double *partial, int64_t part0, double hD, float *rout,
+void launch_final(const LevelArgs<T> &a, double *partial, int64_t part0, double hD, float *rout, int wg,
                   hipStream_t st);
 template <int D, int N>
 void launch_ir_update(const BoxInfo *info, double *u, const float *e, int64_t nb, const int *active,
                       hipStream_t st);
 template <int D, int N>
-int final_wgs(int64_t nb);
+int final_wgs(int64_t nb, int wg);
 void launch_reduce(const double *partial, int64_t n, double *out, hipStream_t st);
 // forests: per-tree (max, L2) of the per-box partials of each tree's leaf boxes
 void launch_reduce_trees(const double *partial, const int64_t *ptr, const int32_t *boxes, const int *active,

@@ -99,14 +99,18 @@ struct Slot {
     bool valid;  // false for the padding slots of the last workgroup
     int slot, t; // slot in the workgroup, thread in the slot
 };
-template <int D, int N>
-__device__ __forceinline__ Slot<D, N> slot_of(int64_t b0, int nb) {
+// Workgroups of W threads hold W / TPB boxes; with remap set, workgroup ids
+// are remapped so that each XCD takes a contiguous run of boxes.
+template <int D, int N, int W = 256>
+__device__ __forceinline__ Slot<D, N> slot_of(int64_t b0, int nb, bool remap = true) {
     using G = Geo<D, N>;
+    constexpr int BPW = W / G::TPB;
+    static_assert(BPW >= 1 && W % G::TPB == 0, "workgroup must hold whole boxes");
     Slot<D, N> r;
-    const int w = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int w = remap ? xcd_remap((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
     r.slot = (int)threadIdx.x / G::TPB;
     r.t = (int)threadIdx.x % G::TPB;
-    int bl = w * G::BPW + r.slot;
+    int bl = w * BPW + r.slot;
     if (G::TPB == 64) bl = __builtin_amdgcn_readfirstlane(bl);  // one box per wave
     r.valid = bl < nb;
     r.b = b0 + (r.valid ? bl : 0);
@@ -115,9 +119,9 @@ __device__ __forceinline__ Slot<D, N> slot_of(int64_t b0, int nb) {
 
 // Slot of a level kernel.  In a forest, boxes of trees whose mask entry is 0
 // are treated like padding slots: they are read but never written.
-template <int D, int N, typename T>
+template <int D, int N, int W, typename T>
 __device__ __forceinline__ Slot<D, N> slot_of(const LevelArgs<T> &a) {
-    Slot<D, N> r = slot_of<D, N>(a.b0, a.nb);
+    Slot<D, N> r = slot_of<D, N, W>(a.b0, a.nb, a.no_remap == 0);
     if (a.active) r.valid = r.valid && a.active[load_box<D, N>(a.info, r.b).tree] != 0;
     return r;
 }
@@ -314,12 +318,12 @@ __device__ __forceinline__ T gs_finish(const T *s, T raw, int v, T own, int i, i
     return T(0.5) * raw + T(1.25) * own - T(0.25) * ((u2 + u1p) + u1pp);
 }
 
-template <int D, int N, typename T>
-__global__ __launch_bounds__(256) void k_gsrb(LevelArgs<T> a, int colour) {
+template <int D, int N, typename T, int W>
+__global__ __launch_bounds__(W) void k_gsrb(LevelArgs<T> a, int colour) {
     using G = Geo<D, N>;
     constexpr int HN = G::HN;
-    __shared__ T so[G::BPW * oblock<D, N>()];
-    const Slot<D, N> sl = slot_of<D, N>(a);
+    __shared__ T so[(W / G::TPB) * oblock<D, N>()];
+    const Slot<D, N> sl = slot_of<D, N, W>(a);
     T *s = so + sl.slot * oblock<D, N>();
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     T *ub = a.u + (size_t)sl.b * G::C;
@@ -426,11 +430,11 @@ __device__ __forceinline__ void restrict_octant(const T *s, T *__restrict__ dst,
 // Boxes of level l: r = rho - L u; the parent's octant receives mean(u) in u
 // and mean(r) in rho (the restricted residual, turned into the FAS
 // right-hand side by k_coarse_rhs).
-template <int D, int N, typename T>
-__global__ __launch_bounds__(256) void k_resid_restrict(LevelArgs<T> a) {
+template <int D, int N, typename T, int W>
+__global__ __launch_bounds__(W) void k_resid_restrict(LevelArgs<T> a) {
     using G = Geo<D, N>;
-    __shared__ T sm[G::BPW * G::PC];
-    const Slot<D, N> sl = slot_of<D, N>(a);
+    __shared__ T sm[(W / G::TPB) * G::PC];
+    const Slot<D, N> sl = slot_of<D, N, W>(a);
     T *s = sm + sl.slot * G::PC;
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
@@ -468,11 +472,11 @@ __global__ __launch_bounds__(256) void k_resid_restrict(LevelArgs<T> a) {
 // ---------------------------------------------------------------------------
 // Boxes of level l-1: uold <- u; on parents rho <- rbar + L_H u (rho holds
 // rbar, the restricted residual).
-template <int D, int N, typename T>
-__global__ __launch_bounds__(256) void k_coarse_rhs(LevelArgs<T> a) {
+template <int D, int N, typename T, int W>
+__global__ __launch_bounds__(W) void k_coarse_rhs(LevelArgs<T> a) {
     using G = Geo<D, N>;
-    __shared__ T sm[G::BPW * G::PC];
-    const Slot<D, N> sl = slot_of<D, N>(a);
+    __shared__ T sm[(W / G::TPB) * G::PC];
+    const Slot<D, N> sl = slot_of<D, N, W>(a);
     T *s = sm + sl.slot * G::PC;
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
@@ -584,12 +588,12 @@ __device__ __forceinline__ void halo_phase2(T *q, int m, const int o[3], T raw, 
     q[qpad<D, N>(L[0], L[1], L[2])] = val;
 }
 
-template <int D, int N, typename T>
-__global__ __launch_bounds__(256) void k_prolong(LevelArgs<T> a) {
+template <int D, int N, typename T, int W>
+__global__ __launch_bounds__(W) void k_prolong(LevelArgs<T> a) {
     using G = Geo<D, N>;
     constexpr int NH = (2 * D * G::HF + G::TPB - 1) / G::TPB;  // halo cells per thread
-    __shared__ T qs[G::BPW * G::QC];
-    const Slot<D, N> sl = slot_of<D, N>(a);
+    __shared__ T qs[(W / G::TPB) * G::QC];
+    const Slot<D, N> sl = slot_of<D, N, W>(a);
     T *q = qs + sl.slot * G::QC;
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
@@ -659,13 +663,13 @@ __global__ __launch_bounds__(256) void k_prolong(LevelArgs<T> a) {
 // leaf box at partial[box].  With rout set, the leaf residual is also stored
 // there rounded to FP32: the right-hand side of the correction solve of the
 // mixed-precision refinement.
-template <int D, int N, typename T>
-__global__ __launch_bounds__(256) void k_final(LevelArgs<T> a, double *partial, int64_t part0, double hD,
+template <int D, int N, typename T, int W>
+__global__ __launch_bounds__(W) void k_final(LevelArgs<T> a, double *partial, int64_t part0, double hD,
                                                float *__restrict__ rout) {
     using G = Geo<D, N>;
-    __shared__ T sm[G::BPW * G::PC];
-    __shared__ double red_m[256], red_s[256];
-    const Slot<D, N> sl = slot_of<D, N>(a);
+    __shared__ T sm[(W / G::TPB) * G::PC];
+    __shared__ double red_m[W], red_s[W];
+    const Slot<D, N> sl = slot_of<D, N, W>(a);
     T *s = sm + sl.slot * G::PC;
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
@@ -708,7 +712,7 @@ __global__ __launch_bounds__(256) void k_final(LevelArgs<T> a, double *partial, 
         }
         return;
     }
-    for (int w = 128; w > 0; w >>= 1) {
+    for (int w = W / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) {
             red_m[threadIdx.x] = fmax(red_m[threadIdx.x], red_m[threadIdx.x + w]);
             red_s[threadIdx.x] += red_s[threadIdx.x + w];
@@ -806,7 +810,7 @@ template <int D, int N, typename T>
 __global__ __launch_bounds__(256) void k_restrict_rho(LevelArgs<T> a) {
     using G = Geo<D, N>;
     __shared__ T sm[G::BPW * G::C];
-    const Slot<D, N> sl = slot_of<D, N>(a);
+    const Slot<D, N> sl = slot_of<D, N, 256>(a);
     T *s = sm + sl.slot * G::C;
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
@@ -1524,34 +1528,53 @@ __global__ __launch_bounds__(256) void k_bc_grad(const BoxInfo *__restrict__ inf
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <int D, int N>
+template <int D, int N, int W = 256>
 static inline int wg_count(int64_t nb) {
-    using G = Geo<D, N>;
-    return (int)((nb + G::BPW - 1) / G::BPW);
+    constexpr int BPW = W / Geo<D, N>::TPB;
+    return (int)((nb + BPW - 1) / BPW);
 }
 
 #define AFMG_LAUNCH(kernel, grid, stream, ...)                                                      \
     do {                                                                                            \
         if ((grid) > 0) hipLaunchKernelGGL(kernel, dim3(grid), dim3(256), 0, stream, __VA_ARGS__); \
     } while (0)
+#define AFMG_LAUNCH_W(kernel, grid, W, stream, ...)                                               \
+    do {                                                                                          \
+        if ((grid) > 0) hipLaunchKernelGGL(kernel, dim3(grid), dim3(W), 0, stream, __VA_ARGS__); \
+    } while (0)
 
-template <int D, int N, typename T>
-void launch_level(Op op, const LevelArgs<T> &a, int colour, hipStream_t st) {
-    const int g = wg_count<D, N>(a.nb);
+template <int D, int N, typename T, int W>
+static void launch_level_w(Op op, const LevelArgs<T> &a, int colour, hipStream_t st) {
+    const int g = wg_count<D, N, W>(a.nb);
     switch (op) {
-    case Op::GSRB: AFMG_LAUNCH((k_gsrb<D, N, T>), g, st, a, colour); break;
-    case Op::RESID_RESTRICT: AFMG_LAUNCH((k_resid_restrict<D, N, T>), g, st, a); break;
-    case Op::COARSE_RHS: AFMG_LAUNCH((k_coarse_rhs<D, N, T>), g, st, a); break;
-    case Op::PROLONG: AFMG_LAUNCH((k_prolong<D, N, T>), g, st, a); break;
-    case Op::RESTRICT_RHO: AFMG_LAUNCH((k_restrict_rho<D, N, T>), g, st, a); break;
+    case Op::GSRB: AFMG_LAUNCH_W((k_gsrb<D, N, T, W>), g, W, st, a, colour); break;
+    case Op::RESID_RESTRICT: AFMG_LAUNCH_W((k_resid_restrict<D, N, T, W>), g, W, st, a); break;
+    case Op::COARSE_RHS: AFMG_LAUNCH_W((k_coarse_rhs<D, N, T, W>), g, W, st, a); break;
+    case Op::PROLONG: AFMG_LAUNCH_W((k_prolong<D, N, T, W>), g, W, st, a); break;
+    case Op::RESTRICT_RHO: AFMG_LAUNCH((k_restrict_rho<D, N, T>), (wg_count<D, N, 256>(a.nb)), st, a); break;
     }
 }
 
 template <int D, int N, typename T>
-void launch_final(const LevelArgs<T> &a, double *partial, int64_t part0, double hD, float *rout,
+void launch_level(Op op, const LevelArgs<T> &a, int colour, int wg, hipStream_t st) {
+    if (wg == 64) launch_level_w<D, N, T, 64>(op, a, colour, st);
+    else if (wg == 128) launch_level_w<D, N, T, 128>(op, a, colour, st);
+    else launch_level_w<D, N, T, 256>(op, a, colour, st);
+}
+
+template <int D, int N, typename T, int W>
+static void launch_final_w(const LevelArgs<T> &a, double *partial, int64_t part0, double hD, float *rout,
+                           hipStream_t st) {
+    const int g = wg_count<D, N, W>(a.nb);
+    AFMG_LAUNCH_W((k_final<D, N, T, W>), g, W, st, a, partial, part0, hD, rout);
+}
+
+template <int D, int N, typename T>
+void launch_final(const LevelArgs<T> &a, double *partial, int64_t part0, double hD, float *rout, int wg,
                   hipStream_t st) {
-    const int g = wg_count<D, N>(a.nb);
-    AFMG_LAUNCH((k_final<D, N, T>), g, st, a, partial, part0, hD, rout);
+    if (wg == 64) launch_final_w<D, N, T, 64>(a, partial, part0, hD, rout, st);
+    else if (wg == 128) launch_final_w<D, N, T, 128>(a, partial, part0, hD, rout, st);
+    else launch_final_w<D, N, T, 256>(a, partial, part0, hD, rout, st);
 }
 
 template <int D, int N>
@@ -1562,7 +1585,9 @@ void launch_ir_update(const BoxInfo *info, double *u, const float *e, int64_t nb
 }
 
 template <int D, int N>
-int final_wgs(int64_t nb) { return wg_count<D, N>(nb); }
+int final_wgs(int64_t nb, int wg) {
+    return wg == 64 ? wg_count<D, N, 64>(nb) : wg == 128 ? wg_count<D, N, 128>(nb) : wg_count<D, N, 256>(nb);
+}
 
 void launch_reduce(const double *partial, int64_t n, double *out, hipStream_t st) {
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, partial, n, out, 1);
@@ -1698,8 +1723,8 @@ AFMG_ADJ_INST(2, 8)
 AFMG_ADJ_INST(3, 8)
 
 #define AFMG_INST(D, N, T)                                                                              \
-    template void launch_level<D, N, T>(Op, const LevelArgs<T> &, int, hipStream_t);                     \
-    template void launch_final<D, N, T>(const LevelArgs<T> &, double *, int64_t, double, float *,     \
+    template void launch_level<D, N, T>(Op, const LevelArgs<T> &, int, int, hipStream_t);                \
+    template void launch_final<D, N, T>(const LevelArgs<T> &, double *, int64_t, double, float *, int, \
                                         hipStream_t);                                                 \
     template void launch_coarse<D, N, T>(const CoarseArgs<T> &, int, hipStream_t);                      \
     template void launch_permute<D, N, T>(const BoxInfo *, T *, int64_t, int64_t, int, int, hipStream_t); \
@@ -1715,8 +1740,8 @@ template void launch_ir_update<2, 8>(const BoxInfo *, double *, const float *, i
 template void launch_ir_update<3, 8>(const BoxInfo *, double *, const float *, int64_t, const int *, hipStream_t);
 template void launch_copy<float>(const float *, float *, int64_t, hipStream_t);
 template void launch_fill<float>(float *, int64_t, float, hipStream_t);
-template int final_wgs<2, 8>(int64_t);
-template int final_wgs<3, 8>(int64_t);
+template int final_wgs<2, 8>(int64_t, int);
+template int final_wgs<3, 8>(int64_t, int);
 template void launch_bc_derive<2, 8>(const BoxInfo *, int64_t, int64_t, double *, hipStream_t);
 template void launch_bc_derive<3, 8>(const BoxInfo *, int64_t, int64_t, double *, hipStream_t);
 template void launch_copy<double>(const double *, double *, int64_t, hipStream_t);

@@ -32,6 +32,16 @@ void afmg::set_error(const std::string &m) { g_err = m; }
 extern "C" const char *afmg_last_error(void) { return g_err.c_str(); }
 
 namespace {
+// Launch shape of one kernel class on one level: workgroup size (64, 128 or
+// 256 threads) and whether workgroups take boxes in XCD-contiguous runs.
+// Every shape computes bitwise the same values.
+struct Shape {
+    int wg = 256;
+    int no_remap = 0;
+};
+enum { SK_GSRB, SK_RESID, SK_CRHS, SK_PROLONG, SK_FINAL, SK_KINDS };
+constexpr int SHAPE_WGS[3] = {256, 128, 64};
+
 // The repeated cycle recorded as a HIP graph (opts.graph), with the
 // arguments it was recorded for.
 struct Recorded {
@@ -58,6 +68,9 @@ struct afmg_tree {
     double *h_norm = nullptr;        // pinned host copy of (max, L2) per tree
     std::vector<int64_t> part_off;   // first k_final partial of each level (one tree)
     int64_t n_parts = 0;
+    int64_t n_parts_max = 0;         // partials for the smallest workgroups
+    std::vector<Shape> shapes[2][SK_KINDS];  // [FP64, FP32][kernel class][level]
+    int tune_epoch = 0;              // bumped by every autotune
     std::vector<hipEvent_t> events;  // event pairs for opts.profile
     Recorded rec;
     // forests (batches): per-tree mask and tables, and the caller's layout
@@ -108,7 +121,7 @@ WsLayout ws_layout(const afmg_tree *t, int precision) {
     const size_t C = (size_t)cells_per_box(h.dim), F = (size_t)cells_per_face(h.dim);
     const size_t nlt = (size_t)h.n_below_lmax(), nb = (size_t)h.n_boxes;
     const bool mixed = precision == AFMG_MIXED;
-    const size_t np = t->forest ? nb : (size_t)std::max<int64_t>(1, t->n_parts);
+    const size_t np = t->forest ? nb : (size_t)std::max<int64_t>(1, t->n_parts_max);
     WsLayout L{};
     size_t off = 0;
     L.rho = off; off = align256(off + nb * C * sizeof(double));
@@ -124,21 +137,53 @@ WsLayout ws_layout(const afmg_tree *t, int precision) {
     return L;
 }
 
+// Workspace of the autotuner: the arrays of both precisions and a working u.
+struct TuneLayout {
+    size_t u, rho, uold, bc, partial, e, rho_e, uold_e, total;
+};
+
+TuneLayout tune_layout(const afmg_tree *t) {
+    const HostTree &h = t->h;
+    const size_t C = (size_t)cells_per_box(h.dim), F = (size_t)cells_per_face(h.dim);
+    const size_t nlt = (size_t)h.n_below_lmax(), nb = (size_t)h.n_boxes;
+    TuneLayout L{};
+    size_t off = 0;
+    L.u = off; off = align256(off + nb * C * sizeof(double));
+    L.rho = off; off = align256(off + nb * C * sizeof(double));
+    L.uold = off; off = align256(off + std::max<size_t>(1, nlt) * C * sizeof(double));
+    L.bc = off; off = align256(off + (size_t)std::max<int64_t>(1, h.n_bfaces_all) * F * sizeof(double));
+    L.partial = off; off = align256(off + std::max<size_t>(nb, (size_t)t->n_parts_max) * 2 * sizeof(double));
+    L.e = off; off = align256(off + nb * C * sizeof(float));
+    L.rho_e = off; off = align256(off + nb * C * sizeof(float));
+    L.uold_e = off; off = align256(off + std::max<size_t>(1, nlt) * C * sizeof(float));
+    L.total = off;
+    return L;
+}
+
 template <int D>
-int64_t final_wgs_d(int64_t nb) { return final_wgs<D, BOX_N>(nb); }
+int64_t final_wgs_d(int64_t nb, int wg) { return final_wgs<D, BOX_N>(nb, wg); }
 
 bool root_is_leaf(const HostTree &h) { return h.info[0].flags & FLAG_LEAF; }
 
+// k_final partial offsets per level for the current shapes, and the count
+// for the smallest workgroups (the workspace is sized for that)
 void compute_partials(afmg_tree *t) {
     const HostTree &h = t->h;
+    for (auto &pk : t->shapes)
+        for (auto &v : pk)
+            if (v.size() != (size_t)h.lmax + 2) v.assign((size_t)h.lmax + 2, Shape{});
     t->part_off.assign((size_t)h.lmax + 2, 0);
-    int64_t n = 0;
+    int64_t n = 0, nmax = 0;
     for (int l = h.lmax; l >= 1; l--) {
         t->part_off[(size_t)l] = n;
-        if (l >= 2 || root_is_leaf(h))
-            n += h.dim == 3 ? final_wgs_d<3>(h.level_count(l)) : final_wgs_d<2>(h.level_count(l));
+        if (l >= 2 || root_is_leaf(h)) {
+            const int wg = t->shapes[0][SK_FINAL][(size_t)l].wg;
+            n += h.dim == 3 ? final_wgs_d<3>(h.level_count(l), wg) : final_wgs_d<2>(h.level_count(l), wg);
+            nmax += h.dim == 3 ? final_wgs_d<3>(h.level_count(l), 64) : final_wgs_d<2>(h.level_count(l), 64);
+        }
     }
     t->n_parts = n;
+    t->n_parts_max = nmax;
 }
 
 template <class V>
@@ -274,7 +319,15 @@ struct Cycler {
         const int kind = op == Op::GSRB ? AFMG_PROF_GSRB
                          : op == Op::RESID_RESTRICT ? AFMG_PROF_RESID
                          : op == Op::PROLONG ? AFMG_PROF_PROLONG : -1;
-        prof.timed(kind, l, [&] { launch_level<D, BOX_N, T>(op, lev(l), colour, st); });
+        const int sk = op == Op::GSRB ? SK_GSRB
+                       : op == Op::RESID_RESTRICT ? SK_RESID
+                       : op == Op::COARSE_RHS ? SK_CRHS
+                       : op == Op::PROLONG ? SK_PROLONG : -1;
+        Shape sh;
+        if (sk >= 0) sh = t->shapes[sizeof(T) == 4 ? 1 : 0][sk][(size_t)l];
+        LevelArgs<T> a = lev(l);
+        a.no_remap = sh.no_remap;
+        prof.timed(kind, l, [&] { launch_level<D, BOX_N, T>(op, a, colour, sh.wg, st); });
     }
     void gsrb(int l, int n) {
         for (int q = 0; q < n; q++) {
@@ -357,8 +410,11 @@ struct Solver {
             a.nb = (int)h.level_count(l);
             a.h2 = hh * hh;
             a.ih2 = 1.0 / (hh * hh);
+            const Shape sh = t->shapes[0][SK_FINAL][(size_t)l];
+            a.no_remap = sh.no_remap;
             prof.timed(AFMG_PROF_FINAL, l, [&] {
-                launch_final<D, BOX_N, double>(a, partial, t->forest ? -1 : t->part_off[(size_t)l], hD, rout, s);
+                launch_final<D, BOX_N, double>(a, partial, t->forest ? -1 : t->part_off[(size_t)l], hD, rout, sh.wg,
+                                               s);
             });
         }
         if (t->forest)
@@ -609,7 +665,7 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
     std::vector<Track> tr((size_t)n);
     const uintptr_t wsk = (uintptr_t)ws, uk = (uintptr_t)uw;
     const std::vector<uintptr_t> key{(uintptr_t)o.precision, wsk, uk, (uintptr_t)o.n_down, (uintptr_t)o.n_up,
-                                     (uintptr_t)o.n_base};
+                                     (uintptr_t)o.n_base, (uintptr_t)t->tune_epoch};
     if (!any) {
         // nothing to iterate
     } else if (!mixed) {
@@ -705,7 +761,7 @@ AdjLayout adj_layout(const afmg_tree *t) {
     }
     L.puold = off; off = align256(off + nlt * C * sizeof(double));
     L.bc = off; off = align256(off + (size_t)std::max<int64_t>(1, h.n_bfaces_all) * F * sizeof(double));
-    const size_t np = (size_t)std::max<int64_t>(t->n_parts, DOT_WGS);
+    const size_t np = (size_t)std::max<int64_t>(t->n_parts_max, DOT_WGS);
     L.partial = off; off = align256(off + np * 2 * sizeof(double));
     L.norm = off; off = align256(off + 2 * sizeof(double));
     L.total = off;
@@ -793,7 +849,7 @@ int adjoint(afmg_tree *t, hipStream_t st, const double *ubar, double *rho_bar, d
         // the operator is symmetric: lambda solves L lambda = ubar with zero
         // Dirichlet values, one more multigrid solve
         s.base = LevelArgs<double>{t->d_info, X, B, (double *)(ws + A.L.puold), bcz, 0, 0, 1, 0.0, 0.0};
-        Cycler<D, double> cy{h, st, o, s.prof, s.base, nullptr};
+        Cycler<D, double> cy{h, st, o, s.prof, s.base, nullptr, t};
         rc = s.finalize(S.r0_max, S.r0_l2, nullptr);
         if (rc != AFMG_OK) return rc;
         S.r_max = S.r0_max;
@@ -811,7 +867,7 @@ int adjoint(afmg_tree *t, hipStream_t st, const double *ubar, double *rho_bar, d
         double *PH = A.vec(AdjLayout::PH), *SH = A.vec(AdjLayout::SH);
         double *PU = A.vec(AdjLayout::PU), *PRHO = A.vec(AdjLayout::PRHO);
         LevelArgs<double> pb{t->d_info, PU, PRHO, (double *)(ws + A.L.puold), bcz, 0, 0, 1, 0.0, 0.0};
-        Cycler<D, double> cy{h, st, o, s.prof, pb, nullptr};
+        Cycler<D, double> cy{h, st, o, s.prof, pb, nullptr, t};
         auto precond = [&](const double *in, double *out) {
             launch_scale_leaves<D, BOX_N>(t->d_info, PRHO, in, -1, h.n_boxes, st);
             launch_fill<double>(PU, n, 0.0, st);
@@ -883,6 +939,153 @@ int adjoint(afmg_tree *t, hipStream_t st, const double *ubar, double *rho_bar, d
     if (status == AFMG_NOT_CONVERGED) set_error("max_cycles reached before the tolerance");
     if (status == AFMG_ERR_NONFINITE) set_error("residual norm is not finite");
     return status;
+}
+
+// ---------------------------------------------------------------------------
+// autotuning of the launch shapes
+// ---------------------------------------------------------------------------
+// Every candidate shape of one kernel class on one level is timed on the
+// tree's own boxes (REPS launches between two events, best of two rounds);
+// the fastest wins, the default (256 threads, XCD runs) unless another is at
+// least 3% faster.  Arrays are zero-filled scratch: timing does not depend on
+// the values.
+constexpr int TUNE_REPS = 10;
+
+template <class Fn>
+float time_launches(hipStream_t st, hipEvent_t a, hipEvent_t b, Fn fn) {
+    fn();  // warm-up
+    (void)hipEventRecord(a, st);
+    for (int r = 0; r < TUNE_REPS; r++) fn();
+    (void)hipEventRecord(b, st);
+    (void)hipEventSynchronize(b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    return ms / TUNE_REPS;
+}
+
+template <int D, typename T>
+void tune_precision(afmg_tree *t, hipStream_t st, LevelArgs<T> base, double *partial, hipEvent_t e0, hipEvent_t e1) {
+    const HostTree &h = t->h;
+    const int pi = sizeof(T) == 4 ? 1 : 0;
+    for (int kind = 0; kind < SK_KINDS; kind++) {
+        if (kind == SK_FINAL && pi == 1) continue;  // the residual is always FP64
+        const int l0 = kind == SK_FINAL ? 1 : 2;
+        const int l1 = kind == SK_CRHS ? h.lmax - 1 : h.lmax;
+        for (int l = l0; l <= l1; l++) {
+            if (h.level_count(l) == 0) continue;
+            LevelArgs<T> a = base;
+            a.b0 = h.lvl_off[(size_t)l];
+            a.nb = (int)h.level_count(l);
+            const double hh = level_h(l);
+            a.h2 = (T)(hh * hh);
+            a.ih2 = (T)(1.0 / (hh * hh));
+            const Op op = kind == SK_GSRB ? Op::GSRB
+                          : kind == SK_RESID ? Op::RESID_RESTRICT
+                          : kind == SK_CRHS ? Op::COARSE_RHS : Op::PROLONG;
+            auto run = [&](const Shape &sh) {
+                LevelArgs<T> b = a;
+                b.no_remap = sh.no_remap;
+                if (kind == SK_FINAL) {
+                    const double hD = D == 3 ? hh * hh * hh : hh * hh;
+                    launch_final<D, BOX_N, T>(b, partial, t->forest ? -1 : 0, hD, nullptr, sh.wg, st);
+                } else {
+                    launch_level<D, BOX_N, T>(op, b, 0, sh.wg, st);
+                }
+            };
+            Shape best{};
+            float t_def = 0.f, t_best = 0.f;
+            for (int round = 0; round < 2; round++) {
+                for (int wi = 0; wi < 3; wi++) {
+                    for (int nr = 0; nr < 2; nr++) {
+                        const Shape sh{SHAPE_WGS[wi], nr};
+                        const float ms = time_launches(st, e0, e1, [&] { run(sh); });
+                        const bool is_def = wi == 0 && nr == 0;
+                        if (round == 0 && is_def) {
+                            t_def = ms;
+                            t_best = ms;
+                            best = sh;
+                            continue;
+                        }
+                        if (is_def) t_def = std::min(t_def, ms);
+                        if (ms < t_best) {
+                            t_best = ms;
+                            best = sh;
+                        }
+                    }
+                }
+            }
+            if (!(t_best < 0.97f * t_def)) best = Shape{};
+            t->shapes[pi][kind][(size_t)l] = best;
+        }
+    }
+}
+
+template <int D>
+int autotune(afmg_tree *t, hipStream_t st, char *ws) {
+    const HostTree &h = t->h;
+    const TuneLayout L = tune_layout(t);
+    const int64_t C = cells_per_box(D), F = cells_per_face(D);
+    const int64_t nb = h.n_boxes, nlt = std::max<int64_t>(1, h.n_below_lmax());
+    double *u = (double *)(ws + L.u), *rho = (double *)(ws + L.rho), *uold = (double *)(ws + L.uold);
+    double *bc = (double *)(ws + L.bc), *partial = (double *)(ws + L.partial);
+    float *e = (float *)(ws + L.e), *re = (float *)(ws + L.rho_e), *uo = (float *)(ws + L.uold_e);
+    launch_fill<double>(u, nb * C, 0.0, st);
+    launch_fill<double>(rho, nb * C, 0.0, st);
+    launch_fill<double>(uold, nlt * C, 0.0, st);
+    launch_fill<double>(bc, std::max<int64_t>(1, h.n_bfaces_all) * F, 0.0, st);
+    launch_fill<float>(e, nb * C, 0.f, st);
+    launch_fill<float>(re, nb * C, 0.f, st);
+    launch_fill<float>(uo, nlt * C, 0.f, st);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(AFMG_ERR_HIP, "hipEventCreate failed");
+    LevelArgs<double> b64{t->d_info, u, rho, uold, bc, 0, 0, 0, 0.0, 0.0, nullptr, 0};
+    LevelArgs<float> b32{t->d_info, e, re, uo, nullptr, 0, 0, 1, 0.f, 0.f, nullptr, 0};
+    tune_precision<D, double>(t, st, b64, partial, e0, e1);
+    tune_precision<D, float>(t, st, b32, partial, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    hipError_t err = hipStreamSynchronize(st);
+    if (err == hipSuccess) err = hipGetLastError();
+    if (err != hipSuccess) return hip_fail(err, "autotune");
+    compute_partials(t);
+    t->tune_epoch++;
+    return AFMG_OK;
+}
+
+int tree_autotune(afmg_tree *t, void *stream, void *workspace, size_t workspace_bytes) {
+    if (!t || !workspace) return fail(AFMG_ERR_ARG, "null argument");
+    if (!aligned(workspace, 256)) return fail(AFMG_ERR_ARG, "misaligned array");
+    if (workspace_bytes < tune_layout(t).total) return fail(AFMG_ERR_ARG, "workspace too small");
+    int rc = bind_device(t);
+    if (rc != AFMG_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    return t->h.dim == 3 ? autotune<3>(t, st, (char *)workspace) : autotune<2>(t, st, (char *)workspace);
+}
+
+int get_shape(const afmg_tree *t, int precision, int kind, int level, int *wg, int *no_remap) {
+    if (!t || !wg || !no_remap) return fail(AFMG_ERR_ARG, "null argument");
+    if (precision < 0 || precision > 1 || kind < 0 || kind >= SK_KINDS || level < 1 || level > t->h.lmax)
+        return fail(AFMG_ERR_ARG, "shape index out of range");
+    const Shape &sh = t->shapes[precision][kind][(size_t)level];
+    *wg = sh.wg;
+    *no_remap = sh.no_remap;
+    return AFMG_OK;
+}
+
+int set_shape(afmg_tree *t, int precision, int kind, int level, int wg, int no_remap) {
+    if (!t) return fail(AFMG_ERR_ARG, "null argument");
+    if (precision < -1 || precision > 1 || kind < -1 || kind >= SK_KINDS || level < -1 || level == 0 ||
+        level > t->h.lmax || (wg != 64 && wg != 128 && wg != 256) || (no_remap != 0 && no_remap != 1))
+        return fail(AFMG_ERR_ARG, "shape out of range");
+    for (int p = 0; p < 2; p++)
+        for (int k = 0; k < SK_KINDS; k++)
+            for (int l = 1; l <= t->h.lmax; l++)
+                if ((precision < 0 || p == precision) && (kind < 0 || k == kind) && (level < 0 || l == level))
+                    t->shapes[p][k][(size_t)l] = Shape{wg, no_remap};
+    compute_partials(t);
+    t->tune_epoch++;
+    return AFMG_OK;
 }
 
 }  // namespace
@@ -1095,6 +1298,7 @@ int afmg_batch_create(afmg_tree *const *trees, int n_trees, afmg_batch **out) {
             return fail(rc, msg);
         }
         f.forest = true;
+        compute_partials(&f);
         // caller's box of each working box: inside one tree the working order
         // is the tree's own order, level by level
         const HostTree &fh = f.h;
@@ -1176,6 +1380,45 @@ int afmg_batch_solve(afmg_batch *b, void *stream, const double *rho, const doubl
     hipStream_t st = (hipStream_t)stream;
     if (f->h.dim == 3) return solve<3>(f, st, rho, bc, u, (char *)workspace, *opts, stats);
     return solve<2>(f, st, rho, bc, u, (char *)workspace, *opts, stats);
+}
+
+int afmg_autotune_workspace_bytes(const afmg_tree *t, size_t *bytes) {
+    if (!t || !bytes) return fail(AFMG_ERR_ARG, "null argument");
+    *bytes = tune_layout(t).total;
+    return AFMG_OK;
+}
+
+int afmg_tree_autotune(afmg_tree *t, void *stream, void *workspace, size_t workspace_bytes) {
+    return tree_autotune(t, stream, workspace, workspace_bytes);
+}
+
+int afmg_tree_shape(const afmg_tree *t, int precision, int kind, int level, int *wg, int *no_remap) {
+    return get_shape(t, precision, kind, level, wg, no_remap);
+}
+
+int afmg_tree_set_shape(afmg_tree *t, int precision, int kind, int level, int wg, int no_remap) {
+    return set_shape(t, precision, kind, level, wg, no_remap);
+}
+
+int afmg_batch_autotune_workspace_bytes(const afmg_batch *b, size_t *bytes) {
+    if (!b || !bytes) return fail(AFMG_ERR_ARG, "null argument");
+    *bytes = tune_layout(&b->f).total;
+    return AFMG_OK;
+}
+
+int afmg_batch_autotune(afmg_batch *b, void *stream, void *workspace, size_t workspace_bytes) {
+    if (!b) return fail(AFMG_ERR_ARG, "null argument");
+    return tree_autotune(&b->f, stream, workspace, workspace_bytes);
+}
+
+int afmg_batch_shape(const afmg_batch *b, int precision, int kind, int level, int *wg, int *no_remap) {
+    if (!b) return fail(AFMG_ERR_ARG, "null argument");
+    return get_shape(&b->f, precision, kind, level, wg, no_remap);
+}
+
+int afmg_batch_set_shape(afmg_batch *b, int precision, int kind, int level, int wg, int no_remap) {
+    if (!b) return fail(AFMG_ERR_ARG, "null argument");
+    return set_shape(&b->f, precision, kind, level, wg, no_remap);
 }
 
 }  // extern "C"

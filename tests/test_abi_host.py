@@ -188,3 +188,32 @@ def test_batch_workload_generator():
         t = A.Tree(w.dim, w.level, w.idx)
         assert t.n_boxes >= 64
         assert t.n_boxes <= 8192 + 2 ** w.dim * 64
+
+
+def test_shapes_default_set_and_validation():
+    """Launch shapes are host state: defaults, setting one or all, and the
+    range checks (no device work)."""
+    t = A.Tree(3, *W.ball_leaves(3, 8, 4, (0.3, 0.6, 0.4), 0.0, 1))
+    sh = t.shapes()
+    assert all(v == (256, 0) for vals in sh.values() for v in vals)
+    t.set_shape(64, 1, precision="fp64", kind="gsrb", level=t.lmax)
+    assert t.shape("fp64", "gsrb", t.lmax) == (64, 1)
+    assert t.shape("mixed", "gsrb", t.lmax) == (256, 0)
+    assert t.shape("fp64", "gsrb", t.lmax - 1) == (256, 0)
+    t.set_shape(128)
+    assert all(v == (128, 0) for vals in t.shapes().values() for v in vals)
+    for bad in [dict(wg=96), dict(wg=64, no_remap=2), dict(wg=64, level=t.lmax + 1), dict(wg=64, level=0),
+                dict(wg=64, kind=5), dict(wg=64, precision=2)]:
+        with pytest.raises(A.AfmgError) as e:
+            t.set_shape(**bad)
+        assert e.value.code == A.AFMG_ERR_ARG
+    with pytest.raises(A.AfmgError):
+        t.shape("fp64", "gsrb", 0)
+    b = A.Batch([t, A.Tree(3, *W.uniform_leaves(3, 2))])
+    assert b.shape("fp64", "final", 1) == (256, 0)
+    b.set_shape(64, 0, kind="prolong")
+    assert b.shape("mixed", "prolong", 2) == (64, 0)
+    L = A.lib()
+    n = C.c_size_t()
+    assert L.afmg_autotune_workspace_bytes(t.handle, C.byref(n)) == 0 and n.value > t.workspace_bytes()
+    assert L.afmg_tree_autotune(t.handle, None, None, 0) == A.AFMG_ERR_ARG
