@@ -207,6 +207,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-tree batch workload")
     ap.add_argument("--batch-trees", type=int, default=256)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batch workload and print its record (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -233,6 +235,10 @@ def main():
         return 0
 
     from paper_1701_04329_amd import afmg as A
+
+    if args.batch_only:
+        print(json.dumps(batch_bench(args, A, torch, dev, torch.cuda.current_stream(dev))), flush=True)
+        return 0
 
     w, solve_kw = make_workload(args.workload)
     tree = A.Tree(w.dim, w.level, w.idx)
