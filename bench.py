@@ -160,14 +160,16 @@ def batch_bench(args, A, torch, dev, stream):
     errs = [float(np.linalg.norm(m - f) / np.linalg.norm(f))
             for gm, gf in zip(sols["mixed"], sols["fp64"]) for m, f in zip(gm, gf)]
     # the same trees solved one at a time (one pass, mixed, graph replay)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for g in groups:
-        for t, w in zip(g["trees"], g["sub"]):
-            r = t.leaf_to_boxes(torch.tensor(w.rho, device=dev))
-            A.solve(t, r, None, None, cycle="FMG", tol=1e-10, precision="mixed", stream=stream, graph=True)
-    torch.cuda.synchronize()
-    unbatched_ms = (time.perf_counter() - t0) * 1e3
+    unbatched_ms = None
+    if not args.skip_unbatched:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for g in groups:
+            for t, w in zip(g["trees"], g["sub"]):
+                r = t.leaf_to_boxes(torch.tensor(w.rho, device=dev))
+                A.solve(t, r, None, None, cycle="FMG", tol=1e-10, precision="mixed", stream=stream, graph=True)
+        torch.cuda.synchronize()
+        unbatched_ms = (time.perf_counter() - t0) * 1e3
     # oracle check of the smallest tree of each dimension
     oracle = {}
     for gi, g in enumerate(groups):
@@ -197,6 +199,122 @@ def batch_bench(args, A, torch, dev, stream):
     }
 
 
+def timed_loop(args, torch, fn):
+    for _ in range(args.warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / args.steps, r
+
+
+def adaptive_bench(args, A, torch, dev, stream):
+    """The adaptive octree workload: about 2.3e7 unknowns on leaves of levels
+    3-8 around four Gaussians, FMG then V(2,2) to a 1e-10 residual reduction,
+    FP64 against FP32 V-cycles inside FP64 refinement; both against the
+    oracle's FP64 solve of the same problem."""
+    from oracle import oracle as O
+    from paper_1701_04329_amd import workloads as W
+
+    t0 = time.perf_counter()
+    w = W.config3()
+    gen_s = time.perf_counter() - t0
+    tree = A.Tree(w.dim, w.level, w.idx)
+    if not args.no_autotune:
+        tree.autotune(dev, stream)
+    rho = tree.leaf_to_boxes(torch.tensor(w.rho, device=dev))
+    bc = tree.bc_rows(torch.tensor(w.bc, device=dev))
+    u = torch.zeros_like(rho)
+    work = torch.empty(tree.workspace_bytes(A.make_opts(precision="mixed")), dtype=torch.uint8, device=dev)
+    out = {"workload": w.name, "unknowns": int(w.n_unknowns), "leaves": int(w.n_leaves), "boxes": int(tree.n_boxes),
+           "leaf_levels": sorted(set(int(x) for x in w.level)), "generation_s": round(gen_s, 1)}
+    sols = {}
+    for precision in ("fp64", "mixed"):
+        ms, (_, st) = timed_loop(args, torch, lambda: A.solve(
+            tree, rho, bc, u, cycle="FMG", tol=1e-10, precision=precision, workspace=work, stream=stream,
+            use_guess=False, graph=True))
+        sols[precision] = tree.boxes_to_leaf(u).cpu().numpy()
+        out[precision] = {"value": w.n_unknowns / (ms * 1e-3), "unit": "unknowns/s", "ms_per_step": ms,
+                          "cycles": st["cycles"], "final_residual_ratio": st["r_max"] / st["r0_max"]}
+    nrm = np.linalg.norm(sols["fp64"])
+    out["mixed"]["rel_l2_vs_gpu_fp64"] = float(np.linalg.norm(sols["mixed"] - sols["fp64"]) / nrm)
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        uo, so = O.Tree(w.dim, w.N, w.level, w.idx).solve(w.rho, w.bc, cycle="FMG", tol=1e-10)
+        dt = time.perf_counter() - t0
+        no = np.linalg.norm(uo)
+        out["oracle"] = {"value": w.n_unknowns / dt, "unit": "unknowns/s", "cores": O.num_threads(),
+                         "seconds": round(dt, 2), "cycles": so["cycles"]}
+        out["fp64"]["rel_l2_vs_oracle"] = float(np.linalg.norm(sols["fp64"] - uo) / no)
+        out["mixed"]["rel_l2_vs_oracle"] = float(np.linalg.norm(sols["mixed"] - uo) / no)
+    return out
+
+
+def adjoint_bench(args, A, torch, dev, stream):
+    """The adjoint workload: 3D adaptive octree with about 4e6 unknowns, loss
+    = sum over leaf cells of (u - u_t)^2.  Forward: FP64 FMG + V-cycles to
+    1e-10; backward: afmg_adjoint (BiCGSTAB on L^T preconditioned by one
+    V-cycle, to 1e-10).  Checked against central finite differences along
+    seeded random directions of rho and of the Dirichlet values (exact for
+    this quadratic loss up to the solve tolerance)."""
+    from paper_1701_04329_amd import workloads as W
+
+    t0 = time.perf_counter()
+    w, u_t = W.config5()
+    gen_s = time.perf_counter() - t0
+    tree = A.Tree(w.dim, w.level, w.idx)
+    if not args.no_autotune:
+        tree.autotune(dev, stream)
+    rho = tree.leaf_to_boxes(torch.tensor(w.rho, device=dev))
+    bc = tree.bc_rows(torch.tensor(w.bc, device=dev))
+    ut = tree.leaf_to_boxes(torch.tensor(u_t, device=dev))
+    leaf = torch.zeros(tree.n_boxes, dtype=torch.bool, device=dev)
+    leaf[torch.as_tensor(tree.leaf_boxes, device=dev).long()] = True
+    work = torch.empty(max(tree.workspace_bytes(), tree.adjoint_workspace_bytes()), dtype=torch.uint8, device=dev)
+
+    u_buf = torch.empty_like(rho)
+
+    def loss_of(r, b, tol=1e-10):
+        u, st = A.solve(tree, r, b, u_buf, cycle="FMG", tol=tol, workspace=work, stream=stream, use_guess=False,
+                        graph=True)
+        return float(((u - ut)[leaf] ** 2).sum()), u, st
+
+    fwd_ms, (loss, u, st_f) = timed_loop(args, torch, lambda: loss_of(rho, bc))
+    u_bar = torch.where(leaf[:, None], 2.0 * (u - ut), torch.zeros_like(u))
+    bwd_ms, (rho_bar, bc_bar, st_b) = timed_loop(args, torch, lambda: A.adjoint(
+        tree, u_bar, tol=1e-10, max_cycles=200, workspace=work, stream=stream))
+    gen = torch.Generator(device="cpu").manual_seed(5002)
+    checks = []
+    t0 = time.perf_counter()
+    for kind in ("rho", "bc", "rho"):
+        if kind == "rho":
+            d = torch.randn(rho.shape, generator=gen, dtype=torch.float64).to(dev) * leaf[:, None]
+            d *= float(rho.abs().max()) / float(d.abs().max())
+            lp = loss_of(rho + d, bc, 1e-12)[0]
+            lm = loss_of(rho - d, bc, 1e-12)[0]
+            g = float((rho_bar * d).sum())
+        else:
+            d = torch.randn(bc.shape, generator=gen, dtype=torch.float64).to(dev)
+            d *= float(bc.abs().max()) / float(d.abs().max())
+            lp = loss_of(rho, bc + d, 1e-12)[0]
+            lm = loss_of(rho, bc - d, 1e-12)[0]
+            g = float((bc_bar * d).sum())
+        fd = (lp - lm) / 2.0
+        checks.append({"wrt": kind, "adjoint": g, "finite_difference": fd, "rel_err": abs(g - fd) / abs(fd)})
+    fd_ms = (time.perf_counter() - t0) * 1e3 / len(checks)
+    return {
+        "workload": w.name, "unknowns": int(w.n_unknowns), "leaves": int(w.n_leaves), "boxes": int(tree.n_boxes),
+        "loss": loss, "forward_ms": fwd_ms, "forward_cycles": st_f["cycles"],
+        "backward_ms": bwd_ms, "backward_iterations": st_b["cycles"],
+        "backward_residual_ratio": st_b["r_max"] / st_b["r0_max"],
+        "fd_ms_per_check": fd_ms, "fd_checks": checks, "generation_s": round(gen_s, 1),
+        "note": "backward = BiCGSTAB on L^T right-preconditioned by a volume-scaled V-cycle (the operator is "
+                "not symmetric at refinement boundaries); FD checks solve to 1e-12",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,6 +325,10 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-tree batch workload")
     ap.add_argument("--batch-trees", type=int, default=256)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--skip-unbatched", action="store_true",
+                    help="batch workload: skip the one-tree-at-a-time comparison pass")
+    ap.add_argument("--no-adaptive", action="store_true", help="skip the adaptive 3D workload (FP64 vs mixed)")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint workload")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batch workload and print its record (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -370,6 +492,10 @@ def main():
     }
     if not args.no_batch:
         out["batch"] = batch_bench(args, A, torch, dev, stream)
+    if not args.no_adaptive:
+        out["adaptive"] = adaptive_bench(args, A, torch, dev, stream)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_bench(args, A, torch, dev, stream)
     if not args.no_cpu_baseline:
         uo, out["cpu_baseline"] = cpu_baseline(w, solve_kw)
         nrm = np.linalg.norm(uo)

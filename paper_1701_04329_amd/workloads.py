@@ -363,6 +363,20 @@ def config3(N=BOX_N_DEFAULT, lmax=8, threshold=1e-4, seed=3, n_src=4,
     return sample_workload(f"c3_3d_adaptive_l{lmax}", 3, N, lev, idx, mix)
 
 
+def config5(N=BOX_N_DEFAULT, lmax=7, threshold=2e-3):
+    """3D adaptive octree for the adjoint (about 4e6 unknowns): rho and the
+    Dirichlet values from mixture A (4 Gaussians, centres in [0.1, 0.9]^3,
+    sigma log-uniform in [0.01, 0.05], seed 5000), refined where
+    |lap u| h^2 > threshold; the loss target u_t at the leaf cell centres from
+    mixture B (3 Gaussians, sigma uniform in [0.05, 0.1], seed 5001).
+    Returns (workload, u_t [n_leaves, N^3])."""
+    mix_a = gauss_mix_seeded(3, 4, 5000, 0.1, 0.9, (0.01, 0.05), log_sigma=True)
+    lev, idx = adaptive_leaves(3, N, laplacian_flag(mix_a, N, threshold), lmax)
+    w = sample_workload(f"c5_3d_adaptive_l{lmax}", 3, N, lev, idx, mix_a)
+    mix_b = gauss_mix_seeded(3, 3, 5001, 0.1, 0.9, (0.05, 0.1))
+    return w, mix_b.value(cell_centres(3, N, lev, idx))
+
+
 def adaptive_small(dim, N, lmax, threshold, seed, n_src=2, sigma_range=(0.03, 0.08),
                    name=None):
     """Small adaptive grid for tests: Gaussians in [0.1, 0.9]^D."""

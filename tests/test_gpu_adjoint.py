@@ -159,3 +159,46 @@ def test_autograd_through_poisson_solve():
     np.testing.assert_allclose(g_rho, lam, rtol=1e-8, atol=1e-9 * np.abs(lam).max())
     np.testing.assert_allclose(bc.grad.cpu().numpy(), t.bc_rows(gbc), rtol=1e-8,
                                atol=1e-9 * np.abs(gbc).max())
+
+
+def test_full_size_adjoint_workload():
+    """The adjoint benchmark octree at full size (about 4e6 unknowns): the
+    transpose dot-product identity, and the gradients with respect to rho and
+    the Dirichlet values against central differences of GPU solves (exact for
+    the quadratic loss up to the solve tolerance)."""
+    from paper_1701_04329_amd import afmg as AF
+    w, u_t = W.config5()
+    print(f"[case] full-size adjoint {w.name} unknowns={w.n_unknowns}", flush=True)
+    t = AF.Tree(3, w.level, w.idx)
+    D = dev()
+    rng = np.random.default_rng(51)
+    x = t.leaf_to_boxes(torch.tensor(rng.standard_normal((w.n_leaves, 512)), device=D))
+    y = t.leaf_to_boxes(torch.tensor(rng.standard_normal((w.n_leaves, 512)), device=D))
+    a = float((AF.apply(t, x, "L") * y).sum())
+    b = float((x * AF.apply(t, y, "LT")).sum())
+    assert a == pytest.approx(b, rel=1e-11)
+    rho = t.leaf_to_boxes(torch.tensor(w.rho, device=D))
+    bc = t.bc_rows(torch.tensor(w.bc, device=D))
+    utd = t.leaf_to_boxes(torch.tensor(u_t, device=D))
+    leaf = torch.zeros(t.n_boxes, dtype=torch.bool, device=D)
+    leaf[torch.as_tensor(t.leaf_boxes, device=D).long()] = True
+
+    def loss(r, bb):
+        u, st = AF.solve(t, r, bb, cycle="FMG", tol=1e-12, max_cycles=200)
+        assert st["status"] == 0
+        return float(((u - utd)[leaf] ** 2).sum()), u
+
+    _, u = loss(rho, bc)
+    ubar = torch.where(leaf[:, None], 2.0 * (u - utd), torch.zeros_like(u))
+    rb, bb, st = AF.adjoint(t, ubar, tol=1e-12, max_cycles=400)
+    print(f"adjoint iterations {st['cycles']} residual ratio {st['r_max'] / st['r0_max']:.1e}", flush=True)
+    assert st["status"] == 0
+    dr = t.leaf_to_boxes(torch.tensor(rng.standard_normal((w.n_leaves, 512)), device=D))
+    db = torch.tensor(rng.standard_normal(tuple(bc.shape)), device=D)
+    fd_r = (loss(rho + dr, bc)[0] - loss(rho - dr, bc)[0]) / 2.0
+    fd_b = (loss(rho, bc + db)[0] - loss(rho, bc - db)[0]) / 2.0
+    ad_r = float((rb * dr).sum())
+    ad_b = float((bb * db).sum())
+    print(f"rho: adjoint {ad_r:.12e} fd {fd_r:.12e}; bc: adjoint {ad_b:.12e} fd {fd_b:.12e}", flush=True)
+    assert ad_r == pytest.approx(fd_r, rel=1e-7)
+    assert ad_b == pytest.approx(fd_b, rel=1e-7)

@@ -60,3 +60,33 @@ def test_mixed_matches_fp64_oracle(name, cycle):
     assert err <= BOUND
     assert sm["cycles"] <= so["cycles"] + 2
     np.testing.assert_allclose(sm["r0_max"], so["r0_max"], rtol=1e-12)
+
+
+def test_full_size_adaptive_fp64_and_mixed_against_oracle():
+    """The adaptive benchmark octree at full size (about 2.3e7 unknowns on
+    leaves of levels 3-8): FP64 at a fixed cycle count against the oracle to
+    1e-12, and the mixed refinement at a 1e-10 residual reduction against the
+    oracle's FP64 solve to the mixed bound."""
+    from paper_1701_04329_amd import afmg as A
+    w = W.config3()
+    print(f"[case] full-size adaptive {w.name} unknowns={w.n_unknowns}", flush=True)
+    t = A.Tree(w.dim, w.level, w.idx)
+    dev = torch.device("cuda", 0)
+    rho = t.leaf_to_boxes(torch.tensor(w.rho, device=dev))
+    bc = t.bc_rows(torch.tensor(w.bc, device=dev))
+    ot = O.Tree(w.dim, w.N, w.level, w.idx)
+    u, s = A.solve(t, rho, bc, cycle="FMG", fixed_cycles=2)
+    ug = t.boxes_to_leaf(u).cpu().numpy()
+    uo, so = ot.solve(w.rho, w.bc, cycle="FMG", fixed_cycles=2)
+    err = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
+    print(f"FP64 FMG+2V vs oracle: {err:.2e}", flush=True)
+    assert err <= 1e-12
+    np.testing.assert_allclose(s["r0_max"], so["r0_max"], rtol=1e-12)
+    u, s = A.solve(t, rho, bc, cycle="FMG", tol=1e-10, precision="mixed")
+    um = t.boxes_to_leaf(u).cpu().numpy()
+    uo, so = ot.solve(w.rho, w.bc, cycle="FMG", tol=1e-10)
+    err = np.linalg.norm(um - uo) / np.linalg.norm(uo)
+    print(f"mixed to 1e-10: outer={s['cycles']} fp64 oracle cycles={so['cycles']} rel-L2 {err:.2e}", flush=True)
+    assert s["status"] == 0 and s["r_max"] <= 1e-10 * s["r0_max"]
+    assert err <= BOUND
+    assert s["cycles"] <= so["cycles"] + 2
