@@ -10,7 +10,8 @@ the timed region starts.
 Prints one JSON line: throughput in unknowns/s, the roofline of the dominant
 kernel (the finest-level red-black half sweep) measured with HIP events on
 the solve's stream during the timed steps, and the FP64 CPU oracle timed on
-the host cores on the same workload.
+the host cores on the same workload.  Further objects: the mixed-precision solve, the
+256-tree batch, the adaptive octree (FP64 vs mixed) and the adjoint.
 """
 
 from __future__ import annotations
@@ -371,28 +372,30 @@ def main():
     ws = torch.empty(tree.workspace_bytes(opts), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream(dev)
 
-    def timed_steps(precision, graph=False):
+    def timed_steps(precision, graph=False, profile=True):
         """warmup + exactly `steps` timed solves; returns ms/step, the
-        summed event timings of the finest-level kernels (without graph
-        replay) and the last stats."""
+        summed event timings of the finest-level kernels (profile: event
+        pairs around each group of consecutive finest-level half sweeps and
+        each other finest-level launch; profiled solves launch eagerly) and
+        the last stats."""
         kw = dict(solve_kw, precision=precision)
         ws_p = ws if tree.workspace_bytes(A.make_opts(**kw)) <= ws.numel() else torch.empty(
             tree.workspace_bytes(A.make_opts(**kw)), dtype=torch.uint8, device=dev)
 
-        def one(profile):
+        def one(prof):
             # every step starts from u = 0 (the library zeroes u itself)
-            return A.solve(tree, rho, bc, u, workspace=ws_p, stream=stream, profile=profile,
+            return A.solve(tree, rho, bc, u, workspace=ws_p, stream=stream, profile=prof,
                            use_guess=False, graph=graph, **kw)
 
         for _ in range(args.warmup):
-            one(False)
+            one(profile)
         torch.cuda.synchronize()
         prof_ms = np.zeros(4)
         prof_n = np.zeros(4, dtype=np.int64)
         cycles = []
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            _, st = one(not graph)
+            _, st = one(profile)
             prof_ms += np.array(st["prof_ms"])
             prof_n += np.array(st["prof_n"], dtype=np.int64)
             cycles.append(st["cycles"])
@@ -403,8 +406,8 @@ def main():
     # launch shapes: untuned time first, then the autotuner (setup, untimed)
     tune = None
     if not args.no_autotune:
-        ms_untuned, _, _, _, _ = timed_steps("fp64", graph=True)
-        ms_untuned_m, _, _, _, _ = timed_steps("mixed", graph=True)
+        ms_untuned, _, _, _, _ = timed_steps("fp64", graph=True, profile=False)
+        ms_untuned_m, _, _, _, _ = timed_steps("mixed", graph=True, profile=False)
         t0 = time.perf_counter()
         shapes = tree.autotune(dev, stream)
         tune = {"untuned_fp64_graph_ms_per_step": ms_untuned, "untuned_mixed_graph_ms_per_step": ms_untuned_m,
@@ -453,10 +456,10 @@ def main():
         "dominant_avg_launch_ms": round(avg_m, 5),
     }
 
-    # the repeated cycle replayed from a recorded HIP graph (no per-kernel events)
-    ms_g, _, _, _, _ = timed_steps("fp64", graph=True)
-    ms_gm, _, _, _, _ = timed_steps("mixed", graph=True)
-    mixed["graph_ms_per_step"] = ms_gm
+    # context: the repeated cycle replayed from a recorded HIP graph (no
+    # event pairs)
+    ms_g, _, _, _, _ = timed_steps("fp64", graph=True, profile=False)
+    ms_gm, _, _, _, _ = timed_steps("mixed", graph=True, profile=False)
     graph = {"fp64_ms_per_step": ms_g, "mixed_ms_per_step": ms_gm,
              "fp64_value": w.n_unknowns / (ms_g * 1e-3), "mixed_value": w.n_unknowns / (ms_gm * 1e-3)}
 
@@ -484,6 +487,7 @@ def main():
             "v_cycles": int(np.median(cycles)),
             "final_residual_ratio": st64["r_max"] / st64["r0_max"],
             "precision": "fp64",
+            "schedule": "eager launches with event pairs (timed region); autotuned launch shapes",
         },
         "roofline": roofline,
         "mixed": mixed,

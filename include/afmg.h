@@ -75,7 +75,8 @@ typedef struct {
     int use_guess;    /* 1: u holds the initial guess on leaf boxes (V only) */
     int precision;    /* AFMG_FP64 (default) or AFMG_MIXED */
     int profile;      /* 1: time the finest-level kernels with HIP events
-                         (stats.prof_*); adds one event pair per launch */
+                         (stats.prof_*); one event pair per launch, or per
+                         group of consecutive half sweeps */
     int graph;        /* 1: record the repeated cycle (V-cycle, refinement
                          update, residual) once as a HIP graph and replay it;
                          ignored while profiling.  Results are identical. */

@@ -264,8 +264,8 @@ class Tree(_Shapes):
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().afmg_tree_destroy(h)
+        if h is not None and h.value and _lib is not None:
+            _lib.afmg_tree_destroy(h)
             self._h = None
 
     @property
@@ -398,8 +398,8 @@ class Batch(_Shapes):
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().afmg_batch_destroy(h)
+        if h is not None and h.value and _lib is not None:
+            _lib.afmg_batch_destroy(h)
             self._h = None
 
     @property

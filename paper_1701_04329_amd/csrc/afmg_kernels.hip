@@ -665,63 +665,101 @@ __global__ __launch_bounds__(W) void k_prolong(LevelArgs<T> a) {
 // mixed-precision refinement.
 template <int D, int N, typename T, int W>
 __global__ __launch_bounds__(W) void k_final(LevelArgs<T> a, double *partial, int64_t part0, double hD,
-                                               float *__restrict__ rout) {
+                                             float *__restrict__ rout) {
     using G = Geo<D, N>;
+    constexpr int NW = W / 64;  // waves per workgroup
     __shared__ T sm[(W / G::TPB) * G::PC];
-    __shared__ double red_m[W], red_s[W];
+    __shared__ double red_m[NW], red_s[NW];
     const Slot<D, N> sl = slot_of<D, N, W>(a);
     T *s = sm + sl.slot * G::PC;
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
     const bool leaf = bi.flags & FLAG_LEAF;
     Stager<D, N, T> st;
-    if (sl.valid) st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, leaf);
+    if (sl.valid) {
+        if (leaf) st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, true);
+        else st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, false);
+    }
     __syncthreads();
     if (sl.valid && leaf) st.end(s, sl.t);
     __syncthreads();
+    // each thread: 2^D blocks of cells = parent cells; the block mean of u
+    // goes to the parent, the residuals of leaves stay in registers
     double mx = 0.0, ss = 0.0;
     if (sl.valid) {
-        if (bi.parent >= 0) restrict_octant<D, N, T, true>(s, a.u, bi, sl.t);
-        if (leaf) {
-            for (int e = sl.t; e < G::C; e += G::TPB) {
-                int i, j, k;
-                cell_of<D, N>(e, i, j, k);
-                const double r = (double)(a.rho[bo + e] - (nb_sum<D, N, T>(s, i, j, k) -
-                                                          T(2 * D) * s[padi<D, N>(i, j, k)]) * a.ih2);
-                if (rout) rout[bo + e] = (float)r;
-                mx = fmax(mx, fabs(r));
-                ss += r * r;
+        const T w = D == 3 ? T(0.125) : T(0.25);
+        const int flags = bi.flags;
+        const int64_t p = bi.parent;
+        for (int pc = sl.t; pc < G::HC; pc += G::TPB) {
+            const int I = pc % G::H, J = (pc / G::H) % G::H, K = D == 3 ? pc / (G::H * G::H) : 0;
+            T su = T(0);
+            if (leaf) {
+                // all residuals of the block first (their loads in flight
+                // together), then the optional FP32 copies
+                constexpr int NB = D == 3 ? 8 : 4;
+                double r[NB];
+                int e[NB];
+#pragma unroll
+                for (int q = 0; q < NB; q++) {
+                    const int i = 2 * I + (q & 1), j = 2 * J + ((q >> 1) & 1), k = D == 3 ? 2 * K + (q >> 2) : 0;
+                    const T uc = s[padi<D, N>(i, j, k)];
+                    su += uc;
+                    e[q] = cpos<D, N>(i, j, k);
+                    r[q] = (double)(a.rho[bo + e[q]] - (nb_sum<D, N, T>(s, i, j, k) - T(2 * D) * uc) * a.ih2);
+                }
+                if (rout) {
+#pragma unroll
+                    for (int q = 0; q < NB; q++) rout[bo + e[q]] = (float)r[q];
+                }
+#pragma unroll
+                for (int q = 0; q < NB; q++) {
+                    mx = fmax(mx, fabs(r[q]));
+                    ss += r[q] * r[q];
+                }
+            } else {
+                for (int dk = 0; dk < (D == 3 ? 2 : 1); dk++)
+                    for (int dj = 0; dj < 2; dj++)
+                        for (int di = 0; di < 2; di++)
+                            su += s[padi<D, N>(2 * I + di, 2 * J + dj, D == 3 ? 2 * K + dk : 0)];
+            }
+            if (p >= 0) {
+                const int X = obit(flags, 0) * G::H + I, Y = obit(flags, 1) * G::H + J,
+                          Z = D == 3 ? obit(flags, 2) * G::H + K : 0;
+                a.u[(size_t)p * G::C + cpos<D, N>(X, Y, Z)] = w * su;
             }
         }
     }
-    red_m[threadIdx.x] = mx;
-    red_s[threadIdx.x] = ss;
-    __syncthreads();
+    // reduce over the TPB threads of the box (one wave in 3D, 8 lanes in 2D)
+    for (int o = G::TPB / 2; o > 0; o >>= 1) {
+        mx = fmax(mx, __shfl_xor(mx, o));
+        ss += __shfl_xor(ss, o);
+    }
     if (part0 < 0) {
-        // per box: reduce the TPB threads of each slot
-        for (int w = G::TPB / 2; w > 0; w >>= 1) {
-            if (sl.t < w) {
-                red_m[threadIdx.x] = fmax(red_m[threadIdx.x], red_m[threadIdx.x + w]);
-                red_s[threadIdx.x] += red_s[threadIdx.x + w];
-            }
-            __syncthreads();
-        }
         if (sl.valid && leaf && sl.t == 0) {
-            partial[2 * sl.b + 0] = red_m[threadIdx.x];
-            partial[2 * sl.b + 1] = red_s[threadIdx.x] * hD;
+            partial[2 * sl.b + 0] = mx;
+            partial[2 * sl.b + 1] = ss * hD;
         }
         return;
     }
-    for (int w = W / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            red_m[threadIdx.x] = fmax(red_m[threadIdx.x], red_m[threadIdx.x + w]);
-            red_s[threadIdx.x] += red_s[threadIdx.x + w];
-        }
-        __syncthreads();
+    // then over the boxes of the wave and the waves of the workgroup
+    for (int o = 32; o >= G::TPB; o >>= 1) {
+        mx = fmax(mx, __shfl_xor(mx, o));
+        ss += __shfl_xor(ss, o);
     }
+    const int wave = (int)threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0) {
+        red_m[wave] = mx;
+        red_s[wave] = ss;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        partial[2 * (part0 + blockIdx.x) + 0] = red_m[0];
-        partial[2 * (part0 + blockIdx.x) + 1] = red_s[0] * hD;
+        double m = red_m[0], t = red_s[0];
+        for (int q = 1; q < NW; q++) {
+            m = fmax(m, red_m[q]);
+            t += red_s[q];
+        }
+        partial[2 * (part0 + blockIdx.x) + 0] = m;
+        partial[2 * (part0 + blockIdx.x) + 1] = t * hD;
     }
 }
 
@@ -950,21 +988,22 @@ __global__ __launch_bounds__(256) void k_bc_derive(const BoxInfo *__restrict__ i
 // levels <= 1: the root box and the coarse grids below it, one workgroup
 // ---------------------------------------------------------------------------
 // The grids of N, N/2, ..., 2 cells per side (levels 1, 0, ..., lmin) are
-// single boxes with Dirichlet sides only; they live in LDS with a stored ghost
-// layer, in FP64 for every precision of the caller's arrays.
+// single boxes whose sides are all physical (Dirichlet).  They live in LDS
+// without ghost layers, in FP64 for every precision of the caller's arrays.
+// The grid index G (0: N cells per side) is a template parameter, so every
+// index is a compile-time shift; the side ghosts 2 b - u1 (paper §2.4) are
+// formed inline, with the same arithmetic a stored ghost layer would hold.
 template <int D, int N>
 struct CoarseGeo {
     static constexpr int lg(int n) { return n <= 1 ? 0 : 1 + lg(n / 2); }
-    static constexpr int NL = lg(N);  // grids of N, N/2, ..., 2 cells
-    static constexpr int n(int li) { return N >> li; }
-    static constexpr int psz(int li) {
-        return D == 3 ? (n(li) + 2) * (n(li) + 2) * (n(li) + 2) : (n(li) + 2) * (n(li) + 2);
-    }
-    static constexpr int poff(int li) { return li == 0 ? 0 : poff(li - 1) + psz(li - 1); }
-    static constexpr int PTOT = poff(NL);
-    static constexpr int fsz(int li) { return D == 3 ? n(li) * n(li) : n(li); }
-    static constexpr int boff(int li) { return li == 0 ? 0 : boff(li - 1) + 2 * D * fsz(li - 1); }
-    static constexpr int BTOT = boff(NL);
+    static constexpr int NG = lg(N);  // grids of N, N/2, ..., 2 cells
+    static constexpr int n(int g) { return N >> g; }
+    static constexpr int cells(int g) { return D == 3 ? n(g) * n(g) * n(g) : n(g) * n(g); }
+    static constexpr int off(int g) { return g == 0 ? 0 : off(g - 1) + cells(g - 1); }
+    static constexpr int TOT = off(NG);
+    static constexpr int fsz(int g) { return D == 3 ? n(g) * n(g) : n(g); }
+    static constexpr int boff(int g) { return g == 0 ? 0 : boff(g - 1) + 2 * D * fsz(g - 1); }
+    static constexpr int BTOT = boff(NG);
 };
 
 template <int D, int N>
@@ -973,152 +1012,181 @@ struct CoarseState {
     double *u, *rho, *uold, *res, *bc;
     int n_down, n_up, n_base;
 
-    __device__ int pidx(int li, int i, int j, int k) const {
-        const int m = CG::n(li) + 2;
-        return CG::poff(li) + (D == 3 ? (i + 1) + m * ((j + 1) + m * (k + 1)) : (i + 1) + m * (j + 1));
-    }
-    __device__ static double hlev(int li) { return (double)(1 << li) / (double)N; }
-
-    template <int S>
-    __device__ void fill_side(double *f, int li, int m) const {
-        using SD = SideOf<S>;
-        const int n = CG::n(li);
-        int x[3];
-        x[SD::t1] = m % n;
-        x[SD::t2] = D == 3 ? m / n : 0;
-        x[SD::d] = SD::hi ? n - 1 : 0;
-        const double u1 = f[pidx(li, x[0], x[1], x[2])];
-        const double bv = bc[CG::boff(li) + S * CG::fsz(li) + m];
-        x[SD::d] = SD::hi ? n : -1;
-        f[pidx(li, x[0], x[1], x[2])] = 2.0 * bv - u1;
-    }
-    __device__ void fill(double *f, int li) const {
-        const int F = CG::fsz(li);
-        for (int g = threadIdx.x; g < 2 * D * F; g += blockDim.x) {
-            const int side = g / F, m = g % F;
-#define AFMG_CF(S) fill_side<S>(f, li, m)
-            AFMG_SIDE_SWITCH(side, AFMG_CF)
-#undef AFMG_CF
-        }
-        __syncthreads();
-    }
-    __device__ double nbs(const double *f, int li, int i, int j, int k) const {
-        if (D == 2)
-            return (f[pidx(li, i - 1, j, k)] + f[pidx(li, i + 1, j, k)]) +
-                   (f[pidx(li, i, j - 1, k)] + f[pidx(li, i, j + 1, k)]);
-        return (f[pidx(li, i - 1, j, k)] + f[pidx(li, i + 1, j, k)]) +
-               (f[pidx(li, i, j - 1, k)] + f[pidx(li, i, j + 1, k)]) +
-               (f[pidx(li, i, j, k - 1)] + f[pidx(li, i, j, k + 1)]);
-    }
-    __device__ void cell(int li, int c, int &i, int &j, int &k) const {
-        const int n = CG::n(li);
+    template <int G>
+    __device__ __forceinline__ static void ijk(int c, int &i, int &j, int &k) {
+        constexpr int n = CG::n(G);
         i = c % n;
         j = (c / n) % n;
         k = D == 3 ? c / (n * n) : 0;
     }
-    __device__ int ncell(int li) const {
-        return D == 3 ? CG::n(li) * CG::n(li) * CG::n(li) : CG::n(li) * CG::n(li);
+    // Dirichlet value of side `side` next to cell (i, j, k) of grid G (the
+    // tangential axes in increasing order, the first fastest)
+    template <int G>
+    __device__ __forceinline__ double bval(int side, int i, int j, int k) const {
+        constexpr int n = CG::n(G), F = CG::fsz(G);
+        const int d = side >> 1;
+        const int m = d == 0 ? j + n * k : d == 1 ? i + n * k : i + n * j;
+        return bc[CG::boff(G) + side * F + m];
     }
+    // sum of the 2D neighbours of cell (i, j, k) of f on grid G
+    template <int G>
+    __device__ __forceinline__ double nbs(const double *f, int i, int j, int k) const {
+        constexpr int n = CG::n(G);
+        const double *g = f + CG::off(G);
+        const int c = i + n * (j + n * k);
+        const double uc = g[c];
+        const double xm = i > 0 ? g[c - 1] : 2.0 * bval<G>(0, i, j, k) - uc;
+        const double xp = i < n - 1 ? g[c + 1] : 2.0 * bval<G>(1, i, j, k) - uc;
+        const double ym = j > 0 ? g[c - n] : 2.0 * bval<G>(2, i, j, k) - uc;
+        const double yp = j < n - 1 ? g[c + n] : 2.0 * bval<G>(3, i, j, k) - uc;
+        double s = (xm + xp) + (ym + yp);
+        if (D == 3) {
+            const double zm = k > 0 ? g[c - n * n] : 2.0 * bval<G>(4, i, j, k) - uc;
+            const double zp = k < n - 1 ? g[c + n * n] : 2.0 * bval<G>(5, i, j, k) - uc;
+            s = s + (zm + zp);
+        }
+        return s;
+    }
+    template <int G>
+    __device__ static constexpr double hgrid() { return (double)(1 << G) / (double)N; }
 
-    __device__ void half(int li, int colour) const {
-        fill(u, li);
-        const double h = hlev(li), h2 = h * h;
-        for (int c = threadIdx.x; c < ncell(li); c += blockDim.x) {
-            int i, j, k;
-            cell(li, c, i, j, k);
-            if (((i + j + k + D) & 1) != colour) continue;
-            const int p = pidx(li, i, j, k);
-            u[p] = (nbs(u, li, i, j, k) - h2 * rho[p]) / double(2 * D);
+    // one colour of grid G
+    template <int G>
+    __device__ __forceinline__ void half(int colour) const {
+        constexpr int n = CG::n(G), hn = n / 2, o = CG::off(G);
+        constexpr double h = hgrid<G>(), h2 = h * h;
+        for (int q = threadIdx.x; q < CG::cells(G) / 2; q += blockDim.x) {
+            const int r = q / hn, j = r % n, k = D == 3 ? r / n : 0;
+            const int i = 2 * (q % hn) + ((colour + j + k + D) & 1);
+            const int c = i + n * (j + n * k);
+            u[o + c] = (nbs<G>(u, i, j, k) - h2 * rho[o + c]) / double(2 * D);
         }
         __syncthreads();
     }
-    __device__ void gsrb(int li, int nsweep) const {
+    template <int G>
+    __device__ __forceinline__ void gsrb(int nsweep) const {
         for (int q = 0; q < nsweep; q++) {
-            half(li, 0);
-            half(li, 1);
+            half<G>(0);
+            half<G>(1);
         }
     }
-    // res = rho - L u (ghosts of u must be filled)
-    __device__ void residual(int li) const {
-        const double h = hlev(li), ih2 = 1.0 / (h * h);
-        for (int c = threadIdx.x; c < ncell(li); c += blockDim.x) {
-            int i, j, k;
-            cell(li, c, i, j, k);
-            const int p = pidx(li, i, j, k);
-            res[p] = rho[p] - (nbs(u, li, i, j, k) - double(2 * D) * u[p]) * ih2;
+    // grid G+1 <- means of u and of the residual rho - L u of grid G
+    template <int G>
+    __device__ __forceinline__ void resid_restrict() const {
+        constexpr int n = CG::n(G), nc = CG::n(G + 1), o = CG::off(G), oc = CG::off(G + 1);
+        constexpr double h = hgrid<G>(), ih2 = 1.0 / (h * h);
+        const double w = D == 3 ? 0.125 : 0.25;
+        for (int C = threadIdx.x; C < CG::cells(G + 1); C += blockDim.x) {
+            const int I = C % nc, J = (C / nc) % nc, K = D == 3 ? C / (nc * nc) : 0;
+            double au = 0.0, ar = 0.0;
+            for (int dk = 0; dk < (D == 3 ? 2 : 1); dk++)
+                for (int dj = 0; dj < 2; dj++)
+                    for (int di = 0; di < 2; di++) {
+                        const int i = 2 * I + di, j = 2 * J + dj, k = D == 3 ? 2 * K + dk : 0;
+                        const int c = i + n * (j + n * k);
+                        au += u[o + c];
+                        ar += rho[o + c] - (nbs<G>(u, i, j, k) - double(2 * D) * u[o + c]) * ih2;
+                    }
+            u[oc + C] = w * au;
+            res[oc + C] = w * ar;
         }
         __syncthreads();
     }
-    // f at li+1 <- mean of f at li
-    __device__ void restrict_to_coarser(double *f, int li) const {
-        const int nc = CG::n(li + 1);
-        const int cells = D == 3 ? nc * nc * nc : nc * nc;
+    // rho of grid G (FMG) -> grid G+1
+    template <int G>
+    __device__ __forceinline__ void restrict_rho() const {
+        constexpr int n = CG::n(G), nc = CG::n(G + 1), o = CG::off(G), oc = CG::off(G + 1);
         const double w = D == 3 ? 0.125 : 0.25;
-        for (int c = threadIdx.x; c < cells; c += blockDim.x) {
-            const int I = c % nc, J = (c / nc) % nc, K = D == 3 ? c / (nc * nc) : 0;
+        for (int C = threadIdx.x; C < CG::cells(G + 1); C += blockDim.x) {
+            const int I = C % nc, J = (C / nc) % nc, K = D == 3 ? C / (nc * nc) : 0;
             double acc = 0.0;
             for (int dk = 0; dk < (D == 3 ? 2 : 1); dk++)
                 for (int dj = 0; dj < 2; dj++)
                     for (int di = 0; di < 2; di++)
-                        acc += f[pidx(li, 2 * I + di, 2 * J + dj, D == 3 ? 2 * K + dk : 0)];
-            f[pidx(li + 1, I, J, K)] = w * acc;
+                        acc += rho[o + (2 * I + di) + n * ((2 * J + dj) + n * (D == 3 ? 2 * K + dk : 0))];
+            rho[oc + C] = w * acc;
         }
         __syncthreads();
     }
-    __device__ void copy_uold(int li) const {
-        for (int p = threadIdx.x; p < CG::psz(li); p += blockDim.x) uold[CG::poff(li) + p] = u[CG::poff(li) + p];
-        __syncthreads();
-    }
-    // rho <- res + L u (ghosts filled)
-    __device__ void coarse_rhs(int li) const {
-        const double h = hlev(li), ih2 = 1.0 / (h * h);
-        for (int c = threadIdx.x; c < ncell(li); c += blockDim.x) {
+    // copy v' of grid G, and the FAS right-hand side rho <- rbar + L u
+    template <int G>
+    __device__ __forceinline__ void uold_crhs() const {
+        constexpr int o = CG::off(G);
+        constexpr double h = hgrid<G>(), ih2 = 1.0 / (h * h);
+        for (int c = threadIdx.x; c < CG::cells(G); c += blockDim.x) {
             int i, j, k;
-            cell(li, c, i, j, k);
-            const int p = pidx(li, i, j, k);
-            rho[p] = res[p] + (nbs(u, li, i, j, k) - double(2 * D) * u[p]) * ih2;
+            ijk<G>(c, i, j, k);
+            uold[o + c] = u[o + c];
+            rho[o + c] = res[o + c] + (nbs<G>(u, i, j, k) - double(2 * D) * u[o + c]) * ih2;
         }
         __syncthreads();
     }
-    // u(li) += P211(u - uold at li+1, ghosts included)
-    __device__ void prolong(int li) const {
-        for (int c = threadIdx.x; c < ncell(li); c += blockDim.x) {
+    // u - v' on grid G at (I, J, K) + s e_axis; outside the grid the ghost of
+    // u minus the ghost of v' (the Dirichlet value cancels up to rounding)
+    template <int G>
+    __device__ __forceinline__ double delta(int axis, int I, int J, int K, int s) const {
+        constexpr int n = CG::n(G), o = CG::off(G);
+        int a[3] = {I, J, K};
+        a[axis] += s;
+        if (a[axis] >= 0 && a[axis] < n) {
+            const int c = a[0] + n * (a[1] + n * a[2]);
+            return u[o + c] - uold[o + c];
+        }
+        const int c = I + n * (J + n * K);
+        const double b = bval<G>(2 * axis + (s > 0 ? 1 : 0), I, J, K);
+        return (2.0 * b - u[o + c]) - (2.0 * b - uold[o + c]);
+    }
+    // u of grid G += P211(u - v' of grid G+1); with store_old, v' of grid G
+    // first receives u (FMG)
+    template <int G>
+    __device__ __forceinline__ void prolong(bool store_old) const {
+        constexpr int o = CG::off(G);
+        for (int c = threadIdx.x; c < CG::cells(G); c += blockDim.x) {
             int i, j, k;
-            cell(li, c, i, j, k);
+            ijk<G>(c, i, j, k);
             const int I = i >> 1, J = j >> 1, K = k >> 1;
             const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
-            auto del = [&](int a, int b, int cc) {
-                const int p = pidx(li + 1, a, b, cc);
-                return u[p] - uold[p];
-            };
             double v;
             if (D == 2)
-                v = 0.5 * del(I, J, 0) + 0.25 * del(I + sx, J, 0) + 0.25 * del(I, J + sy, 0);
+                v = 0.5 * delta<G + 1>(0, I, J, K, 0) + 0.25 * delta<G + 1>(0, I, J, K, sx) +
+                    0.25 * delta<G + 1>(1, I, J, K, sy);
             else
-                v = 0.25 * (((del(I, J, K) + del(I + sx, J, K)) + del(I, J + sy, K)) + del(I, J, K + sz));
-            const int p = pidx(li, i, j, k);
-            u[p] = u[p] + v;
+                v = 0.25 * (((delta<G + 1>(0, I, J, K, 0) + delta<G + 1>(0, I, J, K, sx)) +
+                             delta<G + 1>(1, I, J, K, sy)) +
+                            delta<G + 1>(2, I, J, K, sz));
+            if (store_old) uold[o + c] = u[o + c];
+            u[o + c] = u[o + c] + v;
         }
         __syncthreads();
     }
-    // FAS V-cycle over grids top..NL-1 (paper §3.2)
-    __device__ void vcycle(int top) const {
-        for (int li = top; li < CG::NL - 1; li++) {
-            gsrb(li, n_down);
-            fill(u, li);
-            residual(li);
-            restrict_to_coarser(u, li);
-            restrict_to_coarser(res, li);
-            fill(u, li + 1);
-            copy_uold(li + 1);
-            coarse_rhs(li + 1);
+    // FAS V-cycle from grid G (paper §3.2)
+    template <int G>
+    __device__ __forceinline__ void vcycle() const {
+        if constexpr (G == CG::NG - 1) {
+            gsrb<G>(n_base);
+        } else {
+            gsrb<G>(n_down);
+            resid_restrict<G>();
+            uold_crhs<G + 1>();
+            vcycle<G + 1>();
+            prolong<G>(false);
+            gsrb<G>(n_up);
         }
-        gsrb(CG::NL - 1, n_base);
-        for (int li = CG::NL - 2; li >= top; li--) {
-            fill(u, li + 1);
-            prolong(li);
-            gsrb(li, n_up);
+    }
+    // FMG from a zero guess on grids G .. NG-1, then the V-cycle from G:
+    // rho restricted down, per grid store v', correct from the coarser grid
+    template <int G>
+    __device__ __forceinline__ void fmg() const {
+        if constexpr (G < CG::NG - 1) {
+            restrict_rho<G>();
+            fmg<G + 1>();
+            prolong<G>(true);
+        } else {
+            for (int c = threadIdx.x; c < CG::cells(G); c += blockDim.x)
+                uold[CG::off(G) + c] = u[CG::off(G) + c];
+            __syncthreads();
         }
+        vcycle<G>();
     }
 };
 
@@ -1126,7 +1194,7 @@ template <int D, int N, typename T>
 __global__ __launch_bounds__(256) void k_coarse(CoarseArgs<T> a) {
     using CG = CoarseGeo<D, N>;
     using G = Geo<D, N>;
-    __shared__ double f_u[CG::PTOT], f_rho[CG::PTOT], f_uold[CG::PTOT], f_res[CG::PTOT], f_bc[CG::BTOT];
+    __shared__ double f_u[CG::TOT], f_rho[CG::TOT], f_uold[CG::TOT], f_res[CG::TOT], f_bc[CG::BTOT];
     CoarseState<D, N> st{f_u, f_rho, f_uold, f_res, f_bc, a.n_down, a.n_up, a.n_base};
     // one workgroup per tree; the roots are boxes 0 .. n_trees-1
     const int64_t root = blockIdx.x;
@@ -1138,71 +1206,82 @@ __global__ __launch_bounds__(256) void k_coarse(CoarseArgs<T> a) {
     T *gu = a.u + root * G::C;
     const T *grho = a.rho + root * G::C;
     T *guold = a.uold ? a.uold + root * G::C : nullptr;
-    // Dirichlet values: root rows, then means down to the 2^D grid
-    for (int g = threadIdx.x; g < 2 * D * G::F; g += blockDim.x) {
-        const int side = g / G::F, m = g % G::F;
-        f_bc[side * G::F + m] = a.homog ? 0.0 : a.bc[(size_t)ri->bcoff[side] * G::F + m];
+    // the root box (colour-split in global memory) and its Dirichlet rows;
+    // the coarser grids start at zero.  Compile-time strides (the kernel
+    // runs with 256 threads) keep all loads of a thread in flight together.
+    constexpr int NT = 256;
+    constexpr int NE = (G::C + NT - 1) / NT, NBC = (2 * D * G::F + NT - 1) / NT;
+    double lu[NE], lr[NE], lb[NBC];
+#pragma unroll
+    for (int q = 0; q < NE; q++) {
+        const int e = (int)threadIdx.x + q * NT;
+        lu[q] = (e < G::C && mode != COARSE_FMG) ? (double)gu[e] : 0.0;
+        lr[q] = e < G::C ? (double)grho[e] : 0.0;
     }
-    __syncthreads();
-    for (int li = 1; li < CG::NL; li++) {
-        const int n = CG::n(li), F = CG::fsz(li), Ff = CG::fsz(li - 1), nf = CG::n(li - 1);
-        for (int g = threadIdx.x; g < 2 * D * F; g += blockDim.x) {
-            const int side = g / F, m = g % F;
-            const int A = m % n, Cc = D == 3 ? m / n : 0;
-            double acc = 0.0;
-            for (int dc = 0; dc < (D == 3 ? 2 : 1); dc++)
-                for (int da = 0; da < 2; da++)
-                    acc += f_bc[CG::boff(li - 1) + side * Ff + (2 * A + da) + nf * (2 * Cc + dc)];
-            f_bc[CG::boff(li) + side * F + m] = acc * (D == 3 ? 0.25 : 0.5);
+#pragma unroll
+    for (int q = 0; q < NBC; q++) {
+        const int g = (int)threadIdx.x + q * NT;
+        lb[q] = (g < 2 * D * G::F && !a.homog) ? a.bc[(size_t)ri->bcoff[g / G::F] * G::F + g % G::F] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NE; q++) {
+        const int e = (int)threadIdx.x + q * NT;
+        if (e < G::C) {
+            int i, j, k;
+            cell_of<D, N>(e, i, j, k);
+            const int c = i + N * (j + N * k);
+            f_u[c] = lu[q];
+            f_rho[c] = mode == COARSE_V_FROM_2 ? 0.0 : lr[q];
+            f_res[c] = mode == COARSE_V_FROM_2 ? lr[q] : 0.0;
+            f_uold[c] = 0.0;
         }
-        __syncthreads();
     }
-    for (int p = threadIdx.x; p < CG::PTOT; p += blockDim.x) {
+    for (int p = G::C + (int)threadIdx.x; p < CG::TOT; p += NT) {
         f_u[p] = 0.0;
         f_rho[p] = 0.0;
         f_uold[p] = 0.0;
         f_res[p] = 0.0;
     }
-    __syncthreads();
-    // stage level 1 (the root box) from global memory (colour-split)
-    for (int e = threadIdx.x; e < G::C; e += blockDim.x) {
-        int i, j, k;
-        cell_of<D, N>(e, i, j, k);
-        const int p = st.pidx(0, i, j, k);
-        if (mode != COARSE_FMG) f_u[p] = (double)gu[e];
-        if (mode == COARSE_V_FROM_2) f_res[p] = (double)grho[e];
-        else f_rho[p] = (double)grho[e];
+#pragma unroll
+    for (int q = 0; q < NBC; q++) {
+        const int g = (int)threadIdx.x + q * NT;
+        if (g < 2 * D * G::F) f_bc[g] = lb[q];
     }
     __syncthreads();
-    if (mode == COARSE_V_FROM_2) {
-        // level 1 right after restriction from level 2: ghosts, copy v'_H,
-        // FAS right-hand side, then the V-cycle from level 1
-        st.fill(f_u, 0);
-        st.copy_uold(0);
-        st.coarse_rhs(0);
-        st.vcycle(0);
-    } else if (mode == COARSE_V_TOP1) {
-        st.vcycle(0);
-    } else {
-        // FMG from a zero guess: rho restricted down, then for l = lmin..1:
-        // store v', correct from the coarser grid, V-cycle from l
-        for (int li = 0; li < CG::NL - 1; li++) st.restrict_to_coarser(f_rho, li);
-        for (int li = CG::NL - 1; li >= 0; li--) {
-            st.fill(f_u, li);
-            st.copy_uold(li);
-            if (li < CG::NL - 1) {
-                st.fill(f_u, li + 1);
-                st.prolong(li);
-            }
-            st.vcycle(li);
+    // Dirichlet values of the coarser grids: means of the covered values
+    for (int li = 1; li < CG::NG; li++) {
+        const int n = N >> li, F = D == 3 ? n * n : n, Ff = D == 3 ? 4 * n * n : 2 * n, nf = 2 * n;
+        int bo = 0, bof = 0;
+        for (int q = 0; q < li; q++) {
+            bof = bo;
+            bo += 2 * D * (D == 3 ? (N >> q) * (N >> q) : (N >> q));
         }
+        for (int g = threadIdx.x; g < 2 * D * F; g += blockDim.x) {
+            const int side = g / F, m = g % F;
+            const int A = m % n, Cc = D == 3 ? m / n : 0;
+            double acc = 0.0;
+            for (int dc = 0; dc < (D == 3 ? 2 : 1); dc++)
+                for (int da = 0; da < 2; da++) acc += f_bc[bof + side * Ff + (2 * A + da) + nf * (2 * Cc + dc)];
+            f_bc[bo + side * F + m] = acc * (D == 3 ? 0.25 : 0.5);
+        }
+        __syncthreads();
+    }
+    if (mode == COARSE_V_FROM_2) {
+        // level 1 right after restriction from level 2: copy v', FAS
+        // right-hand side, then the V-cycle from level 1
+        st.template uold_crhs<0>();
+        st.template vcycle<0>();
+    } else if (mode == COARSE_V_TOP1) {
+        st.template vcycle<0>();
+    } else {
+        st.template fmg<0>();
     }
     for (int e = threadIdx.x; e < G::C; e += blockDim.x) {
         int i, j, k;
         cell_of<D, N>(e, i, j, k);
-        const int p = st.pidx(0, i, j, k);
-        gu[e] = (T)f_u[p];
-        if (guold && mode != COARSE_V_TOP1) guold[e] = (T)f_uold[p];
+        const int c = i + N * (j + N * k);
+        gu[e] = (T)f_u[c];
+        if (guold && mode != COARSE_V_TOP1) guold[e] = (T)f_uold[c];
     }
 }
 

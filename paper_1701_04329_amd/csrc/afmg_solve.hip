@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -264,29 +265,31 @@ struct Prof {
     bool on;
     int lmax;
     afmg_stats *stats;
-    std::vector<std::pair<int, int>> pending;  // (kernel class, event pair)
+    std::vector<std::array<int, 3>> pending;  // (kernel class, event pair, launches)
 
-    // Bracket a finest-level launch with an event pair when profiling.
+    // Bracket `count` consecutive finest-level launches of one kernel class
+    // with an event pair when profiling (s: the stream of the launches).
     template <class Fn>
-    void timed(int kind, int l, Fn fn) {
+    void timed(int kind, int l, Fn fn, hipStream_t s = nullptr, int count = 1) {
         const int pair = (int)pending.size();
-        if (!on || kind < 0 || l != lmax || pair >= PROF_PAIRS) {
+        if (!on || kind < 0 || l != lmax || pair >= PROF_PAIRS || count < 1) {
             fn();
             return;
         }
-        (void)hipEventRecord(t->events[(size_t)(2 * pair)], st);
+        hipStream_t es = s ? s : st;
+        (void)hipEventRecord(t->events[(size_t)(2 * pair)], es);
         fn();
-        (void)hipEventRecord(t->events[(size_t)(2 * pair + 1)], st);
-        pending.emplace_back(kind, pair);
+        (void)hipEventRecord(t->events[(size_t)(2 * pair + 1)], es);
+        pending.push_back({kind, pair, count});
     }
     // after a stream synchronisation: add the timed launches to the stats
     void collect() {
         for (const auto &p : pending) {
             float ms = 0.f;
-            if (hipEventElapsedTime(&ms, t->events[(size_t)(2 * p.second)],
-                                    t->events[(size_t)(2 * p.second + 1)]) == hipSuccess) {
-                stats->prof_ms[p.first] += ms;
-                stats->prof_n[p.first] += 1;
+            if (hipEventElapsedTime(&ms, t->events[(size_t)(2 * p[1])], t->events[(size_t)(2 * p[1] + 1)]) ==
+                hipSuccess) {
+                stats->prof_ms[p[0]] += ms;
+                stats->prof_n[p[0]] += p[2];
             }
         }
         pending.clear();
@@ -315,8 +318,9 @@ struct Cycler {
         a.ih2 = (T)(1.0 / (hh * hh));
         return a;
     }
-    void level(Op op, int l, int colour = 0) {
-        const int kind = op == Op::GSRB ? AFMG_PROF_GSRB
+    void level(Op op, int l, int colour = 0, bool time = true) {
+        const int kind = !time ? -1
+                         : op == Op::GSRB ? AFMG_PROF_GSRB
                          : op == Op::RESID_RESTRICT ? AFMG_PROF_RESID
                          : op == Op::PROLONG ? AFMG_PROF_PROLONG : -1;
         const int sk = op == Op::GSRB ? SK_GSRB
@@ -327,13 +331,19 @@ struct Cycler {
         if (sk >= 0) sh = t->shapes[sizeof(T) == 4 ? 1 : 0][sk][(size_t)l];
         LevelArgs<T> a = lev(l);
         a.no_remap = sh.no_remap;
-        prof.timed(kind, l, [&] { launch_level<D, BOX_N, T>(op, a, colour, sh.wg, st); });
+        prof.timed(kind, l, [&] { launch_level<D, BOX_N, T>(op, a, colour, sh.wg, st); }, st);
     }
+    // n sweeps; their 2n half sweeps are timed as one group
     void gsrb(int l, int n) {
-        for (int q = 0; q < n; q++) {
-            level(Op::GSRB, l, 0);
-            level(Op::GSRB, l, 1);
-        }
+        prof.timed(
+            AFMG_PROF_GSRB, l,
+            [&] {
+                for (int q = 0; q < n; q++) {
+                    level(Op::GSRB, l, 0, false);
+                    level(Op::GSRB, l, 1, false);
+                }
+            },
+            st, 2 * n);
     }
     // one workgroup per tree; a tree that is its root box alone takes the
     // top-level-1 path inside the kernel
@@ -412,10 +422,13 @@ struct Solver {
             a.ih2 = 1.0 / (hh * hh);
             const Shape sh = t->shapes[0][SK_FINAL][(size_t)l];
             a.no_remap = sh.no_remap;
-            prof.timed(AFMG_PROF_FINAL, l, [&] {
-                launch_final<D, BOX_N, double>(a, partial, t->forest ? -1 : t->part_off[(size_t)l], hD, rout, sh.wg,
-                                               s);
-            });
+            prof.timed(
+                AFMG_PROF_FINAL, l,
+                [&] {
+                    launch_final<D, BOX_N, double>(a, partial, t->forest ? -1 : t->part_off[(size_t)l], hD, rout,
+                                                   sh.wg, s);
+                },
+                s);
         }
         if (t->forest)
             launch_reduce_trees(partial, t->d_tree_leaf_ptr, t->d_tree_leaf_box, base.active, norm, h.n_trees, s);
@@ -446,6 +459,8 @@ struct Solver {
     }
     // Enqueue the launches of fn(stream) on st, through the recorded graph
     // when opts.graph is set (recorded on first use or when key changes).
+    // Profiled solves launch eagerly: event pairs recorded inside a graph do
+    // not bracket the kernel nodes' execution reliably.
     template <class Fn>
     int run(const std::vector<uintptr_t> &key, Fn fn) {
         if (!o.graph || o.profile) {
@@ -665,7 +680,7 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
     std::vector<Track> tr((size_t)n);
     const uintptr_t wsk = (uintptr_t)ws, uk = (uintptr_t)uw;
     const std::vector<uintptr_t> key{(uintptr_t)o.precision, wsk, uk, (uintptr_t)o.n_down, (uintptr_t)o.n_up,
-                                     (uintptr_t)o.n_base, (uintptr_t)t->tune_epoch};
+                                     (uintptr_t)o.n_base, (uintptr_t)t->tune_epoch, (uintptr_t)o.profile};
     if (!any) {
         // nothing to iterate
     } else if (!mixed) {

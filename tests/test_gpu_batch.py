@@ -167,6 +167,14 @@ def test_graph_replays_match_eager(precision):
         assert torch.equal(u, u_ref), rep
         assert s["cycles"] == s_ref["cycles"] >= 5
         assert np.array_equal(s["hist_max"], s_ref["hist_max"])
+    announce(f"graph requested while profiling {precision}")
+    u_e, s_e = A.solve(t, rho, bc, None, cycle="FMG", precision=precision, use_guess=False, profile=True)
+    u_g, s_g = A.solve(t, rho, bc, u, cycle="FMG", precision=precision, use_guess=False, graph=True,
+                       profile=True, workspace=work)
+    torch.cuda.synchronize()
+    assert torch.equal(u_e, u_g)
+    assert s_g["prof_n"] == s_e["prof_n"] and s_e["prof_n"][0] > 0
+    assert all(x > 0.0 for x, n in zip(s_g["prof_ms"], s_g["prof_n"]) if n)
     announce(f"graph replay batch {precision}")
     ws = bag(2)
     ub, sb = batched(ws, cycle="V", precision=precision, tol=1e-10)
