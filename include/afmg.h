@@ -120,6 +120,10 @@ typedef struct {
     int nbr[6];       /* per side (-x,+x,-y,+y,-z,+z): >= 0 same-level box,
                          -1 physical boundary, <= -2 refinement boundary with
                          the coarser leaf box -nbr-2 */
+    int children[8];  /* box ids of the 2^D children, octant bits x | y<<1 |
+                         z<<2; -1 for a leaf (entries >= 2^D unused) */
+    double x_lo[3];   /* lower corner of the box (x_lo[2] = 0 in 2D) */
+    double h;         /* cell size of the box's level, 1 / (N 2^(level-1)) */
 } afmg_box_desc;
 
 /* Fill opts with the paper's defaults (V(2,2), N_base = 4, tol 1e-10,
@@ -139,6 +143,35 @@ int afmg_tree_create(int dim, int box_n, int64_t n_leaves, const int32_t *level,
                      const int32_t *idx, afmg_tree **out);
 
 void afmg_tree_destroy(afmg_tree *tree);
+
+/*
+ * Refinement (paper §2.3): a new tree whose leaves are those of `tree` with
+ * the leaf boxes box_ids[0..n) replaced by their 2^D children.  balance:
+ *   0  a refined box whose side neighbour is a coarser leaf (not refined in
+ *      the same call) is an error (AFMG_ERR_TREE: 2:1 balance would break);
+ *   1  such coarser side neighbours are refined too, recursively (the
+ *      paper's rule);
+ *   2  the same for neighbours across sides, edges and corners.
+ * Leaf order of the new tree: the unrefined leaves in their input order, then
+ * the children of each refined box (refined boxes in box-id order, children in
+ * octant order x | y<<1 | z<<2).  `tree` is unchanged; *out is owned by the
+ * caller.  Host-only.  Errors: AFMG_ERR_ARG (ids that are not leaf boxes,
+ * refinement past the maximum level), AFMG_ERR_TREE, AFMG_ERR_OOM.
+ */
+int afmg_tree_refine(const afmg_tree *tree, const int32_t *box_ids, int64_t n, int balance, afmg_tree **out);
+
+/* Upload the tree's device tables (box records, children) to the current
+   device now rather than at its first solve.  Trees are immutable, so this
+   is the only preparation a tree needs.  Errors: AFMG_ERR_ARG (another
+   device than the first use), AFMG_ERR_OOM, AFMG_ERR_HIP. */
+int afmg_tree_finalize(afmg_tree *tree, void *stream);
+
+/* Box lists per level (paper §2.1): all boxes, parents (refined boxes) or
+   leaves of `level` (1 .. lmax), in box-id order, which is Morton order
+   within a level.  *n receives the count; ids (host array of at least that
+   many entries, or NULL to query the count first) receives the ids. */
+typedef enum { AFMG_LIST_ALL = 0, AFMG_LIST_PARENT = 1, AFMG_LIST_LEAF = 2 } afmg_list_kind;
+int afmg_tree_level_list(const afmg_tree *tree, int level, int kind, int32_t *ids, int64_t *n);
 
 int afmg_tree_info(const afmg_tree *tree, afmg_tree_desc *out);
 

@@ -102,6 +102,9 @@ class BoxDesc(C.Structure):
         ("parent", C.c_int),
         ("leaf", C.c_int),
         ("nbr", C.c_int * 6),
+        ("children", C.c_int * 8),
+        ("x_lo", C.c_double * 3),
+        ("h", C.c_double),
     ]
 
 
@@ -112,8 +115,9 @@ EXPORTS = [
     "afmg_batch_create", "afmg_batch_destroy", "afmg_batch_info", "afmg_batch_workspace_bytes",
     "afmg_batch_solve", "afmg_autotune_workspace_bytes", "afmg_tree_autotune", "afmg_tree_shape",
     "afmg_tree_set_shape", "afmg_batch_autotune_workspace_bytes", "afmg_batch_autotune", "afmg_batch_shape",
-    "afmg_batch_set_shape",
+    "afmg_batch_set_shape", "afmg_tree_refine", "afmg_tree_finalize", "afmg_tree_level_list",
 ]
+LISTS = {"all": 0, "parent": 1, "leaf": 2}
 KINDS = {"gsrb": 0, "resid": 1, "coarse_rhs": 2, "prolong": 3, "final": 4}
 OPS = {"L": 0, "LT": 1}
 
@@ -164,6 +168,9 @@ def lib():
             getattr(L, f"afmg_{pre}_shape").argtypes = [vp, C.c_int, C.c_int, C.c_int, ip, ip]
             getattr(L, f"afmg_{pre}_set_shape").argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
         L.afmg_autotune_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+        L.afmg_tree_refine.argtypes = [vp, i32p, i64, C.c_int, C.POINTER(vp)]
+        L.afmg_tree_finalize.argtypes = [vp, vp]
+        L.afmg_tree_level_list.argtypes = [vp, C.c_int, C.c_int, i32p, C.POINTER(C.c_int64)]
         L.afmg_batch_autotune_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
         _lib = L
     return _lib
@@ -239,15 +246,18 @@ class _Shapes:
 class Tree(_Shapes):
     """A quadtree/octree of 8^D-cell boxes built from its leaves."""
 
-    def __init__(self, dim, level, idx, box_n=8):
+    def __init__(self, dim, level=None, idx=None, box_n=8, _handle=None):
         L = lib()
-        level = np.ascontiguousarray(level, dtype=np.int32)
-        idx = np.ascontiguousarray(idx, dtype=np.int32).reshape(-1, 3)
-        if len(level) != len(idx):
-            raise ValueError("level and idx lengths differ")
-        h = C.c_void_p()
-        _check(L.afmg_tree_create(dim, box_n, len(level), level.ctypes.data_as(C.POINTER(C.c_int32)),
-                                  idx.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(h)))
+        if _handle is not None:
+            h = _handle
+        else:
+            level = np.ascontiguousarray(level, dtype=np.int32)
+            idx = np.ascontiguousarray(idx, dtype=np.int32).reshape(-1, 3)
+            if len(level) != len(idx):
+                raise ValueError("level and idx lengths differ")
+            h = C.c_void_p()
+            _check(L.afmg_tree_create(dim, box_n, len(level), level.ctypes.data_as(C.POINTER(C.c_int32)),
+                                      idx.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(h)))
         self._h = h
         d = TreeDesc()
         _check(L.afmg_tree_info(h, C.byref(d)))
@@ -275,7 +285,34 @@ class Tree(_Shapes):
     def box(self, b):
         d = BoxDesc()
         _check(lib().afmg_tree_box(self._h, b, C.byref(d)))
-        return dict(level=d.level, idx=tuple(d.idx), parent=d.parent, leaf=bool(d.leaf), nbr=tuple(d.nbr))
+        return dict(level=d.level, idx=tuple(d.idx), parent=d.parent, leaf=bool(d.leaf), nbr=tuple(d.nbr),
+                    children=tuple(d.children[: 2 ** self.dim]), x_lo=tuple(d.x_lo), h=d.h)
+
+    def refine(self, box_ids, balance=1):
+        """A new tree with the given leaf boxes refined (afmg_tree_refine)."""
+        ids = np.ascontiguousarray(box_ids, dtype=np.int32)
+        h = C.c_void_p()
+        _check(lib().afmg_tree_refine(self._h, ids.ctypes.data_as(C.POINTER(C.c_int32)), len(ids), balance,
+                                      C.byref(h)))
+        return Tree(self.dim, _handle=h)
+
+    def finalize(self):
+        _check(lib().afmg_tree_finalize(self._h, None))
+
+    def level_list(self, level, kind="all"):
+        n = C.c_int64()
+        L = lib()
+        _check(L.afmg_tree_level_list(self._h, level, LISTS[kind], None, C.byref(n)))
+        out = np.zeros(max(1, n.value), np.int32)
+        _check(L.afmg_tree_level_list(self._h, level, LISTS[kind], out.ctypes.data_as(C.POINTER(C.c_int32)),
+                                      C.byref(n)))
+        return out[: n.value]
+
+    def leaves(self):
+        """(level, idx) of the leaves in the tree's input order."""
+        boxes = [self.box(int(b)) for b in self.leaf_boxes]
+        return (np.array([b["level"] for b in boxes], np.int32),
+                np.array([b["idx"] for b in boxes], np.int32).reshape(-1, 3))
 
     def adjoint_workspace_bytes(self, opts=None):
         n = C.c_size_t()

@@ -56,6 +56,15 @@ struct HostTree {
 int build_tree(int dim, int N, int n_trees, const int64_t *tree_off, const int32_t *level, const int32_t *idx,
                HostTree &t, std::string &msg);
 
+// Leaves of the tree after refining the leaf boxes `ids` (paper §2.3): the
+// unrefined leaves in their input order, then the 2^D children of each
+// refined box (refined boxes in box order, children in octant order).
+// balance 0: a coarser side neighbour of a refined box is an error; 1: such
+// neighbours are refined too, recursively; 2: the same across sides, edges
+// and corners.
+int refine_leaves(const HostTree &t, const int32_t *ids, int64_t n, int balance, std::vector<int32_t> &level,
+                  std::vector<int32_t> &idx, std::string &msg);
+
 void set_error(const std::string &msg);
 
 }  // namespace afmg

@@ -1196,6 +1196,49 @@ int afmg_tree_box(const afmg_tree *t, int64_t b, afmg_box_desc *out) {
     out->parent = bi.parent;
     out->leaf = bi.flags & FLAG_LEAF;
     for (int s = 0; s < 6; s++) out->nbr[s] = s < 2 * t->h.dim ? bi.nbr[s] : -1;
+    for (int c = 0; c < 8; c++) out->children[c] = c < (1 << t->h.dim) ? t->h.child[(size_t)b * 8 + c] : -1;
+    const double h = level_h(bi.level);
+    out->h = h;
+    out->x_lo[0] = (out->idx[0] - 1) * BOX_N * h;
+    out->x_lo[1] = (out->idx[1] - 1) * BOX_N * h;
+    out->x_lo[2] = t->h.dim == 3 ? (out->idx[2] - 1) * BOX_N * h : 0.0;
+    return AFMG_OK;
+}
+
+int afmg_tree_refine(const afmg_tree *t, const int32_t *ids, int64_t n, int balance, afmg_tree **out) {
+    if (!t || !out) return fail(AFMG_ERR_ARG, "null argument");
+    *out = nullptr;
+    if (t->forest) return fail(AFMG_ERR_ARG, "not a tree");
+    try {
+        std::vector<int32_t> level, idx;
+        std::string msg;
+        const int rc = refine_leaves(t->h, ids, n, balance, level, idx, msg);
+        if (rc != AFMG_OK) return fail(rc, msg);
+        return afmg_tree_create(t->h.dim, t->h.N, (int64_t)level.size(), level.data(), idx.data(), out);
+    } catch (const std::bad_alloc &) {
+        return fail(AFMG_ERR_OOM, "host allocation failed");
+    }
+}
+
+int afmg_tree_finalize(afmg_tree *t, void *stream) {
+    (void)stream;
+    if (!t) return fail(AFMG_ERR_ARG, "null argument");
+    return bind_device(t);
+}
+
+int afmg_tree_level_list(const afmg_tree *t, int level, int kind, int32_t *ids, int64_t *n) {
+    if (!t || !n) return fail(AFMG_ERR_ARG, "null argument");
+    if (level < 1 || level > t->h.lmax || kind < AFMG_LIST_ALL || kind > AFMG_LIST_LEAF)
+        return fail(AFMG_ERR_ARG, "level or kind out of range");
+    int64_t c = 0;
+    for (int64_t b = t->h.lvl_off[(size_t)level]; b < t->h.lvl_off[(size_t)level + 1]; b++) {
+        const bool leaf = t->h.info[(size_t)b].flags & FLAG_LEAF;
+        if (kind == AFMG_LIST_ALL || (kind == AFMG_LIST_LEAF) == leaf) {
+            if (ids) ids[c] = (int32_t)b;
+            c++;
+        }
+    }
+    *n = c;
     return AFMG_OK;
 }
 

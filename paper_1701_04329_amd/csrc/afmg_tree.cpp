@@ -238,4 +238,84 @@ int build_tree(int dim, int N, int n_trees, const int64_t *tree_off, const int32
     return AFMG_OK;
 }
 
+int refine_leaves(const HostTree &t, const int32_t *ids, int64_t n, int balance, std::vector<int32_t> &level,
+                  std::vector<int32_t> &idx, std::string &msg) {
+    if (n < 0 || (n > 0 && !ids)) { msg = "bad leaf id list"; return AFMG_ERR_ARG; }
+    if (balance < 0 || balance > 2) { msg = "balance must be 0, 1 or 2"; return AFMG_ERR_ARG; }
+    if (t.n_trees != 1) { msg = "refinement applies to single trees"; return AFMG_ERR_ARG; }
+    const int dim = t.dim;
+    const int max_level = dim == 3 ? 17 : 20;
+    std::unordered_map<Key, int64_t, KeyHash> leaf;  // leaf key -> box id
+    leaf.reserve((size_t)t.n_leaves * 2);
+    auto key_of = [&](int64_t m) { return Key{0, t.info[(size_t)m].level, t.ix[(size_t)m], t.iy[(size_t)m], t.iz[(size_t)m]}; };
+    for (int64_t m = 0; m < t.n_boxes; m++)
+        if (t.info[(size_t)m].flags & FLAG_LEAF) leaf.emplace(key_of(m), m);
+    std::vector<char> refine((size_t)t.n_boxes, 0);
+    std::vector<int64_t> work;
+    for (int64_t q = 0; q < n; q++) {
+        const int64_t m = ids[q];
+        if (m < 0 || m >= t.n_boxes || !(t.info[(size_t)m].flags & FLAG_LEAF)) {
+            msg = "refinement id is not a leaf box";
+            return AFMG_ERR_ARG;
+        }
+        if (t.info[(size_t)m].level >= max_level) { msg = "refinement beyond the maximum level"; return AFMG_ERR_ARG; }
+        if (!refine[(size_t)m]) {
+            refine[(size_t)m] = 1;
+            work.push_back(m);
+        }
+    }
+    // the leaf covering position (l, i, j, k), or -1 outside the domain
+    auto covering = [&](int l, int i, int j, int k) -> int64_t {
+        const int n1 = 1 << (l - 1);
+        if (i < 1 || i > n1 || j < 1 || j > n1 || k < 1 || k > (dim == 3 ? n1 : 1)) return -1;
+        while (l >= 1) {
+            auto it = leaf.find(Key{0, l, i, j, k});
+            if (it != leaf.end()) return it->second;
+            l--;
+            i = (i + 1) / 2;
+            j = (j + 1) / 2;
+            k = dim == 3 ? (k + 1) / 2 : 1;
+        }
+        return -1;
+    };
+    while (!work.empty()) {
+        const int64_t m = work.back();
+        work.pop_back();
+        const Key kk = key_of(m);
+        for (int dz = (dim == 3 ? -1 : 0); dz <= (dim == 3 ? 1 : 0); dz++)
+            for (int dy = -1; dy <= 1; dy++)
+                for (int dx = -1; dx <= 1; dx++) {
+                    const int nz = (dx != 0) + (dy != 0) + (dz != 0);
+                    if (nz == 0 || (balance < 2 && nz != 1)) continue;
+                    const int64_t v = covering(kk.l, kk.i + dx, kk.j + dy, kk.k + dz);
+                    if (v < 0 || t.info[(size_t)v].level >= kk.l || refine[(size_t)v]) continue;
+                    if (balance == 0) {
+                        msg = "refinement breaks 2:1 balance with a coarser neighbour";
+                        return AFMG_ERR_TREE;
+                    }
+                    refine[(size_t)v] = 1;
+                    work.push_back(v);
+                }
+    }
+    level.clear();
+    idx.clear();
+    for (int64_t q = 0; q < t.n_leaves; q++) {
+        const int64_t m = t.leaf_box[(size_t)q];
+        if (refine[(size_t)m]) continue;
+        const Key kk = key_of(m);
+        level.push_back(kk.l);
+        idx.insert(idx.end(), {kk.i, kk.j, kk.k});
+    }
+    for (int64_t m = 0; m < t.n_boxes; m++) {
+        if (!refine[(size_t)m]) continue;
+        const Key kk = key_of(m);
+        for (int c = 0; c < (1 << dim); c++) {
+            level.push_back(kk.l + 1);
+            idx.insert(idx.end(), {2 * kk.i - 1 + (c & 1), 2 * kk.j - 1 + ((c >> 1) & 1),
+                                   dim == 3 ? 2 * kk.k - 1 + ((c >> 2) & 1) : 1});
+        }
+    }
+    return AFMG_OK;
+}
+
 }  // namespace afmg

@@ -217,3 +217,95 @@ def test_shapes_default_set_and_validation():
     n = C.c_size_t()
     assert L.afmg_autotune_workspace_bytes(t.handle, C.byref(n)) == 0 and n.value > t.workspace_bytes()
     assert L.afmg_tree_autotune(t.handle, None, None, 0) == A.AFMG_ERR_ARG
+
+
+def _leafset(t):
+    lev, idx = t.leaves()
+    return {(int(l),) + tuple(int(x) for x in i) for l, i in zip(lev, idx)}
+
+
+def _side_balanced(dim, leaves):
+    """2:1 across sides, checked by brute force on the leaf set."""
+    def covering(l, i, j, k):
+        n1 = 2 ** (l - 1)
+        if not (1 <= i <= n1 and 1 <= j <= n1 and 1 <= k <= (n1 if dim == 3 else 1)):
+            return None
+        while l >= 1:
+            if (l, i, j, k) in leaves:
+                return (l, i, j, k)
+            l, i, j, k = l - 1, (i + 1) // 2, (j + 1) // 2, (k + 1) // 2 if dim == 3 else 1
+        return None
+    for (l, i, j, k) in leaves:
+        for d in range(dim):
+            for s in (-1, 1):
+                q = [i, j, k]
+                q[d] += s
+                c = covering(l, *q)
+                if c is not None and c[0] < l - 1:
+                    return False
+    return True
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_refine_balance_rules(dim):
+    t = A.Tree(dim, *W.uniform_leaves(dim, 2))
+    corner = t.level_list(2, "leaf")[0]
+    # balance 0: refining one level-2 leaf is fine (its neighbours are level 2)
+    t1 = t.refine([corner], balance=0)
+    assert t1.n_leaves == t.n_leaves - 1 + 2 ** dim
+    # the children of the refined box come last, in octant order
+    lev, idx = t1.leaves()
+    assert list(lev[-2 ** dim:]) == [3] * 2 ** dim
+    b0 = t.box(int(corner))
+    assert tuple(idx[-2 ** dim]) [:dim] == tuple(2 * x - 1 for x in b0["idx"][:dim])
+    # refining a child at the far corner of that box needs its level-2
+    # neighbours refined: error with balance 0, propagation with 1 and 2
+    far = [b for b in t1.level_list(3, "leaf") if t1.box(int(b))["idx"][:dim] == (2,) * dim][0]
+    with pytest.raises(A.AfmgError) as e:
+        t1.refine([far], balance=0)
+    assert e.value.code == A.AFMG_ERR_TREE
+    t2 = t1.refine([far], balance=1)
+    t3 = t1.refine([far], balance=2)
+    assert _side_balanced(dim, _leafset(t2)) and _side_balanced(dim, _leafset(t3))
+    # side propagation refines the D side neighbours; diagonal propagation
+    # also the edge (and corner) neighbours
+    assert t2.n_leaves == t1.n_leaves - 1 + 2 ** dim + dim * (2 ** dim - 1)
+    assert t3.n_leaves == t1.n_leaves - 1 + 2 ** dim + (2 ** dim - 1) * (2 ** dim - 1)
+    # the result equals the workload generator's rule (diagonals included)
+    ls = W._LeafSet(dim)
+    ls.leaves = set(_leafset(t1))
+    for key in [(2, 2, 1, 1 if dim == 2 else 1), (2, 1, 2, 1), (2, 2, 2, 1)] + (
+            [(2, 1, 1, 2), (2, 2, 1, 2), (2, 1, 2, 2), (2, 2, 2, 2)] if dim == 3 else []):
+        if key in ls.leaves:
+            ls.refine(key)
+    ls.refine(t1.box(int(far))["level"] and (3,) + t1.box(int(far))["idx"])
+    assert set(ls.leaves) == _leafset(t3)
+    for bad in ([t1.n_boxes], [0], [-1]):
+        with pytest.raises(A.AfmgError) as e:
+            t1.refine(bad)
+        assert e.value.code == A.AFMG_ERR_ARG
+
+
+def test_level_lists_and_box_geometry():
+    t = A.Tree(3, *W.ball_leaves(3, 8, 4, (0.3, 0.62, 0.41), 0.0, 1))
+    total = 0
+    for l in range(1, t.lmax + 1):
+        al, pa, le = t.level_list(l, "all"), t.level_list(l, "parent"), t.level_list(l, "leaf")
+        assert sorted(np.concatenate([pa, le])) == list(al)
+        assert list(al) == sorted(al)
+        total += len(al)
+        for b in pa:
+            d = t.box(int(b))
+            assert not d["leaf"] and all(c >= 0 for c in d["children"])
+            for c in d["children"]:
+                assert t.box(int(c))["parent"] == b
+        for b in le:
+            d = t.box(int(b))
+            assert d["leaf"] and all(c == -1 for c in d["children"])
+            h = 1.0 / (8 * 2 ** (d["level"] - 1))
+            assert d["h"] == h
+            assert d["x_lo"] == tuple((x - 1) * 8 * h for x in d["idx"])
+    assert total == t.n_boxes
+    assert sum(len(t.level_list(l, "leaf")) for l in range(1, t.lmax + 1)) == t.n_leaves
+    with pytest.raises(A.AfmgError):
+        t.level_list(t.lmax + 1)
