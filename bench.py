@@ -316,6 +316,32 @@ def adjoint_bench(args, A, torch, dev, stream):
     }
 
 
+def paper_ex_bench(args, A, torch, dev, stream):
+    """The paper's scaling problem (§4.2): lap(phi) = 1 on the unit cube,
+    phi = 0 on the boundary, uniform 512^3 grid of 8^3-cell boxes, one FMG
+    cycle.  Time per FMG cycle in ns per unknown, beside the paper's figure
+    for 8^3 boxes on a 16-core CPU (context, another machine)."""
+    from paper_1701_04329_amd import workloads as W
+
+    w = W.uniform_const_rhs(3, 8, 512)
+    tree = A.Tree(w.dim, w.level, w.idx)
+    rho = tree.leaf_to_boxes(torch.tensor(w.rho, device=dev))
+    del w
+    u = torch.empty_like(rho)
+    work = torch.empty(tree.workspace_bytes(A.make_opts(precision="mixed")), dtype=torch.uint8, device=dev)
+    if not args.no_autotune:
+        tree.autotune(dev, stream)
+    out = {"workload": "ex4_3d_uniform_512", "unknowns": int(tree.n_unknowns), "boxes": int(tree.n_boxes),
+           "paper_ns_per_unknown_8cube_16_cores": 22.0}
+    for precision in ("fp64", "mixed"):
+        ms, (_, st) = timed_loop(args, torch, lambda: A.solve(
+            tree, rho, None, u, cycle="FMG", max_cycles=0, precision=precision, workspace=work, stream=stream,
+            use_guess=False, check=False))
+        out[precision] = {"ms_per_fmg_cycle": ms, "ns_per_unknown": ms * 1e6 / tree.n_unknowns,
+                          "residual_ratio_after_fmg": st["r_max"] / st["r0_max"]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -330,6 +356,8 @@ def main():
                     help="batch workload: skip the one-tree-at-a-time comparison pass")
     ap.add_argument("--no-adaptive", action="store_true", help="skip the adaptive 3D workload (FP64 vs mixed)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint workload")
+    ap.add_argument("--no-paper-ex", action="store_true",
+                    help="skip the paper's scaling problem (512^3, one FMG cycle)")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batch workload and print its record (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -426,7 +454,9 @@ def main():
     bytes_per_launch = 12.0 * n_fine
     avg_ms = prof_ms[0] / max(prof_n[0], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = committed_traffic(f"k_gsrb_{w.name}")
+    # the counters were taken on the default shape of the finest level
+    fine_shape = tree.shape("fp64", "gsrb", tree.lmax)
+    traffic = committed_traffic(f"k_gsrb_{w.name}") if fine_shape == (256, 0) else None
     roofline = {
         "bound": "hbm",
         "achieved": round(achieved, 1),
@@ -434,7 +464,7 @@ def main():
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": traffic,
-        "kernel": "k_gsrb<3,8,double> (finest level, one half sweep)",
+        "kernel": "k_gsrb<3,8,double,256> (finest level, one half sweep)",
         "algorithmic_bytes_per_launch": bytes_per_launch,
         "avg_launch_ms": round(avg_ms, 5),
         "launches_timed": int(prof_n[0]),
@@ -451,7 +481,7 @@ def main():
         "outer_iterations": int(np.median(cycles_m)),
         "final_residual_ratio": stm["r_max"] / stm["r0_max"],
         "rel_l2_vs_gpu_fp64": float(np.linalg.norm(umx - u64) / np.linalg.norm(u64)),
-        "dominant_kernel": "k_gsrb<3,8,float> (finest level, one half sweep)",
+        "dominant_kernel": "k_gsrb<3,8,float,256> (finest level, one half sweep)",
         "dominant_achieved_GBs": round(6.0 * n_fine / (avg_m * 1e-3) / 1e9, 1) if prof_nm[0] else None,
         "dominant_avg_launch_ms": round(avg_m, 5),
     }
@@ -500,6 +530,8 @@ def main():
         out["adaptive"] = adaptive_bench(args, A, torch, dev, stream)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_bench(args, A, torch, dev, stream)
+    if not args.no_paper_ex:
+        out["paper_ex"] = paper_ex_bench(args, A, torch, dev, stream)
     if not args.no_cpu_baseline:
         uo, out["cpu_baseline"] = cpu_baseline(w, solve_kw)
         nrm = np.linalg.norm(uo)
