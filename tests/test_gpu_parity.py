@@ -63,11 +63,14 @@ def check_pair(w, **kw):
             ratio = so["r_max"] / (tol * so["r0_max"])
             assert abs(sg["cycles"] - so["cycles"]) == 1 and 0.99 < ratio < 1.01, (sg, so)
     np.testing.assert_allclose(sg["r0_max"], so["r0_max"], rtol=1e-12)
-    # final residuals sit at the rounding floor (about eps * 2D/h^2 * |u|), so
-    # compare them on the scale of the stop test: they must agree to 1% of
-    # tol * r0 for the two stop decisions to agree
+    # final residuals sit at the rounding floor (about eps * 2D/h^2 * |u| on
+    # the finest level), so compare them on the scale of the stop test (they
+    # must agree to 1% of tol * r0 for the two stop decisions to agree) or of
+    # that floor, whichever is larger
     tol = kw.get("tol", 1e-10)
-    np.testing.assert_allclose(sg["r_max"], so["r_max"], rtol=1e-6, atol=1e-2 * tol * so["r0_max"])
+    h_min = 1.0 / (w.N * 2.0 ** (w.lmax - 1))
+    floor = 16 * np.finfo(float).eps * 2 * w.dim / h_min ** 2 * np.abs(uo).max()
+    np.testing.assert_allclose(sg["r_max"], so["r_max"], rtol=1e-6, atol=max(1e-2 * tol * so["r0_max"], floor))
     return ug, sg, uo, so
 
 
@@ -139,3 +142,62 @@ def test_full_size_uniform_256():
     w = W.config2()
     ug, sg, uo, so = check_pair(w, cycle="FMG", tol=1e-10)
     assert sg["status"] == 0 and sg["cycles"] <= 15
+
+
+@pytest.mark.parametrize("dim,lmax", [(2, 14), (3, 10)])
+def test_deep_point_refinement_matches_oracle(dim, lmax):
+    """A grid refined around one point down to a deep level (cells of
+    1/65536 in 2D, 1/4096 in 3D), refinement boundaries at every level:
+    the solution at a fixed cycle count against the oracle."""
+    c = (0.3, 0.62, 0.41)
+    w = W.random_fields(dim, 8, *W.ball_leaves(dim, 8, lmax, c, 0.0, 1), 61 + dim)
+    assert w.lmax == lmax
+    check_pair(w, cycle="FMG", fixed_cycles=3)
+    check_pair(w, cycle="V", tol=1e-10)
+
+
+def test_maximum_size_uniform_512_residual():
+    """The largest uniform grid the benchmark runs (512^3 = 134,217,728
+    unknowns, lap(phi) = 1, phi = 0 on the boundary), solved to a 1e-8
+    residual reduction (the FP64 rounding floor of this residual is about
+    5e-11: |sum of neighbours - 6 u| ~ 0.3 carries ~1e-16 of rounding and is
+    divided by h^2 = 3.8e-6).  The oracle does not run at this size, so the
+    check is a property that holds at any size: the residual of the returned
+    solution, recomputed here from the 7-point stencil with the Dirichlet
+    ghost -u1 (plain numpy on the whole grid), is below 1e-8 of the initial
+    one (max |rho| = 1), up to the rounding floor."""
+    from paper_1701_04329_amd import afmg as A
+    w = W.uniform_const_rhs(3, 8, 512)
+    announce(f"maximum size {w.name} unknowns={w.n_unknowns}")
+    t = A.Tree(3, w.level, w.idx)
+    dev = torch.device("cuda", 0)
+    rho = t.leaf_to_boxes(torch.tensor(w.rho, device=dev))
+    u, st = A.solve(t, rho, None, cycle="FMG", tol=1e-8)
+    assert st["status"] == 0 and st["r_max"] <= 1e-8 * st["r0_max"]
+    assert st["r0_max"] == 1.0
+    ul = t.boxes_to_leaf(u)
+    del u, rho
+    # leaves in box order -> one 512^3 array (z, y, x)
+    lev, idx = w.level, w.idx
+    g = np.zeros((512, 512, 512))
+    ulh = ul.cpu().numpy().reshape(-1, 8, 8, 8)
+    del ul
+    i0, j0, k0 = (idx[:, 0] - 1) * 8, (idx[:, 1] - 1) * 8, (idx[:, 2] - 1) * 8
+    for q in range(len(lev)):
+        g[k0[q]:k0[q] + 8, j0[q]:j0[q] + 8, i0[q]:i0[q] + 8] = ulh[q]
+    del ulh
+    p = np.pad(g, 1)
+    for ax in range(3):  # Dirichlet ghosts 2b - u1 with b = 0
+        sl_lo = [slice(None)] * 3
+        sl_in = [slice(None)] * 3
+        sl_lo[ax], sl_in[ax] = 0, 1
+        p[tuple(sl_lo)] = -p[tuple(sl_in)]
+        sl_lo[ax], sl_in[ax] = -1, -2
+        p[tuple(sl_lo)] = -p[tuple(sl_in)]
+    h = 1.0 / 512
+    lap = (p[:-2, 1:-1, 1:-1] + p[2:, 1:-1, 1:-1] + p[1:-1, :-2, 1:-1] + p[1:-1, 2:, 1:-1]
+           + p[1:-1, 1:-1, :-2] + p[1:-1, 1:-1, 2:] - 6.0 * g) / (h * h)
+    r = np.abs(1.0 - lap).max()
+    print(f"512^3: cycles={st['cycles']} library r_max={st['r_max']:.3e} numpy r_max={r:.3e}", flush=True)
+    assert r <= 1e-8 + 2e-10
+    assert abs(r - st["r_max"]) <= 2e-10
