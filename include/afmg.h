@@ -340,6 +340,43 @@ int afmg_batch_autotune(afmg_batch *batch, void *stream, void *workspace, size_t
 int afmg_batch_shape(const afmg_batch *batch, int precision, int kind, int level, int *wg, int *no_remap);
 int afmg_batch_set_shape(afmg_batch *batch, int precision, int kind, int level, int wg, int no_remap);
 
+/*
+ * One step of the cycle on caller arrays, for checking the kernels one at a
+ * time against a reference implementation (a solve does not need it).
+ *   AFMG_STEP_HALF_SWEEP      one red (colour 0) or black (1) half sweep of
+ *                             every box of `level` >= 1, side ghosts formed
+ *                             from the current u (§3.1, §2.4, §3.3)
+ *   AFMG_STEP_RESID_RESTRICT  boxes of `level` >= 2: r = rho - L u; each
+ *                             parent's octant receives mean(u) in u and
+ *                             mean(r) in rho (eq. residual, §2.5)
+ *   AFMG_STEP_COARSE_RHS      boxes of `level` >= 2: uold <- u; on parents
+ *                             rho <- rho + L u (eq. coarse-rhs; rho holds the
+ *                             restricted residual on input)
+ *   AFMG_STEP_PROLONG         boxes of `level` >= 2: u += P211(u - uold of the
+ *                             parent) (eq. coarse-corr, §2.5); uold of the
+ *                             parents holds v' as copied by COARSE_RHS
+ *   AFMG_STEP_COARSE          the root box right after a restriction from
+ *                             level 2 (rho of the root = restricted residual):
+ *                             its FAS right-hand side, copy v', and the
+ *                             V-cycle from level 1 through the coarse grids
+ *                             below it; `level` is ignored; needs lmax >= 2
+ * u, rho, uold: device [n_boxes][N^D] in the layout of afmg_solve (uold
+ * full-size too); every box is read and only the step's outputs change.  bc:
+ * the leaf Dirichlet rows or NULL (zero); homog = 1 uses zero values.  opts:
+ * n_down / n_up / n_base of AFMG_STEP_COARSE (NULL: defaults).  workspace:
+ * afmg_workspace_bytes for FP64.  Synchronises the stream.
+ */
+typedef enum {
+    AFMG_STEP_HALF_SWEEP = 0,
+    AFMG_STEP_RESID_RESTRICT = 1,
+    AFMG_STEP_COARSE_RHS = 2,
+    AFMG_STEP_PROLONG = 3,
+    AFMG_STEP_COARSE = 4
+} afmg_step_op;
+int afmg_step(afmg_tree *tree, void *stream, int op, int level, int colour, int homog, double *u,
+              double *rho, double *uold, const double *bc, void *workspace, size_t workspace_bytes,
+              const afmg_opts *opts);
+
 /* Message for the last failing call on this thread. */
 const char *afmg_last_error(void);
 

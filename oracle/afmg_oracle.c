@@ -798,6 +798,36 @@ void or_copy_uold(void *p, int l) {
     otree *t = (otree *)p;
     for (int m = 0; m < lvl_count(t, l); m++) copy_box_padded(t, lvl_box(t, l, m), t->u, t->uold);
 }
+/* the residual of level l restricted, with u, into the parents (the first
+   half of the V-cycle's step at level l) */
+void or_resid_restrict_level(void *p, int l, int homog) {
+    otree *t = (otree *)p;
+    fill_gc(t, l, t->u, homog);
+    for (int m = 0; m < lvl_count(t, l); m++) {
+        int b = lvl_box(t, l, m);
+        box_residual(t, b, t->res);
+        restrict_box(t, b, t->u, t->u);
+        restrict_box(t, b, t->res, t->res);
+    }
+}
+/* on level l: u_old <- u, and rho <- res + L u on parents (the second half
+   of the V-cycle's step at level l+1) */
+void or_coarse_rhs_level(void *p, int l, int homog) {
+    otree *t = (otree *)p;
+    fill_gc(t, l, t->u, homog);
+    double H = level_h(t, l), iH2 = 1.0 / (H * H), twoD = 2.0 * t->dim;
+    for (int m = 0; m < lvl_count(t, l); m++) {
+        int b = lvl_box(t, l, m);
+        copy_box_padded(t, b, t->u, t->uold);
+        if (t->leaf[b]) continue;
+        FOR_CELLS(t, b, i, j, k) {
+            int64_t c = PX(t, b, i, j, k);
+            t->rho[c] = t->res[c] + (nb_sum(t, t->u, b, i, j, k) - twoD * t->u[c]) * iH2;
+        }
+    }
+}
+/* the V-cycle from level top */
+void or_vcycle_from(void *p, int top, const or_opts *o) { vcycle((otree *)p, top, o); }
 void or_prolong_level(void *p, int l) {
     otree *t = (otree *)p;
     for (int m = 0; m < lvl_count(t, l); m++) prolong_correct_box(t, lvl_box(t, l, m));

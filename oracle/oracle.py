@@ -86,6 +86,9 @@ def lib():
         L.or_restrict_level.argtypes = [vp, C.c_int, C.c_int]
         L.or_copy_uold.argtypes = [vp, C.c_int]
         L.or_prolong_level.argtypes = [vp, C.c_int]
+        L.or_resid_restrict_level.argtypes = [vp, C.c_int, C.c_int]
+        L.or_coarse_rhs_level.argtypes = [vp, C.c_int, C.c_int]
+        L.or_vcycle_from.argtypes = [vp, C.c_int, C.POINTER(Opts)]
         L.or_get_box.argtypes = [vp, C.c_int, C.c_int, dp]
         L.or_set_box.argtypes = [vp, C.c_int, C.c_int, dp]
         L.or_get_leaf_field.argtypes = [vp, C.c_int, dp]
@@ -220,6 +223,16 @@ class Tree:
 
     def prolong_level(self, level):
         lib().or_prolong_level(self.h, level)
+
+    def resid_restrict_level(self, level, homog=False):
+        lib().or_resid_restrict_level(self.h, level, 1 if homog else 0)
+
+    def coarse_rhs_level(self, level, homog=False):
+        lib().or_coarse_rhs_level(self.h, level, 1 if homog else 0)
+
+    def vcycle_from(self, top, n_down=2, n_up=2, n_base=4, homog=False):
+        o = Opts(0, n_down, n_up, n_base, 0.0, 1, 1, 1, 1 if homog else 0)
+        lib().or_vcycle_from(self.h, top, C.byref(o))
 
     def box_padded(self, b, field="u"):
         n = self.box_info(b)["n"]

@@ -115,8 +115,9 @@ EXPORTS = [
     "afmg_batch_create", "afmg_batch_destroy", "afmg_batch_info", "afmg_batch_workspace_bytes",
     "afmg_batch_solve", "afmg_autotune_workspace_bytes", "afmg_tree_autotune", "afmg_tree_shape",
     "afmg_tree_set_shape", "afmg_batch_autotune_workspace_bytes", "afmg_batch_autotune", "afmg_batch_shape",
-    "afmg_batch_set_shape", "afmg_tree_refine", "afmg_tree_finalize", "afmg_tree_level_list",
+    "afmg_batch_set_shape", "afmg_tree_refine", "afmg_tree_finalize", "afmg_tree_level_list", "afmg_step",
 ]
+STEPS = {"half_sweep": 0, "resid_restrict": 1, "coarse_rhs": 2, "prolong": 3, "coarse": 4}
 LISTS = {"all": 0, "parent": 1, "leaf": 2}
 KINDS = {"gsrb": 0, "resid": 1, "coarse_rhs": 2, "prolong": 3, "final": 4}
 OPS = {"L": 0, "LT": 1}
@@ -171,6 +172,8 @@ def lib():
         L.afmg_tree_refine.argtypes = [vp, i32p, i64, C.c_int, C.POINTER(vp)]
         L.afmg_tree_finalize.argtypes = [vp, vp]
         L.afmg_tree_level_list.argtypes = [vp, C.c_int, C.c_int, i32p, C.POINTER(C.c_int64)]
+        L.afmg_step.argtypes = [vp, vp, C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, vp, C.c_size_t,
+                                C.POINTER(Opts)]
         L.afmg_batch_autotune_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
         _lib = L
     return _lib
@@ -504,6 +507,26 @@ def solve_batch(batch: Batch, rho, bc=None, u=None, *, cycle="V", tol=1e-10, max
         d["rc"] = rc
         out.append(d)
     return u, out
+
+
+def step(tree: Tree, op, level, u, rho, uold, bc=None, colour=0, homog=False, n_down=2, n_up=2, n_base=4,
+         workspace=None, stream=None):
+    """One step of the cycle (afmg_step) in place on u, rho, uold: float64
+    device tensors [n_boxes, N^D] in box order."""
+    import torch
+    for t_, name in ((u, "u"), (rho, "rho"), (uold, "uold")):
+        _check_field(tree, t_, name)
+    opts = make_opts("V", n_down, n_up, n_base)
+    nbytes = tree.workspace_bytes(opts)
+    if workspace is None or workspace.numel() * workspace.element_size() < nbytes:
+        workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=u.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(u.device)
+    with torch.cuda.device(u.device):
+        _check(lib().afmg_step(tree.handle, C.c_void_p(stream.cuda_stream), STEPS[op], level, colour,
+                               1 if homog else 0, _ptr(u), _ptr(rho), _ptr(uold),
+                               _ptr(bc.contiguous()) if bc is not None else None, _ptr(workspace), nbytes,
+                               C.byref(opts)))
 
 
 def _check_field(tree, t, name):

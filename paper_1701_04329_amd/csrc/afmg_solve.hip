@@ -957,6 +957,51 @@ int adjoint(afmg_tree *t, hipStream_t st, const double *ubar, double *rho_bar, d
 }
 
 // ---------------------------------------------------------------------------
+// one step of the cycle on caller arrays (kernel-by-kernel checks)
+// ---------------------------------------------------------------------------
+template <int D>
+int step(afmg_tree *t, hipStream_t st, int op, int level, int colour, int homog, double *u, double *rho,
+         double *uold, const double *bc, char *ws, const afmg_opts &o) {
+    const HostTree &h = t->h;
+    const WsLayout L = ws_layout(t, AFMG_FP64);
+    const int64_t F = cells_per_face(D);
+    double *bc_w = (double *)(ws + L.bc);
+    if (h.n_bfaces_leaf > 0) {
+        if (bc) {
+            hipError_t e = hipMemcpyAsync(bc_w, bc, (size_t)(h.n_bfaces_leaf * F) * sizeof(double),
+                                          hipMemcpyDeviceToDevice, st);
+            if (e != hipSuccess) return hip_fail(e, "copy of Dirichlet values");
+        } else {
+            launch_fill<double>(bc_w, h.n_bfaces_leaf * F, 0.0, st);
+        }
+    }
+    for (int l = h.lmax; l >= 2; l--)
+        launch_bc_derive<D, BOX_N>(t->d_info, h.lvl_off[(size_t)l], h.level_count(l), bc_w, st);
+    for (double *f : {u, rho, uold}) launch_permute<D, BOX_N, double>(t->d_info, f, 0, h.n_boxes, 1, 0, st);
+    LevelArgs<double> a{t->d_info, u, rho, uold, bc_w, h.lvl_off[(size_t)level], (int)h.level_count(level),
+                        homog, 0.0, 0.0, nullptr, 0};
+    const double hh = level_h(level);
+    a.h2 = hh * hh;
+    a.ih2 = 1.0 / (hh * hh);
+    switch (op) {
+    case AFMG_STEP_HALF_SWEEP: launch_level<D, BOX_N, double>(Op::GSRB, a, colour, 256, st); break;
+    case AFMG_STEP_RESID_RESTRICT: launch_level<D, BOX_N, double>(Op::RESID_RESTRICT, a, 0, 256, st); break;
+    case AFMG_STEP_COARSE_RHS: launch_level<D, BOX_N, double>(Op::COARSE_RHS, a, 0, 256, st); break;
+    case AFMG_STEP_PROLONG: launch_level<D, BOX_N, double>(Op::PROLONG, a, 0, 256, st); break;
+    default: {
+        CoarseArgs<double> c{t->d_info, u, rho, uold, homog ? nullptr : bc_w, COARSE_V_FROM_2, homog,
+                             o.n_down, o.n_up, o.n_base, nullptr};
+        launch_coarse<D, BOX_N, double>(c, 1, st);
+    }
+    }
+    for (double *f : {u, rho, uold}) launch_permute<D, BOX_N, double>(t->d_info, f, 0, h.n_boxes, 0, 0, st);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "step");
+    return AFMG_OK;
+}
+
+// ---------------------------------------------------------------------------
 // autotuning of the launch shapes
 // ---------------------------------------------------------------------------
 // Every candidate shape of one kernel class on one level is timed on the
@@ -1477,6 +1522,36 @@ int afmg_batch_shape(const afmg_batch *b, int precision, int kind, int level, in
 int afmg_batch_set_shape(afmg_batch *b, int precision, int kind, int level, int wg, int no_remap) {
     if (!b) return fail(AFMG_ERR_ARG, "null argument");
     return set_shape(&b->f, precision, kind, level, wg, no_remap);
+}
+
+int afmg_step(afmg_tree *t, void *stream, int op, int level, int colour, int homog, double *u, double *rho,
+              double *uold, const double *bc, void *workspace, size_t workspace_bytes, const afmg_opts *opts) {
+    if (!t || !u || !rho || !uold || !workspace) return fail(AFMG_ERR_ARG, "null argument");
+    if (t->forest) return fail(AFMG_ERR_ARG, "not a tree");
+    afmg_opts o;
+    afmg_default_opts(&o);
+    if (opts) {
+        const int rc = check_opts(opts);
+        if (rc != AFMG_OK) return rc;
+        o = *opts;
+    }
+    if (op < AFMG_STEP_HALF_SWEEP || op > AFMG_STEP_COARSE) return fail(AFMG_ERR_ARG, "bad step");
+    const int lo = op == AFMG_STEP_HALF_SWEEP ? 1 : 2;
+    if (op == AFMG_STEP_COARSE) {
+        if (t->h.lmax < 2) return fail(AFMG_ERR_ARG, "the coarse step needs a refined root");
+    } else if (level < lo || level > t->h.lmax) {
+        return fail(AFMG_ERR_ARG, "level out of range for this step");
+    }
+    if (colour != 0 && colour != 1) return fail(AFMG_ERR_ARG, "colour must be 0 or 1");
+    if (!aligned(u, 8) || !aligned(rho, 8) || !aligned(uold, 8) || (bc && !aligned(bc, 8)) ||
+        !aligned(workspace, 256))
+        return fail(AFMG_ERR_ARG, "misaligned array");
+    if (workspace_bytes < ws_layout(t, AFMG_FP64).total) return fail(AFMG_ERR_ARG, "workspace too small");
+    int rc = bind_device(t);
+    if (rc != AFMG_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (t->h.dim == 3) return step<3>(t, st, op, level, colour, homog != 0, u, rho, uold, bc, (char *)workspace, o);
+    return step<2>(t, st, op, level, colour, homog != 0, u, rho, uold, bc, (char *)workspace, o);
 }
 
 }  // extern "C"
