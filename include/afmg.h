@@ -80,6 +80,13 @@ typedef struct {
     int graph;        /* 1: record the repeated cycle (V-cycle, refinement
                          update, residual) once as a HIP graph and replay it;
                          ignored while profiling.  Results are identical. */
+    int check_every;  /* read the residual norms (one stream synchronisation)
+                         and apply the stop test every check_every cycles
+                         (default 1; 0 is taken as 1).  The composite
+                         residual of the FP64 path is then only computed at
+                         those cycles; a solve may run up to check_every - 1
+                         cycles past convergence; stats history entries of
+                         the unchecked cycles are NaN. */
 } afmg_opts;
 
 /* kernel classes timed when opts.profile is set (finest level only) */

@@ -251,6 +251,7 @@ int check_opts(const afmg_opts *o) {
         o->fixed_cycles > 100000)
         return fail(AFMG_ERR_ARG, "tol / max_cycles / fixed_cycles out of range");
     if (o->precision != AFMG_FP64 && o->precision != AFMG_MIXED) return fail(AFMG_ERR_ARG, "bad precision");
+    if (o->check_every < 0 || o->check_every > 1000) return fail(AFMG_ERR_ARG, "check_every out of range");
     return AFMG_OK;
 }
 
@@ -538,8 +539,12 @@ struct Track {
     double prev = 0.0;
 };
 
-// Outer loop of the solve over the trees of t: `step(k)` runs cycle k on the
-// trees whose mask entry is set and leaves their norms in t->h_norm.
+// Outer loop of the solve over the trees of t: `step(k, m)` runs cycles
+// k .. k+m-1 on the trees whose mask entry is set and leaves their norms
+// after the last one in t->h_norm.  The norms are read, and the stop test
+// applied, every check_every cycles (and after the last allowed cycle); the
+// history of the cycles in between holds NaN.  Running trees have run the
+// same number of cycles, so one m serves them all.
 template <int D, class Step>
 int iterate_trees(Solver<D> &s, afmg_stats *S, std::vector<Track> &tr, Step step) {
     afmg_tree *t = s.t;
@@ -547,13 +552,14 @@ int iterate_trees(Solver<D> &s, afmg_stats *S, std::vector<Track> &tr, Step step
     const int n = t->h.n_trees;
     const bool fixed = o.fixed_cycles > 0;
     const int nmax = fixed ? o.fixed_cycles : o.max_cycles;
+    const int every = std::max(1, o.check_every);
     for (int i = 0; i < n; i++) {
         tr[(size_t)i].prev = S[i].r_max;
         if (S[i].status != AFMG_OK) tr[(size_t)i].done = true;
         tr[(size_t)i].conv = !fixed && S[i].r_max <= o.tol * S[i].r0_max;
         if (tr[(size_t)i].conv) tr[(size_t)i].done = true;
     }
-    for (int k = 0;; k++) {
+    for (int k = 0;;) {
         bool any = false;
         for (int i = 0; i < n; i++) {
             Track &q = tr[(size_t)i];
@@ -562,13 +568,17 @@ int iterate_trees(Solver<D> &s, afmg_stats *S, std::vector<Track> &tr, Step step
             any |= !q.done;
         }
         if (!any) break;
+        const int m = std::min(every, nmax - k);
         int rc = s.upload_mask();
-        if (rc == AFMG_OK) rc = step(k);
+        if (rc == AFMG_OK) rc = step(k, m);
         if (rc != AFMG_OK) return rc;
+        k += m;
         for (int i = 0; i < n; i++) {
             Track &q = tr[(size_t)i];
             if (q.done) continue;
             afmg_stats &x = S[i];
+            for (int c = 1; c < m; c++, x.cycles++)
+                if (x.cycles < AFMG_HIST) x.hist_max[x.cycles] = x.hist_l2[x.cycles] = NAN;
             x.r_max = t->h_norm[2 * i];
             x.r_l2 = t->h_norm[2 * i + 1];
             if (x.cycles < AFMG_HIST) {
@@ -692,11 +702,13 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
             if ((rc = s.finalize(nullptr)) != AFMG_OK) return rc;
             take_norms(t, S, false);
         }
-        rc = iterate_trees(s, S, tr, [&](int) {
-            const int q = s.run(key, [&](hipStream_t cs) {
+        rc = iterate_trees(s, S, tr, [&](int, int m) {
+            std::vector<uintptr_t> km = key;
+            km.push_back((uintptr_t)m);
+            const int q = s.run(km, [&](hipStream_t cs) {
                 Cycler<D, double> c2 = cy;
                 c2.st = cs;
-                c2.vcycle(h.lmax);
+                for (int c = 0; c < m; c++) c2.vcycle(h.lmax);
                 s.finalize_launch(nullptr, cs);
             });
             return q != AFMG_OK ? q : s.read_norms();
@@ -720,13 +732,16 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
             launch_ir_update<D, BOX_N>(t->d_info, uw, e32, h.n_boxes, t->d_active, cs);
             s.finalize_launch(rho32, cs);
         };
-        rc = iterate_trees(s, S, tr, [&](int k) {
-            int q;
+        rc = iterate_trees(s, S, tr, [&](int k, int m) {
+            int q = AFMG_OK;
             if (k == 0 && o.cycle == AFMG_CYCLE_FMG_V) {
-                refine(st, true);
-                q = AFMG_OK;
+                for (int c = 0; c < m; c++) refine(st, c == 0);
             } else {
-                q = s.run(key, [&](hipStream_t cs) { refine(cs, false); });
+                std::vector<uintptr_t> km = key;
+                km.push_back((uintptr_t)m);
+                q = s.run(km, [&](hipStream_t cs) {
+                    for (int c = 0; c < m; c++) refine(cs, false);
+                });
             }
             return q != AFMG_OK ? q : s.read_norms();
         });
@@ -1169,6 +1184,7 @@ void afmg_default_opts(afmg_opts *o) {
     o->precision = AFMG_FP64;
     o->profile = 0;
     o->graph = 0;
+    o->check_every = 1;
 }
 
 int afmg_tree_create(int dim, int box_n, int64_t n_leaves, const int32_t *level, const int32_t *idx,

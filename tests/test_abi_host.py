@@ -309,3 +309,12 @@ def test_level_lists_and_box_geometry():
     assert sum(len(t.level_list(l, "leaf")) for l in range(1, t.lmax + 1)) == t.n_leaves
     with pytest.raises(A.AfmgError):
         t.level_list(t.lmax + 1)
+
+
+def test_check_every_validation():
+    t = A.Tree(2, *W.uniform_leaves(2, 2))
+    assert t.workspace_bytes(A.make_opts(check_every=5)) > 0
+    with pytest.raises(A.AfmgError) as e:
+        t.workspace_bytes(A.make_opts(check_every=-1))
+    assert e.value.code == A.AFMG_ERR_ARG
+    assert A.make_opts().check_every == 1

@@ -206,3 +206,30 @@ def test_full_batch_workload_sampled():
         err = np.linalg.norm(ub[order[0]] - uo) / np.linalg.norm(uo)
         print(f"dim={dim} smallest tree {w.name}: mixed batch vs FP64 oracle {err:.2e}", flush=True)
         assert err <= 1e-8
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_check_every(precision):
+    """Reading the norms every k cycles runs the same cycles: at equal cycle
+    counts the solution is bitwise that of checking every cycle, the checked
+    history entries are equal and the others NaN, and a tolerance stop lands
+    on the first check at or after the cycle where every-cycle checking
+    stops.  Batches follow the same rule per tree."""
+    w = W.adaptive_small(3, 8, 5, 1e-3, 6, n_src=2, sigma_range=(0.04, 0.08))
+    announce(f"check_every {precision}")
+    u1, s1 = single(w, cycle="FMG", precision=precision, fixed_cycles=6)
+    u3, s3 = single(w, cycle="FMG", precision=precision, fixed_cycles=6, check_every=3)
+    assert np.array_equal(u1, u3) and s3["cycles"] == 6
+    assert np.isnan(s3["hist_max"][[0, 1, 3, 4]]).all()
+    assert np.array_equal(s3["hist_max"][[2, 5]], s1["hist_max"][[2, 5]])
+    ut, st = single(w, cycle="FMG", precision=precision, tol=1e-10)
+    u2, s2 = single(w, cycle="FMG", precision=precision, tol=1e-10, check_every=4)
+    expect = -(-st["cycles"] // 4) * 4
+    assert s2["status"] == 0 and s2["cycles"] == expect, (st["cycles"], s2["cycles"])
+    uf, sf = single(w, cycle="FMG", precision=precision, fixed_cycles=expect)
+    assert np.array_equal(u2, uf)
+    ws = bag(3)
+    ub, sb = batched(ws, cycle="V", precision=precision, tol=1e-10, check_every=2, graph=True)
+    for x, ux, sx in zip(ws, ub, sb):
+        us, ss = single(x, cycle="V", precision=precision, tol=1e-10, check_every=2)
+        assert np.array_equal(ux, us) and sx["cycles"] == ss["cycles"], x.name
