@@ -109,25 +109,37 @@ def batch_bench(args, A, torch, dev, stream):
         groups.append(dict(dim=dim, sub=sub, trees=trees, b=b, rho=rho, u=u, work={}))
     n_unk = sum(g["b"].n_unknowns for g in groups)
 
-    def step(precision, graph=True):
-        sts = []
-        for g in groups:
-            key = precision
-            if key not in g["work"]:
-                nb = g["b"].workspace_bytes(A.make_opts(precision=precision))
-                g["work"][key] = torch.empty(nb, dtype=torch.uint8, device=dev)
-            _, st = A.solve_batch(g["b"], g["rho"], None, g["u"], cycle="FMG", tol=1e-10, precision=precision,
-                                  workspace=g["work"][key], stream=stream, use_guess=False, graph=graph)
-            sts.append(st)
+    import concurrent.futures as cf
+    for g in groups:
+        g["stream"] = torch.cuda.Stream(device=dev)  # default priority
+    pool = cf.ThreadPoolExecutor(max_workers=max(1, len(groups)))
+
+    def solve_group(g, precision, st):
+        if precision not in g["work"]:
+            nb = g["b"].workspace_bytes(A.make_opts(precision=precision))
+            g["work"][precision] = torch.empty(nb, dtype=torch.uint8, device=dev)
+        _, sts = A.solve_batch(g["b"], g["rho"], None, g["u"], cycle="FMG", tol=1e-10, precision=precision,
+                               workspace=g["work"][precision], stream=st, use_guess=False, graph=True)
         return sts
 
-    def timed(precision):
+    def step(precision, schedule="concurrent", only=None):
+        """one step: every tree solved.  sequential: the batches one after the
+        other on one stream; concurrent: each batch on its own stream, driven
+        by its own host thread (the library calls release the GIL)"""
+        gs = [g for g in groups if only is None or g["dim"] == only]
+        if schedule == "sequential":
+            return [solve_group(g, precision, stream) for g in gs]
+        torch.cuda.synchronize()
+        futs = [pool.submit(solve_group, g, precision, g["stream"]) for g in gs]
+        return [f.result() for f in futs]
+
+    def timed(precision, schedule="concurrent", only=None):
         for _ in range(args.warmup):
-            step(precision)
+            step(precision, schedule, only)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            sts = step(precision)
+            sts = step(precision, schedule, only)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / args.steps, sts
 
@@ -142,21 +154,18 @@ def batch_bench(args, A, torch, dev, stream):
     res = {}
     sols = {}
     for precision in ("fp64", "mixed"):
-        for _ in range(args.warmup):
-            step(precision)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            sts = step(precision)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        ms, sts = timed(precision)
         cyc = [s["cycles"] for st in sts for s in st]
         res[precision] = {"value": n_unk / (ms * 1e-3), "unit": "unknowns/s", "ms_per_step": ms,
                           "cycles_min": int(min(cyc)), "cycles_max": int(max(cyc)),
                           "cycles_median": float(np.median(cyc)),
-                          "all_converged": bool(all(s["status"] == 0 for st in sts for s in st))}
+                          "all_converged": bool(all(s["status"] == 0 for st in sts for s in st)),
+                          "sequential_ms_per_step": timed(precision, "sequential")[0]}
+        for g in groups:
+            res[precision][f"{g['dim']}d_alone_ms_per_step"] = timed(precision, "sequential", g["dim"])[0]
         sols[precision] = [[t.boxes_to_leaf(x).cpu().numpy() for t, x in zip(g["trees"], g["b"].split(g["u"]))]
                            for g in groups]
+    pool.shutdown()
     # per-tree error of the mixed solution against the FP64 one
     errs = [float(np.linalg.norm(m - f) / np.linalg.norm(f))
             for gm, gf in zip(sols["mixed"], sols["fp64"]) for m, f in zip(gm, gf)]
@@ -195,8 +204,9 @@ def batch_bench(args, A, torch, dev, stream):
         "untuned": untuned,
         "oracle_rel_l2_smallest_trees": oracle,
         "generation_s": round(gen_s, 1),
-        "note": "one step = every tree solved (FMG, then V(2,2) until its own residual dropped by 1e-10), "
-                "one batch launch sequence per dimension, cycles replayed from recorded HIP graphs",
+        "note": "one step = every tree solved (FMG, then V(2,2) until its own residual dropped by 1e-10); "
+                "one batch per dimension, each on its own stream driven by its own host thread, cycles "
+                "replayed from recorded HIP graphs; sequential = the two batches one after the other",
     }
 
 
