@@ -154,8 +154,9 @@ __device__ __forceinline__ void face_cell(int m, int x[3]) {
 
 // raw operand of the ghost on side S next to face cell m of box bi.  The
 // address is selected without branches (one load per ghost, so the loads of a
-// thread stay in flight together); a homogeneous Dirichlet side loads a
-// harmless in-range value and returns 0.
+// thread stay in flight together), and the loaded value is not used here: a
+// homogeneous Dirichlet side loads a harmless in-range value, replaced by 0
+// when the ghost is finished (after the barrier, so no load waits before it).
 template <int D, int N, int S, typename T>
 __device__ __forceinline__ T ghost_raw(const BoxInfo &bi, int m, const T *__restrict__ u,
                                        const T *__restrict__ bc, int homog, int &v) {
@@ -174,19 +175,18 @@ __device__ __forceinline__ T ghost_raw(const BoxInfo &bi, int m, const T *__rest
     const size_t iu = (size_t)box * G::C + cpos<D, N>(q[0], q[1], q[2]);
     const bool from_bc = dir && !homog;
     const size_t ib = from_bc ? (size_t)bi.bcoff[S] * G::F + m : 0;
-    const T val = from_bc ? bc[ib] : u[iu];
-    return (dir && homog) ? T(0) : val;
+    return from_bc ? bc[ib] : u[iu];
 }
 
 // finish the ghost from its raw operand; s is the padded box in LDS
 template <int D, int N, int S, typename T>
-__device__ __forceinline__ T ghost_finish(const T *s, int m, T raw, int v) {
+__device__ __forceinline__ T ghost_finish(const T *s, int m, T raw, int v, int homog) {
     using SD = SideOf<S>;
     if (v >= 0) return raw;
     int x[3];
     face_cell<D, N, S>(m, x);
     const T u1 = s[padi<D, N>(x[0], x[1], x[2])];
-    if (v == -1) return T(2) * raw - u1;
+    if (v == -1) return T(2) * (homog ? T(0) : raw) - u1;
     int y[3] = {x[0], x[1], x[2]};
     y[SD::d] = SD::hi ? N - 2 : 1;
     const T u2 = s[padi<D, N>(y[0], y[1], y[2])];
@@ -229,11 +229,13 @@ struct Stager {
     using G = Geo<D, N>;
     T raw[6];
     int v[6];
+    int hg;
 
     __device__ void begin(T *s, const BoxInfo &bi, const T *__restrict__ ub,
                           const T *__restrict__ u, const T *__restrict__ bc, int homog, int t, bool ghosts) {
         int j, k;
         row_of<D, N>(t, j, k);
+        hg = homog;
         T rowv[2][G::HN];
 #pragma unroll
         for (int c = 0; c < 2; c++)
@@ -257,13 +259,13 @@ struct Stager {
         }
     }
     __device__ void end(T *s, int t) {
-        s[ghost_slot<D, N, 0>(t)] = ghost_finish<D, N, 0, T>(s, t, raw[0], v[0]);
-        s[ghost_slot<D, N, 1>(t)] = ghost_finish<D, N, 1, T>(s, t, raw[1], v[1]);
-        s[ghost_slot<D, N, 2>(t)] = ghost_finish<D, N, 2, T>(s, t, raw[2], v[2]);
-        s[ghost_slot<D, N, 3>(t)] = ghost_finish<D, N, 3, T>(s, t, raw[3], v[3]);
+        s[ghost_slot<D, N, 0>(t)] = ghost_finish<D, N, 0, T>(s, t, raw[0], v[0], hg);
+        s[ghost_slot<D, N, 1>(t)] = ghost_finish<D, N, 1, T>(s, t, raw[1], v[1], hg);
+        s[ghost_slot<D, N, 2>(t)] = ghost_finish<D, N, 2, T>(s, t, raw[2], v[2], hg);
+        s[ghost_slot<D, N, 3>(t)] = ghost_finish<D, N, 3, T>(s, t, raw[3], v[3], hg);
         if (D == 3) {
-            s[ghost_slot<D, N, 4>(t)] = ghost_finish<D, N, 4, T>(s, t, raw[4], v[4]);
-            s[ghost_slot<D, N, 5>(t)] = ghost_finish<D, N, 5, T>(s, t, raw[5], v[5]);
+            s[ghost_slot<D, N, 4>(t)] = ghost_finish<D, N, 4, T>(s, t, raw[4], v[4], hg);
+            s[ghost_slot<D, N, 5>(t)] = ghost_finish<D, N, 5, T>(s, t, raw[5], v[5], hg);
         }
     }
 };
@@ -301,10 +303,10 @@ template <int D, int N>
 constexpr int oblock() { return Geo<D, N>::HALF + (D == 3 ? 0 : 1); }
 
 template <int D, int N, int S, typename T>
-__device__ __forceinline__ T gs_finish(const T *s, T raw, int v, T own, int i, int j, int k) {
+__device__ __forceinline__ T gs_finish(const T *s, T raw, int v, T own, int homog, int i, int j, int k) {
     using SD = SideOf<S>;
     if (v >= 0) return raw;
-    if (v == -1) return T(2) * raw - own;
+    if (v == -1) return T(2) * (homog ? T(0) : raw) - own;
     int y[3] = {i, j, k};
     y[SD::d] += SD::hi ? -1 : 1;
     int p1[3] = {i, j, k};
@@ -353,21 +355,38 @@ __global__ __launch_bounds__(W) void k_gsrb(LevelArgs<T> a, int colour) {
         if (p == 0) gx = ghost_raw<D, N, 0, T>(bi, r, a.u, a.bc, a.homog, vx);
         else gx = ghost_raw<D, N, 1, T>(bi, r, a.u, a.bc, a.homog, vx);
         bool need_own = vx < 0;
+        // y / z ghosts.  Across a same-level side they are the other-colour
+        // cells of one row of the neighbour (row j' = N-1-j, resp. k' =
+        // N-1-k), HN contiguous values like the thread's own row.
         if (j == 0 || j == N - 1) {
+            vy = bi.nbr[j == 0 ? 2 : 3];
+            if (vy >= 0) {
+                const T *nr = a.u + (size_t)vy * G::C + oth0 + ((D == 3 ? N * k : 0) + (N - 1 - j) - r) * HN;
 #pragma unroll
-            for (int m = 0; m < HN; m++) {
-                const int fm = (2 * m + p) + (D == 3 ? N * k : 0);
-                if (j == 0) gy[m] = ghost_raw<D, N, 2, T>(bi, fm, a.u, a.bc, a.homog, vy);
-                else gy[m] = ghost_raw<D, N, 3, T>(bi, fm, a.u, a.bc, a.homog, vy);
+                for (int m = 0; m < HN; m++) gy[m] = nr[m];
+            } else {
+#pragma unroll
+                for (int m = 0; m < HN; m++) {
+                    const int fm = (2 * m + p) + (D == 3 ? N * k : 0);
+                    if (j == 0) gy[m] = ghost_raw<D, N, 2, T>(bi, fm, a.u, a.bc, a.homog, vy);
+                    else gy[m] = ghost_raw<D, N, 3, T>(bi, fm, a.u, a.bc, a.homog, vy);
+                }
             }
             need_own |= vy < 0;
         }
         if (D == 3 && (k == 0 || k == N - 1)) {
+            vz = bi.nbr[k == 0 ? 4 : 5];
+            if (vz >= 0) {
+                const T *nr = a.u + (size_t)vz * G::C + oth0 + ((N - 1 - k) * N + j - r) * HN;
 #pragma unroll
-            for (int m = 0; m < HN; m++) {
-                const int fm = (2 * m + p) + N * j;
-                if (k == 0) gz[m] = ghost_raw<D, N, 4, T>(bi, fm, a.u, a.bc, a.homog, vz);
-                else gz[m] = ghost_raw<D, N, 5, T>(bi, fm, a.u, a.bc, a.homog, vz);
+                for (int m = 0; m < HN; m++) gz[m] = nr[m];
+            } else {
+#pragma unroll
+                for (int m = 0; m < HN; m++) {
+                    const int fm = (2 * m + p) + N * j;
+                    if (k == 0) gz[m] = ghost_raw<D, N, 4, T>(bi, fm, a.u, a.bc, a.homog, vz);
+                    else gz[m] = ghost_raw<D, N, 5, T>(bi, fm, a.u, a.bc, a.homog, vz);
+                }
             }
             need_own |= vz < 0;
         }
@@ -383,14 +402,14 @@ __global__ __launch_bounds__(W) void k_gsrb(LevelArgs<T> a, int colour) {
 #pragma unroll
     for (int m = 0; m < HN; m++) {
         const int i = 2 * m + p;
-        const T xm = i > 0 ? s[oslot<D, N>(i - 1, j, k)] : gs_finish<D, N, 0, T>(s, gx, vx, ow[m], i, j, k);
-        const T xp = i < N - 1 ? s[oslot<D, N>(i + 1, j, k)] : gs_finish<D, N, 1, T>(s, gx, vx, ow[m], i, j, k);
-        const T ym = j > 0 ? s[oslot<D, N>(i, j - 1, k)] : gs_finish<D, N, 2, T>(s, gy[m], vy, ow[m], i, j, k);
-        const T yp = j < N - 1 ? s[oslot<D, N>(i, j + 1, k)] : gs_finish<D, N, 3, T>(s, gy[m], vy, ow[m], i, j, k);
+        const T xm = i > 0 ? s[oslot<D, N>(i - 1, j, k)] : gs_finish<D, N, 0, T>(s, gx, vx, ow[m], a.homog, i, j, k);
+        const T xp = i < N - 1 ? s[oslot<D, N>(i + 1, j, k)] : gs_finish<D, N, 1, T>(s, gx, vx, ow[m], a.homog, i, j, k);
+        const T ym = j > 0 ? s[oslot<D, N>(i, j - 1, k)] : gs_finish<D, N, 2, T>(s, gy[m], vy, ow[m], a.homog, i, j, k);
+        const T yp = j < N - 1 ? s[oslot<D, N>(i, j + 1, k)] : gs_finish<D, N, 3, T>(s, gy[m], vy, ow[m], a.homog, i, j, k);
         T sum = (xm + xp) + (ym + yp);
         if (D == 3) {
-            const T zm = k > 0 ? s[oslot<D, N>(i, j, k - 1)] : gs_finish<D, N, 4, T>(s, gz[m], vz, ow[m], i, j, k);
-            const T zp = k < N - 1 ? s[oslot<D, N>(i, j, k + 1)] : gs_finish<D, N, 5, T>(s, gz[m], vz, ow[m], i, j, k);
+            const T zm = k > 0 ? s[oslot<D, N>(i, j, k - 1)] : gs_finish<D, N, 4, T>(s, gz[m], vz, ow[m], a.homog, i, j, k);
+            const T zp = k < N - 1 ? s[oslot<D, N>(i, j, k + 1)] : gs_finish<D, N, 5, T>(s, gz[m], vz, ow[m], a.homog, i, j, k);
             sum = sum + (zm + zp);
         }
         ub[own0 + m] = (sum - a.h2 * rr[m]) / T(2 * D);
@@ -483,11 +502,19 @@ __global__ __launch_bounds__(W) void k_coarse_rhs(LevelArgs<T> a) {
     const bool parent = !(bi.flags & FLAG_LEAF);
     Stager<D, N, T> st;
     if (sl.valid) {
-        for (int e = sl.t; e < G::C; e += G::TPB) a.uold[bo + e] = a.u[bo + e];
-        st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, parent);
+        if (parent) st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, true);
+        else st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, false);
     }
     __syncthreads();
-    if (sl.valid && parent) st.end(s, sl.t);
+    if (sl.valid) {
+        // the copy v' from the staged interior
+        for (int e = sl.t; e < G::C; e += G::TPB) {
+            int i, j, k;
+            cell_of<D, N>(e, i, j, k);
+            a.uold[bo + e] = s[padi<D, N>(i, j, k)];
+        }
+        if (parent) st.end(s, sl.t);
+    }
     __syncthreads();
     if (!sl.valid || !parent) return;
     for (int e = sl.t; e < G::C; e += G::TPB) {
