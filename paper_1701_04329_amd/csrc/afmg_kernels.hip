@@ -77,6 +77,16 @@ __device__ __forceinline__ void row_of(int r, int &j, int &k) {
     k = D == 3 ? r / N : 0;
 }
 
+// fine cell q (0 .. 2^D - 1, x fastest) of the 2^D block under parent cell pc
+// (0 .. (N/2)^D - 1, x fastest) of a box
+template <int D, int N>
+__device__ __forceinline__ void block_cell(int pc, int q, int &i, int &j, int &k) {
+    constexpr int H = N / 2;
+    i = 2 * (pc % H) + (q & 1);
+    j = 2 * ((pc / H) % H) + ((q >> 1) & 1);
+    k = D == 3 ? 2 * (pc / (H * H)) + (q >> 2) : 0;
+}
+
 // Contiguous run of workgroup ids per XCD (workgroups are dispatched to the
 // eight XCDs round-robin).  Bijective on [0, G).
 __device__ __forceinline__ int xcd_remap(int w, int G) {
@@ -152,14 +162,14 @@ __device__ __forceinline__ void face_cell(int m, int x[3]) {
     x[SD::d] = SD::hi ? N - 1 : 0;
 }
 
-// raw operand of the ghost on side S next to face cell m of box bi.  The
-// address is selected without branches (one load per ghost, so the loads of a
+// raw operand of the ghost on side S next to face cell m of box bi (and, by
+// ghost_ptr, its address).  The address is selected without branches (one load per ghost, so the loads of a
 // thread stay in flight together), and the loaded value is not used here: a
 // homogeneous Dirichlet side loads a harmless in-range value, replaced by 0
 // when the ghost is finished (after the barrier, so no load waits before it).
 template <int D, int N, int S, typename T>
-__device__ __forceinline__ T ghost_raw(const BoxInfo &bi, int m, const T *__restrict__ u,
-                                       const T *__restrict__ bc, int homog, int &v) {
+__device__ __forceinline__ const T *ghost_ptr(const BoxInfo &bi, int m, const T *__restrict__ u,
+                                              const T *__restrict__ bc, int homog, int &v) {
     using SD = SideOf<S>;
     using G = Geo<D, N>;
     int x[3];
@@ -175,7 +185,12 @@ __device__ __forceinline__ T ghost_raw(const BoxInfo &bi, int m, const T *__rest
     const size_t iu = (size_t)box * G::C + cpos<D, N>(q[0], q[1], q[2]);
     const bool from_bc = dir && !homog;
     const size_t ib = from_bc ? (size_t)bi.bcoff[S] * G::F + m : 0;
-    return from_bc ? bc[ib] : u[iu];
+    return from_bc ? bc + ib : u + iu;
+}
+template <int D, int N, int S, typename T>
+__device__ __forceinline__ T ghost_raw(const BoxInfo &bi, int m, const T *__restrict__ u,
+                                       const T *__restrict__ bc, int homog, int &v) {
+    return *ghost_ptr<D, N, S, T>(bi, m, u, bc, homog, v);
 }
 
 // finish the ghost from its raw operand; s is the padded box in LDS
@@ -357,36 +372,47 @@ __global__ __launch_bounds__(W) void k_gsrb(LevelArgs<T> a, int colour) {
         bool need_own = vx < 0;
         // y / z ghosts.  Across a same-level side they are the other-colour
         // cells of one row of the neighbour (row j' = N-1-j, resp. k' =
-        // N-1-k), HN contiguous values like the thread's own row.
-        if (j == 0 || j == N - 1) {
+        // N-1-k), HN contiguous values like the thread's own row.  Boxes
+        // with both sides of an axis at the same level take this form, the
+        // others the general one, which comes later in the program so that
+        // the common form's loads never wait for its loads.
+        const bool yrow = j == 0 || j == N - 1, zrow = D == 3 && (k == 0 || k == N - 1);
+        const bool yfast = bi.nbr[2] >= 0 && bi.nbr[3] >= 0;
+        const bool zfast = D == 3 && bi.nbr[4] >= 0 && bi.nbr[5] >= 0;
+        if (yfast && yrow) {
             vy = bi.nbr[j == 0 ? 2 : 3];
-            if (vy >= 0) {
-                const T *nr = a.u + (size_t)vy * G::C + oth0 + ((D == 3 ? N * k : 0) + (N - 1 - j) - r) * HN;
+            const T *nr = a.u + (size_t)vy * G::C + oth0 + ((D == 3 ? N * k : 0) + (N - 1 - j) - r) * HN;
 #pragma unroll
-                for (int m = 0; m < HN; m++) gy[m] = nr[m];
-            } else {
+            for (int m = 0; m < HN; m++) gy[m] = nr[m];
+        }
+        if (zfast && zrow) {
+            vz = bi.nbr[k == 0 ? 4 : 5];
+            const T *nr = a.u + (size_t)vz * G::C + oth0 + ((N - 1 - k) * N + j - r) * HN;
 #pragma unroll
-                for (int m = 0; m < HN; m++) {
-                    const int fm = (2 * m + p) + (D == 3 ? N * k : 0);
-                    if (j == 0) gy[m] = ghost_raw<D, N, 2, T>(bi, fm, a.u, a.bc, a.homog, vy);
-                    else gy[m] = ghost_raw<D, N, 3, T>(bi, fm, a.u, a.bc, a.homog, vy);
-                }
+            for (int m = 0; m < HN; m++) gz[m] = nr[m];
+        }
+        __asm__ volatile("" ::: "memory");
+        if (!yfast && yrow) {
+#pragma unroll
+            for (int m = 0; m < HN; m++) {
+                const int fm = (2 * m + p) + (D == 3 ? N * k : 0);
+                int v2, v3;
+                const T *p2 = ghost_ptr<D, N, 2, T>(bi, fm, a.u, a.bc, a.homog, v2);
+                const T *p3 = ghost_ptr<D, N, 3, T>(bi, fm, a.u, a.bc, a.homog, v3);
+                vy = j == 0 ? v2 : v3;
+                gy[m] = *(j == 0 ? p2 : p3);
             }
             need_own |= vy < 0;
         }
-        if (D == 3 && (k == 0 || k == N - 1)) {
-            vz = bi.nbr[k == 0 ? 4 : 5];
-            if (vz >= 0) {
-                const T *nr = a.u + (size_t)vz * G::C + oth0 + ((N - 1 - k) * N + j - r) * HN;
+        if (D == 3 && !zfast && zrow) {
 #pragma unroll
-                for (int m = 0; m < HN; m++) gz[m] = nr[m];
-            } else {
-#pragma unroll
-                for (int m = 0; m < HN; m++) {
-                    const int fm = (2 * m + p) + N * j;
-                    if (k == 0) gz[m] = ghost_raw<D, N, 4, T>(bi, fm, a.u, a.bc, a.homog, vz);
-                    else gz[m] = ghost_raw<D, N, 5, T>(bi, fm, a.u, a.bc, a.homog, vz);
-                }
+            for (int m = 0; m < HN; m++) {
+                const int fm = (2 * m + p) + N * j;
+                int v4, v5;
+                const T *p4 = ghost_ptr<D, N, 4, T>(bi, fm, a.u, a.bc, a.homog, v4);
+                const T *p5 = ghost_ptr<D, N, 5, T>(bi, fm, a.u, a.bc, a.homog, v5);
+                vz = k == 0 ? v4 : v5;
+                gz[m] = *(k == 0 ? p4 : p5);
             }
             need_own |= vz < 0;
         }
@@ -412,8 +438,12 @@ __global__ __launch_bounds__(W) void k_gsrb(LevelArgs<T> a, int colour) {
             const T zp = k < N - 1 ? s[oslot<D, N>(i, j, k + 1)] : gs_finish<D, N, 5, T>(s, gz[m], vz, ow[m], a.homog, i, j, k);
             sum = sum + (zm + zp);
         }
-        ub[own0 + m] = (sum - a.h2 * rr[m]) / T(2 * D);
+        rr[m] = (sum - a.h2 * rr[m]) / T(2 * D);
     }
+    // the row's new values leave together (two 16-byte stores per thread in
+    // FP64 instead of four scattered 8-byte ones)
+#pragma unroll
+    for (int m = 0; m < HN; m++) ub[own0 + m] = rr[m];
 }
 
 // ---------------------------------------------------------------------------
@@ -457,27 +487,42 @@ __global__ __launch_bounds__(W) void k_resid_restrict(LevelArgs<T> a) {
     T *s = sm + sl.slot * G::PC;
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
+    // each thread: NPC parent cells (2^D blocks); their right-hand side is
+    // fetched before the staging loads so that both are in flight together
+    constexpr int NPC = G::HC / G::TPB, NB = D == 3 ? 8 : 4;
+    T rf[NPC][NB];
     Stager<D, N, T> st;
-    if (sl.valid) st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, true);
+    if (sl.valid) {
+#pragma unroll
+        for (int it = 0; it < NPC; it++)
+#pragma unroll
+            for (int q = 0; q < NB; q++) {
+                int i, j, k;
+                block_cell<D, N>(sl.t + it * G::TPB, q, i, j, k);
+                rf[it][q] = a.rho[bo + cpos<D, N>(i, j, k)];
+            }
+        st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, true);
+    }
     __syncthreads();
     if (sl.valid) st.end(s, sl.t);
     __syncthreads();
     if (!sl.valid) return;
-    // each thread: one 2^D block = one parent cell; residuals in registers
     const T w = D == 3 ? T(0.125) : T(0.25);
     const int flags = bi.flags;
     const int64_t p = bi.parent;
-    for (int pc = sl.t; pc < G::HC; pc += G::TPB) {
+#pragma unroll
+    for (int it = 0; it < NPC; it++) {
+        const int pc = sl.t + it * G::TPB;
         const int I = pc % G::H, J = (pc / G::H) % G::H, K = D == 3 ? pc / (G::H * G::H) : 0;
         T su = T(0), sr = T(0);
-        for (int dk = 0; dk < (D == 3 ? 2 : 1); dk++)
-            for (int dj = 0; dj < 2; dj++)
-                for (int di = 0; di < 2; di++) {
-                    const int i = 2 * I + di, j = 2 * J + dj, k = D == 3 ? 2 * K + dk : 0;
-                    const T uc = s[padi<D, N>(i, j, k)];
-                    su += uc;
-                    sr += a.rho[bo + cpos<D, N>(i, j, k)] - (nb_sum<D, N, T>(s, i, j, k) - T(2 * D) * uc) * a.ih2;
-                }
+#pragma unroll
+        for (int q = 0; q < NB; q++) {
+            int i, j, k;
+            block_cell<D, N>(pc, q, i, j, k);
+            const T uc = s[padi<D, N>(i, j, k)];
+            su += uc;
+            sr += rf[it][q] - (nb_sum<D, N, T>(s, i, j, k) - T(2 * D) * uc) * a.ih2;
+        }
         const int X = obit(flags, 0) * G::H + I, Y = obit(flags, 1) * G::H + J,
                   Z = D == 3 ? obit(flags, 2) * G::H + K : 0;
         const size_t o = (size_t)p * G::C + cpos<D, N>(X, Y, Z);
@@ -500,10 +545,18 @@ __global__ __launch_bounds__(W) void k_coarse_rhs(LevelArgs<T> a) {
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
     const bool parent = !(bi.flags & FLAG_LEAF);
+    constexpr int NE = G::C / G::TPB;  // cells per thread
+    T rf[NE];
     Stager<D, N, T> st;
     if (sl.valid) {
-        if (parent) st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, true);
-        else st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, false);
+        if (parent) {
+            // rbar of the thread's cells, in flight with the staging loads
+#pragma unroll
+            for (int it = 0; it < NE; it++) rf[it] = a.rho[bo + sl.t + it * G::TPB];
+            st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, true);
+        } else {
+            st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, false);
+        }
     }
     __syncthreads();
     if (sl.valid) {
@@ -517,10 +570,12 @@ __global__ __launch_bounds__(W) void k_coarse_rhs(LevelArgs<T> a) {
     }
     __syncthreads();
     if (!sl.valid || !parent) return;
-    for (int e = sl.t; e < G::C; e += G::TPB) {
+#pragma unroll
+    for (int it = 0; it < NE; it++) {
+        const int e = sl.t + it * G::TPB;
         int i, j, k;
         cell_of<D, N>(e, i, j, k);
-        a.rho[bo + e] = a.rho[bo + e] + (nb_sum<D, N, T>(s, i, j, k) - T(2 * D) * s[padi<D, N>(i, j, k)]) * a.ih2;
+        a.rho[bo + e] = rf[it] + (nb_sum<D, N, T>(s, i, j, k) - T(2 * D) * s[padi<D, N>(i, j, k)]) * a.ih2;
     }
 }
 
@@ -542,10 +597,11 @@ __device__ __forceinline__ int qpad(int I, int J, int K) {
 }
 
 // Halo cell m of side S of the octant (o = octant origin in parent cells).
-// Phase 1 stores what needs no LDS data (delta inside the parent or in a
-// same-level neighbour) and returns, for the other halo cells, the side type
-// v and the global operand (delta of the coarser cell uH for a refinement
-// side).  Phase 2 (after a barrier) finishes those from the staged octant.
+// halo_addr gives the cell whose delta is the halo value (inside the parent
+// or in a same-level neighbour: v >= 0) or the global operand of its ghost
+// formula (the coarser cell uH of a refinement side; v <= -2), the side type v
+// and the LDS slot.  Phase 2 (after a barrier) finishes the ghosts (v < 0)
+// from the staged octant.
 template <int D, int N, int S>
 __device__ __forceinline__ void halo_cell(int m, const int o[3], int L[3], int X[3]) {
     using SD = SideOf<S>;
@@ -558,9 +614,9 @@ __device__ __forceinline__ void halo_cell(int m, const int o[3], int L[3], int X
     X[2] = D == 3 ? o[2] + L[2] : 0;
 }
 
-template <int D, int N, int S, typename T>
-__device__ __forceinline__ T halo_phase1(T *q, int m, const int o[3], const BoxInfo &pi, int64_t p,
-                                         const T *__restrict__ u, const T *__restrict__ uold, int &v) {
+template <int D, int N, int S>
+__device__ __forceinline__ size_t halo_addr(int m, const int o[3], const BoxInfo &pi, int64_t p, int &v,
+                                            int &slot) {
     using SD = SideOf<S>;
     using G = Geo<D, N>;
     int L[3], X[3];
@@ -576,10 +632,8 @@ __device__ __forceinline__ T halo_phase1(T *q, int m, const int o[3], const BoxI
     X[SD::t2] = D == 3 ? (cf ? obit(flags, SD::t2) * G::H + (x2 >> 1) : x2) : 0;
     // a Dirichlet side reads the parent's own (in-range) cell and ignores it
     const int64_t box = inside ? p : (v >= 0 ? (int64_t)v : (cf ? (int64_t)(-v - 2) : p));
-    const size_t oo = (size_t)box * G::C + cpos<D, N>(X[0], X[1], X[2]);
-    const T d = u[oo] - uold[oo];
-    if (v >= 0) q[qpad<D, N>(L[0], L[1], L[2])] = d;
-    return d;
+    slot = qpad<D, N>(L[0], L[1], L[2]);
+    return (size_t)box * G::C + cpos<D, N>(X[0], X[1], X[2]);
 }
 
 // Dirichlet: ghost of delta = -delta(face cell) (the values b cancel);
@@ -619,6 +673,8 @@ template <int D, int N, typename T, int W>
 __global__ __launch_bounds__(W) void k_prolong(LevelArgs<T> a) {
     using G = Geo<D, N>;
     constexpr int NH = (2 * D * G::HF + G::TPB - 1) / G::TPB;  // halo cells per thread
+    constexpr int NO = G::HC / G::TPB;                           // octant cells per thread
+    constexpr int NE = G::C / G::TPB;                            // fine cells per thread
     __shared__ T qs[(W / G::TPB) * G::QC];
     const Slot<D, N> sl = slot_of<D, N, W>(a);
     T *q = qs + sl.slot * G::QC;
@@ -626,28 +682,47 @@ __global__ __launch_bounds__(W) void k_prolong(LevelArgs<T> a) {
     const size_t bo = (size_t)sl.b * G::C;
     const int flags = bi.flags;
     const int o[3] = {obit(flags, 0) * G::H, obit(flags, 1) * G::H, D == 3 ? obit(flags, 2) * G::H : 0};
-    T raw[NH];
+    T raw[NH], uf[NE];
     int hv[NH];
     if (sl.valid) {
         const int64_t p = bi.parent;
         const BoxInfo pi = load_box<D, N>(a.info, p);
-        for (int pc = sl.t; pc < G::HC; pc += G::TPB) {
+        // every global operand first (octant, halo, then the fine values that
+        // are needed only after the barriers), the LDS stores after them
+        T od[NO];
+#pragma unroll
+        for (int it = 0; it < NO; it++) {
+            const int pc = sl.t + it * G::TPB;
             const int I = pc % G::H, J = (pc / G::H) % G::H, K = D == 3 ? pc / (G::H * G::H) : 0;
             const size_t oo = (size_t)p * G::C + cpos<D, N>(o[0] + I, o[1] + J, o[2] + K);
-            q[qpad<D, N>(I, J, K)] = a.u[oo] - a.uold[oo];
+            od[it] = a.u[oo] - a.uold[oo];
         }
+        int hs[NH];
 #pragma unroll
         for (int h = 0; h < NH; h++) {
             const int hc = sl.t + h * G::TPB;
+            size_t ho = (size_t)p * G::C;
             hv[h] = 0;
-            raw[h] = T(0);
+            hs[h] = 0;
             if (hc < 2 * D * G::HF) {
                 const int side = hc / G::HF, m = hc % G::HF;
-#define AFMG_H1(S) raw[h] = halo_phase1<D, N, S, T>(q, m, o, pi, p, a.u, a.uold, hv[h])
+#define AFMG_H1(S) ho = halo_addr<D, N, S>(m, o, pi, p, hv[h], hs[h])
                 AFMG_SIDE_SWITCH(side, AFMG_H1)
 #undef AFMG_H1
             }
+            raw[h] = a.u[ho] - a.uold[ho];
         }
+#pragma unroll
+        for (int it = 0; it < NE; it++) uf[it] = a.u[bo + sl.t + it * G::TPB];
+#pragma unroll
+        for (int it = 0; it < NO; it++) {
+            const int pc = sl.t + it * G::TPB;
+            const int I = pc % G::H, J = (pc / G::H) % G::H, K = D == 3 ? pc / (G::H * G::H) : 0;
+            q[qpad<D, N>(I, J, K)] = od[it];
+        }
+#pragma unroll
+        for (int h = 0; h < NH; h++)
+            if (sl.t + h * G::TPB < 2 * D * G::HF && hv[h] >= 0) q[hs[h]] = raw[h];
     }
     __syncthreads();
     if (sl.valid) {
@@ -664,7 +739,9 @@ __global__ __launch_bounds__(W) void k_prolong(LevelArgs<T> a) {
     }
     __syncthreads();
     if (!sl.valid) return;
-    for (int e = sl.t; e < G::C; e += G::TPB) {
+#pragma unroll
+    for (int it = 0; it < NE; it++) {
+        const int e = sl.t + it * G::TPB;
         int i, j, k;
         cell_of<D, N>(e, i, j, k);
         const int I = i >> 1, J = j >> 1, K = k >> 1;
@@ -677,7 +754,7 @@ __global__ __launch_bounds__(W) void k_prolong(LevelArgs<T> a) {
             v = T(0.25) * (((q[qpad<D, N>(I, J, K)] + q[qpad<D, N>(I + sx, J, K)]) + q[qpad<D, N>(I, J + sy, K)]) +
                            q[qpad<D, N>(I, J, K + sz)]);
         }
-        a.u[bo + e] = a.u[bo + e] + v;
+        a.u[bo + e] = uf[it] + v;
     }
 }
 
@@ -702,10 +779,24 @@ __global__ __launch_bounds__(W) void k_final(LevelArgs<T> a, double *partial, in
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
     const bool leaf = bi.flags & FLAG_LEAF;
+    constexpr int NPC = G::HC / G::TPB, NB = D == 3 ? 8 : 4;
+    T rf[NPC][NB];
     Stager<D, N, T> st;
     if (sl.valid) {
-        if (leaf) st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, true);
-        else st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, false);
+        if (leaf) {
+            // rho of the thread's blocks, in flight with the staging loads
+#pragma unroll
+            for (int it = 0; it < NPC; it++)
+#pragma unroll
+                for (int q = 0; q < NB; q++) {
+                    int i, j, k;
+                    block_cell<D, N>(sl.t + it * G::TPB, q, i, j, k);
+                    rf[it][q] = a.rho[bo + cpos<D, N>(i, j, k)];
+                }
+            st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, true);
+        } else {
+            st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, false);
+        }
     }
     __syncthreads();
     if (sl.valid && leaf) st.end(s, sl.t);
@@ -717,22 +808,23 @@ __global__ __launch_bounds__(W) void k_final(LevelArgs<T> a, double *partial, in
         const T w = D == 3 ? T(0.125) : T(0.25);
         const int flags = bi.flags;
         const int64_t p = bi.parent;
-        for (int pc = sl.t; pc < G::HC; pc += G::TPB) {
+#pragma unroll
+        for (int it = 0; it < NPC; it++) {
+            const int pc = sl.t + it * G::TPB;
             const int I = pc % G::H, J = (pc / G::H) % G::H, K = D == 3 ? pc / (G::H * G::H) : 0;
             T su = T(0);
             if (leaf) {
-                // all residuals of the block first (their loads in flight
-                // together), then the optional FP32 copies
-                constexpr int NB = D == 3 ? 8 : 4;
+                // all residuals of the block first, then the optional FP32 copies
                 double r[NB];
                 int e[NB];
 #pragma unroll
                 for (int q = 0; q < NB; q++) {
-                    const int i = 2 * I + (q & 1), j = 2 * J + ((q >> 1) & 1), k = D == 3 ? 2 * K + (q >> 2) : 0;
+                    int i, j, k;
+                    block_cell<D, N>(pc, q, i, j, k);
                     const T uc = s[padi<D, N>(i, j, k)];
                     su += uc;
                     e[q] = cpos<D, N>(i, j, k);
-                    r[q] = (double)(a.rho[bo + e[q]] - (nb_sum<D, N, T>(s, i, j, k) - T(2 * D) * uc) * a.ih2);
+                    r[q] = (double)(rf[it][q] - (nb_sum<D, N, T>(s, i, j, k) - T(2 * D) * uc) * a.ih2);
                 }
                 if (rout) {
 #pragma unroll
