@@ -89,7 +89,8 @@ typedef struct {
                          the unchecked cycles are NaN. */
 } afmg_opts;
 
-/* kernel classes timed when opts.profile is set (finest level only) */
+/* kernel classes timed when opts.profile is set (finest level only; a
+   finest level <= 2 runs inside the coarse kernel and is not timed) */
 enum {
     AFMG_PROF_GSRB = 0,      /* one red or black half sweep */
     AFMG_PROF_RESID = 1,     /* residual + restriction */

@@ -28,10 +28,16 @@ struct LevelArgs {
 
 enum class Op { GSRB, RESID_RESTRICT, COARSE_RHS, PROLONG, RESTRICT_RHO };
 
-enum { COARSE_V_FROM_2 = 0, COARSE_V_TOP1 = 1, COARSE_FMG = 2 };
+// Modes of the coarse kernel.  Levels <= 1: V_FROM_2 (level 1 right after
+// the restriction from level 2), V_TOP1 (V-cycle from level 1), FMG.
+// Levels <= 2 (the 2^D boxes of level 2 as one grid): V2_FROM_3 (level 2
+// right after the restriction from level 3: FAS right-hand side, then the
+// V-cycle from level 2), V2_TOP (V-cycle from level 2).  A tree without the
+// levels a mode assumes takes the mode that fits it.
+enum { COARSE_V_FROM_2 = 0, COARSE_V_TOP1 = 1, COARSE_FMG = 2, COARSE_V2_FROM_3 = 3, COARSE_V2_TOP = 4 };
 
-// Arguments of the kernel for levels <= 1: one workgroup per tree, whose
-// root is box `tree` (the roots come first in the box order).
+// Arguments of the coarse kernel: one workgroup per tree, whose root is box
+// `tree` (the roots come first in the box order).
 template <typename T>
 struct CoarseArgs {
     const BoxInfo *info;
@@ -42,7 +48,9 @@ struct CoarseArgs {
     int mode;
     int homog;
     int n_down, n_up, n_base;
-    const int *active;  // per-tree flag as in LevelArgs (null: all trees)
+    const int *active;    // per-tree flag as in LevelArgs (null: all trees)
+    const int32_t *child; // [n_boxes][8] child ids (modes V2_*)
+    T h2_2, ih2_2;        // h^2 and 1/h^2 of level 2 (modes V2_*)
 };
 
 // wg: workgroup size of the launch (64, 128 or 256 threads; W / N^(D-1)

@@ -1309,50 +1309,274 @@ struct CoarseState {
     }
 };
 
+// Level 2 of a tree inside the coarse kernel: the 2^D boxes under the root
+// form one (2N)^D grid in LDS (natural order, x fastest) in the precision T
+// of the level kernels.  Every step uses the formulas and summation orders of
+// the box kernels (k_gsrb, k_resid_restrict, k_coarse_rhs, k_prolong): level 2
+// is complete (all children of the root exist), so its ghosts are grid cells
+// or Dirichlet ghosts 2 b - u1 (b = 0 when homogeneous), and the deltas of
+// the root seen from level 2 have the ghost -delta(face cell) outside the
+// domain (paper §2.4, §2.5, §3.1, §3.2).
+constexpr int COARSE_NT = 512;  // threads of the coarse kernel
+
 template <int D, int N, typename T>
-__global__ __launch_bounds__(256) void k_coarse(CoarseArgs<T> a) {
+struct Level2 {
+    static constexpr int M = 2 * N;                          // cells per axis
+    static constexpr int CELLS = D == 3 ? M * M * M : M * M;
+    static constexpr int F = D == 3 ? M * M : M;             // cells per side
+    T *u, *rho;    // grid values and right-hand side
+    const T *bc;   // [2D][F] Dirichlet values (zero when homogeneous)
+    T h2, ih2;
+    int parents;   // bit o: the box of octant o is a parent
+
+    __device__ __forceinline__ static int at(int i, int j, int k) { return D == 3 ? i + M * (j + M * k) : i + M * j; }
+    __device__ __forceinline__ static int octant(int i, int j, int k) {
+        return (i >= N ? 1 : 0) | (j >= N ? 2 : 0) | (D == 3 && k >= N ? 4 : 0);
+    }
+    // cell of grid position c
+    __device__ __forceinline__ static void ijk(int c, int &i, int &j, int &k) {
+        i = c % M;
+        j = (c / M) % M;
+        k = D == 3 ? c / (M * M) : 0;
+    }
+    // Dirichlet value of side s next to cell (i, j, k) (tangential axes
+    // increasing, the first fastest)
+    __device__ __forceinline__ T bval(int s, int i, int j, int k) const {
+        const int d = s >> 1;
+        const int m = d == 0 ? j + M * k : d == 1 ? i + M * k : i + M * j;
+        return bc[s * F + m];
+    }
+    // neighbour sum of the stencil, ghosts included
+    __device__ __forceinline__ T nb_sum(int i, int j, int k) const {
+        const int c = at(i, j, k);
+        const T uc = u[c];
+        const T xm = i > 0 ? u[c - 1] : T(2) * bval(0, i, j, k) - uc;
+        const T xp = i < M - 1 ? u[c + 1] : T(2) * bval(1, i, j, k) - uc;
+        const T ym = j > 0 ? u[c - M] : T(2) * bval(2, i, j, k) - uc;
+        const T yp = j < M - 1 ? u[c + M] : T(2) * bval(3, i, j, k) - uc;
+        T sum = (xm + xp) + (ym + yp);
+        if (D == 3) {
+            const T zm = k > 0 ? u[c - M * M] : T(2) * bval(4, i, j, k) - uc;
+            const T zp = k < M - 1 ? u[c + M * M] : T(2) * bval(5, i, j, k) - uc;
+            sum = sum + (zm + zp);
+        }
+        return sum;
+    }
+    // one red (0) or black (1) half sweep; every new value of the thread is
+    // computed before the first is stored, so that the LDS reads of all its
+    // cells are in flight together
+    __device__ __forceinline__ void half(int colour) const {
+        constexpr int hm = M / 2, NQ = CELLS / 2, IT = (NQ + COARSE_NT - 1) / COARSE_NT;
+        T res[IT];
+        int cc[IT];
+#pragma unroll
+        for (int it = 0; it < IT; it++) {
+            const int q = (int)threadIdx.x + it * COARSE_NT;
+            cc[it] = -1;
+            if (q < NQ) {
+                const int r = q / hm, j = r % M, k = D == 3 ? r / M : 0;
+                const int i = 2 * (q % hm) + ((colour + j + k + D) & 1);
+                cc[it] = at(i, j, k);
+                res[it] = (nb_sum(i, j, k) - h2 * rho[cc[it]]) / T(2 * D);
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < IT; it++)
+            if (cc[it] >= 0) u[cc[it]] = res[it];
+        __syncthreads();
+    }
+    __device__ __forceinline__ void gsrb(int n) const {
+        for (int q = 0; q < n; q++) {
+            half(0);
+            half(1);
+        }
+    }
+    // FAS right-hand side on the parent boxes: rho (= rbar) += L u
+    __device__ __forceinline__ void crhs() const {
+        constexpr int IT = (CELLS + COARSE_NT - 1) / COARSE_NT;
+#pragma unroll
+        for (int it = 0; it < IT; it++) {
+            const int c = (int)threadIdx.x + it * COARSE_NT;
+            if (c < CELLS) {
+                int i, j, k;
+                ijk(c, i, j, k);
+                if ((parents >> octant(i, j, k)) & 1) rho[c] = rho[c] + (nb_sum(i, j, k) - T(2 * D) * u[c]) * ih2;
+            }
+        }
+        __syncthreads();
+    }
+    // level-1 cell P (natural order of the root box): means of u and of the
+    // residual over its 2^D block
+    __device__ __forceinline__ void resid_restrict(int P, T &mu, T &mr) const {
+        constexpr int NB = D == 3 ? 8 : 4;
+        const T w = D == 3 ? T(0.125) : T(0.25);
+        const int I = P % N, J = (P / N) % N, K = D == 3 ? P / (N * N) : 0;
+        T su = T(0), sr = T(0);
+#pragma unroll
+        for (int q = 0; q < NB; q++) {
+            const int i = 2 * I + (q & 1), j = 2 * J + ((q >> 1) & 1), k = D == 3 ? 2 * K + (q >> 2) : 0;
+            const int c = at(i, j, k);
+            const T uc = u[c];
+            su += uc;
+            sr += rho[c] - (nb_sum(i, j, k) - T(2 * D) * uc) * ih2;
+        }
+        mu = w * su;
+        mr = w * sr;
+    }
+    // u += P(delta) with delta = u - v' of the root (level 1, FP64 in LDS,
+    // rounded to T as the box path stores it)
+    __device__ __forceinline__ static T delta(const double *fu, const double *fo, int I, int J, int K) {
+        const int c = I + N * (J + N * K);
+        return (T)fu[c] - (T)fo[c];
+    }
+    __device__ __forceinline__ void prolong(const double *fu, const double *fo) const {
+        constexpr int IT = (CELLS + COARSE_NT - 1) / COARSE_NT;
+        T res[IT];
+#pragma unroll
+        for (int it = 0; it < IT; it++) {
+            const int c = (int)threadIdx.x + it * COARSE_NT;
+            if (c >= CELLS) continue;
+            int i, j, k;
+            ijk(c, i, j, k);
+            const int I = i >> 1, J = j >> 1, K = k >> 1;
+            const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
+            const T dP = delta(fu, fo, I, J, K);
+            const T dx = (I + sx >= 0 && I + sx < N) ? delta(fu, fo, I + sx, J, K) : -dP;
+            const T dy = (J + sy >= 0 && J + sy < N) ? delta(fu, fo, I, J + sy, K) : -dP;
+            T v;
+            if (D == 2) {
+                v = T(0.5) * dP + T(0.25) * dx + T(0.25) * dy;
+            } else {
+                const T dz = (K + sz >= 0 && K + sz < N) ? delta(fu, fo, I, J, K + sz) : -dP;
+                v = T(0.25) * (((dP + dx) + dy) + dz);
+            }
+            res[it] = u[c] + v;
+        }
+#pragma unroll
+        for (int it = 0; it < IT; it++) {
+            const int c = (int)threadIdx.x + it * COARSE_NT;
+            if (c < CELLS) u[c] = res[it];
+        }
+        __syncthreads();
+    }
+};
+
+template <int D, int N, typename T>
+__global__ __launch_bounds__(COARSE_NT) void k_coarse(CoarseArgs<T> a) {
     using CG = CoarseGeo<D, N>;
     using G = Geo<D, N>;
+    using L2 = Level2<D, N, T>;
     __shared__ double f_u[CG::TOT], f_rho[CG::TOT], f_uold[CG::TOT], f_res[CG::TOT], f_bc[CG::BTOT];
+    __shared__ T l2_u[L2::CELLS], l2_rho[L2::CELLS], l2_bc[2 * D * L2::F];
     CoarseState<D, N> st{f_u, f_rho, f_uold, f_res, f_bc, a.n_down, a.n_up, a.n_base};
     // one workgroup per tree; the roots are boxes 0 .. n_trees-1
     const int64_t root = blockIdx.x;
     const BoxInfo *ri = a.info + root;
     if (a.active && !a.active[ri->tree]) return;
-    // a V-cycle reaching level 2 starts here after a restriction, unless the
-    // tree is its root box alone
-    const int mode = (a.mode == COARSE_V_FROM_2 && (ri->flags & FLAG_LEAF)) ? COARSE_V_TOP1 : a.mode;
+    // the mode that fits the tree: a tree that is its root box alone starts
+    // at level 1; with level 2 but no level 3, a V-cycle starts at level 2
+    int mode = a.mode;
+    const bool root_leaf = ri->flags & FLAG_LEAF;
+    int parents = 0;
+    if (mode == COARSE_V2_FROM_3 || mode == COARSE_V2_TOP) {
+        if (root_leaf) {
+            mode = COARSE_V_TOP1;
+        } else {
+            for (int o = 0; o < (1 << D); o++)
+                if (!(a.info[a.child[root * 8 + o]].flags & FLAG_LEAF)) parents |= 1 << o;
+            if (mode == COARSE_V2_FROM_3 && parents == 0) mode = COARSE_V2_TOP;
+        }
+    } else if (mode == COARSE_V_FROM_2 && root_leaf) {
+        mode = COARSE_V_TOP1;
+    }
+    const bool two = mode == COARSE_V2_FROM_3 || mode == COARSE_V2_TOP;
     T *gu = a.u + root * G::C;
-    const T *grho = a.rho + root * G::C;
+    T *grho = a.rho + root * G::C;
     T *guold = a.uold ? a.uold + root * G::C : nullptr;
     // the root box (colour-split in global memory) and its Dirichlet rows;
-    // the coarser grids start at zero.  Compile-time strides (the kernel
-    // runs with 256 threads) keep all loads of a thread in flight together.
-    constexpr int NT = 256;
+    // the coarser grids start at zero.  Compile-time strides keep all loads
+    // of a thread in flight together.
+    constexpr int NT = COARSE_NT;
     constexpr int NE = (G::C + NT - 1) / NT, NBC = (2 * D * G::F + NT - 1) / NT;
     double lu[NE], lr[NE], lb[NBC];
+    if (!two) {
 #pragma unroll
-    for (int q = 0; q < NE; q++) {
-        const int e = (int)threadIdx.x + q * NT;
-        lu[q] = (e < G::C && mode != COARSE_FMG) ? (double)gu[e] : 0.0;
-        lr[q] = e < G::C ? (double)grho[e] : 0.0;
+        for (int q = 0; q < NE; q++) {
+            const int e = (int)threadIdx.x + q * NT;
+            lu[q] = (e < G::C && mode != COARSE_FMG) ? (double)gu[e] : 0.0;
+            lr[q] = e < G::C ? (double)grho[e] : 0.0;
+        }
     }
 #pragma unroll
     for (int q = 0; q < NBC; q++) {
         const int g = (int)threadIdx.x + q * NT;
         lb[q] = (g < 2 * D * G::F && !a.homog) ? a.bc[(size_t)ri->bcoff[g / G::F] * G::F + g % G::F] : 0.0;
     }
+    const L2 lv2{l2_u, l2_rho, l2_bc, a.h2_2, a.ih2_2, parents};
+    if (two) {
+        // level 2: the children of the root into one grid, their Dirichlet
+        // rows on the domain sides
+        constexpr int C2 = (1 << D) * G::C, NE2 = (C2 + NT - 1) / NT;
+        T v2u[NE2], v2r[NE2];
 #pragma unroll
-    for (int q = 0; q < NE; q++) {
-        const int e = (int)threadIdx.x + q * NT;
-        if (e < G::C) {
+        for (int q = 0; q < NE2; q++) {
+            const int e = (int)threadIdx.x + q * NT, o = (e < C2 ? e : 0) / G::C;
+            const size_t bx = (size_t)a.child[root * 8 + o];
+            v2u[q] = e < C2 ? a.u[bx * G::C + e % G::C] : T(0);
+            v2r[q] = e < C2 ? a.rho[bx * G::C + e % G::C] : T(0);
+        }
+        for (int g = threadIdx.x; g < 2 * D * L2::F; g += NT) {
+            // side s, grid face cell m: tangential coordinates (t1, t2)
+            const int side = g / L2::F, m = g % L2::F, d = side >> 1;
+            const int x1 = m % L2::M, x2 = D == 3 ? m / L2::M : 0;
+            const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+            const int o = ((side & 1) << d) | ((x1 >= N ? 1 : 0) << t1) | (D == 3 && x2 >= N ? 1 << t2 : 0);
+            const BoxInfo &bi = a.info[a.child[root * 8 + o]];
+            const int mb = (x1 % N) + (D == 3 ? N * (x2 % N) : 0);
+            l2_bc[g] = a.homog ? T(0) : (T)a.bc[(size_t)bi.bcoff[side] * G::F + mb];
+        }
+#pragma unroll
+        for (int q = 0; q < NE2; q++) {
+            const int e = (int)threadIdx.x + q * NT, o = e / G::C;
+            if (e >= C2) continue;
+            int i, j, k;
+            cell_of<D, N>(e % G::C, i, j, k);
+            const int c = L2::at(i + (o & 1) * N, j + ((o >> 1) & 1) * N, D == 3 ? k + ((o >> 2) & 1) * N : 0);
+            l2_u[c] = v2u[q];
+            l2_rho[c] = v2r[q];
+            // after a restriction from level 3: the copy v' of level 2
+            if (mode == COARSE_V2_FROM_3) a.uold[(size_t)a.child[root * 8 + o] * G::C + e % G::C] = v2u[q];
+        }
+        __syncthreads();
+        if (mode == COARSE_V2_FROM_3) lv2.crhs();
+        lv2.gsrb(a.n_down);
+        // residual and u restricted into the root: level 1 then starts as
+        // after a restriction from level 2
+        for (int e = threadIdx.x; e < G::C; e += NT) {
             int i, j, k;
             cell_of<D, N>(e, i, j, k);
             const int c = i + N * (j + N * k);
-            f_u[c] = lu[q];
-            f_rho[c] = mode == COARSE_V_FROM_2 ? 0.0 : lr[q];
-            f_res[c] = mode == COARSE_V_FROM_2 ? lr[q] : 0.0;
+            T mu, mr;
+            lv2.resid_restrict(c, mu, mr);
+            grho[e] = mr;
+            f_u[c] = (double)mu;
+            f_rho[c] = 0.0;
+            f_res[c] = (double)mr;
             f_uold[c] = 0.0;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < NE; q++) {
+            const int e = (int)threadIdx.x + q * NT;
+            if (e < G::C) {
+                int i, j, k;
+                cell_of<D, N>(e, i, j, k);
+                const int c = i + N * (j + N * k);
+                f_u[c] = lu[q];
+                f_rho[c] = mode == COARSE_V_FROM_2 ? 0.0 : lr[q];
+                f_res[c] = mode == COARSE_V_FROM_2 ? lr[q] : 0.0;
+                f_uold[c] = 0.0;
+            }
         }
     }
     for (int p = G::C + (int)threadIdx.x; p < CG::TOT; p += NT) {
@@ -1385,7 +1609,7 @@ __global__ __launch_bounds__(256) void k_coarse(CoarseArgs<T> a) {
         }
         __syncthreads();
     }
-    if (mode == COARSE_V_FROM_2) {
+    if (mode == COARSE_V_FROM_2 || two) {
         // level 1 right after restriction from level 2: copy v', FAS
         // right-hand side, then the V-cycle from level 1
         st.template uold_crhs<0>();
@@ -1401,6 +1625,18 @@ __global__ __launch_bounds__(256) void k_coarse(CoarseArgs<T> a) {
         const int c = i + N * (j + N * k);
         gu[e] = (T)f_u[c];
         if (guold && mode != COARSE_V_TOP1) guold[e] = (T)f_uold[c];
+    }
+    if (!two) return;
+    // back to level 2: correction from the root, smoothing, store
+    lv2.prolong(f_u, f_uold);
+    lv2.gsrb(a.n_up);
+#pragma unroll 4
+    for (int e = threadIdx.x; e < (1 << D) * G::C; e += NT) {
+        const int o = e / G::C;
+        int i, j, k;
+        cell_of<D, N>(e % G::C, i, j, k);
+        const int c = L2::at(i + (o & 1) * N, j + ((o >> 1) & 1) * N, D == 3 ? k + ((o >> 2) & 1) * N : 0);
+        a.u[(size_t)a.child[root * 8 + o] * G::C + e % G::C] = l2_u[c];
     }
 }
 
@@ -1803,7 +2039,7 @@ void launch_level_mask(const int *base, const int32_t *tree_lmax, int l, int *ou
 
 template <int D, int N, typename T>
 void launch_coarse(const CoarseArgs<T> &a, int n_trees, hipStream_t st) {
-    AFMG_LAUNCH((k_coarse<D, N, T>), n_trees, st, a);
+    if (n_trees > 0) hipLaunchKernelGGL((k_coarse<D, N, T>), dim3(n_trees), dim3(COARSE_NT), 0, st, a);
 }
 
 template <int D, int N, typename T>

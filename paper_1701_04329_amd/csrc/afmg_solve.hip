@@ -65,7 +65,7 @@ struct afmg_tree {
     HostTree h;
     int device = -1;
     BoxInfo *d_info = nullptr;
-    int32_t *d_child = nullptr;      // [n_boxes][8] child ids (adjoint)
+    int32_t *d_child = nullptr;      // [n_boxes][8] child ids (adjoint, coarse kernel)
     double *h_norm = nullptr;        // pinned host copy of (max, L2) per tree
     std::vector<int64_t> part_off;   // first k_final partial of each level (one tree)
     int64_t n_parts = 0;
@@ -352,18 +352,28 @@ struct Cycler {
         CoarseArgs<T> c{base.info, base.u, base.rho, base.uold, bc64, mode, base.homog,
                         o.n_down, o.n_up, o.n_base, base.active};
         if (h.lmax == 1) c.uold = nullptr;
+        if (h.lmax >= 2) {
+            const LevelArgs<T> a2 = lev(2);
+            c.child = t->d_child;
+            c.h2_2 = a2.h2;
+            c.ih2_2 = a2.ih2;
+        }
         launch_coarse<D, BOX_N, T>(c, h.n_trees, st);
     }
-    // V-cycle from level top: levels >= 2 box by box, levels <= 1 in the
-    // coarse kernel
+    // V-cycle from level top: levels >= 3 box by box, levels <= 2 in the
+    // coarse kernel (level 2, the 2^D children of the root, as one grid)
     void vcycle(int top) {
-        for (int l = top; l >= 2; l--) {
+        if (top < 2) {
+            coarse(COARSE_V_TOP1);
+            return;
+        }
+        for (int l = top; l >= 3; l--) {
             gsrb(l, o.n_down);
             level(Op::RESID_RESTRICT, l);
-            if (l - 1 >= 2) level(Op::COARSE_RHS, l - 1);
+            if (l - 1 >= 3) level(Op::COARSE_RHS, l - 1);
         }
-        coarse(top >= 2 ? COARSE_V_FROM_2 : COARSE_V_TOP1);
-        for (int l = 2; l <= top; l++) {
+        coarse(top >= 3 ? COARSE_V2_FROM_3 : COARSE_V2_TOP);
+        for (int l = 3; l <= top; l++) {
             level(Op::PROLONG, l);
             gsrb(l, o.n_up);
         }
