@@ -9,7 +9,7 @@ the timed region starts.
 
 Prints one JSON line: throughput in unknowns/s, the roofline of the dominant
 kernel (the finest-level red-black half sweep) measured with HIP events on
-the solve's stream during the timed steps, and the FP64 CPU oracle timed on
+the solve's stream during the last timed step, and the FP64 CPU oracle timed on
 the host cores on the same workload.  Further objects: the mixed-precision solve, the
 256-tree batch, the adaptive octree (FP64 vs mixed) and the adjoint.
 """
@@ -357,7 +357,7 @@ def paper_ex_bench(args, A, torch, dev, stream):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2", choices=["c2", "c1"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -414,10 +414,12 @@ def main():
 
     def timed_steps(precision, graph=False, profile=True):
         """warmup + exactly `steps` timed solves; returns ms/step, the
-        summed event timings of the finest-level kernels (profile: event
-        pairs around each group of consecutive finest-level half sweeps and
-        each other finest-level launch; profiled solves launch eagerly) and
-        the last stats."""
+        summed event timings of the finest-level kernels, the last stats and
+        the cycle counts.  With profile, the last timed solve carries the
+        event pairs (one around each group of consecutive finest-level half
+        sweeps and each other finest-level launch; a profiled solve launches
+        eagerly): the pairs cost about 5% of a solve, so the other timed
+        solves run without them."""
         kw = dict(solve_kw, precision=precision)
         ws_p = ws if tree.workspace_bytes(A.make_opts(**kw)) <= ws.numel() else torch.empty(
             tree.workspace_bytes(A.make_opts(**kw)), dtype=torch.uint8, device=dev)
@@ -428,14 +430,14 @@ def main():
                            use_guess=False, graph=graph, **kw)
 
         for _ in range(args.warmup):
-            one(profile)
+            one(False)
         torch.cuda.synchronize()
         prof_ms = np.zeros(4)
         prof_n = np.zeros(4, dtype=np.int64)
         cycles = []
         t0 = time.perf_counter()
-        for _ in range(args.steps):
-            _, st = one(profile)
+        for i in range(args.steps):
+            _, st = one(profile and i == args.steps - 1)
             prof_ms += np.array(st["prof_ms"])
             prof_n += np.array(st["prof_n"], dtype=np.int64)
             cycles.append(st["cycles"])
@@ -529,7 +531,7 @@ def main():
             "v_cycles": int(np.median(cycles)),
             "final_residual_ratio": st64["r_max"] / st64["r0_max"],
             "precision": "fp64",
-            "schedule": "eager launches with event pairs (timed region); autotuned launch shapes",
+            "schedule": "eager launches, event pairs in the last timed solve; autotuned launch shapes",
         },
         "roofline": roofline,
         "mixed": mixed,
