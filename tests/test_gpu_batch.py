@@ -70,8 +70,8 @@ def zero_tree(dim):
 def bag(dim):
     """Trees of unequal shape: the root alone (lmax 1), refinement boundaries
     at several levels with random rho and Dirichlet values, Gaussian sources,
-    a tree whose zero data converge before the first cycle, and trees of the
-    batch workload recipe at reduced size."""
+    a tree whose zero data converge before the first cycle, trees of the
+    batch workload recipe at reduced size, and a uniform two-level tree."""
     c = (0.3, 0.62, 0.41)
     ws = [
         W.random_fields(dim, 8, *W.uniform_leaves(dim, 1), 11),
@@ -82,6 +82,9 @@ def bag(dim):
     ]
     js = [j for j in range(40) if (j % 2 == 0) == (dim == 2)][:3]
     ws += [W.config4_tree(j, box_range=(64, 400 if dim == 3 else 1500), seed_base=4100) for j in js]
+    # uniform level 2 with data: its V-cycles start at level 2 while deeper
+    # trees of the batch arrive there from level 3
+    ws.append(W.random_fields(dim, 8, *W.uniform_leaves(dim, 2), 14))
     return ws
 
 
