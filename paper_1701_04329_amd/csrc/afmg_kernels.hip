@@ -92,7 +92,8 @@ __device__ __forceinline__ void block_cell(int pc, int q, int &i, int &j, int &k
 __device__ __forceinline__ int xcd_remap(int w, int G) {
     const int q = G >> 3, r = G & 7;
     const int x = w & 7, p = w >> 3;
-    return x < r ? x * (q + 1) + p : r * (q + 1) + (x - r) * q + p;
+    // x < r: x (q + 1) + p; else r (q + 1) + (x - r) q + p (no branch)
+    return x * q + min(x, r) + p;
 }
 
 // Box record of box b.  With one box per wave (3D) the id is made
@@ -110,14 +111,18 @@ struct Slot {
     int slot, t; // slot in the workgroup, thread in the slot
 };
 // Workgroups of W threads hold W / TPB boxes; with remap set, workgroup ids
-// are remapped so that each XCD takes a contiguous run of boxes.
+// are remapped so that each XCD takes a contiguous run of boxes.  The grid is
+// ceil(nb / (W / TPB)) workgroups (wg_count); the count is derived from nb
+// rather than read from the dispatch, which saves the kernel one dependent
+// argument load before its first memory access.
 template <int D, int N, int W = 256>
 __device__ __forceinline__ Slot<D, N> slot_of(int64_t b0, int nb, bool remap = true) {
     using G = Geo<D, N>;
     constexpr int BPW = W / G::TPB;
     static_assert(BPW >= 1 && W % G::TPB == 0, "workgroup must hold whole boxes");
     Slot<D, N> r;
-    const int w = remap ? xcd_remap((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+    const int wr = xcd_remap((int)blockIdx.x, (nb + BPW - 1) / BPW);
+    const int w = remap ? wr : (int)blockIdx.x;
     r.slot = (int)threadIdx.x / G::TPB;
     r.t = (int)threadIdx.x % G::TPB;
     int bl = w * BPW + r.slot;
@@ -127,13 +132,17 @@ __device__ __forceinline__ Slot<D, N> slot_of(int64_t b0, int nb, bool remap = t
     return r;
 }
 
-// Slot of a level kernel.  In a forest, boxes of trees whose mask entry is 0
-// are treated like padding slots: they are read but never written.
+// Slot of a level kernel.
 template <int D, int N, int W, typename T>
 __device__ __forceinline__ Slot<D, N> slot_of(const LevelArgs<T> &a) {
-    Slot<D, N> r = slot_of<D, N, W>(a.b0, a.nb, a.no_remap == 0);
-    if (a.active) r.valid = r.valid && a.active[load_box<D, N>(a.info, r.b).tree] != 0;
-    return r;
+    return slot_of<D, N, W>(a.b0, a.nb, a.no_remap == 0);
+}
+// In a forest, the boxes of trees whose mask entry is 0 are read but never
+// written.  The test is made where a kernel first writes, so that it does not
+// delay the kernel's first loads.
+template <typename T>
+__device__ __forceinline__ bool tree_active(const LevelArgs<T> &a, const BoxInfo &bi) {
+    return !a.active || a.active[bi.tree] != 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -235,23 +244,23 @@ __device__ __forceinline__ int ghost_slot(int m) {
     }
 
 // Staging of one box with its ghosts in two phases around a barrier:
-// begin() loads the interior into the padded LDS box and fetches the raw
-// ghost operands; after __syncthreads, end() writes the ghost slots; one more
-// __syncthreads and the box is ready.  Thread t of the box owns row t (both
-// colours) and face cell t of every side (a side has F == TPB cells).
+// load() fetches row t of the interior and the raw ghost operands, stage()
+// writes the row into the padded LDS box (begin() = both); after
+// __syncthreads, end() writes the ghost slots; one more __syncthreads and the
+// box is ready.  Thread t of the box owns row t (both colours) and face cell t
+// of every side (a side has F == TPB cells).  A kernel issues its other
+// loads between load() and stage(), so that they are in flight together.
 template <int D, int N, typename T>
 struct Stager {
     using G = Geo<D, N>;
     T raw[6];
     int v[6];
     int hg;
+    T rowv[2][G::HN];
 
-    __device__ void begin(T *s, const BoxInfo &bi, const T *__restrict__ ub,
-                          const T *__restrict__ u, const T *__restrict__ bc, int homog, int t, bool ghosts) {
-        int j, k;
-        row_of<D, N>(t, j, k);
+    __device__ __forceinline__ void load(const BoxInfo &bi, const T *__restrict__ ub, const T *__restrict__ u,
+                                         const T *__restrict__ bc, int homog, int t, bool ghosts) {
         hg = homog;
-        T rowv[2][G::HN];
 #pragma unroll
         for (int c = 0; c < 2; c++)
 #pragma unroll
@@ -266,12 +275,22 @@ struct Stager {
                 raw[5] = ghost_raw<D, N, 5, T>(bi, t, u, bc, homog, v[5]);
             }
         }
+    }
+    __device__ __forceinline__ void stage(T *s, int t) const {
+        int j, k;
+        row_of<D, N>(t, j, k);
 #pragma unroll
         for (int c = 0; c < 2; c++) {
             const int p = (c + D + j + k) & 1;
 #pragma unroll
             for (int m = 0; m < G::HN; m++) s[padi<D, N>(2 * m + p, j, k)] = rowv[c][m];
         }
+    }
+    __device__ __forceinline__ void begin(T *s, const BoxInfo &bi, const T *__restrict__ ub,
+                                          const T *__restrict__ u, const T *__restrict__ bc, int homog, int t,
+                                          bool ghosts) {
+        load(bi, ub, u, bc, homog, t, ghosts);
+        stage(s, t);
     }
     __device__ void end(T *s, int t) {
         s[ghost_slot<D, N, 0>(t)] = ghost_finish<D, N, 0, T>(s, t, raw[0], v[0], hg);
@@ -358,7 +377,9 @@ __global__ __launch_bounds__(W) void k_gsrb(LevelArgs<T> a, int colour) {
         gy[m] = T(0);
         gz[m] = T(0);
     }
-    if (sl.valid) {
+    // the padding slots of the last workgroup load a valid box too (sl.b is
+    // clamped), so that no branch separates the loads from the kernel start
+    {
         T ot[HN];
         const int oth0 = (1 - colour) * G::HALF + r * HN;
 #pragma unroll
@@ -424,7 +445,7 @@ __global__ __launch_bounds__(W) void k_gsrb(LevelArgs<T> a, int colour) {
         for (int m = 0; m < HN; m++) s[m * G::TPB + r] = ot[m];
     }
     __syncthreads();
-    if (!sl.valid) return;
+    if (!sl.valid || !tree_active(a, bi)) return;
 #pragma unroll
     for (int m = 0; m < HN; m++) {
         const int i = 2 * m + p;
@@ -492,21 +513,21 @@ __global__ __launch_bounds__(W) void k_resid_restrict(LevelArgs<T> a) {
     constexpr int NPC = G::HC / G::TPB, NB = D == 3 ? 8 : 4;
     T rf[NPC][NB];
     Stager<D, N, T> st;
-    if (sl.valid) {
+    // padding slots (sl.b clamped to a valid box) load too: no branch before
+    // the loads
 #pragma unroll
-        for (int it = 0; it < NPC; it++)
+    for (int it = 0; it < NPC; it++)
 #pragma unroll
-            for (int q = 0; q < NB; q++) {
-                int i, j, k;
-                block_cell<D, N>(sl.t + it * G::TPB, q, i, j, k);
-                rf[it][q] = a.rho[bo + cpos<D, N>(i, j, k)];
-            }
-        st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, true);
-    }
+        for (int q = 0; q < NB; q++) {
+            int i, j, k;
+            block_cell<D, N>(sl.t + it * G::TPB, q, i, j, k);
+            rf[it][q] = a.rho[bo + cpos<D, N>(i, j, k)];
+        }
+    st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, true);
     __syncthreads();
     if (sl.valid) st.end(s, sl.t);
     __syncthreads();
-    if (!sl.valid) return;
+    if (!sl.valid || !tree_active(a, bi)) return;
     const T w = D == 3 ? T(0.125) : T(0.25);
     const int flags = bi.flags;
     const int64_t p = bi.parent;
@@ -548,28 +569,27 @@ __global__ __launch_bounds__(W) void k_coarse_rhs(LevelArgs<T> a) {
     constexpr int NE = G::C / G::TPB;  // cells per thread
     T rf[NE];
     Stager<D, N, T> st;
-    if (sl.valid) {
-        if (parent) {
-            // rbar of the thread's cells, in flight with the staging loads
+    // rows first (padding slots load a valid box too), then what depends on
+    // the box record: ghosts and rbar of parents
+    st.load(bi, a.u + bo, a.u, a.bc, a.homog, sl.t, parent);
+    if (parent) {
 #pragma unroll
-            for (int it = 0; it < NE; it++) rf[it] = a.rho[bo + sl.t + it * G::TPB];
-            st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, true);
-        } else {
-            st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, false);
-        }
+        for (int it = 0; it < NE; it++) rf[it] = a.rho[bo + sl.t + it * G::TPB];
     }
+    st.stage(s, sl.t);
     __syncthreads();
-    if (sl.valid) {
+    const bool act = sl.valid && tree_active(a, bi);
+    if (act) {
         // the copy v' from the staged interior
         for (int e = sl.t; e < G::C; e += G::TPB) {
             int i, j, k;
             cell_of<D, N>(e, i, j, k);
             a.uold[bo + e] = s[padi<D, N>(i, j, k)];
         }
-        if (parent) st.end(s, sl.t);
     }
+    if (sl.valid && parent) st.end(s, sl.t);
     __syncthreads();
-    if (!sl.valid || !parent) return;
+    if (!act || !parent) return;
 #pragma unroll
     for (int it = 0; it < NE; it++) {
         const int e = sl.t + it * G::TPB;
@@ -684,11 +704,14 @@ __global__ __launch_bounds__(W) void k_prolong(LevelArgs<T> a) {
     const int o[3] = {obit(flags, 0) * G::H, obit(flags, 1) * G::H, D == 3 ? obit(flags, 2) * G::H : 0};
     T raw[NH], uf[NE];
     int hv[NH];
-    if (sl.valid) {
+    // the fine values (needed only after the barriers) first: they need no
+    // box record; padding slots (sl.b clamped to a valid box) load too
+#pragma unroll
+    for (int it = 0; it < NE; it++) uf[it] = a.u[bo + sl.t + it * G::TPB];
+    {
         const int64_t p = bi.parent;
         const BoxInfo pi = load_box<D, N>(a.info, p);
-        // every global operand first (octant, halo, then the fine values that
-        // are needed only after the barriers), the LDS stores after them
+        // every global operand (octant, halo) before the LDS stores
         T od[NO];
 #pragma unroll
         for (int it = 0; it < NO; it++) {
@@ -713,8 +736,6 @@ __global__ __launch_bounds__(W) void k_prolong(LevelArgs<T> a) {
             raw[h] = a.u[ho] - a.uold[ho];
         }
 #pragma unroll
-        for (int it = 0; it < NE; it++) uf[it] = a.u[bo + sl.t + it * G::TPB];
-#pragma unroll
         for (int it = 0; it < NO; it++) {
             const int pc = sl.t + it * G::TPB;
             const int I = pc % G::H, J = (pc / G::H) % G::H, K = D == 3 ? pc / (G::H * G::H) : 0;
@@ -738,7 +759,7 @@ __global__ __launch_bounds__(W) void k_prolong(LevelArgs<T> a) {
         }
     }
     __syncthreads();
-    if (!sl.valid) return;
+    if (!sl.valid || !tree_active(a, bi)) return;
 #pragma unroll
     for (int it = 0; it < NE; it++) {
         const int e = sl.t + it * G::TPB;
@@ -782,29 +803,28 @@ __global__ __launch_bounds__(W) void k_final(LevelArgs<T> a, double *partial, in
     constexpr int NPC = G::HC / G::TPB, NB = D == 3 ? 8 : 4;
     T rf[NPC][NB];
     Stager<D, N, T> st;
-    if (sl.valid) {
-        if (leaf) {
-            // rho of the thread's blocks, in flight with the staging loads
+    // rows first (padding slots load a valid box too), then what depends on
+    // the box record: ghosts and rho of leaves
+    st.load(bi, a.u + bo, a.u, a.bc, a.homog, sl.t, leaf);
+    if (leaf) {
 #pragma unroll
-            for (int it = 0; it < NPC; it++)
+        for (int it = 0; it < NPC; it++)
 #pragma unroll
-                for (int q = 0; q < NB; q++) {
-                    int i, j, k;
-                    block_cell<D, N>(sl.t + it * G::TPB, q, i, j, k);
-                    rf[it][q] = a.rho[bo + cpos<D, N>(i, j, k)];
-                }
-            st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, true);
-        } else {
-            st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, false);
-        }
+            for (int q = 0; q < NB; q++) {
+                int i, j, k;
+                block_cell<D, N>(sl.t + it * G::TPB, q, i, j, k);
+                rf[it][q] = a.rho[bo + cpos<D, N>(i, j, k)];
+            }
     }
+    st.stage(s, sl.t);
     __syncthreads();
     if (sl.valid && leaf) st.end(s, sl.t);
     __syncthreads();
     // each thread: 2^D blocks of cells = parent cells; the block mean of u
     // goes to the parent, the residuals of leaves stay in registers
     double mx = 0.0, ss = 0.0;
-    if (sl.valid) {
+    const bool act = sl.valid && tree_active(a, bi);
+    if (act) {
         const T w = D == 3 ? T(0.125) : T(0.25);
         const int flags = bi.flags;
         const int64_t p = bi.parent;
@@ -854,7 +874,7 @@ __global__ __launch_bounds__(W) void k_final(LevelArgs<T> a, double *partial, in
         ss += __shfl_xor(ss, o);
     }
     if (part0 < 0) {
-        if (sl.valid && leaf && sl.t == 0) {
+        if (act && leaf && sl.t == 0) {
             partial[2 * sl.b + 0] = mx;
             partial[2 * sl.b + 1] = ss * hD;
         }
@@ -979,7 +999,7 @@ __global__ __launch_bounds__(256) void k_restrict_rho(LevelArgs<T> a) {
         }
     }
     __syncthreads();
-    if (sl.valid) restrict_octant<D, N, T, false>(s, a.rho, bi, sl.t);
+    if (sl.valid && tree_active(a, bi)) restrict_octant<D, N, T, false>(s, a.rho, bi, sl.t);
 }
 
 // In-place conversion of whole boxes between the caller's order (x fastest)
