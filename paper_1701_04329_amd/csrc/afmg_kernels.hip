@@ -1124,7 +1124,8 @@ __global__ __launch_bounds__(256) void k_bc_derive(const BoxInfo *__restrict__ i
 }
 
 // ---------------------------------------------------------------------------
-// levels <= 1: the root box and the coarse grids below it, one workgroup
+// levels <= 2 of a tree in one workgroup: level 2 (below), the root box and
+// the coarse grids below it
 // ---------------------------------------------------------------------------
 // The grids of N, N/2, ..., 2 cells per side (levels 1, 0, ..., lmin) are
 // single boxes whose sides are all physical (Dirichlet).  They live in LDS
