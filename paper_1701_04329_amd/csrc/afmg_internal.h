@@ -40,6 +40,7 @@ struct HostTree {
     std::vector<int32_t> leaf_box;    // box id of input leaf q
     std::vector<int32_t> child;       // [n_boxes][8] child ids (octant bits x|y<<1|z<<2), -1 if none
     bool uniform = true;              // every tree has all its leaves on one level
+    int lmin_leaf = 1;                // coarsest level holding a leaf (any tree)
     std::vector<int32_t> tree_lmax;        // finest level of each tree
     std::vector<int64_t> tree_leaf_ptr;    // leaf boxes of tree t: tree_leaf_box[ptr[t] .. ptr[t+1])
     std::vector<int32_t> tree_leaf_box;

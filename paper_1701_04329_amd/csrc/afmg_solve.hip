@@ -421,8 +421,12 @@ struct Solver {
     // Restriction of u into parents and the composite leaf residual (FP64),
     // reduced to (max, L2) per tree in norm; rout receives the FP32 leaf
     // residual for the mixed refinement.
-    void finalize_launch(float *rout, hipStream_t s) {
-        for (int l = h.lmax; l >= 1; l--) {
+    // Levels below lfirst are skipped: with no leaf at or below a level, its
+    // restriction into the parents feeds no residual, and the next V-cycle
+    // restricts into those parents again before it reads them
+    // (restrict_parents() fills them at the end of a solve).
+    void finalize_launch(float *rout, hipStream_t s, int lfirst = 1) {
+        for (int l = h.lmax; l >= std::max(1, lfirst); l--) {
             if (l == 1 && !t->forest && !root_is_leaf(h)) continue;
             const double hh = level_h(l);
             const double hD = D == 3 ? hh * hh * hh : hh * hh;
@@ -445,6 +449,12 @@ struct Solver {
             launch_reduce_trees(partial, t->d_tree_leaf_ptr, t->d_tree_leaf_box, base.active, norm, h.n_trees, s);
         else
             launch_reduce(partial, t->n_parts, norm, s);
+    }
+    // parents of the levels that the per-cycle finalize skips receive the
+    // restriction of the solution (k_final's arithmetic and order)
+    void restrict_parents() {
+        for (int l = h.lmin_leaf - 1; l >= 2; l--)
+            launch_restrict_field<D, BOX_N>(t->d_info, base.u, h.lvl_off[(size_t)l], h.level_count(l), st);
     }
     // norms to t->h_norm; synchronises the stream
     int read_norms() {
@@ -709,7 +719,8 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
             rc = s.upload_mask();
             if (rc != AFMG_OK) return rc;
             cy.fmg();
-            if ((rc = s.finalize(nullptr)) != AFMG_OK) return rc;
+            s.finalize_launch(nullptr, st, h.lmin_leaf);
+            if ((rc = s.read_norms()) != AFMG_OK) return rc;
             take_norms(t, S, false);
         }
         rc = iterate_trees(s, S, tr, [&](int, int m) {
@@ -719,7 +730,7 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
                 Cycler<D, double> c2 = cy;
                 c2.st = cs;
                 for (int c = 0; c < m; c++) c2.vcycle(h.lmax);
-                s.finalize_launch(nullptr, cs);
+                s.finalize_launch(nullptr, cs, h.lmin_leaf);
             });
             return q != AFMG_OK ? q : s.read_norms();
         });
@@ -740,7 +751,7 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
                 c2.vcycle(h.lmax);
             }
             launch_ir_update<D, BOX_N>(t->d_info, uw, e32, h.n_boxes, t->d_active, cs);
-            s.finalize_launch(rho32, cs);
+            s.finalize_launch(rho32, cs, h.lmin_leaf);
         };
         rc = iterate_trees(s, S, tr, [&](int k, int m) {
             int q = AFMG_OK;
@@ -757,6 +768,7 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
         });
     }
     if (rc != AFMG_OK) return rc;
+    if (any) s.restrict_parents();
     if (t->forest) launch_store_boxes<D, BOX_N, double>(t->d_box_map, uw, u, h.n_boxes, st);
     else launch_permute<D, BOX_N, double>(t->d_info, u, 0, h.n_boxes, 0, 0, st);
     (void)hipEventRecord(ev1, st);

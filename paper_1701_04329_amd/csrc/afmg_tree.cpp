@@ -197,9 +197,11 @@ int build_tree(int dim, int N, int n_trees, const int64_t *tree_off, const int32
         }
     }
     t.uniform = true;
+    t.lmin_leaf = t.lmax;
     for (int64_t m = 0; m < nb; m++) {
         BoxInfo &bi = t.info[(size_t)m];
         if ((bi.flags & FLAG_LEAF) && bi.level != t.tree_lmax[(size_t)bi.tree]) t.uniform = false;
+        if ((bi.flags & FLAG_LEAF) && bi.level < t.lmin_leaf) t.lmin_leaf = bi.level;
         for (int s = 0; s < 2 * dim; s++) {
             const int v = bi.nbr[s];
             if (v >= 0 && !(t.info[(size_t)v].flags & FLAG_LEAF)) bi.flags |= FLAG_NBR_REFINED << s;
