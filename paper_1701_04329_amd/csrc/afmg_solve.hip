@@ -381,8 +381,9 @@ struct Cycler {
     // FMG from a zero guess: restrict rho down, then per level store v',
     // correct from the coarser level and run a V-cycle from it.  In a forest
     // the step at level l involves only the trees that reach level l.
-    void fmg() {
-        launch_fill<T>(base.u, h.n_boxes * cells_per_box(D), T(0), st);
+    // zero_u = false: u is zero already.
+    void fmg(bool zero_u = true) {
+        if (zero_u) launch_fill<T>(base.u, h.n_boxes * cells_per_box(D), T(0), st);
         for (int l = h.lmax; l >= 2; l--) level(Op::RESTRICT_RHO, l);
         coarse(COARSE_FMG);
         const int64_t C = cells_per_box(D);
@@ -718,7 +719,7 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
         if (o.cycle == AFMG_CYCLE_FMG_V) {
             rc = s.upload_mask();
             if (rc != AFMG_OK) return rc;
-            cy.fmg();
+            cy.fmg(guess);  // without a guess u was zeroed above and is still zero
             s.finalize_launch(nullptr, st, h.lmin_leaf);
             if ((rc = s.read_norms()) != AFMG_OK) return rc;
             take_norms(t, S, false);
