@@ -137,12 +137,13 @@ template <int D, int N, int W, typename T>
 __device__ __forceinline__ Slot<D, N> slot_of(const LevelArgs<T> &a) {
     return slot_of<D, N, W>(a.b0, a.nb, a.no_remap == 0);
 }
-// In a forest, the boxes of trees whose mask entry is 0 are read but never
-// written.  The test is made where a kernel first writes, so that it does not
-// delay the kernel's first loads.
-template <typename T>
+// Level kernels come in two variants: F = false for one tree (a.active is
+// null), whose loads start without waiting for anything but the arguments,
+// and F = true for forests, where the boxes of trees whose mask entry is 0
+// are neither read nor written (the mask test needs the box record first).
+template <bool F, typename T>
 __device__ __forceinline__ bool tree_active(const LevelArgs<T> &a, const BoxInfo &bi) {
-    return !a.active || a.active[bi.tree] != 0;
+    return !F || a.active[bi.tree] != 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -354,7 +355,7 @@ __device__ __forceinline__ T gs_finish(const T *s, T raw, int v, T own, int homo
     return T(0.5) * raw + T(1.25) * own - T(0.25) * ((u2 + u1p) + u1pp);
 }
 
-template <int D, int N, typename T, int W>
+template <int D, int N, typename T, int W, bool F>
 __global__ __launch_bounds__(W) void k_gsrb(LevelArgs<T> a, int colour) {
     using G = Geo<D, N>;
     constexpr int HN = G::HN;
@@ -377,9 +378,11 @@ __global__ __launch_bounds__(W) void k_gsrb(LevelArgs<T> a, int colour) {
         gy[m] = T(0);
         gz[m] = T(0);
     }
-    // the padding slots of the last workgroup load a valid box too (sl.b is
-    // clamped), so that no branch separates the loads from the kernel start
-    {
+    // one tree: the padding slots of the last workgroup load a valid box too
+    // (sl.b is clamped), so that no branch separates the loads from the
+    // kernel start
+    const bool act = sl.valid && tree_active<F>(a, bi);
+    if (!F || act) {
         T ot[HN];
         const int oth0 = (1 - colour) * G::HALF + r * HN;
 #pragma unroll
@@ -445,7 +448,7 @@ __global__ __launch_bounds__(W) void k_gsrb(LevelArgs<T> a, int colour) {
         for (int m = 0; m < HN; m++) s[m * G::TPB + r] = ot[m];
     }
     __syncthreads();
-    if (!sl.valid || !tree_active(a, bi)) return;
+    if (!act) return;
 #pragma unroll
     for (int m = 0; m < HN; m++) {
         const int i = 2 * m + p;
@@ -500,7 +503,7 @@ __device__ __forceinline__ void restrict_octant(const T *s, T *__restrict__ dst,
 // Boxes of level l: r = rho - L u; the parent's octant receives mean(u) in u
 // and mean(r) in rho (the restricted residual, turned into the FAS
 // right-hand side by k_coarse_rhs).
-template <int D, int N, typename T, int W>
+template <int D, int N, typename T, int W, bool F>
 __global__ __launch_bounds__(W) void k_resid_restrict(LevelArgs<T> a) {
     using G = Geo<D, N>;
     __shared__ T sm[(W / G::TPB) * G::PC];
@@ -513,21 +516,24 @@ __global__ __launch_bounds__(W) void k_resid_restrict(LevelArgs<T> a) {
     constexpr int NPC = G::HC / G::TPB, NB = D == 3 ? 8 : 4;
     T rf[NPC][NB];
     Stager<D, N, T> st;
-    // padding slots (sl.b clamped to a valid box) load too: no branch before
-    // the loads
+    // one tree: padding slots (sl.b clamped to a valid box) load too, no
+    // branch before the loads
+    const bool act = sl.valid && tree_active<F>(a, bi);
+    if (!F || act) {
 #pragma unroll
-    for (int it = 0; it < NPC; it++)
+        for (int it = 0; it < NPC; it++)
 #pragma unroll
-        for (int q = 0; q < NB; q++) {
-            int i, j, k;
-            block_cell<D, N>(sl.t + it * G::TPB, q, i, j, k);
-            rf[it][q] = a.rho[bo + cpos<D, N>(i, j, k)];
-        }
-    st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, true);
+            for (int q = 0; q < NB; q++) {
+                int i, j, k;
+                block_cell<D, N>(sl.t + it * G::TPB, q, i, j, k);
+                rf[it][q] = a.rho[bo + cpos<D, N>(i, j, k)];
+            }
+        st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, true);
+    }
     __syncthreads();
-    if (sl.valid) st.end(s, sl.t);
+    if (act) st.end(s, sl.t);
     __syncthreads();
-    if (!sl.valid || !tree_active(a, bi)) return;
+    if (!act) return;
     const T w = D == 3 ? T(0.125) : T(0.25);
     const int flags = bi.flags;
     const int64_t p = bi.parent;
@@ -557,7 +563,7 @@ __global__ __launch_bounds__(W) void k_resid_restrict(LevelArgs<T> a) {
 // ---------------------------------------------------------------------------
 // Boxes of level l-1: uold <- u; on parents rho <- rbar + L_H u (rho holds
 // rbar, the restricted residual).
-template <int D, int N, typename T, int W>
+template <int D, int N, typename T, int W, bool F>
 __global__ __launch_bounds__(W) void k_coarse_rhs(LevelArgs<T> a) {
     using G = Geo<D, N>;
     __shared__ T sm[(W / G::TPB) * G::PC];
@@ -569,16 +575,18 @@ __global__ __launch_bounds__(W) void k_coarse_rhs(LevelArgs<T> a) {
     constexpr int NE = G::C / G::TPB;  // cells per thread
     T rf[NE];
     Stager<D, N, T> st;
-    // rows first (padding slots load a valid box too), then what depends on
-    // the box record: ghosts and rbar of parents
-    st.load(bi, a.u + bo, a.u, a.bc, a.homog, sl.t, parent);
-    if (parent) {
+    // rows first (one tree: padding slots load a valid box too), then what
+    // depends on the box record: ghosts and rbar of parents
+    const bool act = sl.valid && tree_active<F>(a, bi);
+    if (!F || act) {
+        st.load(bi, a.u + bo, a.u, a.bc, a.homog, sl.t, parent);
+        if (parent) {
 #pragma unroll
-        for (int it = 0; it < NE; it++) rf[it] = a.rho[bo + sl.t + it * G::TPB];
+            for (int it = 0; it < NE; it++) rf[it] = a.rho[bo + sl.t + it * G::TPB];
+        }
+        st.stage(s, sl.t);
     }
-    st.stage(s, sl.t);
     __syncthreads();
-    const bool act = sl.valid && tree_active(a, bi);
     if (act) {
         // the copy v' from the staged interior
         for (int e = sl.t; e < G::C; e += G::TPB) {
@@ -587,7 +595,7 @@ __global__ __launch_bounds__(W) void k_coarse_rhs(LevelArgs<T> a) {
             a.uold[bo + e] = s[padi<D, N>(i, j, k)];
         }
     }
-    if (sl.valid && parent) st.end(s, sl.t);
+    if (act && parent) st.end(s, sl.t);
     __syncthreads();
     if (!act || !parent) return;
 #pragma unroll
@@ -689,7 +697,7 @@ __device__ __forceinline__ void halo_phase2(T *q, int m, const int o[3], T raw, 
     q[qpad<D, N>(L[0], L[1], L[2])] = val;
 }
 
-template <int D, int N, typename T, int W>
+template <int D, int N, typename T, int W, bool F>
 __global__ __launch_bounds__(W) void k_prolong(LevelArgs<T> a) {
     using G = Geo<D, N>;
     constexpr int NH = (2 * D * G::HF + G::TPB - 1) / G::TPB;  // halo cells per thread
@@ -700,15 +708,19 @@ __global__ __launch_bounds__(W) void k_prolong(LevelArgs<T> a) {
     T *q = qs + sl.slot * G::QC;
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
-    const int flags = bi.flags;
-    const int o[3] = {obit(flags, 0) * G::H, obit(flags, 1) * G::H, D == 3 ? obit(flags, 2) * G::H : 0};
     T raw[NH], uf[NE];
     int hv[NH];
     // the fine values (needed only after the barriers) first: they need no
-    // box record; padding slots (sl.b clamped to a valid box) load too
+    // box record; one tree: padding slots (sl.b clamped to a valid box) load
+    // too
+    const bool act = sl.valid && tree_active<F>(a, bi);
+    if (!F || act) {
 #pragma unroll
-    for (int it = 0; it < NE; it++) uf[it] = a.u[bo + sl.t + it * G::TPB];
-    {
+        for (int it = 0; it < NE; it++) uf[it] = a.u[bo + sl.t + it * G::TPB];
+    }
+    const int flags = bi.flags;
+    const int o[3] = {obit(flags, 0) * G::H, obit(flags, 1) * G::H, D == 3 ? obit(flags, 2) * G::H : 0};
+    if (!F || act) {
         const int64_t p = bi.parent;
         const BoxInfo pi = load_box<D, N>(a.info, p);
         // every global operand (octant, halo) before the LDS stores
@@ -746,7 +758,7 @@ __global__ __launch_bounds__(W) void k_prolong(LevelArgs<T> a) {
             if (sl.t + h * G::TPB < 2 * D * G::HF && hv[h] >= 0) q[hs[h]] = raw[h];
     }
     __syncthreads();
-    if (sl.valid) {
+    if (act) {
 #pragma unroll
         for (int h = 0; h < NH; h++) {
             const int hc = sl.t + h * G::TPB;
@@ -759,7 +771,7 @@ __global__ __launch_bounds__(W) void k_prolong(LevelArgs<T> a) {
         }
     }
     __syncthreads();
-    if (!sl.valid || !tree_active(a, bi)) return;
+    if (!act) return;
 #pragma unroll
     for (int it = 0; it < NE; it++) {
         const int e = sl.t + it * G::TPB;
@@ -788,7 +800,7 @@ __global__ __launch_bounds__(W) void k_prolong(LevelArgs<T> a) {
 // leaf box at partial[box].  With rout set, the leaf residual is also stored
 // there rounded to FP32: the right-hand side of the correction solve of the
 // mixed-precision refinement.
-template <int D, int N, typename T, int W>
+template <int D, int N, typename T, int W, bool F>
 __global__ __launch_bounds__(W) void k_final(LevelArgs<T> a, double *partial, int64_t part0, double hD,
                                              float *__restrict__ rout) {
     using G = Geo<D, N>;
@@ -803,27 +815,29 @@ __global__ __launch_bounds__(W) void k_final(LevelArgs<T> a, double *partial, in
     constexpr int NPC = G::HC / G::TPB, NB = D == 3 ? 8 : 4;
     T rf[NPC][NB];
     Stager<D, N, T> st;
-    // rows first (padding slots load a valid box too), then what depends on
-    // the box record: ghosts and rho of leaves
-    st.load(bi, a.u + bo, a.u, a.bc, a.homog, sl.t, leaf);
-    if (leaf) {
+    // rows first (one tree: padding slots load a valid box too), then what
+    // depends on the box record: ghosts and rho of leaves
+    const bool act = sl.valid && tree_active<F>(a, bi);
+    if (!F || act) {
+        st.load(bi, a.u + bo, a.u, a.bc, a.homog, sl.t, leaf);
+        if (leaf) {
 #pragma unroll
-        for (int it = 0; it < NPC; it++)
+            for (int it = 0; it < NPC; it++)
 #pragma unroll
-            for (int q = 0; q < NB; q++) {
-                int i, j, k;
-                block_cell<D, N>(sl.t + it * G::TPB, q, i, j, k);
-                rf[it][q] = a.rho[bo + cpos<D, N>(i, j, k)];
-            }
+                for (int q = 0; q < NB; q++) {
+                    int i, j, k;
+                    block_cell<D, N>(sl.t + it * G::TPB, q, i, j, k);
+                    rf[it][q] = a.rho[bo + cpos<D, N>(i, j, k)];
+                }
+        }
+        st.stage(s, sl.t);
     }
-    st.stage(s, sl.t);
     __syncthreads();
-    if (sl.valid && leaf) st.end(s, sl.t);
+    if (act && leaf) st.end(s, sl.t);
     __syncthreads();
     // each thread: 2^D blocks of cells = parent cells; the block mean of u
     // goes to the parent, the residuals of leaves stay in registers
     double mx = 0.0, ss = 0.0;
-    const bool act = sl.valid && tree_active(a, bi);
     if (act) {
         const T w = D == 3 ? T(0.125) : T(0.25);
         const int flags = bi.flags;
@@ -999,7 +1013,7 @@ __global__ __launch_bounds__(256) void k_restrict_rho(LevelArgs<T> a) {
         }
     }
     __syncthreads();
-    if (sl.valid && tree_active(a, bi)) restrict_octant<D, N, T, false>(s, a.rho, bi, sl.t);
+    if (sl.valid && (!a.active || a.active[bi.tree] != 0)) restrict_octant<D, N, T, false>(s, a.rho, bi, sl.t);
 }
 
 // In-place conversion of whole boxes between the caller's order (x fastest)
@@ -1998,16 +2012,21 @@ static inline int wg_count(int64_t nb) {
         if ((grid) > 0) hipLaunchKernelGGL(kernel, dim3(grid), dim3(W), 0, stream, __VA_ARGS__); \
     } while (0)
 
-template <int D, int N, typename T, int W>
-static void launch_level_w(Op op, const LevelArgs<T> &a, int colour, hipStream_t st) {
+template <int D, int N, typename T, int W, bool F>
+static void launch_level_wf(Op op, const LevelArgs<T> &a, int colour, hipStream_t st) {
     const int g = wg_count<D, N, W>(a.nb);
     switch (op) {
-    case Op::GSRB: AFMG_LAUNCH_W((k_gsrb<D, N, T, W>), g, W, st, a, colour); break;
-    case Op::RESID_RESTRICT: AFMG_LAUNCH_W((k_resid_restrict<D, N, T, W>), g, W, st, a); break;
-    case Op::COARSE_RHS: AFMG_LAUNCH_W((k_coarse_rhs<D, N, T, W>), g, W, st, a); break;
-    case Op::PROLONG: AFMG_LAUNCH_W((k_prolong<D, N, T, W>), g, W, st, a); break;
+    case Op::GSRB: AFMG_LAUNCH_W((k_gsrb<D, N, T, W, F>), g, W, st, a, colour); break;
+    case Op::RESID_RESTRICT: AFMG_LAUNCH_W((k_resid_restrict<D, N, T, W, F>), g, W, st, a); break;
+    case Op::COARSE_RHS: AFMG_LAUNCH_W((k_coarse_rhs<D, N, T, W, F>), g, W, st, a); break;
+    case Op::PROLONG: AFMG_LAUNCH_W((k_prolong<D, N, T, W, F>), g, W, st, a); break;
     case Op::RESTRICT_RHO: AFMG_LAUNCH((k_restrict_rho<D, N, T>), (wg_count<D, N, 256>(a.nb)), st, a); break;
     }
+}
+template <int D, int N, typename T, int W>
+static void launch_level_w(Op op, const LevelArgs<T> &a, int colour, hipStream_t st) {
+    if (a.active) launch_level_wf<D, N, T, W, true>(op, a, colour, st);
+    else launch_level_wf<D, N, T, W, false>(op, a, colour, st);
 }
 
 template <int D, int N, typename T>
@@ -2021,7 +2040,8 @@ template <int D, int N, typename T, int W>
 static void launch_final_w(const LevelArgs<T> &a, double *partial, int64_t part0, double hD, float *rout,
                            hipStream_t st) {
     const int g = wg_count<D, N, W>(a.nb);
-    AFMG_LAUNCH_W((k_final<D, N, T, W>), g, W, st, a, partial, part0, hD, rout);
+    if (a.active) AFMG_LAUNCH_W((k_final<D, N, T, W, true>), g, W, st, a, partial, part0, hD, rout);
+    else AFMG_LAUNCH_W((k_final<D, N, T, W, false>), g, W, st, a, partial, part0, hD, rout);
 }
 
 template <int D, int N, typename T>
