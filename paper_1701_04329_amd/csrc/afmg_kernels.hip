@@ -1147,6 +1147,8 @@ __global__ __launch_bounds__(256) void k_bc_derive(const BoxInfo *__restrict__ i
 // The grid index G (0: N cells per side) is a template parameter, so every
 // index is a compile-time shift; the side ghosts 2 b - u1 (paper §2.4) are
 // formed inline, with the same arithmetic a stored ghost layer would hold.
+constexpr int COARSE_NT = 512;  // threads of the coarse kernel
+
 template <int D, int N>
 struct CoarseGeo {
     static constexpr int lg(int n) { return n <= 1 ? 0 : 1 + lg(n / 2); }
@@ -1204,18 +1206,47 @@ struct CoarseState {
     template <int G>
     __device__ static constexpr double hgrid() { return (double)(1 << G) / (double)N; }
 
+    // Grid 0 (the root box) runs on the whole workgroup, the grids below it
+    // (at most N^D / 2^D cells) on its first wave alone, where a phase ends
+    // with a wave-scope fence instead of a workgroup barrier.  Every thread
+    // computes all of its values before it stores the first.
+    template <int G>
+    static constexpr int nth() { return G == 0 ? COARSE_NT : 64; }
+    template <int G>
+    __device__ __forceinline__ static void sync() {
+        if (G == 0) {
+            __syncthreads();
+        } else {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+    template <int G, int X>
+    static constexpr int rounds() { return (X + nth<G>() - 1) / nth<G>(); }
+
     // one colour of grid G
     template <int G>
     __device__ __forceinline__ void half(int colour) const {
-        constexpr int n = CG::n(G), hn = n / 2, o = CG::off(G);
+        constexpr int n = CG::n(G), hn = n / 2, o = CG::off(G), NQ = CG::cells(G) / 2, IT = rounds<G, NQ>();
         constexpr double h = hgrid<G>(), h2 = h * h;
-        for (int q = threadIdx.x; q < CG::cells(G) / 2; q += blockDim.x) {
-            const int r = q / hn, j = r % n, k = D == 3 ? r / n : 0;
-            const int i = 2 * (q % hn) + ((colour + j + k + D) & 1);
-            const int c = i + n * (j + n * k);
-            u[o + c] = (nbs<G>(u, i, j, k) - h2 * rho[o + c]) / double(2 * D);
+        double v[IT];
+        int cc[IT];
+#pragma unroll
+        for (int it = 0; it < IT; it++) {
+            const int q = (int)threadIdx.x + it * nth<G>();
+            cc[it] = -1;
+            if (q < NQ) {
+                const int r = q / hn, j = r % n, k = D == 3 ? r / n : 0;
+                const int i = 2 * (q % hn) + ((colour + j + k + D) & 1);
+                cc[it] = i + n * (j + n * k);
+                v[it] = (nbs<G>(u, i, j, k) - h2 * rho[o + cc[it]]) / double(2 * D);
+            }
         }
-        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < IT; it++)
+            if (cc[it] >= 0) u[o + cc[it]] = v[it];
+        sync<G>();
     }
     template <int G>
     __device__ __forceinline__ void gsrb(int nsweep) const {
@@ -1228,9 +1259,14 @@ struct CoarseState {
     template <int G>
     __device__ __forceinline__ void resid_restrict() const {
         constexpr int n = CG::n(G), nc = CG::n(G + 1), o = CG::off(G), oc = CG::off(G + 1);
+        constexpr int NC = CG::cells(G + 1), IT = rounds<G, NC>();
         constexpr double h = hgrid<G>(), ih2 = 1.0 / (h * h);
         const double w = D == 3 ? 0.125 : 0.25;
-        for (int C = threadIdx.x; C < CG::cells(G + 1); C += blockDim.x) {
+        double mu[IT], mr[IT];
+#pragma unroll
+        for (int it = 0; it < IT; it++) {
+            const int C = (int)threadIdx.x + it * nth<G>();
+            if (C >= NC) continue;
             const int I = C % nc, J = (C / nc) % nc, K = D == 3 ? C / (nc * nc) : 0;
             double au = 0.0, ar = 0.0;
             for (int dk = 0; dk < (D == 3 ? 2 : 1); dk++)
@@ -1241,39 +1277,67 @@ struct CoarseState {
                         au += u[o + c];
                         ar += rho[o + c] - (nbs<G>(u, i, j, k) - double(2 * D) * u[o + c]) * ih2;
                     }
-            u[oc + C] = w * au;
-            res[oc + C] = w * ar;
+            mu[it] = w * au;
+            mr[it] = w * ar;
         }
-        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < IT; it++) {
+            const int C = (int)threadIdx.x + it * nth<G>();
+            if (C >= NC) continue;
+            u[oc + C] = mu[it];
+            res[oc + C] = mr[it];
+        }
+        sync<G>();
     }
     // rho of grid G (FMG) -> grid G+1
     template <int G>
     __device__ __forceinline__ void restrict_rho() const {
         constexpr int n = CG::n(G), nc = CG::n(G + 1), o = CG::off(G), oc = CG::off(G + 1);
+        constexpr int NC = CG::cells(G + 1), IT = rounds<G, NC>();
         const double w = D == 3 ? 0.125 : 0.25;
-        for (int C = threadIdx.x; C < CG::cells(G + 1); C += blockDim.x) {
+        double m[IT];
+#pragma unroll
+        for (int it = 0; it < IT; it++) {
+            const int C = (int)threadIdx.x + it * nth<G>();
+            if (C >= NC) continue;
             const int I = C % nc, J = (C / nc) % nc, K = D == 3 ? C / (nc * nc) : 0;
             double acc = 0.0;
             for (int dk = 0; dk < (D == 3 ? 2 : 1); dk++)
                 for (int dj = 0; dj < 2; dj++)
                     for (int di = 0; di < 2; di++)
                         acc += rho[o + (2 * I + di) + n * ((2 * J + dj) + n * (D == 3 ? 2 * K + dk : 0))];
-            rho[oc + C] = w * acc;
+            m[it] = w * acc;
         }
-        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < IT; it++) {
+            const int C = (int)threadIdx.x + it * nth<G>();
+            if (C < NC) rho[oc + C] = m[it];
+        }
+        sync<G>();
     }
     // copy v' of grid G, and the FAS right-hand side rho <- rbar + L u
     template <int G>
     __device__ __forceinline__ void uold_crhs() const {
-        constexpr int o = CG::off(G);
+        constexpr int o = CG::off(G), NC = CG::cells(G), IT = rounds<G, NC>();
         constexpr double h = hgrid<G>(), ih2 = 1.0 / (h * h);
-        for (int c = threadIdx.x; c < CG::cells(G); c += blockDim.x) {
+        double uc[IT], rc[IT];
+#pragma unroll
+        for (int it = 0; it < IT; it++) {
+            const int c = (int)threadIdx.x + it * nth<G>();
+            if (c >= NC) continue;
             int i, j, k;
             ijk<G>(c, i, j, k);
-            uold[o + c] = u[o + c];
-            rho[o + c] = res[o + c] + (nbs<G>(u, i, j, k) - double(2 * D) * u[o + c]) * ih2;
+            uc[it] = u[o + c];
+            rc[it] = res[o + c] + (nbs<G>(u, i, j, k) - double(2 * D) * u[o + c]) * ih2;
         }
-        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < IT; it++) {
+            const int c = (int)threadIdx.x + it * nth<G>();
+            if (c >= NC) continue;
+            uold[o + c] = uc[it];
+            rho[o + c] = rc[it];
+        }
+        sync<G>();
     }
     // u - v' on grid G at (I, J, K) + s e_axis; outside the grid the ghost of
     // u minus the ghost of v' (the Dirichlet value cancels up to rounding)
@@ -1294,8 +1358,12 @@ struct CoarseState {
     // first receives u (FMG)
     template <int G>
     __device__ __forceinline__ void prolong(bool store_old) const {
-        constexpr int o = CG::off(G);
-        for (int c = threadIdx.x; c < CG::cells(G); c += blockDim.x) {
+        constexpr int o = CG::off(G), NC = CG::cells(G), IT = rounds<G, NC>();
+        double uc[IT], nv[IT];
+#pragma unroll
+        for (int it = 0; it < IT; it++) {
+            const int c = (int)threadIdx.x + it * nth<G>();
+            if (c >= NC) continue;
             int i, j, k;
             ijk<G>(c, i, j, k);
             const int I = i >> 1, J = j >> 1, K = k >> 1;
@@ -1308,10 +1376,17 @@ struct CoarseState {
                 v = 0.25 * (((delta<G + 1>(0, I, J, K, 0) + delta<G + 1>(0, I, J, K, sx)) +
                              delta<G + 1>(1, I, J, K, sy)) +
                             delta<G + 1>(2, I, J, K, sz));
-            if (store_old) uold[o + c] = u[o + c];
-            u[o + c] = u[o + c] + v;
+            uc[it] = u[o + c];
+            nv[it] = uc[it] + v;
         }
-        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < IT; it++) {
+            const int c = (int)threadIdx.x + it * nth<G>();
+            if (c >= NC) continue;
+            if (store_old) uold[o + c] = uc[it];
+            u[o + c] = nv[it];
+        }
+        sync<G>();
     }
     // FAS V-cycle from grid G (paper §3.2)
     template <int G>
@@ -1321,8 +1396,11 @@ struct CoarseState {
         } else {
             gsrb<G>(n_down);
             resid_restrict<G>();
-            uold_crhs<G + 1>();
-            vcycle<G + 1>();
+            if (G > 0 || threadIdx.x < nth<G + 1>()) {
+                uold_crhs<G + 1>();
+                vcycle<G + 1>();
+            }
+            if (G == 0) __syncthreads();
             prolong<G>(false);
             gsrb<G>(n_up);
         }
@@ -1333,38 +1411,43 @@ struct CoarseState {
     __device__ __forceinline__ void fmg() const {
         if constexpr (G < CG::NG - 1) {
             restrict_rho<G>();
-            fmg<G + 1>();
+            if (G > 0 || threadIdx.x < nth<G + 1>()) fmg<G + 1>();
+            if (G == 0) __syncthreads();
             prolong<G>(true);
         } else {
-            for (int c = threadIdx.x; c < CG::cells(G); c += blockDim.x)
-                uold[CG::off(G) + c] = u[CG::off(G) + c];
-            __syncthreads();
+            for (int c = threadIdx.x; c < CG::cells(G); c += nth<G>()) uold[CG::off(G) + c] = u[CG::off(G) + c];
+            sync<G>();
         }
         vcycle<G>();
     }
 };
 
 // Level 2 of a tree inside the coarse kernel: the 2^D boxes under the root
-// form one (2N)^D grid in LDS (natural order, x fastest) in the precision T
+// form one (2N)^D grid in LDS (natural order, x fastest, with a ghost layer
+// that holds the Dirichlet ghosts of the current values) in the precision T
 // of the level kernels.  Every step uses the formulas and summation orders of
 // the box kernels (k_gsrb, k_resid_restrict, k_coarse_rhs, k_prolong): level 2
 // is complete (all children of the root exist), so its ghosts are grid cells
 // or Dirichlet ghosts 2 b - u1 (b = 0 when homogeneous), and the deltas of
 // the root seen from level 2 have the ghost -delta(face cell) outside the
 // domain (paper §2.4, §2.5, §3.1, §3.2).
-constexpr int COARSE_NT = 512;  // threads of the coarse kernel
-
 template <int D, int N, typename T>
 struct Level2 {
     static constexpr int M = 2 * N;                          // cells per axis
     static constexpr int CELLS = D == 3 ? M * M * M : M * M;
     static constexpr int F = D == 3 ? M * M : M;             // cells per side
-    T *u, *rho;    // grid values and right-hand side
+    static constexpr int P = M + 2;                          // padded axis
+    static constexpr int PCELLS = D == 3 ? P * P * P : P * P;
+    T *u;          // grid values with a ghost layer (padded, natural order)
+    T *rho;        // right-hand side (unpadded)
     const T *bc;   // [2D][F] Dirichlet values (zero when homogeneous)
     T h2, ih2;
     int parents;   // bit o: the box of octant o is a parent
 
     __device__ __forceinline__ static int at(int i, int j, int k) { return D == 3 ? i + M * (j + M * k) : i + M * j; }
+    __device__ __forceinline__ static int pad(int i, int j, int k) {
+        return D == 3 ? (i + 1) + P * ((j + 1) + P * (k + 1)) : (i + 1) + P * (j + 1);
+    }
     __device__ __forceinline__ static int octant(int i, int j, int k) {
         return (i >= N ? 1 : 0) | (j >= N ? 2 : 0) | (D == 3 && k >= N ? 4 : 0);
     }
@@ -1381,20 +1464,39 @@ struct Level2 {
         const int m = d == 0 ? j + M * k : d == 1 ? i + M * k : i + M * j;
         return bc[s * F + m];
     }
+    // cell (i, j, k) takes the value v; on the domain boundary its ghosts
+    // 2 b - v follow (each ghost slot belongs to one cell, so the slots hold
+    // the ghost of the cell's current value)
+    __device__ __forceinline__ void set(int i, int j, int k, T v) const {
+        u[pad(i, j, k)] = v;
+        if (i == 0) u[pad(-1, j, k)] = T(2) * bval(0, i, j, k) - v;
+        if (i == M - 1) u[pad(M, j, k)] = T(2) * bval(1, i, j, k) - v;
+        if (j == 0) u[pad(i, -1, k)] = T(2) * bval(2, i, j, k) - v;
+        if (j == M - 1) u[pad(i, M, k)] = T(2) * bval(3, i, j, k) - v;
+        if (D == 3 && k == 0) u[pad(i, j, -1)] = T(2) * bval(4, i, j, k) - v;
+        if (D == 3 && k == M - 1) u[pad(i, j, M)] = T(2) * bval(5, i, j, k) - v;
+    }
+    __device__ __forceinline__ T val(int i, int j, int k) const { return u[pad(i, j, k)]; }
+    // every ghost slot from the current values (after staging)
+    __device__ __forceinline__ void ghosts() const {
+        for (int g = threadIdx.x; g < 2 * D * F; g += blockDim.x) {
+            const int side = g / F, m = g % F, d = side >> 1, hi = side & 1;
+            const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+            int x[3];
+            x[t1] = m % M;
+            x[t2] = D == 3 ? m / M : 0;
+            x[d] = hi ? M - 1 : 0;
+            int y[3] = {x[0], x[1], x[2]};
+            y[d] = hi ? M : -1;
+            u[pad(y[0], y[1], y[2])] = T(2) * bc[g] - u[pad(x[0], x[1], x[2])];
+        }
+        __syncthreads();
+    }
     // neighbour sum of the stencil, ghosts included
     __device__ __forceinline__ T nb_sum(int i, int j, int k) const {
-        const int c = at(i, j, k);
-        const T uc = u[c];
-        const T xm = i > 0 ? u[c - 1] : T(2) * bval(0, i, j, k) - uc;
-        const T xp = i < M - 1 ? u[c + 1] : T(2) * bval(1, i, j, k) - uc;
-        const T ym = j > 0 ? u[c - M] : T(2) * bval(2, i, j, k) - uc;
-        const T yp = j < M - 1 ? u[c + M] : T(2) * bval(3, i, j, k) - uc;
-        T sum = (xm + xp) + (ym + yp);
-        if (D == 3) {
-            const T zm = k > 0 ? u[c - M * M] : T(2) * bval(4, i, j, k) - uc;
-            const T zp = k < M - 1 ? u[c + M * M] : T(2) * bval(5, i, j, k) - uc;
-            sum = sum + (zm + zp);
-        }
+        const int c = pad(i, j, k);
+        T sum = (u[c - 1] + u[c + 1]) + (u[c - P] + u[c + P]);
+        if (D == 3) sum = sum + (u[c - P * P] + u[c + P * P]);
         return sum;
     }
     // one red (0) or black (1) half sweep; every new value of the thread is
@@ -1403,21 +1505,24 @@ struct Level2 {
     __device__ __forceinline__ void half(int colour) const {
         constexpr int hm = M / 2, NQ = CELLS / 2, IT = (NQ + COARSE_NT - 1) / COARSE_NT;
         T res[IT];
-        int cc[IT];
 #pragma unroll
         for (int it = 0; it < IT; it++) {
             const int q = (int)threadIdx.x + it * COARSE_NT;
-            cc[it] = -1;
             if (q < NQ) {
                 const int r = q / hm, j = r % M, k = D == 3 ? r / M : 0;
                 const int i = 2 * (q % hm) + ((colour + j + k + D) & 1);
-                cc[it] = at(i, j, k);
-                res[it] = (nb_sum(i, j, k) - h2 * rho[cc[it]]) / T(2 * D);
+                res[it] = (nb_sum(i, j, k) - h2 * rho[at(i, j, k)]) / T(2 * D);
             }
         }
 #pragma unroll
-        for (int it = 0; it < IT; it++)
-            if (cc[it] >= 0) u[cc[it]] = res[it];
+        for (int it = 0; it < IT; it++) {
+            const int q = (int)threadIdx.x + it * COARSE_NT;
+            if (q < NQ) {
+                const int r = q / hm, j = r % M, k = D == 3 ? r / M : 0;
+                const int i = 2 * (q % hm) + ((colour + j + k + D) & 1);
+                set(i, j, k, res[it]);
+            }
+        }
         __syncthreads();
     }
     __device__ __forceinline__ void gsrb(int n) const {
@@ -1435,7 +1540,7 @@ struct Level2 {
             if (c < CELLS) {
                 int i, j, k;
                 ijk(c, i, j, k);
-                if ((parents >> octant(i, j, k)) & 1) rho[c] = rho[c] + (nb_sum(i, j, k) - T(2 * D) * u[c]) * ih2;
+                if ((parents >> octant(i, j, k)) & 1) rho[c] = rho[c] + (nb_sum(i, j, k) - T(2 * D) * val(i, j, k)) * ih2;
             }
         }
         __syncthreads();
@@ -1450,10 +1555,9 @@ struct Level2 {
 #pragma unroll
         for (int q = 0; q < NB; q++) {
             const int i = 2 * I + (q & 1), j = 2 * J + ((q >> 1) & 1), k = D == 3 ? 2 * K + (q >> 2) : 0;
-            const int c = at(i, j, k);
-            const T uc = u[c];
+            const T uc = val(i, j, k);
             su += uc;
-            sr += rho[c] - (nb_sum(i, j, k) - T(2 * D) * uc) * ih2;
+            sr += rho[at(i, j, k)] - (nb_sum(i, j, k) - T(2 * D) * uc) * ih2;
         }
         mu = w * su;
         mr = w * sr;
@@ -1485,12 +1589,16 @@ struct Level2 {
                 const T dz = (K + sz >= 0 && K + sz < N) ? delta(fu, fo, I, J, K + sz) : -dP;
                 v = T(0.25) * (((dP + dx) + dy) + dz);
             }
-            res[it] = u[c] + v;
+            res[it] = val(i, j, k) + v;
         }
 #pragma unroll
         for (int it = 0; it < IT; it++) {
             const int c = (int)threadIdx.x + it * COARSE_NT;
-            if (c < CELLS) u[c] = res[it];
+            if (c < CELLS) {
+                int i, j, k;
+                ijk(c, i, j, k);
+                set(i, j, k, res[it]);
+            }
         }
         __syncthreads();
     }
@@ -1502,7 +1610,7 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(CoarseArgs<T> a) {
     using G = Geo<D, N>;
     using L2 = Level2<D, N, T>;
     __shared__ double f_u[CG::TOT], f_rho[CG::TOT], f_uold[CG::TOT], f_res[CG::TOT], f_bc[CG::BTOT];
-    __shared__ T l2_u[L2::CELLS], l2_rho[L2::CELLS], l2_bc[2 * D * L2::F];
+    __shared__ T l2_u[L2::PCELLS], l2_rho[L2::CELLS], l2_bc[2 * D * L2::F];
     CoarseState<D, N> st{f_u, f_rho, f_uold, f_res, f_bc, a.n_down, a.n_up, a.n_base};
     // one workgroup per tree; the roots are boxes 0 .. n_trees-1
     const int64_t root = blockIdx.x;
@@ -1576,13 +1684,14 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(CoarseArgs<T> a) {
             if (e >= C2) continue;
             int i, j, k;
             cell_of<D, N>(e % G::C, i, j, k);
-            const int c = L2::at(i + (o & 1) * N, j + ((o >> 1) & 1) * N, D == 3 ? k + ((o >> 2) & 1) * N : 0);
-            l2_u[c] = v2u[q];
-            l2_rho[c] = v2r[q];
+            const int gi = i + (o & 1) * N, gj = j + ((o >> 1) & 1) * N, gk = D == 3 ? k + ((o >> 2) & 1) * N : 0;
+            l2_u[L2::pad(gi, gj, gk)] = v2u[q];
+            l2_rho[L2::at(gi, gj, gk)] = v2r[q];
             // after a restriction from level 3: the copy v' of level 2
             if (mode == COARSE_V2_FROM_3) a.uold[(size_t)a.child[root * 8 + o] * G::C + e % G::C] = v2u[q];
         }
         __syncthreads();
+        lv2.ghosts();
         if (mode == COARSE_V2_FROM_3) lv2.crhs();
         lv2.gsrb(a.n_down);
         // residual and u restricted into the root: level 1 then starts as
@@ -1670,7 +1779,7 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(CoarseArgs<T> a) {
         const int o = e / G::C;
         int i, j, k;
         cell_of<D, N>(e % G::C, i, j, k);
-        const int c = L2::at(i + (o & 1) * N, j + ((o >> 1) & 1) * N, D == 3 ? k + ((o >> 2) & 1) * N : 0);
+        const int c = L2::pad(i + (o & 1) * N, j + ((o >> 1) & 1) * N, D == 3 ? k + ((o >> 2) & 1) * N : 0);
         a.u[(size_t)a.child[root * 8 + o] * G::C + e % G::C] = l2_u[c];
     }
 }
