@@ -24,6 +24,8 @@ struct LevelArgs {
     const int *active;  // forest: per-tree flag, boxes of trees at 0 are left
                         // untouched; null: every box is processed
     int no_remap;       // 1: workgroups take boxes in launch order (no XCD remap)
+    int xmask;          // complete level of one tree (every box present, box
+                        // index = Morton key): the x bits of the key, else 0
 };
 
 enum class Op { GSRB, RESID_RESTRICT, COARSE_RHS, PROLONG, RESTRICT_RHO };

@@ -109,6 +109,17 @@ int64_t cells_per_box(int dim) { return dim == 3 ? BOX_N * BOX_N * BOX_N : BOX_N
 int64_t cells_per_face(int dim) { return dim == 3 ? BOX_N * BOX_N : BOX_N; }
 double level_h(int l) { return 1.0 / ((double)BOX_N * std::ldexp(1.0, l - 1)); }
 
+// x bits of the Morton key of level l when the level is complete (one tree,
+// all 2^(D (l-1)) boxes present, so that box index = key); 0 otherwise
+int cube_xmask(const HostTree &h, int l) {
+    const int lg = l - 1;
+    if (h.n_trees != 1 || lg < 1 || h.dim * lg > 30) return 0;
+    if (h.level_count(l) != ((int64_t)1 << (h.dim * lg))) return 0;
+    int m = 0;
+    for (int b = 0; b < lg; b++) m |= 1 << (h.dim * b);
+    return m;
+}
+
 struct WsLayout {
     // FP64: rho, uold; mixed: rho (FP64 leaf rho), e, rho_e, uold_e (FP32);
     // forests also hold the working u
@@ -314,6 +325,7 @@ struct Cycler {
         LevelArgs<T> a = base;
         a.b0 = h.lvl_off[(size_t)l];
         a.nb = (int)h.level_count(l);
+        a.xmask = cube_xmask(h, l);
         const double hh = level_h(l);
         a.h2 = (T)(hh * hh);
         a.ih2 = (T)(1.0 / (hh * hh));
@@ -1018,6 +1030,7 @@ int step(afmg_tree *t, hipStream_t st, int op, int level, int colour, int homog,
     for (double *f : {u, rho, uold}) launch_permute<D, BOX_N, double>(t->d_info, f, 0, h.n_boxes, 1, 0, st);
     LevelArgs<double> a{t->d_info, u, rho, uold, bc_w, h.lvl_off[(size_t)level], (int)h.level_count(level),
                         homog, 0.0, 0.0, nullptr, 0};
+    a.xmask = cube_xmask(h, level);
     const double hh = level_h(level);
     a.h2 = hh * hh;
     a.ih2 = 1.0 / (hh * hh);
@@ -1074,6 +1087,7 @@ void tune_precision(afmg_tree *t, hipStream_t st, LevelArgs<T> base, double *par
             LevelArgs<T> a = base;
             a.b0 = h.lvl_off[(size_t)l];
             a.nb = (int)h.level_count(l);
+            a.xmask = cube_xmask(h, l);
             const double hh = level_h(l);
             a.h2 = (T)(hh * hh);
             a.ih2 = (T)(1.0 / (hh * hh));
