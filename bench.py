@@ -495,7 +495,7 @@ def main():
         "outer_iterations": int(np.median(cycles_m)),
         "final_residual_ratio": stm["r_max"] / stm["r0_max"],
         "rel_l2_vs_gpu_fp64": float(np.linalg.norm(umx - u64) / np.linalg.norm(u64)),
-        "dominant_kernel": "k_gsrb<3,8,float,W,false> (finest level, one half sweep)",
+        "dominant_kernel": "k_gsrb_cube<3,8,float,W> (finest level, one half sweep)",
         "dominant_achieved_GBs": round(6.0 * n_fine / (avg_m * 1e-3) / 1e9, 1) if prof_nm[0] else None,
         "dominant_avg_launch_ms": round(avg_m, 5),
     }

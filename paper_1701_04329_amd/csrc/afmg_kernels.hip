@@ -2252,11 +2252,14 @@ static void launch_level_wf(Op op, const LevelArgs<T> &a, int colour, hipStream_
     switch (op) {
     case Op::GSRB:
         // the complete-level variant pays off where the level fits the GPU in
-        // about one round of waves (latency-bound); on larger levels the
-        // post-barrier Dirichlet loads of its boundary boxes cost more than
-        // the shorter load chain saves (measured on 256^3: levels of 512 and
-        // 4096 boxes 4-10% faster, 32768 boxes 5% slower)
-        if (!F && a.xmask && (int64_t)a.nb * Geo<D, N>::TPB <= CUBE_MAX_THREADS)
+        // about one round of waves (latency-bound), and on every level in
+        // FP32 (3D), where a box's loads are half as long; on larger FP64
+        // levels the post-barrier Dirichlet loads of its boundary boxes cost
+        // more than the shorter load chain saves (measured on 256^3: levels
+        // of 512 and 4096 boxes 4-10% faster; 32768 boxes 5% slower in FP64,
+        // 15% faster in FP32)
+        if (!F && a.xmask &&
+            ((D == 3 && sizeof(T) == 4) || (int64_t)a.nb * Geo<D, N>::TPB <= CUBE_MAX_THREADS))
             AFMG_LAUNCH_W((k_gsrb_cube<D, N, T, W>), g, W, st, a, colour);
         else
             AFMG_LAUNCH_W((k_gsrb<D, N, T, W, F>), g, W, st, a, colour);

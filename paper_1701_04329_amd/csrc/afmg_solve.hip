@@ -1058,15 +1058,16 @@ int step(afmg_tree *t, hipStream_t st, int op, int level, int colour, int homog,
 // Every candidate shape of one kernel class on one level is timed on the
 // tree's own boxes (REPS launches between two events, best of two rounds);
 // the fastest wins, the default (256 threads, XCD runs) unless another is at
-// least 3% faster.  Arrays are zero-filled scratch: timing does not depend on
-// the values.
+// least 3% faster.  Half sweeps alternate the colours as in a smoothing
+// sweep (one colour repeated would find all its data in the caches).
+// Arrays are zero-filled scratch: timing does not depend on the values.
 constexpr int TUNE_REPS = 10;
 
 template <class Fn>
 float time_launches(hipStream_t st, hipEvent_t a, hipEvent_t b, Fn fn) {
-    fn();  // warm-up
+    fn(1);  // warm-up
     (void)hipEventRecord(a, st);
-    for (int r = 0; r < TUNE_REPS; r++) fn();
+    for (int r = 0; r < TUNE_REPS; r++) fn(r & 1);
     (void)hipEventRecord(b, st);
     (void)hipEventSynchronize(b);
     float ms = 0.f;
@@ -1094,14 +1095,14 @@ void tune_precision(afmg_tree *t, hipStream_t st, LevelArgs<T> base, double *par
             const Op op = kind == SK_GSRB ? Op::GSRB
                           : kind == SK_RESID ? Op::RESID_RESTRICT
                           : kind == SK_CRHS ? Op::COARSE_RHS : Op::PROLONG;
-            auto run = [&](const Shape &sh) {
+            auto run = [&](const Shape &sh, int colour) {
                 LevelArgs<T> b = a;
                 b.no_remap = sh.no_remap;
                 if (kind == SK_FINAL) {
                     const double hD = D == 3 ? hh * hh * hh : hh * hh;
                     launch_final<D, BOX_N, T>(b, partial, t->forest ? -1 : 0, hD, nullptr, sh.wg, st);
                 } else {
-                    launch_level<D, BOX_N, T>(op, b, 0, sh.wg, st);
+                    launch_level<D, BOX_N, T>(op, b, colour, sh.wg, st);
                 }
             };
             Shape best{};
@@ -1110,7 +1111,7 @@ void tune_precision(afmg_tree *t, hipStream_t st, LevelArgs<T> base, double *par
                 for (int wi = 0; wi < 3; wi++) {
                     for (int nr = 0; nr < 2; nr++) {
                         const Shape sh{SHAPE_WGS[wi], nr};
-                        const float ms = time_launches(st, e0, e1, [&] { run(sh); });
+                        const float ms = time_launches(st, e0, e1, [&](int c) { run(sh, c); });
                         const bool is_def = wi == 0 && nr == 0;
                         if (round == 0 && is_def) {
                             t_def = ms;
