@@ -63,7 +63,7 @@ template <int D, int N, typename T>
 void launch_final(const LevelArgs<T> &a, double *partial, int64_t part0, double hD, float *rout, int wg,
                   hipStream_t st);
 template <int D, int N>
-void launch_ir_update(const BoxInfo *info, double *u, const float *e, int64_t nb, const int *active,
+void launch_ir_update(const BoxInfo *info, double *u, float *e, int64_t nb, const int *active,
                       hipStream_t st);
 template <int D, int N>
 int final_wgs(int64_t nb, int wg);

@@ -1164,17 +1164,24 @@ __global__ __launch_bounds__(256) void k_permute(const BoxInfo *__restrict__ inf
     }
 }
 
-// Mixed-precision refinement: u += e on the leaf boxes (e in FP32).
+// Mixed-precision refinement: u += e on the leaf boxes (e in FP32), and e
+// of those boxes back to zero, the initial guess of the next correction
+// solve (its V-cycle writes every parent box's e by restriction before it
+// reads it, so only leaves need the zero).
 template <int D, int N>
 __global__ __launch_bounds__(256) void k_ir_update(const BoxInfo *__restrict__ info, double *__restrict__ u,
-                                                   const float *__restrict__ e, int nb, const int *active) {
+                                                   float *__restrict__ e, int nb, const int *active) {
     using G = Geo<D, N>;
     const Slot<D, N> sl = slot_of<D, N>(0, nb);
     if (!sl.valid) return;
     const BoxInfo bi = load_box<D, N>(info, sl.b);
     if (!(bi.flags & FLAG_LEAF) || (active && !active[bi.tree])) return;
     const size_t bo = (size_t)sl.b * G::C;
-    for (int c = sl.t; c < G::C; c += G::TPB) u[bo + c] = u[bo + c] + (double)e[bo + c];
+    for (int c = sl.t; c < G::C; c += G::TPB) {
+        const float ec = e[bo + c];
+        u[bo + c] = u[bo + c] + (double)ec;
+        e[bo + c] = 0.f;
+    }
 }
 
 // Copy of the caller's boxes (natural order) into the colour-split working
@@ -2300,7 +2307,7 @@ void launch_final(const LevelArgs<T> &a, double *partial, int64_t part0, double 
 }
 
 template <int D, int N>
-void launch_ir_update(const BoxInfo *info, double *u, const float *e, int64_t nb, const int *active,
+void launch_ir_update(const BoxInfo *info, double *u, float *e, int64_t nb, const int *active,
                       hipStream_t st) {
     const int g = wg_count<D, N>(nb);
     AFMG_LAUNCH((k_ir_update<D, N>), g, st, info, u, e, (int)nb, active);
@@ -2458,8 +2465,8 @@ AFMG_INST(2, 8, double)
 AFMG_INST(3, 8, double)
 AFMG_INST(2, 8, float)
 AFMG_INST(3, 8, float)
-template void launch_ir_update<2, 8>(const BoxInfo *, double *, const float *, int64_t, const int *, hipStream_t);
-template void launch_ir_update<3, 8>(const BoxInfo *, double *, const float *, int64_t, const int *, hipStream_t);
+template void launch_ir_update<2, 8>(const BoxInfo *, double *, float *, int64_t, const int *, hipStream_t);
+template void launch_ir_update<3, 8>(const BoxInfo *, double *, float *, int64_t, const int *, hipStream_t);
 template void launch_copy<float>(const float *, float *, int64_t, hipStream_t);
 template void launch_fill<float>(float *, int64_t, float, hipStream_t);
 template int final_wgs<2, 8>(int64_t, int);

@@ -750,19 +750,18 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
     } else {
         // FP32 V-cycles inside FP64 iterative refinement: solve L e = r with
         // homogeneous Dirichlet values in FP32 (coarsest grids in FP64),
-        // u += e on the leaves, new FP64 residual
+        // u += e on the leaves, new FP64 residual.  Each correction solve
+        // starts from e = 0: the first from this fill (or FMG's own), the
+        // others from the update, which clears e on the leaves it adds.
         LevelArgs<float> b32{t->d_info, e32, rho32, (float *)(ws + L.uold_e), nullptr, 0, 0, 1, 0.f, 0.f,
                              t->d_active};
         Cycler<D, float> cy{h, st, o, s.prof, b32, nullptr, t};
+        if (o.cycle != AFMG_CYCLE_FMG_V) launch_fill<float>(e32, h.n_boxes * C, 0.f, st);
         auto refine = [&](hipStream_t cs, bool first_fmg) {
             Cycler<D, float> c2 = cy;
             c2.st = cs;
-            if (first_fmg) {
-                c2.fmg();
-            } else {
-                launch_fill<float>(e32, h.n_boxes * C, 0.f, cs);
-                c2.vcycle(h.lmax);
-            }
+            if (first_fmg) c2.fmg();
+            else c2.vcycle(h.lmax);
             launch_ir_update<D, BOX_N>(t->d_info, uw, e32, h.n_boxes, t->d_active, cs);
             s.finalize_launch(rho32, cs, h.lmin_leaf);
         };
