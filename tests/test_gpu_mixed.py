@@ -90,3 +90,35 @@ def test_full_size_adaptive_fp64_and_mixed_against_oracle():
     assert s["status"] == 0 and s["r_max"] <= 1e-10 * s["r0_max"]
     assert err <= BOUND
     assert s["cycles"] <= so["cycles"] + 2
+
+
+@pytest.mark.parametrize("cycle", ["V", "FMG"])
+def test_mixed_solution_independent_of_workspace_contents(cycle):
+    """Every correction solve starts from e = 0 whatever the workspace held
+    before: the solve itself zeroes e before the first V-cycle (FMG zeroes it
+    on its own), and the refinement update clears e on the leaves it adds.
+    A workspace filled with NaN bytes, and one left by a previous solve of
+    other data, give bitwise the solution of a fresh zeroed workspace."""
+    from paper_1701_04329_amd import afmg as A
+    w = CASES["a3"]()
+    print(f"[case] mixed workspace reuse {cycle} leaves={w.n_leaves}", flush=True)
+    dev = torch.device("cuda", 0)
+    t = A.Tree(w.dim, w.level, w.idx)
+    rho = t.leaf_to_boxes(torch.tensor(w.rho, device=dev))
+    bc = t.bc_rows(torch.tensor(w.bc, device=dev))
+    nbytes = t.workspace_bytes(A.make_opts(cycle, 2, 2, 4, 1e-10, 100, 0, False, "mixed", False, False, 1))
+    results = []
+    for fill in ("zero", "nan", "reused"):
+        ws = torch.zeros(max(nbytes, 256), dtype=torch.uint8, device=dev)
+        if fill == "nan":
+            ws.fill_(0xFF)  # every FP32 and FP64 word a NaN
+        elif fill == "reused":
+            A.solve(t, 3.0 * rho + 1.0, bc, cycle=cycle, precision="mixed", tol=1e-10, workspace=ws)
+        u, st = A.solve(t, rho, bc, cycle=cycle, precision="mixed", tol=1e-10, workspace=ws)
+        torch.cuda.synchronize()
+        assert st["status"] == 0, (fill, st)
+        results.append((fill, u.clone(), st["cycles"]))
+    for fill, u, cycles in results[1:]:
+        print(f"{fill}: cycles {cycles} vs {results[0][2]}", flush=True)
+        assert cycles == results[0][2], fill
+        assert torch.equal(u, results[0][1]), fill
