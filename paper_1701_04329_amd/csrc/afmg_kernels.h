@@ -26,6 +26,12 @@ struct LevelArgs {
     int no_remap;       // 1: workgroups take boxes in launch order (no XCD remap)
     int xmask;          // complete level of one tree (every box present, box
                         // index = Morton key): the x bits of the key, else 0
+    // half sweeps of a mixed-precision correction on a complete level that
+    // holds every leaf of the one tree (xmask != 0), else null / 0:
+    double *add_to;     // last half sweep: instead of storing the new values,
+                        // add_to += u on every cell, u of the updated colour = 0
+    int own_zero;       // first half sweep after one with add_to: the old
+                        // values of the updated colour are taken as zero
 };
 
 enum class Op { GSRB, RESID_RESTRICT, COARSE_RHS, PROLONG, RESTRICT_RHO };

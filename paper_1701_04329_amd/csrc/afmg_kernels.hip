@@ -491,8 +491,20 @@ __global__ __launch_bounds__(W) void k_gsrb(LevelArgs<T> a, int colour) {
 // waiting for the box table.  Boxes on the domain boundary fetch their
 // Dirichlet values b and the old values u1 of their own cells after the
 // barrier (ghost 2 b - u1).  Same arithmetic and order as k_gsrb.
-template <int D, int N, typename T, int W>
+// Modes for a mixed-precision correction on a tree whose leaves all lie on
+// this level.  CUBE_ADD (its last half sweep): instead of storing the new
+// values, add e (the new values and the other colour's) to the FP64
+// solution a.add_to on every cell of the box, and set the updated colour of
+// e to zero: the refinement update u += e, bitwise as the separate update
+// kernel computes it.  The other colour keeps its values (neighbouring boxes
+// read them as ghosts during the launch).  CUBE_OWN_ZERO (the first half
+// sweep of the next correction): the old values of the updated colour are
+// taken as zero; they enter only through the Dirichlet ghost 2b - u1, so
+// that with the other colour zero this half sweep equals the one from e = 0.
+enum { CUBE_PLAIN = 0, CUBE_ADD = 1, CUBE_OWN_ZERO = 2 };
+template <int D, int N, typename T, int W, int MODE>
 __global__ __launch_bounds__(W) void k_gsrb_cube(LevelArgs<T> a, int colour) {
+    constexpr bool ADD = MODE == CUBE_ADD;
     using G = Geo<D, N>;
     constexpr int HN = G::HN;
     __shared__ T so[(W / G::TPB) * oblock<D, N>()];
@@ -501,6 +513,7 @@ __global__ __launch_bounds__(W) void k_gsrb_cube(LevelArgs<T> a, int colour) {
     // the branches of the neighbour computation
     __asm__ volatile("" ::"s"(a.u), "s"(a.rho), "s"(a.b0), "s"(a.nb), "s"(a.no_remap), "s"(a.xmask),
                      "s"(colour));
+    if (ADD) __asm__ volatile("" ::"s"(a.add_to));
     const Slot<D, N> sl = slot_of<D, N, W>(a);
     T *s = so + sl.slot * oblock<D, N>();
     T *ub = a.u + (size_t)sl.b * G::C;
@@ -540,6 +553,15 @@ __global__ __launch_bounds__(W) void k_gsrb_cube(LevelArgs<T> a, int colour) {
 #pragma unroll
         for (int m = 0; m < HN; m++) gz[m] = nr[m];
     }
+    double fo[HN], ft[HN];  // ADD: the FP64 solution on this row's cells of each colour
+    if (ADD) {
+        const double *fb = a.add_to + (size_t)sl.b * G::C;
+#pragma unroll
+        for (int m = 0; m < HN; m++) {
+            fo[m] = fb[own0 + m];
+            ft[m] = fb[oth0 + m];
+        }
+    }
 #pragma unroll
     for (int m = 0; m < HN; m++) s[m * G::TPB + r] = ot[m];
     __syncthreads();
@@ -555,8 +577,10 @@ __global__ __launch_bounds__(W) void k_gsrb_cube(LevelArgs<T> a, int colour) {
     }
     if (dx || dy || dz) {
         const BoxInfo bi = load_box<D, N>(a.info, sl.b);
+        if (MODE != CUBE_OWN_ZERO) {
 #pragma unroll
-        for (int m = 0; m < HN; m++) ow[m] = ub[own0 + m];
+            for (int m = 0; m < HN; m++) ow[m] = ub[own0 + m];
+        }
         if (!a.homog) {
             if (dx) bx = a.bc[(size_t)(p == 0 ? bi.bcoff[0] : bi.bcoff[1]) * G::F + r];
             if (dy) {
@@ -588,6 +612,21 @@ __global__ __launch_bounds__(W) void k_gsrb_cube(LevelArgs<T> a, int colour) {
             sum = sum + (zm_ + zp_);
         }
         rr[m] = (sum - a.h2 * rr[m]) / T(2 * D);
+    }
+    if (ADD) {
+        double *fb = a.add_to + (size_t)sl.b * G::C;
+#pragma unroll
+        for (int m = 0; m < HN; m++) {
+            fo[m] = fo[m] + (double)rr[m];
+            ft[m] = ft[m] + (double)ot[m];
+        }
+#pragma unroll
+        for (int m = 0; m < HN; m++) fb[own0 + m] = fo[m];
+#pragma unroll
+        for (int m = 0; m < HN; m++) fb[oth0 + m] = ft[m];
+#pragma unroll
+        for (int m = 0; m < HN; m++) ub[own0 + m] = T(0);
+        return;
     }
 #pragma unroll
     for (int m = 0; m < HN; m++) ub[own0 + m] = rr[m];
@@ -2265,9 +2304,15 @@ static void launch_level_wf(Op op, const LevelArgs<T> &a, int colour, hipStream_
         // more than the shorter load chain saves (measured on 256^3: levels
         // of 512 and 4096 boxes 4-10% faster; 32768 boxes 5% slower in FP64,
         // 15% faster in FP32)
-        if (!F && a.xmask &&
-            ((D == 3 && sizeof(T) == 4) || (int64_t)a.nb * Geo<D, N>::TPB <= CUBE_MAX_THREADS))
-            AFMG_LAUNCH_W((k_gsrb_cube<D, N, T, W>), g, W, st, a, colour);
+        // (the modes of a correction: the caller checked that the level is
+        // complete and holds every leaf of the one tree)
+        if (a.add_to)
+            AFMG_LAUNCH_W((k_gsrb_cube<D, N, T, W, CUBE_ADD>), g, W, st, a, colour);
+        else if (a.own_zero)
+            AFMG_LAUNCH_W((k_gsrb_cube<D, N, T, W, CUBE_OWN_ZERO>), g, W, st, a, colour);
+        else if (!F && a.xmask &&
+                 ((D == 3 && sizeof(T) == 4) || (int64_t)a.nb * Geo<D, N>::TPB <= CUBE_MAX_THREADS))
+            AFMG_LAUNCH_W((k_gsrb_cube<D, N, T, W, CUBE_PLAIN>), g, W, st, a, colour);
         else
             AFMG_LAUNCH_W((k_gsrb<D, N, T, W, F>), g, W, st, a, colour);
         break;

@@ -320,6 +320,19 @@ struct Cycler {
     LevelArgs<T> base;
     const double *bc64;  // Dirichlet rows for the coarse kernel (null when homogeneous)
     afmg_tree *t;        // forests: tree levels and the FMG step mask
+    // mixed-precision correction on a tree whose leaves all lie on level
+    // lmax (complete): the last half sweep of a V-cycle from lmax adds e to
+    // this FP64 solution and clears e (see fuses_update)
+    double *add_to = nullptr;
+    // set for a V-cycle that follows one with the fused update: its first
+    // half sweep on lmax takes the updated colour's old values as zero (the
+    // fused update cleared only the other colour of e)
+    bool zero_start = false;
+
+    // whether a V-cycle from level top ends with the fused update
+    bool fuses_update(int top) const {
+        return add_to != nullptr && top == h.lmax && top >= 3 && o.n_up > 0 && o.n_down > 0;
+    }
 
     LevelArgs<T> lev(int l) const {
         LevelArgs<T> a = base;
@@ -331,7 +344,7 @@ struct Cycler {
         a.ih2 = (T)(1.0 / (hh * hh));
         return a;
     }
-    void level(Op op, int l, int colour = 0, bool time = true) {
+    void level(Op op, int l, int colour = 0, bool time = true, double *add = nullptr, bool own_zero = false) {
         const int kind = !time ? -1
                          : op == Op::GSRB ? AFMG_PROF_GSRB
                          : op == Op::RESID_RESTRICT ? AFMG_PROF_RESID
@@ -344,16 +357,21 @@ struct Cycler {
         if (sk >= 0) sh = t->shapes[sizeof(T) == 4 ? 1 : 0][sk][(size_t)l];
         LevelArgs<T> a = lev(l);
         a.no_remap = sh.no_remap;
+        a.add_to = add;
+        a.own_zero = own_zero ? 1 : 0;
         prof.timed(kind, l, [&] { launch_level<D, BOX_N, T>(op, a, colour, sh.wg, st); }, st);
     }
-    // n sweeps; their 2n half sweeps are timed as one group
-    void gsrb(int l, int n) {
+    // n sweeps; their 2n half sweeps are timed as one group.  add: the last
+    // half sweep adds the level's values to this FP64 array and clears its
+    // colour; own_zero: the first half sweep takes its colour's old values
+    // as zero.
+    void gsrb(int l, int n, double *add = nullptr, bool own_zero = false) {
         prof.timed(
             AFMG_PROF_GSRB, l,
             [&] {
                 for (int q = 0; q < n; q++) {
-                    level(Op::GSRB, l, 0, false);
-                    level(Op::GSRB, l, 1, false);
+                    level(Op::GSRB, l, 0, false, nullptr, q == 0 && own_zero);
+                    level(Op::GSRB, l, 1, false, q == n - 1 ? add : nullptr);
                 }
             },
             st, 2 * n);
@@ -380,14 +398,14 @@ struct Cycler {
             return;
         }
         for (int l = top; l >= 3; l--) {
-            gsrb(l, o.n_down);
+            gsrb(l, o.n_down, nullptr, l == top && zero_start && fuses_update(top));
             level(Op::RESID_RESTRICT, l);
             if (l - 1 >= 3) level(Op::COARSE_RHS, l - 1);
         }
         coarse(top >= 3 ? COARSE_V2_FROM_3 : COARSE_V2_TOP);
         for (int l = 3; l <= top; l++) {
             level(Op::PROLONG, l);
-            gsrb(l, o.n_up);
+            gsrb(l, o.n_up, l == top && fuses_update(top) ? add_to : nullptr);
         }
     }
     // FMG from a zero guess: restrict rho down, then per level store v',
@@ -752,17 +770,27 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
         // homogeneous Dirichlet values in FP32 (coarsest grids in FP64),
         // u += e on the leaves, new FP64 residual.  Each correction solve
         // starts from e = 0: the first from this fill (or FMG's own), the
-        // others from the update, which clears e on the leaves it adds.
+        // others from the update, which clears e on the leaves it adds.  On
+        // one tree whose leaves all lie on its complete finest level, the
+        // update rides on the last half sweep of the correction's V-cycle,
+        // which clears one colour of e; the next V-cycle's first half sweep
+        // takes the other colour's old values as zero.
         LevelArgs<float> b32{t->d_info, e32, rho32, (float *)(ws + L.uold_e), nullptr, 0, 0, 1, 0.f, 0.f,
                              t->d_active};
         Cycler<D, float> cy{h, st, o, s.prof, b32, nullptr, t};
+        if (!t->forest && h.uniform && cube_xmask(h, h.lmax) != 0) cy.add_to = uw;
         if (o.cycle != AFMG_CYCLE_FMG_V) launch_fill<float>(e32, h.n_boxes * C, 0.f, st);
         auto refine = [&](hipStream_t cs, bool first_fmg) {
             Cycler<D, float> c2 = cy;
             c2.st = cs;
-            if (first_fmg) c2.fmg();
-            else c2.vcycle(h.lmax);
-            launch_ir_update<D, BOX_N>(t->d_info, uw, e32, h.n_boxes, t->d_active, cs);
+            if (first_fmg) {
+                c2.fmg();
+            } else {
+                c2.zero_start = true;  // after the fill, or after a fused update
+                c2.vcycle(h.lmax);
+            }
+            if (!c2.fuses_update(h.lmax))
+                launch_ir_update<D, BOX_N>(t->d_info, uw, e32, h.n_boxes, t->d_active, cs);
             s.finalize_launch(rho32, cs, h.lmin_leaf);
         };
         rc = iterate_trees(s, S, tr, [&](int k, int m) {

@@ -122,3 +122,26 @@ def test_mixed_solution_independent_of_workspace_contents(cycle):
         print(f"{fill}: cycles {cycles} vs {results[0][2]}", flush=True)
         assert cycles == results[0][2], fill
         assert torch.equal(u, results[0][1]), fill
+
+
+@pytest.mark.parametrize("name,n_down,n_up", [("u3_64", 1, 3), ("u3_64", 0, 2), ("u3_64", 2, 0),
+                                              ("u2_5", 1, 1)])
+def test_mixed_fused_update_smoothing_counts(name, n_down, n_up):
+    """On a tree whose leaves all lie on its complete finest level the
+    refinement update rides on the last half sweep of each correction, and
+    the next correction's first half sweep takes its colour's old values as
+    zero; without post- or pre-smoothing steps on that level the separate
+    update runs instead.  Each case against the FP64 oracle with the same
+    smoothing counts, at a 1e-8 residual reduction with the bound 1e-6 (the
+    margin of 100 of the cases above)."""
+    w = W.random_fields(2, 8, *W.uniform_leaves(2, 5), 95) if name == "u2_5" else CASES[name]()
+    print(f"[case] mixed {name} V({n_down},{n_up})", flush=True)
+    um, sm = run_mixed(w, cycle="V", tol=1e-8, n_down=n_down, n_up=n_up, max_cycles=200)
+    uo, so = O.Tree(w.dim, w.N, w.level, w.idx).solve(w.rho, w.bc, cycle="V", tol=1e-8, n_down=n_down,
+                                                       n_up=n_up, max_cycles=200)
+    assert sm["status"] == 0, sm
+    err = np.linalg.norm(um - uo) / np.linalg.norm(uo)
+    print(f"mixed {name} V({n_down},{n_up}): outer={sm['cycles']} fp64 cycles={so['cycles']} "
+          f"rel-L2 vs FP64 oracle {err:.2e}", flush=True)
+    assert err <= 1e-6
+    assert sm["cycles"] <= so["cycles"] + 2
