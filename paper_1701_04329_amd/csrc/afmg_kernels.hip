@@ -1111,6 +1111,7 @@ __global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ part
         const double s = rsum[0];
         out[0] = (s == s) ? rm[0] : s;
         out[1] = root ? sqrt(s) : s;
+        __threadfence_system();  // out may be host memory the host reads after the launch
     }
 }
 
@@ -1144,6 +1145,7 @@ __global__ __launch_bounds__(256) void k_reduce_trees(const double *__restrict__
         const double s = rsum[0];
         out[2 * tr + 0] = (s == s) ? rm[0] : s;
         out[2 * tr + 1] = sqrt(s);
+        __threadfence_system();  // out may be host memory the host reads after the launch
     }
 }
 

@@ -66,7 +66,9 @@ struct afmg_tree {
     int device = -1;
     BoxInfo *d_info = nullptr;
     int32_t *d_child = nullptr;      // [n_boxes][8] child ids (adjoint, coarse kernel)
-    double *h_norm = nullptr;        // pinned host copy of (max, L2) per tree
+    double *h_norm = nullptr;        // (max, L2) per tree: pinned, coherent host memory
+                                     // that the norm kernels write directly
+    double *d_norm_host = nullptr;   // h_norm's device address
     std::vector<int64_t> part_off;   // first k_final partial of each level (one tree)
     int64_t n_parts = 0;
     int64_t n_parts_max = 0;         // partials for the smallest workgroups
@@ -123,7 +125,7 @@ int cube_xmask(const HostTree &h, int l) {
 struct WsLayout {
     // FP64: rho, uold; mixed: rho (FP64 leaf rho), e, rho_e, uold_e (FP32);
     // forests also hold the working u
-    size_t rho, uold, bc, partial, norm, e, rho_e, uold_e, u, total;
+    size_t rho, uold, bc, partial, e, rho_e, uold_e, u, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -140,7 +142,6 @@ WsLayout ws_layout(const afmg_tree *t, int precision) {
     L.uold = off; off = align256(off + (mixed ? 0 : nlt * C * sizeof(double)));
     L.bc = off; off = align256(off + (size_t)std::max<int64_t>(1, h.n_bfaces_all) * F * sizeof(double));
     L.partial = off; off = align256(off + np * 2 * sizeof(double));
-    L.norm = off; off = align256(off + (size_t)h.n_trees * 2 * sizeof(double));
     L.e = off; off = align256(off + (mixed ? nb * C * sizeof(float) : 0));
     L.rho_e = off; off = align256(off + (mixed ? nb * C * sizeof(float) : 0));
     L.uold_e = off; off = align256(off + (mixed ? nlt * C * sizeof(float) : 0));
@@ -221,8 +222,11 @@ int bind_device(afmg_tree *t) {
     int rc;
     if ((rc = upload(t->d_info, h.info, "the box table")) != AFMG_OK) return rc;
     if ((rc = upload(t->d_child, h.child, "the child table")) != AFMG_OK) return rc;
-    e = hipHostMalloc(&t->h_norm, 2 * sizeof(double) * (size_t)h.n_trees, hipHostMallocDefault);
+    e = hipHostMalloc(&t->h_norm, 2 * sizeof(double) * (size_t)h.n_trees,
+                      hipHostMallocCoherent | hipHostMallocMapped);
     if (e != hipSuccess) return fail(AFMG_ERR_OOM, "hipHostMalloc failed");
+    e = hipHostGetDevicePointer((void **)&t->d_norm_host, t->h_norm, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipHostGetDevicePointer");
     if (t->forest) {
         e = hipHostMalloc(&t->h_active, sizeof(int) * (size_t)h.n_trees, hipHostMallocDefault);
         if (e != hipSuccess) return fail(AFMG_ERR_OOM, "hipHostMalloc failed");
@@ -448,7 +452,7 @@ struct Solver {
     const afmg_opts &o;
     Prof prof;
     LevelArgs<double> base;  // FP64 state: u, rho, uold (FP64 path), Dirichlet rows
-    double *partial, *norm;
+    double *partial;
 
     Solver(afmg_tree *t_, hipStream_t s, const afmg_opts &o_, afmg_stats *S)
         : t(t_), h(t_->h), st(s), o(o_), prof{t_, s, o_.profile != 0, t_->h.lmax, S, {}} {}
@@ -481,9 +485,10 @@ struct Solver {
                 s);
         }
         if (t->forest)
-            launch_reduce_trees(partial, t->d_tree_leaf_ptr, t->d_tree_leaf_box, base.active, norm, h.n_trees, s);
+            launch_reduce_trees(partial, t->d_tree_leaf_ptr, t->d_tree_leaf_box, base.active, t->d_norm_host,
+                                h.n_trees, s);
         else
-            launch_reduce(partial, t->n_parts, norm, s);
+            launch_reduce(partial, t->n_parts, t->d_norm_host, s);
     }
     // parents of the levels that the per-cycle finalize skips receive the
     // restriction of the solution (k_final's arithmetic and order)
@@ -491,12 +496,11 @@ struct Solver {
         for (int l = h.lmin_leaf - 1; l >= 2; l--)
             launch_restrict_field<D, BOX_N>(t->d_info, base.u, h.lvl_off[(size_t)l], h.level_count(l), st);
     }
-    // norms to t->h_norm; synchronises the stream
+    // the norms in t->h_norm (written there by the reduction kernels, no
+    // copy); synchronises the stream
     int read_norms() {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "kernel launch");
-        e = hipMemcpyAsync(t->h_norm, norm, 2 * sizeof(double) * (size_t)h.n_trees, hipMemcpyDeviceToHost, st);
-        if (e != hipSuccess) return hip_fail(e, "norm readback");
         e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(e, "stream synchronize");
         prof.collect();
@@ -695,7 +699,6 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
     double *bc_w = (double *)(ws + L.bc);
     double *uw = t->forest ? (double *)(ws + L.u) : u;  // working u (colour-split)
     s.partial = (double *)(ws + L.partial);
-    s.norm = (double *)(ws + L.norm);
     s.base = LevelArgs<double>{t->d_info, uw, rho_i, mixed ? nullptr : (double *)(ws + L.uold), bc_w, 0, 0, 0,
                                0.0, 0.0, t->d_active};
     const int64_t F = cells_per_face(D), C = cells_per_box(D);
@@ -939,7 +942,6 @@ int adjoint(afmg_tree *t, hipStream_t st, const double *ubar, double *rho_bar, d
     launch_fill<double>(X, n, 0.0, st);
     Solver<D> s(t, st, o, &S);
     s.partial = A.partial;
-    s.norm = A.norm;
     int status = AFMG_OK, rc;
     if (h.uniform) {
         // the operator is symmetric: lambda solves L lambda = ubar with zero
