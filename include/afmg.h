@@ -333,7 +333,7 @@ int afmg_autotune_workspace_bytes(const afmg_tree *tree, size_t *bytes);
 /*
  * Time every shape of every kernel class on every level of the tree, for
  * FP64 and FP32 arrays, on zero-filled scratch arrays in workspace, and keep
- * the fastest for later solves (the default unless another is at least 3%
+ * the fastest for later solves (the default unless another is at least 10%
  * faster).  Synchronises the stream.  Errors: AFMG_ERR_ARG, AFMG_ERR_HIP.
  */
 int afmg_tree_autotune(afmg_tree *tree, void *stream, void *workspace, size_t workspace_bytes);

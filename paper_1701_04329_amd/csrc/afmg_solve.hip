@@ -1091,10 +1091,15 @@ int step(afmg_tree *t, hipStream_t st, int op, int level, int colour, int homog,
 // Every candidate shape of one kernel class on one level is timed on the
 // tree's own boxes (REPS launches between two events, best of two rounds);
 // the fastest wins, the default (256 threads, XCD runs) unless another is at
-// least 3% faster.  Half sweeps alternate the colours as in a smoothing
-// sweep (one colour repeated would find all its data in the caches).
-// Arrays are zero-filled scratch: timing does not depend on the values.
+// least TUNE_MARGIN faster.  Half sweeps alternate the colours as in a
+// smoothing sweep (one colour repeated would find all its data in the
+// caches).  The trials still run in other cache states than the solve's
+// launches, and smaller measured gains did not carry over: on a level of
+// 4096 boxes the three workgroup sizes timed within 5% of each other, and a
+// 64-thread pick then ran 30% slower inside the solve.  Arrays are
+// zero-filled scratch: timing does not depend on the values.
 constexpr int TUNE_REPS = 10;
+constexpr float TUNE_MARGIN = 0.10f;
 
 template <class Fn>
 float time_launches(hipStream_t st, hipEvent_t a, hipEvent_t b, Fn fn) {
@@ -1160,7 +1165,7 @@ void tune_precision(afmg_tree *t, hipStream_t st, LevelArgs<T> base, double *par
                     }
                 }
             }
-            if (!(t_best < 0.97f * t_def)) best = Shape{};
+            if (!(t_best < (1.0f - TUNE_MARGIN) * t_def)) best = Shape{};
             t->shapes[pi][kind][(size_t)l] = best;
         }
     }
