@@ -92,6 +92,34 @@ def test_full_size_adaptive_fp64_and_mixed_against_oracle():
     assert s["cycles"] <= so["cycles"] + 2
 
 
+def test_full_size_uniform_256_mixed_tuned_against_oracle():
+    """The benchmark workload (uniform 256^3) in the mixed path as the
+    benchmark runs it: autotuned launch shapes, FMG then refinement to a
+    1e-10 residual reduction, the refinement update riding on the last half
+    sweep of each correction.  The whole leaf solution against the oracle's
+    FP64 solve to the mixed bound, and bitwise against the same solve with
+    the default shapes."""
+    from paper_1701_04329_amd import afmg as A
+    w = W.config2()
+    print(f"[case] full-size uniform mixed {w.name} unknowns={w.n_unknowns}", flush=True)
+    dev = torch.device("cuda", 0)
+    t = A.Tree(w.dim, w.level, w.idx)
+    rho = t.leaf_to_boxes(torch.tensor(w.rho, device=dev))
+    bc = t.bc_rows(torch.tensor(w.bc, device=dev))
+    u_def, s_def = A.solve(t, rho, bc, cycle="FMG", tol=1e-10, precision="mixed")
+    t.autotune(dev)
+    u, s = A.solve(t, rho, bc, cycle="FMG", tol=1e-10, precision="mixed")
+    torch.cuda.synchronize()
+    assert torch.equal(u, u_def) and s["cycles"] == s_def["cycles"]
+    um = t.boxes_to_leaf(u).cpu().numpy()
+    uo, so = O.Tree(w.dim, w.N, w.level, w.idx).solve(w.rho, w.bc, cycle="FMG", tol=1e-10)
+    err = np.linalg.norm(um - uo) / np.linalg.norm(uo)
+    print(f"mixed 256^3: outer={s['cycles']} fp64 oracle cycles={so['cycles']} rel-L2 {err:.2e}", flush=True)
+    assert s["status"] == 0 and s["r_max"] <= 1e-10 * s["r0_max"]
+    assert err <= BOUND
+    assert s["cycles"] <= so["cycles"] + 2
+
+
 @pytest.mark.parametrize("cycle", ["V", "FMG"])
 def test_mixed_solution_independent_of_workspace_contents(cycle):
     """Every correction solve starts from e = 0 whatever the workspace held
