@@ -31,9 +31,17 @@ def test_library_exports_every_header_symbol():
 
 
 def test_default_opts_are_the_papers():
-    o = A.make_opts()
-    assert (o.n_down, o.n_up, o.n_base) == (2, 2, 4)
+    """afmg_default_opts against the smoothing counts printed in §3.2
+    (tests/golden/paper_coefficients.json, entry "defaults")."""
+    import json
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_coefficients.json")))["defaults"]
+    o = A.Opts()
+    A.lib().afmg_default_opts(C.byref(o))
+    assert (o.n_down, o.n_up, o.n_base) == (gold["n_down"], gold["n_up"], gold["n_base"])
     assert o.tol == 1e-10 and o.max_cycles == 100 and o.cycle == 0
+    # the binding's keyword defaults are the library's
+    p = A.make_opts()
+    assert (p.n_down, p.n_up, p.n_base, p.tol) == (o.n_down, o.n_up, o.n_base, o.tol)
 
 
 @pytest.mark.parametrize("dim,lev", [(2, 1), (2, 3), (3, 1), (3, 3)])

@@ -16,6 +16,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_1701_04329_amd import workloads as W
+from parity import assert_leaf_parity, assert_norms_close
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -124,9 +125,12 @@ def test_batch_matches_oracle(dim):
         if nrm == 0.0:
             assert not u.any(), w.name
             continue
-        err = np.linalg.norm(u - uo) / nrm
-        assert err <= REL, (w.name, err)
+        assert_leaf_parity(u, uo, REL, w.name)
         np.testing.assert_allclose(s["r0_max"], so["r0_max"], rtol=1e-12)
+        np.testing.assert_allclose(s["r0_l2"], so["r0_l2"], rtol=1e-12)
+        floor = 16 * np.finfo(float).eps * 2 * w.dim * (w.N * 2.0 ** (w.lmax - 1)) ** 2 * np.abs(uo).max()
+        assert_norms_close(s["hist_max"], so["hist_max"], floor, what=w.name)
+        assert_norms_close(s["hist_l2"], so["hist_l2"], floor, what=w.name)
         assert s["cycles"] == so["cycles"] == 3
 
 

@@ -764,3 +764,141 @@ def test_composite_operator_is_nonsymmetric_at_refinement_boundaries():
     lev_u, idx_u = W.uniform_leaves(3, 3)
     Au = O.assemble_L(O.Tree(3, 4, lev_u, idx_u))
     assert abs(Au - Au.T).max() == 0.0
+
+
+# ----------------------------------------------------------------------------
+# residual norms reported by the solve, and the coarsest-grid relaxation count
+# ----------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_residual_norms_equal_dense_composite_residual(case):
+    """The two norms of the composite leaf residual r = rho - A u - g (§3.2,
+    eq. residual; §4.1 plots the maximum): max |r_c| and the volume-weighted
+    sqrt(sum r_c^2 h_c^D), against the dense assembly with the cell volumes
+    taken from the leaf levels.  A dropped h^D, square root or boundary term
+    changes one of them by orders of magnitude."""
+    dim, N, lev, idx = tiny_trees()[case]
+    rng = np.random.default_rng(900 + case)
+    rho = rng.standard_normal((len(lev), N ** dim))
+    u = rng.standard_normal((len(lev), N ** dim))
+    bc = rng.standard_normal((len(lev), 2 * dim, N ** (dim - 1)))
+    bc *= W.physical_side_mask(dim, lev, idx)[:, :, None]
+    A, g = dense_ref.assemble(dim, N, lev, idx, bc)
+    r = rho.ravel() - A @ u.ravel() - g
+    vol = dense_ref.leaf_cell_volumes(dim, N, lev)
+    want_max = np.abs(r).max()
+    want_l2 = np.sqrt(np.sum(r * r * vol))
+    t = O.Tree(dim, N, lev, idx)
+    t.load(rho, bc, u)
+    got_max, got_l2 = t.finalize()
+    assert got_max == pytest.approx(want_max, rel=1e-12)
+    assert got_l2 == pytest.approx(want_l2, rel=1e-12)
+    # the solve reports the same pair for its initial guess
+    _, st = t.solve(rho, bc, u0=u, fixed_cycles=1)
+    assert st["r0_max"] == pytest.approx(want_max, rel=1e-12)
+    assert st["r0_l2"] == pytest.approx(want_l2, rel=1e-12)
+
+
+def _dense_red_black(A, g, rho, x, dim, N, sweeps):
+    """Red-black Gauss-Seidel written on the assembled matrix of one box of
+    N^D cells: red cells (1-based index sum even, §3.1) first, then black.
+    As in the ghost-cell form of the smoother, the central stencil
+    coefficient -2D/h^2 is the one solved for; the part of the diagonal that
+    a boundary ghost contributes (-u_c/h^2 for a Dirichlet side) multiplies
+    the cell's value from before the half sweep."""
+    x = x.copy()
+    n = len(x)
+    # np.ndindex runs its last axis fastest, which is x in the box array; the
+    # index sum does not depend on the axis order.  1-based sum = 0-based
+    # sum + dim.
+    par = np.array([sum(loc) % 2 for loc in np.ndindex(*([N] * dim))])
+    red = ((par + dim) % 2) == 0
+    central = np.diag(A).copy()
+    # the stencil's own coefficient is -2D/h^2; 1/h^2 is the entry of an
+    # in-box neighbour
+    h2inv = max(A[0, j] for j in range(n) if j != 0)
+    D0 = -2.0 * dim * h2inv
+    for _ in range(sweeps):
+        for colour in (red, ~red):
+            old = x.copy()
+            for c in np.nonzero(colour)[0]:
+                s = rho[c] - g[c] - (A[c] @ old - A[c, c] * old[c]) - (central[c] - D0) * old[c]
+                x[c] = s / D0
+    return x
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_coarsest_grid_gets_n_base_iterations(dim):
+    """§3.2 step 2: N_base (printed default 4) relaxation steps on the
+    coarsest grid.  On a tree that is one box of 2^D cells the coarsest grid
+    is the whole tree, so a V-cycle is exactly N_base red-black iterations;
+    these are recomputed on the independently assembled matrix.  A count of
+    3 or 5 gives a different iterate."""
+    n_base = GOLDEN["defaults"]["n_base"]
+    assert n_base == 4
+    N = 2
+    lev, idx = W.uniform_leaves(dim, 1)
+    rng = np.random.default_rng(950 + dim)
+    rho = rng.standard_normal((1, N ** dim))
+    u0 = rng.standard_normal((1, N ** dim))
+    bc = rng.standard_normal((1, 2 * dim, N ** (dim - 1)))
+    A, g = dense_ref.assemble(dim, N, lev, idx, bc)
+    want = _dense_red_black(A, g, rho.ravel(), u0.ravel(), dim, N, n_base)
+    t = O.Tree(dim, N, lev, idx)
+    assert t.lmin == 1 and t.lmax == 1
+    got, _ = t.solve(rho, bc, u0=u0, fixed_cycles=1, n_base=n_base)
+    np.testing.assert_allclose(got.ravel(), want, rtol=1e-13, atol=1e-13 * np.abs(want).max())
+    for other in (n_base - 1, n_base + 1):
+        alt = _dense_red_black(A, g, rho.ravel(), u0.ravel(), dim, N, other)
+        assert np.abs(alt - want).max() > 1e-6 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_vcycle_order_with_unequal_smoothing_counts(dim):
+    """§3.2: the V-cycle as a sequence of its steps with N_down = 1, N_up = 3
+    and N_base from the printed defaults, on a tree with extra coarse grids
+    below the root and refinement boundaries: N_down sweeps, residual and
+    restriction, FAS right-hand side and copy v' on the way down; 2 N_base
+    half sweeps on the coarsest grid (a 2^D-cell grid); correction and N_up
+    sweeps on the way up.  Built from the oracle's single steps and compared
+    with its V-cycle, bitwise."""
+    n_base = GOLDEN["defaults"]["n_base"]
+    N = 8
+    lev, idx = W.ball_leaves(dim, N, 4, (0.3, 0.62, 0.41), 0.0, 0)
+    rng = np.random.default_rng(970 + dim)
+    rho = rng.standard_normal((len(lev), N ** dim))
+    u0 = rng.standard_normal((len(lev), N ** dim))
+    bc = rng.standard_normal((len(lev), 2 * dim, N ** (dim - 1)))
+    bc *= W.physical_side_mask(dim, lev, idx)[:, :, None]
+    ref = O.Tree(dim, N, lev, idx)
+    ref.load(rho, bc, u0)
+    ref.vcycle(n_down=1, n_up=3, n_base=n_base)
+    want = ref.leaf_field("u")
+    t = O.Tree(dim, N, lev, idx)
+    assert t.lmin == -1
+    # the coarsest grid has 2^D cells
+    assert t.box_info(0)["level"] == t.lmin and t.box_info(0)["n"] == 2
+    t.load(rho, bc, u0)
+    top = t.lmax
+    for l in range(top, t.lmin, -1):
+        t.half_sweep(l, 0)
+        t.half_sweep(l, 1)
+        t.resid_restrict_level(l)
+        t.coarse_rhs_level(l - 1)
+    for _ in range(n_base):
+        t.half_sweep(t.lmin, 0)
+        t.half_sweep(t.lmin, 1)
+    for l in range(t.lmin + 1, top + 1):
+        t.fill_gc(l - 1)
+        t.prolong_level(l)
+        for _ in range(3):
+            t.half_sweep(l, 0)
+            t.half_sweep(l, 1)
+    got = t.leaf_field("u")
+    assert np.array_equal(got, want)
+    # and a count other than N_base on the coarsest grid differs
+    alt = O.Tree(dim, N, lev, idx)
+    alt.load(rho, bc, u0)
+    alt.vcycle(n_down=1, n_up=3, n_base=n_base + 1)
+    assert not np.array_equal(alt.leaf_field("u"), want)
