@@ -216,6 +216,28 @@ int afmg_solve(afmg_tree *tree, void *stream, const double *rho, const double *b
                void *workspace, size_t workspace_bytes, const afmg_opts *opts,
                afmg_stats *stats);
 
+/*
+ * afmg_solve without a caller workspace, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same kernels and result as afmg_solve, bitwise.
+ * The workspace is instead an array inside the library of AFMG_SCRATCH_BYTES
+ * (128 MiB), one copy on every GPU the library runs on, held until the
+ * process ends; trees whose workspace (afmg_workspace_bytes for these
+ * options) is larger are rejected.  The call allocates nothing, so the tree
+ * must already be prepared on the current device (afmg_tree_finalize, or an
+ * earlier solve), and opts->graph and opts->profile must be 0 (recording a
+ * graph and profiling events allocate).  All calls on one GPU share that
+ * GPU's array: calls that overlap on one GPU (on other streams or from other
+ * host threads) race and must be serialised by the caller.  The array keeps
+ * the contents of the last call; a solve writes every part it reads.
+ * Arguments and return values otherwise as afmg_solve.  Errors: AFMG_ERR_ARG
+ * (null or misaligned arrays, a batch, an unprepared tree, graph or profile
+ * set, workspace above AFMG_SCRATCH_BYTES), AFMG_ERR_HIP.
+ */
+#define AFMG_SCRATCH_BYTES ((size_t)128 << 20)
+int afmg_solve_noalloc(afmg_tree *tree, void *stream, const double *rho, const double *bc, double *u,
+                       const afmg_opts *opts, afmg_stats *stats);
+
 /* Operators of afmg_apply (homogeneous Dirichlet values). */
 typedef enum { AFMG_OP_L = 0, AFMG_OP_LT = 1 } afmg_op;
 

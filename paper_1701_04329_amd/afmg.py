@@ -117,6 +117,7 @@ EXPORTS = [
     "afmg_batch_solve", "afmg_autotune_workspace_bytes", "afmg_tree_autotune", "afmg_tree_shape",
     "afmg_tree_set_shape", "afmg_batch_autotune_workspace_bytes", "afmg_batch_autotune", "afmg_batch_shape",
     "afmg_batch_set_shape", "afmg_tree_refine", "afmg_tree_finalize", "afmg_tree_level_list", "afmg_step",
+    "afmg_solve_noalloc",
 ]
 STEPS = {"half_sweep": 0, "resid_restrict": 1, "coarse_rhs": 2, "prolong": 3, "coarse": 4}
 LISTS = {"all": 0, "parent": 1, "leaf": 2}
@@ -154,6 +155,7 @@ def lib():
         L.afmg_tree_box.argtypes = [vp, i64, C.POINTER(BoxDesc)]
         L.afmg_workspace_bytes.argtypes = [vp, C.POINTER(Opts), C.POINTER(C.c_size_t)]
         L.afmg_solve.argtypes = [vp, vp, vp, vp, vp, vp, C.c_size_t, C.POINTER(Opts), C.POINTER(Stats)]
+        L.afmg_solve_noalloc.argtypes = [vp, vp, vp, vp, vp, C.POINTER(Opts), C.POINTER(Stats)]
         L.afmg_last_error.restype = C.c_char_p
         L.afmg_adjoint_workspace_bytes.argtypes = [vp, C.POINTER(Opts), C.POINTER(C.c_size_t)]
         L.afmg_apply.argtypes = [vp, vp, C.c_int, vp, vp, vp, C.c_size_t]
@@ -411,6 +413,37 @@ def solve(tree: Tree, rho, bc=None, u=None, *, cycle="V", tol=1e-10, max_cycles=
     d = st.to_dict()
     d["rc"] = rc
     return u, d
+
+
+SCRATCH_BYTES = 128 << 20  # AFMG_SCRATCH_BYTES
+
+
+def solve_noalloc(tree: Tree, rho, bc, u, *, cycle="V", tol=1e-10, max_cycles=100, fixed_cycles=0, n_down=2,
+                  n_up=2, n_base=4, precision="fp64", stream=None, check=True, use_guess=False, check_every=1):
+    """afmg_solve_noalloc: the solve with the library's own scratch array as
+    its workspace (nothing is allocated; the tree must be finalized on the
+    device).  rho, u: float64 device tensors [n_boxes, N^D] in box order, u
+    overwritten; bc: Dirichlet rows or None.  Returns (rc, stats dict)."""
+    import torch
+
+    for t_, name in ((rho, "rho"), (u, "u")):
+        _check_field(tree, t_, name)
+    if bc is not None and (bc.dtype != torch.float64 or not bc.is_contiguous()
+                           or bc.numel() != tree.n_bfaces * tree.box_n ** (tree.dim - 1)):
+        raise ValueError("bc has the wrong dtype, layout or size")
+    opts = make_opts(cycle, n_down, n_up, n_base, tol, max_cycles, fixed_cycles, use_guess, precision, False,
+                     False, check_every)
+    if stream is None:
+        stream = torch.cuda.current_stream(u.device)
+    st = Stats()
+    with torch.cuda.device(u.device):
+        rc = lib().afmg_solve_noalloc(tree.handle, C.c_void_p(stream.cuda_stream), _ptr(rho), _ptr(bc), _ptr(u),
+                                      C.byref(opts), C.byref(st))
+    if check:
+        _check(rc, allow=(AFMG_OK, AFMG_NOT_CONVERGED))
+    d = st.to_dict()
+    d["rc"] = rc
+    return rc, d
 
 
 class Batch(_Shapes):

@@ -17,6 +17,7 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "afmg.h"
@@ -25,8 +26,18 @@
 
 using namespace afmg;
 
+// Workspace of afmg_solve_noalloc, one copy on every GPU the library runs on
+// (held until the process ends).  In host code this name is only a handle
+// for hipGetSymbolAddress: the device address of each GPU's copy is looked up
+// once per device and used everywhere the host needs the array.
+static __device__ __align__(256) unsigned char scratch[AFMG_SCRATCH_BYTES];
+
 namespace {
 thread_local std::string g_err;
+
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[SCRATCH_DEVICES] = {};
 }
 
 void afmg::set_error(const std::string &m) { g_err = m; }
@@ -75,6 +86,7 @@ struct afmg_tree {
     std::vector<Shape> shapes[2][SK_KINDS];  // [FP64, FP32][kernel class][level]
     int tune_epoch = 0;              // bumped by every autotune
     std::vector<hipEvent_t> events;  // event pairs for opts.profile
+    hipEvent_t span[2] = {nullptr, nullptr};  // first kernel .. last norm of a solve
     Recorded rec;
     // forests (batches): per-tree mask and tables, and the caller's layout
     bool forest = false;
@@ -227,6 +239,10 @@ int bind_device(afmg_tree *t) {
     if (e != hipSuccess) return fail(AFMG_ERR_OOM, "hipHostMalloc failed");
     e = hipHostGetDevicePointer((void **)&t->d_norm_host, t->h_norm, 0);
     if (e != hipSuccess) return hip_fail(e, "hipHostGetDevicePointer");
+    for (hipEvent_t &ev : t->span) {
+        e = hipEventCreate(&ev);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
     if (t->forest) {
         e = hipHostMalloc(&t->h_active, sizeof(int) * (size_t)h.n_trees, hipHostMallocDefault);
         if (e != hipSuccess) return fail(AFMG_ERR_OOM, "hipHostMalloc failed");
@@ -253,6 +269,8 @@ void release(afmg_tree *t) {
     if (t->h_norm) (void)hipHostFree(t->h_norm);
     if (t->h_active) (void)hipHostFree(t->h_active);
     for (auto ev : t->events) (void)hipEventDestroy(ev);
+    for (auto ev : t->span)
+        if (ev) (void)hipEventDestroy(ev);
 }
 
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
@@ -703,9 +721,7 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
                                0.0, 0.0, t->d_active};
     const int64_t F = cells_per_face(D), C = cells_per_box(D);
 
-    hipEvent_t ev0, ev1;
-    (void)hipEventCreate(&ev0);
-    (void)hipEventCreate(&ev1);
+    hipEvent_t ev0 = t->span[0], ev1 = t->span[1];
     (void)hipEventRecord(ev0, st);
     // Dirichlet rows: caller's leaf rows, then parent rows from fine to coarse
     if (h.n_bfaces_leaf > 0) {
@@ -822,8 +838,6 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
     (void)hipEventSynchronize(ev1);
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, ev0, ev1);
-    (void)hipEventDestroy(ev0);
-    (void)hipEventDestroy(ev1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "solve");
     int status = AFMG_OK;
@@ -927,9 +941,7 @@ int adjoint(afmg_tree *t, hipStream_t st, const double *ubar, double *rho_bar, d
     double *X = A.vec(AdjLayout::X), *B = A.vec(AdjLayout::B);
     double *bcz = (double *)(ws + A.L.bc);
     const int64_t n = A.n, F = cells_per_face(D);
-    hipEvent_t ev0, ev1;
-    (void)hipEventCreate(&ev0);
-    (void)hipEventCreate(&ev1);
+    hipEvent_t ev0 = t->span[0], ev1 = t->span[1];
     (void)hipEventRecord(ev0, st);
     // u_bar in the working layout; values on parent boxes (the restriction of
     // the leaves) are pushed to the leaves through the transposed restriction
@@ -1029,8 +1041,6 @@ int adjoint(afmg_tree *t, hipStream_t st, const double *ubar, double *rho_bar, d
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, ev0, ev1);
     S.t_ms = ms;
-    (void)hipEventDestroy(ev0);
-    (void)hipEventDestroy(ev1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "adjoint");
     S.status = status;
@@ -1239,6 +1249,22 @@ int set_shape(afmg_tree *t, int precision, int kind, int level, int wg, int no_r
     return AFMG_OK;
 }
 
+// device address of the current GPU's copy of `scratch`, looked up on the
+// first call on that device
+int scratch_address(int dev, void **out) {
+    if (dev < 0 || dev >= SCRATCH_DEVICES) return fail(AFMG_ERR_ARG, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress of the scratch array");
+        if (!p || !aligned(p, 256)) return fail(AFMG_ERR_HIP, "scratch array has no aligned device address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return AFMG_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1443,6 +1469,33 @@ int afmg_solve(afmg_tree *t, void *stream, const double *rho, const double *bc, 
     hipStream_t st = (hipStream_t)stream;
     if (t->h.dim == 3) return solve<3>(t, st, rho, bc, u, (char *)workspace, *opts, stats);
     return solve<2>(t, st, rho, bc, u, (char *)workspace, *opts, stats);
+}
+
+int afmg_solve_noalloc(afmg_tree *t, void *stream, const double *rho, const double *bc, double *u,
+                       const afmg_opts *opts, afmg_stats *stats) {
+    if (!t || !rho || !u || !stats) return fail(AFMG_ERR_ARG, "null argument");
+    if (t->forest) return fail(AFMG_ERR_ARG, "not a tree");
+    int rc = check_opts(opts);
+    if (rc != AFMG_OK) return rc;
+    if (opts->graph || opts->profile)
+        return fail(AFMG_ERR_ARG, "afmg_solve_noalloc: graph recording and profiling allocate; set both to 0");
+    if (!aligned(rho, 8) || !aligned(u, 8) || (bc && !aligned(bc, 8))) return fail(AFMG_ERR_ARG, "misaligned array");
+    const size_t need = ws_layout(t, opts->precision).total;
+    if (need > AFMG_SCRATCH_BYTES)
+        return fail(AFMG_ERR_ARG, "afmg_solve_noalloc: the tree needs " + std::to_string(need) +
+                                      " bytes of workspace, more than the " + std::to_string(AFMG_SCRATCH_BYTES) +
+                                      " of the scratch array; use afmg_solve with a caller workspace");
+    if (t->device < 0) return fail(AFMG_ERR_ARG, "afmg_solve_noalloc: prepare the tree first (afmg_tree_finalize)");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (t->device != dev) return fail(AFMG_ERR_ARG, "tree was first used on another device");
+    void *ws = nullptr;
+    if ((rc = scratch_address(dev, &ws)) != AFMG_OK) return rc;
+    std::memset(stats, 0, sizeof(*stats));
+    hipStream_t st = (hipStream_t)stream;
+    if (t->h.dim == 3) return solve<3>(t, st, rho, bc, u, (char *)ws, *opts, stats);
+    return solve<2>(t, st, rho, bc, u, (char *)ws, *opts, stats);
 }
 
 int afmg_batch_create(afmg_tree *const *trees, int n_trees, afmg_batch **out) {

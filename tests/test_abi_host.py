@@ -326,3 +326,26 @@ def test_check_every_validation():
         t.workspace_bytes(A.make_opts(check_every=-1))
     assert e.value.code == A.AFMG_ERR_ARG
     assert A.make_opts().check_every == 1
+
+
+def test_noalloc_argument_checks_without_device():
+    """afmg_solve_noalloc rejects, before any device work: graph or profile
+    options (they allocate), trees whose workspace exceeds the scratch array,
+    and trees not yet prepared on a device."""
+    level, idx = W.uniform_leaves(2, 3)
+    t = A.Tree(2, level, idx)
+    fake = C.c_void_p(1 << 20)  # aligned, never dereferenced by these checks
+    st = A.Stats()
+    L = A.lib()
+    for kw in (dict(graph=True), dict(profile=True)):
+        o = A.make_opts(**kw)
+        assert L.afmg_solve_noalloc(t.handle, None, fake, None, fake, C.byref(o), C.byref(st)) == A.AFMG_ERR_ARG
+    o = A.make_opts()
+    assert L.afmg_solve_noalloc(t.handle, None, fake, None, fake, C.byref(o), C.byref(st)) == A.AFMG_ERR_ARG
+    assert "afmg_tree_finalize" in A.last_error()
+    lev6, idx6 = W.uniform_leaves(3, 6)
+    big = A.Tree(3, lev6, idx6)
+    assert big.workspace_bytes(o) > A.SCRATCH_BYTES
+    assert L.afmg_solve_noalloc(big.handle, None, fake, None, fake, C.byref(o), C.byref(st)) == A.AFMG_ERR_ARG
+    assert "scratch" in A.last_error()
+    assert L.afmg_solve_noalloc(None, None, fake, None, fake, C.byref(o), C.byref(st)) == A.AFMG_ERR_ARG
