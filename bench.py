@@ -89,7 +89,9 @@ def batch_bench(args, A, torch, dev, stream):
     """The batch workload: independent trees of 64-8192 boxes, D alternating
     2/3, 1-3 Gaussian sources, zero Dirichlet values.  One step solves every
     tree (FMG, then V-cycles until each tree's own residual dropped by 1e-10):
-    one batch per dimension, one after the other on the stream."""
+    one batch per dimension, the two solved concurrently, each on its own
+    stream driven by its own host thread; the sequential time (one batch
+    after the other on one stream) is reported beside it."""
     from oracle import oracle as O
     from paper_1701_04329_amd import workloads as W
 

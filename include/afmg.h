@@ -185,6 +185,10 @@ int afmg_tree_finalize(afmg_tree *tree, void *stream);
 typedef enum { AFMG_LIST_ALL = 0, AFMG_LIST_PARENT = 1, AFMG_LIST_LEAF = 2 } afmg_list_kind;
 int afmg_tree_level_list(const afmg_tree *tree, int level, int kind, int32_t *ids, int64_t *n);
 
+/* Sizes of the tree (paper §2.1: boxes of N^D cells on levels 1 .. lmax,
+   §3.2: coarse grids below level 1 down to lmin): dim, N, box, leaf and
+   Dirichlet-row counts, level range, unknowns (leaf cells).  Host-only.
+   Errors: AFMG_ERR_ARG (null). */
 int afmg_tree_info(const afmg_tree *tree, afmg_tree_desc *out);
 
 /* box id of each input leaf: out[n_leaves] (host array) */
@@ -193,6 +197,11 @@ int afmg_tree_leaf_boxes(const afmg_tree *tree, int32_t *out);
 /* (box id, side) of each Dirichlet row: out[2*n_bfaces] (host array) */
 int afmg_tree_bfaces(const afmg_tree *tree, int32_t *out);
 
+/* The record of one box (paper §2.1: refinement level, spatial index,
+   parent, children and side neighbours, with the neighbour codes of
+   afmg_box_desc; origin and cell size from the level).  box in
+   [0, n_boxes).  Host-only.  Errors: AFMG_ERR_ARG (null, box out of
+   range). */
 int afmg_tree_box(const afmg_tree *tree, int64_t box, afmg_box_desc *out);
 
 /* Device workspace bytes afmg_solve needs for these options. */
@@ -269,7 +278,11 @@ int afmg_apply(afmg_tree *tree, void *stream, int op, const double *x, double *y
  * comes from BiCGSTAB on L^T, right-preconditioned by one V-cycle of L scaled
  * by the cell volumes.  opts: tol (relative max-norm of u_bar - L^T lambda),
  * max_cycles (iterations), n_down/n_up/n_base of the V-cycle; stats.cycles
- * counts V-cycles or BiCGSTAB iterations, stats.r_max is the final residual.
+ * counts V-cycles or BiCGSTAB iterations, stats.r_max is the final true
+ * residual max |u_bar - L^T lambda|.  Where BiCGSTAB's recursive residual
+ * meets tol but the true one does not, the iteration restarts from the true
+ * residual (at most twice); if it still misses tol the call returns
+ * AFMG_NOT_CONVERGED.
  *   u_bar    device [n_boxes][N^D]; entries on parent boxes (where u* is the
  *            restriction of the leaves) reach the leaves through the
  *            transposed restriction

@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import warnings
 
 import numpy as np
 
@@ -626,6 +627,9 @@ def _autograd_function():
         def forward(ctx, rho, bc, tree, opts):
             u, st = solve(tree, rho.detach().contiguous(), None if bc is None else bc.detach().contiguous(),
                           **opts)
+            if st["status"] != AFMG_OK:
+                warnings.warn(f"poisson_solve: forward solve not converged (status {st['status']}, "
+                              f"residual ratio {st['r_max'] / max(st['r0_max'], 1e-300):.2e})", RuntimeWarning)
             ctx.tree = tree
             ctx.opts = opts
             ctx.has_bc = bc is not None
@@ -635,10 +639,13 @@ def _autograd_function():
         @staticmethod
         def backward(ctx, u_bar):
             o = ctx.opts
-            rho_bar, bc_bar, _ = adjoint(ctx.tree, u_bar.contiguous(), tol=o.get("tol", 1e-10),
-                                         max_cycles=max(o.get("max_cycles", 100), 200),
-                                         n_down=o.get("n_down", 2), n_up=o.get("n_up", 2),
-                                         n_base=o.get("n_base", 4))
+            rho_bar, bc_bar, st = adjoint(ctx.tree, u_bar.contiguous(), tol=o.get("tol", 1e-10),
+                                          max_cycles=max(o.get("max_cycles", 100), 200),
+                                          n_down=o.get("n_down", 2), n_up=o.get("n_up", 2),
+                                          n_base=o.get("n_base", 4))
+            if st["status"] != AFMG_OK:
+                warnings.warn(f"poisson_solve: adjoint solve not converged (status {st['status']}, "
+                              f"residual ratio {st['r_max'] / max(st['r0_max'], 1e-300):.2e})", RuntimeWarning)
             return rho_bar, (bc_bar if ctx.has_bc else None), None, None
 
     return PoissonSolve

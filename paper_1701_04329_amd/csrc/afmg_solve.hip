@@ -985,53 +985,66 @@ int adjoint(afmg_tree *t, hipStream_t st, const double *ubar, double *rho_bar, d
             launch_scale_leaves<D, BOX_N>(t->d_info, out, PU, +1, h.n_boxes, st);
         };
         launch_copy<double>(B, R, n, st);
-        launch_copy<double>(B, RH, n, st);
-        launch_fill<double>(P, n, 0.0, st);
-        launch_fill<double>(Vv, n, 0.0, st);
         double mx, sum;
         if ((rc = A.dot(R, R, mx, sum)) != AFMG_OK) return rc;
         S.r0_max = mx;
         S.r0_l2 = std::sqrt(sum);
         S.r_max = mx;
         S.r_l2 = S.r0_l2;
-        double rho_old = 1.0, alpha = 1.0, omega = 1.0;
-        status = iterate(o, S, [&](int) -> int {
-            double rho_new, dummy;
-            int q;
-            if ((q = A.dot(RH, R, dummy, rho_new)) != AFMG_OK) return q;
-            if (rho_new == 0.0) return fail(AFMG_ERR_DIVERGED, "BiCGSTAB breakdown (rho = 0)");
-            const double beta = (rho_new / rho_old) * (alpha / omega);
-            launch_lc3(P, 1.0, R, beta, P, -beta * omega, Vv, n, st);
-            precond(P, PH);
-            A.apply_lt(PH, Vv);
-            double rv;
-            if ((q = A.dot(RH, Vv, dummy, rv)) != AFMG_OK) return q;
-            if (rv == 0.0) return fail(AFMG_ERR_DIVERGED, "BiCGSTAB breakdown (r.v = 0)");
-            alpha = rho_new / rv;
-            launch_lc3(SV, 1.0, R, -alpha, Vv, 0.0, nullptr, n, st);
-            precond(SV, SH);
-            A.apply_lt(SH, T);
-            double tt, ts;
-            if ((q = A.dot(T, T, dummy, tt)) != AFMG_OK) return q;
-            if ((q = A.dot(T, SV, dummy, ts)) != AFMG_OK) return q;
-            omega = tt > 0.0 ? ts / tt : 0.0;
-            launch_lc3(X, 1.0, X, alpha, PH, omega, SH, n, st);
-            launch_lc3(R, 1.0, SV, -omega, T, 0.0, nullptr, n, st);
-            double rs;
-            if ((q = A.dot(R, R, S.r_max, rs)) != AFMG_OK) return q;
-            S.r_l2 = std::sqrt(rs);
-            rho_old = rho_new;
-            if (omega == 0.0) return fail(AFMG_ERR_DIVERGED, "BiCGSTAB breakdown (omega = 0)");
-            return AFMG_OK;
-        });
-        if (status < 0 && status != AFMG_ERR_NONFINITE && status != AFMG_ERR_DIVERGED) return status;
-        // true residual of the result
-        A.apply_lt(X, T);
-        launch_lc3(T, 1.0, B, -1.0, T, 0.0, nullptr, n, st);
-        double tmx, tsum;
-        if ((rc = A.dot(T, T, tmx, tsum)) != AFMG_OK) return rc;
-        S.r_max = tmx;
-        S.r_l2 = std::sqrt(tsum);
+        // BiCGSTAB judges convergence by its recursive residual; the true
+        // residual u_bar - L^T lambda is computed afterwards, and where it
+        // misses the tolerance the iteration restarts from it (twice at
+        // most, within max_cycles iterations in all)
+        for (int restart = 0;; restart++) {
+            launch_copy<double>(R, RH, n, st);
+            launch_fill<double>(P, n, 0.0, st);
+            launch_fill<double>(Vv, n, 0.0, st);
+            double rho_old = 1.0, alpha = 1.0, omega = 1.0;
+            status = iterate(o, S, [&](int) -> int {
+                double rho_new, dummy;
+                int q;
+                if ((q = A.dot(RH, R, dummy, rho_new)) != AFMG_OK) return q;
+                if (rho_new == 0.0) return fail(AFMG_ERR_DIVERGED, "BiCGSTAB breakdown (rho = 0)");
+                const double beta = (rho_new / rho_old) * (alpha / omega);
+                launch_lc3(P, 1.0, R, beta, P, -beta * omega, Vv, n, st);
+                precond(P, PH);
+                A.apply_lt(PH, Vv);
+                double rv;
+                if ((q = A.dot(RH, Vv, dummy, rv)) != AFMG_OK) return q;
+                if (rv == 0.0) return fail(AFMG_ERR_DIVERGED, "BiCGSTAB breakdown (r.v = 0)");
+                alpha = rho_new / rv;
+                launch_lc3(SV, 1.0, R, -alpha, Vv, 0.0, nullptr, n, st);
+                precond(SV, SH);
+                A.apply_lt(SH, T);
+                double tt, ts;
+                if ((q = A.dot(T, T, dummy, tt)) != AFMG_OK) return q;
+                if ((q = A.dot(T, SV, dummy, ts)) != AFMG_OK) return q;
+                omega = tt > 0.0 ? ts / tt : 0.0;
+                launch_lc3(X, 1.0, X, alpha, PH, omega, SH, n, st);
+                launch_lc3(R, 1.0, SV, -omega, T, 0.0, nullptr, n, st);
+                double rs;
+                if ((q = A.dot(R, R, S.r_max, rs)) != AFMG_OK) return q;
+                S.r_l2 = std::sqrt(rs);
+                rho_old = rho_new;
+                if (omega == 0.0) return fail(AFMG_ERR_DIVERGED, "BiCGSTAB breakdown (omega = 0)");
+                return AFMG_OK;
+            });
+            if (status < 0 && status != AFMG_ERR_NONFINITE && status != AFMG_ERR_DIVERGED) return status;
+            // true residual of the result
+            A.apply_lt(X, T);
+            launch_lc3(T, 1.0, B, -1.0, T, 0.0, nullptr, n, st);
+            double tmx, tsum;
+            if ((rc = A.dot(T, T, tmx, tsum)) != AFMG_OK) return rc;
+            S.r_max = tmx;
+            S.r_l2 = std::sqrt(tsum);
+            const bool fixed = o.fixed_cycles > 0;
+            const bool missed = !(tmx <= o.tol * S.r0_max);
+            if (status != AFMG_OK || fixed || !missed || restart == 2 || S.cycles >= o.max_cycles) {
+                if (status == AFMG_OK && !fixed && missed) status = AFMG_NOT_CONVERGED;
+                break;
+            }
+            launch_copy<double>(T, R, n, st);
+        }
     }
     if (status < 0 && status != AFMG_ERR_NONFINITE && status != AFMG_ERR_DIVERGED) return status;
     launch_store_leaves<D, BOX_N>(t->d_info, X, rho_bar, h.n_boxes, st);
