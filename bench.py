@@ -21,6 +21,7 @@ import hashlib
 import json
 import os
 import re
+import subprocess
 import sys
 import time
 
@@ -56,6 +57,85 @@ def committed_traffic(kernel_tag):
     return float(m_bytes.group(1))
 
 
+def solve_byte_model(tree, v_cycles, fmg, s=8, n_down=2, n_up=2):
+    """Algorithmic HBM bytes of one FP64 solve: every array a kernel touches
+    counted once per launch, with the kernels and launch sequence of the
+    library's scheduler (paper §3.2).  Per cell of a level (D: dimension):
+    half sweep 1.5 s (other colour, own rho, own colour written); residual +
+    restriction 2 s + 2 s / 2^D; FAS right-hand side + copy 4 s; prolongation
+    + correction 2 s + 2 s / 2^D; end-of-cycle pass 2 s + s / 2^D on leaves,
+    s + s / 2^D on parents; the coarse kernel (levels <= 2) 4 s per level-2
+    cell; layout conversions 2 s; fills s."""
+    D = tree.dim
+    C = tree.cells_per_box
+    lmax = tree.lmax
+    all_c = {l: len(tree.level_list(l, "all")) * C for l in range(1, lmax + 1)}
+    leaf_c = {l: len(tree.level_list(l, "leaf")) * C for l in range(1, lmax + 1)}
+    lmin_leaf = min(l for l in range(1, lmax + 1) if leaf_c[l] > 0)
+    r = 1.0 / 2 ** D
+    n_all = sum(all_c.values())
+    n_leaf = sum(leaf_c.values())
+
+    def finalize(lfirst):
+        b = 0.0
+        for l in range(max(1, lfirst), lmax + 1):
+            if l == 1 and leaf_c[1] == 0:
+                continue
+            b += leaf_c[l] * (2 * s + s * r) + (all_c[l] - leaf_c[l]) * (s + s * r)
+        return b
+
+    def coarse():
+        return 4 * s * all_c.get(2, 0)
+
+    def vcycle(top):
+        if top < 3:  # levels <= 2 are smoothed inside the coarse kernel, in LDS
+            return coarse()
+        b = 0.0
+        for l in range(top, 2, -1):
+            b += 2 * n_down * 1.5 * s * all_c[l] + (2 * s + 2 * s * r) * all_c[l]
+            if l - 1 >= 3:
+                b += 4 * s * all_c[l - 1]
+        b += coarse()
+        for l in range(3, top + 1):
+            b += (2 * s + 2 * s * r) * all_c[l] + 2 * n_up * 1.5 * s * all_c[l]
+        return b
+
+    b = 2 * s * n_leaf + s * n_all + finalize(1)  # rho layout, u = 0, initial residual
+    if fmg:
+        b += sum((s + s * r) * all_c[l] for l in range(2, lmax + 1))  # rho restricted down
+        b += coarse()
+        for l in range(2, lmax + 1):
+            if l < lmax:
+                b += 2 * s * all_c[l]  # the copy v'
+            b += (2 * s + 2 * s * r) * all_c[l] + vcycle(l)
+        b += finalize(lmin_leaf)
+    b += v_cycles * (vcycle(lmax) + finalize(lmin_leaf))
+    b += 2 * s * n_all  # layout conversion of u on return
+    return b
+
+
+def committed_solve_traffic(tag):
+    """HBM bytes of one whole FP64 solve from the committed rocprofv3 counter
+    summary, or None if it is missing or was taken on other sources."""
+    path = os.path.join(PROFILES, f"{tag}_solve_counters.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_hash = re.search(r"library source hash:\s*`?([0-9a-f]{16})", txt)
+    m_bytes = re.search(r"HBM bytes per solve \(calibrated\):\s*([0-9.eE+]+)", txt)
+    if not m_hash or not m_bytes or m_hash.group(1) != library_source_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+def library_source_hash():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1701_04329_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_1701_04329_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def make_workload(name):
     from paper_1701_04329_amd import workloads as W
     if name == "c2":
@@ -65,23 +145,92 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(w, solve_kw):
-    """Time the oracle on the host cores: the same workload and stop rule.
-    Returns the baseline record and the oracle's solution (leaf order)."""
+def oracle_worker(args):
+    """Child process of the CPU-baseline leg (no GPU): time the oracle on the
+    OpenMP threads the parent gave this process (OMP_NUM_THREADS,
+    OMP_PROC_BIND) and print one JSON line.  Full solves use the workload's
+    stop rule; a sample is the FMG cycle and one V-cycle (or one V-cycle)."""
     from oracle import oracle as O
+    w, solve_kw = make_workload(args.workload)
     t = O.Tree(w.dim, w.N, w.level, w.idx)
-    kw = dict(solve_kw)
-    t0 = time.perf_counter()
-    u, st = t.solve(w.rho, w.bc, **kw)
-    dt = time.perf_counter() - t0
+    out = {"threads": O.num_threads(), "full_s": [], "sample_s": [], "cycles": None}
+    u = None
+    for _ in range(args.oracle_full):
+        t0 = time.perf_counter()
+        u, st = t.solve(w.rho, w.bc, **solve_kw)
+        out["full_s"].append(time.perf_counter() - t0)
+        out["cycles"] = st["cycles"]
+    for _ in range(args.oracle_sample):
+        t0 = time.perf_counter()
+        t.solve(w.rho, w.bc, **dict(solve_kw, fixed_cycles=1))
+        out["sample_s"].append(time.perf_counter() - t0)
+    if args.oracle_save and u is not None:
+        np.save(args.oracle_save, u)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def run_oracle_worker(workload, threads, full, sample, save=None):
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads), OMP_PROC_BIND="close")
+    cmd = [sys.executable, os.path.abspath(__file__), "--oracle-worker", "--workload", workload,
+           "--oracle-full", str(full), "--oracle-sample", str(sample)]
+    if save:
+        cmd += ["--oracle-save", save]
+    r = subprocess.run(cmd, env=env, capture_output=True, text=True, check=True)
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def cpu_baseline(w, solve_kw, workload):
+    """The oracle on the host, in child processes with OMP_PROC_BIND=close:
+    on all cores this process may use (the OpenMP thread count of the box),
+    median of 3 full solves with the workload's stop rule; on one core,
+    median of 3 bounded samples (the FMG cycle and one V-cycle), scaled to a
+    full solve by the all-core ratio of full-solve to sample time.  Returns
+    the baseline record and the oracle's solution (leaf order)."""
+    import tempfile
+    threads = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)))
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "oracle_u.npy")
+        allc = run_oracle_worker(workload, threads, 3, 3, path)
+        u = np.load(path)
+    one = run_oracle_worker(workload, 1, 0, 3)
+    t_full = float(np.median(allc["full_s"]))
+    t_samp = float(np.median(allc["sample_s"]))
+    ratio = t_full / t_samp
+    t_one = float(np.median(one["sample_s"])) * ratio
+    cyc = allc["cycles"]
+    fmg = "FMG + " if solve_kw.get("cycle") == "FMG" else ""
     return u, {
-        "value": w.n_unknowns / dt,
+        "value": w.n_unknowns / t_full,
         "unit": "unknowns/s",
-        "cores": O.num_threads(),
+        "cores": allc["threads"],
         "kind": "oracle",
-        "sample": f"one full solve of the benchmark workload ({w.n_unknowns} unknowns, "
-                  f"{'FMG + ' if kw.get('cycle') == 'FMG' else ''}{st['cycles']} V-cycles to "
-                  f"{kw.get('tol', 1e-10):g}), FP64, OpenMP over boxes, {dt:.1f} s",
+        "sample": f"median of 3 full solves of the benchmark workload ({w.n_unknowns} unknowns, {fmg}{cyc} "
+                  f"V-cycles to {solve_kw.get('tol', 1e-10):g}), FP64, OpenMP over boxes, {allc['threads']} "
+                  f"threads, OMP_PROC_BIND=close: {', '.join(f'{x:.2f}' for x in allc['full_s'])} s",
+        "cpu_model": cpu_model(),
+        "nproc": os.cpu_count(),
+        "affinity_cpus": len(os.sched_getaffinity(0)),
+        "omp_proc_bind": "close",
+        "one_core": {
+            "value": w.n_unknowns / t_one,
+            "unit": "unknowns/s",
+            "cores": one["threads"],
+            "sample": f"median of 3 samples ({fmg}1 V-cycle) on 1 thread: "
+                      f"{', '.join(f'{x:.2f}' for x in one['sample_s'])} s, scaled by the all-core "
+                      f"full/sample time ratio {ratio:.3f} to {t_one:.1f} s per full solve",
+        },
+        "speedup_all_vs_one_core": t_one / t_full,
     }
 
 
@@ -168,6 +317,26 @@ def batch_bench(args, A, torch, dev, stream):
         sols[precision] = [[t.boxes_to_leaf(x).cpu().numpy() for t, x in zip(g["trees"], g["b"].split(g["u"]))]
                            for g in groups]
     pool.shutdown()
+    # dominant kernel of the batch: the half sweep of the 3D batch's level
+    # with the most boxes, timed with event pairs in one eager FP64 solve of
+    # fixed length (FMG + 8 V-cycles), so that every tree takes part in every
+    # launch of that level
+    roof = None
+    g3 = [g for g in groups if g["dim"] == 3]
+    if g3:
+        g = g3[0]
+        counts = {}
+        for t in g["trees"]:
+            for l in range(1, t.lmax + 1):
+                counts[l] = counts.get(l, 0) + len(t.level_list(l, "all"))
+        lbusy = max(counts, key=lambda l: counts[l])
+        _, stp = A.solve_batch(g["b"], g["rho"], None, g["u"], cycle="FMG", fixed_cycles=8, precision="fp64",
+                               workspace=g["work"]["fp64"], stream=stream, use_guess=False, profile=True,
+                               prof_level=lbusy)
+        cells = counts[lbusy] * g["b"].cells_per_box
+        roof = gsrb_roofline(stp[0]["prof_ms"][0], stp[0]["prof_n"][0], cells,
+                             f"k_gsrb<3,8,double,W,true> (3D batch, level {lbusy}: {counts[lbusy]} boxes of "
+                             f"{len(g['trees'])} trees; forest variant)")
     # per-tree error of the mixed solution against the FP64 one
     errs = [float(np.linalg.norm(m - f) / np.linalg.norm(f))
             for gm, gf in zip(sols["mixed"], sols["fp64"]) for m, f in zip(gm, gf)]
@@ -205,6 +374,7 @@ def batch_bench(args, A, torch, dev, stream):
         "unbatched_mixed_ms": unbatched_ms,
         "untuned": untuned,
         "oracle_rel_l2_smallest_trees": oracle,
+        "roofline": roof,
         "generation_s": round(gen_s, 1),
         "note": "one step = every tree solved (FMG, then V(2,2) until its own residual dropped by 1e-10); "
                 "one batch per dimension, each on its own stream driven by its own host thread, cycles "
@@ -221,6 +391,61 @@ def timed_loop(args, torch, fn):
         r = fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) * 1e3 / args.steps, r
+
+
+def gsrb_roofline(prof_ms, prof_n, cells, kernel):
+    """Roofline record of the half sweep timed by opts.profile: 12 B per
+    cell of the level in FP64 (other colour and own rho read, own colour
+    written, 1.5 x 8 B) over the average launch time."""
+    avg = prof_ms / max(prof_n, 1)
+    achieved = 12.0 * cells / (avg * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kernel,
+            "algorithmic_bytes_per_launch": 12.0 * cells, "avg_launch_ms": round(avg, 5),
+            "launches_timed": int(prof_n)}
+
+
+def c1_bench(args, A, torch, dev, stream):
+    """The 2D uniform 128^2 workload (16,384 unknowns, u = exp(-|x-x0|^2/0.01),
+    zero Dirichlet values), V(2,2) cycles to a 1e-10 residual reduction in
+    FP64.  The whole state is about 1 MB, so the solve is latency-bound: time
+    and unknowns/s are reported, no HBM fraction.  Checked against the
+    oracle's solve of the same problem."""
+    from oracle import oracle as O
+    from paper_1701_04329_amd import workloads as W
+    w = W.config1()
+    tree = A.Tree(w.dim, w.level, w.idx)
+    rho = tree.leaf_to_boxes(torch.tensor(w.rho, device=dev))
+    u = torch.zeros_like(rho)
+    work = torch.empty(tree.workspace_bytes(A.make_opts()), dtype=torch.uint8, device=dev)
+    n = max(args.steps, 50)
+    out = {"workload": w.name, "unknowns": int(w.n_unknowns), "boxes": int(tree.n_boxes),
+           "cycle": "V(2,2)", "tol": 1e-10, "steps": n}
+    for graph in (False, True):
+        def one():
+            return A.solve(tree, rho, None, u, cycle="V", tol=1e-10, workspace=work, stream=stream,
+                           use_guess=False, graph=graph)
+        for _ in range(max(args.warmup, 3)):
+            one()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(n):
+            t0 = time.perf_counter()
+            _, st = one()
+            times.append(time.perf_counter() - t0)
+        ms = float(np.median(times)) * 1e3
+        key = "graph" if graph else "eager"
+        out[key] = {"ms_per_solve_median": ms, "value": w.n_unknowns / (ms * 1e-3), "unit": "unknowns/s",
+                    "cycles": st["cycles"], "final_residual_ratio": st["r_max"] / st["r0_max"]}
+    ug = tree.boxes_to_leaf(u).cpu().numpy()
+    t0 = time.perf_counter()
+    uo, so = O.Tree(w.dim, w.N, w.level, w.idx).solve(w.rho, w.bc, cycle="V", tol=1e-10)
+    out["oracle"] = {"ms": (time.perf_counter() - t0) * 1e3, "cycles": so["cycles"], "cores": O.num_threads()}
+    out["rel_l2_vs_oracle"] = float(np.linalg.norm(ug - uo) / np.linalg.norm(uo))
+    out["max_cell_vs_oracle"] = float(np.abs(ug - uo).max() / np.abs(uo).max())
+    out["note"] = "latency-bound (about 1 MB of state); median host wall time per solve, including its " \
+                  "per-cycle norm readbacks"
+    return out
 
 
 def adaptive_bench(args, A, torch, dev, stream):
@@ -253,6 +478,17 @@ def adaptive_bench(args, A, torch, dev, stream):
                           "cycles": st["cycles"], "final_residual_ratio": st["r_max"] / st["r0_max"]}
     nrm = np.linalg.norm(sols["fp64"])
     out["mixed"]["rel_l2_vs_gpu_fp64"] = float(np.linalg.norm(sols["mixed"] - sols["fp64"]) / nrm)
+    # dominant kernel: the finest-level half sweep (the finest level holds
+    # most of the cells), timed with event pairs in one eager FP64 solve
+    _, stp = A.solve(tree, rho, bc, u, cycle="FMG", tol=1e-10, workspace=work, stream=stream, use_guess=False,
+                     profile=True)
+    n_fine = len(tree.level_list(tree.lmax, "all")) * tree.cells_per_box
+    out["roofline"] = gsrb_roofline(stp["prof_ms"][0], stp["prof_n"][0], n_fine,
+                                    f"k_gsrb<3,8,double,W,false> (finest level {tree.lmax}, "
+                                    f"{n_fine // tree.cells_per_box} boxes)")
+    bm = solve_byte_model(tree, out["fp64"]["cycles"], True)
+    out["fp64"]["byte_model_bytes"] = bm
+    out["fp64"]["byte_model_frac"] = round(bm / (out["fp64"]["ms_per_step"] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         uo, so = O.Tree(w.dim, w.N, w.level, w.idx).solve(w.rho, w.bc, cycle="FMG", tol=1e-10)
@@ -376,7 +612,18 @@ def main():
                     help="run only the batch workload and print its record (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (for HBM counter calibration)")
+    ap.add_argument("--solve-only", action="store_true",
+                    help="run only warmup + steps FP64 solves of the workload with the default launch shapes, "
+                         "eager (for whole-solve HBM counters)")
+    ap.add_argument("--no-c1", action="store_true", help="skip the 2D 128^2 latency-bound workload")
+    ap.add_argument("--oracle-worker", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--oracle-full", type=int, default=0, help=argparse.SUPPRESS)
+    ap.add_argument("--oracle-sample", type=int, default=0, help=argparse.SUPPRESS)
+    ap.add_argument("--oracle-save", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
+
+    if args.oracle_worker:
+        return oracle_worker(args)
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solve is not "
@@ -403,6 +650,27 @@ def main():
 
     if args.batch_only:
         print(json.dumps(batch_bench(args, A, torch, dev, torch.cuda.current_stream(dev))), flush=True)
+        return 0
+
+    if args.solve_only:
+        w, solve_kw = make_workload(args.workload)
+        tree = A.Tree(w.dim, w.level, w.idx)
+        rho = tree.leaf_to_boxes(torch.tensor(w.rho, device=dev))
+        bc = tree.bc_rows(torch.tensor(w.bc, device=dev)) if tree.n_bfaces else None
+        u = torch.zeros_like(rho)
+        ws = torch.empty(tree.workspace_bytes(A.make_opts(**solve_kw)), dtype=torch.uint8, device=dev)
+        stream = torch.cuda.current_stream(dev)
+        for _ in range(args.warmup):
+            A.solve(tree, rho, bc, u, workspace=ws, stream=stream, use_guess=False, **solve_kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, st = A.solve(tree, rho, bc, u, workspace=ws, stream=stream, use_guess=False, **solve_kw)
+        torch.cuda.synchronize()
+        print(json.dumps({"workload": w.name, "solves": args.steps, "warmup": args.warmup,
+                          "ms_per_solve": (time.perf_counter() - t0) * 1e3 / max(args.steps, 1),
+                          "v_cycles": st["cycles"], "library_source_hash": library_source_hash(),
+                          "launch": "eager, default launch shapes"}), flush=True)
         return 0
 
     w, solve_kw = make_workload(args.workload)
@@ -509,6 +777,23 @@ def main():
     graph = {"fp64_ms_per_step": ms_g, "mixed_ms_per_step": ms_gm,
              "fp64_value": w.n_unknowns / (ms_g * 1e-3), "mixed_value": w.n_unknowns / (ms_gm * 1e-3)}
 
+    # the whole solve against the algorithmic byte model and, where the
+    # committed counter summary matches these sources, the measured HBM bytes
+    bm = solve_byte_model(tree, int(np.median(cycles)), solve_kw["cycle"] == "FMG")
+    hbm = committed_solve_traffic(w.name)
+    solve_level = {
+        "v_cycles": int(np.median(cycles)),
+        "byte_model_bytes": bm,
+        "byte_model_GBs": round(bm / (ms * 1e-3) / 1e9, 1),
+        "byte_model_frac": round(bm / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+        "hbm_bytes_measured": hbm,
+        "hbm_GBs": round(hbm / (ms * 1e-3) / 1e9, 1) if hbm else None,
+        "hbm_frac": round(hbm / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4) if hbm else None,
+        "note": "byte model: every array a kernel touches once per launch, the scheduler's launch sequence; "
+                "measured: calibrated FETCH_SIZE + WRITE_SIZE summed over one solve's dispatches "
+                "(profiles/, default launch shapes)",
+    }
+
     out = {
         "metric": "Poisson unknowns/s to 1e-10 residual reduction (FP64 vs mixed); HBM % of peak",
         "value": value,
@@ -536,10 +821,13 @@ def main():
             "schedule": "eager launches, event pairs in the last timed solve; autotuned launch shapes",
         },
         "roofline": roofline,
+        "solve": solve_level,
         "mixed": mixed,
         "graph": graph,
         "autotune": tune,
     }
+    if not args.no_c1:
+        out["c1"] = c1_bench(args, A, torch, dev, stream)
     if not args.no_batch:
         out["batch"] = batch_bench(args, A, torch, dev, stream)
     if not args.no_adaptive:
@@ -549,7 +837,7 @@ def main():
     if not args.no_paper_ex:
         out["paper_ex"] = paper_ex_bench(args, A, torch, dev, stream)
     if not args.no_cpu_baseline:
-        uo, out["cpu_baseline"] = cpu_baseline(w, solve_kw)
+        uo, out["cpu_baseline"] = cpu_baseline(w, solve_kw, args.workload)
         nrm = np.linalg.norm(uo)
         out["config"]["rel_l2_vs_oracle"] = float(np.linalg.norm(u64 - uo) / nrm)
         out["mixed"]["rel_l2_vs_oracle"] = float(np.linalg.norm(umx - uo) / nrm)

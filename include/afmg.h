@@ -87,10 +87,13 @@ typedef struct {
                          those cycles; a solve may run up to check_every - 1
                          cycles past convergence; stats history entries of
                          the unchecked cycles are NaN. */
+    int prof_level;   /* level whose launches opts.profile times (2 .. lmax;
+                         0: the finest level, the default) */
 } afmg_opts;
 
-/* kernel classes timed when opts.profile is set (finest level only; a
-   finest level <= 2 runs inside the coarse kernel and is not timed) */
+/* kernel classes timed when opts.profile is set (on level opts.prof_level,
+   by default the finest; levels <= 2 run inside the coarse kernel and are
+   not timed) */
 enum {
     AFMG_PROF_GSRB = 0,      /* one red or black half sweep (in the mixed
                                 path of a tree whose leaves all lie on its

@@ -45,6 +45,7 @@ class Opts(C.Structure):
         ("profile", C.c_int),
         ("graph", C.c_int),
         ("check_every", C.c_int),
+        ("prof_level", C.c_int),
     ]
 
 
@@ -194,7 +195,7 @@ def _check(rc, allow=(AFMG_OK,)):
 
 
 def make_opts(cycle="V", n_down=2, n_up=2, n_base=4, tol=1e-10, max_cycles=100, fixed_cycles=0,
-              use_guess=False, precision="fp64", profile=False, graph=False, check_every=1):
+              use_guess=False, precision="fp64", profile=False, graph=False, check_every=1, prof_level=0):
     o = Opts()
     lib().afmg_default_opts(C.byref(o))
     o.cycle = CYCLES[cycle]
@@ -207,6 +208,7 @@ def make_opts(cycle="V", n_down=2, n_up=2, n_base=4, tol=1e-10, max_cycles=100, 
     o.profile = 1 if profile else 0
     o.graph = 1 if graph else 0
     o.check_every = check_every
+    o.prof_level = prof_level
     return o
 
 
@@ -373,7 +375,7 @@ def _ptr(t):
 
 def solve(tree: Tree, rho, bc=None, u=None, *, cycle="V", tol=1e-10, max_cycles=100, fixed_cycles=0,
           n_down=2, n_up=2, n_base=4, precision="fp64", workspace=None, stream=None, check=True,
-          profile=False, use_guess=None, graph=False, check_every=1):
+          profile=False, use_guess=None, graph=False, check_every=1, prof_level=0):
     """Solve lap_h(u) = rho on `tree`.
 
     rho, u: torch float64 CUDA tensors [n_boxes, N^D] in box order; bc:
@@ -399,7 +401,7 @@ def solve(tree: Tree, rho, bc=None, u=None, *, cycle="V", tol=1e-10, max_cycles=
             raise ValueError("bc has the wrong dtype or size")
         bc = bc.contiguous()
     opts = make_opts(cycle, n_down, n_up, n_base, tol, max_cycles, fixed_cycles, use_guess, precision,
-                     profile, graph, check_every)
+                     profile, graph, check_every, prof_level)
     nbytes = tree.workspace_bytes(opts)
     if workspace is None or workspace.numel() * workspace.element_size() < nbytes:
         workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
@@ -503,7 +505,7 @@ class Batch(_Shapes):
 
 def solve_batch(batch: Batch, rho, bc=None, u=None, *, cycle="V", tol=1e-10, max_cycles=100, fixed_cycles=0,
                 n_down=2, n_up=2, n_base=4, precision="fp64", workspace=None, stream=None, check=True,
-                profile=False, use_guess=None, graph=False, check_every=1):
+                profile=False, use_guess=None, graph=False, check_every=1, prof_level=0):
     """afmg_solve on every tree of the batch.  rho, u: float64 device tensors
     [batch.n_boxes, N^D] (the trees' arrays one after the other); bc: the
     trees' Dirichlet rows one after the other, or None.  Returns (u, list of
@@ -525,7 +527,7 @@ def solve_batch(batch: Batch, rho, bc=None, u=None, *, cycle="V", tol=1e-10, max
             raise ValueError("bc has the wrong dtype or size")
         bc = bc.contiguous()
     opts = make_opts(cycle, n_down, n_up, n_base, tol, max_cycles, fixed_cycles, use_guess, precision,
-                     profile, graph, check_every)
+                     profile, graph, check_every, prof_level)
     nbytes = batch.workspace_bytes(opts)
     if workspace is None or workspace.numel() * workspace.element_size() < nbytes:
         workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)

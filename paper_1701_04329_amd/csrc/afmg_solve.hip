@@ -285,6 +285,7 @@ int check_opts(const afmg_opts *o) {
         return fail(AFMG_ERR_ARG, "tol / max_cycles / fixed_cycles out of range");
     if (o->precision != AFMG_FP64 && o->precision != AFMG_MIXED) return fail(AFMG_ERR_ARG, "bad precision");
     if (o->check_every < 0 || o->check_every > 1000) return fail(AFMG_ERR_ARG, "check_every out of range");
+    if (o->prof_level < 0 || o->prof_level > 64) return fail(AFMG_ERR_ARG, "prof_level out of range");
     return AFMG_OK;
 }
 
@@ -297,7 +298,7 @@ struct Prof {
     afmg_tree *t;
     hipStream_t st;
     bool on;
-    int lmax;
+    int lmax;  // the level whose launches are timed (opts.prof_level, else the finest)
     afmg_stats *stats;
     std::vector<std::array<int, 3>> pending;  // (kernel class, event pair, launches)
 
@@ -473,7 +474,8 @@ struct Solver {
     double *partial;
 
     Solver(afmg_tree *t_, hipStream_t s, const afmg_opts &o_, afmg_stats *S)
-        : t(t_), h(t_->h), st(s), o(o_), prof{t_, s, o_.profile != 0, t_->h.lmax, S, {}} {}
+        : t(t_), h(t_->h), st(s), o(o_),
+          prof{t_, s, o_.profile != 0, o_.prof_level > 0 ? o_.prof_level : t_->h.lmax, S, {}} {}
 
     // Restriction of u into parents and the composite leaf residual (FP64),
     // reduced to (max, L2) per tree in norm; rout receives the FP32 leaf
@@ -1298,6 +1300,7 @@ void afmg_default_opts(afmg_opts *o) {
     o->use_guess = 0;
     o->precision = AFMG_FP64;
     o->profile = 0;
+    o->prof_level = 0;
     o->graph = 0;
     o->check_every = 1;
 }
