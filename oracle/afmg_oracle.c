@@ -10,8 +10,11 @@
  * Data model (paper §2.1): every box holds n^D cells plus one stored ghost
  * layer, so each field of a box is an (n+2)^D array indexed 1..n in the
  * interior and 0 / n+1 in the ghost layer (1-based, as the paper numbers
- * cells).  Boxes of the tree have n = N; below the root (level 1) extra coarse
- * grids of N/2, N/4, ..., 2 cells per side are added (paper §3.2, V-cycle).
+ * cells).  Boxes of the tree have n = N.  The coarse grid (paper §2.2) is
+ * one or more level-1 boxes on an integer lattice; below each of them extra
+ * coarse grids of N/2, N/4, ..., 2 cells per side are added (paper §3.2,
+ * V-cycle), linked like their level-1 boxes.  Each side orientation of the
+ * domain is Dirichlet, Neumann or periodic (paper §3).
  *
  * Steps, each following the paper:
  *   fill_gc      side ghost cells: same-level copy, Dirichlet, or the default
@@ -26,9 +29,10 @@
  * Readings where the paper is silent (each also listed in the design notes):
  *   - red cells are those whose 1-based global index sum is even;
  *   - side ghosts are refreshed before every half sweep;
- *   - a Dirichlet ghost is 2 b - u1 (linear through the face value b);
- *   - Dirichlet values of non-leaf boxes are the means of their children's
- *     face values;
+ *   - a Dirichlet ghost is 2 b - u1 (linear through the face value b), a
+ *     Neumann ghost u1 + h q (q the outward normal derivative at the face);
+ *   - boundary values (Dirichlet or Neumann) of non-leaf boxes are the means
+ *     of their children's face values;
  *   - the copy v'_H includes side ghosts filled right after restriction;
  *   - the stop test uses the max-norm of the composite leaf residual relative
  *     to that of the zero initial guess.
@@ -61,6 +65,9 @@ typedef struct {
     int *lvl_first[OR_MAXLEV];
     int lvl_cnt[OR_MAXLEV];
     int *lvl_store;
+    int bctype[6];  /* side type per orientation (OR_DIRICHLET, OR_NEUMANN, OR_PERIODIC) */
+    int ext[3];     /* extent of the coarse-grid lattice (level-1 boxes) per axis */
+    int nroot;      /* level-1 boxes */
 } otree;
 
 /* ------------------------------------------------------------------------ */
@@ -139,11 +146,34 @@ static void seterr(char *err, int errlen, const char *msg) {
 /* ------------------------------------------------------------------------ */
 void or_tree_free(void *p);
 
-void *or_tree_new(int dim, int N, int64_t n_leaves, const int32_t *level, const int32_t *idx,
-                  char *err, int errlen) {
+/* Side types of the domain boundary (paper §3: Dirichlet, Neumann or
+   periodic, or a mix), one per side orientation -x, +x, -y, +y, -z, +z. */
+#define OR_DIRICHLET 0
+#define OR_NEUMANN 1
+#define OR_PERIODIC 2
+
+/* The coarse grid (paper §2.2) is the set of level-1 boxes that contain
+   leaves: boxes of unit size at 1-based lattice positions 1..ext[d] along
+   each axis, which may leave out positions (an L-shaped domain).  Each root
+   box gets its own chain of extra coarse grids of N/2, ..., 2 cells per side
+   below level 1 (paper §3.2), linked to the chains of its neighbouring roots,
+   so a domain of several roots has several 2^D-cell boxes on its coarsest
+   level.  A periodic axis wraps the neighbour search around the lattice and
+   needs a rectangular coarse grid. */
+void *or_tree_new_bc(int dim, int N, const int32_t *bctype, int64_t n_leaves, const int32_t *level,
+                     const int32_t *idx, char *err, int errlen) {
     if (dim != 2 && dim != 3) { seterr(err, errlen, "dim must be 2 or 3"); return NULL; }
     if (N < 2 || (N & (N - 1))) { seterr(err, errlen, "N must be a power of two >= 2"); return NULL; }
     if (n_leaves <= 0) { seterr(err, errlen, "no leaves"); return NULL; }
+    int bct[6] = {0, 0, 0, 0, 0, 0};
+    for (int s = 0; s < 2 * dim; s++) {
+        bct[s] = bctype ? bctype[s] : OR_DIRICHLET;
+        if (bct[s] < OR_DIRICHLET || bct[s] > OR_PERIODIC) { seterr(err, errlen, "bad side type"); return NULL; }
+    }
+    for (int d = 0; d < dim; d++)
+        if ((bct[2 * d] == OR_PERIODIC) != (bct[2 * d + 1] == OR_PERIODIC)) {
+            seterr(err, errlen, "periodic sides come in pairs"); return NULL;
+        }
     int lg = 0;
     while ((2 << lg) < N) lg++; /* N = 2^(lg+1) */
     otree *t = (otree *)calloc(1, sizeof(otree));
@@ -151,6 +181,22 @@ void *or_tree_new(int dim, int N, int64_t n_leaves, const int32_t *level, const 
     t->N = N;
     t->lmin = 1 - lg;
     t->lmax = 1;
+    for (int s = 0; s < 6; s++) t->bctype[s] = bct[s];
+    t->ext[0] = t->ext[1] = t->ext[2] = 1;
+    for (int64_t q = 0; q < n_leaves; q++) {
+        int l = level[q], c[3] = {idx[3 * q], idx[3 * q + 1], dim == 3 ? idx[3 * q + 2] : 1};
+        if (l < 1 || l > 18) { seterr(err, errlen, "leaf level out of range [1,18]"); free(t); return NULL; }
+        for (int d = 0; d < 3; d++) {
+            if (c[d] < 1 || c[d] >= (1 << 19) || (d == 2 && dim == 2 && c[d] != 1)) {
+                seterr(err, errlen, "leaf spatial index out of range"); free(t); return NULL;
+            }
+            int r = ((c[d] - 1) >> (l - 1)) + 1;
+            if (r > t->ext[d]) t->ext[d] = r;
+        }
+    }
+    if ((int64_t)t->ext[0] * t->ext[1] * t->ext[2] > 4096) {
+        seterr(err, errlen, "coarse grid larger than 4096 boxes"); free(t); return NULL;
+    }
     ohash h;
     int64_t cap = n_leaves * 2 + 64;
     if (oh_init(&h, cap) != 0) { free(t); seterr(err, errlen, "out of memory"); return NULL; }
@@ -161,11 +207,6 @@ void *or_tree_new(int dim, int N, int64_t n_leaves, const int32_t *level, const 
     int nb = 0;
     for (int64_t q = 0; q < n_leaves; q++) {
         int l = level[q], i = idx[3 * q], j = idx[3 * q + 1], k = dim == 3 ? idx[3 * q + 2] : 1;
-        if (l < 1 || l > 18) { seterr(err, errlen, "leaf level out of range [1,18]"); goto fail; }
-        int n1 = 1 << (l - 1);
-        if (i < 1 || i > n1 || j < 1 || j > n1 || k < 1 || k > (dim == 3 ? n1 : 1)) {
-            seterr(err, errlen, "leaf spatial index out of range"); goto fail;
-        }
         if (oh_put(&h, okey(l, i, j, k), nb) >= 0) { seterr(err, errlen, "duplicate leaf"); goto fail; }
         L[nb] = l; I[nb] = i; J[nb] = j; K[nb] = k; isleaf[nb] = 1;
         nb++;
@@ -194,9 +235,19 @@ void *or_tree_new(int dim, int N, int64_t n_leaves, const int32_t *level, const 
             nb++;
         }
     }
-    /* final numbering: coarse grids first (levels lmin..0), then tree boxes in
-       the provisional order, grouped by level */
-    int ncoarse = 1 - t->lmin;
+    /* the roots: level-1 boxes, in provisional order */
+    int nroot = 0;
+    for (int q = 0; q < nb; q++) if (L[q] == 1) nroot++;
+    t->nroot = nroot;
+    int periodic_any = 0;
+    for (int d = 0; d < dim; d++) periodic_any |= bct[2 * d] == OR_PERIODIC;
+    if (periodic_any && nroot != t->ext[0] * t->ext[1] * (dim == 3 ? t->ext[2] : 1)) {
+        seterr(err, errlen, "periodic sides need a rectangular coarse grid"); goto fail;
+    }
+    /* final numbering: coarse grids first (levels lmin..0, nroot boxes each,
+       box (l, r) at (l - lmin) * nroot + r), then the tree boxes level by
+       level in provisional order, so root r is box ncoarse + r */
+    int ncoarse = (1 - t->lmin) * nroot;
     t->nbox = nb + ncoarse;
     int B = t->nbox;
     t->lev = malloc(sizeof(int) * B); t->ix = malloc(sizeof(int) * B); t->iy = malloc(sizeof(int) * B);
@@ -205,12 +256,7 @@ void *or_tree_new(int dim, int N, int64_t n_leaves, const int32_t *level, const 
     t->nbr = malloc(sizeof(int) * B * 6); t->off = malloc(sizeof(int64_t) * B);
     t->bcoff = malloc(sizeof(int64_t) * B * 6);
     int *newid = malloc(sizeof(int) * nb);
-    int pos = 0;
-    for (int l = t->lmin; l <= 0; l++) {
-        t->lev[pos] = l; t->ix[pos] = t->iy[pos] = t->iz[pos] = 1;
-        t->n[pos] = N >> (1 - l); t->leaf[pos] = 0;
-        pos++;
-    }
+    int pos = ncoarse;
     for (int l = 1; l <= t->lmax; l++)
         for (int q = 0; q < nb; q++)
             if (L[q] == l) {
@@ -219,6 +265,12 @@ void *or_tree_new(int dim, int N, int64_t n_leaves, const int32_t *level, const 
                 t->n[pos] = N; t->leaf[pos] = isleaf[q];
                 pos++;
             }
+    for (int l = t->lmin; l <= 0; l++)
+        for (int r = 0; r < nroot; r++) {
+            int b = (l - t->lmin) * nroot + r, R = ncoarse + r;
+            t->lev[b] = l; t->ix[b] = t->ix[R]; t->iy[b] = t->iy[R]; t->iz[b] = t->iz[R];
+            t->n[b] = N >> (1 - l); t->leaf[b] = 0;
+        }
     for (int64_t p = 0; p < h.cap; p++) if (h.key[p]) h.val[p] = newid[h.val[p]];
     t->nleaf_in = (int)n_leaves;
     t->leaf_box = malloc(sizeof(int) * n_leaves);
@@ -233,7 +285,10 @@ void *or_tree_new(int dim, int N, int64_t n_leaves, const int32_t *level, const 
     for (int b = 0; b < B; b++) {
         int l = t->lev[b];
         if (l <= 1) {
-            t->parent[b] = l > t->lmin ? (l - 1 - t->lmin) : -1; /* coarse grid box ids are l - lmin */
+            /* chain of root r: (l - 1, r) is the parent of (l, r), and the
+               coarse box covers its only child completely */
+            int r = l == 1 ? b - ncoarse : b % nroot;
+            t->parent[b] = l > t->lmin ? (l - 1 - t->lmin) * nroot + r : -1;
             if (t->parent[b] >= 0) t->child[8 * t->parent[b]] = b;
             continue;
         }
@@ -248,27 +303,44 @@ void *or_tree_new(int dim, int N, int64_t n_leaves, const int32_t *level, const 
         for (int c = 0; c < nch; c++)
             if (t->child[8 * b + c] < 0) { seterr(err, errlen, "leaves do not tile the domain (missing child)"); goto fail2; }
     }
-    /* neighbours */
-    for (int b = 0; b < B; b++) {
+    /* neighbours of the tree boxes: same-level box, physical side (-1:
+       outside the lattice on a non-periodic axis, or a lattice position
+       without a root), or refinement boundary (-2) */
+    for (int b = ncoarse; b < B; b++) {
         int l = t->lev[b];
         for (int s = 0; s < 6; s++) t->nbr[6 * b + s] = -1;
-        if (l < 1) continue;
-        int n1 = 1 << (l - 1);
         for (int s = 0; s < 2 * dim; s++) {
             int d = s / 2, dir = (s % 2) ? 1 : -1;
             int q[3] = {t->ix[b], t->iy[b], t->iz[b]};
+            int n1 = t->ext[d] << (l - 1);
             q[d] += dir;
-            if (q[d] < 1 || q[d] > n1) { t->nbr[6 * b + s] = -1; continue; }
+            if (q[d] < 1 || q[d] > n1) {
+                if (bct[s] != OR_PERIODIC) continue;
+                q[d] = q[d] < 1 ? n1 : 1;
+            }
             int nb2 = oh_get(&h, okey(l, q[0], q[1], q[2]));
             if (nb2 >= 0) { t->nbr[6 * b + s] = nb2; continue; }
+            int rq[3] = {((q[0] - 1) >> (l - 1)) + 1, ((q[1] - 1) >> (l - 1)) + 1,
+                         dim == 3 ? ((q[2] - 1) >> (l - 1)) + 1 : 1};
+            if (oh_get(&h, okey(1, rq[0], rq[1], rq[2])) < 0) continue; /* a hole in the coarse grid */
             t->nbr[6 * b + s] = -2;
             /* 2:1 balance: the parent's neighbour must exist */
             int p = t->parent[b];
             int pq[3] = {t->ix[p], t->iy[p], t->iz[p]};
+            int n0 = t->ext[d] << (l - 2);
             pq[d] += dir;
+            if (pq[d] < 1 || pq[d] > n0) pq[d] = pq[d] < 1 ? n0 : 1; /* periodic here */
             if (oh_get(&h, okey(l - 1, pq[0], pq[1], pq[2])) < 0) {
                 seterr(err, errlen, "grid violates 2:1 balance across a box side"); goto fail2;
             }
+        }
+    }
+    /* neighbours on the coarse grids below level 1 mirror those of the roots */
+    for (int b = 0; b < ncoarse; b++) {
+        int r = b % nroot, l = t->lev[b];
+        for (int s = 0; s < 6; s++) {
+            int v = t->nbr[6 * (ncoarse + r) + s];
+            t->nbr[6 * b + s] = v >= 0 ? (l - t->lmin) * nroot + (v - ncoarse) : -1;
         }
     }
     /* level lists */
@@ -313,6 +385,17 @@ fail:
     return NULL;
 }
 
+/* one root box on [0,1]^D with Dirichlet sides */
+void *or_tree_new(int dim, int N, int64_t n_leaves, const int32_t *level, const int32_t *idx,
+                  char *err, int errlen) {
+    for (int64_t q = 0; q < n_leaves; q++) {
+        int l = level[q], n1 = (l >= 1 && l <= 18) ? 1 << (l - 1) : 0;
+        for (int d = 0; d < dim; d++)
+            if (idx[3 * q + d] > n1) { seterr(err, errlen, "leaf spatial index out of range"); return NULL; }
+    }
+    return or_tree_new_bc(dim, N, NULL, n_leaves, level, idx, err, errlen);
+}
+
 void or_tree_free(void *p) {
     otree *t = (otree *)p;
     if (!t) return;
@@ -325,11 +408,12 @@ void or_tree_free(void *p) {
 
 const char *or_last_error(void) { return or_errbuf; }
 
-/* info: [nbox, lmin, lmax, n_leaf_in, dim, N] */
+/* info: [nbox, lmin, lmax, n_leaf_in, dim, N, nroot, ext0, ext1, ext2] */
 void or_tree_info(void *p, int64_t *out) {
     otree *t = (otree *)p;
     out[0] = t->nbox; out[1] = t->lmin; out[2] = t->lmax; out[3] = t->nleaf_in;
-    out[4] = t->dim; out[5] = t->N;
+    out[4] = t->dim; out[5] = t->N; out[6] = t->nroot;
+    out[7] = t->ext[0]; out[8] = t->ext[1]; out[9] = t->ext[2];
 }
 
 /* per box: [level, ix, iy, iz, n, parent, leaf, nbr0..nbr5] */
@@ -484,7 +568,10 @@ static void fill_gc(otree *t, int l, double *f, int homog) {
                         f[ig] = f[PX(t, nb, q[0], q[1], q[2])];
                     } else if (nb == -1) {
                         double bv = homog ? 0.0 : t->bc[t->bcoff[6 * b + s] + (a - 1) + (int64_t)n * ((D == 3 ? c : 1) - 1)];
-                        f[ig] = 2.0 * bv - u1;
+                        if (t->bctype[s] == OR_NEUMANN)
+                            f[ig] = u1 + level_h(t, t->lev[b]) * bv; /* outward derivative bv across the face */
+                        else
+                            f[ig] = 2.0 * bv - u1;                  /* value bv at the face */
                     } else {
                         /* refinement boundary: coarse value from the parent's neighbour */
                         int p = t->parent[b];
@@ -926,7 +1013,8 @@ int64_t or_assemble_L(void *p, int32_t *rows, int32_t *cols, double *vals) {
                         }
                     }
                 } else if (nb == -1) {
-                    diag -= ih2;
+                    /* physical side: ghost -u_c (Dirichlet) or +u_c (Neumann) */
+                    diag += t->bctype[s] == OR_NEUMANN ? ih2 : -ih2;
                 } else {
                     int par = t->parent[b];
                     int cb = t->nbr[6 * par + s];

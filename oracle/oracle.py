@@ -69,6 +69,8 @@ def lib():
         vp, i32p, dp = C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double)
         L.or_tree_new.restype = vp
         L.or_tree_new.argtypes = [C.c_int, C.c_int, C.c_int64, i32p, i32p, C.c_char_p, C.c_int]
+        L.or_tree_new_bc.restype = vp
+        L.or_tree_new_bc.argtypes = [C.c_int, C.c_int, i32p, C.c_int64, i32p, i32p, C.c_char_p, C.c_int]
         L.or_tree_free.argtypes = [vp]
         L.or_last_error.restype = C.c_char_p
         L.or_tree_info.argtypes = [vp, C.POINTER(C.c_int64)]
@@ -112,23 +114,50 @@ class OracleError(RuntimeError):
     pass
 
 
-class Tree:
-    """Oracle tree built from a leaf list (level int32 [n], idx int32 [n,3])."""
+BC_TYPES = {"dirichlet": 0, "neumann": 1, "periodic": 2}
 
-    def __init__(self, dim, N, level, idx):
+
+def bc_type_codes(bc_type, dim):
+    """Side types per orientation (-x, +x, -y, +y, -z, +z): None (all
+    Dirichlet), one name for all sides, or a sequence of 2D names / codes."""
+    if bc_type is None:
+        return np.zeros(6, np.int32)
+    if isinstance(bc_type, str):
+        bc_type = [bc_type] * (2 * dim)
+    out = np.zeros(6, np.int32)
+    for s, v in enumerate(bc_type):
+        out[s] = BC_TYPES[v] if isinstance(v, str) else int(v)
+    return out
+
+
+class Tree:
+    """Oracle tree built from a leaf list (level int32 [n], idx int32 [n,3]).
+    The coarse grid is the set of level-1 boxes holding the leaves (one unit
+    box at each 1-based lattice position); bc_type gives the side type of
+    each orientation (see bc_type_codes)."""
+
+    def __init__(self, dim, N, level, idx, bc_type=None):
         L = lib()
         self.dim, self.N = dim, N
         level = np.ascontiguousarray(level, dtype=np.int32)
         idx = np.ascontiguousarray(idx, dtype=np.int32).reshape(-1, 3)
         err = C.create_string_buffer(512)
-        h = L.or_tree_new(dim, N, len(level), level.ctypes.data_as(C.POINTER(C.c_int32)),
-                          idx.ctypes.data_as(C.POINTER(C.c_int32)), err, 512)
+        i32p = C.POINTER(C.c_int32)
+        if bc_type is None:
+            h = L.or_tree_new(dim, N, len(level), level.ctypes.data_as(i32p), idx.ctypes.data_as(i32p), err, 512)
+        else:
+            codes = bc_type_codes(bc_type, dim)
+            h = L.or_tree_new_bc(dim, N, codes.ctypes.data_as(i32p), len(level), level.ctypes.data_as(i32p),
+                                 idx.ctypes.data_as(i32p), err, 512)
         if not h:
             raise OracleError(err.value.decode())
         self.h = h
-        info = (C.c_int64 * 6)()
+        info = (C.c_int64 * 10)()
         L.or_tree_info(h, info)
         self.nbox, self.lmin, self.lmax, self.n_leaves = info[0], info[1], info[2], info[3]
+        self.nroot = info[6]
+        self.ext = (info[7], info[8], info[9])
+        self.bc_type = bc_type_codes(bc_type, dim)
         self.level = level
         self.idx = idx
 
@@ -278,10 +307,11 @@ def assemble_L(tree):
 
 def adjoint(tree, ubar):
     """lambda = L^-T ubar on the leaf unknowns (sparse direct solve), and the
-    gradient with respect to the Dirichlet values, -2 lambda / h^2 on the leaf
-    cells next to each physical side, as [n_leaves, 2D, N^(D-1)] (zero on
-    non-physical sides).  The derivation: u = L^-1 (rho - B b) with
-    (B b)_c = sum over the Dirichlet sides of c of 2 b / h^2."""
+    gradient with respect to the boundary values, as [n_leaves, 2D, N^(D-1)]
+    (zero on non-physical sides): -2 lambda / h^2 on the leaf cells next to a
+    Dirichlet side, -lambda / h next to a Neumann side.  The derivation:
+    u = L^-1 (rho - B b) with (B b)_c = sum over the physical sides of c of
+    2 b / h^2 (Dirichlet ghost 2 b - u_c) or b / h (Neumann ghost u_c + h b)."""
     import scipy.sparse.linalg as spla
     A = assemble_L(tree)
     # minimum-degree ordering on A + A^T keeps the fill of 3D grids small
@@ -295,15 +325,18 @@ def boundary_gradient(tree, lam):
     lam = np.asarray(lam).reshape((tree.n_leaves,) + (N,) * dim)
     h = 1.0 / (N * 2.0 ** (tree.level.astype(np.float64) - 1))
     out = np.zeros((tree.n_leaves, 2 * dim, N ** (dim - 1)))
-    nmax = 2 ** (tree.level - 1)
+    boxes = tree.leaf_boxes()
     for s in range(2 * dim):
-        d, hi = s // 2, s % 2
-        phys = (tree.idx[:, d] == (nmax if hi else 1))
-        ax = dim - 1 - d
+        phys = np.array([tree.box_info(int(b))["nbr"][s] == -1 for b in boxes])
+        ax = dim - 1 - s // 2
         sl = [slice(None)] * (dim + 1)
-        sl[1 + ax] = N - 1 if hi else 0
+        sl[1 + ax] = N - 1 if s % 2 else 0
         face = lam[tuple(sl)].reshape(tree.n_leaves, -1)
-        out[:, s, :] = np.where(phys[:, None], -2.0 * face / (h[:, None] ** 2), 0.0)
+        if tree.bc_type[s] == BC_TYPES["neumann"]:
+            g = -face / h[:, None]
+        else:
+            g = -2.0 * face / (h[:, None] ** 2)
+        out[:, s, :] = np.where(phys[:, None], g, 0.0)
     return out
 
 

@@ -146,6 +146,78 @@ def physical_side_mask(dim, level, idx):
     return m
 
 
+def domain_side_mask(dim, level, idx, bc_type=None):
+    """[n, 2D] bool: the side of each leaf lies on the domain boundary.  The
+    domain is the union of the level-1 boxes holding the leaves (unit boxes
+    on the integer lattice); a side is on the boundary when the position
+    across it is outside the lattice on a non-periodic axis or in a lattice
+    position without a level-1 box.  bc_type: None, one name, or 2D names
+    among "dirichlet", "neumann", "periodic" (pairs per axis)."""
+    level = np.asarray(level)
+    idx = np.asarray(idx)
+    types = side_types(dim, bc_type)
+    roots = {tuple(((idx[q, d] - 1) >> (level[q] - 1)) + 1 for d in range(dim)) for q in range(len(level))}
+    ext = [max(r[d] for r in roots) for d in range(dim)]
+    m = np.zeros((len(level), 2 * dim), dtype=bool)
+    for q in range(len(level)):
+        l = int(level[q])
+        for s in range(2 * dim):
+            d, dr = s // 2, (1 if s % 2 else -1)
+            p = [int(idx[q, e]) for e in range(dim)]
+            p[d] += dr
+            n1 = ext[d] * 2 ** (l - 1)
+            if not 1 <= p[d] <= n1:
+                if types[s] != "periodic":
+                    m[q, s] = True
+                    continue
+                p[d] = (p[d] - 1) % n1 + 1
+            root = tuple((p[e] - 1) // 2 ** (l - 1) + 1 for e in range(dim))
+            m[q, s] = root not in roots
+    return m
+
+
+def side_types(dim, bc_type):
+    if bc_type is None:
+        return ["dirichlet"] * (2 * dim)
+    if isinstance(bc_type, str):
+        return [bc_type] * (2 * dim)
+    return list(bc_type)
+
+
+def domain_leaves(dim, N, roots, lmax, centre, radius=0.0, n_buf=0, periodic=None):
+    """Leaves over a coarse grid of several level-1 boxes (roots: lattice
+    positions, 1-based), refined to lmax around a ball; periodic: per axis."""
+    return adaptive_leaves(dim, N, ball_flag(dim, N, centre, radius), lmax, n_buf=n_buf, roots=roots,
+                           periodic=periodic)
+
+
+def domain_fields(dim, N, level, idx, seed, bc_type=None):
+    """Seeded random rho and boundary values (Dirichlet values or outward
+    derivatives, per the side types) on a general domain.  Without any
+    Dirichlet side the problem is singular: rho is then shifted by a
+    constant so that the volume integral of rho equals the boundary integral
+    of the Neumann derivatives, the discrete compatibility condition."""
+    rng = np.random.default_rng(seed)
+    level = np.asarray(level, np.int32)
+    idx = np.asarray(idx, np.int32)
+    n = len(level)
+    types = side_types(dim, bc_type)
+    rho = rng.standard_normal((n, N ** dim))
+    bc = rng.standard_normal((n, 2 * dim, N ** (dim - 1)))
+    bc *= domain_side_mask(dim, level, idx, types)[:, :, None]
+    if "dirichlet" not in types:
+        h = box_h(level, N)
+        vol = np.sum(h ** dim) * N ** dim
+        flux = 0.0
+        for s in range(2 * dim):
+            if types[s] == "neumann":
+                flux += np.sum(bc[:, s, :] * (h[:, None] ** (dim - 1)))
+        excess = np.sum(rho * (h[:, None] ** dim)) - flux
+        rho -= excess / vol
+    name = f"domain_{dim}d_{'_'.join(t[0] for t in types)}_s{seed}"
+    return Workload(name, dim, N, level, idx, rho, bc)
+
+
 # ----------------------------------------------------------------------------
 # leaf lists
 # ----------------------------------------------------------------------------
@@ -173,19 +245,42 @@ def _neighbour_offsets(dim):
 
 class _LeafSet:
     """Mutable set of leaves keyed by (level, i, j, k); used only to build
-    input grids."""
+    input grids.  The coarse grid is a set of level-1 boxes (roots) at
+    1-based lattice positions; a periodic axis wraps positions around the
+    lattice's extent."""
 
-    def __init__(self, dim):
+    def __init__(self, dim, roots=None, periodic=None):
         self.dim = dim
-        self.leaves = {(1, 1, 1, 1)}
+        roots = [(1, 1, 1)] if roots is None else [tuple(int(v) for v in r) for r in roots]
+        if dim == 2:
+            roots = [(r[0], r[1], 1) for r in roots]
+        self.roots = set(roots)
+        self.ext = tuple(max(r[d] for r in roots) for d in range(3))
+        self.periodic = tuple(periodic) if periodic is not None else (False, False, False)
+        self.leaves = {(1,) + r for r in roots}
+
+    def wrap(self, level, i, j, k):
+        """The position (level, i, j, k) inside the domain (periodic axes
+        wrapped), or None outside it or in a hole of the coarse grid."""
+        q = [i, j, k]
+        for d in range(self.dim):
+            n1 = self.ext[d] * 2 ** (level - 1)
+            if not 1 <= q[d] <= n1:
+                if not self.periodic[d]:
+                    return None
+                q[d] = (q[d] - 1) % n1 + 1
+        root = tuple((q[d] - 1) // 2 ** (level - 1) + 1 for d in range(self.dim)) + ((1,) if self.dim == 2 else ())
+        if root not in self.roots:
+            return None
+        return (level, q[0], q[1], q[2] if self.dim == 3 else 1)
 
     def covering_leaf(self, level, i, j, k):
         """The leaf covering box position (level, i, j, k), or None if that
         position is refined further (or outside the domain)."""
-        n1 = 2 ** (level - 1)
-        if not (1 <= i <= n1 and 1 <= j <= n1 and (self.dim == 2 or 1 <= k <= n1)):
+        w = self.wrap(level, i, j, k)
+        if w is None:
             return None
-        l, a, b, c = level, i, j, k
+        l, a, b, c = w
         while l >= 1:
             if (l, a, b, c) in self.leaves:
                 return (l, a, b, c)
@@ -211,15 +306,17 @@ class _LeafSet:
         return lev, idx
 
 
-def adaptive_leaves(dim, N, flag_fn, lmax, n_buf=2):
-    """Refine from the root until stable.
+def adaptive_leaves(dim, N, flag_fn, lmax, n_buf=2, roots=None, periodic=None):
+    """Refine from the root (or the given roots) until stable.
 
     flag_fn(level, idx[n,3]) -> bool [n, N^D] cell flags for the given boxes.
     A box is refined when any cell is flagged (and its level < lmax); same-level
     neighbours whose cells lie within n_buf cells of a flagged cell are refined
     too; coarser neighbours (diagonals included) are refined for 2:1 balance.
+    roots: lattice positions of the level-1 boxes (default the unit box);
+    periodic: per axis, whether neighbours wrap around the lattice.
     """
-    ls = _LeafSet(dim)
+    ls = _LeafSet(dim, roots, periodic)
     offs = _neighbour_offsets(dim)
     evaluated = set()
     while True:
@@ -251,7 +348,7 @@ def adaptive_leaves(dim, N, flag_fn, lmax, n_buf=2):
                     sl = tuple(sl[::-1])  # array axes are (z,) y, x
                     if f[sl].any():
                         l, i, j, k = key
-                        nb = (l, i + o[0], j + o[1], k + o[2] if dim == 3 else 1)
+                        nb = ls.wrap(l, i + o[0], j + o[1], k + o[2] if dim == 3 else 1)
                         if nb in ls.leaves:
                             flagged.add(nb)
         flagged = {k for k in flagged if k[0] < lmax}

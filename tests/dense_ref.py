@@ -9,12 +9,19 @@ where u_nb across a face is (paper §2.4, §3.3):
   * the neighbouring leaf cell at the same level;
   * the mean of the 2^D leaf cells that refine the neighbouring cell when that
     neighbour is refined (its value is the restriction, paper §2.5);
-  * 2 b - u_c at a physical Dirichlet face with value b;
+  * 2 b - u_c at a physical Dirichlet face with value b, u_c + h q at a
+    Neumann face with outward derivative q (paper §3: Dirichlet, Neumann or
+    periodic boundaries; periodic axes wrap around the domain);
   * the default refinement-boundary ghost of paper §3.3 when the neighbour is
     coarser: 1/2 u_H + u_c - 1/4 (u_c' + u_c2) in 2D and
     1/2 u_H + 5/4 u_c - 1/4 (u_c2 + u_c' + u_c'') in 3D, with u_H the coarse
     leaf cell containing the ghost centre, u_c2 the next cell inward and
     u_c', u_c'' the tangential partners of u_c inside the same coarse cell.
+
+The domain is the union of the level-1 boxes holding the leaves (unit boxes
+on the integer lattice, paper §2.2); a face is physical when the cell across
+it lies outside the lattice on a non-periodic axis or in a lattice position
+without a level-1 box.
 
 This is written independently of the oracle (global cell indices instead of
 boxes with stored ghost layers) and only serves to pin it.
@@ -25,12 +32,22 @@ from __future__ import annotations
 import numpy as np
 
 
-def assemble(dim, N, level, idx, bc=None):
-    """Return (A, g, cells) with A u = rho - g for the leaf unknowns in
-    leaf-list order (x fastest within each leaf), g the Dirichlet part."""
+def assemble(dim, N, level, idx, bc=None, bc_type=None):
+    """Return (A, g) with A u = rho - g for the leaf unknowns in leaf-list
+    order (x fastest within each leaf), g the boundary part.  bc_type: None
+    (all Dirichlet), one name or 2D names among "dirichlet", "neumann",
+    "periodic"."""
     level = np.asarray(level)
     idx = np.asarray(idx)
     n_leaf = len(level)
+    if bc_type is None:
+        types = ["dirichlet"] * (2 * dim)
+    elif isinstance(bc_type, str):
+        types = [bc_type] * (2 * dim)
+    else:
+        types = list(bc_type)
+    roots = {tuple(((int(idx[q, d]) - 1) >> (int(level[q]) - 1)) + 1 for d in range(dim)) for q in range(n_leaf)}
+    ext = [max(r[d] for r in roots) for d in range(dim)]
     boxes = set()
     leaves = {}
     for q in range(n_leaf):
@@ -77,7 +94,7 @@ def assemble(dim, N, level, idx, bc=None):
         l = int(level[q])
         h = 1.0 / (N * 2.0 ** (l - 1))
         ih2 = 1.0 / (h * h)
-        nl = N * 2 ** (l - 1)  # cells per axis at level l
+        per_root = N * 2 ** (l - 1)  # cells per axis of one level-1 box at level l
         org = [(int(idx[q, d]) - 1) * N for d in range(dim)]
         for loc in locs:
             row = q * ncell + loc_pos[loc]
@@ -85,16 +102,28 @@ def assemble(dim, N, level, idx, bc=None):
             A[row, row] -= 2 * dim * ih2
             for d in range(dim):
                 for sgn in (-1, 1):
+                    side = 2 * d + (1 if sgn > 0 else 0)
                     Gn = list(G)
                     Gn[d] += sgn
-                    if Gn[d] < 0 or Gn[d] >= nl:
-                        # Dirichlet: ghost = 2 b - u_c
-                        side = 2 * d + (1 if sgn > 0 else 0)
-                        A[row, row] -= ih2
-                        if bc is not None:
-                            tang = [loc[e] for e in range(dim) if e != d]
-                            fi = tang[0] + (N * tang[1] if dim == 3 else 0)
-                            gvec[row] += 2.0 * bc[q, side, fi] * ih2
+                    nl = ext[d] * per_root
+                    outside = Gn[d] < 0 or Gn[d] >= nl
+                    if outside and types[side] == "periodic":
+                        Gn[d] %= nl
+                        outside = False
+                    if not outside:
+                        outside = tuple(g // per_root + 1 for g in Gn) not in roots  # a hole
+                    if outside:
+                        tang = [loc[e] for e in range(dim) if e != d]
+                        fi = tang[0] + (N * tang[1] if dim == 3 else 0)
+                        bv = 0.0 if bc is None else bc[q, side, fi]
+                        if types[side] == "neumann":
+                            # ghost = u_c + h q
+                            A[row, row] += ih2
+                            gvec[row] += bv * h * ih2
+                        else:
+                            # Dirichlet: ghost = 2 b - u_c
+                            A[row, row] -= ih2
+                            gvec[row] += 2.0 * bv * ih2
                         continue
                     if box_exists(l, Gn):
                         col = cell_unknown(l, Gn)
