@@ -13,9 +13,11 @@
  *   - side ghost cells: copy from a same-level neighbour, Dirichlet values
  *     through g = 2 b - u1, and the default conservative scheme at refinement
  *     boundaries (§2.4, §3.3);
- *   - extra coarse grids of N/2, ..., 2 cells below the root (§3.2).
+ *   - extra coarse grids of N/2, ..., 2 cells below the root (§3.2);
+ *   - general domains (afmg_tree_create_domain): a coarse grid of several
+ *     level-1 boxes (§2.2) and Dirichlet, Neumann or periodic sides (§3).
  * The operator is the 5-point (2D) / 7-point (3D) Laplacian: the library
- * solves lap_h(u) = rho with Dirichlet boundary values.
+ * solves lap_h(u) = rho with the given boundary values.
  *
  * Conventions
  *   - All entry points return an afmg_status; nothing is thrown or exits.
@@ -25,11 +27,13 @@
  *     afmg_tree_leaf_boxes maps the caller's leaf order to box ids.
  *   - Cell fields are device arrays of doubles laid out [n_boxes][N^D] in
  *     box-id order, x fastest within a box, no ghost cells.
- *   - Dirichlet values are a device array [n_bfaces][N^(D-1)]: one row per
+ *   - Boundary values are a device array [n_bfaces][N^(D-1)]: one row per
  *     physical-boundary side of a LEAF box, rows ordered as
  *     afmg_tree_bfaces lists them; within a row the tangential axes are
  *     taken in increasing order, the first fastest; values sit at the face
- *     centres.  Values for coarser boxes are derived by averaging.
+ *     centres: the solution on Dirichlet sides, its outward normal
+ *     derivative on Neumann sides (afmg_tree_create_domain).  Values for
+ *     coarser boxes are derived by averaging.
  *   - Every device operation is enqueued on the caller's HIP stream.
  *   - A tree may be used by one stream at a time.
  */
@@ -125,7 +129,19 @@ typedef struct {
     int lmin, lmax;   /* lmin < 1: coarse grids below the root */
     int64_t cells_per_box;
     int64_t n_unknowns;  /* leaf cells */
+    int n_roots;      /* level-1 boxes (boxes 0 .. n_roots-1) */
+    int ext[3];       /* extent of their lattice per axis (1 for unused axes) */
+    int bc_type[6];   /* afmg_bc_type per side orientation */
+    int singular;     /* 1: no Dirichlet side; solutions are defined up to a
+                         constant and rho must be compatible */
 } afmg_tree_desc;
+
+/* Side types of the domain boundary (paper §3), per orientation -x, +x, -y,
+   +y, -z, +z.  Dirichlet rows hold the value b at the face centre (ghost
+   2 b - u1); Neumann rows the outward normal derivative q (ghost u1 + h q);
+   periodic sides have no rows (the neighbour across is the box at the other
+   end of the axis). */
+typedef enum { AFMG_BC_DIRICHLET = 0, AFMG_BC_NEUMANN = 1, AFMG_BC_PERIODIC = 2 } afmg_bc_type;
 
 typedef struct {
     int level;
@@ -156,6 +172,30 @@ void afmg_default_opts(afmg_opts *opts);
  */
 int afmg_tree_create(int dim, int box_n, int64_t n_leaves, const int32_t *level,
                      const int32_t *idx, afmg_tree **out);
+
+/*
+ * A tree on a general domain (paper §2.2, §3).  The coarse grid is the set
+ * of level-1 boxes that hold the leaves: unit boxes at 1-based lattice
+ * positions 1 .. ext[d] per axis (ext[d] <= 64, at most 4096 positions),
+ * which may leave positions out (L shapes, holes); the leaves tile their
+ * union.  Below every level-1 box the solve adds coarse grids of N/2, ...,
+ * 2 cells, linked like the level-1 boxes, so a non-square coarse grid has
+ * several 2^D-cell boxes at the bottom and may need a larger opts.n_base
+ * (§3.2).  bc_type[2 * dim] gives the type of each side orientation
+ * (afmg_bc_type; NULL: all Dirichlet); faces of holes take the type of
+ * their orientation; periodic sides come in pairs and need every lattice
+ * position filled.  Neighbour searches wrap on periodic axes, 2:1 balance
+ * included.  Without a Dirichlet side the problem is singular: rho must be
+ * compatible (its volume integral equals the boundary integral of the
+ * Neumann derivatives), the solution is defined up to a constant, and
+ * afmg_adjoint refuses the tree.  Trees made here are not accepted by
+ * afmg_batch_create unless they have one level-1 box and Dirichlet sides.
+ * Host-only.  Errors: AFMG_ERR_ARG (bad types, unpaired periodic sides,
+ * periodic sides on a non-rectangular coarse grid, indices out of range),
+ * AFMG_ERR_TREE, AFMG_ERR_OOM.
+ */
+int afmg_tree_create_domain(int dim, int box_n, const int32_t *bc_type, int64_t n_leaves,
+                            const int32_t *level, const int32_t *idx, afmg_tree **out);
 
 void afmg_tree_destroy(afmg_tree *tree);
 

@@ -83,7 +83,27 @@ class TreeDesc(C.Structure):
         ("lmax", C.c_int),
         ("cells_per_box", C.c_int64),
         ("n_unknowns", C.c_int64),
+        ("n_roots", C.c_int),
+        ("ext", C.c_int * 3),
+        ("bc_type", C.c_int * 6),
+        ("singular", C.c_int),
     ]
+
+
+BC_TYPES = {"dirichlet": 0, "neumann": 1, "periodic": 2}
+
+
+def bc_type_codes(bc_type, dim):
+    """Side types per orientation (-x, +x, -y, +y, -z, +z): None (all
+    Dirichlet), one name for all sides, or 2D names / codes."""
+    out = np.zeros(6, np.int32)
+    if bc_type is None:
+        return out
+    if isinstance(bc_type, str):
+        bc_type = [bc_type] * (2 * dim)
+    for s, v in enumerate(bc_type):
+        out[s] = BC_TYPES[v] if isinstance(v, str) else int(v)
+    return out
 
 
 class BatchDesc(C.Structure):
@@ -119,7 +139,7 @@ EXPORTS = [
     "afmg_batch_solve", "afmg_autotune_workspace_bytes", "afmg_tree_autotune", "afmg_tree_shape",
     "afmg_tree_set_shape", "afmg_batch_autotune_workspace_bytes", "afmg_batch_autotune", "afmg_batch_shape",
     "afmg_batch_set_shape", "afmg_tree_refine", "afmg_tree_finalize", "afmg_tree_level_list", "afmg_step",
-    "afmg_solve_noalloc",
+    "afmg_solve_noalloc", "afmg_tree_create_domain",
 ]
 STEPS = {"half_sweep": 0, "resid_restrict": 1, "coarse_rhs": 2, "prolong": 3, "coarse": 4}
 LISTS = {"all": 0, "parent": 1, "leaf": 2}
@@ -149,6 +169,7 @@ def lib():
         L.afmg_default_opts.argtypes = [C.POINTER(Opts)]
         L.afmg_default_opts.restype = None
         L.afmg_tree_create.argtypes = [C.c_int, C.c_int, i64, i32p, i32p, C.POINTER(vp)]
+        L.afmg_tree_create_domain.argtypes = [C.c_int, C.c_int, i32p, i64, i32p, i32p, C.POINTER(vp)]
         L.afmg_tree_destroy.argtypes = [vp]
         L.afmg_tree_destroy.restype = None
         L.afmg_tree_info.argtypes = [vp, C.POINTER(TreeDesc)]
@@ -254,9 +275,13 @@ class _Shapes:
 
 
 class Tree(_Shapes):
-    """A quadtree/octree of 8^D-cell boxes built from its leaves."""
+    """A quadtree/octree of 8^D-cell boxes built from its leaves.  With
+    bc_type (see bc_type_codes) the domain is general: the level-1 boxes
+    holding the leaves form the coarse grid on an integer lattice, and each
+    side orientation is Dirichlet, Neumann or periodic
+    (afmg_tree_create_domain)."""
 
-    def __init__(self, dim, level=None, idx=None, box_n=8, _handle=None):
+    def __init__(self, dim, level=None, idx=None, box_n=8, _handle=None, bc_type=None):
         L = lib()
         if _handle is not None:
             h = _handle
@@ -266,8 +291,15 @@ class Tree(_Shapes):
             if len(level) != len(idx):
                 raise ValueError("level and idx lengths differ")
             h = C.c_void_p()
-            _check(L.afmg_tree_create(dim, box_n, len(level), level.ctypes.data_as(C.POINTER(C.c_int32)),
-                                      idx.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(h)))
+            i32p = C.POINTER(C.c_int32)
+            if bc_type is None:
+                _check(L.afmg_tree_create(dim, box_n, len(level), level.ctypes.data_as(i32p),
+                                          idx.ctypes.data_as(i32p), C.byref(h)))
+            else:
+                codes = bc_type_codes(bc_type, dim)
+                _check(L.afmg_tree_create_domain(dim, box_n, codes.ctypes.data_as(i32p), len(level),
+                                                 level.ctypes.data_as(i32p), idx.ctypes.data_as(i32p),
+                                                 C.byref(h)))
         self._h = h
         d = TreeDesc()
         _check(L.afmg_tree_info(h, C.byref(d)))
@@ -276,6 +308,10 @@ class Tree(_Shapes):
         self.lmin, self.lmax = d.lmin, d.lmax
         self.cells_per_box = d.cells_per_box
         self.n_unknowns = d.n_unknowns
+        self.n_roots = d.n_roots
+        self.ext = tuple(d.ext)
+        self.bc_type = tuple(d.bc_type[: 2 * self.dim])
+        self.singular = bool(d.singular)
         self.leaf_boxes = np.zeros(self.n_leaves, np.int32)
         _check(L.afmg_tree_leaf_boxes(h, self.leaf_boxes.ctypes.data_as(C.POINTER(C.c_int32))))
         bf = np.zeros(2 * max(1, self.n_bfaces), np.int32)

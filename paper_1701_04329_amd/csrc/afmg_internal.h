@@ -24,6 +24,13 @@ static_assert(sizeof(BoxInfo) == 64, "BoxInfo must be 64 bytes");
 constexpr int FLAG_LEAF = 1;
 // bits 4..9: the same-level neighbour on side s is refined (a parent box)
 constexpr int FLAG_NBR_REFINED = 1 << 4;
+// bits 10..15: side s is a physical side of Neumann type (its boundary row
+// holds the outward derivative q, ghost u1 + h q); other physical sides are
+// Dirichlet (ghost 2 b - u1)
+constexpr int FLAG_NEUMANN = 1 << 10;
+
+// side types of the domain boundary, per orientation
+constexpr int BC_DIRICHLET = 0, BC_NEUMANN = 1, BC_PERIODIC = 2;
 inline int oct_bit(int flags, int axis) { return (flags >> (1 + axis)) & 1; }
 
 // Host tree, or forest of independent trees (built from leaves, immutable
@@ -40,6 +47,18 @@ struct HostTree {
     std::vector<int32_t> leaf_box;    // box id of input leaf q
     std::vector<int32_t> child;       // [n_boxes][8] child ids (octant bits x|y<<1|z<<2), -1 if none
     bool uniform = true;              // every tree has all its leaves on one level
+    // domain of a single tree (paper §2.2, §3): the level-1 boxes sit on an
+    // integer lattice of extent ext (a subset of it: L shapes and holes),
+    // each side orientation has a type; general = more than one level-1 box
+    // or a side that is not Dirichlet (such trees take the general coarse
+    // path)
+    int bc_type[6] = {0, 0, 0, 0, 0, 0};
+    int ext[3] = {1, 1, 1};
+    int n_roots = 1;                  // level-1 boxes (boxes 0 .. n_roots-1)
+    bool general = false;
+    bool singular = false;            // no Dirichlet side anywhere: L has the constants in its null space
+    bool level1_leaf = false;         // some level-1 box is a leaf
+    std::vector<char> root_at;        // [ext2][ext1][ext0]: a level-1 box sits at that lattice position
     int lmin_leaf = 1;                // coarsest level holding a leaf (any tree)
     std::vector<int32_t> tree_lmax;        // finest level of each tree
     std::vector<int64_t> tree_leaf_ptr;    // leaf boxes of tree t: tree_leaf_box[ptr[t] .. ptr[t+1])
@@ -55,7 +74,7 @@ struct HostTree {
 // tree_off[t] .. tree_off[t+1]-1 of level / idx.  Returns AFMG_OK or an
 // error with msg filled.
 int build_tree(int dim, int N, int n_trees, const int64_t *tree_off, const int32_t *level, const int32_t *idx,
-               HostTree &t, std::string &msg);
+               HostTree &t, std::string &msg, const int32_t *bc_type = nullptr);
 
 // Leaves of the tree after refining the leaf boxes `ids` (paper §2.3): the
 // unrefined leaves in their input order, then the 2^D children of each
@@ -65,6 +84,9 @@ int build_tree(int dim, int N, int n_trees, const int64_t *tree_off, const int32
 // and corners.
 int refine_leaves(const HostTree &t, const int32_t *ids, int64_t n, int balance, std::vector<int32_t> &level,
                   std::vector<int32_t> &idx, std::string &msg);
+// the position (l, q) inside a single tree's domain (periodic axes wrapped),
+// false outside it or in a lattice position without a level-1 box
+bool domain_position(const HostTree &t, int l, int q[3]);
 
 void set_error(const std::string &msg);
 

@@ -32,6 +32,7 @@ struct LevelArgs {
                         // add_to += u on every cell, u of the updated colour = 0
     int own_zero;       // first half sweep after one with add_to: the old
                         // values of the updated colour are taken as zero
+    T h;                // cell size of the level (Neumann ghosts u1 + h q)
 };
 
 enum class Op { GSRB, RESID_RESTRICT, COARSE_RHS, PROLONG, RESTRICT_RHO };
@@ -61,6 +62,23 @@ struct CoarseArgs {
     T h2_2, ih2_2;        // h^2 and 1/h^2 of level 2 (modes V2_*)
 };
 
+// Arguments of the coarse kernel of a general domain (several level-1 boxes,
+// Neumann or periodic sides): one workgroup for the tree's levels <= 1; the
+// level-1 boxes are boxes 0 .. n_roots-1.
+template <typename T>
+struct CoarseGenArgs {
+    const BoxInfo *info;
+    T *u;
+    T *rho;
+    T *uold;            // null when the tree has one level
+    const double *bc;
+    double *ws;         // scratch of coarse_gen_doubles(n_roots) doubles
+    int n_roots;
+    int mode;           // COARSE_V_FROM_2, COARSE_V_TOP1 or COARSE_FMG
+    int homog;
+    int n_down, n_up, n_base;
+};
+
 // wg: workgroup size of the launch (64, 128 or 256 threads; W / N^(D-1)
 // boxes per workgroup); every size gives bitwise the same results
 template <int D, int N, typename T>
@@ -81,6 +99,10 @@ void launch_reduce_trees(const double *partial, const int64_t *ptr, const int32_
 void launch_level_mask(const int *base, const int32_t *tree_lmax, int l, int *out, int n_trees, hipStream_t st);
 template <int D, int N, typename T>
 void launch_coarse(const CoarseArgs<T> &a, int n_trees, hipStream_t st);
+template <int D, int N, typename T>
+void launch_coarse_gen(const CoarseGenArgs<T> &a, hipStream_t st);
+template <int D, int N>
+size_t coarse_gen_doubles(int n_roots);
 template <int D, int N, typename T>
 void launch_permute(const BoxInfo *info, T *f, int64_t b0, int64_t nb, int to_split, int leaves_only,
                     hipStream_t st);

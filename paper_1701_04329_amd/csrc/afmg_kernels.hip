@@ -165,8 +165,11 @@ __device__ __forceinline__ bool tree_active(const LevelArgs<T> &a, const BoxInfo
 // side ghosts (paper §2.4, §3.3)
 // ---------------------------------------------------------------------------
 // A ghost next to face cell x on side S is
-//   same-level neighbour v:  its face cell across the side
-//   physical side:           2 b - u1          (b = 0 when homog)
+//   same-level neighbour v:  its face cell across the side (periodic sides
+//                            have their wrapped neighbour here)
+//   physical side:           2 b - u1          Dirichlet (b = 0 when homog)
+//                            u1 + h q          Neumann, q the outward
+//                                              derivative (q = 0 when homog)
 //   refinement boundary:     2D 1/2 uH + u1 - 1/4 (u1' + u2)
 //                            3D 1/2 uH + 5/4 u1 - 1/4 (u2 + u1' + u1'')
 // uH: cell of the coarser neighbour box containing the ghost centre; u2: next
@@ -218,15 +221,23 @@ __device__ __forceinline__ T ghost_raw(const BoxInfo &bi, int m, const T *__rest
     return *ghost_ptr<D, N, S, T>(bi, m, u, bc, homog, v);
 }
 
+// the ghost of a physical side from its boundary value b (zero when
+// homogeneous) and the face cell's value u1
+template <typename T>
+__device__ __forceinline__ T phys_ghost(bool neumann, T b, T u1, T h) {
+    return neumann ? u1 + h * b : T(2) * b - u1;
+}
+__device__ __forceinline__ bool neumann_side(int flags, int s) { return (flags >> (10 + s)) & 1; }
+
 // finish the ghost from its raw operand; s is the padded box in LDS
 template <int D, int N, int S, typename T>
-__device__ __forceinline__ T ghost_finish(const T *s, int m, T raw, int v, int homog) {
+__device__ __forceinline__ T ghost_finish(const T *s, int m, T raw, int v, int homog, int flags, T h) {
     using SD = SideOf<S>;
     if (v >= 0) return raw;
     int x[3];
     face_cell<D, N, S>(m, x);
     const T u1 = s[padi<D, N>(x[0], x[1], x[2])];
-    if (v == -1) return T(2) * (homog ? T(0) : raw) - u1;
+    if (v == -1) return phys_ghost<T>(neumann_side(flags, S), homog ? T(0) : raw, u1, h);
     int y[3] = {x[0], x[1], x[2]};
     y[SD::d] = SD::hi ? N - 2 : 1;
     const T u2 = s[padi<D, N>(y[0], y[1], y[2])];
@@ -272,11 +283,15 @@ struct Stager {
     T raw[6];
     int v[6];
     int hg;
+    int fl;  // box flags (Neumann sides)
+    T hh;    // cell size (Neumann ghosts)
     T rowv[2][G::HN];
 
     __device__ __forceinline__ void load(const BoxInfo &bi, const T *__restrict__ ub, const T *__restrict__ u,
-                                         const T *__restrict__ bc, int homog, int t, bool ghosts) {
+                                         const T *__restrict__ bc, int homog, int t, bool ghosts, T h = T(0)) {
         hg = homog;
+        fl = bi.flags;
+        hh = h;
 #pragma unroll
         for (int c = 0; c < 2; c++)
 #pragma unroll
@@ -304,18 +319,18 @@ struct Stager {
     }
     __device__ __forceinline__ void begin(T *s, const BoxInfo &bi, const T *__restrict__ ub,
                                           const T *__restrict__ u, const T *__restrict__ bc, int homog, int t,
-                                          bool ghosts) {
-        load(bi, ub, u, bc, homog, t, ghosts);
+                                          bool ghosts, T h = T(0)) {
+        load(bi, ub, u, bc, homog, t, ghosts, h);
         stage(s, t);
     }
     __device__ void end(T *s, int t) {
-        s[ghost_slot<D, N, 0>(t)] = ghost_finish<D, N, 0, T>(s, t, raw[0], v[0], hg);
-        s[ghost_slot<D, N, 1>(t)] = ghost_finish<D, N, 1, T>(s, t, raw[1], v[1], hg);
-        s[ghost_slot<D, N, 2>(t)] = ghost_finish<D, N, 2, T>(s, t, raw[2], v[2], hg);
-        s[ghost_slot<D, N, 3>(t)] = ghost_finish<D, N, 3, T>(s, t, raw[3], v[3], hg);
+        s[ghost_slot<D, N, 0>(t)] = ghost_finish<D, N, 0, T>(s, t, raw[0], v[0], hg, fl, hh);
+        s[ghost_slot<D, N, 1>(t)] = ghost_finish<D, N, 1, T>(s, t, raw[1], v[1], hg, fl, hh);
+        s[ghost_slot<D, N, 2>(t)] = ghost_finish<D, N, 2, T>(s, t, raw[2], v[2], hg, fl, hh);
+        s[ghost_slot<D, N, 3>(t)] = ghost_finish<D, N, 3, T>(s, t, raw[3], v[3], hg, fl, hh);
         if (D == 3) {
-            s[ghost_slot<D, N, 4>(t)] = ghost_finish<D, N, 4, T>(s, t, raw[4], v[4], hg);
-            s[ghost_slot<D, N, 5>(t)] = ghost_finish<D, N, 5, T>(s, t, raw[5], v[5], hg);
+            s[ghost_slot<D, N, 4>(t)] = ghost_finish<D, N, 4, T>(s, t, raw[4], v[4], hg, fl, hh);
+            s[ghost_slot<D, N, 5>(t)] = ghost_finish<D, N, 5, T>(s, t, raw[5], v[5], hg, fl, hh);
         }
     }
 };
@@ -353,10 +368,11 @@ template <int D, int N>
 constexpr int oblock() { return Geo<D, N>::HALF + (D == 3 ? 0 : 1); }
 
 template <int D, int N, int S, typename T>
-__device__ __forceinline__ T gs_finish(const T *s, T raw, int v, T own, int homog, int i, int j, int k) {
+__device__ __forceinline__ T gs_finish(const T *s, T raw, int v, T own, int homog, int i, int j, int k, int flags,
+                                       T h) {
     using SD = SideOf<S>;
     if (v >= 0) return raw;
-    if (v == -1) return T(2) * (homog ? T(0) : raw) - own;
+    if (v == -1) return phys_ghost<T>(neumann_side(flags, S), homog ? T(0) : raw, own, h);
     int y[3] = {i, j, k};
     y[SD::d] += SD::hi ? -1 : 1;
     int p1[3] = {i, j, k};
@@ -467,14 +483,15 @@ __global__ __launch_bounds__(W) void k_gsrb(LevelArgs<T> a, int colour) {
 #pragma unroll
     for (int m = 0; m < HN; m++) {
         const int i = 2 * m + p;
-        const T xm = i > 0 ? s[oslot<D, N>(i - 1, j, k)] : gs_finish<D, N, 0, T>(s, gx, vx, ow[m], a.homog, i, j, k);
-        const T xp = i < N - 1 ? s[oslot<D, N>(i + 1, j, k)] : gs_finish<D, N, 1, T>(s, gx, vx, ow[m], a.homog, i, j, k);
-        const T ym = j > 0 ? s[oslot<D, N>(i, j - 1, k)] : gs_finish<D, N, 2, T>(s, gy[m], vy, ow[m], a.homog, i, j, k);
-        const T yp = j < N - 1 ? s[oslot<D, N>(i, j + 1, k)] : gs_finish<D, N, 3, T>(s, gy[m], vy, ow[m], a.homog, i, j, k);
+        const int fl = bi.flags;
+        const T xm = i > 0 ? s[oslot<D, N>(i - 1, j, k)] : gs_finish<D, N, 0, T>(s, gx, vx, ow[m], a.homog, i, j, k, fl, a.h);
+        const T xp = i < N - 1 ? s[oslot<D, N>(i + 1, j, k)] : gs_finish<D, N, 1, T>(s, gx, vx, ow[m], a.homog, i, j, k, fl, a.h);
+        const T ym = j > 0 ? s[oslot<D, N>(i, j - 1, k)] : gs_finish<D, N, 2, T>(s, gy[m], vy, ow[m], a.homog, i, j, k, fl, a.h);
+        const T yp = j < N - 1 ? s[oslot<D, N>(i, j + 1, k)] : gs_finish<D, N, 3, T>(s, gy[m], vy, ow[m], a.homog, i, j, k, fl, a.h);
         T sum = (xm + xp) + (ym + yp);
         if (D == 3) {
-            const T zm = k > 0 ? s[oslot<D, N>(i, j, k - 1)] : gs_finish<D, N, 4, T>(s, gz[m], vz, ow[m], a.homog, i, j, k);
-            const T zp = k < N - 1 ? s[oslot<D, N>(i, j, k + 1)] : gs_finish<D, N, 5, T>(s, gz[m], vz, ow[m], a.homog, i, j, k);
+            const T zm = k > 0 ? s[oslot<D, N>(i, j, k - 1)] : gs_finish<D, N, 4, T>(s, gz[m], vz, ow[m], a.homog, i, j, k, fl, a.h);
+            const T zp = k < N - 1 ? s[oslot<D, N>(i, j, k + 1)] : gs_finish<D, N, 5, T>(s, gz[m], vz, ow[m], a.homog, i, j, k, fl, a.h);
             sum = sum + (zm + zp);
         }
         rr[m] = (sum - a.h2 * rr[m]) / T(2 * D);
@@ -690,7 +707,7 @@ __global__ __launch_bounds__(W) void k_resid_restrict(LevelArgs<T> a) {
                 block_cell<D, N>(sl.t + it * G::TPB, q, i, j, k);
                 rf[it][q] = a.rho[bo + cpos<D, N>(i, j, k)];
             }
-        st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, true);
+        st.begin(s, bi, a.u + bo, a.u, a.bc, a.homog, sl.t, true, a.h);
     }
     __syncthreads();
     if (act) st.end(s, sl.t);
@@ -741,7 +758,7 @@ __global__ __launch_bounds__(W) void k_coarse_rhs(LevelArgs<T> a) {
     // depends on the box record: ghosts and rbar of parents
     const bool act = sl.valid && tree_active<F>(a, bi);
     if (!F || act) {
-        st.load(bi, a.u + bo, a.u, a.bc, a.homog, sl.t, parent);
+        st.load(bi, a.u + bo, a.u, a.bc, a.homog, sl.t, parent, a.h);
         if (parent) {
 #pragma unroll
             for (int it = 0; it < NE; it++) rf[it] = a.rho[bo + sl.t + it * G::TPB];
@@ -826,10 +843,11 @@ __device__ __forceinline__ size_t halo_addr(int m, const int o[3], const BoxInfo
     return (size_t)box * G::C + cpos<D, N>(X[0], X[1], X[2]);
 }
 
-// Dirichlet: ghost of delta = -delta(face cell) (the values b cancel);
-// refinement side: the default scheme applied to deltas.
+// Dirichlet: ghost of delta = -delta(face cell), Neumann: +delta(face cell)
+// (the boundary values cancel); refinement side: the default scheme applied
+// to deltas.
 template <int D, int N, int S, typename T>
-__device__ __forceinline__ void halo_phase2(T *q, int m, const int o[3], T raw, int v) {
+__device__ __forceinline__ void halo_phase2(T *q, int m, const int o[3], T raw, int v, int pflags) {
     using SD = SideOf<S>;
     if (v >= 0) return;
     int L[3], X[3];
@@ -839,7 +857,7 @@ __device__ __forceinline__ void halo_phase2(T *q, int m, const int o[3], T raw, 
     const T d1 = q[qpad<D, N>(f[0], f[1], f[2])];
     T val;
     if (v == -1) {
-        val = -d1;
+        val = neumann_side(pflags, S) ? d1 : -d1;
     } else {
         int y[3] = {f[0], f[1], f[2]};
         y[SD::d] += SD::hi ? -1 : 1;
@@ -872,6 +890,7 @@ __global__ __launch_bounds__(W) void k_prolong(LevelArgs<T> a) {
     const size_t bo = (size_t)sl.b * G::C;
     T raw[NH], uf[NE];
     int hv[NH];
+    int pfl = 0;  // the parent's flags (Neumann sides of its halo)
     // the fine values (needed only after the barriers) first: they need no
     // box record; one tree: padding slots (sl.b clamped to a valid box) load
     // too
@@ -885,6 +904,7 @@ __global__ __launch_bounds__(W) void k_prolong(LevelArgs<T> a) {
     if (!F || act) {
         const int64_t p = bi.parent;
         const BoxInfo pi = load_box<D, N>(a.info, p);
+        pfl = pi.flags;
         // every global operand (octant, halo) before the LDS stores
         T od[NO];
 #pragma unroll
@@ -926,7 +946,7 @@ __global__ __launch_bounds__(W) void k_prolong(LevelArgs<T> a) {
             const int hc = sl.t + h * G::TPB;
             if (hc < 2 * D * G::HF && hv[h] < 0) {
                 const int side = hc / G::HF, m = hc % G::HF;
-#define AFMG_H2(S) halo_phase2<D, N, S, T>(q, m, o, raw[h], hv[h])
+#define AFMG_H2(S) halo_phase2<D, N, S, T>(q, m, o, raw[h], hv[h], pfl)
                 AFMG_SIDE_SWITCH(side, AFMG_H2)
 #undef AFMG_H2
             }
@@ -981,7 +1001,7 @@ __global__ __launch_bounds__(W) void k_final(LevelArgs<T> a, double *partial, in
     // depends on the box record: ghosts and rho of leaves
     const bool act = sl.valid && tree_active<F>(a, bi);
     if (!F || act) {
-        st.load(bi, a.u + bo, a.u, a.bc, a.homog, sl.t, leaf);
+        st.load(bi, a.u + bo, a.u, a.bc, a.homog, sl.t, leaf, a.h);
         if (leaf) {
 #pragma unroll
             for (int it = 0; it < NPC; it++)
@@ -1956,6 +1976,300 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(CoarseArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
+// levels <= 1 of a tree on a general domain: a coarse grid of several
+// level-1 boxes and Neumann or periodic sides (paper §2.2, §3, §3.2)
+// ---------------------------------------------------------------------------
+// Grid g = 0 is level 1 (N cells per side), grids g = 1 .. NG-1 the extra
+// coarse grids of N/2, ..., 2 cells below it.  Every level-1 box (root r, box
+// id r: level 1 comes first in the box order) has one box on every grid,
+// linked to the boxes of its neighbouring roots as the roots are (a periodic
+// side names its wrapped neighbour, a side without a neighbour is physical),
+// so a non-square coarse grid has several 2^D-cell boxes at the bottom.  One
+// workgroup keeps all grids in FP64 in a global scratch area (some KB per
+// root, cache resident), natural order x fastest, and runs the FAS cycle
+// (paper §3.2) on them: the smoothing, residual, restriction, FAS right-hand
+// side and 2-1-1 prolongation of the box kernels, with side ghosts from the
+// neighbouring root's box or the boundary values.  Phases end with workgroup
+// barriers; within a phase the arrays read and written are distinct, except
+// the in-place red-black update, which reads only the other colour and the
+// cell's own old value.
+template <int D, int N>
+struct GenGeo {
+    static constexpr int lg(int n) { return n <= 1 ? 0 : 1 + lg(n / 2); }
+    static constexpr int NG = lg(N);  // grids of N, N/2, ..., 2 cells
+    static constexpr int n(int g) { return N >> g; }
+    static constexpr int cells(int g) { return D == 3 ? n(g) * n(g) * n(g) : n(g) * n(g); }
+    static constexpr int off(int g) { return g == 0 ? 0 : off(g - 1) + cells(g - 1); }
+    static constexpr int TOT = off(NG);
+    static constexpr int fsz(int g) { return D == 3 ? n(g) * n(g) : n(g); }
+    static constexpr int boff(int g) { return g == 0 ? 0 : boff(g - 1) + 2 * D * fsz(g - 1); }
+    static constexpr int BTOT = boff(NG);
+};
+
+template <int D, int N>
+struct GenState {
+    using GG = GenGeo<D, N>;
+    const BoxInfo *info;
+    double *U, *RHO, *UOLD, *RES, *BC;  // [root][TOT] each, BC [root][BTOT]
+    int R, homog, n_down, n_up, n_base;
+
+    __device__ static double hgrid(int g) { return (double)(1 << g) / (double)N; }
+    __device__ double *at(double *f, int r, int g) const { return f + (size_t)r * GG::TOT + GG::off(g); }
+    __device__ static int cidx(int n, int i, int j, int k) { return i + n * (j + n * k); }
+    // boundary value of side s next to cell (i, j, k) of root r on grid g
+    // (tangential axes in increasing order, the first fastest)
+    __device__ double bval(int r, int g, int s, int i, int j, int k) const {
+        if (homog) return 0.0;
+        const int n = GG::n(g), d = s >> 1;
+        const int m = d == 0 ? j + n * k : d == 1 ? i + n * k : i + n * j;
+        return BC[(size_t)r * GG::BTOT + GG::boff(g) + s * GG::fsz(g) + m];
+    }
+    // value across side s of cell (i, j, k) of root r on grid g: a cell of
+    // the box, of the neighbouring root's box, or the physical ghost
+    __device__ double across(const double *f0, int r, int g, int s, int i, int j, int k) const {
+        const int n = GG::n(g), d = s >> 1, hi = s & 1;
+        int x[3] = {i, j, k};
+        x[d] += hi ? 1 : -1;
+        const double *f = f0 + GG::off(g);
+        if (x[d] >= 0 && x[d] < n) return f[(size_t)r * GG::TOT + cidx(n, x[0], x[1], x[2])];
+        const int v = info[r].nbr[s];
+        if (v >= 0) {
+            x[d] = hi ? 0 : n - 1;
+            return f[(size_t)v * GG::TOT + cidx(n, x[0], x[1], x[2])];
+        }
+        const double uc = f[(size_t)r * GG::TOT + cidx(n, i, j, k)];
+        return phys_ghost<double>(neumann_side(info[r].flags, s), bval(r, g, s, i, j, k), uc, hgrid(g));
+    }
+    __device__ double nbs(const double *f, int r, int g, int i, int j, int k) const {
+        double sum = (across(f, r, g, 0, i, j, k) + across(f, r, g, 1, i, j, k)) +
+                     (across(f, r, g, 2, i, j, k) + across(f, r, g, 3, i, j, k));
+        if (D == 3) sum = sum + (across(f, r, g, 4, i, j, k) + across(f, r, g, 5, i, j, k));
+        return sum;
+    }
+    __device__ static void ijk(int n, int c, int &i, int &j, int &k) {
+        i = c % n;
+        j = (c / n) % n;
+        k = D == 3 ? c / (n * n) : 0;
+    }
+    // one red (0) or black (1) half sweep of grid g, every root
+    __device__ void half(int g, int colour) const {
+        const int n = GG::n(g), hn = n / 2, nq = GG::cells(g) / 2;
+        const double h = hgrid(g), h2 = h * h;
+        for (int e = threadIdx.x; e < R * nq; e += blockDim.x) {
+            const int r = e / nq, q = e % nq;
+            const int row = q / hn, j = row % n, k = D == 3 ? row / n : 0;
+            const int i = 2 * (q % hn) + ((colour + j + k + D) & 1);
+            const int c = cidx(n, i, j, k);
+            const double v = (nbs(U, r, g, i, j, k) - h2 * at(RHO, r, g)[c]) / double(2 * D);
+            at(U, r, g)[c] = v;
+        }
+        __syncthreads();
+    }
+    __device__ void gsrb(int g, int nsweep) const {
+        for (int q = 0; q < nsweep; q++) {
+            half(g, 0);
+            half(g, 1);
+        }
+    }
+    // grid g+1 <- means of u and of the residual rho - L u of grid g
+    __device__ void resid_restrict(int g) const {
+        const int n = GG::n(g), nc = GG::n(g + 1), NC = GG::cells(g + 1);
+        const double h = hgrid(g), ih2 = 1.0 / (h * h);
+        const double w = D == 3 ? 0.125 : 0.25;
+        for (int e = threadIdx.x; e < R * NC; e += blockDim.x) {
+            const int r = e / NC, C = e % NC;
+            int I, J, K;
+            ijk(nc, C, I, J, K);
+            double au = 0.0, ar = 0.0;
+            for (int dk = 0; dk < (D == 3 ? 2 : 1); dk++)
+                for (int dj = 0; dj < 2; dj++)
+                    for (int di = 0; di < 2; di++) {
+                        const int i = 2 * I + di, j = 2 * J + dj, k = D == 3 ? 2 * K + dk : 0;
+                        const int c = cidx(n, i, j, k);
+                        const double uc = at(U, r, g)[c];
+                        au += uc;
+                        ar += at(RHO, r, g)[c] - (nbs(U, r, g, i, j, k) - double(2 * D) * uc) * ih2;
+                    }
+            at(U, r, g + 1)[C] = w * au;
+            at(RES, r, g + 1)[C] = w * ar;
+        }
+        __syncthreads();
+    }
+    // rho of grid g -> grid g+1 (FMG)
+    __device__ void restrict_rho(int g) const {
+        const int n = GG::n(g), nc = GG::n(g + 1), NC = GG::cells(g + 1);
+        const double w = D == 3 ? 0.125 : 0.25;
+        for (int e = threadIdx.x; e < R * NC; e += blockDim.x) {
+            const int r = e / NC, C = e % NC;
+            int I, J, K;
+            ijk(nc, C, I, J, K);
+            double acc = 0.0;
+            for (int dk = 0; dk < (D == 3 ? 2 : 1); dk++)
+                for (int dj = 0; dj < 2; dj++)
+                    for (int di = 0; di < 2; di++)
+                        acc += at(RHO, r, g)[cidx(n, 2 * I + di, 2 * J + dj, D == 3 ? 2 * K + dk : 0)];
+            at(RHO, r, g + 1)[C] = w * acc;
+        }
+        __syncthreads();
+    }
+    // the copy v' of grid g and, on the roots marked in `parents` (every
+    // root below level 1), the FAS right-hand side rho <- rbar + L u
+    __device__ void uold_crhs(int g, bool all_parents) const {
+        const int n = GG::n(g), NC = GG::cells(g);
+        const double h = hgrid(g), ih2 = 1.0 / (h * h);
+        for (int e = threadIdx.x; e < R * NC; e += blockDim.x) {
+            const int r = e / NC, c = e % NC;
+            int i, j, k;
+            ijk(n, c, i, j, k);
+            const double uc = at(U, r, g)[c];
+            at(UOLD, r, g)[c] = uc;
+            if (all_parents || !(info[r].flags & FLAG_LEAF))
+                at(RHO, r, g)[c] = at(RES, r, g)[c] + (nbs(U, r, g, i, j, k) - double(2 * D) * uc) * ih2;
+        }
+        __syncthreads();
+    }
+    // u - v' on grid g at the cell (I, J, K) + one step along `axis` (sgn), or
+    // at the cell itself (sgn = 0); across a box side the difference of the
+    // ghosts of u and of v'
+    __device__ double delta(int r, int g, int axis, int sgn, int I, int J, int K) const {
+        const int n = GG::n(g);
+        if (sgn == 0) {
+            const int c = cidx(n, I, J, K);
+            return at(U, r, g)[c] - at(UOLD, r, g)[c];
+        }
+        int x[3] = {I, J, K};
+        x[axis] += sgn;
+        if (x[axis] >= 0 && x[axis] < n) {
+            const int c = cidx(n, x[0], x[1], x[2]);
+            return at(U, r, g)[c] - at(UOLD, r, g)[c];
+        }
+        const int s = 2 * axis + (sgn > 0 ? 1 : 0);
+        return across(U, r, g, s, I, J, K) - across(UOLD, r, g, s, I, J, K);
+    }
+    // u of grid g += P211(u - v' of grid g+1); with store_old, v' of grid g
+    // first receives u (FMG)
+    __device__ void prolong(int g, bool store_old) const {
+        const int n = GG::n(g), NC = GG::cells(g);
+        for (int e = threadIdx.x; e < R * NC; e += blockDim.x) {
+            const int r = e / NC, c = e % NC;
+            int i, j, k;
+            ijk(n, c, i, j, k);
+            const int I = i >> 1, J = j >> 1, K = k >> 1;
+            const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
+            double v;
+            if (D == 2)
+                v = 0.5 * delta(r, g + 1, 0, 0, I, J, K) + 0.25 * delta(r, g + 1, 0, sx, I, J, K) +
+                    0.25 * delta(r, g + 1, 1, sy, I, J, K);
+            else
+                v = 0.25 * (((delta(r, g + 1, 0, 0, I, J, K) + delta(r, g + 1, 0, sx, I, J, K)) +
+                             delta(r, g + 1, 1, sy, I, J, K)) +
+                            delta(r, g + 1, 2, sz, I, J, K));
+            const double uc = at(U, r, g)[c];
+            if (store_old) at(UOLD, r, g)[c] = uc;
+            at(U, r, g)[c] = uc + v;
+        }
+        __syncthreads();
+    }
+    // FAS V-cycle from grid g0 (paper §3.2)
+    __device__ void vcycle(int g0) const {
+        for (int g = g0; g < GG::NG - 1; g++) {
+            gsrb(g, n_down);
+            resid_restrict(g);
+            uold_crhs(g + 1, true);
+        }
+        gsrb(GG::NG - 1, n_base);
+        for (int g = GG::NG - 2; g >= g0; g--) {
+            prolong(g, false);
+            gsrb(g, n_up);
+        }
+    }
+    // FMG from a zero guess on grids 0 .. NG-1, then the V-cycle from grid 0
+    __device__ void fmg() const {
+        for (int g = 0; g < GG::NG - 1; g++) restrict_rho(g);
+        const int last = GG::NG - 1, nl = GG::cells(last);
+        for (int e = threadIdx.x; e < R * nl; e += blockDim.x) {
+            const int r = e / nl, c = e % nl;
+            at(UOLD, r, last)[c] = at(U, r, last)[c];
+        }
+        __syncthreads();
+        gsrb(last, n_base);
+        for (int g = last - 1; g >= 0; g--) {
+            prolong(g, true);
+            vcycle(g);
+        }
+    }
+};
+
+template <int D, int N, typename T>
+__global__ __launch_bounds__(COARSE_NT) void k_coarse_gen(CoarseGenArgs<T> a) {
+    using GG = GenGeo<D, N>;
+    using G = Geo<D, N>;
+    const int R = a.n_roots;
+    double *ws = a.ws;
+    GenState<D, N> st{a.info, ws, ws + (size_t)R * GG::TOT, ws + (size_t)2 * R * GG::TOT,
+                      ws + (size_t)3 * R * GG::TOT, ws + (size_t)4 * R * GG::TOT, R, a.homog,
+                      a.n_down, a.n_up, a.n_base};
+    const int mode = a.mode;
+    // level 1 from the roots' boxes (colour-split in the tree's arrays), the
+    // coarser grids start at zero
+    for (int e = threadIdx.x; e < R * GG::TOT; e += blockDim.x) {
+        const int r = e / GG::TOT, p = e % GG::TOT;
+        double u = 0.0, rho = 0.0, res = 0.0;
+        if (p < G::C) {
+            const int i = p % N, j = (p / N) % N, k = D == 3 ? p / (N * N) : 0;
+            const size_t gi = (size_t)r * G::C + cpos<D, N>(i, j, k);
+            const bool leaf = a.info[r].flags & FLAG_LEAF;
+            u = mode == COARSE_FMG ? 0.0 : (double)a.u[gi];
+            const double rg = (double)a.rho[gi];
+            // after the restriction from level 2 the rho of a refined root
+            // is the restricted residual; its FAS right-hand side follows
+            if (mode == COARSE_V_FROM_2 && !leaf) res = rg;
+            else rho = rg;
+        }
+        st.U[e] = u;
+        st.RHO[e] = rho;
+        st.RES[e] = res;
+        st.UOLD[e] = 0.0;
+    }
+    // boundary values: the roots' rows on grid 0, means of the covered
+    // values below
+    for (int e = threadIdx.x; e < R * 2 * D * G::F; e += blockDim.x) {
+        const int r = e / (2 * D * G::F), g = e % (2 * D * G::F), s = g / G::F;
+        const int32_t row = a.info[r].bcoff[s];
+        st.BC[(size_t)r * GG::BTOT + g] = (row >= 0 && !a.homog) ? a.bc[(size_t)row * G::F + g % G::F] : 0.0;
+    }
+    __syncthreads();
+    for (int gl = 1; gl < GG::NG; gl++) {
+        const int n = GG::n(gl), F = GG::fsz(gl), Ff = GG::fsz(gl - 1), nf = 2 * n;
+        for (int e = threadIdx.x; e < R * 2 * D * F; e += blockDim.x) {
+            const int r = e / (2 * D * F), g = e % (2 * D * F), s = g / F, m = g % F;
+            const int A = m % n, Cc = D == 3 ? m / n : 0;
+            const double *src = st.BC + (size_t)r * GG::BTOT + GG::boff(gl - 1) + s * Ff;
+            double acc = 0.0;
+            for (int dc = 0; dc < (D == 3 ? 2 : 1); dc++)
+                for (int da = 0; da < 2; da++) acc += src[(2 * A + da) + nf * (2 * Cc + dc)];
+            st.BC[(size_t)r * GG::BTOT + GG::boff(gl) + s * F + m] = acc * (D == 3 ? 0.25 : 0.5);
+        }
+        __syncthreads();
+    }
+    if (mode == COARSE_V_FROM_2) {
+        st.uold_crhs(0, false);
+        st.vcycle(0);
+    } else if (mode == COARSE_FMG) {
+        st.fmg();
+    } else {
+        st.vcycle(0);
+    }
+    for (int e = threadIdx.x; e < R * G::C; e += blockDim.x) {
+        const int r = e / G::C, p = e % G::C;
+        const int i = p % N, j = (p / N) % N, k = D == 3 ? p / (N * N) : 0;
+        const size_t gi = (size_t)r * G::C + cpos<D, N>(i, j, k);
+        a.u[gi] = (T)st.U[(size_t)r * GG::TOT + p];
+        if (a.uold && mode != COARSE_V_TOP1) a.uold[gi] = (T)st.UOLD[(size_t)r * GG::TOT + p];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // the composite operator and its transpose on leaf cells (adjoint)
 // ---------------------------------------------------------------------------
 // With homogeneous Dirichlet values the composite operator L is a sparse
@@ -1997,7 +2311,7 @@ __device__ double lt_face(const BoxInfo &bi, const int c[3], const double *s, co
     using G = Geo<D, N>;
     const int v = bi.nbr[S];
     const double yc = s[padi<D, N>(c[0], c[1], c[2])];
-    if (v == -1) return -ih2 * yc;
+    if (v == -1) return neumann_side(bi.flags, S) ? ih2 * yc : -ih2 * yc;
     if (v >= 0) {
         if (!(bi.flags & (FLAG_NBR_REFINED << S))) {
             int o[3] = {c[0], c[1], c[2]};
@@ -2123,7 +2437,7 @@ __global__ __launch_bounds__(256) void k_apply_l(const BoxInfo *__restrict__ inf
     const bool leaf = bi.flags & FLAG_LEAF;
     const size_t bo = (size_t)sl.b * G::C;
     Stager<D, N, double> st;
-    if (sl.valid && leaf) st.begin(s, bi, x + bo, x, nullptr, 1, sl.t, true);
+    if (sl.valid && leaf) st.begin(s, bi, x + bo, x, nullptr, 1, sl.t, true, 0.0);
     __syncthreads();
     if (sl.valid && leaf) st.end(s, sl.t);
     __syncthreads();
@@ -2250,9 +2564,10 @@ __global__ __launch_bounds__(256) void k_store_leaves(const BoxInfo *__restrict_
     }
 }
 
-// gradient with respect to the Dirichlet rows of the leaves:
-// d loss / d b_f = -2 lambda_c(f) / h^2 (the boundary part of the rhs is
-// 2 b / h^2 per Dirichlet side of a cell)
+// gradient with respect to the boundary rows of the leaves:
+// d loss / d b_f = -2 lambda_c(f) / h^2 for a Dirichlet side (the boundary
+// part of the rhs is 2 b / h^2 per Dirichlet side of a cell) and
+// -lambda_c(f) / h for a Neumann side (q / h per Neumann side)
 template <int D, int N>
 __global__ __launch_bounds__(256) void k_bc_grad(const BoxInfo *__restrict__ info, const double *__restrict__ lam,
                                                  double *__restrict__ bc_bar, int nb) {
@@ -2271,7 +2586,8 @@ __global__ __launch_bounds__(256) void k_bc_grad(const BoxInfo *__restrict__ inf
     x[t2] = D == 3 ? m / N : 0;
     x[d] = hi ? N - 1 : 0;
     const double ih2 = level_ih2(N, bi->level);
-    bc_bar[(size_t)bi->bcoff[side] * G::F + m] = -2.0 * ih2 * lam[(size_t)b * G::C + cpos<D, N>(x[0], x[1], x[2])];
+    const double lc = lam[(size_t)b * G::C + cpos<D, N>(x[0], x[1], x[2])];
+    bc_bar[(size_t)bi->bcoff[side] * G::F + m] = neumann_side(bi->flags, side) ? -sqrt(ih2) * lc : -2.0 * ih2 * lc;
 }
 
 // ---------------------------------------------------------------------------
@@ -2382,6 +2698,15 @@ void launch_level_mask(const int *base, const int32_t *tree_lmax, int l, int *ou
 template <int D, int N, typename T>
 void launch_coarse(const CoarseArgs<T> &a, int n_trees, hipStream_t st) {
     if (n_trees > 0) hipLaunchKernelGGL((k_coarse<D, N, T>), dim3(n_trees), dim3(COARSE_NT), 0, st, a);
+}
+
+template <int D, int N, typename T>
+void launch_coarse_gen(const CoarseGenArgs<T> &a, hipStream_t st) {
+    hipLaunchKernelGGL((k_coarse_gen<D, N, T>), dim3(1), dim3(COARSE_NT), 0, st, a);
+}
+template <int D, int N>
+size_t coarse_gen_doubles(int n_roots) {
+    return (size_t)n_roots * (4 * GenGeo<D, N>::TOT + GenGeo<D, N>::BTOT);
 }
 
 template <int D, int N, typename T>
@@ -2503,6 +2828,7 @@ AFMG_ADJ_INST(3, 8)
     template void launch_final<D, N, T>(const LevelArgs<T> &, double *, int64_t, double, float *, int, \
                                         hipStream_t);                                                 \
     template void launch_coarse<D, N, T>(const CoarseArgs<T> &, int, hipStream_t);                      \
+    template void launch_coarse_gen<D, N, T>(const CoarseGenArgs<T> &, hipStream_t);                     \
     template void launch_permute<D, N, T>(const BoxInfo *, T *, int64_t, int64_t, int, int, hipStream_t); \
     template void launch_load_rho<D, N, T>(const BoxInfo *, const int32_t *, const T *, T *, int64_t, int, \
                                            hipStream_t);                                              \
@@ -2516,6 +2842,8 @@ template void launch_ir_update<2, 8>(const BoxInfo *, double *, float *, int64_t
 template void launch_ir_update<3, 8>(const BoxInfo *, double *, float *, int64_t, const int *, hipStream_t);
 template void launch_copy<float>(const float *, float *, int64_t, hipStream_t);
 template void launch_fill<float>(float *, int64_t, float, hipStream_t);
+template size_t coarse_gen_doubles<2, 8>(int);
+template size_t coarse_gen_doubles<3, 8>(int);
 template int final_wgs<2, 8>(int64_t, int);
 template int final_wgs<3, 8>(int64_t, int);
 template void launch_bc_derive<2, 8>(const BoxInfo *, int64_t, int64_t, double *, hipStream_t);

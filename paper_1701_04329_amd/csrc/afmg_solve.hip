@@ -127,7 +127,7 @@ double level_h(int l) { return 1.0 / ((double)BOX_N * std::ldexp(1.0, l - 1)); }
 // all 2^(D (l-1)) boxes present, so that box index = key); 0 otherwise
 int cube_xmask(const HostTree &h, int l) {
     const int lg = l - 1;
-    if (h.n_trees != 1 || lg < 1 || h.dim * lg > 30) return 0;
+    if (h.n_trees != 1 || h.general || lg < 1 || h.dim * lg > 30) return 0;
     if (h.level_count(l) != ((int64_t)1 << (h.dim * lg))) return 0;
     int m = 0;
     for (int b = 0; b < lg; b++) m |= 1 << (h.dim * b);
@@ -136,9 +136,16 @@ int cube_xmask(const HostTree &h, int l) {
 
 struct WsLayout {
     // FP64: rho, uold; mixed: rho (FP64 leaf rho), e, rho_e, uold_e (FP32);
-    // forests also hold the working u
-    size_t rho, uold, bc, partial, e, rho_e, uold_e, u, total;
+    // forests also hold the working u; general domains the grids of the
+    // coarse kernel
+    size_t rho, uold, bc, partial, e, rho_e, uold_e, u, cg, total;
 };
+
+// doubles of the general coarse kernel's grids (0 unless the domain is general)
+size_t coarse_gen_bytes(const HostTree &h) {
+    if (!h.general) return 0;
+    return sizeof(double) * (h.dim == 3 ? coarse_gen_doubles<3, 8>(h.n_roots) : coarse_gen_doubles<2, 8>(h.n_roots));
+}
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -158,6 +165,7 @@ WsLayout ws_layout(const afmg_tree *t, int precision) {
     L.rho_e = off; off = align256(off + (mixed ? nb * C * sizeof(float) : 0));
     L.uold_e = off; off = align256(off + (mixed ? nlt * C * sizeof(float) : 0));
     L.u = off; off = align256(off + (t->forest ? nb * C * sizeof(double) : 0));
+    L.cg = off; off = align256(off + coarse_gen_bytes(h));
     L.total = off;
     return L;
 }
@@ -188,7 +196,6 @@ TuneLayout tune_layout(const afmg_tree *t) {
 template <int D>
 int64_t final_wgs_d(int64_t nb, int wg) { return final_wgs<D, BOX_N>(nb, wg); }
 
-bool root_is_leaf(const HostTree &h) { return h.info[0].flags & FLAG_LEAF; }
 
 // k_final partial offsets per level for the current shapes, and the count
 // for the smallest workgroups (the workspace is sized for that)
@@ -201,7 +208,7 @@ void compute_partials(afmg_tree *t) {
     int64_t n = 0, nmax = 0;
     for (int l = h.lmax; l >= 1; l--) {
         t->part_off[(size_t)l] = n;
-        if (l >= 2 || root_is_leaf(h)) {
+        if (l >= 2 || h.level1_leaf) {
             const int wg = t->shapes[0][SK_FINAL][(size_t)l].wg;
             n += h.dim == 3 ? final_wgs_d<3>(h.level_count(l), wg) : final_wgs_d<2>(h.level_count(l), wg);
             nmax += h.dim == 3 ? final_wgs_d<3>(h.level_count(l), 64) : final_wgs_d<2>(h.level_count(l), 64);
@@ -341,8 +348,9 @@ struct Cycler {
     const afmg_opts &o;
     Prof &prof;
     LevelArgs<T> base;
-    const double *bc64;  // Dirichlet rows for the coarse kernel (null when homogeneous)
+    const double *bc64;  // boundary rows for the coarse kernel (null when homogeneous)
     afmg_tree *t;        // forests: tree levels and the FMG step mask
+    double *cg = nullptr;  // general domains: the grids of the coarse kernel
     // mixed-precision correction on a tree whose leaves all lie on level
     // lmax (complete): the last half sweep of a V-cycle from lmax adds e to
     // this FP64 solution and clears e (see fuses_update)
@@ -365,6 +373,7 @@ struct Cycler {
         const double hh = level_h(l);
         a.h2 = (T)(hh * hh);
         a.ih2 = (T)(1.0 / (hh * hh));
+        a.h = (T)hh;
         return a;
     }
     void level(Op op, int l, int colour = 0, bool time = true, double *add = nullptr, bool own_zero = false) {
@@ -404,8 +413,15 @@ struct Cycler {
         if (add) level(Op::GSRB, l, 1, false, add);
     }
     // one workgroup per tree; a tree that is its root box alone takes the
-    // top-level-1 path inside the kernel
+    // top-level-1 path inside the kernel.  General domains: one workgroup for
+    // all level-1 boxes and the grids below them.
     void coarse(int mode) {
+        if (h.general) {
+            CoarseGenArgs<T> c{base.info, base.u, base.rho, h.lmax >= 2 ? base.uold : nullptr, bc64, cg,
+                               h.n_roots, mode, base.homog, o.n_down, o.n_up, o.n_base};
+            launch_coarse_gen<D, BOX_N, T>(c, st);
+            return;
+        }
         CoarseArgs<T> c{base.info, base.u, base.rho, base.uold, bc64, mode, base.homog,
                         o.n_down, o.n_up, o.n_base, base.active};
         if (h.lmax == 1) c.uold = nullptr;
@@ -418,19 +434,22 @@ struct Cycler {
         launch_coarse<D, BOX_N, T>(c, h.n_trees, st);
     }
     // V-cycle from level top: levels >= 3 box by box, levels <= 2 in the
-    // coarse kernel (level 2, the 2^D children of the root, as one grid)
+    // coarse kernel (level 2, the 2^D children of the root, as one grid);
+    // general domains: levels >= 2 box by box, levels <= 1 in their coarse
+    // kernel
     void vcycle(int top) {
         if (top < 2) {
             coarse(COARSE_V_TOP1);
             return;
         }
-        for (int l = top; l >= 3; l--) {
+        const int lo = h.general ? 2 : 3;
+        for (int l = top; l >= lo; l--) {
             gsrb(l, o.n_down, nullptr, l == top && zero_start && fuses_update(top));
             level(Op::RESID_RESTRICT, l);
-            if (l - 1 >= 3) level(Op::COARSE_RHS, l - 1);
+            if (l - 1 >= lo) level(Op::COARSE_RHS, l - 1);
         }
-        coarse(top >= 3 ? COARSE_V2_FROM_3 : COARSE_V2_TOP);
-        for (int l = 3; l <= top; l++) {
+        coarse(h.general ? COARSE_V_FROM_2 : top >= 3 ? COARSE_V2_FROM_3 : COARSE_V2_TOP);
+        for (int l = lo; l <= top; l++) {
             level(Op::PROLONG, l);
             gsrb(l, o.n_up, l == top && fuses_update(top) ? add_to : nullptr);
         }
@@ -486,7 +505,7 @@ struct Solver {
     // (restrict_parents() fills them at the end of a solve).
     void finalize_launch(float *rout, hipStream_t s, int lfirst = 1) {
         for (int l = h.lmax; l >= std::max(1, lfirst); l--) {
-            if (l == 1 && !t->forest && !root_is_leaf(h)) continue;
+            if (l == 1 && !t->forest && !h.level1_leaf) continue;
             const double hh = level_h(l);
             const double hD = D == 3 ? hh * hh * hh : hh * hh;
             LevelArgs<double> a = base;
@@ -494,6 +513,7 @@ struct Solver {
             a.nb = (int)h.level_count(l);
             a.h2 = hh * hh;
             a.ih2 = 1.0 / (hh * hh);
+            a.h = hh;
             const Shape sh = t->shapes[0][SK_FINAL][(size_t)l];
             a.no_remap = sh.no_remap;
             prof.timed(
@@ -771,6 +791,7 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
         // nothing to iterate
     } else if (!mixed) {
         Cycler<D, double> cy{h, st, o, s.prof, s.base, bc_w, t};
+        cy.cg = (double *)(ws + L.cg);
         if (o.cycle == AFMG_CYCLE_FMG_V) {
             rc = s.upload_mask();
             if (rc != AFMG_OK) return rc;
@@ -803,6 +824,7 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
         LevelArgs<float> b32{t->d_info, e32, rho32, (float *)(ws + L.uold_e), nullptr, 0, 0, 1, 0.f, 0.f,
                              t->d_active};
         Cycler<D, float> cy{h, st, o, s.prof, b32, nullptr, t};
+        cy.cg = (double *)(ws + L.cg);
         if (!t->forest && h.uniform && cube_xmask(h, h.lmax) != 0) cy.add_to = uw;
         if (o.cycle != AFMG_CYCLE_FMG_V) launch_fill<float>(e32, h.n_boxes * C, 0.f, st);
         auto refine = [&](hipStream_t cs, bool first_fmg) {
@@ -861,7 +883,7 @@ struct AdjLayout {
     // Krylov vectors and preconditioner arrays, each [n_boxes][N^D] FP64
     enum { X, R, RH, P, V, SV, T, PH, SH, B, PU, PRHO, NVEC };
     size_t vec[NVEC];
-    size_t puold, bc, partial, norm, total;
+    size_t puold, bc, partial, norm, cg, total;
 };
 
 AdjLayout adj_layout(const afmg_tree *t) {
@@ -879,6 +901,7 @@ AdjLayout adj_layout(const afmg_tree *t) {
     const size_t np = (size_t)std::max<int64_t>(t->n_parts_max, DOT_WGS);
     L.partial = off; off = align256(off + np * 2 * sizeof(double));
     L.norm = off; off = align256(off + 2 * sizeof(double));
+    L.cg = off; off = align256(off + coarse_gen_bytes(h));
     L.total = off;
     return L;
 }
@@ -962,6 +985,7 @@ int adjoint(afmg_tree *t, hipStream_t st, const double *ubar, double *rho_bar, d
         // Dirichlet values, one more multigrid solve
         s.base = LevelArgs<double>{t->d_info, X, B, (double *)(ws + A.L.puold), bcz, 0, 0, 1, 0.0, 0.0};
         Cycler<D, double> cy{h, st, o, s.prof, s.base, nullptr, t};
+        cy.cg = (double *)(ws + A.L.cg);
         rc = s.finalize(S.r0_max, S.r0_l2, nullptr);
         if (rc != AFMG_OK) return rc;
         S.r_max = S.r0_max;
@@ -980,6 +1004,7 @@ int adjoint(afmg_tree *t, hipStream_t st, const double *ubar, double *rho_bar, d
         double *PU = A.vec(AdjLayout::PU), *PRHO = A.vec(AdjLayout::PRHO);
         LevelArgs<double> pb{t->d_info, PU, PRHO, (double *)(ws + A.L.puold), bcz, 0, 0, 1, 0.0, 0.0};
         Cycler<D, double> cy{h, st, o, s.prof, pb, nullptr, t};
+        cy.cg = (double *)(ws + A.L.cg);
         auto precond = [&](const double *in, double *out) {
             launch_scale_leaves<D, BOX_N>(t->d_info, PRHO, in, -1, h.n_boxes, st);
             launch_fill<double>(PU, n, 0.0, st);
@@ -1092,16 +1117,22 @@ int step(afmg_tree *t, hipStream_t st, int op, int level, int colour, int homog,
     const double hh = level_h(level);
     a.h2 = hh * hh;
     a.ih2 = 1.0 / (hh * hh);
+    a.h = hh;
     switch (op) {
     case AFMG_STEP_HALF_SWEEP: launch_level<D, BOX_N, double>(Op::GSRB, a, colour, 256, st); break;
     case AFMG_STEP_RESID_RESTRICT: launch_level<D, BOX_N, double>(Op::RESID_RESTRICT, a, 0, 256, st); break;
     case AFMG_STEP_COARSE_RHS: launch_level<D, BOX_N, double>(Op::COARSE_RHS, a, 0, 256, st); break;
     case AFMG_STEP_PROLONG: launch_level<D, BOX_N, double>(Op::PROLONG, a, 0, 256, st); break;
-    default: {
-        CoarseArgs<double> c{t->d_info, u, rho, uold, homog ? nullptr : bc_w, COARSE_V_FROM_2, homog,
-                             o.n_down, o.n_up, o.n_base, nullptr};
-        launch_coarse<D, BOX_N, double>(c, 1, st);
-    }
+    default:
+        if (h.general) {
+            CoarseGenArgs<double> c{t->d_info, u, rho, uold, homog ? nullptr : bc_w, (double *)(ws + L.cg),
+                                    h.n_roots, COARSE_V_FROM_2, homog, o.n_down, o.n_up, o.n_base};
+            launch_coarse_gen<D, BOX_N, double>(c, st);
+        } else {
+            CoarseArgs<double> c{t->d_info, u, rho, uold, homog ? nullptr : bc_w, COARSE_V_FROM_2, homog,
+                                 o.n_down, o.n_up, o.n_base, nullptr};
+            launch_coarse<D, BOX_N, double>(c, 1, st);
+        }
     }
     for (double *f : {u, rho, uold}) launch_permute<D, BOX_N, double>(t->d_info, f, 0, h.n_boxes, 0, 0, st);
     hipError_t e = hipGetLastError();
@@ -1155,6 +1186,7 @@ void tune_precision(afmg_tree *t, hipStream_t st, LevelArgs<T> base, double *par
             const double hh = level_h(l);
             a.h2 = (T)(hh * hh);
             a.ih2 = (T)(1.0 / (hh * hh));
+            a.h = (T)hh;
             const Op op = kind == SK_GSRB ? Op::GSRB
                           : kind == SK_RESID ? Op::RESID_RESTRICT
                           : kind == SK_CRHS ? Op::COARSE_RHS : Op::PROLONG;
@@ -1305,8 +1337,8 @@ void afmg_default_opts(afmg_opts *o) {
     o->check_every = 1;
 }
 
-int afmg_tree_create(int dim, int box_n, int64_t n_leaves, const int32_t *level, const int32_t *idx,
-                     afmg_tree **out) {
+int afmg_tree_create_domain(int dim, int box_n, const int32_t *bc_type, int64_t n_leaves, const int32_t *level,
+                            const int32_t *idx, afmg_tree **out) {
     if (!out) return fail(AFMG_ERR_ARG, "out is null");
     *out = nullptr;
     afmg_tree *t = nullptr;
@@ -1314,7 +1346,7 @@ int afmg_tree_create(int dim, int box_n, int64_t n_leaves, const int32_t *level,
         t = new afmg_tree();
         std::string msg;
         const int64_t off[2] = {0, n_leaves};
-        int rc = build_tree(dim, box_n, 1, off, level, idx, t->h, msg);
+        int rc = build_tree(dim, box_n, 1, off, level, idx, t->h, msg, bc_type);
         if (rc != AFMG_OK) {
             delete t;
             return fail(rc, msg);
@@ -1326,6 +1358,21 @@ int afmg_tree_create(int dim, int box_n, int64_t n_leaves, const int32_t *level,
     }
     *out = t;
     return AFMG_OK;
+}
+
+int afmg_tree_create(int dim, int box_n, int64_t n_leaves, const int32_t *level, const int32_t *idx,
+                     afmg_tree **out) {
+    if (!out) return fail(AFMG_ERR_ARG, "out is null");
+    *out = nullptr;
+    if (!level || !idx || n_leaves <= 0) return fail(AFMG_ERR_ARG, "empty or null leaf list");
+    // one level-1 box at (1, 1, 1): every leaf index within 2^(level - 1)
+    for (int64_t q = 0; q < n_leaves; q++) {
+        const int l = level[q];
+        if (l < 1 || l > 30) return fail(AFMG_ERR_ARG, "leaf level out of range");
+        for (int d = 0; d < (dim == 3 ? 3 : 2); d++)
+            if (idx[3 * q + d] > (1 << (l - 1))) return fail(AFMG_ERR_ARG, "leaf spatial index out of range");
+    }
+    return afmg_tree_create_domain(dim, box_n, nullptr, n_leaves, level, idx, out);
 }
 
 void afmg_tree_destroy(afmg_tree *t) {
@@ -1346,6 +1393,10 @@ int afmg_tree_info(const afmg_tree *t, afmg_tree_desc *out) {
     out->lmax = h.lmax;
     out->cells_per_box = cells_per_box(h.dim);
     out->n_unknowns = h.n_leaves * cells_per_box(h.dim);
+    out->n_roots = h.n_roots;
+    for (int d = 0; d < 3; d++) out->ext[d] = h.ext[d];
+    for (int s = 0; s < 6; s++) out->bc_type[s] = h.bc_type[s];
+    out->singular = h.singular ? 1 : 0;
     return AFMG_OK;
 }
 
@@ -1393,7 +1444,8 @@ int afmg_tree_refine(const afmg_tree *t, const int32_t *ids, int64_t n, int bala
         std::string msg;
         const int rc = refine_leaves(t->h, ids, n, balance, level, idx, msg);
         if (rc != AFMG_OK) return fail(rc, msg);
-        return afmg_tree_create(t->h.dim, t->h.N, (int64_t)level.size(), level.data(), idx.data(), out);
+        return afmg_tree_create_domain(t->h.dim, t->h.N, t->h.general ? t->h.bc_type : nullptr,
+                                       (int64_t)level.size(), level.data(), idx.data(), out);
     } catch (const std::bad_alloc &) {
         return fail(AFMG_ERR_OOM, "host allocation failed");
     }
@@ -1462,6 +1514,8 @@ int afmg_adjoint(afmg_tree *t, void *stream, const double *u_bar, double *rho_ba
     if (!aligned(u_bar, 8) || !aligned(rho_bar, 8) || (bc_bar && !aligned(bc_bar, 8)) || !aligned(workspace, 256))
         return fail(AFMG_ERR_ARG, "misaligned array");
     if (workspace_bytes < adj_layout(t).total) return fail(AFMG_ERR_ARG, "workspace too small");
+    if (t->h.singular)
+        return fail(AFMG_ERR_ARG, "afmg_adjoint: without a Dirichlet side the operator is singular");
     std::memset(stats, 0, sizeof(*stats));
     rc = bind_device(t);
     if (rc != AFMG_OK) return rc;
@@ -1521,6 +1575,8 @@ int afmg_batch_create(afmg_tree *const *trees, int n_trees, afmg_batch **out) {
     for (int i = 0; i < n_trees; i++) {
         if (!trees[i]) return fail(AFMG_ERR_ARG, "null tree");
         if (trees[i]->forest) return fail(AFMG_ERR_ARG, "not a tree");
+        if (trees[i]->h.general)
+            return fail(AFMG_ERR_ARG, "batches take trees of one level-1 box with Dirichlet sides");
         if (trees[i]->h.dim != trees[0]->h.dim || trees[i]->h.N != trees[0]->h.N)
             return fail(AFMG_ERR_ARG, "trees of one batch must share dim and box_n");
     }

@@ -1,7 +1,9 @@
 // Host-side construction of a tree, or a forest of independent trees, from
 // leaf lists (paper §2.1-§2.3): ancestors, completeness and 2:1 checks, Morton
 // order per level (§2.3), neighbour / parent / child tables, and the
-// numbering of Dirichlet rows.
+// numbering of boundary rows.  A single tree may have a coarse grid of several
+// level-1 boxes on an integer lattice (§2.2) and Dirichlet, Neumann or
+// periodic sides (§3); periodic axes wrap the neighbour search.
 //
 // Box numbering: by level over the whole forest, then by tree, then Morton
 // index.  The boxes of one level of all trees form one contiguous range, the
@@ -58,8 +60,21 @@ uint64_t morton(int dim, int i, int j, int k) {
 
 }  // namespace
 
+bool domain_position(const HostTree &t, int l, int q[3]) {
+    int r[3] = {1, 1, 1};
+    for (int d = 0; d < t.dim; d++) {
+        const int n1 = t.ext[d] << (l - 1);
+        if (q[d] < 1 || q[d] > n1) {
+            if (t.bc_type[2 * d] != BC_PERIODIC) return false;
+            q[d] = q[d] < 1 ? q[d] + n1 : q[d] - n1;
+        }
+        r[d] = ((q[d] - 1) >> (l - 1)) + 1;
+    }
+    return t.root_at[(size_t)((r[2] - 1) * t.ext[1] + (r[1] - 1)) * t.ext[0] + (r[0] - 1)] != 0;
+}
+
 int build_tree(int dim, int N, int n_trees, const int64_t *tree_off, const int32_t *level, const int32_t *idx,
-               HostTree &t, std::string &msg) {
+               HostTree &t, std::string &msg, const int32_t *bc_type) {
     if (dim != 2 && dim != 3) { msg = "dim must be 2 or 3"; return AFMG_ERR_ARG; }
     if (N != 8) { msg = "box_n must be 8"; return AFMG_ERR_ARG; }
     if (n_trees <= 0 || !tree_off || !level || !idx) { msg = "empty or null leaf list"; return AFMG_ERR_ARG; }
@@ -69,6 +84,34 @@ int build_tree(int dim, int N, int n_trees, const int64_t *tree_off, const int32
     const int64_t n_leaves = tree_off[n_trees];
     if (n_leaves > (int64_t)1 << 28) { msg = "too many leaves"; return AFMG_ERR_ARG; }
     const int max_level = dim == 3 ? 17 : 20;  // keeps box counts and indices in int32
+    // the domain (one tree only): side types and the lattice of level-1
+    // boxes; forests are trees of one level-1 box with Dirichlet sides
+    for (int s = 0; s < 6; s++) t.bc_type[s] = BC_DIRICHLET;
+    t.ext[0] = t.ext[1] = t.ext[2] = 1;
+    if (bc_type) {
+        if (n_trees != 1) { msg = "side types apply to single trees"; return AFMG_ERR_ARG; }
+        for (int s = 0; s < 2 * dim; s++) {
+            if (bc_type[s] < BC_DIRICHLET || bc_type[s] > BC_PERIODIC) { msg = "bad side type"; return AFMG_ERR_ARG; }
+            t.bc_type[s] = bc_type[s];
+        }
+        for (int d = 0; d < dim; d++)
+            if ((t.bc_type[2 * d] == BC_PERIODIC) != (t.bc_type[2 * d + 1] == BC_PERIODIC)) {
+                msg = "periodic sides come in pairs";
+                return AFMG_ERR_ARG;
+            }
+        for (int64_t q = 0; q < n_leaves; q++) {
+            const int l = level[q];
+            if (l < 1 || l > max_level) { msg = "leaf level out of range"; return AFMG_ERR_ARG; }
+            for (int d = 0; d < dim; d++) {
+                const int c = idx[3 * q + d];
+                if (c < 1 || ((int64_t)(c - 1) >> (l - 1)) >= 64) { msg = "leaf spatial index out of range"; return AFMG_ERR_ARG; }
+                t.ext[d] = std::max(t.ext[d], ((c - 1) >> (l - 1)) + 1);
+            }
+            if (dim == 2 && idx[3 * q + 2] != 1) { msg = "leaf spatial index out of range"; return AFMG_ERR_ARG; }
+        }
+        if ((int64_t)t.ext[0] * t.ext[1] * t.ext[2] > 4096) { msg = "coarse grid larger than 4096 boxes"; return AFMG_ERR_ARG; }
+    }
+    t.root_at.assign((size_t)t.ext[0] * t.ext[1] * t.ext[2], 0);
     struct Box { Key key; bool leaf; int64_t input; };
     std::vector<Box> boxes;
     std::unordered_map<Key, int64_t, KeyHash> map;
@@ -78,9 +121,15 @@ int build_tree(int dim, int N, int n_trees, const int64_t *tree_off, const int32
         for (int64_t q = tree_off[tr]; q < tree_off[tr + 1]; q++) {
             Key k{tr, level[q], idx[3 * q], idx[3 * q + 1], dim == 3 ? idx[3 * q + 2] : 1};
             if (k.l < 1 || k.l > max_level) { msg = "leaf level out of range"; return AFMG_ERR_ARG; }
-            int n1 = 1 << (k.l - 1);
-            if (k.i < 1 || k.i > n1 || k.j < 1 || k.j > n1 || k.k < 1 || k.k > (dim == 3 ? n1 : 1)) {
+            const int n1 = 1 << (k.l - 1);
+            if (k.i < 1 || k.i > t.ext[0] * n1 || k.j < 1 || k.j > t.ext[1] * n1 || k.k < 1 ||
+                k.k > (dim == 3 ? t.ext[2] * n1 : 1)) {
                 msg = "leaf spatial index out of range";
+                return AFMG_ERR_ARG;
+            }
+            // Morton keys hold 21 bits per axis in 3D
+            if (dim == 3 && ((int64_t)std::max(t.ext[0], std::max(t.ext[1], t.ext[2])) << (k.l - 1)) > (1 << 21)) {
+                msg = "leaf level too fine for the extent of the coarse grid";
                 return AFMG_ERR_ARG;
             }
             auto ins = map.emplace(k, (int64_t)boxes.size());
@@ -101,6 +150,21 @@ int build_tree(int dim, int N, int n_trees, const int64_t *tree_off, const int32
             boxes.push_back({p, false, -1});
             k = p;
         }
+    }
+    // level-1 boxes on the lattice; periodic axes need every position
+    int64_t n_roots = 0;
+    for (const Box &b : boxes)
+        if (b.key.l == 1) {
+            // (forests: every tree's one level-1 box sits at (1, 1, 1))
+            n_roots++;
+            t.root_at[(size_t)((b.key.k - 1) * t.ext[1] + (b.key.j - 1)) * t.ext[0] + (b.key.i - 1)] = 1;
+        }
+    t.n_roots = n_trees == 1 ? (int)n_roots : 1;
+    bool periodic = false;
+    for (int d = 0; d < dim; d++) periodic |= t.bc_type[2 * d] == BC_PERIODIC;
+    if (periodic && n_roots != (int64_t)t.ext[0] * t.ext[1] * t.ext[2]) {
+        msg = "periodic sides need a rectangular coarse grid";
+        return AFMG_ERR_ARG;
     }
     // every refined box has all 2^D children
     const int nch = 1 << dim;
@@ -172,17 +236,23 @@ int build_tree(int dim, int N, int n_trees, const int64_t *tree_off, const int32
             Key p{key.tr, key.l - 1, (key.i + 1) / 2, (key.j + 1) / 2, dim == 3 ? (key.k + 1) / 2 : 1};
             bi.parent = (int32_t)newid[(size_t)map.at(p)];
         }
-        const int n1 = 1 << (key.l - 1);
         for (int s = 0; s < 2 * dim; s++) {
             int d = s / 2, dir = (s & 1) ? 1 : -1;
             int q[3] = {key.i, key.j, key.k};
             q[d] += dir;
-            if (q[d] < 1 || q[d] > n1) { bi.nbr[s] = -1; continue; }
+            // outside the lattice on a non-periodic axis, or a lattice
+            // position without a level-1 box: a physical side
+            if (!domain_position(t, key.l, q)) {
+                bi.nbr[s] = -1;
+                if (t.bc_type[s] == BC_NEUMANN) bi.flags |= FLAG_NEUMANN << s;
+                continue;
+            }
             auto it = map.find(Key{key.tr, key.l, q[0], q[1], q[2]});
             if (it != map.end()) { bi.nbr[s] = (int32_t)newid[(size_t)it->second]; continue; }
             int pq[3] = {(key.i + 1) / 2, (key.j + 1) / 2, dim == 3 ? (key.k + 1) / 2 : 1};
             pq[d] += dir;
-            auto itp = map.find(Key{key.tr, key.l - 1, pq[0], pq[1], pq[2]});
+            const bool inside = domain_position(t, key.l - 1, pq);
+            auto itp = inside ? map.find(Key{key.tr, key.l - 1, pq[0], pq[1], pq[2]}) : map.end();
             if (itp == map.end()) { msg = "grid is not 2:1 balanced across a box side"; return AFMG_ERR_TREE; }
             bi.nbr[s] = -2 - (int32_t)newid[(size_t)itp->second];
         }
@@ -198,10 +268,16 @@ int build_tree(int dim, int N, int n_trees, const int64_t *tree_off, const int32
     }
     t.uniform = true;
     t.lmin_leaf = t.lmax;
+    t.singular = true;
+    for (int s = 0; s < 2 * dim; s++) t.singular &= t.bc_type[s] != BC_DIRICHLET;
+    t.general = t.n_roots > 1;
+    for (int s = 0; s < 2 * dim; s++) t.general |= t.bc_type[s] != BC_DIRICHLET;
+    t.level1_leaf = false;
     for (int64_t m = 0; m < nb; m++) {
         BoxInfo &bi = t.info[(size_t)m];
         if ((bi.flags & FLAG_LEAF) && bi.level != t.tree_lmax[(size_t)bi.tree]) t.uniform = false;
         if ((bi.flags & FLAG_LEAF) && bi.level < t.lmin_leaf) t.lmin_leaf = bi.level;
+        if ((bi.flags & FLAG_LEAF) && bi.level == 1) t.level1_leaf = true;
         for (int s = 0; s < 2 * dim; s++) {
             const int v = bi.nbr[s];
             if (v >= 0 && !(t.info[(size_t)v].flags & FLAG_LEAF)) bi.flags |= FLAG_NBR_REFINED << s;
@@ -219,7 +295,8 @@ int build_tree(int dim, int N, int n_trees, const int64_t *tree_off, const int32
             if (t.info[(size_t)m].flags & FLAG_LEAF)
                 t.tree_leaf_box[(size_t)next[(size_t)t.info[(size_t)m].tree]++] = (int32_t)m;
     }
-    // Dirichlet rows: leaf sides first (box order, side order), then parents
+    // boundary rows (Dirichlet values or Neumann derivatives): leaf sides
+    // first (box order, side order), then parents
     t.bface_box.clear();
     t.bface_side.clear();
     for (int pass = 0; pass < 2; pass++) {
@@ -266,10 +343,14 @@ int refine_leaves(const HostTree &t, const int32_t *ids, int64_t n, int balance,
             work.push_back(m);
         }
     }
-    // the leaf covering position (l, i, j, k), or -1 outside the domain
+    // the leaf covering position (l, i, j, k) (periodic axes wrapped), or -1
+    // outside the domain
     auto covering = [&](int l, int i, int j, int k) -> int64_t {
-        const int n1 = 1 << (l - 1);
-        if (i < 1 || i > n1 || j < 1 || j > n1 || k < 1 || k > (dim == 3 ? n1 : 1)) return -1;
+        int q[3] = {i, j, dim == 3 ? k : 1};
+        if (!domain_position(t, l, q)) return -1;
+        i = q[0];
+        j = q[1];
+        k = q[2];
         while (l >= 1) {
             auto it = leaf.find(Key{0, l, i, j, k});
             if (it != leaf.end()) return it->second;

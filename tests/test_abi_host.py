@@ -349,3 +349,75 @@ def test_noalloc_argument_checks_without_device():
     assert L.afmg_solve_noalloc(big.handle, None, fake, None, fake, C.byref(o), C.byref(st)) == A.AFMG_ERR_ARG
     assert "scratch" in A.last_error()
     assert L.afmg_solve_noalloc(None, None, fake, None, fake, C.byref(o), C.byref(st)) == A.AFMG_ERR_ARG
+
+
+@pytest.mark.parametrize("case", ["L", "periodic", "neumann3d"])
+def test_general_domain_topology(case):
+    """afmg_tree_create_domain: the level-1 boxes on their lattice, side
+    neighbours with periodic wrap and holes, refinement boundaries, and one
+    boundary row per physical leaf side, against the geometry computed
+    here."""
+    if case == "L":
+        dim, roots, types = 2, [(1, 1), (2, 1), (1, 2)], ["dirichlet", "neumann", "neumann", "dirichlet"]
+        lev, idx = W.domain_leaves(2, 8, roots, 5, (0.97, 0.97))
+        periodic = (False, False, False)
+    elif case == "periodic":
+        dim, roots, types = 2, [(1, 1), (2, 1)], ["periodic", "periodic", "dirichlet", "neumann"]
+        periodic = (True, False, False)
+        lev, idx = W.domain_leaves(2, 8, roots, 5, (1.98, 0.3), periodic=periodic)
+    else:
+        dim, roots, types = 3, [(1, 1, 1), (2, 1, 1)], ["neumann", "dirichlet", "dirichlet", "dirichlet",
+                                                         "neumann", "neumann"]
+        periodic = (False, False, False)
+        lev, idx = W.domain_leaves(3, 8, roots, 4, (1.0, 0.4, 0.6))
+    t = A.Tree(dim, lev, idx, bc_type=types)
+    assert t.n_roots == len(roots) and t.bc_type == tuple(A.bc_type_codes(types, dim)[: 2 * dim])
+    assert t.n_bfaces == int(W.domain_side_mask(dim, lev, idx, types).sum())
+    rootset = {tuple(r) + ((1,) if dim == 2 else ()) for r in roots}
+    ext = [max(r[d] for r in rootset) for d in range(3)]
+    boxes = [t.box(b) for b in range(t.n_boxes)]
+    key = {(b["level"],) + b["idx"]: i for i, b in enumerate(boxes)}
+    # level-1 boxes first, in lattice order of their Morton keys
+    assert sorted(b["idx"] for b in boxes[: t.n_roots]) == sorted(rootset)
+    for i, b in enumerate(boxes):
+        l = b["level"]
+        for s in range(2 * dim):
+            d, dr = s // 2, (1 if s % 2 else -1)
+            q = list(b["idx"])
+            q[d] += dr
+            n1 = ext[d] * 2 ** (l - 1)
+            if not 1 <= q[d] <= n1:
+                if not periodic[d]:
+                    assert b["nbr"][s] == -1, (i, s)
+                    continue
+                q[d] = (q[d] - 1) % n1 + 1
+            root = tuple((q[e] - 1) // 2 ** (l - 1) + 1 for e in range(3))
+            if root not in rootset:
+                assert b["nbr"][s] == -1, (i, s, "hole")
+                continue
+            k = (l,) + tuple(q)
+            if k in key:
+                assert b["nbr"][s] == key[k], (i, s)
+            else:
+                pk = (l - 1,) + tuple((v + 1) // 2 for v in q)
+                assert b["nbr"][s] == -2 - key[pk], (i, s, "coarser neighbour")
+    # refinement keeps the domain and its side types
+    leaf = [int(b) for b in t.level_list(t.lmax, "leaf")][:1]
+    t2 = t.refine(leaf, balance=1)
+    assert t2.n_roots == t.n_roots and t2.bc_type == t.bc_type and t2.lmax == t.lmax + 1
+
+
+def test_general_domain_validation():
+    level = np.array([1, 1, 1], np.int32)
+    idx = np.array([[1, 1, 1], [2, 1, 1], [1, 2, 1]], np.int32)
+    with pytest.raises(A.AfmgError):
+        A.Tree(2, level, idx, bc_type=["periodic", "dirichlet", "dirichlet", "dirichlet"])  # unpaired
+    with pytest.raises(A.AfmgError):
+        A.Tree(2, level, idx, bc_type=["periodic", "periodic", "dirichlet", "dirichlet"])  # not rectangular
+    t = A.Tree(2, level, idx, bc_type="neumann")
+    assert t.singular and t.n_roots == 3 and t.ext == (2, 2, 1)
+    with pytest.raises(A.AfmgError):
+        A.Batch([t])  # batches take one level-1 box with Dirichlet sides
+    # the plain constructor keeps one level-1 box
+    with pytest.raises(A.AfmgError):
+        A.Tree(2, level, idx)

@@ -2,7 +2,9 @@
 + restriction, FAS right-hand side + copy v', prolongation + correction, the
 coarse-grid V-cycle of levels <= 1) run once through the C-ABI (afmg_step)
 and once by the oracle on the same random state, with refinement boundaries
-at the level under test and non-zero or zero Dirichlet values.
+at the level under test and non-zero or zero boundary values; on the unit
+square / cube with Dirichlet sides and on general domains (coarse grids of
+several level-1 boxes, Neumann and periodic sides, paper §2.2, §3).
 
 The GPU stores no ghost layers: it forms the ghosts from interior values
 (and the ghosts of u - v' from interior differences) where the oracle fills
@@ -24,12 +26,24 @@ REL = 1e-14
 
 
 def grids():
+    """name -> (dim, (level, idx), side types or None)"""
     c = (0.3, 0.62, 0.41)
+    D_, N_, P_ = "dirichlet", "neumann", "periodic"
     return {
-        "a3": (3, W.ball_leaves(3, 8, 5, c, 0.0, 1)),
-        "a2": (2, W.ball_leaves(2, 8, 6, c, 0.0, 1)),
-        "u3": (3, W.uniform_leaves(3, 3)),
+        "a3": (3, W.ball_leaves(3, 8, 5, c, 0.0, 1), None),
+        "a2": (2, W.ball_leaves(2, 8, 6, c, 0.0, 1), None),
+        "u3": (3, W.uniform_leaves(3, 3), None),
+        # L-shaped coarse grid, refinement at the re-entrant corner, mixed sides
+        "L2": (2, W.domain_leaves(2, 8, [(1, 1), (2, 1), (1, 2)], 5, (0.97, 0.97)), [D_, N_, N_, D_]),
+        # 2x1 coarse grid periodic in x, refinement across the periodic side
+        "p3": (3, W.domain_leaves(3, 8, [(1, 1, 1), (2, 1, 1)], 4, (1.98, 0.4, 0.6), periodic=(True, False, False)),
+               [P_, P_, N_, D_, D_, N_]),
+        # one level-1 box, Neumann sides along x and y
+        "n3": (3, W.ball_leaves(3, 8, 4, c, 0.0, 1), [N_, N_, N_, N_, D_, D_]),
     }
+
+
+NAMES = ["a3", "a2", "u3", "L2", "p3", "n3"]
 
 
 class Pair:
@@ -38,10 +52,10 @@ class Pair:
     def __init__(self, name, seed):
         from paper_1701_04329_amd import afmg as A
         self.A = A
-        dim, (lev, idx) = grids()[name]
+        dim, (lev, idx), types = grids()[name]
         self.dim, self.N = dim, 8
-        self.t = A.Tree(dim, lev, idx)
-        self.o = O.Tree(dim, 8, lev, idx)
+        self.t = A.Tree(dim, lev, idx, bc_type=types)
+        self.o = O.Tree(dim, 8, lev, idx, bc_type=types)
         C = 8 ** dim
         key_o = {}
         for b in range(self.o.nbox):
@@ -54,7 +68,7 @@ class Pair:
         self.u = rng.standard_normal((self.t.n_boxes, C))
         self.rho = rng.standard_normal((self.t.n_boxes, C))
         self.uold = rng.standard_normal((self.t.n_boxes, C))
-        phys = W.physical_side_mask(dim, lev, idx)[:, :, None]
+        phys = W.domain_side_mask(dim, lev, idx, types)[:, :, None]
         self.bc_leaf = rng.standard_normal((len(lev), 2 * dim, 8 ** (dim - 1))) * phys
         self.lev, self.idx = lev, idx
 
@@ -112,7 +126,7 @@ def announce(msg):
 
 
 @pytest.mark.parametrize("homog", [False, True])
-@pytest.mark.parametrize("name", ["a3", "a2", "u3"])
+@pytest.mark.parametrize("name", NAMES)
 def test_half_sweep_steps(name, homog):
     P = Pair(name, 1)
     for level in range(1, P.t.lmax + 1):
@@ -128,7 +142,7 @@ def test_half_sweep_steps(name, homog):
 
 
 @pytest.mark.parametrize("homog", [False, True])
-@pytest.mark.parametrize("name", ["a3", "a2", "u3"])
+@pytest.mark.parametrize("name", NAMES)
 def test_resid_restrict_steps(name, homog):
     P = Pair(name, 2)
     for level in range(2, P.t.lmax + 1):
@@ -142,7 +156,7 @@ def test_resid_restrict_steps(name, homog):
 
 
 @pytest.mark.parametrize("homog", [False, True])
-@pytest.mark.parametrize("name", ["a3", "a2", "u3"])
+@pytest.mark.parametrize("name", NAMES)
 def test_coarse_rhs_steps(name, homog):
     P = Pair(name, 3)
     for level in range(2, P.t.lmax):
@@ -159,7 +173,7 @@ def test_coarse_rhs_steps(name, homog):
 
 
 @pytest.mark.parametrize("homog", [False, True])
-@pytest.mark.parametrize("name", ["a3", "a2", "u3"])
+@pytest.mark.parametrize("name", NAMES)
 def test_prolong_steps(name, homog):
     P = Pair(name, 4)
     for level in range(2, P.t.lmax + 1):
@@ -179,7 +193,7 @@ def test_prolong_steps(name, homog):
 
 
 @pytest.mark.parametrize("homog", [False, True])
-@pytest.mark.parametrize("name", ["a3", "a2", "u3"])
+@pytest.mark.parametrize("name", NAMES)
 def test_coarse_grid_step(name, homog):
     P = Pair(name, 5)
     announce(f"coarse grids {name} homog {homog}")
@@ -189,5 +203,5 @@ def test_coarse_grid_step(name, homog):
     P.o.coarse_rhs_level(1, homog=homog)
     P.o.vcycle_from(1, homog=homog)
     root = P.boxes(1)
-    close("root u", u[root], P._get("u")[root])
-    close("root uold", uold[root], P._get("uold")[root])
+    close("level-1 u", u[root], P._get("u")[root])
+    close("level-1 uold", uold[root], P._get("uold")[root])
