@@ -270,8 +270,11 @@ def batch_bench(args, A, torch, dev, stream):
             nb = g["b"].workspace_bytes(A.make_opts(precision=precision))
             g["work"][precision] = torch.empty(nb, dtype=torch.uint8, device=dev)
         _, sts = A.solve_batch(g["b"], g["rho"], None, g["u"], cycle="FMG", tol=1e-10, precision=precision,
-                               workspace=g["work"][precision], stream=st, use_guess=False, graph=True)
+                               workspace=g["work"][precision], stream=st, use_guess=False, graph=True,
+                               check_every=every[0])
         return sts
+
+    every = [args.batch_check_every]
 
     def step(precision, schedule="concurrent", only=None):
         """one step: every tree solved.  sequential: the batches one after the
@@ -307,13 +310,36 @@ def batch_bench(args, A, torch, dev, stream):
     for precision in ("fp64", "mixed"):
         ms, sts = timed(precision)
         cyc = [s["cycles"] for st in sts for s in st]
+        if precision == "fp64":
+            # byte model of the step: every tree's FP64 solve with its own
+            # cycle count (the work the batch has to do), per dimension
+            bm = {}
+            for g, st in zip(groups, sts):
+                bm[g["dim"]] = sum(solve_byte_model(t, s["cycles"], True) for t, s in zip(g["trees"], st))
+            byte_model = {f"{d}d_bytes": b for d, b in bm.items()}
+            byte_model.update({f"{d}d_bytes_per_unknown": b / next(g["b"].n_unknowns for g in groups if g["dim"] == d)
+                               for d, b in bm.items()})
         res[precision] = {"value": n_unk / (ms * 1e-3), "unit": "unknowns/s", "ms_per_step": ms,
                           "cycles_min": int(min(cyc)), "cycles_max": int(max(cyc)),
                           "cycles_median": float(np.median(cyc)),
                           "all_converged": bool(all(s["status"] == 0 for st in sts for s in st)),
                           "sequential_ms_per_step": timed(precision, "sequential")[0]}
         for g in groups:
-            res[precision][f"{g['dim']}d_alone_ms_per_step"] = timed(precision, "sequential", g["dim"])[0]
+            ms_alone = timed(precision, "sequential", g["dim"])[0]
+            res[precision][f"{g['dim']}d_alone_ms_per_step"] = ms_alone
+            res[precision][f"{g['dim']}d_alone_value"] = g["b"].n_unknowns / (ms_alone * 1e-3)
+            if precision == "fp64":
+                b = byte_model[f"{g['dim']}d_bytes"]
+                res[precision][f"{g['dim']}d_alone_byte_model_frac"] = round(
+                    b / (ms_alone * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
+        if precision == "fp64":
+            res[precision]["byte_model"] = byte_model
+        # the same step with a host synchronisation after every cycle (the
+        # stop test runs on the device after every cycle either way)
+        if every[0] != 1:
+            every[0] = 1
+            res[precision]["check_every_1_ms_per_step"] = timed(precision)[0]
+            every[0] = args.batch_check_every
         sols[precision] = [[t.boxes_to_leaf(x).cpu().numpy() for t, x in zip(g["trees"], g["b"].split(g["u"]))]
                            for g in groups]
     pool.shutdown()
@@ -376,9 +402,12 @@ def batch_bench(args, A, torch, dev, stream):
         "oracle_rel_l2_smallest_trees": oracle,
         "roofline": roof,
         "generation_s": round(gen_s, 1),
+        "check_every": args.batch_check_every,
         "note": "one step = every tree solved (FMG, then V(2,2) until its own residual dropped by 1e-10); "
                 "one batch per dimension, each on its own stream driven by its own host thread, cycles "
-                "replayed from recorded HIP graphs; sequential = the two batches one after the other",
+                "replayed from recorded HIP graphs (check_every cycles per replay; every tree's stop test on "
+                "the device after every cycle; launches cover only the boxes of trees still iterating); "
+                "sequential = the two batches one after the other",
     }
 
 
@@ -601,6 +630,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-tree batch workload")
     ap.add_argument("--batch-trees", type=int, default=256)
+    ap.add_argument("--batch-check-every", type=int, default=3,
+                    help="batch workload: cycles between host synchronisations (each tree's stop test runs on "
+                         "the device after every cycle)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--skip-unbatched", action="store_true",
                     help="batch workload: skip the one-tree-at-a-time comparison pass")
@@ -832,6 +864,11 @@ def main():
         out["batch"] = batch_bench(args, A, torch, dev, stream)
     if not args.no_adaptive:
         out["adaptive"] = adaptive_bench(args, A, torch, dev, stream)
+        if "batch" in out:
+            # the 3D batch's rate against the single adaptive tree's (FP64)
+            v3 = out["batch"]["fp64"].get("3d_alone_value")
+            if v3:
+                out["batch"]["fp64"]["3d_alone_vs_c3_single_tree"] = round(v3 / out["adaptive"]["fp64"]["value"], 4)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_bench(args, A, torch, dev, stream)
     if not args.no_paper_ex:

@@ -90,7 +90,12 @@ typedef struct {
                          residual of the FP64 path is then only computed at
                          those cycles; a solve may run up to check_every - 1
                          cycles past convergence; stats history entries of
-                         the unchecked cycles are NaN. */
+                         the unchecked cycles are NaN.  Batches apply every
+                         tree's stop test on the device after every cycle,
+                         so results and histories do not depend on
+                         check_every, which only sets the cycles between
+                         host synchronisations (one recorded graph replay
+                         each with opts.graph). */
     int prof_level;   /* level whose launches opts.profile times (2 .. lmax;
                          0: the finest level, the default) */
 } afmg_opts;
@@ -348,7 +353,10 @@ int afmg_adjoint(afmg_tree *tree, void *stream, const double *u_bar, double *rho
  * it alone (same kernels and arithmetic, its own stop test): trees that have
  * stopped are masked out of later cycles, and an FMG step at level l involves
  * only trees that reach level l.  The solution of each tree is therefore
- * identical to its afmg_solve result.
+ * identical to its afmg_solve result.  Each tree's stop test runs on the
+ * device after every cycle; a tree that stops leaves the per-level lists of
+ * boxes the kernels take their work from, so later launches do no work for
+ * it.
  */
 typedef struct {
     int dim, box_n, n_trees;

@@ -33,6 +33,23 @@ struct LevelArgs {
     int own_zero;       // first half sweep after one with add_to: the old
                         // values of the updated colour are taken as zero
     T h;                // cell size of the level (Neumann ghosts u1 + h q)
+    // forests: the level's compacted list of boxes of trees still iterating
+    // (box ids, *nact of them); the forest variants of the level kernels
+    // take their boxes from it
+    const int32_t *act;
+    const int *nact;
+};
+
+// Per-tree stop rule of a forest, kept on the device (paper: no error
+// control is built into the method, §3.2; the stop rule is the library's)
+struct TreeStop {
+    int cycles;   // V-cycles (or refinement steps) run
+    int status;   // afmg_status of the tree
+    int grow;     // consecutive cycles whose max-norm grew
+    int conv;     // 1 once max |r| <= tol max |r0|
+    double prev;  // max |r| of the previous cycle
+    double r0;    // max |r| of the initial guess
+    double rmax, rl2;  // norms after the last cycle
 };
 
 enum class Op { GSRB, RESID_RESTRICT, COARSE_RHS, PROLONG, RESTRICT_RHO };
@@ -97,6 +114,16 @@ void launch_reduce_trees(const double *partial, const int64_t *ptr, const int32_
                          double *out, int n_trees, hipStream_t st);
 // out[t] = base[t] (1 if base is null) and tree_lmax[t] >= l
 void launch_level_mask(const int *base, const int32_t *tree_lmax, int l, int *out, int n_trees, hipStream_t st);
+// forests: per level l = 1 .. lmax, the boxes of the trees whose mask entry
+// is set, into act[lvl_off[l] ..] (count nact[l]); ltoff [(lmax+2)][n+1]: first
+// box of tree t on level l
+void launch_compact(const int *mask, const int64_t *ltoff, const int64_t *lvl_off, int n_trees, int lmax,
+                    int32_t *act, int *nact, hipStream_t st);
+// forests: the stop rule after one cycle for every tree whose mask entry is
+// set (norm: (max, L2) per tree; hist [n][2][AFMG_HIST]); a tree that stops
+// leaves the mask
+void launch_tree_stop(const double *norm, int *mask, TreeStop *state, double *hist, int n_trees, double tol,
+                      int fixed, int nmax, hipStream_t st);
 template <int D, int N, typename T>
 void launch_coarse(const CoarseArgs<T> &a, int n_trees, hipStream_t st);
 template <int D, int N, typename T>

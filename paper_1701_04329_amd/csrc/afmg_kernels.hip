@@ -147,18 +147,32 @@ __device__ __forceinline__ Slot<D, N> slot_of(int64_t b0, int nb, bool remap = t
     return r;
 }
 
-// Slot of a level kernel.
-template <int D, int N, int W, typename T>
-__device__ __forceinline__ Slot<D, N> slot_of(const LevelArgs<T> &a) {
-    return slot_of<D, N, W>(a.b0, a.nb, a.no_remap == 0);
-}
-// Level kernels come in two variants: F = false for one tree (a.active is
-// null), whose loads start without waiting for anything but the arguments,
-// and F = true for forests, where the boxes of trees whose mask entry is 0
-// are neither read nor written (the mask test needs the box record first).
-template <bool F, typename T>
-__device__ __forceinline__ bool tree_active(const LevelArgs<T> &a, const BoxInfo &bi) {
-    return !F || a.active[bi.tree] != 0;
+// Slot of a level kernel.  Level kernels come in two variants: F = false for
+// one tree, whose loads start without waiting for anything but the
+// arguments, and F = true for forests, which take their boxes from the
+// level's compacted list of boxes of trees still iterating (a.act[0 ..
+// *a.nact)): the first ceil(n / boxes per workgroup) workgroups take them, in
+// contiguous runs per XCD over that count, and the other workgroups of the
+// grid (sized for the whole level) find no box and exit, so that stopped
+// trees cost neither memory traffic nor more than an empty workgroup.
+template <int D, int N, int W, bool F, typename T>
+__device__ __forceinline__ Slot<D, N> slot_lvl(const LevelArgs<T> &a) {
+    if (!F) return slot_of<D, N, W>(a.b0, a.nb, a.no_remap == 0);
+    using G = Geo<D, N>;
+    constexpr int BPW = W / G::TPB;
+    Slot<D, N> r;
+    const int n = *a.nact;
+    const int g = (n + BPW - 1) / BPW;
+    const int wb = (int)blockIdx.x;
+    const int w = a.no_remap ? wb : xcd_remap(wb, g);
+    r.slot = (int)threadIdx.x / G::TPB;
+    r.t = (int)threadIdx.x % G::TPB;
+    int bl = w * BPW + r.slot;
+    if (G::TPB == 64) bl = __builtin_amdgcn_readfirstlane(bl);  // one box per wave
+    r.valid = wb < g && bl < n;
+    const int q = r.valid ? bl : 0;
+    r.b = r.valid ? (int64_t)a.act[q] : a.b0;
+    return r;
 }
 
 // ---------------------------------------------------------------------------
@@ -391,7 +405,7 @@ __global__ __launch_bounds__(W) void k_gsrb(LevelArgs<T> a, int colour) {
     using G = Geo<D, N>;
     constexpr int HN = G::HN;
     __shared__ T so[(W / G::TPB) * oblock<D, N>()];
-    const Slot<D, N> sl = slot_of<D, N, W>(a);
+    const Slot<D, N> sl = slot_lvl<D, N, W, F>(a);
     T *s = so + sl.slot * oblock<D, N>();
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     T *ub = a.u + (size_t)sl.b * G::C;
@@ -412,7 +426,7 @@ __global__ __launch_bounds__(W) void k_gsrb(LevelArgs<T> a, int colour) {
     // one tree: the padding slots of the last workgroup load a valid box too
     // (sl.b is clamped), so that no branch separates the loads from the
     // kernel start
-    const bool act = sl.valid && tree_active<F>(a, bi);
+    const bool act = sl.valid;
     if (!F || act) {
         T ot[HN];
         const int oth0 = (1 - colour) * G::HALF + r * HN;
@@ -531,7 +545,7 @@ __global__ __launch_bounds__(W) void k_gsrb_cube(LevelArgs<T> a, int colour) {
     __asm__ volatile("" ::"s"(a.u), "s"(a.rho), "s"(a.b0), "s"(a.nb), "s"(a.no_remap), "s"(a.xmask),
                      "s"(colour));
     if (ADD) __asm__ volatile("" ::"s"(a.add_to));
-    const Slot<D, N> sl = slot_of<D, N, W>(a);
+    const Slot<D, N> sl = slot_lvl<D, N, W, false>(a);
     T *s = so + sl.slot * oblock<D, N>();
     T *ub = a.u + (size_t)sl.b * G::C;
     const int r = sl.t;
@@ -686,7 +700,7 @@ template <int D, int N, typename T, int W, bool F>
 __global__ __launch_bounds__(W) void k_resid_restrict(LevelArgs<T> a) {
     using G = Geo<D, N>;
     __shared__ T sm[(W / G::TPB) * G::PC];
-    const Slot<D, N> sl = slot_of<D, N, W>(a);
+    const Slot<D, N> sl = slot_lvl<D, N, W, F>(a);
     T *s = sm + sl.slot * G::PC;
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
@@ -697,7 +711,7 @@ __global__ __launch_bounds__(W) void k_resid_restrict(LevelArgs<T> a) {
     Stager<D, N, T> st;
     // one tree: padding slots (sl.b clamped to a valid box) load too, no
     // branch before the loads
-    const bool act = sl.valid && tree_active<F>(a, bi);
+    const bool act = sl.valid;
     if (!F || act) {
 #pragma unroll
         for (int it = 0; it < NPC; it++)
@@ -746,7 +760,7 @@ template <int D, int N, typename T, int W, bool F>
 __global__ __launch_bounds__(W) void k_coarse_rhs(LevelArgs<T> a) {
     using G = Geo<D, N>;
     __shared__ T sm[(W / G::TPB) * G::PC];
-    const Slot<D, N> sl = slot_of<D, N, W>(a);
+    const Slot<D, N> sl = slot_lvl<D, N, W, F>(a);
     T *s = sm + sl.slot * G::PC;
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
@@ -756,7 +770,7 @@ __global__ __launch_bounds__(W) void k_coarse_rhs(LevelArgs<T> a) {
     Stager<D, N, T> st;
     // rows first (one tree: padding slots load a valid box too), then what
     // depends on the box record: ghosts and rbar of parents
-    const bool act = sl.valid && tree_active<F>(a, bi);
+    const bool act = sl.valid;
     if (!F || act) {
         st.load(bi, a.u + bo, a.u, a.bc, a.homog, sl.t, parent, a.h);
         if (parent) {
@@ -884,7 +898,7 @@ __global__ __launch_bounds__(W) void k_prolong(LevelArgs<T> a) {
     constexpr int NO = G::HC / G::TPB;                           // octant cells per thread
     constexpr int NE = G::C / G::TPB;                            // fine cells per thread
     __shared__ T qs[(W / G::TPB) * G::QC];
-    const Slot<D, N> sl = slot_of<D, N, W>(a);
+    const Slot<D, N> sl = slot_lvl<D, N, W, F>(a);
     T *q = qs + sl.slot * G::QC;
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
@@ -894,7 +908,7 @@ __global__ __launch_bounds__(W) void k_prolong(LevelArgs<T> a) {
     // the fine values (needed only after the barriers) first: they need no
     // box record; one tree: padding slots (sl.b clamped to a valid box) load
     // too
-    const bool act = sl.valid && tree_active<F>(a, bi);
+    const bool act = sl.valid;
     if (!F || act) {
 #pragma unroll
         for (int it = 0; it < NE; it++) uf[it] = a.u[bo + sl.t + it * G::TPB];
@@ -989,7 +1003,7 @@ __global__ __launch_bounds__(W) void k_final(LevelArgs<T> a, double *partial, in
     constexpr int NW = W / 64;  // waves per workgroup
     __shared__ T sm[(W / G::TPB) * G::PC];
     __shared__ double red_m[NW], red_s[NW];
-    const Slot<D, N> sl = slot_of<D, N, W>(a);
+    const Slot<D, N> sl = slot_lvl<D, N, W, F>(a);
     T *s = sm + sl.slot * G::PC;
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
@@ -999,7 +1013,7 @@ __global__ __launch_bounds__(W) void k_final(LevelArgs<T> a, double *partial, in
     Stager<D, N, T> st;
     // rows first (one tree: padding slots load a valid box too), then what
     // depends on the box record: ghosts and rho of leaves
-    const bool act = sl.valid && tree_active<F>(a, bi);
+    const bool act = sl.valid;
     if (!F || act) {
         st.load(bi, a.u + bo, a.u, a.bc, a.homog, sl.t, leaf, a.h);
         if (leaf) {
@@ -1177,15 +1191,75 @@ __global__ __launch_bounds__(256) void k_level_mask(const int *__restrict__ base
     if (t < n) out[t] = ((base ? base[t] : 1) != 0 && tree_lmax[t] >= l) ? 1 : 0;
 }
 
+// Compacted box lists of a forest: workgroup l-1 lists, for level l, the
+// boxes of the trees whose mask entry is set, in box order, at act[lvl_off[l]
+// ..] and their count at nact[l].  The boxes of one tree on one level are
+// contiguous (box order: level, tree, Morton), ltoff[l][t] .. ltoff[l][t+1].
+__global__ __launch_bounds__(256) void k_compact(const int *__restrict__ mask, const int64_t *__restrict__ ltoff,
+                                                 const int64_t *__restrict__ lvl_off, int n_trees,
+                                                 int32_t *__restrict__ act, int *__restrict__ nact) {
+    const int l = (int)blockIdx.x + 1;
+    const int64_t *to = ltoff + (size_t)l * (n_trees + 1);
+    const int64_t base = lvl_off[l];
+    int64_t pos = 0;  // every thread walks the trees in the same order
+    for (int t = 0; t < n_trees; t++) {
+        if (!mask[t]) continue;
+        const int64_t b0 = to[t], cnt = to[t + 1] - b0;
+        for (int64_t k = threadIdx.x; k < cnt; k += 256) act[base + pos + k] = (int32_t)(b0 + k);
+        pos += cnt;
+    }
+    if (threadIdx.x == 0) nact[l] = (int)pos;
+}
+
+// The stop rule of every tree of a forest whose mask entry is set, after one
+// cycle: the history entry, the cycle count, a non-finite norm, three
+// growths in a row, convergence (max |r| <= tol max |r0|) or the last allowed
+// cycle; a tree that stops leaves the mask, so later cycles skip it.
+__global__ __launch_bounds__(256) void k_tree_stop(const double *__restrict__ norm, int *__restrict__ mask,
+                                                   TreeStop *__restrict__ state, double *__restrict__ hist,
+                                                   int n, double tol, int fixed, int nmax) {
+    const int t = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (t >= n || !mask[t]) return;
+    TreeStop s = state[t];
+    const double rmax = norm[2 * t], rl2 = norm[2 * t + 1];
+    s.rmax = rmax;
+    s.rl2 = rl2;
+    if (s.cycles < AFMG_HIST) {
+        hist[((size_t)t * 2 + 0) * AFMG_HIST + s.cycles] = rmax;
+        hist[((size_t)t * 2 + 1) * AFMG_HIST + s.cycles] = rl2;
+    }
+    s.cycles++;
+    bool done = false;
+    if (!isfinite(rmax)) {
+        s.status = AFMG_ERR_NONFINITE;
+        done = true;
+    } else if (!fixed) {
+        s.grow = rmax > s.prev ? s.grow + 1 : 0;
+        if (s.grow >= 3) {
+            s.status = AFMG_ERR_DIVERGED;
+            done = true;
+        } else if (rmax <= tol * s.r0) {
+            s.conv = 1;
+            done = true;
+        }
+    }
+    if (!done) {
+        s.prev = rmax;
+        if (s.cycles >= nmax) done = true;
+    }
+    state[t] = s;
+    if (done) mask[t] = 0;
+}
+
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
 // FMG: the parent's octant of rho receives the mean of the box's rho.
-template <int D, int N, typename T>
+template <int D, int N, typename T, bool F>
 __global__ __launch_bounds__(256) void k_restrict_rho(LevelArgs<T> a) {
     using G = Geo<D, N>;
     __shared__ T sm[G::BPW * G::C];
-    const Slot<D, N> sl = slot_of<D, N, 256>(a);
+    const Slot<D, N> sl = slot_lvl<D, N, 256, F>(a);
     T *s = sm + sl.slot * G::C;
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
@@ -1197,7 +1271,7 @@ __global__ __launch_bounds__(256) void k_restrict_rho(LevelArgs<T> a) {
         }
     }
     __syncthreads();
-    if (sl.valid && (!a.active || a.active[bi.tree] != 0)) restrict_octant<D, N, T, false>(s, a.rho, bi, sl.t);
+    if (sl.valid) restrict_octant<D, N, T, false>(s, a.rho, bi, sl.t);
 }
 
 // In-place conversion of whole boxes between the caller's order (x fastest)
@@ -2637,7 +2711,7 @@ static void launch_level_wf(Op op, const LevelArgs<T> &a, int colour, hipStream_
     case Op::RESID_RESTRICT: AFMG_LAUNCH_W((k_resid_restrict<D, N, T, W, F>), g, W, st, a); break;
     case Op::COARSE_RHS: AFMG_LAUNCH_W((k_coarse_rhs<D, N, T, W, F>), g, W, st, a); break;
     case Op::PROLONG: AFMG_LAUNCH_W((k_prolong<D, N, T, W, F>), g, W, st, a); break;
-    case Op::RESTRICT_RHO: AFMG_LAUNCH((k_restrict_rho<D, N, T>), (wg_count<D, N, 256>(a.nb)), st, a); break;
+    case Op::RESTRICT_RHO: AFMG_LAUNCH((k_restrict_rho<D, N, T, F>), (wg_count<D, N, 256>(a.nb)), st, a); break;
     }
 }
 template <int D, int N, typename T, int W>
@@ -2688,6 +2762,17 @@ void launch_reduce(const double *partial, int64_t n, double *out, hipStream_t st
 void launch_reduce_trees(const double *partial, const int64_t *ptr, const int32_t *boxes, const int *active,
                          double *out, int n_trees, hipStream_t st) {
     AFMG_LAUNCH(k_reduce_trees, n_trees, st, partial, ptr, boxes, active, out);
+}
+
+void launch_compact(const int *mask, const int64_t *ltoff, const int64_t *lvl_off, int n_trees, int lmax,
+                    int32_t *act, int *nact, hipStream_t st) {
+    AFMG_LAUNCH(k_compact, lmax, st, mask, ltoff, lvl_off, n_trees, act, nact);
+}
+
+void launch_tree_stop(const double *norm, int *mask, TreeStop *state, double *hist, int n_trees, double tol,
+                      int fixed, int nmax, hipStream_t st) {
+    const int g = (n_trees + 255) / 256;
+    AFMG_LAUNCH(k_tree_stop, g, st, norm, mask, state, hist, n_trees, tol, fixed, nmax);
 }
 
 void launch_level_mask(const int *base, const int32_t *tree_lmax, int l, int *out, int n_trees, hipStream_t st) {

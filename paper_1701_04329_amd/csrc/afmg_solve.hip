@@ -99,6 +99,14 @@ struct afmg_tree {
     std::vector<int32_t> box_map;         // caller's box of each working box
     std::vector<int32_t> row_map;         // caller's Dirichlet row of each leaf row
     int32_t *d_box_map = nullptr, *d_row_map = nullptr;
+    // forests: the stop rule on the device and the compacted box lists
+    double *d_tnorm = nullptr;            // (max, L2) per tree after a cycle
+    TreeStop *d_tstop = nullptr, *h_tstop = nullptr;  // per-tree state (h_: pinned)
+    double *d_thist = nullptr, *h_thist = nullptr;    // [n][2][AFMG_HIST] history
+    int64_t *d_ltoff = nullptr;           // [(lmax+2)][n+1] first box of tree t on level l
+    int64_t *d_lvloff = nullptr;          // first box of each level
+    int32_t *d_act = nullptr;             // per level: boxes of the trees still iterating
+    int *d_nact = nullptr;                // their count per level
     int64_t user_boxes = 0, user_rows = 0, user_unknowns = 0;
 };
 
@@ -261,6 +269,32 @@ int bind_device(afmg_tree *t) {
         if ((rc = upload(t->d_tree_leaf_box, h.tree_leaf_box, "the tree leaf lists")) != AFMG_OK) return rc;
         if ((rc = upload(t->d_box_map, t->box_map, "the box map")) != AFMG_OK) return rc;
         if ((rc = upload(t->d_row_map, t->row_map, "the row map")) != AFMG_OK) return rc;
+        const size_t n = (size_t)h.n_trees, L = (size_t)h.lmax + 2;
+        if ((rc = upload(t->d_tnorm, std::vector<double>(2 * n, 0.0), "the tree norms")) != AFMG_OK) return rc;
+        if ((rc = upload(t->d_tstop, std::vector<TreeStop>(n, TreeStop{}), "the tree states")) != AFMG_OK) return rc;
+        if ((rc = upload(t->d_thist, std::vector<double>(2 * n * AFMG_HIST, 0.0), "the tree histories")) != AFMG_OK)
+            return rc;
+        e = hipHostMalloc(&t->h_tstop, sizeof(TreeStop) * n, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc(&t->h_thist, sizeof(double) * 2 * n * AFMG_HIST, hipHostMallocDefault);
+        if (e != hipSuccess) return fail(AFMG_ERR_OOM, "hipHostMalloc failed");
+        // boxes of one tree on one level are contiguous (level, tree, Morton)
+        std::vector<int64_t> ltoff(L * (n + 1), 0);
+        for (int l = 1; l <= h.lmax; l++) {
+            int64_t *to = ltoff.data() + (size_t)l * (n + 1);
+            int64_t b = h.lvl_off[(size_t)l];
+            for (size_t tr = 0; tr <= n; tr++) {
+                while (b < h.lvl_off[(size_t)l + 1] && (size_t)h.info[(size_t)b].tree < tr) b++;
+                to[tr] = b;
+            }
+        }
+        if ((rc = upload(t->d_ltoff, ltoff, "the tree offsets")) != AFMG_OK) return rc;
+        if ((rc = upload(t->d_lvloff, h.lvl_off, "the level offsets")) != AFMG_OK) return rc;
+        if ((rc = upload(t->d_act, std::vector<int32_t>((size_t)h.n_boxes, 0), "the box lists")) != AFMG_OK) return rc;
+        if ((rc = upload(t->d_nact, std::vector<int>(L, 0), "the box counts")) != AFMG_OK) return rc;
+        // every tree listed until a solve sets the mask
+        launch_compact(t->d_active, t->d_ltoff, t->d_lvloff, h.n_trees, h.lmax, t->d_act, t->d_nact, nullptr);
+        e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "box lists");
     }
     t->device = dev;
     return AFMG_OK;
@@ -271,10 +305,14 @@ void release(afmg_tree *t) {
     if (t->rec.cap) (void)hipStreamDestroy(t->rec.cap);
     for (void *p : {(void *)t->d_info, (void *)t->d_child, (void *)t->d_active, (void *)t->d_mask,
                     (void *)t->d_tree_lmax, (void *)t->d_tree_leaf_ptr, (void *)t->d_tree_leaf_box,
-                    (void *)t->d_box_map, (void *)t->d_row_map})
+                    (void *)t->d_box_map, (void *)t->d_row_map, (void *)t->d_tnorm, (void *)t->d_tstop,
+                    (void *)t->d_thist, (void *)t->d_ltoff, (void *)t->d_lvloff, (void *)t->d_act,
+                    (void *)t->d_nact})
         if (p) (void)hipFree(p);
     if (t->h_norm) (void)hipHostFree(t->h_norm);
     if (t->h_active) (void)hipHostFree(t->h_active);
+    if (t->h_tstop) (void)hipHostFree(t->h_tstop);
+    if (t->h_thist) (void)hipHostFree(t->h_thist);
     for (auto ev : t->events) (void)hipEventDestroy(ev);
     for (auto ev : t->span)
         if (ev) (void)hipEventDestroy(ev);
@@ -374,6 +412,10 @@ struct Cycler {
         a.h2 = (T)(hh * hh);
         a.ih2 = (T)(1.0 / (hh * hh));
         a.h = (T)hh;
+        if (t->forest) {
+            a.act = t->d_act + h.lvl_off[(size_t)l];
+            a.nact = t->d_nact + l;
+        }
         return a;
     }
     void level(Op op, int l, int colour = 0, bool time = true, double *add = nullptr, bool own_zero = false) {
@@ -468,6 +510,7 @@ struct Cycler {
             if (saved.active) {
                 launch_level_mask(saved.active, t->d_tree_lmax, l, t->d_mask, h.n_trees, st);
                 base.active = t->d_mask;
+                compact(t->d_mask);
             }
             if (l < h.lmax)
                 launch_copy<T>(base.u + h.lvl_off[(size_t)l] * C, base.uold + h.lvl_off[(size_t)l] * C,
@@ -476,6 +519,11 @@ struct Cycler {
             vcycle(l);
         }
         base = saved;
+        if (saved.active) compact(saved.active);
+    }
+    // forests: the compacted box lists of the trees set in `mask`
+    void compact(const int *mask) {
+        launch_compact(mask, t->d_ltoff, t->d_lvloff, h.n_trees, h.lmax, t->d_act, t->d_nact, st);
     }
 };
 
@@ -503,7 +551,7 @@ struct Solver {
     // restriction into the parents feeds no residual, and the next V-cycle
     // restricts into those parents again before it reads them
     // (restrict_parents() fills them at the end of a solve).
-    void finalize_launch(float *rout, hipStream_t s, int lfirst = 1) {
+    void finalize_launch(float *rout, hipStream_t s, int lfirst = 1, double *norm_out = nullptr) {
         for (int l = h.lmax; l >= std::max(1, lfirst); l--) {
             if (l == 1 && !t->forest && !h.level1_leaf) continue;
             const double hh = level_h(l);
@@ -514,6 +562,10 @@ struct Solver {
             a.h2 = hh * hh;
             a.ih2 = 1.0 / (hh * hh);
             a.h = hh;
+            if (t->forest) {
+                a.act = t->d_act + h.lvl_off[(size_t)l];
+                a.nact = t->d_nact + l;
+            }
             const Shape sh = t->shapes[0][SK_FINAL][(size_t)l];
             a.no_remap = sh.no_remap;
             prof.timed(
@@ -524,11 +576,11 @@ struct Solver {
                 },
                 s);
         }
+        double *out = norm_out ? norm_out : t->d_norm_host;
         if (t->forest)
-            launch_reduce_trees(partial, t->d_tree_leaf_ptr, t->d_tree_leaf_box, base.active, t->d_norm_host,
-                                h.n_trees, s);
+            launch_reduce_trees(partial, t->d_tree_leaf_ptr, t->d_tree_leaf_box, base.active, out, h.n_trees, s);
         else
-            launch_reduce(partial, t->n_parts, t->d_norm_host, s);
+            launch_reduce(partial, t->n_parts, out, s);
     }
     // parents of the levels that the per-cycle finalize skips receive the
     // restriction of the solution (k_final's arithmetic and order)
@@ -708,6 +760,102 @@ int iterate_trees(Solver<D> &s, afmg_stats *S, std::vector<Track> &tr, Step step
     return AFMG_OK;
 }
 
+// Outer loop of a forest (batch).  Each tree's stop rule runs on the device
+// after every cycle (k_tree_stop): a tree that stops leaves the mask and the
+// compacted box lists, so it runs exactly the cycles of its own solve.  The
+// host waits for the device only every check_every cycles (the cycles in
+// between replay one recorded graph) and then reads the trees' states back:
+// no per-cycle synchronisation or mask upload.  cycle(stream, first)
+// enqueues one cycle, with the trees' norms into t->d_tnorm; first: the
+// mixed path's FMG step, run eagerly as the first cycle.
+template <int D, class Cycle>
+int iterate_forest(Solver<D> &s, afmg_stats *S, const std::vector<uintptr_t> &key, bool first_fmg, Cycle cycle) {
+    afmg_tree *t = s.t;
+    const afmg_opts &o = s.o;
+    const HostTree &h = t->h;
+    const int n = h.n_trees;
+    const bool fixed = o.fixed_cycles > 0;
+    const int nmax = fixed ? o.fixed_cycles : o.max_cycles;
+    const int every = std::max(1, o.check_every);
+    hipStream_t st = s.st;
+    bool any = false;
+    for (int i = 0; i < n; i++) {
+        TreeStop &q = t->h_tstop[i];
+        q = TreeStop{};
+        q.status = S[i].status;
+        q.prev = S[i].r_max;
+        q.r0 = S[i].r0_max;
+        q.rmax = S[i].r_max;
+        q.rl2 = S[i].r_l2;
+        q.conv = (!fixed && S[i].r_max <= o.tol * S[i].r0_max) ? 1 : 0;
+        const bool go = q.status == AFMG_OK && !q.conv && nmax > 0;
+        t->h_active[i] = go ? 1 : 0;
+        any |= go;
+    }
+    hipError_t e = hipMemcpyAsync(t->d_tstop, t->h_tstop, sizeof(TreeStop) * (size_t)n, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "tree state upload");
+    if (s.upload_mask() != AFMG_OK) return AFMG_ERR_HIP;
+    auto stop_and_compact = [&](hipStream_t cs) {
+        launch_tree_stop(t->d_tnorm, t->d_active, t->d_tstop, t->d_thist, n, o.tol, fixed ? 1 : 0, nmax, cs);
+        launch_compact(t->d_active, t->d_ltoff, t->d_lvloff, n, h.lmax, t->d_act, t->d_nact, cs);
+    };
+    launch_compact(t->d_active, t->d_ltoff, t->d_lvloff, n, h.lmax, t->d_act, t->d_nact, st);
+    auto read = [&]() -> int {
+        hipError_t err = hipMemcpyAsync(t->h_tstop, t->d_tstop, sizeof(TreeStop) * (size_t)n,
+                                        hipMemcpyDeviceToHost, st);
+        if (err == hipSuccess)
+            err = hipMemcpyAsync(t->h_active, t->d_active, sizeof(int) * (size_t)n, hipMemcpyDeviceToHost, st);
+        if (err != hipSuccess) return hip_fail(err, "tree state readback");
+        const int rc = s.read_norms();
+        if (rc != AFMG_OK) return rc;
+        any = false;
+        for (int i = 0; i < n; i++) any |= t->h_active[i] != 0;
+        return AFMG_OK;
+    };
+    int done = 0;  // cycles run by every tree still iterating
+    if (any && first_fmg) {
+        cycle(st, true);
+        stop_and_compact(st);
+        const int rc = read();
+        if (rc != AFMG_OK) return rc;
+        done = 1;
+    }
+    while (any) {
+        const int m = std::max(1, std::min(every, nmax - done));
+        std::vector<uintptr_t> km = key;
+        km.push_back((uintptr_t)m);
+        int rc = s.run(km, [&](hipStream_t cs) {
+            for (int c = 0; c < m; c++) {
+                cycle(cs, false);
+                stop_and_compact(cs);
+            }
+        });
+        if (rc == AFMG_OK) rc = read();
+        if (rc != AFMG_OK) return rc;
+        done += m;
+    }
+    e = hipMemcpyAsync(t->h_thist, t->d_thist, sizeof(double) * 2 * (size_t)n * AFMG_HIST, hipMemcpyDeviceToHost,
+                       st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "tree history readback");
+    for (int i = 0; i < n; i++) {
+        const TreeStop &q = t->h_tstop[i];
+        afmg_stats &x = S[i];
+        x.cycles = q.cycles;
+        x.status = q.status;
+        if (q.cycles > 0) {
+            x.r_max = q.rmax;
+            x.r_l2 = q.rl2;
+        }
+        for (int c = 0; c < std::min(q.cycles, AFMG_HIST); c++) {
+            x.hist_max[c] = t->h_thist[((size_t)i * 2 + 0) * AFMG_HIST + c];
+            x.hist_l2[c] = t->h_thist[((size_t)i * 2 + 1) * AFMG_HIST + c];
+        }
+        if (x.status == AFMG_OK && !fixed && !q.conv) x.status = AFMG_NOT_CONVERGED;
+    }
+    return AFMG_OK;
+}
+
 // norms of the trees marked in t->h_active (all trees for one tree) from
 // t->h_norm into the stats
 void take_norms(const afmg_tree *t, afmg_stats *S, bool initial) {
@@ -774,6 +922,7 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
     if (t->forest)
         for (int i = 0; i < n; i++) t->h_active[i] = 1;
     int rc = s.upload_mask();
+    if (t->forest) launch_compact(t->d_active, t->d_ltoff, t->d_lvloff, n, h.lmax, t->d_act, t->d_nact, st);
     if (rc == AFMG_OK) rc = s.finalize(rho32);
     if (rc != AFMG_OK) return rc;
     take_norms(t, S, true);
@@ -795,22 +944,32 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
         if (o.cycle == AFMG_CYCLE_FMG_V) {
             rc = s.upload_mask();
             if (rc != AFMG_OK) return rc;
+            if (t->forest) cy.compact(t->d_active);
             cy.fmg(guess);  // without a guess u was zeroed above and is still zero
             s.finalize_launch(nullptr, st, h.lmin_leaf);
             if ((rc = s.read_norms()) != AFMG_OK) return rc;
             take_norms(t, S, false);
         }
-        rc = iterate_trees(s, S, tr, [&](int, int m) {
-            std::vector<uintptr_t> km = key;
-            km.push_back((uintptr_t)m);
-            const int q = s.run(km, [&](hipStream_t cs) {
+        if (t->forest) {
+            rc = iterate_forest(s, S, key, false, [&](hipStream_t cs, bool) {
                 Cycler<D, double> c2 = cy;
                 c2.st = cs;
-                for (int c = 0; c < m; c++) c2.vcycle(h.lmax);
-                s.finalize_launch(nullptr, cs, h.lmin_leaf);
+                c2.vcycle(h.lmax);
+                s.finalize_launch(nullptr, cs, h.lmin_leaf, t->d_tnorm);
             });
-            return q != AFMG_OK ? q : s.read_norms();
-        });
+        } else {
+            rc = iterate_trees(s, S, tr, [&](int, int m) {
+                std::vector<uintptr_t> km = key;
+                km.push_back((uintptr_t)m);
+                const int q = s.run(km, [&](hipStream_t cs) {
+                    Cycler<D, double> c2 = cy;
+                    c2.st = cs;
+                    for (int c = 0; c < m; c++) c2.vcycle(h.lmax);
+                    s.finalize_launch(nullptr, cs, h.lmin_leaf);
+                });
+                return q != AFMG_OK ? q : s.read_norms();
+            });
+        }
     } else {
         // FP32 V-cycles inside FP64 iterative refinement: solve L e = r with
         // homogeneous Dirichlet values in FP32 (coarsest grids in FP64),
@@ -838,21 +997,26 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
             }
             if (!c2.fuses_update(h.lmax))
                 launch_ir_update<D, BOX_N>(t->d_info, uw, e32, h.n_boxes, t->d_active, cs);
-            s.finalize_launch(rho32, cs, h.lmin_leaf);
+            s.finalize_launch(rho32, cs, h.lmin_leaf, t->forest ? t->d_tnorm : nullptr);
         };
-        rc = iterate_trees(s, S, tr, [&](int k, int m) {
-            int q = AFMG_OK;
-            if (k == 0 && o.cycle == AFMG_CYCLE_FMG_V) {
-                for (int c = 0; c < m; c++) refine(st, c == 0);
-            } else {
-                std::vector<uintptr_t> km = key;
-                km.push_back((uintptr_t)m);
-                q = s.run(km, [&](hipStream_t cs) {
-                    for (int c = 0; c < m; c++) refine(cs, false);
-                });
-            }
-            return q != AFMG_OK ? q : s.read_norms();
-        });
+        if (t->forest) {
+            rc = iterate_forest(s, S, key, o.cycle == AFMG_CYCLE_FMG_V,
+                                [&](hipStream_t cs, bool first) { refine(cs, first); });
+        } else {
+            rc = iterate_trees(s, S, tr, [&](int k, int m) {
+                int q = AFMG_OK;
+                if (k == 0 && o.cycle == AFMG_CYCLE_FMG_V) {
+                    for (int c = 0; c < m; c++) refine(st, c == 0);
+                } else {
+                    std::vector<uintptr_t> km = key;
+                    km.push_back((uintptr_t)m);
+                    q = s.run(km, [&](hipStream_t cs) {
+                        for (int c = 0; c < m; c++) refine(cs, false);
+                    });
+                }
+                return q != AFMG_OK ? q : s.read_norms();
+            });
+        }
     }
     if (rc != AFMG_OK) return rc;
     if (any) s.restrict_parents();
@@ -1187,6 +1351,10 @@ void tune_precision(afmg_tree *t, hipStream_t st, LevelArgs<T> base, double *par
             a.h2 = (T)(hh * hh);
             a.ih2 = (T)(1.0 / (hh * hh));
             a.h = (T)hh;
+            if (t->forest) {
+                a.act = t->d_act + h.lvl_off[(size_t)l];
+                a.nact = t->d_nact + l;
+            }
             const Op op = kind == SK_GSRB ? Op::GSRB
                           : kind == SK_RESID ? Op::RESID_RESTRICT
                           : kind == SK_CRHS ? Op::COARSE_RHS : Op::PROLONG;
@@ -1249,6 +1417,13 @@ int autotune(afmg_tree *t, hipStream_t st, char *ws) {
         return fail(AFMG_ERR_HIP, "hipEventCreate failed");
     LevelArgs<double> b64{t->d_info, u, rho, uold, bc, 0, 0, 0, 0.0, 0.0, nullptr, 0};
     LevelArgs<float> b32{t->d_info, e, re, uo, nullptr, 0, 0, 1, 0.f, 0.f, nullptr, 0};
+    if (t->forest) {
+        // the trials run every tree: lists of all boxes
+        launch_level_mask(nullptr, t->d_tree_lmax, 1, t->d_mask, h.n_trees, st);
+        launch_compact(t->d_mask, t->d_ltoff, t->d_lvloff, h.n_trees, h.lmax, t->d_act, t->d_nact, st);
+        b64.active = t->d_mask;
+        b32.active = t->d_mask;
+    }
     tune_precision<D, double>(t, st, b64, partial, e0, e1);
     tune_precision<D, float>(t, st, b32, partial, e0, e1);
     (void)hipEventDestroy(e0);

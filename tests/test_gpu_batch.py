@@ -221,7 +221,7 @@ def test_check_every(precision):
     counts the solution is bitwise that of checking every cycle, the checked
     history entries are equal and the others NaN, and a tolerance stop lands
     on the first check at or after the cycle where every-cycle checking
-    stops.  Batches follow the same rule per tree."""
+    stops.  Batches check every tree on the device after every cycle."""
     w = W.adaptive_small(3, 8, 5, 1e-3, 6, n_src=2, sigma_range=(0.04, 0.08))
     announce(f"check_every {precision}")
     u1, s1 = single(w, cycle="FMG", precision=precision, fixed_cycles=6)
@@ -235,8 +235,14 @@ def test_check_every(precision):
     assert s2["status"] == 0 and s2["cycles"] == expect, (st["cycles"], s2["cycles"])
     uf, sf = single(w, cycle="FMG", precision=precision, fixed_cycles=expect)
     assert np.array_equal(u2, uf)
+    # batches apply every tree's stop test on the device after every cycle:
+    # whatever the interval of host synchronisations, each tree runs the
+    # cycles of its own solve with per-cycle checking, full history included
     ws = bag(3)
-    ub, sb = batched(ws, cycle="V", precision=precision, tol=1e-10, check_every=2, graph=True)
-    for x, ux, sx in zip(ws, ub, sb):
-        us, ss = single(x, cycle="V", precision=precision, tol=1e-10, check_every=2)
-        assert np.array_equal(ux, us) and sx["cycles"] == ss["cycles"], x.name
+    ref = [single(x, cycle="V", precision=precision, tol=1e-10) for x in ws]
+    for every in (1, 2, 5):
+        ub, sb = batched(ws, cycle="V", precision=precision, tol=1e-10, check_every=every, graph=True)
+        for x, ux, sx, (us, ss) in zip(ws, ub, sb, ref):
+            assert np.array_equal(ux, us) and sx["cycles"] == ss["cycles"], (x.name, every)
+            assert np.array_equal(sx["hist_max"], ss["hist_max"]), (x.name, every)
+            assert not np.isnan(sx["hist_max"]).any()
