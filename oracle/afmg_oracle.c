@@ -23,8 +23,13 @@
  *   vcycle       the FAS V-cycle (paper §3.2, eqs. residual, coarse-rhs,
  *                coarse-corr)
  *   fmg          the FMG cycle without an initial guess (paper §3.2)
- *   restriction  averaging over the 2^D children (paper §2.5)
+ *   restriction  averaging over the 2^D children (paper §2.5); in the
+ *                cylindrical form the mean over the parent cell's volume
  *   prolongation 2-1-1 interpolation (paper §2.5)
+ *   operators    the Laplacian, or div(eps grad u) with eps per cell and the
+ *                harmonic mean of the two cells' eps on each face (paper
+ *                §3.4), or the cylindrical (r, z) form of either (paper §3.5,
+ *                §4.1 case 2); an eps-weighted prolongation (paper §3.5)
  *
  * Readings where the paper is silent (each also listed in the design notes):
  *   - red cells are those whose 1-based global index sum is even;
@@ -68,6 +73,8 @@ typedef struct {
     int bctype[6];  /* side type per orientation (OR_DIRICHLET, OR_NEUMANN, OR_PERIODIC) */
     int ext[3];     /* extent of the coarse-grid lattice (level-1 boxes) per axis */
     int nroot;      /* level-1 boxes */
+    int opk;        /* operator: OR_OP_* bits, 0 for the Laplacian */
+    double *eps;    /* eps per cell with ghosts (OR_OP_EPS), else NULL */
 } otree;
 
 /* ------------------------------------------------------------------------ */
@@ -402,7 +409,7 @@ void or_tree_free(void *p) {
     free(t->lev); free(t->ix); free(t->iy); free(t->iz); free(t->n); free(t->parent);
     free(t->leaf); free(t->child); free(t->nbr); free(t->off); free(t->bcoff);
     free(t->leaf_box); free(t->lvl_store);
-    free(t->u); free(t->rho); free(t->uold); free(t->res); free(t->bc);
+    free(t->u); free(t->rho); free(t->uold); free(t->res); free(t->bc); free(t->eps);
     free(t);
 }
 
@@ -437,6 +444,7 @@ static double *fld(otree *t, int which) {
     case 0: return t->u;
     case 1: return t->rho;
     case 2: return t->uold;
+    case 4: return t->eps;
     default: return t->res;
     }
 }
@@ -610,6 +618,106 @@ static double nb_sum(const otree *t, const double *f, int b, int i, int j, int k
 }
 
 /* ------------------------------------------------------------------------ */
+/* operators (paper §3.4, §3.5)                                              */
+/* ------------------------------------------------------------------------ */
+/* With an operator set, the equation of a cell is
+     (1/h^2) sum over its 2D sides of w_s (u_s - u_c) = rho_c
+   where u_s is the value across side s (neighbour or ghost, as for the
+   Laplacian) and w_s the face coefficient:
+     OR_OP_EPS: 2 eps_c eps_s / (eps_c + eps_s), eps_s the eps of the cell
+                across the side (a ghost of eps, see fill_eps_gc);
+     OR_OP_CYL: the radial sides (x is r) also carry r_face / r_c, from the
+                finite-volume form of (1/r) d/dr (r eps du/dr); the face on
+                the axis (r = 0) has w = 0.
+   With every w_s = 1 this is the Laplacian. */
+#define OR_OP_EPS 1
+#define OR_OP_CYL 2
+#define OR_OP_PROLONG_EPS 4
+
+static double face_coef(const otree *t, int b, int i, int j, int k, int s) {
+    double w = 1.0;
+    if (t->opk & OR_OP_EPS) {
+        int d = s / 2, hi = s % 2;
+        int q[3] = {i, j, k};
+        q[d] += hi ? 1 : -1;
+        double ec = t->eps[PX(t, b, i, j, k)], en = t->eps[PX(t, b, q[0], q[1], q[2])];
+        w = 2.0 * ec * en / (ec + en);
+    }
+    if ((t->opk & OR_OP_CYL) && s < 2) {
+        double h = level_h(t, t->lev[b]);
+        double x0 = (double)(t->ix[b] - 1) * t->n[b] * h; /* left edge of the box */
+        double rc = x0 + (i - 0.5) * h;
+        double rf = x0 + (s == 1 ? i : i - 1) * h;
+        w *= rf / rc;
+    }
+    return w;
+}
+
+/* sum over the 2D sides of w_s f_s, and in *diag the sum of the w_s */
+static double op_sum(const otree *t, const double *f, int b, int i, int j, int k, double *diag) {
+    double sum = 0.0, dg = 0.0;
+    for (int s = 0; s < 2 * t->dim; s++) {
+        int d = s / 2, hi = s % 2;
+        int q[3] = {i, j, k};
+        q[d] += hi ? 1 : -1;
+        double w = face_coef(t, b, i, j, k, s);
+        sum += w * f[PX(t, b, q[0], q[1], q[2])];
+        dg += w;
+    }
+    *diag = dg;
+    return sum;
+}
+
+/* (L f)_c * h^2 on cell (i, j, k) of box b (ghosts filled) */
+static double op_h2(const otree *t, const double *f, int b, int i, int j, int k) {
+    if (!t->opk) return nb_sum(t, f, b, i, j, k) - 2.0 * t->dim * f[PX(t, b, i, j, k)];
+    double dg, sm = op_sum(t, f, b, i, j, k, &dg);
+    return sm - dg * f[PX(t, b, i, j, k)];
+}
+
+/* Side ghosts of eps on every box of level l: the eps of the cell across
+   the side; on a physical side the face cell's own eps; on a refinement
+   boundary the eps of the coarse cell that contains the ghost centre (the
+   jumps lie on coarse-grid faces, paper §3.4, so this is the eps there). */
+static void fill_eps_gc(otree *t, int l) {
+    int D = t->dim;
+    double *f = t->eps;
+    for (int m = 0; m < lvl_count(t, l); m++) {
+        int b = lvl_box(t, l, m);
+        int n = t->n[b];
+        for (int s = 0; s < 2 * D; s++) {
+            int d = s / 2, hi = s % 2;
+            int nb = t->nbr[6 * b + s];
+            int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+            for (int c = 1; c <= (D == 3 ? n : 1); c++)
+                for (int a = 1; a <= n; a++) {
+                    int g[3], c1[3];
+                    g[t1] = c1[t1] = a;
+                    g[t2] = c1[t2] = D == 3 ? c : 1;
+                    g[d] = hi ? n + 1 : 0;
+                    c1[d] = hi ? n : 1;
+                    double v;
+                    if (nb >= 0) {
+                        int q[3] = {c1[0], c1[1], c1[2]};
+                        q[d] = hi ? 1 : n;
+                        v = f[PX(t, nb, q[0], q[1], q[2])];
+                    } else if (nb == -1) {
+                        v = f[PX(t, b, c1[0], c1[1], c1[2])];
+                    } else {
+                        int cb = t->nbr[6 * t->parent[b] + s];
+                        int qc[3];
+                        qc[d] = hi ? 1 : n;
+                        qc[t1] = child_offset(t, b, t1) + (a + 1) / 2;
+                        qc[t2] = D == 3 ? child_offset(t, b, t2) + (c + 1) / 2 : 1;
+                        v = f[PX(t, cb, qc[0], qc[1], qc[2])];
+                    }
+                    f[PX(t, b, g[0], g[1], g[2])] = v;
+                }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* smoother (paper §3.1)                                                     */
 /* ------------------------------------------------------------------------ */
 /* colour 0 = red: 1-based index sum even (within a box this equals the
@@ -625,7 +733,13 @@ static void half_sweep(otree *t, int l, int colour, int homog) {
             int par = (i + j + (t->dim == 3 ? k : 0)) & 1;
             if (par != colour) continue;
             int64_t c = PX(t, b, i, j, k);
-            t->u[c] = (nb_sum(t, t->u, b, i, j, k) - h2 * t->rho[c]) / twoD;
+            if (t->opk) {
+                /* the cell's own equation solved with the neighbours fixed */
+                double dg, sm = op_sum(t, t->u, b, i, j, k, &dg);
+                t->u[c] = (sm - h2 * t->rho[c]) / dg;
+            } else {
+                t->u[c] = (nb_sum(t, t->u, b, i, j, k) - h2 * t->rho[c]) / twoD;
+            }
         }
     }
 }
@@ -639,22 +753,42 @@ static void gsrb(otree *t, int l, int nsweep, int homog) {
 /* r = rho - L u on the given box (ghosts must be filled) */
 static void box_residual(otree *t, int b, double *out) {
     double h = level_h(t, t->lev[b]), ih2 = 1.0 / (h * h);
-    double twoD = 2.0 * t->dim;
     FOR_CELLS(t, b, i, j, k) {
         int64_t c = PX(t, b, i, j, k);
-        out[c] = t->rho[c] - (nb_sum(t, t->u, b, i, j, k) - twoD * t->u[c]) * ih2;
+        out[c] = t->rho[c] - op_h2(t, t->u, b, i, j, k) * ih2;
     }
 }
 
 /* ------------------------------------------------------------------------ */
 /* restriction / prolongation (paper §2.5)                                   */
 /* ------------------------------------------------------------------------ */
-/* parent cells covered by box b <- mean of its 2^D cells, for field src -> dst */
+/* parent cells covered by box b <- mean of its 2^D cells, for field src -> dst
+   (in the cylindrical form the mean over the parent cell's volume, each
+   child weighted by its volume, which is proportional to its radius) */
 static void restrict_box(otree *t, int b, const double *src, double *dst) {
     int p = t->parent[b], D = t->dim, n = t->n[b];
     int o0 = child_offset(t, b, 0), o1 = child_offset(t, b, 1), o2 = D == 3 ? child_offset(t, b, 2) : 0;
     int nk = D == 3 ? n / 2 : 1;
     double w = D == 3 ? 0.125 : 0.25;
+    if (t->opk & OR_OP_CYL) {
+        /* volume mean: the children's volumes are proportional to their
+           radius r (x); the parent cell's volume is their sum */
+        double h = level_h(t, t->lev[b]);
+        double x0 = (double)(t->ix[b] - 1) * n * h;
+        for (int J = 1; J <= n / 2; J++)
+            for (int I = 1; I <= n / 2; I++) {
+                double s = 0.0, v = 0.0;
+                for (int dj = 0; dj < 2; dj++)
+                    for (int di = 0; di < 2; di++) {
+                        int i = 2 * I - 1 + di;
+                        double r = x0 + (i - 0.5) * h;
+                        s += r * src[PX(t, b, i, 2 * J - 1 + dj, 1)];
+                        v += r;
+                    }
+                dst[PX(t, p, o0 + I, o1 + J, 1)] = s / v;
+            }
+        return;
+    }
     for (int K = 1; K <= nk; K++)
         for (int J = 1; J <= n / 2; J++)
             for (int I = 1; I <= n / 2; I++) {
@@ -668,7 +802,15 @@ static void restrict_box(otree *t, int b, const double *src, double *dst) {
             }
 }
 
-/* u_b += P211(delta) where delta = u - uold of the parent, ghosts included */
+/* u_b += P211(delta) where delta = u - uold of the parent, ghosts included.
+   With OR_OP_PROLONG_EPS the weights come from the parent's eps: along each
+   axis d the fine cell sits a quarter coarse cell from its coarse cell P
+   towards the neighbour P + s_d e_d, and the piecewise-linear profile with
+   continuous value and continuous flux eps du/dx at the face between them
+   (the local reconstruction of paper §3.4) puts it at
+     delta(P) + eps_d / (2 (eps_P + eps_d)) (delta(P + s_d e_d) - delta(P));
+   the corrections of the axes add up.  With equal eps every weight is 1/4,
+   which is the default interpolation in 2D and 3D. */
 static void prolong_correct_box(otree *t, int b) {
     int p = t->parent[b], D = t->dim;
     int o0 = child_offset(t, b, 0), o1 = child_offset(t, b, 1), o2 = D == 3 ? child_offset(t, b, 2) : 0;
@@ -677,7 +819,16 @@ static void prolong_correct_box(otree *t, int b) {
         int s[3] = {(i & 1) ? -1 : 1, (j & 1) ? -1 : 1, (k & 1) ? -1 : 1};
 #define DEL(a, bb, cc) (t->u[PX(t, p, a, bb, cc)] - t->uold[PX(t, p, a, bb, cc)])
         double v;
-        if (D == 2) {
+        if (t->opk & OR_OP_PROLONG_EPS) {
+            double d0 = DEL(P[0], P[1], P[2]), e0 = t->eps[PX(t, p, P[0], P[1], P[2])];
+            v = d0;
+            for (int d = 0; d < D; d++) {
+                int Q[3] = {P[0], P[1], P[2]};
+                Q[d] += s[d];
+                double ed = t->eps[PX(t, p, Q[0], Q[1], Q[2])];
+                v += ed / (2.0 * (e0 + ed)) * (DEL(Q[0], Q[1], Q[2]) - d0);
+            }
+        } else if (D == 2) {
             v = 0.5 * DEL(P[0], P[1], 1) + 0.25 * DEL(P[0] + s[0], P[1], 1) + 0.25 * DEL(P[0], P[1] + s[1], 1);
         } else {
             v = 0.25 * (DEL(P[0], P[1], P[2]) + DEL(P[0] + s[0], P[1], P[2]) +
@@ -727,7 +878,7 @@ static void vcycle(otree *t, int top, const or_opts *o) {
             restrict_box(t, b, t->res, t->res);
         }
         fill_gc(t, l - 1, t->u, homog);
-        double H = level_h(t, l - 1), iH2 = 1.0 / (H * H), twoD = 2.0 * t->dim;
+        double H = level_h(t, l - 1), iH2 = 1.0 / (H * H);
 #pragma omp parallel for schedule(dynamic, 16)
         for (int m = 0; m < lvl_count(t, l - 1); m++) {
             int b = lvl_box(t, l - 1, m);
@@ -735,7 +886,7 @@ static void vcycle(otree *t, int top, const or_opts *o) {
             if (t->leaf[b]) continue;
             FOR_CELLS(t, b, i, j, k) {
                 int64_t c = PX(t, b, i, j, k);
-                t->rho[c] = t->res[c] + (nb_sum(t, t->u, b, i, j, k) - twoD * t->u[c]) * iH2;
+                t->rho[c] = t->res[c] + op_h2(t, t->u, b, i, j, k) * iH2;
             }
         }
     }
@@ -902,14 +1053,14 @@ void or_resid_restrict_level(void *p, int l, int homog) {
 void or_coarse_rhs_level(void *p, int l, int homog) {
     otree *t = (otree *)p;
     fill_gc(t, l, t->u, homog);
-    double H = level_h(t, l), iH2 = 1.0 / (H * H), twoD = 2.0 * t->dim;
+    double H = level_h(t, l), iH2 = 1.0 / (H * H);
     for (int m = 0; m < lvl_count(t, l); m++) {
         int b = lvl_box(t, l, m);
         copy_box_padded(t, b, t->u, t->uold);
         if (t->leaf[b]) continue;
         FOR_CELLS(t, b, i, j, k) {
             int64_t c = PX(t, b, i, j, k);
-            t->rho[c] = t->res[c] + (nb_sum(t, t->u, b, i, j, k) - twoD * t->u[c]) * iH2;
+            t->rho[c] = t->res[c] + op_h2(t, t->u, b, i, j, k) * iH2;
         }
     }
 }
@@ -943,6 +1094,34 @@ int or_get_bc(void *p, int b, int s, double *out) {
 }
 int or_num_threads(void) { return omp_get_max_threads(); }
 
+/* Operator of later solves (paper §3.4, §3.5): kind = OR_OP_EPS and / or
+   OR_OP_CYL bits (0: the Laplacian); eps_leaf [n_leaves][N^D] (x fastest),
+   positive, required with OR_OP_EPS; prolong = 1 selects the eps-weighted
+   prolongation (needs OR_OP_EPS).  eps of parents and of the coarse grids
+   is the mean over their children (paper §2.5), so a jump on a coarse-grid
+   face stays on a face on every level.  Returns 0, or -1 with a message. */
+int or_set_operator(void *p, int kind, const double *eps_leaf, int prolong) {
+    otree *t = (otree *)p;
+    if (kind < 0 || kind > (OR_OP_EPS | OR_OP_CYL)) { seterr(NULL, 0, "bad operator kind"); return -1; }
+    if ((kind & OR_OP_CYL) && t->dim != 2) { seterr(NULL, 0, "the cylindrical operator is 2D (r, z)"); return -1; }
+    if ((kind & OR_OP_EPS) && !eps_leaf) { seterr(NULL, 0, "eps missing"); return -1; }
+    if (prolong && !(kind & OR_OP_EPS)) { seterr(NULL, 0, "the eps prolongation needs eps"); return -1; }
+    int64_t nc = t->dim == 3 ? (int64_t)t->N * t->N * t->N : (int64_t)t->N * t->N;
+    if (kind & OR_OP_EPS)
+        for (int64_t i = 0; i < nc * t->nleaf_in; i++)
+            if (!(eps_leaf[i] > 0.0) || !isfinite(eps_leaf[i])) { seterr(NULL, 0, "eps must be positive and finite"); return -1; }
+    free(t->eps);
+    t->eps = NULL;
+    t->opk = kind | (prolong ? OR_OP_PROLONG_EPS : 0);
+    if (!(kind & OR_OP_EPS)) return 0;
+    t->eps = calloc(t->ntot, sizeof(double));
+    load_leaf_field(t, t->eps, eps_leaf);
+    for (int l = t->lmax; l > t->lmin; l--)
+        for (int m = 0; m < lvl_count(t, l); m++) restrict_box(t, lvl_box(t, l, m), t->eps, t->eps);
+    for (int l = t->lmin; l <= t->lmax; l++) fill_eps_gc(t, l);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* sparse assembly of the composite operator (for the adjoint oracle)        */
 /* ------------------------------------------------------------------------ */
@@ -965,6 +1144,7 @@ static int64_t leaf_unknown(const otree *t, const int *leaf_of_box, int b, int i
 
 int64_t or_assemble_L(void *p, int32_t *rows, int32_t *cols, double *vals) {
     otree *t = (otree *)p;
+    if (t->opk) { seterr(NULL, 0, "assembly covers the Laplacian only"); return -1; }
     int D = t->dim, N = t->N;
     int *leaf_of_box = malloc(sizeof(int) * t->nbox);
     for (int b = 0; b < t->nbox; b++) leaf_of_box[b] = -1;

@@ -99,6 +99,8 @@ def lib():
         L.or_num_threads.restype = C.c_int
         L.or_assemble_L.argtypes = [vp, i32p, i32p, dp]
         L.or_assemble_L.restype = C.c_int64
+        L.or_set_operator.argtypes = [vp, C.c_int, dp, C.c_int]
+        L.or_set_operator.restype = C.c_int
         _lib = L
     return _lib
 
@@ -107,7 +109,11 @@ def _dp(a):
     return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
 
 
-FIELD = {"u": 0, "rho": 1, "uold": 2, "res": 3}
+FIELD = {"u": 0, "rho": 1, "uold": 2, "res": 3, "eps": 4}
+
+# operators (paper §3.4, §3.5): bit 1 a coefficient eps per cell with the
+# harmonic mean on faces, bit 2 the cylindrical (r, z) form (2D, x = r)
+OPERATORS = {"laplacian": 0, "eps": 1, "cyl": 2, "cyl_eps": 3}
 
 
 class OracleError(RuntimeError):
@@ -211,6 +217,17 @@ class Tree:
             status=rc, cycles=st.cycles, r0_max=st.r0_max, r0_l2=st.r0_l2, r_max=st.r_max,
             r_l2=st.r_l2, hist_max=hist, hist_l2=np.array(st.hist_l2[:min(st.cycles, 128)]))
 
+    def set_operator(self, kind="laplacian", eps=None, prolong="default"):
+        """Operator of later solves and steps: "laplacian", "eps" (div(eps
+        grad u)), "cyl" (cylindrical (r, z)) or "cyl_eps"; eps [n_leaves,
+        N^D] > 0 per leaf cell; prolong "default" or "eps" (eps-weighted)."""
+        code = OPERATORS[kind] if isinstance(kind, str) else int(kind)
+        e = None if eps is None else self._leaf_arr(eps, "eps")
+        rc = lib().or_set_operator(self.h, code, _dp(e), 1 if prolong == "eps" else 0)
+        if rc != 0:
+            raise OracleError(lib().or_last_error().decode())
+        self.operator = (code, prolong)
+
     def apply_L(self, u, bc=None, homog=True):
         u = self._leaf_arr(u, "u")
         bc = self._bc_arr(bc)
@@ -300,6 +317,8 @@ def assemble_L(tree):
     """Sparse matrix (scipy CSR) of the homogeneous composite operator on the
     leaf unknowns, numbered q * N^D + cell in the caller's leaf order."""
     import scipy.sparse as sp
+    if getattr(tree, "operator", (0,))[0]:
+        raise OracleError("the sparse assembly covers the Laplacian only")
     r, c, v = _assemble(tree)
     n = tree.n_leaves * tree.cells_per_box
     return sp.csr_matrix((v, (r, c)), shape=(n, n))

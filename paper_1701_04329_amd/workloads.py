@@ -63,6 +63,15 @@ class GaussMix:
             out += a * np.exp(-r2 / (s * s))
         return out
 
+    def gradient(self, x: np.ndarray) -> np.ndarray:
+        """x: [..., D] -> [..., D]: sum_k -2 (x - c_k) / s_k^2 * g_k."""
+        out = np.zeros(x.shape)
+        for c, s, a in zip(self.centres, self.sigmas, self.amps):
+            r2 = np.sum((x - c) ** 2, axis=-1)
+            g = a * np.exp(-r2 / (s * s))
+            out += (-2.0 / (s * s)) * (x - c) * g[..., None]
+        return out
+
     def laplacian(self, x: np.ndarray) -> np.ndarray:
         """Analytic Laplacian: (4 r^2 / s^4 - 2 D / s^2) * g for each term."""
         d = x.shape[-1]
@@ -393,6 +402,7 @@ class Workload:
     bc: np.ndarray  # float64 [n, 2D, N^(D-1)]
     u_exact: np.ndarray | None = None  # float64 [n, N^D] analytic at centres
     mix: GaussMix | None = None
+    eps: np.ndarray | None = None  # float64 [n, N^D] cell coefficients (variable operators)
 
     @property
     def n_leaves(self):
@@ -612,3 +622,83 @@ def ball_leaves(dim, N, lmax, centre, radius=0.0, n_buf=0):
     """Grid refined to lmax around a ball (small grids with refinement
     boundaries at several levels, used by tests)."""
     return adaptive_leaves(dim, N, ball_flag(dim, N, centre, radius), lmax, n_buf=n_buf)
+
+
+# ----------------------------------------------------------------------------
+# variable coefficients and the cylindrical form (paper §3.4, §3.5, §4.1)
+# ----------------------------------------------------------------------------
+
+
+def random_eps(n_leaves, N, dim, seed, lo=0.5, hi=2.0):
+    """Cell coefficients log-uniform in [lo, hi], one per leaf cell."""
+    rng = np.random.default_rng(seed)
+    return np.exp(rng.uniform(math.log(lo), math.log(hi), size=(n_leaves, N ** dim)))
+
+
+def eps_sampled(eps_fn, dim, N, level, idx):
+    """eps_fn(x [..., D]) sampled at the leaf cell centres."""
+    return np.ascontiguousarray(eps_fn(cell_centres(dim, N, level, idx)))
+
+
+def case2_eps(x):
+    """Paper §4.1, case 2: eps = 100 in the lower left quadrant [0, 0.25]^2
+    of the (r, z) domain, 1 elsewhere."""
+    return np.where((x[..., 0] < 0.25) & (x[..., 1] < 0.25), 100.0, 1.0)
+
+
+def case2_mix():
+    """u = sum of two Gaussians at (0.25, 0.25) and (0.75, 0.75), sigma 0.04
+    (the manufactured solution of paper §4.1, read as Gaussians)."""
+    return GaussMix(np.array([[0.25, 0.25], [0.75, 0.75]]), np.array([0.04, 0.04]), np.ones(2))
+
+
+def divergence_source(mix: GaussMix, eps_fn, dim, N, level, idx, cyl=False):
+    """Cell values of rho = div(eps grad u) for a smooth u and a piecewise
+    constant eps (cylindrical: (1/r) d/dr (r eps du/dr) + d/dz (eps du/dz),
+    x = r).  Away from jumps this is eps(x_c) times the Laplacian of u at the
+    cell centre.  A jump of eps on a cell face adds the surface source
+    (eps_across - eps_own) du/dn at the face centre (n the outward normal),
+    spread over the two cells that share the face, half to each: each takes
+    its half times face area / cell volume, 1/(2h) (times r_face / r_c on a
+    radial face of the cylindrical form)."""
+    level = np.asarray(level)
+    idx = np.asarray(idx)
+    xc = cell_centres(dim, N, level, idx)
+    h = box_h(level, N)[:, None]
+    e_c = eps_fn(xc)
+    lap = mix.laplacian(xc)
+    if cyl:
+        lap = lap + mix.gradient(xc)[..., 0] / xc[..., 0]
+    rho = e_c * lap
+    for d in range(dim):
+        for sgn in (-1.0, 1.0):
+            off = np.zeros(dim)
+            off[d] = sgn
+            e_o = eps_fn(xc + off * h[..., None])
+            jump = e_o != e_c
+            if not jump.any():
+                continue
+            xf = xc + 0.5 * off * h[..., None]
+            dn = sgn * mix.gradient(xf)[..., d]
+            geo = xf[..., 0] / xc[..., 0] if (cyl and d == 0) else 1.0
+            rho = rho + np.where(jump, 0.5 * (e_o - e_c) * dn * geo / h, 0.0)
+    return rho
+
+
+def case2_workload(N=BOX_N_DEFAULT, lmax=7, threshold=1e-3):
+    """Paper §4.1, case 2: the cylindrical (r, z) problem with eps = 100 in
+    [0, 0.25]^2 on [0, 1]^2, Dirichlet values from u on every side (the one
+    on the axis r = 0 carries no flux), boxes refined where
+    h^2 |rho| / eps > threshold."""
+    mix = case2_mix()
+
+    def flag(level, idx):
+        rho = divergence_source(mix, case2_eps, 2, N, level, idx, cyl=True)
+        e = eps_sampled(case2_eps, 2, N, level, idx)
+        return np.abs(rho) * box_h(level, N)[:, None] ** 2 / e > threshold
+
+    lev, idx = adaptive_leaves(2, N, flag, lmax)
+    w = sample_workload("case2", 2, N, lev, idx, mix)
+    w.rho = np.ascontiguousarray(divergence_source(mix, case2_eps, 2, N, lev, idx, cyl=True))
+    w.eps = eps_sampled(case2_eps, 2, N, lev, idx)
+    return w

@@ -23,6 +23,16 @@ on the integer lattice, paper §2.2); a face is physical when the cell across
 it lies outside the lattice on a non-periodic axis or in a lattice position
 without a level-1 box.
 
+Variable coefficients and the cylindrical form (paper §3.4, §3.5): each face
+term (u_nb - u_c) / h^2 is multiplied by a face weight w, the harmonic mean
+2 e_c e_nb / (e_c + e_nb) of the coefficient of the cell and of the cell
+across the face (its own value at a physical face; for a refined neighbour
+the volume mean of the children's values; for a coarser neighbour the value
+of the coarse leaf cell), times r_face / r_c on the radial faces of the
+cylindrical form (x = r, the face on the axis has weight 0).  In the
+cylindrical form the value of a refined cell (u and eps) is the mean over
+its volume: children weighted by their radius.
+
 This is written independently of the oracle (global cell indices instead of
 boxes with stored ghost layers) and only serves to pin it.
 """
@@ -32,11 +42,12 @@ from __future__ import annotations
 import numpy as np
 
 
-def assemble(dim, N, level, idx, bc=None, bc_type=None):
+def assemble(dim, N, level, idx, bc=None, bc_type=None, eps=None, cyl=False):
     """Return (A, g) with A u = rho - g for the leaf unknowns in leaf-list
     order (x fastest within each leaf), g the boundary part.  bc_type: None
     (all Dirichlet), one name or 2D names among "dirichlet", "neumann",
-    "periodic"."""
+    "periodic".  eps: [n_leaves, N^D] cell coefficients (None: 1); cyl: the
+    cylindrical (r, z) form (2D)."""
     level = np.asarray(level)
     idx = np.asarray(idx)
     n_leaf = len(level)
@@ -88,6 +99,25 @@ def assemble(dim, N, level, idx, bc=None, bc_type=None):
     def box_exists(l, G):
         return ((l,) + tuple(g // N + 1 for g in G)) in boxes
 
+    epsf = None if eps is None else np.asarray(eps, dtype=np.float64).reshape(n_leaf, ncell)
+
+    def child_weights(l, G):
+        """children of cell G of level l and their volume fractions"""
+        kids = [[2 * G[e] + off[e] for e in range(dim)] for off in np.ndindex(*([2] * dim))]
+        if cyl:
+            hc = 1.0 / (N * 2.0 ** l)  # child cell size
+            r = np.array([(k[0] + 0.5) * hc for k in kids])
+            return kids, r / r.sum()
+        return kids, np.full(len(kids), 1.0 / len(kids))
+
+    def cell_eps(l, G):
+        """volume mean of the leaf coefficients inside cell G of level l"""
+        u = cell_unknown(l, G)
+        if u is not None:
+            return epsf.reshape(-1)[u]
+        kids, wk = child_weights(l, G)
+        return float(sum(w * cell_eps(l + 1, k) for k, w in zip(kids, wk)))
+
     A = np.zeros((n, n))
     gvec = np.zeros(n)
     for q in range(n_leaf):
@@ -99,9 +129,15 @@ def assemble(dim, N, level, idx, bc=None, bc_type=None):
         for loc in locs:
             row = q * ncell + loc_pos[loc]
             G = [org[d] + loc[d] for d in range(dim)]
-            A[row, row] -= 2 * dim * ih2
+            e_c = None if epsf is None else epsf[q, loc_pos[loc]]
             for d in range(dim):
                 for sgn in (-1, 1):
+                    # face weight: geometric factor now, the coefficient part
+                    # once the cell across the face is known
+                    geo = 1.0
+                    if cyl and d == 0:
+                        r_c = (G[0] + 0.5) * h
+                        geo = (G[0] + (1.0 if sgn > 0 else 0.0)) * h / r_c
                     side = 2 * d + (1 if sgn > 0 else 0)
                     Gn = list(G)
                     Gn[d] += sgn
@@ -113,35 +149,45 @@ def assemble(dim, N, level, idx, bc=None, bc_type=None):
                     if not outside:
                         outside = tuple(g // per_root + 1 for g in Gn) not in roots  # a hole
                     if outside:
+                        # the coefficient across a physical face is the cell's own
+                        wf = geo * (1.0 if e_c is None else e_c) * ih2
+                        A[row, row] -= wf
                         tang = [loc[e] for e in range(dim) if e != d]
                         fi = tang[0] + (N * tang[1] if dim == 3 else 0)
                         bv = 0.0 if bc is None else bc[q, side, fi]
                         if types[side] == "neumann":
                             # ghost = u_c + h q
-                            A[row, row] += ih2
-                            gvec[row] += bv * h * ih2
+                            A[row, row] += wf
+                            gvec[row] += bv * h * wf
                         else:
                             # Dirichlet: ghost = 2 b - u_c
-                            A[row, row] -= ih2
-                            gvec[row] += 2.0 * bv * ih2
+                            A[row, row] -= wf
+                            gvec[row] += 2.0 * bv * wf
                         continue
+
+                    def harm(e_n):
+                        return 1.0 if e_c is None else 2.0 * e_c * e_n / (e_c + e_n)
+
                     if box_exists(l, Gn):
                         col = cell_unknown(l, Gn)
+                        wf = geo * (1.0 if e_c is None else harm(cell_eps(l, Gn))) * ih2
+                        A[row, row] -= wf
                         if col is not None:
-                            A[row, col] += ih2
+                            A[row, col] += wf
                         else:
                             # refined neighbour: mean of its 2^D children
-                            w = ih2 / 2 ** dim
-                            for off in np.ndindex(*([2] * dim)):
-                                Gc = [2 * Gn[e] + off[e] for e in range(dim)]
+                            kids, wk = child_weights(l, Gn)
+                            for Gc, w in zip(kids, wk):
                                 cc = cell_unknown(l + 1, Gc)
                                 assert cc is not None, "2:1 balance violated"
-                                A[row, cc] += w
+                                A[row, cc] += wf * w
                         continue
                     # coarser neighbour: default refinement-boundary ghost
                     GH = [g // 2 for g in Gn]
                     cH = cell_unknown(l - 1, GH)
                     assert cH is not None, "coarse neighbour is not a leaf"
+                    wf = geo * (1.0 if e_c is None else harm(epsf.reshape(-1)[cH])) * ih2
+                    A[row, row] -= wf
                     G2 = list(G)
                     G2[d] -= sgn
                     c2 = cell_unknown(l, G2)
@@ -151,16 +197,16 @@ def assemble(dim, N, level, idx, bc=None, bc_type=None):
                         Gp = list(G)
                         Gp[e] ^= 1
                         partners.append(cell_unknown(l, Gp))
-                    A[row, cH] += 0.5 * ih2
+                    A[row, cH] += 0.5 * wf
                     if dim == 2:
-                        A[row, row] += 1.0 * ih2
-                        A[row, partners[0]] -= 0.25 * ih2
-                        A[row, c2] -= 0.25 * ih2
+                        A[row, row] += 1.0 * wf
+                        A[row, partners[0]] -= 0.25 * wf
+                        A[row, c2] -= 0.25 * wf
                     else:
-                        A[row, row] += 1.25 * ih2
-                        A[row, c2] -= 0.25 * ih2
-                        A[row, partners[0]] -= 0.25 * ih2
-                        A[row, partners[1]] -= 0.25 * ih2
+                        A[row, row] += 1.25 * wf
+                        A[row, c2] -= 0.25 * wf
+                        A[row, partners[0]] -= 0.25 * wf
+                        A[row, partners[1]] -= 0.25 * wf
     return A, gvec
 
 
