@@ -139,6 +139,8 @@ typedef struct {
     int bc_type[6];   /* afmg_bc_type per side orientation */
     int singular;     /* 1: no Dirichlet side; solutions are defined up to a
                          constant and rho must be compatible */
+    int op;           /* afmg_operator set by afmg_tree_set_operator */
+    int prolong;      /* afmg_prolong set by afmg_tree_set_operator */
 } afmg_tree_desc;
 
 /* Side types of the domain boundary (paper §3), per orientation -x, +x, -y,
@@ -225,6 +227,55 @@ int afmg_tree_refine(const afmg_tree *tree, const int32_t *box_ids, int64_t n, i
    is the only preparation a tree needs.  Errors: AFMG_ERR_ARG (another
    device than the first use), AFMG_ERR_OOM, AFMG_ERR_HIP. */
 int afmg_tree_finalize(afmg_tree *tree, void *stream);
+
+/*
+ * Elliptic operator of the tree's later solves and steps (paper §3.4, §3.5;
+ * the default is the Laplacian).  Each cell's equation is
+ *   (1/h^2) sum over its 2D sides s of w_s (u_s - u_c) = rho_c
+ * with u_s the value across the side (neighbour cell or ghost, as for the
+ * Laplacian) and the face weight w_s:
+ *   AFMG_OPERATOR_EPS   div(eps grad u) with eps per cell: w_s is the
+ *                       harmonic mean 2 eps_c eps_s / (eps_c + eps_s) of the
+ *                       cell's eps and the eps across the side (the
+ *                       neighbour cell; the cell's own on a physical side;
+ *                       the coarse cell holding the ghost centre on a
+ *                       refinement side).  The paper's setting is a jump on
+ *                       a coarse-grid cell face (§3.4); any positive eps is
+ *                       accepted.
+ *   AFMG_OPERATOR_CYL   cylindrical (r, z) coordinates, 2D only, x = r >= 0
+ *                       (the domain starts on the axis): the radial sides
+ *                       carry r_face / r_c as well, the face on the axis has
+ *                       weight 0; restriction is the mean over the parent
+ *                       cell's volume (children weighted by radius).
+ *   AFMG_OPERATOR_CYL_EPS both (the paper's §4.1 case 2).
+ * prolong: AFMG_PROLONG_DEFAULT (the 2-1-1 interpolation of §2.5) or
+ * AFMG_PROLONG_EPS (needs eps): per axis the fine cell moves from its coarse
+ * cell P towards P + s e_d by eps_d / (2 (eps_P + eps_d)) of the difference,
+ * the piecewise-linear profile with continuous value and flux eps du/dn
+ * (the local reconstruction of §3.4; with equal eps the default weights).
+ *   eps     device, [n_boxes][N^D] FP64 in the layout of rho (x fastest;
+ *           only leaf boxes are read), positive and finite; NULL unless the
+ *           operator has eps.  Copied: the caller may free it on return.
+ * Parents receive the (volume) means of their children's eps.  The tree
+ * keeps the coefficients in device memory of its own (allocated here,
+ * released with the tree).  The solve then takes the general coarse path
+ * (afmg_workspace_bytes grows: query it after this call) and FP64 only.
+ * Synchronises the stream.  Errors: AFMG_ERR_ARG (a batch, a bad operator
+ * or prolongation, the cylindrical form in 3D, eps missing, misaligned, not
+ * positive or not finite), AFMG_ERR_OOM, AFMG_ERR_HIP.  With an operator
+ * set, afmg_apply, afmg_adjoint, the autotuner, launch shapes other than the
+ * default and afmg_batch_create reject the tree (AFMG_ERR_ARG);
+ * afmg_tree_refine returns a tree with the Laplacian.  Setting
+ * AFMG_OPERATOR_LAPLACIAN with AFMG_PROLONG_DEFAULT restores the default.
+ */
+typedef enum {
+    AFMG_OPERATOR_LAPLACIAN = 0,
+    AFMG_OPERATOR_EPS = 1,
+    AFMG_OPERATOR_CYL = 2,
+    AFMG_OPERATOR_CYL_EPS = 3
+} afmg_operator;
+typedef enum { AFMG_PROLONG_DEFAULT = 0, AFMG_PROLONG_EPS = 1 } afmg_prolong;
+int afmg_tree_set_operator(afmg_tree *tree, void *stream, int op, const double *eps, int prolong);
 
 /* Box lists per level (paper §2.1): all boxes, parents (refined boxes) or
    leaves of `level` (1 .. lmax), in box-id order, which is Morton order

@@ -87,6 +87,8 @@ class TreeDesc(C.Structure):
         ("ext", C.c_int * 3),
         ("bc_type", C.c_int * 6),
         ("singular", C.c_int),
+        ("op", C.c_int),
+        ("prolong", C.c_int),
     ]
 
 
@@ -139,8 +141,11 @@ EXPORTS = [
     "afmg_batch_solve", "afmg_autotune_workspace_bytes", "afmg_tree_autotune", "afmg_tree_shape",
     "afmg_tree_set_shape", "afmg_batch_autotune_workspace_bytes", "afmg_batch_autotune", "afmg_batch_shape",
     "afmg_batch_set_shape", "afmg_tree_refine", "afmg_tree_finalize", "afmg_tree_level_list", "afmg_step",
-    "afmg_solve_noalloc", "afmg_tree_create_domain",
+    "afmg_solve_noalloc", "afmg_tree_create_domain", "afmg_tree_set_operator",
 ]
+# operators (paper §3.4, §3.5) and prolongations of afmg_tree_set_operator
+OPERATORS = {"laplacian": 0, "eps": 1, "cyl": 2, "cyl_eps": 3}
+PROLONGS = {"default": 0, "eps": 1}
 STEPS = {"half_sweep": 0, "resid_restrict": 1, "coarse_rhs": 2, "prolong": 3, "coarse": 4}
 LISTS = {"all": 0, "parent": 1, "leaf": 2}
 KINDS = {"gsrb": 0, "resid": 1, "coarse_rhs": 2, "prolong": 3, "final": 4}
@@ -201,6 +206,7 @@ def lib():
         L.afmg_step.argtypes = [vp, vp, C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, vp, C.c_size_t,
                                 C.POINTER(Opts)]
         L.afmg_batch_autotune_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+        L.afmg_tree_set_operator.argtypes = [vp, vp, C.c_int, vp, C.c_int]
         _lib = L
     return _lib
 
@@ -344,6 +350,24 @@ class Tree(_Shapes):
 
     def finalize(self):
         _check(lib().afmg_tree_finalize(self._h, None))
+
+    def set_operator(self, kind="laplacian", eps=None, prolong="default"):
+        """Operator of later solves (afmg_tree_set_operator): "laplacian",
+        "eps", "cyl" or "cyl_eps"; eps a float64 CUDA tensor [n_boxes, N^D]
+        in box order (leaf boxes read); prolong "default" or "eps"."""
+        code = OPERATORS[kind] if isinstance(kind, str) else int(kind)
+        pro = PROLONGS[prolong] if isinstance(prolong, str) else int(prolong)
+        if eps is not None:
+            if eps.dtype != __import__("torch").float64 or not eps.is_cuda or not eps.is_contiguous():
+                raise ValueError("eps must be a contiguous float64 CUDA tensor")
+            if eps.numel() != self.n_boxes * self.cells_per_box:
+                raise ValueError("eps must hold n_boxes x N^D values")
+        import torch
+        dev = eps.device if eps is not None else torch.device("cuda", torch.cuda.current_device())
+        with torch.cuda.device(dev):
+            stream = torch.cuda.current_stream(dev)
+            _check(lib().afmg_tree_set_operator(self._h, C.c_void_p(stream.cuda_stream), code, _ptr(eps), pro))
+        self.operator = (code, pro)
 
     def level_list(self, level, kind="all"):
         n = C.c_int64()

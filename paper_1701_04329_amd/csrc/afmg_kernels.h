@@ -38,7 +38,23 @@ struct LevelArgs {
     // take their boxes from it
     const int32_t *act;
     const int *nact;
+    // operator of the tree (OPK_* bits, 0: the Laplacian), its cell
+    // coefficients eps (colour-split like u; leaves and their restriction on
+    // parents) and the x index of every box (cylindrical radius)
+    const T *eps;
+    const int32_t *bx;
+    int opk;
 };
+
+// Operators (paper §3.4, §3.5): a cell's equation is
+//   (1/h^2) sum over its 2D sides of w_s (u_s - u_c) = rho_c
+// with u_s the value across side s (neighbour cell or ghost) and w_s = 1 for
+// the Laplacian; OPK_EPS: w_s = 2 eps_c eps_s / (eps_c + eps_s), eps_s the
+// coefficient across the side; OPK_CYL: the cylindrical (r, z) form, x = r,
+// the radial sides also carry r_face / r_c, and restriction is the mean over
+// the parent cell's volume (children weighted by radius); OPK_PROLONG_EPS:
+// eps-weighted prolongation.
+constexpr int OPK_EPS = 1, OPK_CYL = 2, OPK_PROLONG_EPS = 4;
 
 // Per-tree stop rule of a forest, kept on the device (paper: no error
 // control is built into the method, §3.2; the stop rule is the library's)
@@ -94,6 +110,11 @@ struct CoarseGenArgs {
     int mode;           // COARSE_V_FROM_2, COARSE_V_TOP1 or COARSE_FMG
     int homog;
     int n_down, n_up, n_base;
+    // operator (as in LevelArgs): eps of the tree's boxes (the level-1
+    // boxes' values are read), x index of the boxes
+    const double *eps;
+    const int32_t *bx;
+    int opk;
 };
 
 // wg: workgroup size of the launch (64, 128 or 256 threads; W / N^(D-1)
@@ -154,6 +175,14 @@ template <int D, int N>
 void launch_apply_l(const BoxInfo *info, const double *x, double *out, int64_t nb, hipStream_t st);
 template <int D, int N>
 void launch_restrict_field(const BoxInfo *info, double *f, int64_t b0, int64_t nb, hipStream_t st);
+// the same with the operator's restriction (opk: OPK_CYL weights by volume)
+template <int D, int N>
+void launch_restrict_field_op(const BoxInfo *info, double *f, int64_t b0, int64_t nb, int opk, const int32_t *bx,
+                              double h, hipStream_t st);
+// *flag |= 1 if a cell of a leaf box among the nb boxes from b0 is not
+// positive and finite
+template <int D, int N>
+void launch_check_positive(const BoxInfo *info, const double *f, int64_t nb, int *flag, hipStream_t st);
 template <int D, int N>
 void launch_push_down(const BoxInfo *info, double *f, int64_t b0, int64_t nb, hipStream_t st);
 template <int D, int N>

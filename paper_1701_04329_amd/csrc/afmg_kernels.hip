@@ -1112,6 +1112,559 @@ __global__ __launch_bounds__(W) void k_final(LevelArgs<T> a, double *partial, in
     }
 }
 
+// ---------------------------------------------------------------------------
+// operators (paper §3.4, §3.5)
+// ---------------------------------------------------------------------------
+// Level kernels of a tree with an operator (LevelArgs::opk != 0; one tree,
+// 256-thread workgroups).  A box is staged in LDS with its side ghosts as in
+// the Laplacian's kernels, and its coefficients eps with their own ghosts:
+// the coefficient of the cell across the side, the face cell's own on a
+// physical side, and on a refinement side that of the coarse cell holding
+// the ghost centre (the jumps lie on coarse-grid faces, paper §3.4).
+
+// left edge (x = r) of box b on a level with cell size h
+template <int N, typename T>
+__device__ __forceinline__ T box_x0(const int32_t *__restrict__ bx, int64_t b, T h) {
+    return T(bx[b] - 1) * T(N) * h;
+}
+
+// sum over the 2D sides of w_s u_s, and in dg the sum of the w_s, for cell
+// (i, j, k); s and se are the padded box and its coefficients in LDS
+template <int D, int N, typename T>
+__device__ __forceinline__ T op_sum(const T *s, const T *se, int i, int j, int k, int opk, T x0, T h, T &dg) {
+    int nb[6];
+    nb[0] = padi<D, N>(i - 1, j, k);
+    nb[1] = padi<D, N>(i + 1, j, k);
+    nb[2] = padi<D, N>(i, j - 1, k);
+    nb[3] = padi<D, N>(i, j + 1, k);
+    nb[4] = padi<D, N>(i, j, k - 1);
+    nb[5] = padi<D, N>(i, j, k + 1);
+    const bool eps = opk & OPK_EPS, cyl = opk & OPK_CYL;
+    const T ec = eps ? se[padi<D, N>(i, j, k)] : T(1);
+    const T rc = x0 + (T(i) + T(0.5)) * h;
+    T sum = T(0), d = T(0);
+#pragma unroll
+    for (int q = 0; q < 2 * D; q++) {
+        T w = T(1);
+        if (eps) {
+            const T en = se[nb[q]];
+            w = T(2) * ec * en / (ec + en);
+        }
+        if (cyl && q < 2) w *= (x0 + T(i + q) * h) / rc;
+        sum += w * s[nb[q]];
+        d += w;
+    }
+    dg = d;
+    return sum;
+}
+
+// h^2 (L u) at cell (i, j, k)
+template <int D, int N, typename T>
+__device__ __forceinline__ T op_h2(const T *s, const T *se, int i, int j, int k, int opk, T x0, T h) {
+    T dg;
+    const T sm = op_sum<D, N, T>(s, se, i, j, k, opk, x0, h, dg);
+    return sm - dg * s[padi<D, N>(i, j, k)];
+}
+
+// restriction weight of fine cell column i (0-based in the box): 1, or the
+// radius of its centre for the cylindrical form
+template <typename T>
+__device__ __forceinline__ T vol_w(bool cyl, T x0, T h, int i) {
+    return cyl ? x0 + (T(i) + T(0.5)) * h : T(1);
+}
+
+// Side ghosts of the coefficients (copy rules above); load / stage / end as
+// in Stager.
+template <int D, int N, typename T>
+struct EpsStager {
+    using G = Geo<D, N>;
+    T raw[6];
+    int v[6];
+    T rowv[2][G::HN];
+    __device__ __forceinline__ void load(const BoxInfo &bi, const T *__restrict__ eb, const T *__restrict__ e,
+                                         int t) {
+#pragma unroll
+        for (int c = 0; c < 2; c++)
+#pragma unroll
+            for (int m = 0; m < G::HN; m++) rowv[c][m] = eb[c * G::HALF + t * G::HN + m];
+        // a physical side reads an in-range value of box 0 and ignores it
+        raw[0] = ghost_raw<D, N, 0, T>(bi, t, e, nullptr, 1, v[0]);
+        raw[1] = ghost_raw<D, N, 1, T>(bi, t, e, nullptr, 1, v[1]);
+        raw[2] = ghost_raw<D, N, 2, T>(bi, t, e, nullptr, 1, v[2]);
+        raw[3] = ghost_raw<D, N, 3, T>(bi, t, e, nullptr, 1, v[3]);
+        if (D == 3) {
+            raw[4] = ghost_raw<D, N, 4, T>(bi, t, e, nullptr, 1, v[4]);
+            raw[5] = ghost_raw<D, N, 5, T>(bi, t, e, nullptr, 1, v[5]);
+        }
+    }
+    __device__ __forceinline__ void stage(T *s, int t) const {
+        int j, k;
+        row_of<D, N>(t, j, k);
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+            const int p = (c + D + j + k) & 1;
+#pragma unroll
+            for (int m = 0; m < G::HN; m++) s[padi<D, N>(2 * m + p, j, k)] = rowv[c][m];
+        }
+    }
+    template <int S>
+    __device__ __forceinline__ void end1(T *s, int t) const {
+        int x[3];
+        face_cell<D, N, S>(t, x);
+        s[ghost_slot<D, N, S>(t)] = v[S] == -1 ? s[padi<D, N>(x[0], x[1], x[2])] : raw[S];
+    }
+    __device__ void end(T *s, int t) const {
+        end1<0>(s, t);
+        end1<1>(s, t);
+        end1<2>(s, t);
+        end1<3>(s, t);
+        if (D == 3) {
+            end1<4>(s, t);
+            end1<5>(s, t);
+        }
+    }
+};
+
+// Gauss-Seidel red-black half sweep (paper §3.1) with the operator: each
+// cell of `colour` solves its own equation with the neighbours and ghosts
+// of the old state, u_c = (sum w_s u_s - h^2 rho_c) / sum w_s.  The whole
+// box is staged; the cells written are the updated colour, which no ghost of
+// an updated cell reads (its neighbours across sides are the other colour).
+template <int D, int N, typename T>
+__global__ __launch_bounds__(256) void k_vgsrb(LevelArgs<T> a, int colour) {
+    using G = Geo<D, N>;
+    constexpr int HN = G::HN;
+    __shared__ T sm[G::BPW * G::PC];
+    __shared__ T sme[G::BPW * G::PC];
+    const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb, a.no_remap == 0);
+    T *s = sm + sl.slot * G::PC, *se = sme + sl.slot * G::PC;
+    const BoxInfo bi = load_box<D, N>(a.info, sl.b);
+    const size_t bo = (size_t)sl.b * G::C;
+    const int r = sl.t;
+    int j, k;
+    row_of<D, N>(r, j, k);
+    const int p = (colour + D + j + k) & 1;
+    const int own0 = colour * G::HALF + r * HN;
+    const bool act = sl.valid, eps = a.opk & OPK_EPS;
+    T rr[HN];
+    Stager<D, N, T> st;
+    EpsStager<D, N, T> es;
+    // padding slots (sl.b clamped to a valid box) load too
+#pragma unroll
+    for (int m = 0; m < HN; m++) rr[m] = a.rho[bo + own0 + m];
+    st.load(bi, a.u + bo, a.u, a.bc, a.homog, r, true, a.h);
+    if (eps) es.load(bi, a.eps + bo, a.eps, r);
+    st.stage(s, r);
+    if (eps) es.stage(se, r);
+    __syncthreads();
+    if (act) {
+        st.end(s, r);
+        if (eps) es.end(se, r);
+    }
+    __syncthreads();
+    if (!act) return;
+    const T x0 = (a.opk & OPK_CYL) ? box_x0<N, T>(a.bx, sl.b, a.h) : T(0);
+    T out[HN];
+#pragma unroll
+    for (int m = 0; m < HN; m++) {
+        T dg;
+        const T sum = op_sum<D, N, T>(s, se, 2 * m + p, j, k, a.opk, x0, a.h, dg);
+        out[m] = (sum - a.h2 * rr[m]) / dg;
+    }
+#pragma unroll
+    for (int m = 0; m < HN; m++) a.u[bo + own0 + m] = out[m];
+}
+
+// residual r = rho - L u on the boxes of level l; the parent's octant
+// receives the means of u and of r (volume means in the cylindrical form)
+template <int D, int N, typename T>
+__global__ __launch_bounds__(256) void k_vresid_restrict(LevelArgs<T> a) {
+    using G = Geo<D, N>;
+    __shared__ T sm[G::BPW * G::PC];
+    __shared__ T sme[G::BPW * G::PC];
+    const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb, a.no_remap == 0);
+    T *s = sm + sl.slot * G::PC, *se = sme + sl.slot * G::PC;
+    const BoxInfo bi = load_box<D, N>(a.info, sl.b);
+    const size_t bo = (size_t)sl.b * G::C;
+    constexpr int NPC = G::HC / G::TPB, NB = D == 3 ? 8 : 4;
+    const bool act = sl.valid, eps = a.opk & OPK_EPS, cyl = a.opk & OPK_CYL;
+    T rf[NPC][NB];
+    Stager<D, N, T> st;
+    EpsStager<D, N, T> es;
+#pragma unroll
+    for (int it = 0; it < NPC; it++)
+#pragma unroll
+        for (int q = 0; q < NB; q++) {
+            int i, j, k;
+            block_cell<D, N>(sl.t + it * G::TPB, q, i, j, k);
+            rf[it][q] = a.rho[bo + cpos<D, N>(i, j, k)];
+        }
+    st.load(bi, a.u + bo, a.u, a.bc, a.homog, sl.t, true, a.h);
+    if (eps) es.load(bi, a.eps + bo, a.eps, sl.t);
+    st.stage(s, sl.t);
+    if (eps) es.stage(se, sl.t);
+    __syncthreads();
+    if (act) {
+        st.end(s, sl.t);
+        if (eps) es.end(se, sl.t);
+    }
+    __syncthreads();
+    if (!act) return;
+    const T x0 = cyl ? box_x0<N, T>(a.bx, sl.b, a.h) : T(0);
+    const T w = D == 3 ? T(0.125) : T(0.25);
+    const int flags = bi.flags;
+    const int64_t p = bi.parent;
+#pragma unroll
+    for (int it = 0; it < NPC; it++) {
+        const int pc = sl.t + it * G::TPB;
+        const int I = pc % G::H, J = (pc / G::H) % G::H, K = D == 3 ? pc / (G::H * G::H) : 0;
+        T su = T(0), sr = T(0), vol = T(0);
+#pragma unroll
+        for (int q = 0; q < NB; q++) {
+            int i, j, k;
+            block_cell<D, N>(pc, q, i, j, k);
+            const T uc = s[padi<D, N>(i, j, k)];
+            const T res = rf[it][q] - op_h2<D, N, T>(s, se, i, j, k, a.opk, x0, a.h) * a.ih2;
+            const T wq = vol_w<T>(cyl, x0, a.h, i);
+            su += cyl ? wq * uc : uc;
+            sr += cyl ? wq * res : res;
+            vol += wq;
+        }
+        const int X = obit(flags, 0) * G::H + I, Y = obit(flags, 1) * G::H + J,
+                  Z = D == 3 ? obit(flags, 2) * G::H + K : 0;
+        const size_t o = (size_t)p * G::C + cpos<D, N>(X, Y, Z);
+        a.u[o] = cyl ? su / vol : w * su;
+        a.rho[o] = cyl ? sr / vol : w * sr;
+    }
+}
+
+// boxes of level l-1: uold <- u; on parents rho <- rbar + L_H u
+template <int D, int N, typename T>
+__global__ __launch_bounds__(256) void k_vcoarse_rhs(LevelArgs<T> a) {
+    using G = Geo<D, N>;
+    __shared__ T sm[G::BPW * G::PC];
+    __shared__ T sme[G::BPW * G::PC];
+    const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb, a.no_remap == 0);
+    T *s = sm + sl.slot * G::PC, *se = sme + sl.slot * G::PC;
+    const BoxInfo bi = load_box<D, N>(a.info, sl.b);
+    const size_t bo = (size_t)sl.b * G::C;
+    const bool parent = !(bi.flags & FLAG_LEAF);
+    const bool act = sl.valid, eps = (a.opk & OPK_EPS) && parent;
+    constexpr int NE = G::C / G::TPB;
+    T rf[NE];
+    Stager<D, N, T> st;
+    EpsStager<D, N, T> es;
+    st.load(bi, a.u + bo, a.u, a.bc, a.homog, sl.t, parent, a.h);
+    if (parent) {
+#pragma unroll
+        for (int it = 0; it < NE; it++) rf[it] = a.rho[bo + sl.t + it * G::TPB];
+    }
+    if (eps) es.load(bi, a.eps + bo, a.eps, sl.t);
+    st.stage(s, sl.t);
+    if (eps) es.stage(se, sl.t);
+    __syncthreads();
+    if (act) {
+        for (int e = sl.t; e < G::C; e += G::TPB) {
+            int i, j, k;
+            cell_of<D, N>(e, i, j, k);
+            a.uold[bo + e] = s[padi<D, N>(i, j, k)];
+        }
+    }
+    if (act && parent) {
+        st.end(s, sl.t);
+        if (eps) es.end(se, sl.t);
+    }
+    __syncthreads();
+    if (!act || !parent) return;
+    const T x0 = (a.opk & OPK_CYL) ? box_x0<N, T>(a.bx, sl.b, a.h) : T(0);
+#pragma unroll
+    for (int it = 0; it < NE; it++) {
+        const int e = sl.t + it * G::TPB;
+        int i, j, k;
+        cell_of<D, N>(e, i, j, k);
+        a.rho[bo + e] = rf[it] + op_h2<D, N, T>(s, se, i, j, k, a.opk, x0, a.h) * a.ih2;
+    }
+}
+
+// end of a cycle with the operator: the parent's octant receives the mean of
+// u (volume mean in the cylindrical form); on leaves r = rho - L u and its
+// (max |r|, sum r^2 h^D) per workgroup at partial[part0 + workgroup]
+template <int D, int N, typename T>
+__global__ __launch_bounds__(256) void k_vfinal(LevelArgs<T> a, double *partial, int64_t part0, double hD) {
+    using G = Geo<D, N>;
+    constexpr int NW = 256 / 64;
+    __shared__ T sm[G::BPW * G::PC];
+    __shared__ T sme[G::BPW * G::PC];
+    __shared__ double red_m[NW], red_s[NW];
+    const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb, a.no_remap == 0);
+    T *s = sm + sl.slot * G::PC, *se = sme + sl.slot * G::PC;
+    const BoxInfo bi = load_box<D, N>(a.info, sl.b);
+    const size_t bo = (size_t)sl.b * G::C;
+    const bool leaf = bi.flags & FLAG_LEAF;
+    const bool act = sl.valid, eps = (a.opk & OPK_EPS) && leaf, cyl = a.opk & OPK_CYL;
+    constexpr int NPC = G::HC / G::TPB, NB = D == 3 ? 8 : 4;
+    T rf[NPC][NB];
+    Stager<D, N, T> st;
+    EpsStager<D, N, T> es;
+    st.load(bi, a.u + bo, a.u, a.bc, a.homog, sl.t, leaf, a.h);
+    if (leaf) {
+#pragma unroll
+        for (int it = 0; it < NPC; it++)
+#pragma unroll
+            for (int q = 0; q < NB; q++) {
+                int i, j, k;
+                block_cell<D, N>(sl.t + it * G::TPB, q, i, j, k);
+                rf[it][q] = a.rho[bo + cpos<D, N>(i, j, k)];
+            }
+    }
+    if (eps) es.load(bi, a.eps + bo, a.eps, sl.t);
+    st.stage(s, sl.t);
+    if (eps) es.stage(se, sl.t);
+    __syncthreads();
+    if (act && leaf) {
+        st.end(s, sl.t);
+        if (eps) es.end(se, sl.t);
+    }
+    __syncthreads();
+    double mx = 0.0, ss = 0.0;
+    if (act) {
+        const T x0 = cyl ? box_x0<N, T>(a.bx, sl.b, a.h) : T(0);
+        const T w = D == 3 ? T(0.125) : T(0.25);
+        const int flags = bi.flags;
+        const int64_t p = bi.parent;
+#pragma unroll
+        for (int it = 0; it < NPC; it++) {
+            const int pc = sl.t + it * G::TPB;
+            const int I = pc % G::H, J = (pc / G::H) % G::H, K = D == 3 ? pc / (G::H * G::H) : 0;
+            T su = T(0), vol = T(0);
+#pragma unroll
+            for (int q = 0; q < NB; q++) {
+                int i, j, k;
+                block_cell<D, N>(pc, q, i, j, k);
+                const T uc = s[padi<D, N>(i, j, k)];
+                const T wq = vol_w<T>(cyl, x0, a.h, i);
+                su += cyl ? wq * uc : uc;
+                vol += wq;
+                if (leaf) {
+                    const double r = (double)(rf[it][q] - op_h2<D, N, T>(s, se, i, j, k, a.opk, x0, a.h) * a.ih2);
+                    mx = fmax(mx, fabs(r));
+                    ss += r * r;
+                }
+            }
+            if (p >= 0) {
+                const int X = obit(flags, 0) * G::H + I, Y = obit(flags, 1) * G::H + J,
+                          Z = D == 3 ? obit(flags, 2) * G::H + K : 0;
+                a.u[(size_t)p * G::C + cpos<D, N>(X, Y, Z)] = cyl ? su / vol : w * su;
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        mx = fmax(mx, __shfl_xor(mx, o));
+        ss += __shfl_xor(ss, o);
+    }
+    const int wave = (int)threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0) {
+        red_m[wave] = mx;
+        red_s[wave] = ss;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red_m[0], t = red_s[0];
+        for (int q = 1; q < NW; q++) {
+            m = fmax(m, red_m[q]);
+            t += red_s[q];
+        }
+        partial[2 * (part0 + blockIdx.x) + 0] = m;
+        partial[2 * (part0 + blockIdx.x) + 1] = t * hD;
+    }
+}
+
+// coarse-grid correction with the eps-weighted prolongation: along each
+// axis d the fine cell lies a quarter coarse cell from its coarse cell P
+// towards P + s_d e_d; the piecewise-linear profile that is continuous in
+// value and in flux eps du/dx across the face between them (the local
+// reconstruction of paper §3.4) gives
+//   u += d(P) + sum_d eps_d / (2 (eps_P + eps_d)) (d(P + s_d e_d) - d(P)),
+// d = u - uold of the parent level; with equal eps this is the default
+// interpolation.  The coefficients of the parent's octant and its halo are
+// staged beside the deltas, with the copy rules of the coefficient ghosts.
+template <int D, int N, typename T>
+__global__ __launch_bounds__(256) void k_vprolong(LevelArgs<T> a) {
+    using G = Geo<D, N>;
+    constexpr int NH = (2 * D * G::HF + G::TPB - 1) / G::TPB;
+    constexpr int NO = G::HC / G::TPB;
+    constexpr int NE = G::C / G::TPB;
+    __shared__ T qs[G::BPW * G::QC];
+    __shared__ T qes[G::BPW * G::QC];
+    const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb, a.no_remap == 0);
+    T *q = qs + sl.slot * G::QC, *qe = qes + sl.slot * G::QC;
+    const BoxInfo bi = load_box<D, N>(a.info, sl.b);
+    const size_t bo = (size_t)sl.b * G::C;
+    const bool act = sl.valid;
+    T raw[NH], rawe[NH], uf[NE];
+    int hv[NH], hs[NH];
+#pragma unroll
+    for (int it = 0; it < NE; it++) uf[it] = a.u[bo + sl.t + it * G::TPB];
+    const int flags = bi.flags;
+    const int o[3] = {obit(flags, 0) * G::H, obit(flags, 1) * G::H, D == 3 ? obit(flags, 2) * G::H : 0};
+    const int64_t p = bi.parent;
+    const BoxInfo pi = load_box<D, N>(a.info, p);
+    const int pfl = pi.flags;
+    {
+        T od[NO], oe[NO];
+#pragma unroll
+        for (int it = 0; it < NO; it++) {
+            const int pc = sl.t + it * G::TPB;
+            const int I = pc % G::H, J = (pc / G::H) % G::H, K = D == 3 ? pc / (G::H * G::H) : 0;
+            const size_t oo = (size_t)p * G::C + cpos<D, N>(o[0] + I, o[1] + J, o[2] + K);
+            od[it] = a.u[oo] - a.uold[oo];
+            oe[it] = a.eps[oo];
+        }
+#pragma unroll
+        for (int h = 0; h < NH; h++) {
+            const int hc = sl.t + h * G::TPB;
+            size_t ho = (size_t)p * G::C;
+            hv[h] = 0;
+            hs[h] = 0;
+            if (hc < 2 * D * G::HF) {
+                const int side = hc / G::HF, m = hc % G::HF;
+#define AFMG_H1(S) ho = halo_addr<D, N, S>(m, o, pi, p, hv[h], hs[h])
+                AFMG_SIDE_SWITCH(side, AFMG_H1)
+#undef AFMG_H1
+            }
+            raw[h] = a.u[ho] - a.uold[ho];
+            rawe[h] = a.eps[ho];
+        }
+#pragma unroll
+        for (int it = 0; it < NO; it++) {
+            const int pc = sl.t + it * G::TPB;
+            const int I = pc % G::H, J = (pc / G::H) % G::H, K = D == 3 ? pc / (G::H * G::H) : 0;
+            q[qpad<D, N>(I, J, K)] = od[it];
+            qe[qpad<D, N>(I, J, K)] = oe[it];
+        }
+#pragma unroll
+        for (int h = 0; h < NH; h++)
+            if (sl.t + h * G::TPB < 2 * D * G::HF) {
+                if (hv[h] >= 0) q[hs[h]] = raw[h];
+                if (hv[h] != -1) qe[hs[h]] = rawe[h];
+            }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+        for (int h = 0; h < NH; h++) {
+            const int hc = sl.t + h * G::TPB;
+            if (hc < 2 * D * G::HF && hv[h] < 0) {
+                const int side = hc / G::HF, m = hc % G::HF;
+#define AFMG_H2(S) halo_phase2<D, N, S, T>(q, m, o, raw[h], hv[h], pfl)
+                AFMG_SIDE_SWITCH(side, AFMG_H2)
+#undef AFMG_H2
+                if (hv[h] == -1) {
+                    // physical side of the parent: the face cell's own coefficient
+                    int L[3], X[3];
+#define AFMG_H3(S)                                          \
+    {                                                       \
+        halo_cell<D, N, S>(m, o, L, X);                     \
+        int f[3] = {L[0], L[1], L[2]};                      \
+        f[SideOf<S>::d] = SideOf<S>::hi ? L[SideOf<S>::d] - 1 : 0; \
+        qe[qpad<D, N>(L[0], L[1], L[2])] = qe[qpad<D, N>(f[0], f[1], f[2])]; \
+    }
+                    AFMG_SIDE_SWITCH(side, AFMG_H3)
+#undef AFMG_H3
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (!act) return;
+#pragma unroll
+    for (int it = 0; it < NE; it++) {
+        const int e = sl.t + it * G::TPB;
+        int i, j, k;
+        cell_of<D, N>(e, i, j, k);
+        const int P[3] = {i >> 1, j >> 1, k >> 1};
+        const int sg[3] = {(i & 1) ? 1 : -1, (j & 1) ? 1 : -1, (k & 1) ? 1 : -1};
+        const T d0 = q[qpad<D, N>(P[0], P[1], P[2])], e0 = qe[qpad<D, N>(P[0], P[1], P[2])];
+        T v = d0;
+#pragma unroll
+        for (int d = 0; d < D; d++) {
+            int Q[3] = {P[0], P[1], P[2]};
+            Q[d] += sg[d];
+            const int qi = qpad<D, N>(Q[0], Q[1], Q[2]);
+            const T ed = qe[qi];
+            v += ed / (T(2) * (e0 + ed)) * (q[qi] - d0);
+        }
+        a.u[bo + e] = uf[it] + v;
+    }
+}
+
+// FMG / end of a solve: the parent's octant of field f receives the mean of
+// the box's values, a volume mean in the cylindrical form
+template <int D, int N, typename T>
+__device__ __forceinline__ void restrict_octant_op(const T *s, T *__restrict__ dst, const BoxInfo &bi, int t,
+                                                   bool cyl, T x0, T h) {
+    using G = Geo<D, N>;
+    const T w = D == 3 ? T(0.125) : T(0.25);
+    const int flags = bi.flags;
+    const int64_t p = bi.parent;
+    for (int pc = t; pc < G::HC; pc += G::TPB) {
+        const int I = pc % G::H, J = (pc / G::H) % G::H, K = D == 3 ? pc / (G::H * G::H) : 0;
+        T acc = T(0), vol = T(0);
+#pragma unroll
+        for (int dk = 0; dk < (D == 3 ? 2 : 1); dk++)
+#pragma unroll
+            for (int dj = 0; dj < 2; dj++)
+#pragma unroll
+                for (int di = 0; di < 2; di++) {
+                    const int i = 2 * I + di, j = 2 * J + dj, k = D == 3 ? 2 * K + dk : 0;
+                    const T f = s[D == 3 ? i + N * (j + N * k) : i + N * j];
+                    const T wq = vol_w<T>(cyl, x0, h, i);
+                    acc += cyl ? wq * f : f;
+                    vol += wq;
+                }
+        const int X = obit(flags, 0) * G::H + I, Y = obit(flags, 1) * G::H + J,
+                  Z = D == 3 ? obit(flags, 2) * G::H + K : 0;
+        dst[(size_t)p * G::C + cpos<D, N>(X, Y, Z)] = cyl ? acc / vol : w * acc;
+    }
+}
+
+template <int D, int N, typename T>
+__global__ __launch_bounds__(256) void k_vrestrict(const BoxInfo *__restrict__ info, T *f, int64_t b0, int nb,
+                                                   int opk, const int32_t *__restrict__ bx, T h) {
+    using G = Geo<D, N>;
+    __shared__ T sm[G::BPW * G::C];
+    const Slot<D, N> sl = slot_of<D, N>(b0, nb);
+    T *s = sm + sl.slot * G::C;
+    const BoxInfo bi = load_box<D, N>(info, sl.b);
+    const size_t bo = (size_t)sl.b * G::C;
+    if (sl.valid) {
+        for (int e = sl.t; e < G::C; e += G::TPB) {
+            int i, j, k;
+            cell_of<D, N>(e, i, j, k);
+            s[D == 3 ? i + N * (j + N * k) : i + N * j] = f[bo + e];
+        }
+    }
+    __syncthreads();
+    const bool cyl = opk & OPK_CYL;
+    if (sl.valid) restrict_octant_op<D, N, T>(s, f, bi, sl.t, cyl, cyl ? box_x0<N, T>(bx, sl.b, h) : T(0), h);
+}
+
+// *flag |= 1 for a leaf cell that is not positive and finite
+template <int D, int N>
+__global__ __launch_bounds__(256) void k_check_positive(const BoxInfo *__restrict__ info,
+                                                        const double *__restrict__ f, int nb, int *flag) {
+    using G = Geo<D, N>;
+    const Slot<D, N> sl = slot_of<D, N>(0, nb, false);
+    if (!sl.valid) return;
+    if (!(info[sl.b].flags & FLAG_LEAF)) return;
+    int bad = 0;
+    for (int e = sl.t; e < G::C; e += G::TPB) {
+        const double x = f[(size_t)sl.b * G::C + e];
+        bad |= !(x > 0.0 && x <= 1.7976931348623157e308);
+    }
+    if (bad) atomicOr(flag, 1);
+}
+
 // One workgroup of 1024 threads: out[0] = max of the partial maxima, out[1] =
 // sqrt of the sum of the partial sums; the reduction order is fixed.
 __global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ partial, int64_t n, double *out,
@@ -2086,6 +2639,9 @@ struct GenState {
     const BoxInfo *info;
     double *U, *RHO, *UOLD, *RES, *BC;  // [root][TOT] each, BC [root][BTOT]
     int R, homog, n_down, n_up, n_base;
+    double *E;             // coefficients [root][TOT] (OPK_EPS)
+    const int32_t *bx;     // x index of the boxes (roots first)
+    int opk;               // operator (OPK_* bits)
 
     __device__ static double hgrid(int g) { return (double)(1 << g) / (double)N; }
     __device__ double *at(double *f, int r, int g) const { return f + (size_t)r * GG::TOT + GG::off(g); }
@@ -2120,6 +2676,72 @@ struct GenState {
         if (D == 3) sum = sum + (across(f, r, g, 4, i, j, k) + across(f, r, g, 5, i, j, k));
         return sum;
     }
+    // coefficient across side s of cell (i, j, k): the cell there, or the
+    // cell's own on a physical side
+    __device__ double eacross(int r, int g, int s, int i, int j, int k) const {
+        const int n = GG::n(g), d = s >> 1, hi = s & 1;
+        int x[3] = {i, j, k};
+        x[d] += hi ? 1 : -1;
+        const double *f = E + GG::off(g);
+        if (x[d] >= 0 && x[d] < n) return f[(size_t)r * GG::TOT + cidx(n, x[0], x[1], x[2])];
+        const int v = info[r].nbr[s];
+        if (v >= 0) {
+            x[d] = hi ? 0 : n - 1;
+            return f[(size_t)v * GG::TOT + cidx(n, x[0], x[1], x[2])];
+        }
+        return f[(size_t)r * GG::TOT + cidx(n, i, j, k)];
+    }
+    // left edge (x = r) of root r's box on grid g (its grids cover one unit)
+    __device__ double x0(int r, int g) const { return (double)(bx[r] - 1) * (double)GG::n(g) * hgrid(g); }
+    // with the operator: sum over the sides of w_s f_s, dg = sum of w_s
+    __device__ double osum(const double *f, int r, int g, int i, int j, int k, double &dg) const {
+        const double h = hgrid(g);
+        const bool eps = opk & OPK_EPS, cyl = opk & OPK_CYL;
+        const double ec = eps ? at(E, r, g)[cidx(GG::n(g), i, j, k)] : 1.0;
+        const double xl = cyl ? x0(r, g) : 0.0;
+        const double rc = xl + (i + 0.5) * h;
+        double sum = 0.0, d = 0.0;
+        for (int s = 0; s < 2 * D; s++) {
+            double w = 1.0;
+            if (eps) {
+                const double en = eacross(r, g, s, i, j, k);
+                w = 2.0 * ec * en / (ec + en);
+            }
+            if (cyl && s < 2) w *= (xl + (i + s) * h) / rc;
+            sum += w * across(f, r, g, s, i, j, k);
+            d += w;
+        }
+        dg = d;
+        return sum;
+    }
+    // h^2 (L f) at cell (i, j, k) of grid g
+    __device__ double oph2(const double *f, int r, int g, int i, int j, int k) const {
+        const double uc = at(const_cast<double *>(f), r, g)[cidx(GG::n(g), i, j, k)];
+        if (!opk) return nbs(f, r, g, i, j, k) - double(2 * D) * uc;
+        double dg;
+        const double sm = osum(f, r, g, i, j, k, dg);
+        return sm - dg * uc;
+    }
+    // restriction weight of column i of grid g (volume in the cylindrical form)
+    __device__ double rw(int r, int g, int i) const {
+        return (opk & OPK_CYL) ? x0(r, g) + (i + 0.5) * hgrid(g) : 1.0;
+    }
+    // mean of the 2^D block under coarse cell (I, J, K) of grid g+1 for field f
+    __device__ double block_mean(const double *f, int r, int g, int I, int J, int K) const {
+        const int n = GG::n(g);
+        const bool cyl = opk & OPK_CYL;
+        double acc = 0.0, vol = 0.0;
+        for (int dk = 0; dk < (D == 3 ? 2 : 1); dk++)
+            for (int dj = 0; dj < 2; dj++)
+                for (int di = 0; di < 2; di++) {
+                    const int i = 2 * I + di;
+                    const double v = at(const_cast<double *>(f), r, g)[cidx(n, i, 2 * J + dj, D == 3 ? 2 * K + dk : 0)];
+                    const double wq = rw(r, g, i);
+                    acc += cyl ? wq * v : v;
+                    vol += wq;
+                }
+        return cyl ? acc / vol : (D == 3 ? 0.125 : 0.25) * acc;
+    }
     __device__ static void ijk(int n, int c, int &i, int &j, int &k) {
         i = c % n;
         j = (c / n) % n;
@@ -2134,7 +2756,14 @@ struct GenState {
             const int row = q / hn, j = row % n, k = D == 3 ? row / n : 0;
             const int i = 2 * (q % hn) + ((colour + j + k + D) & 1);
             const int c = cidx(n, i, j, k);
-            const double v = (nbs(U, r, g, i, j, k) - h2 * at(RHO, r, g)[c]) / double(2 * D);
+            double v;
+            if (opk) {
+                double dg;
+                const double sm = osum(U, r, g, i, j, k, dg);
+                v = (sm - h2 * at(RHO, r, g)[c]) / dg;
+            } else {
+                v = (nbs(U, r, g, i, j, k) - h2 * at(RHO, r, g)[c]) / double(2 * D);
+            }
             at(U, r, g)[c] = v;
         }
         __syncthreads();
@@ -2154,18 +2783,22 @@ struct GenState {
             const int r = e / NC, C = e % NC;
             int I, J, K;
             ijk(nc, C, I, J, K);
-            double au = 0.0, ar = 0.0;
+            double au = 0.0, ar = 0.0, vol = 0.0;
+            const bool cyl = opk & OPK_CYL;
             for (int dk = 0; dk < (D == 3 ? 2 : 1); dk++)
                 for (int dj = 0; dj < 2; dj++)
                     for (int di = 0; di < 2; di++) {
                         const int i = 2 * I + di, j = 2 * J + dj, k = D == 3 ? 2 * K + dk : 0;
                         const int c = cidx(n, i, j, k);
                         const double uc = at(U, r, g)[c];
-                        au += uc;
-                        ar += at(RHO, r, g)[c] - (nbs(U, r, g, i, j, k) - double(2 * D) * uc) * ih2;
+                        const double res = at(RHO, r, g)[c] - oph2(U, r, g, i, j, k) * ih2;
+                        const double wq = rw(r, g, i);
+                        au += cyl ? wq * uc : uc;
+                        ar += cyl ? wq * res : res;
+                        vol += wq;
                     }
-            at(U, r, g + 1)[C] = w * au;
-            at(RES, r, g + 1)[C] = w * ar;
+            at(U, r, g + 1)[C] = cyl ? au / vol : w * au;
+            at(RES, r, g + 1)[C] = cyl ? ar / vol : w * ar;
         }
         __syncthreads();
     }
@@ -2177,6 +2810,10 @@ struct GenState {
             const int r = e / NC, C = e % NC;
             int I, J, K;
             ijk(nc, C, I, J, K);
+            if (opk & OPK_CYL) {
+                at(RHO, r, g + 1)[C] = block_mean(RHO, r, g, I, J, K);
+                continue;
+            }
             double acc = 0.0;
             for (int dk = 0; dk < (D == 3 ? 2 : 1); dk++)
                 for (int dj = 0; dj < 2; dj++)
@@ -2198,7 +2835,7 @@ struct GenState {
             const double uc = at(U, r, g)[c];
             at(UOLD, r, g)[c] = uc;
             if (all_parents || !(info[r].flags & FLAG_LEAF))
-                at(RHO, r, g)[c] = at(RES, r, g)[c] + (nbs(U, r, g, i, j, k) - double(2 * D) * uc) * ih2;
+                at(RHO, r, g)[c] = at(RES, r, g)[c] + oph2(U, r, g, i, j, k) * ih2;
         }
         __syncthreads();
     }
@@ -2231,7 +2868,21 @@ struct GenState {
             const int I = i >> 1, J = j >> 1, K = k >> 1;
             const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
             double v;
-            if (D == 2)
+            if (opk & OPK_PROLONG_EPS) {
+                // eps-weighted (see k_vprolong)
+                const int nc = GG::n(g + 1);
+                const int sg[3] = {sx, sy, sz};
+                const double d0 = delta(r, g + 1, 0, 0, I, J, K);
+                const double e0 = at(E, r, g + 1)[cidx(nc, I, J, K)];
+                v = d0;
+                for (int d = 0; d < D; d++) {
+                    int Q[3] = {I, J, K};
+                    Q[d] += sg[d];
+                    const double ed = (Q[d] >= 0 && Q[d] < nc) ? at(E, r, g + 1)[cidx(nc, Q[0], Q[1], Q[2])]
+                                                              : eacross(r, g + 1, 2 * d + (sg[d] > 0 ? 1 : 0), I, J, K);
+                    v += ed / (2.0 * (e0 + ed)) * (delta(r, g + 1, d, sg[d], I, J, K) - d0);
+                }
+            } else if (D == 2)
                 v = 0.5 * delta(r, g + 1, 0, 0, I, J, K) + 0.25 * delta(r, g + 1, 0, sx, I, J, K) +
                     0.25 * delta(r, g + 1, 1, sy, I, J, K);
             else
@@ -2282,7 +2933,8 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse_gen(CoarseGenArgs<T> a) {
     double *ws = a.ws;
     GenState<D, N> st{a.info, ws, ws + (size_t)R * GG::TOT, ws + (size_t)2 * R * GG::TOT,
                       ws + (size_t)3 * R * GG::TOT, ws + (size_t)4 * R * GG::TOT, R, a.homog,
-                      a.n_down, a.n_up, a.n_base};
+                      a.n_down, a.n_up, a.n_base,
+                      ws + (size_t)4 * R * GG::TOT + (size_t)R * GG::BTOT, a.bx, a.opk};
     const int mode = a.mode;
     // level 1 from the roots' boxes (colour-split in the tree's arrays), the
     // coarser grids start at zero
@@ -2304,6 +2956,25 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse_gen(CoarseGenArgs<T> a) {
         st.RHO[e] = rho;
         st.RES[e] = res;
         st.UOLD[e] = 0.0;
+        if (a.opk & OPK_EPS) {
+            if (p < G::C) {
+                const int i = p % N, j = (p / N) % N, k = D == 3 ? p / (N * N) : 0;
+                st.E[e] = a.eps[(size_t)r * G::C + cpos<D, N>(i, j, k)];
+            }
+        }
+    }
+    // the coefficients of the coarser grids: means of the finer ones
+    if (a.opk & OPK_EPS) {
+        __syncthreads();
+        for (int g = 0; g + 1 < GG::NG; g++) {
+            const int NC = GG::cells(g + 1), nc = GG::n(g + 1);
+            for (int e = threadIdx.x; e < R * NC; e += blockDim.x) {
+                const int r = e / NC, C = e % NC;
+                const int I = C % nc, J = (C / nc) % nc, K = D == 3 ? C / (nc * nc) : 0;
+                st.at(st.E, r, g + 1)[C] = st.block_mean(st.E, r, g, I, J, K);
+            }
+            __syncthreads();
+        }
     }
     // boundary values: the roots' rows on grid 0, means of the covered
     // values below
@@ -2720,8 +3391,33 @@ static void launch_level_w(Op op, const LevelArgs<T> &a, int colour, hipStream_t
     else launch_level_wf<D, N, T, W, false>(op, a, colour, st);
 }
 
+// trees with an operator: one tree, 256-thread workgroups (FP64 only; the
+// FP32 instantiation launches nothing, the scheduler never asks for it)
+template <int D, int N, typename T>
+static void launch_level_op(Op op, const LevelArgs<T> &a, int colour, hipStream_t st) {
+    if constexpr (sizeof(T) == 8) {
+        const int g = wg_count<D, N, 256>(a.nb);
+        switch (op) {
+        case Op::GSRB: AFMG_LAUNCH((k_vgsrb<D, N, T>), g, st, a, colour); break;
+        case Op::RESID_RESTRICT: AFMG_LAUNCH((k_vresid_restrict<D, N, T>), g, st, a); break;
+        case Op::COARSE_RHS: AFMG_LAUNCH((k_vcoarse_rhs<D, N, T>), g, st, a); break;
+        case Op::PROLONG:
+            if (a.opk & OPK_PROLONG_EPS) AFMG_LAUNCH((k_vprolong<D, N, T>), g, st, a);
+            else AFMG_LAUNCH((k_prolong<D, N, T, 256, false>), g, st, a);
+            break;
+        case Op::RESTRICT_RHO:
+            AFMG_LAUNCH((k_vrestrict<D, N, T>), g, st, a.info, a.rho, a.b0, a.nb, a.opk, a.bx, a.h);
+            break;
+        }
+    }
+}
+
 template <int D, int N, typename T>
 void launch_level(Op op, const LevelArgs<T> &a, int colour, int wg, hipStream_t st) {
+    if (a.opk) {
+        launch_level_op<D, N, T>(op, a, colour, st);
+        return;
+    }
     if (wg == 64) launch_level_w<D, N, T, 64>(op, a, colour, st);
     else if (wg == 128) launch_level_w<D, N, T, 128>(op, a, colour, st);
     else launch_level_w<D, N, T, 256>(op, a, colour, st);
@@ -2738,6 +3434,11 @@ static void launch_final_w(const LevelArgs<T> &a, double *partial, int64_t part0
 template <int D, int N, typename T>
 void launch_final(const LevelArgs<T> &a, double *partial, int64_t part0, double hD, float *rout, int wg,
                   hipStream_t st) {
+    if (a.opk) {
+        if constexpr (sizeof(T) == 8)
+            AFMG_LAUNCH((k_vfinal<D, N, T>), (wg_count<D, N, 256>(a.nb)), st, a, partial, part0, hD);
+        return;
+    }
     if (wg == 64) launch_final_w<D, N, T, 64>(a, partial, part0, hD, rout, st);
     else if (wg == 128) launch_final_w<D, N, T, 128>(a, partial, part0, hD, rout, st);
     else launch_final_w<D, N, T, 256>(a, partial, part0, hD, rout, st);
@@ -2790,8 +3491,18 @@ void launch_coarse_gen(const CoarseGenArgs<T> &a, hipStream_t st) {
     hipLaunchKernelGGL((k_coarse_gen<D, N, T>), dim3(1), dim3(COARSE_NT), 0, st, a);
 }
 template <int D, int N>
+void launch_restrict_field_op(const BoxInfo *info, double *f, int64_t b0, int64_t nb, int opk, const int32_t *bx,
+                              double h, hipStream_t st) {
+    AFMG_LAUNCH((k_vrestrict<D, N, double>), (wg_count<D, N>(nb)), st, info, f, b0, (int)nb, opk, bx, h);
+}
+template <int D, int N>
+void launch_check_positive(const BoxInfo *info, const double *f, int64_t nb, int *flag, hipStream_t st) {
+    AFMG_LAUNCH((k_check_positive<D, N>), (wg_count<D, N>(nb)), st, info, f, (int)nb, flag);
+}
+
+template <int D, int N>
 size_t coarse_gen_doubles(int n_roots) {
-    return (size_t)n_roots * (4 * GenGeo<D, N>::TOT + GenGeo<D, N>::BTOT);
+    return (size_t)n_roots * (5 * GenGeo<D, N>::TOT + GenGeo<D, N>::BTOT);
 }
 
 template <int D, int N, typename T>
@@ -2928,6 +3639,12 @@ template void launch_ir_update<3, 8>(const BoxInfo *, double *, float *, int64_t
 template void launch_copy<float>(const float *, float *, int64_t, hipStream_t);
 template void launch_fill<float>(float *, int64_t, float, hipStream_t);
 template size_t coarse_gen_doubles<2, 8>(int);
+template void launch_restrict_field_op<2, 8>(const BoxInfo *, double *, int64_t, int64_t, int, const int32_t *,
+                                             double, hipStream_t);
+template void launch_restrict_field_op<3, 8>(const BoxInfo *, double *, int64_t, int64_t, int, const int32_t *,
+                                             double, hipStream_t);
+template void launch_check_positive<2, 8>(const BoxInfo *, const double *, int64_t, int *, hipStream_t);
+template void launch_check_positive<3, 8>(const BoxInfo *, const double *, int64_t, int *, hipStream_t);
 template size_t coarse_gen_doubles<3, 8>(int);
 template int final_wgs<2, 8>(int64_t, int);
 template int final_wgs<3, 8>(int64_t, int);
@@ -2935,5 +3652,6 @@ template void launch_bc_derive<2, 8>(const BoxInfo *, int64_t, int64_t, double *
 template void launch_bc_derive<3, 8>(const BoxInfo *, int64_t, int64_t, double *, hipStream_t);
 template void launch_copy<double>(const double *, double *, int64_t, hipStream_t);
 template void launch_fill<double>(double *, int64_t, double, hipStream_t);
+template void launch_fill<int>(int *, int64_t, int, hipStream_t);
 
 }  // namespace afmg

@@ -108,6 +108,14 @@ struct afmg_tree {
     int32_t *d_act = nullptr;             // per level: boxes of the trees still iterating
     int *d_nact = nullptr;                // their count per level
     int64_t user_boxes = 0, user_rows = 0, user_unknowns = 0;
+    // operator (afmg_tree_set_operator): OPK_* bits, the cell coefficients
+    // (colour-split, [n_boxes][N^D] plus a flag word), the x index of every
+    // box, and whether the domain itself needs the general coarse path
+    int opk = 0;
+    double *d_eps = nullptr;
+    int32_t *d_bx = nullptr;
+    int op_kind = 0, op_prolong = 0;
+    int domain_general = -1;  // -1 until the first set_operator
 };
 
 struct afmg_batch {
@@ -307,7 +315,7 @@ void release(afmg_tree *t) {
                     (void *)t->d_tree_lmax, (void *)t->d_tree_leaf_ptr, (void *)t->d_tree_leaf_box,
                     (void *)t->d_box_map, (void *)t->d_row_map, (void *)t->d_tnorm, (void *)t->d_tstop,
                     (void *)t->d_thist, (void *)t->d_ltoff, (void *)t->d_lvloff, (void *)t->d_act,
-                    (void *)t->d_nact})
+                    (void *)t->d_nact, (void *)t->d_eps, (void *)t->d_bx})
         if (p) (void)hipFree(p);
     if (t->h_norm) (void)hipHostFree(t->h_norm);
     if (t->h_active) (void)hipHostFree(t->h_active);
@@ -461,6 +469,9 @@ struct Cycler {
         if (h.general) {
             CoarseGenArgs<T> c{base.info, base.u, base.rho, h.lmax >= 2 ? base.uold : nullptr, bc64, cg,
                                h.n_roots, mode, base.homog, o.n_down, o.n_up, o.n_base};
+            c.eps = t->d_eps;
+            c.bx = t->d_bx;
+            c.opk = t->opk;
             launch_coarse_gen<D, BOX_N, T>(c, st);
             return;
         }
@@ -585,8 +596,13 @@ struct Solver {
     // parents of the levels that the per-cycle finalize skips receive the
     // restriction of the solution (k_final's arithmetic and order)
     void restrict_parents() {
-        for (int l = h.lmin_leaf - 1; l >= 2; l--)
-            launch_restrict_field<D, BOX_N>(t->d_info, base.u, h.lvl_off[(size_t)l], h.level_count(l), st);
+        for (int l = h.lmin_leaf - 1; l >= 2; l--) {
+            if (t->opk)
+                launch_restrict_field_op<D, BOX_N>(t->d_info, base.u, h.lvl_off[(size_t)l], h.level_count(l), t->opk,
+                                                   t->d_bx, level_h(l), st);
+            else
+                launch_restrict_field<D, BOX_N>(t->d_info, base.u, h.lvl_off[(size_t)l], h.level_count(l), st);
+        }
     }
     // the norms in t->h_norm (written there by the reduction kernels, no
     // copy); synchronises the stream
@@ -889,6 +905,9 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
     s.partial = (double *)(ws + L.partial);
     s.base = LevelArgs<double>{t->d_info, uw, rho_i, mixed ? nullptr : (double *)(ws + L.uold), bc_w, 0, 0, 0,
                                0.0, 0.0, t->d_active};
+    s.base.eps = t->d_eps;
+    s.base.bx = t->d_bx;
+    s.base.opk = t->opk;
     const int64_t F = cells_per_face(D), C = cells_per_box(D);
 
     hipEvent_t ev0 = t->span[0], ev1 = t->span[1];
@@ -1278,6 +1297,9 @@ int step(afmg_tree *t, hipStream_t st, int op, int level, int colour, int homog,
     LevelArgs<double> a{t->d_info, u, rho, uold, bc_w, h.lvl_off[(size_t)level], (int)h.level_count(level),
                         homog, 0.0, 0.0, nullptr, 0};
     a.xmask = cube_xmask(h, level);
+    a.eps = t->d_eps;
+    a.bx = t->d_bx;
+    a.opk = t->opk;
     const double hh = level_h(level);
     a.h2 = hh * hh;
     a.ih2 = 1.0 / (hh * hh);
@@ -1291,6 +1313,9 @@ int step(afmg_tree *t, hipStream_t st, int op, int level, int colour, int homog,
         if (h.general) {
             CoarseGenArgs<double> c{t->d_info, u, rho, uold, homog ? nullptr : bc_w, (double *)(ws + L.cg),
                                     h.n_roots, COARSE_V_FROM_2, homog, o.n_down, o.n_up, o.n_base};
+            c.eps = t->d_eps;
+            c.bx = t->d_bx;
+            c.opk = t->opk;
             launch_coarse_gen<D, BOX_N, double>(c, st);
         } else {
             CoarseArgs<double> c{t->d_info, u, rho, uold, homog ? nullptr : bc_w, COARSE_V_FROM_2, homog,
@@ -1438,6 +1463,7 @@ int autotune(afmg_tree *t, hipStream_t st, char *ws) {
 
 int tree_autotune(afmg_tree *t, void *stream, void *workspace, size_t workspace_bytes) {
     if (!t || !workspace) return fail(AFMG_ERR_ARG, "null argument");
+    if (t->opk) return fail(AFMG_ERR_ARG, "the autotuner covers the Laplacian's kernels");
     if (!aligned(workspace, 256)) return fail(AFMG_ERR_ARG, "misaligned array");
     if (workspace_bytes < tune_layout(t).total) return fail(AFMG_ERR_ARG, "workspace too small");
     int rc = bind_device(t);
@@ -1458,6 +1484,8 @@ int get_shape(const afmg_tree *t, int precision, int kind, int level, int *wg, i
 
 int set_shape(afmg_tree *t, int precision, int kind, int level, int wg, int no_remap) {
     if (!t) return fail(AFMG_ERR_ARG, "null argument");
+    if (t->opk && (wg != 256 || no_remap != 0))
+        return fail(AFMG_ERR_ARG, "a tree with an operator set runs the default launch shapes");
     if (precision < -1 || precision > 1 || kind < -1 || kind >= SK_KINDS || level < -1 || level == 0 ||
         level > t->h.lmax || (wg != 64 && wg != 128 && wg != 256) || (no_remap != 0 && no_remap != 1))
         return fail(AFMG_ERR_ARG, "shape out of range");
@@ -1488,6 +1516,26 @@ int scratch_address(int dev, void **out) {
 }
 
 }  // namespace
+
+// The operator's coefficients: the caller's eps (leaf boxes) in the
+// colour-split layout, (volume) means into the parents, and a check that
+// every leaf value is positive and finite.
+template <int D>
+int load_eps(afmg_tree *t, hipStream_t st, const double *eps, int opk, int *flag) {
+    const HostTree &h = t->h;
+    launch_load_rho<D, BOX_N, double>(t->d_info, nullptr, eps, t->d_eps, h.n_boxes, 1, st);
+    for (int l = h.lmax; l >= 2; l--)
+        launch_restrict_field_op<D, BOX_N>(t->d_info, t->d_eps, h.lvl_off[(size_t)l], h.level_count(l), opk, t->d_bx,
+                                           level_h(l), st);
+    launch_fill<int>(flag, 1, 0, st);
+    launch_check_positive<D, BOX_N>(t->d_info, t->d_eps, h.n_boxes, flag, st);
+    int bad = 0;
+    hipError_t e = hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "eps");
+    if (bad) return fail(AFMG_ERR_ARG, "eps must be positive and finite on every leaf cell");
+    return AFMG_OK;
+}
 
 // ---------------------------------------------------------------------------
 // C-ABI
@@ -1572,6 +1620,8 @@ int afmg_tree_info(const afmg_tree *t, afmg_tree_desc *out) {
     for (int d = 0; d < 3; d++) out->ext[d] = h.ext[d];
     for (int s = 0; s < 6; s++) out->bc_type[s] = h.bc_type[s];
     out->singular = h.singular ? 1 : 0;
+    out->op = t->op_kind;
+    out->prolong = t->op_prolong;
     return AFMG_OK;
 }
 
@@ -1626,6 +1676,57 @@ int afmg_tree_refine(const afmg_tree *t, const int32_t *ids, int64_t n, int bala
     }
 }
 
+int afmg_tree_set_operator(afmg_tree *t, void *stream, int op, const double *eps, int prolong) {
+    if (!t) return fail(AFMG_ERR_ARG, "null tree");
+    if (t->forest) return fail(AFMG_ERR_ARG, "not a tree");
+    if (op < AFMG_OPERATOR_LAPLACIAN || op > AFMG_OPERATOR_CYL_EPS) return fail(AFMG_ERR_ARG, "bad operator");
+    if (prolong != AFMG_PROLONG_DEFAULT && prolong != AFMG_PROLONG_EPS) return fail(AFMG_ERR_ARG, "bad prolongation");
+    const bool has_eps = op & AFMG_OPERATOR_EPS;
+    if ((op & AFMG_OPERATOR_CYL) && t->h.dim != 2) return fail(AFMG_ERR_ARG, "the cylindrical form is 2D (r, z)");
+    if (prolong == AFMG_PROLONG_EPS && !has_eps) return fail(AFMG_ERR_ARG, "the eps prolongation needs eps");
+    if (has_eps && !eps) return fail(AFMG_ERR_ARG, "eps is null");
+    if (eps && !aligned(eps, 8)) return fail(AFMG_ERR_ARG, "misaligned array");
+    int rc = bind_device(t);
+    if (rc != AFMG_OK) return rc;
+    HostTree &h = t->h;
+    if (t->domain_general < 0) t->domain_general = h.general ? 1 : 0;
+    const int opk = (has_eps ? OPK_EPS : 0) | ((op & AFMG_OPERATOR_CYL) ? OPK_CYL : 0) |
+                    (prolong == AFMG_PROLONG_EPS ? OPK_PROLONG_EPS : 0);
+    t->rec.drop();  // a recorded cycle holds the old operator's launches
+    t->opk = 0;
+    t->op_kind = 0;
+    t->op_prolong = 0;
+    h.general = t->domain_general != 0;
+    if (opk == 0) return AFMG_OK;
+    const size_t C = (size_t)cells_per_box(h.dim);
+    if (!t->d_bx && (rc = upload(t->d_bx, h.ix, "the box x indices")) != AFMG_OK) return rc;
+    if (!t->d_eps) {
+        // the coefficients, then one word for the check's flag
+        hipError_t e = hipMalloc(&t->d_eps, sizeof(double) * ((size_t)h.n_boxes * C + 1));
+        if (e != hipSuccess) {
+            t->d_eps = nullptr;
+            return fail(AFMG_ERR_OOM, "hipMalloc of the coefficients failed");
+        }
+    }
+    hipStream_t st = (hipStream_t)stream;
+    int *flag = (int *)(t->d_eps + (size_t)h.n_boxes * C);
+    if (has_eps) {
+        rc = h.dim == 3 ? load_eps<3>(t, st, eps, opk, flag) : load_eps<2>(t, st, eps, opk, flag);
+        if (rc != AFMG_OK) return rc;
+    }
+    // the operator's kernels run with the default shapes (one partial per
+    // 256-thread workgroup of the norm kernel)
+    for (auto &pk : t->shapes)
+        for (auto &v : pk) v.assign((size_t)h.lmax + 2, Shape{});
+    compute_partials(t);
+    t->tune_epoch++;
+    h.general = true;
+    t->opk = opk;
+    t->op_kind = op;
+    t->op_prolong = prolong;
+    return AFMG_OK;
+}
+
 int afmg_tree_finalize(afmg_tree *t, void *stream) {
     (void)stream;
     if (!t) return fail(AFMG_ERR_ARG, "null argument");
@@ -1672,6 +1773,7 @@ int afmg_apply(afmg_tree *t, void *stream, int op, const double *x, double *y, v
                size_t workspace_bytes) {
     if (!t || !x || !y || !workspace) return fail(AFMG_ERR_ARG, "null argument");
     if (op != AFMG_OP_L && op != AFMG_OP_LT) return fail(AFMG_ERR_ARG, "bad operator");
+    if (t->opk) return fail(AFMG_ERR_ARG, "afmg_apply covers the Laplacian only");
     if (!aligned(x, 8) || !aligned(y, 8) || !aligned(workspace, 256)) return fail(AFMG_ERR_ARG, "misaligned array");
     if (workspace_bytes < adj_layout(t).total) return fail(AFMG_ERR_ARG, "workspace too small");
     int rc = bind_device(t);
@@ -1691,6 +1793,7 @@ int afmg_adjoint(afmg_tree *t, void *stream, const double *u_bar, double *rho_ba
     if (workspace_bytes < adj_layout(t).total) return fail(AFMG_ERR_ARG, "workspace too small");
     if (t->h.singular)
         return fail(AFMG_ERR_ARG, "afmg_adjoint: without a Dirichlet side the operator is singular");
+    if (t->opk) return fail(AFMG_ERR_ARG, "afmg_adjoint covers the Laplacian only");
     std::memset(stats, 0, sizeof(*stats));
     rc = bind_device(t);
     if (rc != AFMG_OK) return rc;
@@ -1708,6 +1811,8 @@ int afmg_solve(afmg_tree *t, void *stream, const double *rho, const double *bc, 
         return fail(AFMG_ERR_ARG, "misaligned array");
     const WsLayout L = ws_layout(t, opts->precision);
     if (workspace_bytes < L.total) return fail(AFMG_ERR_ARG, "workspace too small");
+    if (t->opk && opts->precision != AFMG_FP64)
+        return fail(AFMG_ERR_ARG, "a tree with an operator set solves in FP64");
     std::memset(stats, 0, sizeof(*stats));
     rc = bind_device(t);
     if (rc != AFMG_OK) return rc;
@@ -1731,6 +1836,8 @@ int afmg_solve_noalloc(afmg_tree *t, void *stream, const double *rho, const doub
                                       " bytes of workspace, more than the " + std::to_string(AFMG_SCRATCH_BYTES) +
                                       " of the scratch array; use afmg_solve with a caller workspace");
     if (t->device < 0) return fail(AFMG_ERR_ARG, "afmg_solve_noalloc: prepare the tree first (afmg_tree_finalize)");
+    if (t->opk && opts->precision != AFMG_FP64)
+        return fail(AFMG_ERR_ARG, "a tree with an operator set solves in FP64");
     int dev = -1;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -1752,6 +1859,7 @@ int afmg_batch_create(afmg_tree *const *trees, int n_trees, afmg_batch **out) {
         if (trees[i]->forest) return fail(AFMG_ERR_ARG, "not a tree");
         if (trees[i]->h.general)
             return fail(AFMG_ERR_ARG, "batches take trees of one level-1 box with Dirichlet sides");
+        if (trees[i]->opk) return fail(AFMG_ERR_ARG, "batches take trees with the Laplacian");
         if (trees[i]->h.dim != trees[0]->h.dim || trees[i]->h.N != trees[0]->h.N)
             return fail(AFMG_ERR_ARG, "trees of one batch must share dim and box_n");
     }
