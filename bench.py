@@ -621,6 +621,98 @@ def paper_ex_bench(args, A, torch, dev, stream):
     return out
 
 
+def operators_bench(args, A, torch, dev, stream):
+    """Variable-coefficient and cylindrical operators (paper §3.4, §3.5).
+
+    * case2: the paper's §4.1 case 2 at its own configuration (cylindrical
+      (r, z), eps = 100 in [0, 0.25]^2, 8^2 boxes, refinement h^2 |rho| / eps
+      > 1e-3 up to level 7, FMG + V(2,2) to a 1e-10 residual reduction),
+      checked against the oracle; latency-bound (about 3.6e4 unknowns).
+    * eps3d: the 256^3 uniform octree of the headline workload with eps =
+      100 in the octant [0, 1/2)^3 (a jump on a coarse-grid face on every
+      level), FMG + V(2,2) to 1e-10 in FP64; roofline of the finest-level
+      half sweep k_vgsrb: 20 B per cell of the level algorithmically (other
+      colour s/2, own rho s/2, own colour written s/2, eps of every cell s;
+      s = 8 B)."""
+    from oracle import oracle as O
+    from paper_1701_04329_amd import workloads as W
+
+    out = {}
+    # --- case 2 ---------------------------------------------------------
+    w = W.case2_workload(lmax=7)
+    tree = A.Tree(2, w.level, w.idx)
+    tree.set_operator("cyl_eps", tree.leaf_to_boxes(torch.tensor(w.eps, device=dev)).contiguous())
+    rho = tree.leaf_to_boxes(torch.tensor(w.rho, device=dev))
+    bc = tree.bc_rows(torch.tensor(w.bc, device=dev))
+    u = torch.zeros_like(rho)
+    work = torch.empty(tree.workspace_bytes(), dtype=torch.uint8, device=dev)
+    c2 = {"workload": "case2_cyl_eps_l7", "unknowns": int(w.n_unknowns), "leaves": int(w.n_leaves),
+          "leaf_levels": sorted(set(int(x) for x in w.level)), "cycle": "FMG + V(2,2)", "tol": 1e-10}
+    for graph in (False, True):
+        def one():
+            return A.solve(tree, rho, bc, u, cycle="FMG", tol=1e-10, workspace=work, stream=stream,
+                           use_guess=False, graph=graph)
+        for _ in range(3):
+            one()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(max(args.steps, 20)):
+            t0 = time.perf_counter()
+            _, st = one()
+            times.append(time.perf_counter() - t0)
+        ms = float(np.median(times)) * 1e3
+        c2["graph" if graph else "eager"] = {"ms_per_solve_median": ms, "value": w.n_unknowns / (ms * 1e-3),
+                                             "unit": "unknowns/s", "cycles": st["cycles"]}
+    h = np.concatenate([[st["r0_max"]], st["hist_max"]])
+    c2["residual_factors"] = [round(float(x), 4) for x in h[1:] / h[:-1]]
+    ug = tree.boxes_to_leaf(u).cpu().numpy()
+    _, stf = A.solve(tree, rho, bc, u, cycle="FMG", fixed_cycles=0, max_cycles=0, workspace=work, stream=stream,
+                     use_guess=False)
+    uf = tree.boxes_to_leaf(u).cpu().numpy()
+    c2["error_after_fmg"] = float(np.abs(uf - w.u_exact).max())
+    c2["discretisation_error"] = float(np.abs(ug - w.u_exact).max())
+    ot = O.Tree(2, w.N, w.level, w.idx)
+    ot.set_operator("cyl_eps", w.eps)
+    t0 = time.perf_counter()
+    uo, so = ot.solve(w.rho, w.bc, cycle="FMG", tol=1e-10)
+    c2["oracle"] = {"ms": (time.perf_counter() - t0) * 1e3, "cycles": so["cycles"], "cores": O.num_threads()}
+    c2["rel_l2_vs_oracle"] = float(np.linalg.norm(ug - uo) / np.linalg.norm(uo))
+    out["case2"] = c2
+    del tree, work
+
+    # --- 3D eps jump on the 256^3 octree -----------------------------------
+    w, _ = make_workload("c2")
+    tree = A.Tree(w.dim, w.level, w.idx)
+    eps_fn = lambda x: np.where(np.all(x < 0.5, axis=-1), 100.0, 1.0)  # noqa: E731
+    eps = W.eps_sampled(eps_fn, w.dim, w.N, w.level, w.idx)
+    tree.set_operator("eps", tree.leaf_to_boxes(torch.tensor(eps, device=dev)).contiguous())
+    del eps
+    rho = tree.leaf_to_boxes(torch.tensor(w.rho, device=dev))
+    bc = tree.bc_rows(torch.tensor(w.bc, device=dev)) if tree.n_bfaces else None
+    u = torch.zeros_like(rho)
+    work = torch.empty(tree.workspace_bytes(), dtype=torch.uint8, device=dev)
+    e3 = {"workload": "c2_3d_uniform_256_eps_jump", "unknowns": int(w.n_unknowns), "cycle": "FMG + V(2,2)",
+          "tol": 1e-10, "eps": "100 in [0, 1/2)^3, 1 elsewhere"}
+    for graph in (False, True):
+        ms, (_, st) = timed_loop(args, torch, lambda: A.solve(
+            tree, rho, bc, u, cycle="FMG", tol=1e-10, workspace=work, stream=stream, use_guess=False, graph=graph))
+        e3["graph" if graph else "eager"] = {"ms_per_step": ms, "value": w.n_unknowns / (ms * 1e-3),
+                                             "unit": "unknowns/s", "cycles": st["cycles"],
+                                             "final_residual_ratio": st["r_max"] / st["r0_max"]}
+    _, stp = A.solve(tree, rho, bc, u, cycle="FMG", tol=1e-10, workspace=work, stream=stream, use_guess=False,
+                     profile=True)
+    n_fine = tree.n_leaves * tree.cells_per_box
+    avg = stp["prof_ms"][0] / max(stp["prof_n"][0], 1)
+    ach = 20.0 * n_fine / (avg * 1e-3) / 1e9
+    e3["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                      "kernel": "k_vgsrb<3,8,double> (finest level, one half sweep)",
+                      "algorithmic_bytes_per_launch": 20.0 * n_fine, "avg_launch_ms": round(avg, 5),
+                      "launches_timed": int(stp["prof_n"][0])}
+    out["eps3d"] = e3
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -648,6 +740,10 @@ def main():
                     help="run only warmup + steps FP64 solves of the workload with the default launch shapes, "
                          "eager (for whole-solve HBM counters)")
     ap.add_argument("--no-c1", action="store_true", help="skip the 2D 128^2 latency-bound workload")
+    ap.add_argument("--no-operators", action="store_true",
+                    help="skip the variable-coefficient / cylindrical operator workloads")
+    ap.add_argument("--operators-only", action="store_true",
+                    help="run only the operator workloads and print their record")
     ap.add_argument("--oracle-worker", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--oracle-full", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--oracle-sample", type=int, default=0, help=argparse.SUPPRESS)
@@ -682,6 +778,9 @@ def main():
 
     if args.batch_only:
         print(json.dumps(batch_bench(args, A, torch, dev, torch.cuda.current_stream(dev))), flush=True)
+        return 0
+    if args.operators_only:
+        print(json.dumps(operators_bench(args, A, torch, dev, torch.cuda.current_stream(dev))), flush=True)
         return 0
 
     if args.solve_only:
@@ -873,6 +972,8 @@ def main():
         out["adjoint"] = adjoint_bench(args, A, torch, dev, stream)
     if not args.no_paper_ex:
         out["paper_ex"] = paper_ex_bench(args, A, torch, dev, stream)
+    if not args.no_operators:
+        out["operators"] = operators_bench(args, A, torch, dev, stream)
     if not args.no_cpu_baseline:
         uo, out["cpu_baseline"] = cpu_baseline(w, solve_kw, args.workload)
         nrm = np.linalg.norm(uo)
