@@ -1669,7 +1669,10 @@ int afmg_tree_refine(const afmg_tree *t, const int32_t *ids, int64_t n, int bala
         std::string msg;
         const int rc = refine_leaves(t->h, ids, n, balance, level, idx, msg);
         if (rc != AFMG_OK) return fail(rc, msg);
-        return afmg_tree_create_domain(t->h.dim, t->h.N, t->h.general ? t->h.bc_type : nullptr,
+        // the domain's own kind (an operator makes the solve take the general
+        // path, but the new tree starts with the Laplacian)
+        const bool general = t->domain_general >= 0 ? t->domain_general != 0 : t->h.general;
+        return afmg_tree_create_domain(t->h.dim, t->h.N, general ? t->h.bc_type : nullptr,
                                        (int64_t)level.size(), level.data(), idx.data(), out);
     } catch (const std::bad_alloc &) {
         return fail(AFMG_ERR_OOM, "host allocation failed");
