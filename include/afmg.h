@@ -268,6 +268,55 @@ int afmg_tree_finalize(afmg_tree *tree, void *stream);
  * afmg_tree_refine returns a tree with the Laplacian.  Setting
  * AFMG_OPERATOR_LAPLACIAN with AFMG_PROLONG_DEFAULT restores the default.
  */
+/*
+ * Mesh adaptation (paper §2.3): a new tree from per-cell flags on the leaves.
+ *   flags   device int8 [n_boxes][N^D] in the layout of rho (x fastest; only
+ *           leaf boxes are read): > 0 refine, < 0 derefine, 0 keep
+ *   n_buf   buffer distance in cells (0 .. box_n; the paper's default is 2)
+ *   counts  host int64[2] or NULL: boxes refined, boxes whose children were
+ *           removed
+ * Rules: a leaf with a refine-flagged cell is refined, and so is every
+ * same-level leaf neighbour (across sides, edges or corners) that such a
+ * cell lies within n_buf cells of; coarser leaves that touch a refined box
+ * are refined as well until 2:1 balance holds across sides, edges and
+ * corners; the 2^D children of a box are removed when all are leaves whose
+ * cells are all flagged for derefinement, none of them is refined, and the
+ * box as a leaf keeps 2:1 balance.  The grid changes by at most one level;
+ * boxes at the deepest level (17 in 3D, 20 in 2D) are not refined.  The new
+ * tree has the same domain and side types and the Laplacian (its boxes are
+ * ordered by level and Morton index as every tree's); free it with
+ * afmg_tree_destroy.  The flags are reduced on the device (one word per
+ * box), the rules run on the host.  Allocates (a device word per box, the
+ * new tree) and synchronises the stream.  Errors: AFMG_ERR_ARG (null, a
+ * batch, n_buf out of range), AFMG_ERR_OOM, AFMG_ERR_HIP.
+ */
+int afmg_tree_adapt(afmg_tree *tree, void *stream, const int8_t *flags, int n_buf, afmg_tree **out,
+                    int64_t *counts);
+
+/*
+ * Transfer of a cell field from tree `from` to tree `to` (paper §2.3: the
+ * prolongation and restriction of §2.5 applied when the mesh changes).  The
+ * trees share the domain, and every leaf of `to` is a box of `from` or a
+ * child of a leaf of `from` (afmg_tree_adapt's result, or
+ * afmg_tree_refine's, satisfies this).
+ *   u_from   device [n_boxes(from)][N^D], layout of rho; leaf boxes read
+ *   bc_from  device Dirichlet / Neumann rows of `from` (as for afmg_solve),
+ *            or NULL for zero values: they enter the ghosts of prolongation
+ *   u_to     device [n_boxes(to)][N^D] out: on every leaf of `to`, the value
+ *            of the same box in `from` (a leaf there, or a box whose children
+ *            were removed: the mean of its children), or for a new box the
+ *            default prolongation from its parent in `from` with the side
+ *            ghosts of the solve; parents receive the means of their children
+ *   workspace  device, >= afmg_transfer_workspace_bytes(from, to), 256-byte
+ *            aligned
+ * Synchronises the stream.  Errors: AFMG_ERR_ARG (null, misaligned, trees of
+ * different domains, a leaf of `to` two or more levels below the leaves of
+ * `from`), AFMG_ERR_HIP.
+ */
+int afmg_transfer_workspace_bytes(const afmg_tree *from, const afmg_tree *to, size_t *bytes);
+int afmg_tree_transfer(afmg_tree *from, afmg_tree *to, void *stream, const double *u_from, const double *bc_from,
+                       double *u_to, void *workspace, size_t workspace_bytes);
+
 typedef enum {
     AFMG_OPERATOR_LAPLACIAN = 0,
     AFMG_OPERATOR_EPS = 1,

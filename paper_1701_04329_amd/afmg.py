@@ -141,7 +141,8 @@ EXPORTS = [
     "afmg_batch_solve", "afmg_autotune_workspace_bytes", "afmg_tree_autotune", "afmg_tree_shape",
     "afmg_tree_set_shape", "afmg_batch_autotune_workspace_bytes", "afmg_batch_autotune", "afmg_batch_shape",
     "afmg_batch_set_shape", "afmg_tree_refine", "afmg_tree_finalize", "afmg_tree_level_list", "afmg_step",
-    "afmg_solve_noalloc", "afmg_tree_create_domain", "afmg_tree_set_operator",
+    "afmg_solve_noalloc", "afmg_tree_create_domain", "afmg_tree_set_operator", "afmg_tree_adapt",
+    "afmg_transfer_workspace_bytes", "afmg_tree_transfer",
 ]
 # operators (paper §3.4, §3.5) and prolongations of afmg_tree_set_operator
 OPERATORS = {"laplacian": 0, "eps": 1, "cyl": 2, "cyl_eps": 3}
@@ -207,6 +208,9 @@ def lib():
                                 C.POINTER(Opts)]
         L.afmg_batch_autotune_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
         L.afmg_tree_set_operator.argtypes = [vp, vp, C.c_int, vp, C.c_int]
+        L.afmg_tree_adapt.argtypes = [vp, vp, vp, C.c_int, C.POINTER(vp), C.POINTER(C.c_int64)]
+        L.afmg_transfer_workspace_bytes.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
+        L.afmg_tree_transfer.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.c_size_t]
         _lib = L
     return _lib
 
@@ -431,6 +435,47 @@ class Tree(_Shapes):
 
 def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def adapt(tree: Tree, flags, n_buf=2, stream=None):
+    """afmg_tree_adapt: the tree after one mesh adaptation (paper §2.3).
+    flags: int8 CUDA tensor [n_boxes, N^D] in box order (> 0 refine, < 0
+    derefine, 0 keep; leaf boxes read).  Returns (new Tree, (boxes refined,
+    boxes whose children were removed))."""
+    import torch
+
+    if flags.dtype != torch.int8 or not flags.is_cuda or not flags.is_contiguous() or \
+            flags.numel() != tree.n_boxes * tree.cells_per_box:
+        raise ValueError("flags must be a contiguous int8 CUDA tensor of n_boxes x N^D values")
+    if stream is None:
+        stream = torch.cuda.current_stream(flags.device)
+    h = C.c_void_p()
+    counts = (C.c_int64 * 2)()
+    with torch.cuda.device(flags.device):
+        _check(lib().afmg_tree_adapt(tree.handle, C.c_void_p(stream.cuda_stream), _ptr(flags), n_buf, C.byref(h),
+                                     counts))
+    return Tree(tree.dim, _handle=h), (counts[0], counts[1])
+
+
+def transfer(src: Tree, dst: Tree, u, bc=None, out=None, workspace=None, stream=None):
+    """afmg_tree_transfer: the cell field u (float64 CUDA tensor [n_boxes(src),
+    N^D], box order) on tree dst; bc: src's boundary rows or None."""
+    import torch
+
+    _check_field(src, u, "u")
+    if out is None:
+        out = torch.empty((dst.n_boxes, dst.cells_per_box), dtype=torch.float64, device=u.device)
+    _check_field(dst, out, "out")
+    n = C.c_size_t()
+    _check(lib().afmg_transfer_workspace_bytes(src.handle, dst.handle, C.byref(n)))
+    if workspace is None or workspace.numel() * workspace.element_size() < n.value:
+        workspace = torch.empty(max(n.value, 256), dtype=torch.uint8, device=u.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(u.device)
+    with torch.cuda.device(u.device):
+        _check(lib().afmg_tree_transfer(src.handle, dst.handle, C.c_void_p(stream.cuda_stream), _ptr(u), _ptr(bc),
+                                        _ptr(out), _ptr(workspace), n.value))
+    return out
 
 
 def solve(tree: Tree, rho, bc=None, u=None, *, cycle="V", tol=1e-10, max_cycles=100, fixed_cycles=0,

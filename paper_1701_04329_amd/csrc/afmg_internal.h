@@ -84,6 +84,20 @@ int build_tree(int dim, int N, int n_trees, const int64_t *tree_off, const int32
 // and corners.
 int refine_leaves(const HostTree &t, const int32_t *ids, int64_t n, int balance, std::vector<int32_t> &level,
                   std::vector<int32_t> &idx, std::string &msg);
+// Mesh adaptation (paper §2.3) from one word per box (written by the flag
+// kernel): ADAPT_REFINE when a cell is flagged for refinement, ADAPT_REMOVE
+// when every cell is flagged for derefinement, and one bit per neighbour
+// direction (dx, dy, dz in -1..1) that lies within the buffer distance of a
+// refine-flagged cell.  The leaves after the adaptation: flagged leaves and
+// their buffer neighbours (same-level leaves) refined, 2:1 balance across
+// sides, edges and corners restored by refining coarser neighbours, and the
+// children of a box removed when all are marked leaves, none is refined and
+// the box as a leaf keeps 2:1 balance.  counts: boxes refined, boxes whose
+// children were removed.
+constexpr int ADAPT_REFINE = 1, ADAPT_REMOVE = 2;
+constexpr int adapt_dir_bit(int dx, int dy, int dz) { return 1 << (2 + (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)); }
+int adapt_leaves(const HostTree &t, const int32_t *words, std::vector<int32_t> &level, std::vector<int32_t> &idx,
+                 int64_t counts[2], std::string &msg);
 // the position (l, q) inside a single tree's domain (periodic axes wrapped),
 // false outside it or in a lattice position without a level-1 box
 bool domain_position(const HostTree &t, int l, int q[3]);

@@ -183,6 +183,17 @@ void launch_restrict_field_op(const BoxInfo *info, double *f, int64_t b0, int64_
 // positive and finite
 template <int D, int N>
 void launch_check_positive(const BoxInfo *info, const double *f, int64_t nb, int *flag, hipStream_t st);
+// mesh adaptation: one word per box from the int8 cell flags (see adapt_leaves)
+template <int D, int N>
+void launch_box_flags(const BoxInfo *info, const int8_t *flags, int64_t nb, int n_buf, int32_t *words,
+                      hipStream_t st);
+// field transfer between trees (colour-split arrays): whole boxes copied
+// (copy_dst[q] <- copy_src[q]) and new boxes prolonged from their parent in
+// the from-tree (pro_dst[q] <- P(pro_src[q]), ghosts from bc unless homog)
+template <int D, int N>
+void launch_transfer(const BoxInfo *to_info, const BoxInfo *from_info, const int32_t *copy_dst,
+                     const int32_t *copy_src, int64_t n_copy, const int32_t *pro_dst, const int32_t *pro_src,
+                     int64_t n_pro, const double *from, const double *bc, int homog, double *to, hipStream_t st);
 template <int D, int N>
 void launch_push_down(const BoxInfo *info, double *f, int64_t b0, int64_t nb, hipStream_t st);
 template <int D, int N>

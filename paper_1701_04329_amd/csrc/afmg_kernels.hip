@@ -1665,6 +1665,177 @@ __global__ __launch_bounds__(256) void k_check_positive(const BoxInfo *__restric
     if (bad) atomicOr(flag, 1);
 }
 
+// ---------------------------------------------------------------------------
+// mesh adaptation (paper §2.3) and field transfer
+// ---------------------------------------------------------------------------
+// One word per box from the cell flags of a leaf box (int8, the caller's
+// x-fastest order; > 0 refine, < 0 derefine): ADAPT_REFINE if some cell is
+// flagged for refinement, ADAPT_REMOVE if every cell is flagged for
+// derefinement, and the bit of each neighbour direction (dx, dy, dz) such
+// that a refine-flagged cell lies within n_buf cells of that neighbour
+// (along every axis where the direction is not 0, the cell is among the
+// n_buf cells next to that side).  Parents get 0.  Thread t of a box scans
+// row t; the words of a box's threads are combined across their lanes.
+template <int D, int N>
+__global__ __launch_bounds__(256) void k_box_flags(const BoxInfo *__restrict__ info, const int8_t *__restrict__ flags,
+                                                   int nb, int n_buf, int32_t *__restrict__ words) {
+    using G = Geo<D, N>;
+    const Slot<D, N> sl = slot_of<D, N>(0, nb, false);
+    const bool leaf = sl.valid && (info[sl.b].flags & FLAG_LEAF);
+    int w = 0, all_rm = 1;
+    if (leaf) {
+        int j, k;
+        row_of<D, N>(sl.t, j, k);
+        const int8_t *f = flags + (size_t)sl.b * G::C + (size_t)sl.t * N;
+        for (int i = 0; i < N; i++) {
+            const int v = f[i];
+            all_rm &= v < 0 ? 1 : 0;
+            if (v <= 0) continue;
+            w |= ADAPT_REFINE;
+            const bool lo[3] = {i < n_buf, j < n_buf, k < n_buf};
+            const bool hi[3] = {i >= N - n_buf, j >= N - n_buf, k >= N - n_buf};
+            for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); dz++)
+                for (int dy = -1; dy <= 1; dy++)
+                    for (int dx = -1; dx <= 1; dx++) {
+                        if (dx == 0 && dy == 0 && dz == 0) continue;
+                        const int o[3] = {dx, dy, dz};
+                        bool near = true;
+                        for (int d = 0; d < D; d++)
+                            if ((o[d] == -1 && !lo[d]) || (o[d] == 1 && !hi[d])) near = false;
+                        if (near) w |= adapt_dir_bit(dx, dy, dz);
+                    }
+        }
+    }
+    for (int o = G::TPB / 2; o > 0; o >>= 1) {
+        w |= __shfl_xor(w, o);
+        all_rm &= __shfl_xor(all_rm, o);
+    }
+    if (sl.valid && sl.t == 0) words[sl.b] = leaf ? (w | (all_rm ? ADAPT_REMOVE : 0)) : 0;
+}
+
+// whole boxes: to[dst[q]] = from[src[q]] (both colour-split)
+template <int D, int N>
+__global__ __launch_bounds__(256) void k_transfer_copy(const int32_t *__restrict__ dst, const int32_t *__restrict__ src,
+                                                       int n, const double *__restrict__ from, double *__restrict__ to) {
+    using G = Geo<D, N>;
+    const Slot<D, N> sl = slot_of<D, N>(0, n, false);
+    if (!sl.valid) return;
+    const size_t a = (size_t)src[sl.b] * G::C, b = (size_t)dst[sl.b] * G::C;
+    for (int e = sl.t; e < G::C; e += G::TPB) to[b + e] = from[a + e];
+}
+
+// New boxes: to-box dst[q] receives the default prolongation (paper §2.5) of
+// the from-tree's leaf src[q], its parent: the octant under the box plus a
+// one-cell halo is staged, halo cells outside the parent box are the side
+// ghosts of the solve (neighbour cells; 2 b - u1 or u1 + h q on physical
+// sides with the boundary rows bc, zero values when homog; the default
+// refinement-boundary scheme), and
+//   2D: 1/2 u(P) + 1/4 u(P + sx ex) + 1/4 u(P + sy ey)
+//   3D: 1/4 [u(P) + u(P + sx ex) + u(P + sy ey) + u(P + sz ez)].
+template <int D, int N>
+__global__ __launch_bounds__(256) void k_transfer_prolong(const BoxInfo *__restrict__ to_info,
+                                                          const BoxInfo *__restrict__ from_info,
+                                                          const int32_t *__restrict__ dst, const int32_t *__restrict__ src,
+                                                          int n, const double *__restrict__ from,
+                                                          const double *__restrict__ bc, int homog,
+                                                          double *__restrict__ to) {
+    using G = Geo<D, N>;
+    constexpr int NH = (2 * D * G::HF + G::TPB - 1) / G::TPB;
+    constexpr int NO = G::HC / G::TPB;
+    constexpr int NE = G::C / G::TPB;
+    __shared__ double qs[G::BPW * G::QC];
+    const Slot<D, N> sl = slot_of<D, N>(0, n, false);
+    double *q = qs + sl.slot * G::QC;
+    const bool act = sl.valid;
+    const int64_t b = act ? dst[sl.b] : 0, p = act ? src[sl.b] : 0;
+    const BoxInfo bi = to_info[b];
+    const BoxInfo pi = from_info[p];
+    const int o[3] = {obit(bi.flags, 0) * G::H, obit(bi.flags, 1) * G::H, D == 3 ? obit(bi.flags, 2) * G::H : 0};
+    const double hp = 1.0 / ((double)N * ldexp(1.0, pi.level - 1));
+    double raw[NH];
+    int hv[NH], hs[NH];
+    if (act) {
+        double od[NO];
+#pragma unroll
+        for (int it = 0; it < NO; it++) {
+            const int pc = sl.t + it * G::TPB;
+            const int I = pc % G::H, J = (pc / G::H) % G::H, K = D == 3 ? pc / (G::H * G::H) : 0;
+            od[it] = from[(size_t)p * G::C + cpos<D, N>(o[0] + I, o[1] + J, o[2] + K)];
+        }
+#pragma unroll
+        for (int h = 0; h < NH; h++) {
+            const int hc = sl.t + h * G::TPB;
+            size_t ho = (size_t)p * G::C;
+            hv[h] = 0;
+            hs[h] = 0;
+            if (hc < 2 * D * G::HF) {
+                const int side = hc / G::HF, m = hc % G::HF;
+#define AFMG_H1(S) ho = halo_addr<D, N, S>(m, o, pi, p, hv[h], hs[h])
+                AFMG_SIDE_SWITCH(side, AFMG_H1)
+#undef AFMG_H1
+            }
+            raw[h] = from[ho];
+        }
+#pragma unroll
+        for (int it = 0; it < NO; it++) {
+            const int pc = sl.t + it * G::TPB;
+            const int I = pc % G::H, J = (pc / G::H) % G::H, K = D == 3 ? pc / (G::H * G::H) : 0;
+            q[qpad<D, N>(I, J, K)] = od[it];
+        }
+#pragma unroll
+        for (int h = 0; h < NH; h++)
+            if (sl.t + h * G::TPB < 2 * D * G::HF && hv[h] >= 0) q[hs[h]] = raw[h];
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+        for (int h = 0; h < NH; h++) {
+            const int hc = sl.t + h * G::TPB;
+            if (hc >= 2 * D * G::HF || hv[h] >= 0) continue;
+            const int side = hc / G::HF, m = hc % G::HF;
+            if (hv[h] <= -2) {
+#define AFMG_H2(S) halo_phase2<D, N, S, double>(q, m, o, raw[h], hv[h], pi.flags)
+                AFMG_SIDE_SWITCH(side, AFMG_H2)
+#undef AFMG_H2
+                continue;
+            }
+            // physical side of the parent: the ghost of the values
+#define AFMG_H3(S)                                                                                    \
+    {                                                                                                 \
+        using SD = SideOf<S>;                                                                         \
+        int L[3], X[3];                                                                               \
+        halo_cell<D, N, S>(m, o, L, X);                                                               \
+        int f[3] = {L[0], L[1], L[2]};                                                                \
+        f[SD::d] = SD::hi ? L[SD::d] - 1 : 0;                                                         \
+        const double d1 = q[qpad<D, N>(f[0], f[1], f[2])];                                            \
+        const int mf = X[SD::t1] + (D == 3 ? N * X[SD::t2] : 0);                                      \
+        const double bv = (homog || pi.bcoff[S] < 0) ? 0.0 : bc[(size_t)pi.bcoff[S] * G::F + mf];     \
+        q[qpad<D, N>(L[0], L[1], L[2])] = phys_ghost<double>(neumann_side(pi.flags, S), bv, d1, hp);  \
+    }
+            AFMG_SIDE_SWITCH(side, AFMG_H3)
+#undef AFMG_H3
+        }
+    }
+    __syncthreads();
+    if (!act) return;
+#pragma unroll
+    for (int it = 0; it < NE; it++) {
+        const int e = sl.t + it * G::TPB;
+        int i, j, k;
+        cell_of<D, N>(e, i, j, k);
+        const int I = i >> 1, J = j >> 1, K = k >> 1;
+        const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
+        double v;
+        if (D == 2) {
+            v = 0.5 * q[qpad<D, N>(I, J, 0)] + 0.25 * q[qpad<D, N>(I + sx, J, 0)] + 0.25 * q[qpad<D, N>(I, J + sy, 0)];
+        } else {
+            v = 0.25 * (((q[qpad<D, N>(I, J, K)] + q[qpad<D, N>(I + sx, J, K)]) + q[qpad<D, N>(I, J + sy, K)]) +
+                        q[qpad<D, N>(I, J, K + sz)]);
+        }
+        to[(size_t)b * G::C + e] = v;
+    }
+}
+
 // One workgroup of 1024 threads: out[0] = max of the partial maxima, out[1] =
 // sqrt of the sum of the partial sums; the reduction order is fixed.
 __global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ partial, int64_t n, double *out,
@@ -3501,6 +3672,20 @@ void launch_check_positive(const BoxInfo *info, const double *f, int64_t nb, int
 }
 
 template <int D, int N>
+void launch_box_flags(const BoxInfo *info, const int8_t *flags, int64_t nb, int n_buf, int32_t *words,
+                      hipStream_t st) {
+    AFMG_LAUNCH((k_box_flags<D, N>), (wg_count<D, N>(nb)), st, info, flags, (int)nb, n_buf, words);
+}
+template <int D, int N>
+void launch_transfer(const BoxInfo *to_info, const BoxInfo *from_info, const int32_t *copy_dst,
+                     const int32_t *copy_src, int64_t n_copy, const int32_t *pro_dst, const int32_t *pro_src,
+                     int64_t n_pro, const double *from, const double *bc, int homog, double *to, hipStream_t st) {
+    AFMG_LAUNCH((k_transfer_copy<D, N>), (wg_count<D, N>(n_copy)), st, copy_dst, copy_src, (int)n_copy, from, to);
+    AFMG_LAUNCH((k_transfer_prolong<D, N>), (wg_count<D, N>(n_pro)), st, to_info, from_info, pro_dst, pro_src,
+                (int)n_pro, from, bc, homog, to);
+}
+
+template <int D, int N>
 size_t coarse_gen_doubles(int n_roots) {
     return (size_t)n_roots * (5 * GenGeo<D, N>::TOT + GenGeo<D, N>::BTOT);
 }
@@ -3644,6 +3829,14 @@ template void launch_restrict_field_op<2, 8>(const BoxInfo *, double *, int64_t,
 template void launch_restrict_field_op<3, 8>(const BoxInfo *, double *, int64_t, int64_t, int, const int32_t *,
                                              double, hipStream_t);
 template void launch_check_positive<2, 8>(const BoxInfo *, const double *, int64_t, int *, hipStream_t);
+template void launch_box_flags<2, 8>(const BoxInfo *, const int8_t *, int64_t, int, int32_t *, hipStream_t);
+template void launch_box_flags<3, 8>(const BoxInfo *, const int8_t *, int64_t, int, int32_t *, hipStream_t);
+template void launch_transfer<2, 8>(const BoxInfo *, const BoxInfo *, const int32_t *, const int32_t *, int64_t,
+                                    const int32_t *, const int32_t *, int64_t, const double *, const double *, int,
+                                    double *, hipStream_t);
+template void launch_transfer<3, 8>(const BoxInfo *, const BoxInfo *, const int32_t *, const int32_t *, int64_t,
+                                    const int32_t *, const int32_t *, int64_t, const double *, const double *, int,
+                                    double *, hipStream_t);
 template void launch_check_positive<3, 8>(const BoxInfo *, const double *, int64_t, int *, hipStream_t);
 template size_t coarse_gen_doubles<3, 8>(int);
 template int final_wgs<2, 8>(int64_t, int);

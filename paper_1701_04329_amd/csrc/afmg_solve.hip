@@ -19,6 +19,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 
 #include "afmg.h"
 #include "afmg_internal.h"
@@ -1537,6 +1538,90 @@ int load_eps(afmg_tree *t, hipStream_t st, const double *eps, int opk, int *flag
     return AFMG_OK;
 }
 
+// Workspace of afmg_tree_transfer: the from-tree's field (colour-split, with
+// its parents), its boundary rows with the derived parent rows, and the
+// box lists of the transfer.
+struct XferLayout {
+    size_t u, bc, lists, total;
+};
+XferLayout xfer_layout(const afmg_tree *from, const afmg_tree *to) {
+    const size_t C = (size_t)cells_per_box(from->h.dim), F = (size_t)cells_per_face(from->h.dim);
+    XferLayout L{};
+    size_t off = 0;
+    L.u = off; off = align256(off + (size_t)from->h.n_boxes * C * sizeof(double));
+    L.bc = off; off = align256(off + (size_t)std::max<int64_t>(1, from->h.n_bfaces_all) * F * sizeof(double));
+    L.lists = off; off = align256(off + (size_t)std::max<int64_t>(1, to->h.n_boxes) * 4 * sizeof(int32_t));
+    L.total = off;
+    return L;
+}
+
+template <int D>
+int transfer(afmg_tree *from, afmg_tree *to, hipStream_t st, const double *u_from, const double *bc, double *u_to,
+             char *ws) {
+    const HostTree &hf = from->h, &ht = to->h;
+    const XferLayout L = xfer_layout(from, to);
+    const int64_t C = cells_per_box(D), F = cells_per_face(D);
+    // the box lists: a leaf of `to` that is a box of `from` takes its values
+    // (the mean of its children if it was refined there); a new leaf is
+    // prolonged from its parent, a leaf of `from`
+    std::unordered_map<uint64_t, int32_t> from_box;
+    from_box.reserve((size_t)hf.n_boxes * 2);
+    auto key = [](int l, int i, int j, int k) {
+        return ((uint64_t)l << 58) ^ ((uint64_t)(uint32_t)i << 38) ^ ((uint64_t)(uint32_t)j << 19) ^ (uint64_t)(uint32_t)k;
+    };
+    for (int64_t m = 0; m < hf.n_boxes; m++)
+        from_box.emplace(key(hf.info[(size_t)m].level, hf.ix[(size_t)m], hf.iy[(size_t)m], hf.iz[(size_t)m]), (int32_t)m);
+    std::vector<int32_t> cdst, csrc, pdst, psrc;
+    for (int64_t m = 0; m < ht.n_boxes; m++) {
+        if (!(ht.info[(size_t)m].flags & FLAG_LEAF)) continue;
+        const int l = ht.info[(size_t)m].level;
+        auto it = from_box.find(key(l, ht.ix[(size_t)m], ht.iy[(size_t)m], ht.iz[(size_t)m]));
+        if (it != from_box.end()) {
+            cdst.push_back((int32_t)m);
+            csrc.push_back(it->second);
+            continue;
+        }
+        auto ip = l > 1 ? from_box.find(key(l - 1, (ht.ix[(size_t)m] + 1) / 2, (ht.iy[(size_t)m] + 1) / 2,
+                                            D == 3 ? (ht.iz[(size_t)m] + 1) / 2 : 1))
+                        : from_box.end();
+        if (ip == from_box.end() || !(hf.info[(size_t)ip->second].flags & FLAG_LEAF))
+            return fail(AFMG_ERR_ARG, "a leaf of the target lies two or more levels below the source's leaves");
+        pdst.push_back((int32_t)m);
+        psrc.push_back(ip->second);
+    }
+    int32_t *lists = (int32_t *)(ws + L.lists);
+    std::vector<int32_t> all;
+    all.reserve(2 * (size_t)ht.n_boxes);
+    all.insert(all.end(), cdst.begin(), cdst.end());
+    all.insert(all.end(), csrc.begin(), csrc.end());
+    all.insert(all.end(), pdst.begin(), pdst.end());
+    all.insert(all.end(), psrc.begin(), psrc.end());
+    hipError_t e = hipMemcpyAsync(lists, all.data(), sizeof(int32_t) * all.size(), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "transfer lists");
+    const int64_t nc = (int64_t)cdst.size(), np = (int64_t)pdst.size();
+    // the from-field with its parents, and its boundary rows
+    double *uf = (double *)(ws + L.u), *bc_w = (double *)(ws + L.bc);
+    launch_load_rho<D, BOX_N, double>(from->d_info, nullptr, u_from, uf, hf.n_boxes, 1, st);
+    for (int l = hf.lmax; l >= 2; l--)
+        launch_restrict_field<D, BOX_N>(from->d_info, uf, hf.lvl_off[(size_t)l], hf.level_count(l), st);
+    if (hf.n_bfaces_leaf > 0 && bc) {
+        e = hipMemcpyAsync(bc_w, bc, (size_t)(hf.n_bfaces_leaf * F) * sizeof(double), hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, "copy of boundary values");
+        for (int l = hf.lmax; l >= 2; l--)
+            launch_bc_derive<D, BOX_N>(from->d_info, hf.lvl_off[(size_t)l], hf.level_count(l), bc_w, st);
+    }
+    launch_transfer<D, BOX_N>(to->d_info, from->d_info, lists, lists + nc, nc, lists + 2 * nc, lists + 2 * nc + np, np,
+                              uf, bc_w, bc ? 0 : 1, u_to, st);
+    for (int l = ht.lmax; l >= 2; l--)
+        launch_restrict_field<D, BOX_N>(to->d_info, u_to, ht.lvl_off[(size_t)l], ht.level_count(l), st);
+    launch_permute<D, BOX_N, double>(to->d_info, u_to, 0, ht.n_boxes, 0, 0, st);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(st);  // the host lists above must outlive their copy
+    if (e != hipSuccess) return hip_fail(e, "transfer");
+    (void)C;
+    return AFMG_OK;
+}
+
 // ---------------------------------------------------------------------------
 // C-ABI
 // ---------------------------------------------------------------------------
@@ -1674,6 +1759,75 @@ int afmg_tree_refine(const afmg_tree *t, const int32_t *ids, int64_t n, int bala
         const bool general = t->domain_general >= 0 ? t->domain_general != 0 : t->h.general;
         return afmg_tree_create_domain(t->h.dim, t->h.N, general ? t->h.bc_type : nullptr,
                                        (int64_t)level.size(), level.data(), idx.data(), out);
+    } catch (const std::bad_alloc &) {
+        return fail(AFMG_ERR_OOM, "host allocation failed");
+    }
+}
+
+int afmg_tree_adapt(afmg_tree *t, void *stream, const int8_t *flags, int n_buf, afmg_tree **out, int64_t *counts) {
+    if (!t || !flags || !out) return fail(AFMG_ERR_ARG, "null argument");
+    *out = nullptr;
+    if (t->forest) return fail(AFMG_ERR_ARG, "not a tree");
+    if (n_buf < 0 || n_buf > t->h.N) return fail(AFMG_ERR_ARG, "n_buf must lie in [0, box_n]");
+    int rc = bind_device(t);
+    if (rc != AFMG_OK) return rc;
+    const HostTree &h = t->h;
+    hipStream_t st = (hipStream_t)stream;
+    try {
+        std::vector<int32_t> words((size_t)h.n_boxes);
+        int32_t *d_words = nullptr;
+        hipError_t e = hipMalloc(&d_words, sizeof(int32_t) * words.size());
+        if (e != hipSuccess) return fail(AFMG_ERR_OOM, "hipMalloc of the box words failed");
+        if (h.dim == 3) launch_box_flags<3, BOX_N>(t->d_info, flags, h.n_boxes, n_buf, d_words, st);
+        else launch_box_flags<2, BOX_N>(t->d_info, flags, h.n_boxes, n_buf, d_words, st);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(words.data(), d_words, sizeof(int32_t) * words.size(),
+                                                hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        (void)hipFree(d_words);
+        if (e != hipSuccess) return hip_fail(e, "cell flags");
+        std::vector<int32_t> level, idx;
+        std::string msg;
+        int64_t cnt[2] = {0, 0};
+        rc = adapt_leaves(h, words.data(), level, idx, cnt, msg);
+        if (rc != AFMG_OK) return fail(rc, msg);
+        if (counts) {
+            counts[0] = cnt[0];
+            counts[1] = cnt[1];
+        }
+        const bool general = t->domain_general >= 0 ? t->domain_general != 0 : h.general;
+        return afmg_tree_create_domain(h.dim, h.N, general ? h.bc_type : nullptr, (int64_t)level.size(),
+                                       level.data(), idx.data(), out);
+    } catch (const std::bad_alloc &) {
+        return fail(AFMG_ERR_OOM, "host allocation failed");
+    }
+}
+
+int afmg_transfer_workspace_bytes(const afmg_tree *from, const afmg_tree *to, size_t *bytes) {
+    if (!from || !to || !bytes) return fail(AFMG_ERR_ARG, "null argument");
+    *bytes = xfer_layout(from, to).total;
+    return AFMG_OK;
+}
+
+int afmg_tree_transfer(afmg_tree *from, afmg_tree *to, void *stream, const double *u_from, const double *bc_from,
+                       double *u_to, void *workspace, size_t workspace_bytes) {
+    if (!from || !to || !u_from || !u_to || !workspace) return fail(AFMG_ERR_ARG, "null argument");
+    if (from->forest || to->forest) return fail(AFMG_ERR_ARG, "not a tree");
+    const HostTree &a = from->h, &b = to->h;
+    bool same = a.dim == b.dim && a.N == b.N && a.n_roots == b.n_roots;
+    for (int d = 0; d < 3; d++) same = same && a.ext[d] == b.ext[d];
+    for (int s = 0; s < 6; s++) same = same && a.bc_type[s] == b.bc_type[s];
+    if (!same) return fail(AFMG_ERR_ARG, "the trees must share the domain");
+    if (!aligned(u_from, 8) || !aligned(u_to, 8) || (bc_from && !aligned(bc_from, 8)) || !aligned(workspace, 256))
+        return fail(AFMG_ERR_ARG, "misaligned array");
+    if (workspace_bytes < xfer_layout(from, to).total) return fail(AFMG_ERR_ARG, "workspace too small");
+    int rc = bind_device(from);
+    if (rc == AFMG_OK) rc = bind_device(to);
+    if (rc != AFMG_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    try {
+        if (a.dim == 3) return transfer<3>(from, to, st, u_from, bc_from, u_to, (char *)workspace);
+        return transfer<2>(from, to, st, u_from, bc_from, u_to, (char *)workspace);
     } catch (const std::bad_alloc &) {
         return fail(AFMG_ERR_OOM, "host allocation failed");
     }

@@ -317,18 +317,121 @@ int build_tree(int dim, int N, int n_trees, const int64_t *tree_off, const int32
     return AFMG_OK;
 }
 
+namespace {
+
+// Leaf and box lookup of a single tree by (level, i, j, k).
+struct Lookup {
+    const HostTree &t;
+    std::unordered_map<Key, int64_t, KeyHash> leaf, box;
+    explicit Lookup(const HostTree &tt) : t(tt) {
+        leaf.reserve((size_t)t.n_leaves * 2);
+        box.reserve((size_t)t.n_boxes * 2);
+        for (int64_t m = 0; m < t.n_boxes; m++) {
+            const Key k = key_of(m);
+            box.emplace(k, m);
+            if (t.info[(size_t)m].flags & FLAG_LEAF) leaf.emplace(k, m);
+        }
+    }
+    Key key_of(int64_t m) const {
+        return Key{0, t.info[(size_t)m].level, t.ix[(size_t)m], t.iy[(size_t)m], t.iz[(size_t)m]};
+    }
+    // box at (l, i, j, k) after wrapping periodic axes, or -1 (outside the
+    // domain, or no box there)
+    int64_t box_at(int l, int i, int j, int k) const {
+        int q[3] = {i, j, t.dim == 3 ? k : 1};
+        if (!domain_position(t, l, q)) return -1;
+        auto it = box.find(Key{0, l, q[0], q[1], q[2]});
+        return it == box.end() ? -1 : it->second;
+    }
+    // the leaf covering position (l, i, j, k), or -1 outside the domain
+    int64_t covering(int l, int i, int j, int k) const {
+        int q[3] = {i, j, t.dim == 3 ? k : 1};
+        if (!domain_position(t, l, q)) return -1;
+        i = q[0];
+        j = q[1];
+        k = q[2];
+        while (l >= 1) {
+            auto it = leaf.find(Key{0, l, i, j, k});
+            if (it != leaf.end()) return it->second;
+            l--;
+            i = (i + 1) / 2;
+            j = (j + 1) / 2;
+            k = t.dim == 3 ? (k + 1) / 2 : 1;
+        }
+        return -1;
+    }
+};
+
+// Coarser leaves that touch a leaf to be refined are refined too, until no
+// refinement breaks 2:1 balance (balance 1: across sides; 2: also edges and
+// corners).  refine[m] marks the leaf boxes to refine; `work` holds the ones
+// whose neighbours are still to be checked.
+int close_refinement(const Lookup &lk, std::vector<char> &refine, std::vector<int64_t> &work, int balance,
+                     std::string &msg) {
+    const HostTree &t = lk.t;
+    const int dim = t.dim;
+    while (!work.empty()) {
+        const int64_t m = work.back();
+        work.pop_back();
+        const Key kk = lk.key_of(m);
+        for (int dz = (dim == 3 ? -1 : 0); dz <= (dim == 3 ? 1 : 0); dz++)
+            for (int dy = -1; dy <= 1; dy++)
+                for (int dx = -1; dx <= 1; dx++) {
+                    const int nz = (dx != 0) + (dy != 0) + (dz != 0);
+                    if (nz == 0 || (balance < 2 && nz != 1)) continue;
+                    const int64_t v = lk.covering(kk.l, kk.i + dx, kk.j + dy, kk.k + dz);
+                    if (v < 0 || t.info[(size_t)v].level >= kk.l || refine[(size_t)v]) continue;
+                    if (balance == 0) {
+                        msg = "refinement breaks 2:1 balance with a coarser neighbour";
+                        return AFMG_ERR_TREE;
+                    }
+                    refine[(size_t)v] = 1;
+                    work.push_back(v);
+                }
+    }
+    return AFMG_OK;
+}
+
+// the leaves of t with the boxes marked in `refine` replaced by their
+// children and the children of the boxes marked in `coarsen` by their parent
+void emit_leaves(const Lookup &lk, const std::vector<char> &refine, const std::vector<char> &coarsen,
+                 std::vector<int32_t> &level, std::vector<int32_t> &idx) {
+    const HostTree &t = lk.t;
+    const int dim = t.dim;
+    level.clear();
+    idx.clear();
+    for (int64_t q = 0; q < t.n_leaves; q++) {
+        const int64_t m = t.leaf_box[(size_t)q];
+        const int32_t p = t.info[(size_t)m].parent;
+        if (refine[(size_t)m] || (p >= 0 && coarsen[(size_t)p])) continue;
+        const Key kk = lk.key_of(m);
+        level.push_back(kk.l);
+        idx.insert(idx.end(), {kk.i, kk.j, kk.k});
+    }
+    for (int64_t m = 0; m < t.n_boxes; m++) {
+        const Key kk = lk.key_of(m);
+        if (coarsen[(size_t)m]) {
+            level.push_back(kk.l);
+            idx.insert(idx.end(), {kk.i, kk.j, kk.k});
+        }
+        if (!refine[(size_t)m]) continue;
+        for (int c = 0; c < (1 << dim); c++) {
+            level.push_back(kk.l + 1);
+            idx.insert(idx.end(), {2 * kk.i - 1 + (c & 1), 2 * kk.j - 1 + ((c >> 1) & 1),
+                                   dim == 3 ? 2 * kk.k - 1 + ((c >> 2) & 1) : 1});
+        }
+    }
+}
+
+}  // namespace
+
 int refine_leaves(const HostTree &t, const int32_t *ids, int64_t n, int balance, std::vector<int32_t> &level,
                   std::vector<int32_t> &idx, std::string &msg) {
     if (n < 0 || (n > 0 && !ids)) { msg = "bad leaf id list"; return AFMG_ERR_ARG; }
     if (balance < 0 || balance > 2) { msg = "balance must be 0, 1 or 2"; return AFMG_ERR_ARG; }
     if (t.n_trees != 1) { msg = "refinement applies to single trees"; return AFMG_ERR_ARG; }
-    const int dim = t.dim;
-    const int max_level = dim == 3 ? 17 : 20;
-    std::unordered_map<Key, int64_t, KeyHash> leaf;  // leaf key -> box id
-    leaf.reserve((size_t)t.n_leaves * 2);
-    auto key_of = [&](int64_t m) { return Key{0, t.info[(size_t)m].level, t.ix[(size_t)m], t.iy[(size_t)m], t.iz[(size_t)m]}; };
-    for (int64_t m = 0; m < t.n_boxes; m++)
-        if (t.info[(size_t)m].flags & FLAG_LEAF) leaf.emplace(key_of(m), m);
+    const int max_level = t.dim == 3 ? 17 : 20;
+    const Lookup lk(t);
     std::vector<char> refine((size_t)t.n_boxes, 0);
     std::vector<int64_t> work;
     for (int64_t q = 0; q < n; q++) {
@@ -343,61 +446,87 @@ int refine_leaves(const HostTree &t, const int32_t *ids, int64_t n, int balance,
             work.push_back(m);
         }
     }
-    // the leaf covering position (l, i, j, k) (periodic axes wrapped), or -1
-    // outside the domain
-    auto covering = [&](int l, int i, int j, int k) -> int64_t {
-        int q[3] = {i, j, dim == 3 ? k : 1};
-        if (!domain_position(t, l, q)) return -1;
-        i = q[0];
-        j = q[1];
-        k = q[2];
-        while (l >= 1) {
-            auto it = leaf.find(Key{0, l, i, j, k});
-            if (it != leaf.end()) return it->second;
-            l--;
-            i = (i + 1) / 2;
-            j = (j + 1) / 2;
-            k = dim == 3 ? (k + 1) / 2 : 1;
+    const int rc = close_refinement(lk, refine, work, balance, msg);
+    if (rc != AFMG_OK) return rc;
+    emit_leaves(lk, refine, std::vector<char>((size_t)t.n_boxes, 0), level, idx);
+    return AFMG_OK;
+}
+
+int adapt_leaves(const HostTree &t, const int32_t *words, std::vector<int32_t> &level, std::vector<int32_t> &idx,
+                 int64_t counts[2], std::string &msg) {
+    if (t.n_trees != 1) { msg = "adaptation applies to single trees"; return AFMG_ERR_ARG; }
+    const int dim = t.dim;
+    const int max_level = dim == 3 ? 17 : 20;
+    const Lookup lk(t);
+    std::vector<char> refine((size_t)t.n_boxes, 0);
+    std::vector<int64_t> work;
+    auto mark = [&](int64_t m) {
+        if (m >= 0 && !refine[(size_t)m] && (t.info[(size_t)m].flags & FLAG_LEAF) &&
+            t.info[(size_t)m].level < max_level) {
+            refine[(size_t)m] = 1;
+            work.push_back(m);
         }
-        return -1;
     };
-    while (!work.empty()) {
-        const int64_t m = work.back();
-        work.pop_back();
-        const Key kk = key_of(m);
+    // a flagged cell refines its box, and the same-level leaves within the
+    // buffer distance of it (direction bits of the box's word)
+    for (int64_t q = 0; q < t.n_leaves; q++) {
+        const int64_t m = t.leaf_box[(size_t)q];
+        const int32_t w = words[m];
+        if (!(w & ADAPT_REFINE)) continue;
+        mark(m);
+        const Key kk = lk.key_of(m);
         for (int dz = (dim == 3 ? -1 : 0); dz <= (dim == 3 ? 1 : 0); dz++)
             for (int dy = -1; dy <= 1; dy++)
                 for (int dx = -1; dx <= 1; dx++) {
-                    const int nz = (dx != 0) + (dy != 0) + (dz != 0);
-                    if (nz == 0 || (balance < 2 && nz != 1)) continue;
-                    const int64_t v = covering(kk.l, kk.i + dx, kk.j + dy, kk.k + dz);
-                    if (v < 0 || t.info[(size_t)v].level >= kk.l || refine[(size_t)v]) continue;
-                    if (balance == 0) {
-                        msg = "refinement breaks 2:1 balance with a coarser neighbour";
-                        return AFMG_ERR_TREE;
-                    }
-                    refine[(size_t)v] = 1;
-                    work.push_back(v);
+                    if (dx == 0 && dy == 0 && dz == 0) continue;
+                    if (!(w & adapt_dir_bit(dx, dy, dz))) continue;
+                    const int64_t v = lk.box_at(kk.l, kk.i + dx, kk.j + dy, kk.k + dz);
+                    mark(v);
                 }
     }
-    level.clear();
-    idx.clear();
-    for (int64_t q = 0; q < t.n_leaves; q++) {
-        const int64_t m = t.leaf_box[(size_t)q];
-        if (refine[(size_t)m]) continue;
-        const Key kk = key_of(m);
-        level.push_back(kk.l);
-        idx.insert(idx.end(), {kk.i, kk.j, kk.k});
-    }
-    for (int64_t m = 0; m < t.n_boxes; m++) {
-        if (!refine[(size_t)m]) continue;
-        const Key kk = key_of(m);
-        for (int c = 0; c < (1 << dim); c++) {
-            level.push_back(kk.l + 1);
-            idx.insert(idx.end(), {2 * kk.i - 1 + (c & 1), 2 * kk.j - 1 + ((c >> 1) & 1),
-                                   dim == 3 ? 2 * kk.k - 1 + ((c >> 2) & 1) : 1});
+    int rc = close_refinement(lk, refine, work, 2, msg);
+    if (rc != AFMG_OK) return rc;
+    // removal: parents whose children are all leaves marked for removal and
+    // none to be refined, and whose neighbours' children that touch them stay
+    // leaves (the parent as a leaf keeps 2:1 balance)
+    std::vector<char> coarsen((size_t)t.n_boxes, 0);
+    const int nch = 1 << dim;
+    for (int64_t p = 0; p < t.n_boxes; p++) {
+        if (t.info[(size_t)p].flags & FLAG_LEAF) continue;
+        bool all = true;
+        for (int c = 0; c < nch && all; c++) {
+            const int32_t ch = t.child[(size_t)p * 8 + c];
+            all = ch >= 0 && (t.info[(size_t)ch].flags & FLAG_LEAF) && (words[ch] & ADAPT_REMOVE) && !refine[(size_t)ch];
         }
+        if (!all) continue;
+        const Key kp = lk.key_of(p);
+        bool ok = true;
+        for (int dz = (dim == 3 ? -1 : 0); dz <= (dim == 3 ? 1 : 0) && ok; dz++)
+            for (int dy = -1; dy <= 1 && ok; dy++)
+                for (int dx = -1; dx <= 1 && ok; dx++) {
+                    if (dx == 0 && dy == 0 && dz == 0) continue;
+                    const int64_t v = lk.box_at(kp.l, kp.i + dx, kp.j + dy, kp.k + dz);
+                    if (v < 0 || (t.info[(size_t)v].flags & FLAG_LEAF)) continue;
+                    const int o[3] = {dx, dy, dz};
+                    for (int c = 0; c < nch && ok; c++) {
+                        bool touch = true;
+                        for (int d = 0; d < dim; d++) {
+                            const int bit = (c >> d) & 1;
+                            if ((o[d] == -1 && bit != 1) || (o[d] == 1 && bit != 0)) touch = false;
+                        }
+                        if (!touch) continue;
+                        const int32_t ch = t.child[(size_t)v * 8 + c];
+                        if (ch < 0 || !(t.info[(size_t)ch].flags & FLAG_LEAF) || refine[(size_t)ch]) ok = false;
+                    }
+                }
+        if (ok) coarsen[(size_t)p] = 1;
     }
+    counts[0] = counts[1] = 0;
+    for (int64_t m = 0; m < t.n_boxes; m++) {
+        counts[0] += refine[(size_t)m];
+        counts[1] += coarsen[(size_t)m];
+    }
+    emit_leaves(lk, refine, coarsen, level, idx);
     return AFMG_OK;
 }
 
