@@ -713,6 +713,70 @@ def operators_bench(args, A, torch, dev, stream):
     return out
 
 
+def adapt_bench(args, A, torch, dev, stream):
+    """Mesh adaptation (paper §2.3) on the adaptive octree workload (about
+    2.3e7 unknowns): after its FP64 solve the four sources move by 0.02 in
+    x; cells are flagged for refinement where the moved source's |lap u| h^2
+    exceeds 1e-4 (the workload's own criterion, on leaves above its deepest
+    level) and for derefinement where it is below 1e-6.  Timed: afmg_tree_adapt (device flag reduction, host
+    rules, new tree) and afmg_tree_transfer of the solution (whole calls,
+    median).  Bytes of the transfer by model: the caller's field read and
+    converted (16 B per old leaf cell), the old boxes of levels >= 2
+    restricted into their parents (9 B per cell), every new leaf cell read
+    from its source and written (16 B, an upper bound: a prolonged cell reads
+    1 B of its parent), the new boxes restricted (9 B per cell) and
+    converted to the caller's order (16 B per cell)."""
+    from paper_1701_04329_amd import workloads as W
+
+    t0 = time.perf_counter()
+    w = W.config3()
+    tree = A.Tree(w.dim, w.level, w.idx)
+    rho = tree.leaf_to_boxes(torch.tensor(w.rho, device=dev))
+    bc = tree.bc_rows(torch.tensor(w.bc, device=dev))
+    u, st = A.solve(tree, rho, bc, None, cycle="FMG", tol=1e-10, stream=stream)
+    moved = W.GaussMix(w.mix.centres + np.array([0.02, 0.0, 0.0]), w.mix.sigmas, w.mix.amps)
+    xc = W.cell_centres(w.dim, w.N, w.level, w.idx)
+    crit = np.abs(moved.laplacian(xc)) * (W.box_h(w.level, w.N)[:, None] ** 2)
+    del xc
+    # the workload's deepest level stays the deepest (as when it was built)
+    fine = (w.level < w.lmax)[:, None]
+    flags = np.where((crit > 1e-4) & fine, 1, np.where(crit < 1e-6, -1, 0)).astype(np.int8)
+    del crit
+    fl = tree.leaf_to_boxes(torch.tensor(flags, device=dev)).contiguous()
+    gen_s = time.perf_counter() - t0
+    n = max(args.steps, 5)
+    ta = []
+    for _ in range(n + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nt, counts = A.adapt(tree, fl, n_buf=2, stream=stream)
+        ta.append(time.perf_counter() - t0)
+    out_u = torch.empty((nt.n_boxes, nt.cells_per_box), dtype=torch.float64, device=dev)
+    tt = []
+    for _ in range(n + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        A.transfer(tree, nt, u, bc, out=out_u, stream=stream)
+        tt.append(time.perf_counter() - t0)
+    ms_a = float(np.median(ta[1:])) * 1e3
+    ms_t = float(np.median(tt[1:])) * 1e3
+    C = tree.cells_per_box
+    n_old_leaf, n_new_leaf = tree.n_leaves * C, nt.n_leaves * C
+    roots = len(tree.level_list(1))
+    bytes_model = (16.0 * n_old_leaf + 9.0 * C * (tree.n_boxes - roots) + 16.0 * n_new_leaf
+                   + 9.0 * C * (nt.n_boxes - roots) + 16.0 * C * nt.n_boxes)
+    return {"workload": "c3_adaptive_moved_sources", "old_leaves": int(tree.n_leaves), "new_leaves": int(nt.n_leaves),
+            "old_unknowns": int(tree.n_unknowns), "new_unknowns": int(nt.n_unknowns),
+            "boxes_refined": int(counts[0]), "boxes_coarsened": int(counts[1]), "n_buf": 2,
+            "adapt_ms_median": ms_a, "transfer_ms_median": ms_t, "calls": n,
+            "transfer_bytes_model": bytes_model,
+            "transfer_GBs_model": round(bytes_model / (ms_t * 1e-3) / 1e9, 1),
+            "transfer_frac_model": round(bytes_model / (ms_t * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+            "setup_s": round(gen_s, 1),
+            "note": "whole calls with their host work and synchronisation; adapt = device flag reduction, the rules "
+                    "on the host, the new tree's tables"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -744,6 +808,9 @@ def main():
                     help="skip the variable-coefficient / cylindrical operator workloads")
     ap.add_argument("--operators-only", action="store_true",
                     help="run only the operator workloads and print their record")
+    ap.add_argument("--no-adapt", action="store_true", help="skip the mesh adaptation workload")
+    ap.add_argument("--adapt-only", action="store_true",
+                    help="run only the mesh adaptation workload and print its record")
     ap.add_argument("--oracle-worker", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--oracle-full", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--oracle-sample", type=int, default=0, help=argparse.SUPPRESS)
@@ -781,6 +848,9 @@ def main():
         return 0
     if args.operators_only:
         print(json.dumps(operators_bench(args, A, torch, dev, torch.cuda.current_stream(dev))), flush=True)
+        return 0
+    if args.adapt_only:
+        print(json.dumps(adapt_bench(args, A, torch, dev, torch.cuda.current_stream(dev))), flush=True)
         return 0
 
     if args.solve_only:
@@ -974,6 +1044,8 @@ def main():
         out["paper_ex"] = paper_ex_bench(args, A, torch, dev, stream)
     if not args.no_operators:
         out["operators"] = operators_bench(args, A, torch, dev, stream)
+    if not args.no_adapt:
+        out["adapt"] = adapt_bench(args, A, torch, dev, stream)
     if not args.no_cpu_baseline:
         uo, out["cpu_baseline"] = cpu_baseline(w, solve_kw, args.workload)
         nrm = np.linalg.norm(uo)

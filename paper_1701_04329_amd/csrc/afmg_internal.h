@@ -98,6 +98,9 @@ constexpr int ADAPT_REFINE = 1, ADAPT_REMOVE = 2;
 constexpr int adapt_dir_bit(int dx, int dy, int dz) { return 1 << (2 + (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)); }
 int adapt_leaves(const HostTree &t, const int32_t *words, std::vector<int32_t> &level, std::vector<int32_t> &idx,
                  int64_t counts[2], std::string &msg);
+// Morton index of box m on its level (boxes of a level of one tree are in
+// increasing Morton order; a parent's index is a child's shifted right by D)
+uint64_t box_morton(const HostTree &t, int64_t m);
 // the position (l, q) inside a single tree's domain (periodic axes wrapped),
 // false outside it or in a lattice position without a level-1 box
 bool domain_position(const HostTree &t, int l, int q[3]);

@@ -19,7 +19,6 @@
 #include <cstring>
 #include <mutex>
 #include <string>
-#include <unordered_map>
 
 #include "afmg.h"
 #include "afmg_internal.h"
@@ -1563,31 +1562,31 @@ int transfer(afmg_tree *from, afmg_tree *to, hipStream_t st, const double *u_fro
     const int64_t C = cells_per_box(D), F = cells_per_face(D);
     // the box lists: a leaf of `to` that is a box of `from` takes its values
     // (the mean of its children if it was refined there); a new leaf is
-    // prolonged from its parent, a leaf of `from`
-    std::unordered_map<uint64_t, int32_t> from_box;
-    from_box.reserve((size_t)hf.n_boxes * 2);
-    auto key = [](int l, int i, int j, int k) {
-        return ((uint64_t)l << 58) ^ ((uint64_t)(uint32_t)i << 38) ^ ((uint64_t)(uint32_t)j << 19) ^ (uint64_t)(uint32_t)k;
-    };
-    for (int64_t m = 0; m < hf.n_boxes; m++)
-        from_box.emplace(key(hf.info[(size_t)m].level, hf.ix[(size_t)m], hf.iy[(size_t)m], hf.iz[(size_t)m]), (int32_t)m);
+    // prolonged from its parent, a leaf of `from`.  Both trees hold each level
+    // in increasing Morton order, so one merge per level finds the boxes.
+    std::vector<uint64_t> kf((size_t)hf.n_boxes);
+    for (int64_t m = 0; m < hf.n_boxes; m++) kf[(size_t)m] = box_morton(hf, m);
     std::vector<int32_t> cdst, csrc, pdst, psrc;
-    for (int64_t m = 0; m < ht.n_boxes; m++) {
-        if (!(ht.info[(size_t)m].flags & FLAG_LEAF)) continue;
-        const int l = ht.info[(size_t)m].level;
-        auto it = from_box.find(key(l, ht.ix[(size_t)m], ht.iy[(size_t)m], ht.iz[(size_t)m]));
-        if (it != from_box.end()) {
-            cdst.push_back((int32_t)m);
-            csrc.push_back(it->second);
-            continue;
+    for (int l = 1; l <= ht.lmax; l++) {
+        int64_t a = l <= hf.lmax ? hf.lvl_off[(size_t)l] : 0, a_end = l <= hf.lmax ? hf.lvl_off[(size_t)l + 1] : 0;
+        int64_t p = l - 1 >= 1 && l - 1 <= hf.lmax ? hf.lvl_off[(size_t)l - 1] : 0;
+        const int64_t p_end = l - 1 >= 1 && l - 1 <= hf.lmax ? hf.lvl_off[(size_t)l] : 0;
+        for (int64_t m = ht.lvl_off[(size_t)l]; m < ht.lvl_off[(size_t)l + 1]; m++) {
+            if (!(ht.info[(size_t)m].flags & FLAG_LEAF)) continue;
+            const uint64_t km = box_morton(ht, m);
+            while (a < a_end && kf[(size_t)a] < km) a++;
+            if (a < a_end && kf[(size_t)a] == km) {
+                cdst.push_back((int32_t)m);
+                csrc.push_back((int32_t)a);
+                continue;
+            }
+            const uint64_t kp = km >> D;
+            while (p < p_end && kf[(size_t)p] < kp) p++;
+            if (p >= p_end || kf[(size_t)p] != kp || !(hf.info[(size_t)p].flags & FLAG_LEAF))
+                return fail(AFMG_ERR_ARG, "a leaf of the target lies two or more levels below the source's leaves");
+            pdst.push_back((int32_t)m);
+            psrc.push_back((int32_t)p);
         }
-        auto ip = l > 1 ? from_box.find(key(l - 1, (ht.ix[(size_t)m] + 1) / 2, (ht.iy[(size_t)m] + 1) / 2,
-                                            D == 3 ? (ht.iz[(size_t)m] + 1) / 2 : 1))
-                        : from_box.end();
-        if (ip == from_box.end() || !(hf.info[(size_t)ip->second].flags & FLAG_LEAF))
-            return fail(AFMG_ERR_ARG, "a leaf of the target lies two or more levels below the source's leaves");
-        pdst.push_back((int32_t)m);
-        psrc.push_back(ip->second);
     }
     int32_t *lists = (int32_t *)(ws + L.lists);
     std::vector<int32_t> all;

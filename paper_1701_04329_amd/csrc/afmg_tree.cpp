@@ -60,6 +60,10 @@ uint64_t morton(int dim, int i, int j, int k) {
 
 }  // namespace
 
+uint64_t box_morton(const HostTree &t, int64_t m) {
+    return morton(t.dim, t.ix[(size_t)m], t.iy[(size_t)m], t.iz[(size_t)m]);
+}
+
 bool domain_position(const HostTree &t, int l, int q[3]) {
     int r[3] = {1, 1, 1};
     for (int d = 0; d < t.dim; d++) {
