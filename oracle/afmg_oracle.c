@@ -26,6 +26,12 @@
  *   restriction  averaging over the 2^D children (paper §2.5); in the
  *                cylindrical form the mean over the parent cell's volume
  *   prolongation 2-1-1 interpolation (paper §2.5)
+ *   schemes      the refinement-boundary ghost of paper §3.3 (the default,
+ *                from the two closest fine values) or its bilinear
+ *                extrapolation variant; 2-1-1 or bi/trilinear prolongation
+ *                (paper §2.5), the latter with edge and corner ghosts
+ *                copied from a diagonal neighbour or extrapolated as
+ *                b + c - a (paper §2.4)
  *   operators    the Laplacian, or div(eps grad u) with eps per cell and the
  *                harmonic mean of the two cells' eps on each face (paper
  *                §3.4), or the cylindrical (r, z) form of either (paper §3.5,
@@ -75,6 +81,10 @@ typedef struct {
     int nroot;      /* level-1 boxes */
     int opk;        /* operator: OR_OP_* bits, 0 for the Laplacian */
     double *eps;    /* eps per cell with ghosts (OR_OP_EPS), else NULL */
+    int ghost_bil;  /* 1: bilinear-extrapolation refinement ghosts */
+    int prolong_lin;/* 1: bi/trilinear prolongation (edge and corner ghosts filled) */
+    int *dnbr;      /* [nbox*27]: same-level box across direction (dx,dy,dz), index
+                       (dx+1) + 3 (dy+1) + 9 (dz+1), -1 if none */
 } otree;
 
 /* ------------------------------------------------------------------------ */
@@ -261,6 +271,7 @@ void *or_tree_new_bc(int dim, int N, const int32_t *bctype, int64_t n_leaves, co
     t->iz = malloc(sizeof(int) * B); t->n = malloc(sizeof(int) * B); t->parent = malloc(sizeof(int) * B);
     t->leaf = malloc(sizeof(int) * B); t->child = malloc(sizeof(int) * B * 8);
     t->nbr = malloc(sizeof(int) * B * 6); t->off = malloc(sizeof(int64_t) * B);
+    t->dnbr = malloc(sizeof(int) * B * 27);
     t->bcoff = malloc(sizeof(int64_t) * B * 6);
     int *newid = malloc(sizeof(int) * nb);
     int pos = ncoarse;
@@ -342,12 +353,35 @@ void *or_tree_new_bc(int dim, int N, const int32_t *bctype, int64_t n_leaves, co
             }
         }
     }
+    /* same-level boxes across every direction (sides, edges, corners;
+       periodic axes wrapped), for edge and corner ghosts */
+    for (int b = ncoarse; b < B; b++) {
+        int l = t->lev[b];
+        for (int o = 0; o < 27; o++) {
+            int dd[3] = {o % 3 - 1, (o / 3) % 3 - 1, o / 9 - 1};
+            t->dnbr[27 * b + o] = -1;
+            if (dim == 2 && dd[2] != 0) continue;
+            int q[3] = {t->ix[b] + dd[0], t->iy[b] + dd[1], t->iz[b] + dd[2]}, inside = 1;
+            for (int d = 0; d < dim; d++) {
+                int n1 = t->ext[d] << (l - 1);
+                if (q[d] < 1 || q[d] > n1) {
+                    if (bct[2 * d] != OR_PERIODIC) inside = 0;
+                    else q[d] = q[d] < 1 ? n1 : 1;
+                }
+            }
+            if (inside) t->dnbr[27 * b + o] = oh_get(&h, okey(l, q[0], q[1], q[2]));
+        }
+    }
     /* neighbours on the coarse grids below level 1 mirror those of the roots */
     for (int b = 0; b < ncoarse; b++) {
         int r = b % nroot, l = t->lev[b];
         for (int s = 0; s < 6; s++) {
             int v = t->nbr[6 * (ncoarse + r) + s];
             t->nbr[6 * b + s] = v >= 0 ? (l - t->lmin) * nroot + (v - ncoarse) : -1;
+        }
+        for (int o = 0; o < 27; o++) {
+            int v = t->dnbr[27 * (ncoarse + r) + o];
+            t->dnbr[27 * b + o] = v >= 0 ? (l - t->lmin) * nroot + (v - ncoarse) : -1;
         }
     }
     /* level lists */
@@ -407,7 +441,7 @@ void or_tree_free(void *p) {
     otree *t = (otree *)p;
     if (!t) return;
     free(t->lev); free(t->ix); free(t->iy); free(t->iz); free(t->n); free(t->parent);
-    free(t->leaf); free(t->child); free(t->nbr); free(t->off); free(t->bcoff);
+    free(t->leaf); free(t->child); free(t->nbr); free(t->off); free(t->bcoff); free(t->dnbr);
     free(t->leaf_box); free(t->lvl_store);
     free(t->u); free(t->rho); free(t->uold); free(t->res); free(t->bc); free(t->eps);
     free(t);
@@ -546,6 +580,66 @@ static void set_bc(otree *t, const double *bc_leaf) {
 /* ------------------------------------------------------------------------ */
 /* ghost cells (paper §2.4, §3.3)                                            */
 /* ------------------------------------------------------------------------ */
+/* Edge (3D) and corner ghosts of every box at level l (paper §2.4): copied
+   from the same-level box across that edge or corner when there is one,
+   otherwise extrapolated linearly from the box's own side ghosts and cells:
+   an edge or 2D corner ghost is b + c - a (b, c: the two values that share
+   it with the inner cell a), a 3D corner ghost is the sum of its three
+   edge ghosts minus its three side ghosts plus the inner cell (the same
+   linear extrapolation applied along all three axes).  Side ghosts must be
+   filled; edges are filled before corners. */
+static void fill_gc_corners(otree *t, int l, double *f) {
+    int D = t->dim;
+    for (int pass = 2; pass <= D; pass++) /* edges (2 axes outside), then corners */
+        for (int m = 0; m < lvl_count(t, l); m++) {
+            int b = lvl_box(t, l, m), n = t->n[b];
+            for (int o = 0; o < 27; o++) {
+                int dd[3] = {o % 3 - 1, (o / 3) % 3 - 1, o / 9 - 1};
+                if (D == 2 && dd[2] != 0) continue;
+                int nout = (dd[0] != 0) + (dd[1] != 0) + (dd[2] != 0);
+                if (nout != pass) continue;
+                int v = t->dnbr[27 * b + o];
+                int lo[3], hi[3];
+                for (int d = 0; d < 3; d++) {
+                    if (d >= D) { lo[d] = hi[d] = 1; continue; }
+                    lo[d] = dd[d] == -1 ? 0 : dd[d] == 1 ? n + 1 : 1;
+                    hi[d] = dd[d] == -1 ? 0 : dd[d] == 1 ? n + 1 : n;
+                }
+                for (int k = lo[2]; k <= hi[2]; k++)
+                    for (int j = lo[1]; j <= hi[1]; j++)
+                        for (int i = lo[0]; i <= hi[0]; i++) {
+                            int g[3] = {i, j, k};
+                            double val;
+                            if (v >= 0) {
+                                int q[3] = {i, j, k};
+                                for (int d = 0; d < D; d++)
+                                    if (dd[d] != 0) q[d] = dd[d] == -1 ? n : 1;
+                                val = f[PX(t, v, q[0], q[1], q[2])];
+                            } else {
+                                /* inclusion-exclusion over the outside axes:
+                                   each value with a subset of them moved one
+                                   cell inward, sign (-1)^(size of subset + 1) */
+                                val = 0.0;
+                                int ax[3], na = 0;
+                                for (int d = 0; d < D; d++)
+                                    if (dd[d] != 0) ax[na++] = d;
+                                for (int sub = 1; sub < (1 << na); sub++) {
+                                    int q[3] = {g[0], g[1], g[2]}, cnt = 0;
+                                    for (int a = 0; a < na; a++)
+                                        if (sub & (1 << a)) {
+                                            q[ax[a]] += dd[ax[a]] == -1 ? 1 : -1;
+                                            cnt++;
+                                        }
+                                    double w = (cnt % 2) ? 1.0 : -1.0;
+                                    val += w * f[PX(t, b, q[0], q[1], q[2])];
+                                }
+                            }
+                            f[PX(t, b, g[0], g[1], g[2])] = val;
+                        }
+            }
+        }
+}
+
 /* Fill the side ghosts of every box at level l for field f.  homog != 0
    uses zero Dirichlet values. */
 static void fill_gc(otree *t, int l, double *f, int homog) {
@@ -593,18 +687,41 @@ static void fill_gc(otree *t, int l, double *f, int homog) {
                         int p1[3] = {c1[0], c1[1], c1[2]};
                         p1[t1] = (a % 2) ? a + 1 : a - 1; /* partner inside the same coarse cell */
                         double u1p = f[PX(t, b, p1[0], p1[1], p1[2])];
+                        int q1[3] = {c2[0], c2[1], c2[2]};
+                        q1[t1] = p1[t1];
+                        double u2p = f[PX(t, b, q1[0], q1[1], q1[2])]; /* partner of u2 */
                         if (D == 2) {
-                            f[ig] = 0.5 * uH + u1 - 0.25 * (u1p + u2);
+                            if (t->ghost_bil) /* bilinear extrapolation (paper §3.3) */
+                                f[ig] = 0.5 * uH + 1.125 * u1 - 0.375 * (u1p + u2) + 0.125 * u2p;
+                            else
+                                f[ig] = 0.5 * uH + u1 - 0.25 * (u1p + u2);
                         } else {
                             int p2[3] = {c1[0], c1[1], c1[2]};
                             p2[t2] = (c % 2) ? c + 1 : c - 1;
                             double u1pp = f[PX(t, b, p2[0], p2[1], p2[2])];
-                            f[ig] = 0.5 * uH + 1.25 * u1 - 0.25 * (u2 + u1p + u1pp);
+                            if (t->ghost_bil) {
+                                /* trilinear extrapolation: the 2D scheme's
+                                   construction with one more tangential axis */
+                                int p3[3] = {p1[0], p1[1], p1[2]};
+                                p3[t2] = p2[t2];
+                                int q2[3] = {c2[0], c2[1], c2[2]}, q3[3] = {c2[0], c2[1], c2[2]};
+                                q2[t2] = p2[t2];
+                                q3[t1] = p1[t1];
+                                q3[t2] = p2[t2];
+                                double u1ppp = f[PX(t, b, p3[0], p3[1], p3[2])];
+                                double u2pp = f[PX(t, b, q2[0], q2[1], q2[2])];
+                                double u2ppp = f[PX(t, b, q3[0], q3[1], q3[2])];
+                                f[ig] = 0.5 * uH + (27.0 / 16.0) * u1 - (9.0 / 16.0) * (u2 + u1p + u1pp) +
+                                        (3.0 / 16.0) * (u2p + u2pp + u1ppp) - (1.0 / 16.0) * u2ppp;
+                            } else {
+                                f[ig] = 0.5 * uH + 1.25 * u1 - 0.25 * (u2 + u1p + u1pp);
+                            }
                         }
                     }
                 }
         }
     }
+    if (t->prolong_lin) fill_gc_corners(t, l, f);
 }
 
 /* sum of the 2D side neighbours of cell (i,j,k) (ghosts included) */
@@ -819,7 +936,21 @@ static void prolong_correct_box(otree *t, int b) {
         int s[3] = {(i & 1) ? -1 : 1, (j & 1) ? -1 : 1, (k & 1) ? -1 : 1};
 #define DEL(a, bb, cc) (t->u[PX(t, p, a, bb, cc)] - t->uold[PX(t, p, a, bb, cc)])
         double v;
-        if (t->opk & OR_OP_PROLONG_EPS) {
+        if (t->prolong_lin) {
+            /* bi/trilinear: weights 3/4 and 1/4 per axis over the 2^D
+               nearest coarse cells (edge and corner ghosts included) */
+            if (D == 2) {
+                v = 0.5625 * DEL(P[0], P[1], 1) + 0.1875 * DEL(P[0] + s[0], P[1], 1) +
+                    0.1875 * DEL(P[0], P[1] + s[1], 1) + 0.0625 * DEL(P[0] + s[0], P[1] + s[1], 1);
+            } else {
+                v = 0.421875 * DEL(P[0], P[1], P[2]) +
+                    0.140625 * (DEL(P[0] + s[0], P[1], P[2]) + DEL(P[0], P[1] + s[1], P[2]) +
+                                DEL(P[0], P[1], P[2] + s[2])) +
+                    0.046875 * (DEL(P[0] + s[0], P[1] + s[1], P[2]) + DEL(P[0] + s[0], P[1], P[2] + s[2]) +
+                                DEL(P[0], P[1] + s[1], P[2] + s[2])) +
+                    0.015625 * DEL(P[0] + s[0], P[1] + s[1], P[2] + s[2]);
+            }
+        } else if (t->opk & OR_OP_PROLONG_EPS) {
             double d0 = DEL(P[0], P[1], P[2]), e0 = t->eps[PX(t, p, P[0], P[1], P[2])];
             v = d0;
             for (int d = 0; d < D; d++) {
@@ -1103,16 +1234,18 @@ int or_num_threads(void) { return omp_get_max_threads(); }
 int or_set_operator(void *p, int kind, const double *eps_leaf, int prolong) {
     otree *t = (otree *)p;
     if (kind < 0 || kind > (OR_OP_EPS | OR_OP_CYL)) { seterr(NULL, 0, "bad operator kind"); return -1; }
+    if (prolong < 0 || prolong > 2) { seterr(NULL, 0, "bad prolongation"); return -1; }
     if ((kind & OR_OP_CYL) && t->dim != 2) { seterr(NULL, 0, "the cylindrical operator is 2D (r, z)"); return -1; }
     if ((kind & OR_OP_EPS) && !eps_leaf) { seterr(NULL, 0, "eps missing"); return -1; }
-    if (prolong && !(kind & OR_OP_EPS)) { seterr(NULL, 0, "the eps prolongation needs eps"); return -1; }
+    if (prolong == 1 && !(kind & OR_OP_EPS)) { seterr(NULL, 0, "the eps prolongation needs eps"); return -1; }
     int64_t nc = t->dim == 3 ? (int64_t)t->N * t->N * t->N : (int64_t)t->N * t->N;
     if (kind & OR_OP_EPS)
         for (int64_t i = 0; i < nc * t->nleaf_in; i++)
             if (!(eps_leaf[i] > 0.0) || !isfinite(eps_leaf[i])) { seterr(NULL, 0, "eps must be positive and finite"); return -1; }
     free(t->eps);
     t->eps = NULL;
-    t->opk = kind | (prolong ? OR_OP_PROLONG_EPS : 0);
+    t->opk = kind | (prolong == 1 ? OR_OP_PROLONG_EPS : 0);
+    t->prolong_lin = prolong == 2;
     if (!(kind & OR_OP_EPS)) return 0;
     t->eps = calloc(t->ntot, sizeof(double));
     load_leaf_field(t, t->eps, eps_leaf);
@@ -1142,9 +1275,19 @@ static int64_t leaf_unknown(const otree *t, const int *leaf_of_box, int b, int i
     return (int64_t)q * (t->dim == 3 ? (int64_t)N * N * N : (int64_t)N * N) + cell;
 }
 
+/* Refinement-boundary ghost scheme of later solves: 0 the default (from the
+   two closest fine values), 1 bilinear (3D: trilinear) extrapolation (paper
+   §3.3).  Both keep the coarse flux equal to the mean of the fine fluxes. */
+int or_set_ghost_scheme(void *p, int scheme) {
+    otree *t = (otree *)p;
+    if (scheme != 0 && scheme != 1) { seterr(NULL, 0, "bad ghost scheme"); return -1; }
+    t->ghost_bil = scheme;
+    return 0;
+}
+
 int64_t or_assemble_L(void *p, int32_t *rows, int32_t *cols, double *vals) {
     otree *t = (otree *)p;
-    if (t->opk) { seterr(NULL, 0, "assembly covers the Laplacian only"); return -1; }
+    if (t->opk || t->ghost_bil) { seterr(NULL, 0, "assembly covers the Laplacian with the default ghosts only"); return -1; }
     int D = t->dim, N = t->N;
     int *leaf_of_box = malloc(sizeof(int) * t->nbox);
     for (int b = 0; b < t->nbox; b++) leaf_of_box[b] = -1;

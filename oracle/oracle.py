@@ -101,6 +101,8 @@ def lib():
         L.or_assemble_L.restype = C.c_int64
         L.or_set_operator.argtypes = [vp, C.c_int, dp, C.c_int]
         L.or_set_operator.restype = C.c_int
+        L.or_set_ghost_scheme.argtypes = [vp, C.c_int]
+        L.or_set_ghost_scheme.restype = C.c_int
         _lib = L
     return _lib
 
@@ -114,6 +116,9 @@ FIELD = {"u": 0, "rho": 1, "uold": 2, "res": 3, "eps": 4}
 # operators (paper §3.4, §3.5): bit 1 a coefficient eps per cell with the
 # harmonic mean on faces, bit 2 the cylindrical (r, z) form (2D, x = r)
 OPERATORS = {"laplacian": 0, "eps": 1, "cyl": 2, "cyl_eps": 3}
+# prolongations (paper §2.5 and §3.5) and refinement-boundary ghosts (§3.3)
+PROLONGS = {"default": 0, "eps": 1, "linear": 2}
+GHOSTS = {"default": 0, "bilinear": 1}
 
 
 class OracleError(RuntimeError):
@@ -220,13 +225,21 @@ class Tree:
     def set_operator(self, kind="laplacian", eps=None, prolong="default"):
         """Operator of later solves and steps: "laplacian", "eps" (div(eps
         grad u)), "cyl" (cylindrical (r, z)) or "cyl_eps"; eps [n_leaves,
-        N^D] > 0 per leaf cell; prolong "default" or "eps" (eps-weighted)."""
+        N^D] > 0 per leaf cell; prolong "default" (2-1-1), "eps"
+        (eps-weighted) or "linear" (bi/trilinear with edge and corner
+        ghosts)."""
         code = OPERATORS[kind] if isinstance(kind, str) else int(kind)
         e = None if eps is None else self._leaf_arr(eps, "eps")
-        rc = lib().or_set_operator(self.h, code, _dp(e), 1 if prolong == "eps" else 0)
+        rc = lib().or_set_operator(self.h, code, _dp(e), PROLONGS[prolong])
         if rc != 0:
             raise OracleError(lib().or_last_error().decode())
         self.operator = (code, prolong)
+
+    def set_ghost_scheme(self, scheme="default"):
+        """Refinement-boundary ghosts: "default" or "bilinear"."""
+        if lib().or_set_ghost_scheme(self.h, GHOSTS[scheme]) != 0:
+            raise OracleError(lib().or_last_error().decode())
+        self.ghost_scheme = scheme
 
     def apply_L(self, u, bc=None, homog=True):
         u = self._leaf_arr(u, "u")
@@ -317,8 +330,8 @@ def assemble_L(tree):
     """Sparse matrix (scipy CSR) of the homogeneous composite operator on the
     leaf unknowns, numbered q * N^D + cell in the caller's leaf order."""
     import scipy.sparse as sp
-    if getattr(tree, "operator", (0,))[0]:
-        raise OracleError("the sparse assembly covers the Laplacian only")
+    if getattr(tree, "operator", (0,))[0] or getattr(tree, "ghost_scheme", "default") != "default":
+        raise OracleError("the sparse assembly covers the Laplacian with the default ghosts only")
     r, c, v = _assemble(tree)
     n = tree.n_leaves * tree.cells_per_box
     return sp.csr_matrix((v, (r, c)), shape=(n, n))

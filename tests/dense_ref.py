@@ -42,12 +42,17 @@ from __future__ import annotations
 import numpy as np
 
 
-def assemble(dim, N, level, idx, bc=None, bc_type=None, eps=None, cyl=False):
+def assemble(dim, N, level, idx, bc=None, bc_type=None, eps=None, cyl=False, ghost="default"):
     """Return (A, g) with A u = rho - g for the leaf unknowns in leaf-list
     order (x fastest within each leaf), g the boundary part.  bc_type: None
     (all Dirichlet), one name or 2D names among "dirichlet", "neumann",
     "periodic".  eps: [n_leaves, N^D] cell coefficients (None: 1); cyl: the
-    cylindrical (r, z) form (2D)."""
+    cylindrical (r, z) form (2D); ghost: "default" or "bilinear", the
+    bilinear-extrapolation refinement ghost of paper §3.3: in 2D
+    1/2 u_H + 9/8 u_c - 3/8 (u_p + u_c2) + 1/8 u_c2p, in 3D the same
+    construction with one more tangential axis,
+    1/2 u_H + 27/16 u_c - 9/16 (u_c2 + u_p + u_q) + 3/16 (u_c2p + u_c2q + u_pq)
+    - 1/16 u_c2pq (p, q: partner along the first, second tangential axis)."""
     level = np.asarray(level)
     idx = np.asarray(idx)
     n_leaf = len(level)
@@ -198,6 +203,27 @@ def assemble(dim, N, level, idx, bc=None, bc_type=None, eps=None, cyl=False):
                         Gp[e] ^= 1
                         partners.append(cell_unknown(l, Gp))
                     A[row, cH] += 0.5 * wf
+                    if ghost == "bilinear":
+                        def cell(G0, flips):
+                            Gq = list(G0)
+                            for e in flips:
+                                Gq[e] ^= 1
+                            return cell_unknown(l, Gq)
+                        if dim == 2:
+                            e1 = tang[0]
+                            A[row, row] += 1.125 * wf
+                            A[row, partners[0]] -= 0.375 * wf
+                            A[row, c2] -= 0.375 * wf
+                            A[row, cell(G2, [e1])] += 0.125 * wf
+                        else:
+                            e1, e2 = tang
+                            A[row, row] += 27.0 / 16.0 * wf
+                            for c_ in (c2, partners[0], partners[1]):
+                                A[row, c_] -= 9.0 / 16.0 * wf
+                            for c_ in (cell(G2, [e1]), cell(G2, [e2]), cell(G, [e1, e2])):
+                                A[row, c_] += 3.0 / 16.0 * wf
+                            A[row, cell(G2, [e1, e2])] -= 1.0 / 16.0 * wf
+                        continue
                     if dim == 2:
                         A[row, row] += 1.0 * wf
                         A[row, partners[0]] -= 0.25 * wf
