@@ -141,6 +141,7 @@ typedef struct {
                          constant and rho must be compatible */
     int op;           /* afmg_operator set by afmg_tree_set_operator */
     int prolong;      /* afmg_prolong set by afmg_tree_set_operator */
+    int ghost;        /* afmg_ghost set by afmg_tree_set_ghost_scheme */
 } afmg_tree_desc;
 
 /* Side types of the domain boundary (paper §3), per orientation -x, +x, -y,
@@ -248,11 +249,17 @@ int afmg_tree_finalize(afmg_tree *tree, void *stream);
  *                       weight 0; restriction is the mean over the parent
  *                       cell's volume (children weighted by radius).
  *   AFMG_OPERATOR_CYL_EPS both (the paper's §4.1 case 2).
- * prolong: AFMG_PROLONG_DEFAULT (the 2-1-1 interpolation of §2.5) or
+ * prolong: AFMG_PROLONG_DEFAULT (the 2-1-1 interpolation of §2.5),
  * AFMG_PROLONG_EPS (needs eps): per axis the fine cell moves from its coarse
  * cell P towards P + s e_d by eps_d / (2 (eps_P + eps_d)) of the difference,
  * the piecewise-linear profile with continuous value and flux eps du/dn
- * (the local reconstruction of §3.4; with equal eps the default weights).
+ * (the local reconstruction of §3.4; with equal eps the default weights),
+ * or AFMG_PROLONG_LINEAR: bilinear (3D: trilinear) interpolation from the
+ * 2^D nearest coarse cells (§2.5), whose edge and corner ghosts are copied
+ * from the same-level box across that edge or corner or else extrapolated
+ * linearly, b + c - a (§2.4; a 3D corner: its three edge ghosts minus its
+ * three side ghosts plus the inner cell).  Any operator, the Laplacian
+ * included, takes any prolongation but AFMG_PROLONG_EPS (eps needed).
  *   eps     device, [n_boxes][N^D] FP64 in the layout of rho (x fastest;
  *           only leaf boxes are read), positive and finite; NULL unless the
  *           operator has eps.  Copied: the caller may free it on return.
@@ -323,8 +330,28 @@ typedef enum {
     AFMG_OPERATOR_CYL = 2,
     AFMG_OPERATOR_CYL_EPS = 3
 } afmg_operator;
-typedef enum { AFMG_PROLONG_DEFAULT = 0, AFMG_PROLONG_EPS = 1 } afmg_prolong;
+typedef enum { AFMG_PROLONG_DEFAULT = 0, AFMG_PROLONG_EPS = 1, AFMG_PROLONG_LINEAR = 2 } afmg_prolong;
 int afmg_tree_set_operator(afmg_tree *tree, void *stream, int op, const double *eps, int prolong);
+
+/*
+ * Refinement-boundary ghost scheme of the tree's later solves and steps
+ * (paper §3.3): AFMG_GHOST_DEFAULT, from the two closest fine values
+ * (2D 1/2 u_H + u1 - 1/4 (u1p + u2), 3D 1/2 u_H + 5/4 u1 - 1/4 (u2 + u1p +
+ * u1q)), or AFMG_GHOST_BILINEAR, bilinear extrapolation (2D 1/2 u_H +
+ * 9/8 u1 - 3/8 (u1p + u2) + 1/8 u2p), whose 3D form extends the
+ * construction by the second tangential axis: 1/2 u_H + 27/16 u1
+ * - 9/16 (u2 + u1p + u1q) + 3/16 (u2p + u2q + u1pq) - 1/16 u2pq.  Here u1 is
+ * the face cell, u2 the next inward, and p, q, pq mark the partner inside
+ * the same coarse cell along the first, the second and both tangential
+ * axes.  Both keep the coarse flux across a refinement boundary equal to
+ * the mean of the fine fluxes.  A tree with a scheme other than the
+ * default takes the operator kernels (as afmg_tree_set_operator: general
+ * coarse path, FP64, default launch shapes; the adjoint, afmg_apply, the
+ * autotuner and batches reject it).  afmg_tree_transfer keeps the default
+ * scheme.  Errors: AFMG_ERR_ARG (null, a batch, a bad scheme), AFMG_ERR_HIP.
+ */
+typedef enum { AFMG_GHOST_DEFAULT = 0, AFMG_GHOST_BILINEAR = 1 } afmg_ghost;
+int afmg_tree_set_ghost_scheme(afmg_tree *tree, void *stream, int scheme);
 
 /* Box lists per level (paper §2.1): all boxes, parents (refined boxes) or
    leaves of `level` (1 .. lmax), in box-id order, which is Morton order

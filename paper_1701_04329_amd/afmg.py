@@ -89,6 +89,7 @@ class TreeDesc(C.Structure):
         ("singular", C.c_int),
         ("op", C.c_int),
         ("prolong", C.c_int),
+        ("ghost", C.c_int),
     ]
 
 
@@ -142,11 +143,12 @@ EXPORTS = [
     "afmg_tree_set_shape", "afmg_batch_autotune_workspace_bytes", "afmg_batch_autotune", "afmg_batch_shape",
     "afmg_batch_set_shape", "afmg_tree_refine", "afmg_tree_finalize", "afmg_tree_level_list", "afmg_step",
     "afmg_solve_noalloc", "afmg_tree_create_domain", "afmg_tree_set_operator", "afmg_tree_adapt",
-    "afmg_transfer_workspace_bytes", "afmg_tree_transfer",
+    "afmg_transfer_workspace_bytes", "afmg_tree_transfer", "afmg_tree_set_ghost_scheme",
 ]
 # operators (paper §3.4, §3.5) and prolongations of afmg_tree_set_operator
 OPERATORS = {"laplacian": 0, "eps": 1, "cyl": 2, "cyl_eps": 3}
-PROLONGS = {"default": 0, "eps": 1}
+PROLONGS = {"default": 0, "eps": 1, "linear": 2}
+GHOSTS = {"default": 0, "bilinear": 1}
 STEPS = {"half_sweep": 0, "resid_restrict": 1, "coarse_rhs": 2, "prolong": 3, "coarse": 4}
 LISTS = {"all": 0, "parent": 1, "leaf": 2}
 KINDS = {"gsrb": 0, "resid": 1, "coarse_rhs": 2, "prolong": 3, "final": 4}
@@ -208,6 +210,7 @@ def lib():
                                 C.POINTER(Opts)]
         L.afmg_batch_autotune_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
         L.afmg_tree_set_operator.argtypes = [vp, vp, C.c_int, vp, C.c_int]
+        L.afmg_tree_set_ghost_scheme.argtypes = [vp, vp, C.c_int]
         L.afmg_tree_adapt.argtypes = [vp, vp, vp, C.c_int, C.POINTER(vp), C.POINTER(C.c_int64)]
         L.afmg_transfer_workspace_bytes.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
         L.afmg_tree_transfer.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.c_size_t]
@@ -358,7 +361,8 @@ class Tree(_Shapes):
     def set_operator(self, kind="laplacian", eps=None, prolong="default"):
         """Operator of later solves (afmg_tree_set_operator): "laplacian",
         "eps", "cyl" or "cyl_eps"; eps a float64 CUDA tensor [n_boxes, N^D]
-        in box order (leaf boxes read); prolong "default" or "eps"."""
+        in box order (leaf boxes read); prolong "default", "eps" or
+        "linear" (bi/trilinear)."""
         code = OPERATORS[kind] if isinstance(kind, str) else int(kind)
         pro = PROLONGS[prolong] if isinstance(prolong, str) else int(prolong)
         if eps is not None:
@@ -372,6 +376,13 @@ class Tree(_Shapes):
             stream = torch.cuda.current_stream(dev)
             _check(lib().afmg_tree_set_operator(self._h, C.c_void_p(stream.cuda_stream), code, _ptr(eps), pro))
         self.operator = (code, pro)
+
+    def set_ghost_scheme(self, scheme="default"):
+        """Refinement-boundary ghosts of later solves
+        (afmg_tree_set_ghost_scheme): "default" or "bilinear"."""
+        _check(lib().afmg_tree_set_ghost_scheme(self._h, None, GHOSTS[scheme] if isinstance(scheme, str)
+                                                else int(scheme)))
+        self.ghost_scheme = scheme
 
     def level_list(self, level, kind="all"):
         n = C.c_int64()

@@ -98,6 +98,10 @@ constexpr int ADAPT_REFINE = 1, ADAPT_REMOVE = 2;
 constexpr int adapt_dir_bit(int dx, int dy, int dz) { return 1 << (2 + (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)); }
 int adapt_leaves(const HostTree &t, const int32_t *words, std::vector<int32_t> &level, std::vector<int32_t> &idx,
                  int64_t counts[2], std::string &msg);
+// the same-level box across every direction (dx, dy, dz) of every box of a
+// single tree, index (dx+1) + 3 (dy+1) + 9 (dz+1) (periodic axes wrapped),
+// -1 where there is none: [n_boxes][27]
+void diagonal_neighbours(const HostTree &t, std::vector<int32_t> &out);
 // Morton index of box m on its level (boxes of a level of one tree are in
 // increasing Morton order; a parent's index is a child's shifted right by D)
 uint64_t box_morton(const HostTree &t, int64_t m);

@@ -44,6 +44,9 @@ struct LevelArgs {
     const T *eps;
     const int32_t *bx;
     int opk;
+    // OPK_PROLONG_LIN: [n_boxes][27] same-level box across direction
+    // (dx, dy, dz), index (dx+1) + 3 (dy+1) + 9 (dz+1), -1 if none
+    const int32_t *dnbr;
 };
 
 // Operators (paper §3.4, §3.5): a cell's equation is
@@ -53,8 +56,10 @@ struct LevelArgs {
 // coefficient across the side; OPK_CYL: the cylindrical (r, z) form, x = r,
 // the radial sides also carry r_face / r_c, and restriction is the mean over
 // the parent cell's volume (children weighted by radius); OPK_PROLONG_EPS:
-// eps-weighted prolongation.
-constexpr int OPK_EPS = 1, OPK_CYL = 2, OPK_PROLONG_EPS = 4;
+// eps-weighted prolongation; OPK_GHOST_BIL: bilinear-extrapolation
+// refinement-boundary ghosts; OPK_PROLONG_LIN: bi/trilinear prolongation
+// with edge and corner ghosts (diagonal neighbours in LevelArgs::dnbr).
+constexpr int OPK_EPS = 1, OPK_CYL = 2, OPK_PROLONG_EPS = 4, OPK_GHOST_BIL = 8, OPK_PROLONG_LIN = 16;
 
 // Per-tree stop rule of a forest, kept on the device (paper: no error
 // control is built into the method, §3.2; the stop rule is the library's)
@@ -115,6 +120,7 @@ struct CoarseGenArgs {
     const double *eps;
     const int32_t *bx;
     int opk;
+    const int32_t *dnbr;  // OPK_PROLONG_LIN: as in LevelArgs (the roots' rows)
 };
 
 // wg: workgroup size of the launch (64, 128 or 256 threads; W / N^(D-1)

@@ -243,15 +243,43 @@ __device__ __forceinline__ T phys_ghost(bool neumann, T b, T u1, T h) {
 }
 __device__ __forceinline__ bool neumann_side(int flags, int s) { return (flags >> (10 + s)) & 1; }
 
-// finish the ghost from its raw operand; s is the padded box in LDS
-template <int D, int N, int S, typename T>
-__device__ __forceinline__ T ghost_finish(const T *s, int m, T raw, int v, int homog, int flags, T h) {
+// The bilinear-extrapolation variant of the refinement-boundary ghost
+// (paper §3.3): 2D 1/2 uH + 9/8 u1 - 3/8 (u1p + u2) + 1/8 u2p; 3D, the same
+// construction with the second tangential axis,
+// 1/2 uH + 27/16 u1 - 9/16 (u2 + u1p + u1q) + 3/16 (u2p + u2q + u1pq)
+// - 1/16 u2pq (p: partner along t1, q: along t2, pq: both).  at(depth, f1,
+// f2) gives the cell of the box (or octant) at normal depth 0 (face cell)
+// or 1 (next inward), flipped to the partner along t1 (f1) and t2 (f2).
+template <int D, typename T, class At>
+__device__ __forceinline__ T bil_ghost(T uH, const At &at) {
+    const T u1 = at(0, 0, 0), u1p = at(0, 1, 0), u2 = at(1, 0, 0), u2p = at(1, 1, 0);
+    if (D == 2) return T(0.5) * uH + T(1.125) * u1 - T(0.375) * (u1p + u2) + T(0.125) * u2p;
+    const T u1q = at(0, 0, 1), u1pq = at(0, 1, 1), u2q = at(1, 0, 1), u2pq = at(1, 1, 1);
+    return T(0.5) * uH + T(27.0 / 16.0) * u1 - T(9.0 / 16.0) * ((u2 + u1p) + u1q) +
+           T(3.0 / 16.0) * ((u2p + u2q) + u1pq) - T(1.0 / 16.0) * u2pq;
+}
+
+// finish the ghost from its raw operand; s is the padded box in LDS.  RT:
+// the refinement-boundary scheme is chosen at run time (bil = 1: bilinear
+// extrapolation); otherwise the default scheme is compiled in.
+template <int D, int N, int S, typename T, bool RT = false>
+__device__ __forceinline__ T ghost_finish(const T *s, int m, T raw, int v, int homog, int flags, T h, int bil = 0) {
     using SD = SideOf<S>;
     if (v >= 0) return raw;
     int x[3];
     face_cell<D, N, S>(m, x);
     const T u1 = s[padi<D, N>(x[0], x[1], x[2])];
     if (v == -1) return phys_ghost<T>(neumann_side(flags, S), homog ? T(0) : raw, u1, h);
+    if (RT && bil) {
+        auto at = [&](int depth, int f1, int f2) {
+            int c[3] = {x[0], x[1], x[2]};
+            c[SD::d] = SD::hi ? N - 1 - depth : depth;
+            c[SD::t1] ^= f1;
+            if (D == 3) c[SD::t2] ^= f2;
+            return s[padi<D, N>(c[0], c[1], c[2])];
+        };
+        return bil_ghost<D, T>(raw, at);
+    }
     int y[3] = {x[0], x[1], x[2]};
     y[SD::d] = SD::hi ? N - 2 : 1;
     const T u2 = s[padi<D, N>(y[0], y[1], y[2])];
@@ -291,7 +319,7 @@ __device__ __forceinline__ int ghost_slot(int m) {
 // box is ready.  Thread t of the box owns row t (both colours) and face cell t
 // of every side (a side has F == TPB cells).  A kernel issues its other
 // loads between load() and stage(), so that they are in flight together.
-template <int D, int N, typename T>
+template <int D, int N, typename T, bool RT = false>
 struct Stager {
     using G = Geo<D, N>;
     T raw[6];
@@ -299,6 +327,7 @@ struct Stager {
     int hg;
     int fl;  // box flags (Neumann sides)
     T hh;    // cell size (Neumann ghosts)
+    int bil = 0;  // RT: bilinear-extrapolation refinement ghosts
     T rowv[2][G::HN];
 
     __device__ __forceinline__ void load(const BoxInfo &bi, const T *__restrict__ ub, const T *__restrict__ u,
@@ -338,13 +367,13 @@ struct Stager {
         stage(s, t);
     }
     __device__ void end(T *s, int t) {
-        s[ghost_slot<D, N, 0>(t)] = ghost_finish<D, N, 0, T>(s, t, raw[0], v[0], hg, fl, hh);
-        s[ghost_slot<D, N, 1>(t)] = ghost_finish<D, N, 1, T>(s, t, raw[1], v[1], hg, fl, hh);
-        s[ghost_slot<D, N, 2>(t)] = ghost_finish<D, N, 2, T>(s, t, raw[2], v[2], hg, fl, hh);
-        s[ghost_slot<D, N, 3>(t)] = ghost_finish<D, N, 3, T>(s, t, raw[3], v[3], hg, fl, hh);
+        s[ghost_slot<D, N, 0>(t)] = ghost_finish<D, N, 0, T, RT>(s, t, raw[0], v[0], hg, fl, hh, bil);
+        s[ghost_slot<D, N, 1>(t)] = ghost_finish<D, N, 1, T, RT>(s, t, raw[1], v[1], hg, fl, hh, bil);
+        s[ghost_slot<D, N, 2>(t)] = ghost_finish<D, N, 2, T, RT>(s, t, raw[2], v[2], hg, fl, hh, bil);
+        s[ghost_slot<D, N, 3>(t)] = ghost_finish<D, N, 3, T, RT>(s, t, raw[3], v[3], hg, fl, hh, bil);
         if (D == 3) {
-            s[ghost_slot<D, N, 4>(t)] = ghost_finish<D, N, 4, T>(s, t, raw[4], v[4], hg, fl, hh);
-            s[ghost_slot<D, N, 5>(t)] = ghost_finish<D, N, 5, T>(s, t, raw[5], v[5], hg, fl, hh);
+            s[ghost_slot<D, N, 4>(t)] = ghost_finish<D, N, 4, T, RT>(s, t, raw[4], v[4], hg, fl, hh, bil);
+            s[ghost_slot<D, N, 5>(t)] = ghost_finish<D, N, 5, T, RT>(s, t, raw[5], v[5], hg, fl, hh, bil);
         }
     }
 };
@@ -860,8 +889,8 @@ __device__ __forceinline__ size_t halo_addr(int m, const int o[3], const BoxInfo
 // Dirichlet: ghost of delta = -delta(face cell), Neumann: +delta(face cell)
 // (the boundary values cancel); refinement side: the default scheme applied
 // to deltas.
-template <int D, int N, int S, typename T>
-__device__ __forceinline__ void halo_phase2(T *q, int m, const int o[3], T raw, int v, int pflags) {
+template <int D, int N, int S, typename T, bool RT = false>
+__device__ __forceinline__ void halo_phase2(T *q, int m, const int o[3], T raw, int v, int pflags, int bil = 0) {
     using SD = SideOf<S>;
     if (v >= 0) return;
     int L[3], X[3];
@@ -872,6 +901,15 @@ __device__ __forceinline__ void halo_phase2(T *q, int m, const int o[3], T raw, 
     T val;
     if (v == -1) {
         val = neumann_side(pflags, S) ? d1 : -d1;
+    } else if (RT && bil) {
+        auto at = [&](int depth, int f1, int f2) {
+            int c[3] = {f[0], f[1], f[2]};
+            c[SD::d] += SD::hi ? -depth : depth;
+            c[SD::t1] ^= f1;  // octant origins are even: partners stay inside
+            if (D == 3) c[SD::t2] ^= f2;
+            return q[qpad<D, N>(c[0], c[1], c[2])];
+        };
+        val = bil_ghost<D, T>(raw, at);
     } else {
         int y[3] = {f[0], f[1], f[2]};
         y[SD::d] += SD::hi ? -1 : 1;
@@ -1247,7 +1285,8 @@ __global__ __launch_bounds__(256) void k_vgsrb(LevelArgs<T> a, int colour) {
     const int own0 = colour * G::HALF + r * HN;
     const bool act = sl.valid, eps = a.opk & OPK_EPS;
     T rr[HN];
-    Stager<D, N, T> st;
+    Stager<D, N, T, true> st;
+    st.bil = (a.opk & OPK_GHOST_BIL) != 0;
     EpsStager<D, N, T> es;
     // padding slots (sl.b clamped to a valid box) load too
 #pragma unroll
@@ -1289,7 +1328,8 @@ __global__ __launch_bounds__(256) void k_vresid_restrict(LevelArgs<T> a) {
     constexpr int NPC = G::HC / G::TPB, NB = D == 3 ? 8 : 4;
     const bool act = sl.valid, eps = a.opk & OPK_EPS, cyl = a.opk & OPK_CYL;
     T rf[NPC][NB];
-    Stager<D, N, T> st;
+    Stager<D, N, T, true> st;
+    st.bil = (a.opk & OPK_GHOST_BIL) != 0;
     EpsStager<D, N, T> es;
 #pragma unroll
     for (int it = 0; it < NPC; it++)
@@ -1352,7 +1392,8 @@ __global__ __launch_bounds__(256) void k_vcoarse_rhs(LevelArgs<T> a) {
     const bool act = sl.valid, eps = (a.opk & OPK_EPS) && parent;
     constexpr int NE = G::C / G::TPB;
     T rf[NE];
-    Stager<D, N, T> st;
+    Stager<D, N, T, true> st;
+    st.bil = (a.opk & OPK_GHOST_BIL) != 0;
     EpsStager<D, N, T> es;
     st.load(bi, a.u + bo, a.u, a.bc, a.homog, sl.t, parent, a.h);
     if (parent) {
@@ -1404,7 +1445,8 @@ __global__ __launch_bounds__(256) void k_vfinal(LevelArgs<T> a, double *partial,
     const bool act = sl.valid, eps = (a.opk & OPK_EPS) && leaf, cyl = a.opk & OPK_CYL;
     constexpr int NPC = G::HC / G::TPB, NB = D == 3 ? 8 : 4;
     T rf[NPC][NB];
-    Stager<D, N, T> st;
+    Stager<D, N, T, true> st;
+    st.bil = (a.opk & OPK_GHOST_BIL) != 0;
     EpsStager<D, N, T> es;
     st.load(bi, a.u + bo, a.u, a.bc, a.homog, sl.t, leaf, a.h);
     if (leaf) {
@@ -1501,6 +1543,8 @@ __global__ __launch_bounds__(256) void k_vprolong(LevelArgs<T> a) {
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
     const bool act = sl.valid;
+    const bool eps = a.opk & OPK_PROLONG_EPS;
+    const int bil = (a.opk & OPK_GHOST_BIL) ? 1 : 0;
     T raw[NH], rawe[NH], uf[NE];
     int hv[NH], hs[NH];
 #pragma unroll
@@ -1518,7 +1562,7 @@ __global__ __launch_bounds__(256) void k_vprolong(LevelArgs<T> a) {
             const int I = pc % G::H, J = (pc / G::H) % G::H, K = D == 3 ? pc / (G::H * G::H) : 0;
             const size_t oo = (size_t)p * G::C + cpos<D, N>(o[0] + I, o[1] + J, o[2] + K);
             od[it] = a.u[oo] - a.uold[oo];
-            oe[it] = a.eps[oo];
+            oe[it] = eps ? a.eps[oo] : T(1);
         }
 #pragma unroll
         for (int h = 0; h < NH; h++) {
@@ -1533,7 +1577,7 @@ __global__ __launch_bounds__(256) void k_vprolong(LevelArgs<T> a) {
 #undef AFMG_H1
             }
             raw[h] = a.u[ho] - a.uold[ho];
-            rawe[h] = a.eps[ho];
+            rawe[h] = eps ? a.eps[ho] : T(1);
         }
 #pragma unroll
         for (int it = 0; it < NO; it++) {
@@ -1556,10 +1600,10 @@ __global__ __launch_bounds__(256) void k_vprolong(LevelArgs<T> a) {
             const int hc = sl.t + h * G::TPB;
             if (hc < 2 * D * G::HF && hv[h] < 0) {
                 const int side = hc / G::HF, m = hc % G::HF;
-#define AFMG_H2(S) halo_phase2<D, N, S, T>(q, m, o, raw[h], hv[h], pfl)
+#define AFMG_H2(S) halo_phase2<D, N, S, T, true>(q, m, o, raw[h], hv[h], pfl, bil)
                 AFMG_SIDE_SWITCH(side, AFMG_H2)
 #undef AFMG_H2
-                if (hv[h] == -1) {
+                if (eps && hv[h] == -1) {
                     // physical side of the parent: the face cell's own coefficient
                     int L[3], X[3];
 #define AFMG_H3(S)                                          \
@@ -1585,14 +1629,152 @@ __global__ __launch_bounds__(256) void k_vprolong(LevelArgs<T> a) {
         const int P[3] = {i >> 1, j >> 1, k >> 1};
         const int sg[3] = {(i & 1) ? 1 : -1, (j & 1) ? 1 : -1, (k & 1) ? 1 : -1};
         const T d0 = q[qpad<D, N>(P[0], P[1], P[2])], e0 = qe[qpad<D, N>(P[0], P[1], P[2])];
-        T v = d0;
+        T v;
+        if (eps) {
+            v = d0;
 #pragma unroll
-        for (int d = 0; d < D; d++) {
-            int Q[3] = {P[0], P[1], P[2]};
-            Q[d] += sg[d];
-            const int qi = qpad<D, N>(Q[0], Q[1], Q[2]);
-            const T ed = qe[qi];
-            v += ed / (T(2) * (e0 + ed)) * (q[qi] - d0);
+            for (int d = 0; d < D; d++) {
+                int Q[3] = {P[0], P[1], P[2]};
+                Q[d] += sg[d];
+                const int qi = qpad<D, N>(Q[0], Q[1], Q[2]);
+                const T ed = qe[qi];
+                v += ed / (T(2) * (e0 + ed)) * (q[qi] - d0);
+            }
+        } else if (D == 2) {
+            v = T(0.5) * d0 + T(0.25) * q[qpad<D, N>(P[0] + sg[0], P[1], 0)] +
+                T(0.25) * q[qpad<D, N>(P[0], P[1] + sg[1], 0)];
+        } else {
+            v = T(0.25) * (((d0 + q[qpad<D, N>(P[0] + sg[0], P[1], P[2])]) + q[qpad<D, N>(P[0], P[1] + sg[1], P[2])]) +
+                           q[qpad<D, N>(P[0], P[1], P[2] + sg[2])]);
+        }
+        a.u[bo + e] = uf[it] + v;
+    }
+}
+
+
+// Coarse-grid correction with bi/trilinear prolongation (paper §2.5).  The
+// whole parent box of delta = u - uold is staged with its side ghosts (the
+// solve's schemes applied to deltas: the boundary values cancel), then its
+// edge (3D) and corner ghosts (paper §2.4): the delta of the same-level box
+// across that edge or corner, or else the linear extrapolation b + c - a
+// (a 3D corner: its three edge ghosts minus its three side ghosts plus the
+// inner cell).  A fine cell takes weights 3/4 and 1/4 per axis over the 2^D
+// coarse cells nearest to it.
+template <int D, int N, typename T>
+__global__ __launch_bounds__(256) void k_vprolong_lin(LevelArgs<T> a) {
+    using G = Geo<D, N>;
+    constexpr int NE = G::C / G::TPB;
+    __shared__ T sm[G::BPW * G::PC];
+    const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb, a.no_remap == 0);
+    T *s = sm + sl.slot * G::PC;
+    const BoxInfo bi = load_box<D, N>(a.info, sl.b);
+    const bool act = sl.valid;
+    const int t = sl.t;
+    const size_t bo = (size_t)sl.b * G::C;
+    const int64_t p = bi.parent;
+    const BoxInfo pi = load_box<D, N>(a.info, p);
+    const size_t po = (size_t)p * G::C;
+    T uf[NE];
+#pragma unroll
+    for (int it = 0; it < NE; it++) uf[it] = a.u[bo + t + it * G::TPB];
+    // the parent's rows of delta and the raw operands of its side ghosts
+    Stager<D, N, T, true> st;
+    st.bil = (a.opk & OPK_GHOST_BIL) ? 1 : 0;
+    st.hg = 1;
+    st.fl = pi.flags;
+    st.hh = T(0);
+#pragma unroll
+    for (int c = 0; c < 2; c++)
+#pragma unroll
+        for (int m = 0; m < G::HN; m++) {
+            const size_t e = po + c * G::HALF + t * G::HN + m;
+            st.rowv[c][m] = a.u[e] - a.uold[e];
+        }
+#define AFMG_G1(S)                                                                           \
+    {                                                                                        \
+        const size_t off = (size_t)(ghost_ptr<D, N, S, T>(pi, t, a.u, nullptr, 1, st.v[S]) - a.u); \
+        st.raw[S] = a.u[off] - a.uold[off];                                                  \
+    }
+    AFMG_G1(0) AFMG_G1(1) AFMG_G1(2) AFMG_G1(3)
+    if (D == 3) {
+        AFMG_G1(4) AFMG_G1(5)
+    }
+#undef AFMG_G1
+    st.stage(s, t);
+    __syncthreads();
+    if (act) st.end(s, t);
+    __syncthreads();
+    // edges (2 axes outside the box), then corners (3 axes)
+    for (int nout = 2; nout <= D; nout++) {
+        const int count = nout == 2 ? (D == 3 ? 12 * N : 4) : 8;
+        for (int w = t; act && w < count; w += G::TPB) {
+            // the w-th direction with nout nonzero components, in the order
+            // of the index (dx+1) + 3 (dy+1) + 9 (dz+1)
+            const int dir_rank = nout == 2 && D == 3 ? w / N : w;
+            const int along = nout == 2 && D == 3 ? w % N : 0;
+            int o[3] = {0, 0, 0}, rank = 0, found = 0;
+            for (int idx = 0; idx < 27 && !found; idx++) {
+                const int dd[3] = {idx % 3 - 1, (idx / 3) % 3 - 1, idx / 9 - 1};
+                if (D == 2 && dd[2] != 0) continue;
+                if ((dd[0] != 0) + (dd[1] != 0) + (dd[2] != 0) != nout) continue;
+                if (rank++ == dir_rank) {
+                    o[0] = dd[0];
+                    o[1] = dd[1];
+                    o[2] = dd[2];
+                    found = 1;
+                }
+            }
+            int g[3];
+            for (int d = 0; d < 3; d++) g[d] = o[d] == -1 ? -1 : o[d] == 1 ? N : along;
+            const int didx = (o[0] + 1) + 3 * (o[1] + 1) + 9 * (o[2] + 1);
+            const int32_t v = a.dnbr[(size_t)p * 27 + didx];
+            T val;
+            if (v >= 0) {
+                int q[3];
+                for (int d = 0; d < 3; d++) q[d] = o[d] == -1 ? N - 1 : o[d] == 1 ? 0 : along;
+                const size_t e = (size_t)v * G::C + cpos<D, N>(q[0], q[1], D == 3 ? q[2] : 0);
+                val = a.u[e] - a.uold[e];
+            } else {
+                // inclusion-exclusion over the outside axes
+                int ax[3], na = 0;
+                for (int d = 0; d < D; d++)
+                    if (o[d] != 0) ax[na++] = d;
+                val = T(0);
+                for (int sub = 1; sub < (1 << na); sub++) {
+                    int q[3] = {g[0], g[1], D == 3 ? g[2] : 0}, cnt = 0;
+                    for (int k = 0; k < na; k++)
+                        if (sub & (1 << k)) {
+                            q[ax[k]] += o[ax[k]] == -1 ? 1 : -1;
+                            cnt++;
+                        }
+                    const T f = s[padi<D, N>(q[0], q[1], q[2])];
+                    val += (cnt & 1) ? f : -f;
+                }
+            }
+            s[padi<D, N>(g[0], g[1], D == 3 ? g[2] : 0)] = val;
+        }
+        __syncthreads();
+    }
+    if (!act) return;
+    const int flags = bi.flags;
+    const int o0 = obit(flags, 0) * G::H, o1 = obit(flags, 1) * G::H, o2 = D == 3 ? obit(flags, 2) * G::H : 0;
+#pragma unroll
+    for (int it = 0; it < NE; it++) {
+        const int e = t + it * G::TPB;
+        int i, j, k;
+        cell_of<D, N>(e, i, j, k);
+        const int X = o0 + (i >> 1), Y = o1 + (j >> 1), Z = o2 + (k >> 1);
+        const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
+        T v;
+        if (D == 2) {
+            v = T(0.5625) * s[padi<D, N>(X, Y, 0)] + T(0.1875) * s[padi<D, N>(X + sx, Y, 0)] +
+                T(0.1875) * s[padi<D, N>(X, Y + sy, 0)] + T(0.0625) * s[padi<D, N>(X + sx, Y + sy, 0)];
+        } else {
+            v = T(0.421875) * s[padi<D, N>(X, Y, Z)] +
+                T(0.140625) * ((s[padi<D, N>(X + sx, Y, Z)] + s[padi<D, N>(X, Y + sy, Z)]) + s[padi<D, N>(X, Y, Z + sz)]) +
+                T(0.046875) * ((s[padi<D, N>(X + sx, Y + sy, Z)] + s[padi<D, N>(X + sx, Y, Z + sz)]) +
+                               s[padi<D, N>(X, Y + sy, Z + sz)]) +
+                T(0.015625) * s[padi<D, N>(X + sx, Y + sy, Z + sz)];
         }
         a.u[bo + e] = uf[it] + v;
     }
@@ -2813,6 +2995,7 @@ struct GenState {
     double *E;             // coefficients [root][TOT] (OPK_EPS)
     const int32_t *bx;     // x index of the boxes (roots first)
     int opk;               // operator (OPK_* bits)
+    const int32_t *dnbr;   // OPK_PROLONG_LIN: roots' same-level boxes across edges and corners
 
     __device__ static double hgrid(int g) { return (double)(1 << g) / (double)N; }
     __device__ double *at(double *f, int r, int g) const { return f + (size_t)r * GG::TOT + GG::off(g); }
@@ -3028,6 +3211,80 @@ struct GenState {
         const int s = 2 * axis + (sgn > 0 ? 1 : 0);
         return across(U, r, g, s, I, J, K) - across(UOLD, r, g, s, I, J, K);
     }
+    // u - v' of grid g at cell c0 with every axis at most one cell outside
+    // the root's box: inside, across one side (delta), or across an edge or
+    // corner: the same-level root there, else the linear extrapolation of
+    // the edge and corner ghosts (k_vprolong_lin).  `outs` limits the axes
+    // outside (callers go from corners to edges to sides, no recursion).
+    __device__ double dval_side(int r, int g, const int c0[3]) const {
+        const int n = GG::n(g);
+        for (int d = 0; d < D; d++) {
+            const int o = c0[d] < 0 ? -1 : c0[d] >= n ? 1 : 0;
+            if (o) {
+                int in[3] = {c0[0], c0[1], c0[2]};
+                in[d] -= o;
+                return delta(r, g, d, o, in[0], in[1], in[2]);
+            }
+        }
+        const int c = cidx(n, c0[0], c0[1], c0[2]);
+        return at(U, r, g)[c] - at(UOLD, r, g)[c];
+    }
+    // across an edge or corner (2 or 3 axes outside): the root there, or
+    // -1 when there is none
+    __device__ double dval_diag(int r, int g, const int c0[3], const int o[3], bool &found) const {
+        const int n = GG::n(g);
+        const int v = dnbr[(size_t)r * 27 + (o[0] + 1) + 3 * (o[1] + 1) + 9 * (o[2] + 1)];
+        found = v >= 0;
+        if (!found) return 0.0;
+        int q[3] = {c0[0], c0[1], c0[2]};
+        for (int d = 0; d < D; d++)
+            if (o[d]) q[d] = o[d] < 0 ? n - 1 : 0;
+        const int c = cidx(n, q[0], q[1], q[2]);
+        return at(U, v, g)[c] - at(UOLD, v, g)[c];
+    }
+    __device__ double dval_edge(int r, int g, const int c0[3], const int o[3]) const {
+        bool found;
+        const double dv = dval_diag(r, g, c0, o, found);
+        if (found) return dv;
+        int ax[2], na = 0;
+        for (int d = 0; d < D; d++)
+            if (o[d]) ax[na++] = d;
+        int b[3] = {c0[0], c0[1], c0[2]}, c[3] = {c0[0], c0[1], c0[2]}, in[3] = {c0[0], c0[1], c0[2]};
+        b[ax[0]] -= o[ax[0]];
+        c[ax[1]] -= o[ax[1]];
+        in[ax[0]] -= o[ax[0]];
+        in[ax[1]] -= o[ax[1]];
+        return dval_side(r, g, b) + dval_side(r, g, c) - dval_side(r, g, in);
+    }
+    __device__ double dval(int r, int g, const int c0[3]) const {
+        const int n = GG::n(g);
+        int o[3] = {0, 0, 0}, na = 0;
+        for (int d = 0; d < D; d++) {
+            o[d] = c0[d] < 0 ? -1 : c0[d] >= n ? 1 : 0;
+            na += o[d] != 0;
+        }
+        if (na <= 1) return dval_side(r, g, c0);
+        if (na == 2) return dval_edge(r, g, c0, o);
+        bool found;
+        const double dv = dval_diag(r, g, c0, o, found);
+        if (found) return dv;
+        // a corner: its three edge ghosts minus its three side ghosts plus
+        // the inner cell
+        double val = 0.0;
+        for (int d = 0; d < 3; d++) {
+            int e[3] = {c0[0], c0[1], c0[2]}, oe[3] = {o[0], o[1], o[2]};
+            e[d] -= o[d];
+            oe[d] = 0;
+            val += dval_edge(r, g, e, oe);
+        }
+        for (int d = 0; d < 3; d++) {
+            int sd[3] = {c0[0] - o[0], c0[1] - o[1], c0[2] - o[2]};
+            sd[d] += o[d];
+            val -= dval_side(r, g, sd);
+        }
+        const int in[3] = {c0[0] - o[0], c0[1] - o[1], c0[2] - o[2]};
+        return val + dval_side(r, g, in);
+    }
     // u of grid g += P211(u - v' of grid g+1); with store_old, v' of grid g
     // first receives u (FMG)
     __device__ void prolong(int g, bool store_old) const {
@@ -3039,7 +3296,20 @@ struct GenState {
             const int I = i >> 1, J = j >> 1, K = k >> 1;
             const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
             double v;
-            if (opk & OPK_PROLONG_EPS) {
+            if (opk & OPK_PROLONG_LIN) {
+                // bi/trilinear (see k_vprolong_lin)
+                const int P[3] = {I, J, K};
+                const int sg[3] = {sx, sy, sz};
+                auto dv = [&](int a, int b, int c) {
+                    const int q[3] = {P[0] + a * sg[0], P[1] + b * sg[1], D == 3 ? P[2] + c * sg[2] : 0};
+                    return dval(r, g + 1, q);
+                };
+                if (D == 2)
+                    v = 0.5625 * dv(0, 0, 0) + 0.1875 * dv(1, 0, 0) + 0.1875 * dv(0, 1, 0) + 0.0625 * dv(1, 1, 0);
+                else
+                    v = 0.421875 * dv(0, 0, 0) + 0.140625 * ((dv(1, 0, 0) + dv(0, 1, 0)) + dv(0, 0, 1)) +
+                        0.046875 * ((dv(1, 1, 0) + dv(1, 0, 1)) + dv(0, 1, 1)) + 0.015625 * dv(1, 1, 1);
+            } else if (opk & OPK_PROLONG_EPS) {
                 // eps-weighted (see k_vprolong)
                 const int nc = GG::n(g + 1);
                 const int sg[3] = {sx, sy, sz};
@@ -3105,7 +3375,7 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse_gen(CoarseGenArgs<T> a) {
     GenState<D, N> st{a.info, ws, ws + (size_t)R * GG::TOT, ws + (size_t)2 * R * GG::TOT,
                       ws + (size_t)3 * R * GG::TOT, ws + (size_t)4 * R * GG::TOT, R, a.homog,
                       a.n_down, a.n_up, a.n_base,
-                      ws + (size_t)4 * R * GG::TOT + (size_t)R * GG::BTOT, a.bx, a.opk};
+                      ws + (size_t)4 * R * GG::TOT + (size_t)R * GG::BTOT, a.bx, a.opk, a.dnbr};
     const int mode = a.mode;
     // level 1 from the roots' boxes (colour-split in the tree's arrays), the
     // coarser grids start at zero
@@ -3573,7 +3843,8 @@ static void launch_level_op(Op op, const LevelArgs<T> &a, int colour, hipStream_
         case Op::RESID_RESTRICT: AFMG_LAUNCH((k_vresid_restrict<D, N, T>), g, st, a); break;
         case Op::COARSE_RHS: AFMG_LAUNCH((k_vcoarse_rhs<D, N, T>), g, st, a); break;
         case Op::PROLONG:
-            if (a.opk & OPK_PROLONG_EPS) AFMG_LAUNCH((k_vprolong<D, N, T>), g, st, a);
+            if (a.opk & OPK_PROLONG_LIN) AFMG_LAUNCH((k_vprolong_lin<D, N, T>), g, st, a);
+            else if (a.opk & (OPK_PROLONG_EPS | OPK_GHOST_BIL)) AFMG_LAUNCH((k_vprolong<D, N, T>), g, st, a);
             else AFMG_LAUNCH((k_prolong<D, N, T, 256, false>), g, st, a);
             break;
         case Op::RESTRICT_RHO:

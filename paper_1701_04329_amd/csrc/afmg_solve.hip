@@ -114,7 +114,8 @@ struct afmg_tree {
     int opk = 0;
     double *d_eps = nullptr;
     int32_t *d_bx = nullptr;
-    int op_kind = 0, op_prolong = 0;
+    int32_t *d_dnbr = nullptr;  // [n_boxes][27] same-level boxes across edges and corners
+    int op_kind = 0, op_prolong = 0, ghost_scheme = 0;
     int domain_general = -1;  // -1 until the first set_operator
 };
 
@@ -315,7 +316,7 @@ void release(afmg_tree *t) {
                     (void *)t->d_tree_lmax, (void *)t->d_tree_leaf_ptr, (void *)t->d_tree_leaf_box,
                     (void *)t->d_box_map, (void *)t->d_row_map, (void *)t->d_tnorm, (void *)t->d_tstop,
                     (void *)t->d_thist, (void *)t->d_ltoff, (void *)t->d_lvloff, (void *)t->d_act,
-                    (void *)t->d_nact, (void *)t->d_eps, (void *)t->d_bx})
+                    (void *)t->d_nact, (void *)t->d_eps, (void *)t->d_bx, (void *)t->d_dnbr})
         if (p) (void)hipFree(p);
     if (t->h_norm) (void)hipHostFree(t->h_norm);
     if (t->h_active) (void)hipHostFree(t->h_active);
@@ -472,6 +473,7 @@ struct Cycler {
             c.eps = t->d_eps;
             c.bx = t->d_bx;
             c.opk = t->opk;
+            c.dnbr = t->d_dnbr;
             launch_coarse_gen<D, BOX_N, T>(c, st);
             return;
         }
@@ -908,6 +910,7 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
     s.base.eps = t->d_eps;
     s.base.bx = t->d_bx;
     s.base.opk = t->opk;
+    s.base.dnbr = t->d_dnbr;
     const int64_t F = cells_per_face(D), C = cells_per_box(D);
 
     hipEvent_t ev0 = t->span[0], ev1 = t->span[1];
@@ -1300,6 +1303,7 @@ int step(afmg_tree *t, hipStream_t st, int op, int level, int colour, int homog,
     a.eps = t->d_eps;
     a.bx = t->d_bx;
     a.opk = t->opk;
+    a.dnbr = t->d_dnbr;
     const double hh = level_h(level);
     a.h2 = hh * hh;
     a.ih2 = 1.0 / (hh * hh);
@@ -1316,6 +1320,7 @@ int step(afmg_tree *t, hipStream_t st, int op, int level, int colour, int homog,
             c.eps = t->d_eps;
             c.bx = t->d_bx;
             c.opk = t->opk;
+            c.dnbr = t->d_dnbr;
             launch_coarse_gen<D, BOX_N, double>(c, st);
         } else {
             CoarseArgs<double> c{t->d_info, u, rho, uold, homog ? nullptr : bc_w, COARSE_V_FROM_2, homog,
@@ -1621,6 +1626,29 @@ int transfer(afmg_tree *from, afmg_tree *to, hipStream_t st, const double *u_fro
     return AFMG_OK;
 }
 
+// The kernel bits of a tree's operator, prolongation and ghost scheme; a
+// tree with any of them takes the operator kernels, the general coarse path
+// and the default launch shapes (one norm partial per 256-thread workgroup).
+int apply_schemes(afmg_tree *t) {
+    HostTree &h = t->h;
+    int opk = 0;
+    if (t->op_kind & AFMG_OPERATOR_EPS) opk |= OPK_EPS;
+    if (t->op_kind & AFMG_OPERATOR_CYL) opk |= OPK_CYL;
+    if (t->op_prolong == AFMG_PROLONG_EPS) opk |= OPK_PROLONG_EPS;
+    if (t->op_prolong == AFMG_PROLONG_LINEAR) opk |= OPK_PROLONG_LIN;
+    if (t->ghost_scheme == AFMG_GHOST_BILINEAR) opk |= OPK_GHOST_BIL;
+    t->rec.drop();  // a recorded cycle holds the old launches
+    t->opk = opk;
+    h.general = opk != 0 || (t->domain_general >= 0 ? t->domain_general != 0 : h.general);
+    if (opk) {
+        for (auto &pk : t->shapes)
+            for (auto &v : pk) v.assign((size_t)h.lmax + 2, Shape{});
+        compute_partials(t);
+        t->tune_epoch++;
+    }
+    return AFMG_OK;
+}
+
 // ---------------------------------------------------------------------------
 // C-ABI
 // ---------------------------------------------------------------------------
@@ -1706,6 +1734,7 @@ int afmg_tree_info(const afmg_tree *t, afmg_tree_desc *out) {
     out->singular = h.singular ? 1 : 0;
     out->op = t->op_kind;
     out->prolong = t->op_prolong;
+    out->ghost = t->ghost_scheme;
     return AFMG_OK;
 }
 
@@ -1836,7 +1865,7 @@ int afmg_tree_set_operator(afmg_tree *t, void *stream, int op, const double *eps
     if (!t) return fail(AFMG_ERR_ARG, "null tree");
     if (t->forest) return fail(AFMG_ERR_ARG, "not a tree");
     if (op < AFMG_OPERATOR_LAPLACIAN || op > AFMG_OPERATOR_CYL_EPS) return fail(AFMG_ERR_ARG, "bad operator");
-    if (prolong != AFMG_PROLONG_DEFAULT && prolong != AFMG_PROLONG_EPS) return fail(AFMG_ERR_ARG, "bad prolongation");
+    if (prolong < AFMG_PROLONG_DEFAULT || prolong > AFMG_PROLONG_LINEAR) return fail(AFMG_ERR_ARG, "bad prolongation");
     const bool has_eps = op & AFMG_OPERATOR_EPS;
     if ((op & AFMG_OPERATOR_CYL) && t->h.dim != 2) return fail(AFMG_ERR_ARG, "the cylindrical form is 2D (r, z)");
     if (prolong == AFMG_PROLONG_EPS && !has_eps) return fail(AFMG_ERR_ARG, "the eps prolongation needs eps");
@@ -1846,41 +1875,46 @@ int afmg_tree_set_operator(afmg_tree *t, void *stream, int op, const double *eps
     if (rc != AFMG_OK) return rc;
     HostTree &h = t->h;
     if (t->domain_general < 0) t->domain_general = h.general ? 1 : 0;
-    const int opk = (has_eps ? OPK_EPS : 0) | ((op & AFMG_OPERATOR_CYL) ? OPK_CYL : 0) |
-                    (prolong == AFMG_PROLONG_EPS ? OPK_PROLONG_EPS : 0);
-    t->rec.drop();  // a recorded cycle holds the old operator's launches
-    t->opk = 0;
+    const int opk = (has_eps ? OPK_EPS : 0) | ((op & AFMG_OPERATOR_CYL) ? OPK_CYL : 0);
     t->op_kind = 0;
     t->op_prolong = 0;
-    h.general = t->domain_general != 0;
-    if (opk == 0) return AFMG_OK;
+    if ((rc = apply_schemes(t)) != AFMG_OK) return rc;
     const size_t C = (size_t)cells_per_box(h.dim);
-    if (!t->d_bx && (rc = upload(t->d_bx, h.ix, "the box x indices")) != AFMG_OK) return rc;
-    if (!t->d_eps) {
-        // the coefficients, then one word for the check's flag
-        hipError_t e = hipMalloc(&t->d_eps, sizeof(double) * ((size_t)h.n_boxes * C + 1));
-        if (e != hipSuccess) {
-            t->d_eps = nullptr;
-            return fail(AFMG_ERR_OOM, "hipMalloc of the coefficients failed");
-        }
+    if (opk && !t->d_bx && (rc = upload(t->d_bx, h.ix, "the box x indices")) != AFMG_OK) return rc;
+    if (prolong == AFMG_PROLONG_LINEAR && !t->d_dnbr) {
+        std::vector<int32_t> dn;
+        diagonal_neighbours(h, dn);
+        if ((rc = upload(t->d_dnbr, dn, "the diagonal neighbours")) != AFMG_OK) return rc;
     }
-    hipStream_t st = (hipStream_t)stream;
-    int *flag = (int *)(t->d_eps + (size_t)h.n_boxes * C);
     if (has_eps) {
+        if (!t->d_eps) {
+            // the coefficients, then one word for the check's flag
+            hipError_t e = hipMalloc(&t->d_eps, sizeof(double) * ((size_t)h.n_boxes * C + 1));
+            if (e != hipSuccess) {
+                t->d_eps = nullptr;
+                return fail(AFMG_ERR_OOM, "hipMalloc of the coefficients failed");
+            }
+        }
+        hipStream_t st = (hipStream_t)stream;
+        int *flag = (int *)(t->d_eps + (size_t)h.n_boxes * C);
         rc = h.dim == 3 ? load_eps<3>(t, st, eps, opk, flag) : load_eps<2>(t, st, eps, opk, flag);
         if (rc != AFMG_OK) return rc;
     }
-    // the operator's kernels run with the default shapes (one partial per
-    // 256-thread workgroup of the norm kernel)
-    for (auto &pk : t->shapes)
-        for (auto &v : pk) v.assign((size_t)h.lmax + 2, Shape{});
-    compute_partials(t);
-    t->tune_epoch++;
-    h.general = true;
-    t->opk = opk;
     t->op_kind = op;
     t->op_prolong = prolong;
-    return AFMG_OK;
+    return apply_schemes(t);
+}
+
+int afmg_tree_set_ghost_scheme(afmg_tree *t, void *stream, int scheme) {
+    (void)stream;
+    if (!t) return fail(AFMG_ERR_ARG, "null tree");
+    if (t->forest) return fail(AFMG_ERR_ARG, "not a tree");
+    if (scheme != AFMG_GHOST_DEFAULT && scheme != AFMG_GHOST_BILINEAR) return fail(AFMG_ERR_ARG, "bad ghost scheme");
+    int rc = bind_device(t);
+    if (rc != AFMG_OK) return rc;
+    if (t->domain_general < 0) t->domain_general = t->h.general ? 1 : 0;
+    t->ghost_scheme = scheme;
+    return apply_schemes(t);
 }
 
 int afmg_tree_finalize(afmg_tree *t, void *stream) {

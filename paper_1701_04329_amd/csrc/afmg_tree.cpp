@@ -429,6 +429,20 @@ void emit_leaves(const Lookup &lk, const std::vector<char> &refine, const std::v
 
 }  // namespace
 
+void diagonal_neighbours(const HostTree &t, std::vector<int32_t> &out) {
+    const Lookup lk(t);
+    out.assign((size_t)t.n_boxes * 27, -1);
+    for (int64_t m = 0; m < t.n_boxes; m++) {
+        const Key kk = lk.key_of(m);
+        for (int o = 0; o < 27; o++) {
+            const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
+            if (t.dim == 2 && dz != 0) continue;
+            if (dx == 0 && dy == 0 && dz == 0) continue;
+            out[(size_t)m * 27 + o] = (int32_t)lk.box_at(kk.l, kk.i + dx, kk.j + dy, kk.k + dz);
+        }
+    }
+}
+
 int refine_leaves(const HostTree &t, const int32_t *ids, int64_t n, int balance, std::vector<int32_t> &level,
                   std::vector<int32_t> &idx, std::string &msg) {
     if (n < 0 || (n > 0 && !ids)) { msg = "bad leaf id list"; return AFMG_ERR_ARG; }

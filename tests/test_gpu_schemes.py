@@ -1,0 +1,220 @@
+"""GPU parity of the alternative schemes (paper §2.4, §2.5, §3.3): the
+bilinear-extrapolation refinement-boundary ghosts and the bi/trilinear
+prolongation with edge and corner ghosts, alone and with an operator, on
+quadtrees, octrees, an L-shaped coarse grid (re-entrant corner: a diagonal
+neighbour without its side neighbours) and a periodic octree domain.
+
+* steps (afmg_step) against the oracle's same step on a random state,
+  1e-13 of the output's max-norm;
+* solves against the oracle: every leaf cell to 1e-12 of the largest value
+  at equal cycle counts, residual histories, and solving to a tolerance.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1701_04329_amd import workloads as W
+from parity import REL, assert_leaf_parity, assert_norms_close
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+STEP_REL = 1e-13
+D_, N_, P_ = "dirichlet", "neumann", "periodic"
+
+
+def announce(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def cases():
+    """name -> (dim, (level, idx), side types, operator, eps?, prolong, ghost)"""
+    c = (0.3, 0.62, 0.41)
+    return {
+        "b2": (2, W.ball_leaves(2, 8, 5, c, 0.0, 1), None, "laplacian", False, "default", "bilinear"),
+        "b3": (3, W.ball_leaves(3, 8, 4, c, 0.0, 1), None, "laplacian", False, "default", "bilinear"),
+        "l2": (2, W.ball_leaves(2, 8, 5, c, 0.0, 1), None, "laplacian", False, "linear", "default"),
+        "l3": (3, W.ball_leaves(3, 8, 4, c, 0.0, 1), None, "laplacian", False, "linear", "default"),
+        "lL2": (2, W.domain_leaves(2, 8, [(1, 1), (2, 1), (1, 2)], 5, (0.97, 0.97)), [D_, N_, N_, D_], "laplacian",
+                False, "linear", "bilinear"),
+        "lp3": (3, W.domain_leaves(3, 8, [(1, 1, 1), (2, 1, 1)], 4, (1.98, 0.4, 0.6), periodic=(True, False, False)),
+                [P_, P_, N_, D_, D_, N_], "eps", True, "linear", "bilinear"),
+    }
+
+
+_C = None
+
+
+def case(name):
+    global _C
+    if _C is None:
+        _C = cases()
+    return _C[name]
+
+
+NAMES = ["b2", "b3", "l2", "l3", "lL2", "lp3"]
+
+
+def build(name, seed):
+    from paper_1701_04329_amd import afmg as A
+    dim, (lev, idx), types, kind, has_eps, prolong, ghost = case(name)
+    # eps jumps on a coarse-grid face (between the two level-1 boxes), the
+    # setting the ghost schemes are made for (paper §3.4)
+    eps = W.eps_sampled(lambda x: np.where(x[..., 0] < 1.0, 4.0, 1.0), dim, 8, lev, idx) if has_eps else None
+    t = A.Tree(dim, lev, idx, bc_type=types)
+    dev = torch.device("cuda", 0)
+    t.set_operator(kind, None if eps is None else t.leaf_to_boxes(torch.tensor(eps, device=dev)).contiguous(),
+                   prolong)
+    t.set_ghost_scheme(ghost)
+    o = O.Tree(dim, 8, lev, idx, bc_type=types)
+    o.set_operator(kind, eps, prolong)
+    o.set_ghost_scheme(ghost)
+    return t, o
+
+
+class Pair:
+    def __init__(self, name, seed):
+        from paper_1701_04329_amd import afmg as A
+        self.A = A
+        dim, (lev, idx), types, *_ = case(name)
+        self.dim = dim
+        self.t, self.o = build(name, 70 + seed)
+        key_o = {}
+        for b in range(self.o.nbox):
+            i = self.o.box_info(b)
+            if i["level"] >= 1:
+                key_o[(i["level"], i["ix"], i["iy"], i["iz"])] = b
+        self.o_of = np.array([key_o[(self.t.box(b)["level"],) + self.t.box(b)["idx"]] for b in range(self.t.n_boxes)])
+        rng = np.random.default_rng(seed)
+        C = 8 ** dim
+        self.u = rng.standard_normal((self.t.n_boxes, C))
+        self.rho = rng.standard_normal((self.t.n_boxes, C))
+        self.uold = rng.standard_normal((self.t.n_boxes, C))
+        phys = W.domain_side_mask(dim, lev, idx, types)[:, :, None]
+        self.bc_leaf = rng.standard_normal((len(lev), 2 * dim, 8 ** (dim - 1))) * phys
+        self.levels = np.array([self.t.box(b)["level"] for b in range(self.t.n_boxes)])
+        self.leaf = np.array([self.t.box(b)["leaf"] for b in range(self.t.n_boxes)])
+
+    def gpu(self, op, level, colour=0, homog=False):
+        dev = torch.device("cuda", 0)
+        u = torch.tensor(self.u, device=dev)
+        rho = torch.tensor(self.rho, device=dev)
+        uold = torch.tensor(self.uold, device=dev)
+        bc = self.t.bc_rows(torch.tensor(self.bc_leaf, device=dev))
+        self.A.step(self.t, op, level, u, rho, uold, bc, colour=colour, homog=homog)
+        torch.cuda.synchronize()
+        return u.cpu().numpy(), rho.cpu().numpy(), uold.cpu().numpy()
+
+    def _set(self, field, arr):
+        inner = tuple(slice(1, -1) for _ in range(self.dim))
+        for b in range(self.t.n_boxes):
+            ob = int(self.o_of[b])
+            p = self.o.box_padded(ob, field)
+            p[inner] = arr[b].reshape((8,) * self.dim)
+            self.o.set_box_padded(ob, p, field)
+
+    def _get(self, field):
+        inner = tuple(slice(1, -1) for _ in range(self.dim))
+        return np.stack([self.o.box_padded(int(self.o_of[b]), field)[inner].ravel() for b in range(self.t.n_boxes)])
+
+    def oracle_state(self):
+        self.o.load(self.rho[self.t.leaf_boxes], self.bc_leaf)
+        self._set("u", self.u)
+        self._set("rho", self.rho)
+        self._set("uold", self.uold)
+
+    def boxes(self, level, parents=None):
+        sel = self.levels == level
+        if parents is not None:
+            sel &= self.leaf != parents
+        return np.nonzero(sel)[0]
+
+
+def close(what, got, ref, rel=STEP_REL):
+    scale = max(np.abs(ref).max(), 1e-300)
+    err = np.abs(got - ref).max() / scale
+    assert err <= rel, (what, err)
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_scheme_steps(name):
+    P = Pair(name, 3)
+    for homog in (False, True):
+        for level in range(1, P.t.lmax + 1):
+            for colour in (0, 1):
+                announce(f"scheme half sweep {name} level {level} colour {colour} homog {homog}")
+                u, _, _ = P.gpu("half_sweep", level, colour, homog)
+                P.oracle_state()
+                P.o.half_sweep(level, colour, homog=homog)
+                bs = P.boxes(level)
+                close("u", u[bs], P._get("u")[bs])
+        for level in range(2, P.t.lmax + 1):
+            announce(f"scheme residual + restriction {name} level {level} homog {homog}")
+            u, rho, _ = P.gpu("resid_restrict", level, homog=homog)
+            P.oracle_state()
+            P.o.resid_restrict_level(level, homog=homog)
+            par = P.boxes(level - 1, parents=True)
+            close("parent u", u[par], P._get("u")[par])
+            close("parent restricted residual", rho[par], P._get("res")[par])
+        for level in range(2, P.t.lmax + 1):
+            announce(f"scheme prolongation {name} level {level} homog {homog}")
+            u, _, _ = P.gpu("prolong", level, homog=homog)
+            P.oracle_state()
+            # v' of the parent level with the ghosts of its copy, then u
+            P._set("u", P.uold)
+            P.o.fill_gc(level - 1, "u", homog=homog)
+            P.o.copy_uold(level - 1)
+            P._set("u", P.u)
+            P.o.fill_gc(level - 1, "u", homog=homog)
+            P.o.prolong_level(level)
+            bs = P.boxes(level)
+            close("u", u[bs], P._get("u")[bs])
+        announce(f"scheme coarse grids {name} homog {homog}")
+        u, _, uold = P.gpu("coarse", 1, homog=homog)
+        P.oracle_state()
+        P._set("res", P.rho)
+        P.o.coarse_rhs_level(1, homog=homog)
+        P.o.vcycle_from(1, homog=homog)
+        root = P.boxes(1)
+        close("level-1 u", u[root], P._get("u")[root])
+
+
+def inputs(dim, lev, idx, types, seed):
+    rng = np.random.default_rng(seed)
+    rho = rng.standard_normal((len(lev), 8 ** dim))
+    bc = rng.standard_normal((len(lev), 2 * dim, 8 ** (dim - 1)))
+    bc *= W.domain_side_mask(dim, lev, idx, types)[:, :, None]
+    return rho, bc
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_scheme_solves_match_oracle(name):
+    from paper_1701_04329_amd import afmg as A
+    dim, (lev, idx), types, *_ = case(name)
+    t, o = build(name, 5)
+    rho, bc = inputs(dim, lev, idx, types, 17)
+    dev = torch.device("cuda", 0)
+    rho_d = t.leaf_to_boxes(torch.tensor(rho, device=dev))
+    bc_d = t.bc_rows(torch.tensor(bc, device=dev)) if t.n_bfaces else None
+    for kw in (dict(fixed_cycles=3, n_base=16), dict(cycle="FMG", fixed_cycles=1, n_base=16)):
+        announce(f"scheme solve {name} {kw}")
+        u, sg = A.solve(t, rho_d, bc_d, None, **kw)
+        torch.cuda.synchronize()
+        uo, so = o.solve(rho, bc, **kw)
+        assert_leaf_parity(t.boxes_to_leaf(u).cpu().numpy(), uo, REL, (name, kw))
+        assert_norms_close(sg["hist_max"], so["hist_max"], 1e-12 * so["r0_max"], what=(name, "history"))
+    if name == "lp3":
+        # the bilinear-extrapolation ghosts with the eps jump make the
+        # V-cycle diverge slowly on this octree, in the oracle as on the GPU
+        # (equal iterates above); no tolerance is reached
+        return
+    announce(f"scheme solve to tolerance {name}")
+    u, sg = A.solve(t, rho_d, bc_d, None, cycle="FMG", tol=1e-10, n_base=16, max_cycles=80)
+    uo, so = o.solve(rho, bc, cycle="FMG", tol=1e-10, n_base=16, max_cycles=80)
+    assert sg["status"] == 0 and so["status"] == 0
+    assert abs(sg["cycles"] - so["cycles"]) <= 1
+    assert_leaf_parity(t.boxes_to_leaf(u).cpu().numpy(), uo, 1e-9, name)
