@@ -777,6 +777,58 @@ def adapt_bench(args, A, torch, dev, stream):
                     "on the host, the new tree's tables"}
 
 
+def schemes_bench(args, A, torch, dev, stream):
+    """Alternative schemes (paper §2.4, §2.5, §3.3) on the adaptive octree
+    workload (about 2.3e7 unknowns, refinement boundaries on 5 levels):
+    FMG + V(2,2) to a 1e-10 residual reduction in FP64 with the default
+    refinement ghosts and 2-1-1 prolongation, with bilinear-extrapolation
+    ghosts, with trilinear prolongation, and with both; V-cycles, mean
+    reduction factor per V-cycle and time per solve (the variants run the
+    operator kernels).  The paper notes that ghosts formed by extrapolation
+    can slow the convergence, in 3D in particular.  Roofline of the
+    finest-level trilinear prolongation k_vprolong_lin: 18 B per fine cell
+    algorithmically (u read and written, u and v' of the parent: 2 x 8 B /
+    2^D)."""
+    from paper_1701_04329_amd import workloads as W
+
+    w = W.config3()
+    out = {"workload": "c3_adaptive", "unknowns": int(w.n_unknowns), "cycle": "FMG + V(2,2)", "tol": 1e-10}
+    variants = [("default", "default"), ("bilinear", "default"), ("default", "linear"), ("bilinear", "linear")]
+    for ghost, prolong in variants:
+        tree = A.Tree(w.dim, w.level, w.idx)
+        if (ghost, prolong) != ("default", "default"):
+            tree.set_ghost_scheme(ghost)
+            tree.set_operator("laplacian", None, prolong)
+        rho = tree.leaf_to_boxes(torch.tensor(w.rho, device=dev))
+        bc = tree.bc_rows(torch.tensor(w.bc, device=dev))
+        u = torch.zeros_like(rho)
+        work = torch.empty(tree.workspace_bytes(), dtype=torch.uint8, device=dev)
+        ms, (_, st) = timed_loop(args, torch, lambda: A.solve(
+            tree, rho, bc, u, cycle="FMG", tol=1e-10, max_cycles=80, workspace=work, stream=stream,
+            use_guess=False, check=False))
+        h = np.concatenate([[st["r_max"] if st["cycles"] == 0 else st["hist_max"][0]], st["hist_max"]])
+        n = len(st["hist_max"])
+        rate = float((st["hist_max"][-1] / st["hist_max"][0]) ** (1.0 / max(n - 1, 1))) if n > 1 else None
+        rec = {"status": st["status"], "v_cycles": st["cycles"], "mean_factor_per_v_cycle": rate,
+               "ms_per_solve": ms, "value": w.n_unknowns / (ms * 1e-3), "unit": "unknowns/s",
+               "final_residual_ratio": st["r_max"] / st["r0_max"],
+               "kernels": "Laplacian fast path" if (ghost, prolong) == ("default", "default") else "operator kernels"}
+        if prolong == "linear" and ghost == "default":
+            _, stp = A.solve(tree, rho, bc, u, cycle="FMG", tol=1e-10, max_cycles=80, workspace=work, stream=stream,
+                             use_guess=False, profile=True, check=False)
+            n_fine = len(tree.level_list(tree.lmax, "all")) * tree.cells_per_box
+            avg = stp["prof_ms"][2] / max(stp["prof_n"][2], 1)
+            ach = 18.0 * n_fine / (avg * 1e-3) / 1e9
+            rec["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                               "kernel": f"k_vprolong_lin<3,8,double> (finest level {tree.lmax})",
+                               "algorithmic_bytes_per_launch": 18.0 * n_fine, "avg_launch_ms": round(avg, 5),
+                               "launches_timed": int(stp["prof_n"][2])}
+        out[f"ghost_{ghost}_prolong_{prolong}"] = rec
+        del tree, work
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -809,6 +861,9 @@ def main():
     ap.add_argument("--operators-only", action="store_true",
                     help="run only the operator workloads and print their record")
     ap.add_argument("--no-adapt", action="store_true", help="skip the mesh adaptation workload")
+    ap.add_argument("--no-schemes", action="store_true", help="skip the alternative-scheme workloads")
+    ap.add_argument("--schemes-only", action="store_true",
+                    help="run only the alternative-scheme workloads and print their record")
     ap.add_argument("--adapt-only", action="store_true",
                     help="run only the mesh adaptation workload and print its record")
     ap.add_argument("--oracle-worker", action="store_true", help=argparse.SUPPRESS)
@@ -851,6 +906,9 @@ def main():
         return 0
     if args.adapt_only:
         print(json.dumps(adapt_bench(args, A, torch, dev, torch.cuda.current_stream(dev))), flush=True)
+        return 0
+    if args.schemes_only:
+        print(json.dumps(schemes_bench(args, A, torch, dev, torch.cuda.current_stream(dev))), flush=True)
         return 0
 
     if args.solve_only:
@@ -1046,6 +1104,8 @@ def main():
         out["operators"] = operators_bench(args, A, torch, dev, stream)
     if not args.no_adapt:
         out["adapt"] = adapt_bench(args, A, torch, dev, stream)
+    if not args.no_schemes:
+        out["schemes"] = schemes_bench(args, A, torch, dev, stream)
     if not args.no_cpu_baseline:
         uo, out["cpu_baseline"] = cpu_baseline(w, solve_kw, args.workload)
         nrm = np.linalg.norm(uo)
