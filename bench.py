@@ -595,29 +595,89 @@ def adjoint_bench(args, A, torch, dev, stream):
 
 def paper_ex_bench(args, A, torch, dev, stream):
     """The paper's scaling problem (§4.2): lap(phi) = 1 on the unit cube,
-    phi = 0 on the boundary, uniform 512^3 grid of 8^3-cell boxes, one FMG
-    cycle.  Time per FMG cycle in ns per unknown, beside the paper's figure
-    for 8^3 boxes on a 16-core CPU (context, another machine)."""
+    phi = 0 on the boundary, uniform 512^3 grid, one FMG cycle, with boxes of
+    8^3 and of 16^3 cells (the paper's box-size axis).  Time per FMG cycle
+    in ns per unknown, beside the paper's figures for 8^3 and 32^3 boxes on
+    16 CPU cores (context, another machine)."""
     from paper_1701_04329_amd import workloads as W
 
-    w = W.uniform_const_rhs(3, 8, 512)
-    tree = A.Tree(w.dim, w.level, w.idx)
+    out = {"workload": "ex4_3d_uniform_512", "paper_ns_per_unknown_16_cores": {"8": 22.0, "32": 10.0}}
+    for n in (8, 16):
+        w = W.uniform_const_rhs(3, n, 512)
+        tree = A.Tree(w.dim, w.level, w.idx, box_n=n)
+        rho = tree.leaf_to_boxes(torch.tensor(w.rho, device=dev))
+        del w
+        u = torch.empty_like(rho)
+        work = torch.empty(tree.workspace_bytes(A.make_opts(precision="mixed")), dtype=torch.uint8, device=dev)
+        if not args.no_autotune:
+            tree.autotune(dev, stream)
+        rec = {"box_n": n, "unknowns": int(tree.n_unknowns), "boxes": int(tree.n_boxes)}
+        for precision in ("fp64", "mixed"):
+            # FP64: the FMG cycle alone; mixed: the first refinement step,
+            # whose correction is one FP32 FMG cycle
+            ms, (_, st) = timed_loop(args, torch, lambda: A.solve(
+                tree, rho, None, u, cycle="FMG", max_cycles=0 if precision == "fp64" else 1,
+                precision=precision, workspace=work, stream=stream, use_guess=False, check=False))
+            rec[precision] = {"ms_per_fmg_cycle": ms, "ns_per_unknown": ms * 1e6 / tree.n_unknowns,
+                              "residual_ratio_after_fmg": st["r_max"] / st["r0_max"]}
+        out[f"box{n}"] = rec
+        del tree, rho, u, work
+        torch.cuda.empty_cache()
+    # compatibility with earlier records: the 8^3 figures at the top level
+    out.update({"unknowns": out["box8"]["unknowns"], "boxes": out["box8"]["boxes"],
+                "fp64": out["box8"]["fp64"], "mixed": out["box8"]["mixed"]})
+    return out
+
+
+def to_grid(N, level, idx, u_leaf):
+    """leaf values of a uniform 3D grid as one array (z, y, x)"""
+    n = N * 2 ** (int(level[0]) - 1)
+    g = np.empty((n, n, n))
+    ub = np.asarray(u_leaf).reshape(-1, N, N, N)
+    o = (np.asarray(idx)[:, :3] - 1) * N
+    for q in range(len(level)):
+        g[o[q, 2]:o[q, 2] + N, o[q, 1]:o[q, 1] + N, o[q, 0]:o[q, 0] + N] = ub[q]
+    return g
+
+
+def box16_bench(args, A, torch, dev, stream, ref=None):
+    """The headline workload (uniform 256^3, FMG then V(2,2) to a 1e-10
+    residual reduction, FP64 and mixed) on boxes of 16^3 cells instead of
+    8^3 (paper §2.1: the box size is a parameter; §4.2: larger boxes carry
+    less ghost overhead).  Same inputs and stop rule; the finest-level half
+    sweep timed with event pairs in the last FP64 solve, 12 B per cell."""
+    from paper_1701_04329_amd import workloads as W
+
+    w = W.config2(N=16)
+    tree = A.Tree(w.dim, w.level, w.idx, box_n=16)
     rho = tree.leaf_to_boxes(torch.tensor(w.rho, device=dev))
-    del w
-    u = torch.empty_like(rho)
-    work = torch.empty(tree.workspace_bytes(A.make_opts(precision="mixed")), dtype=torch.uint8, device=dev)
+    bc = tree.bc_rows(torch.tensor(w.bc, device=dev))
+    u = torch.zeros_like(rho)
+    ws = torch.empty(tree.workspace_bytes(A.make_opts(precision="mixed")), dtype=torch.uint8, device=dev)
     if not args.no_autotune:
         tree.autotune(dev, stream)
-    out = {"workload": "ex4_3d_uniform_512", "unknowns": int(tree.n_unknowns), "boxes": int(tree.n_boxes),
-           "paper_ns_per_unknown_8cube_16_cores": 22.0}
+    out = {"workload": "c2_3d_uniform_256_box16", "box_n": 16, "unknowns": int(tree.n_unknowns),
+           "boxes": int(tree.n_boxes)}
     for precision in ("fp64", "mixed"):
-        # FP64: the FMG cycle alone; mixed: the first refinement step, whose
-        # correction is one FP32 FMG cycle
-        ms, (_, st) = timed_loop(args, torch, lambda: A.solve(
-            tree, rho, None, u, cycle="FMG", max_cycles=0 if precision == "fp64" else 1, precision=precision,
-            workspace=work, stream=stream, use_guess=False, check=False))
-        out[precision] = {"ms_per_fmg_cycle": ms, "ns_per_unknown": ms * 1e6 / tree.n_unknowns,
-                          "residual_ratio_after_fmg": st["r_max"] / st["r0_max"]}
+        def one(prof=False):
+            return A.solve(tree, rho, bc, u, cycle="FMG", tol=1e-10, precision=precision, workspace=ws,
+                           stream=stream, use_guess=False, profile=prof)
+        ms, (_, st) = timed_loop(args, torch, one)
+        rec = {"ms_per_step": ms, "value": tree.n_unknowns / (ms * 1e-3), "unit": "unknowns/s",
+               "cycles": st["cycles"], "residual_ratio": st["r_max"] / st["r0_max"]}
+        if precision == "fp64":
+            _, stp = one(True)
+            torch.cuda.synchronize()
+            rec["roofline"] = gsrb_roofline(stp["prof_ms"][0], stp["prof_n"][0], tree.n_unknowns,
+                                            "k_gsrb<3,16,double,256,false> (finest level, one half sweep)")
+            if ref is not None:
+                # on a uniform grid the two box sizes give the same grids,
+                # ghosts and red-black order: the same solution to rounding
+                g16 = to_grid(16, w.level, w.idx, tree.boxes_to_leaf(u).cpu().numpy())
+                g8 = to_grid(ref[2], ref[0], ref[1], ref[3])
+                rec["max_rel_diff_vs_box8"] = float(np.abs(g16 - g8).max() / np.abs(g8).max())
+                del g16, g8
+        out[precision] = rec
     return out
 
 
@@ -856,6 +916,10 @@ def main():
                     help="run only warmup + steps FP64 solves of the workload with the default launch shapes, "
                          "eager (for whole-solve HBM counters)")
     ap.add_argument("--no-c1", action="store_true", help="skip the 2D 128^2 latency-bound workload")
+    ap.add_argument("--no-box16", action="store_true", help="skip the 256^3 workload on boxes of 16^3 cells")
+    ap.add_argument("--box16-only", action="store_true",
+                    help="run only the box-size workloads (256^3 and the 512^3 FMG cycle on 16^3 / 8^3 "
+                         "boxes) and print their record")
     ap.add_argument("--no-operators", action="store_true",
                     help="skip the variable-coefficient / cylindrical operator workloads")
     ap.add_argument("--operators-only", action="store_true",
@@ -909,6 +973,11 @@ def main():
         return 0
     if args.schemes_only:
         print(json.dumps(schemes_bench(args, A, torch, dev, torch.cuda.current_stream(dev))), flush=True)
+        return 0
+    if args.box16_only:
+        st_ = torch.cuda.current_stream(dev)
+        print(json.dumps({"box16": box16_bench(args, A, torch, dev, st_),
+                          "paper_ex": paper_ex_bench(args, A, torch, dev, st_)}), flush=True)
         return 0
 
     if args.solve_only:
@@ -1100,6 +1169,9 @@ def main():
         out["adjoint"] = adjoint_bench(args, A, torch, dev, stream)
     if not args.no_paper_ex:
         out["paper_ex"] = paper_ex_bench(args, A, torch, dev, stream)
+    if not args.no_box16:
+        ref = (w.level, w.idx, w.N, u64) if w.name == "c2_3d_uniform_256" else None
+        out["box16"] = box16_bench(args, A, torch, dev, stream, ref)
     if not args.no_operators:
         out["operators"] = operators_bench(args, A, torch, dev, stream)
     if not args.no_adapt:

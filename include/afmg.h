@@ -174,9 +174,11 @@ void afmg_default_opts(afmg_opts *opts);
  * 1-based spatial index idx[3*i .. 3*i+2] (third entry ignored in 2D) name
  * leaf i.  The leaves must tile [0,1]^D exactly and neighbouring leaves
  * (across a side) may differ by at most one level.  Host-only: no device
- * work happens here.  dim in {2,3}; box_n = 8.  On success *out owns the
- * tree (free with afmg_tree_destroy).  Errors: AFMG_ERR_ARG, AFMG_ERR_TREE,
- * AFMG_ERR_OOM.
+ * work happens here.  dim in {2,3}; box_n, the cells per box side (§2.1:
+ * an even parameter of the grid), is 8 or 16.  Below level 1 the solve adds
+ * coarse grids of N/2, ..., 2 cells per side (§3.2: two levels for N = 8,
+ * three for N = 16).  On success *out owns the tree (free with
+ * afmg_tree_destroy).  Errors: AFMG_ERR_ARG, AFMG_ERR_TREE, AFMG_ERR_OOM.
  */
 int afmg_tree_create(int dim, int box_n, int64_t n_leaves, const int32_t *level,
                      const int32_t *idx, afmg_tree **out);
@@ -495,8 +497,10 @@ typedef struct {
 
 /*
  * Group n_trees >= 1 trees of the same dim and box_n.  Their topology is
- * copied: the trees may be destroyed afterwards.  Host-only.  Errors:
- * AFMG_ERR_ARG (null, empty, mixed dimensions), AFMG_ERR_OOM.
+ * copied: the trees may be destroyed afterwards.  Trees take part when they
+ * have one level-1 box, Dirichlet sides and the Laplacian.  Host-only.
+ * Errors: AFMG_ERR_ARG (null, empty, mixed dimensions or box sizes, a tree
+ * that cannot take part), AFMG_ERR_OOM.
  */
 int afmg_batch_create(afmg_tree *const *trees, int n_trees, afmg_batch **out);
 
@@ -525,7 +529,8 @@ int afmg_batch_solve(afmg_batch *batch, void *stream, const double *rho, const d
  *
  * The per-level kernels of the cycle run in workgroups of 64, 128 or 256
  * threads, one thread per x-row of a box (N^(D-1) threads per box, so 1, 2
- * or 4 boxes per workgroup in 3D and 8, 16 or 32 in 2D), and either hand each
+ * or 4 boxes of 8^3 cells per workgroup in 3D and 8, 16 or 32 of 8^2 in 2D;
+ * a box of 16^3 cells needs the 256-thread workgroup), and either hand each
  * of the eight XCDs a contiguous run of boxes (siblings and neighbours share
  * that XCD's L2) or take boxes in launch order.  The shape is chosen per
  * kernel class, level and precision; every shape computes bitwise the same
@@ -556,7 +561,8 @@ int afmg_tree_autotune(afmg_tree *tree, void *stream, void *workspace, size_t wo
 int afmg_tree_shape(const afmg_tree *tree, int precision, int kind, int level, int *wg, int *no_remap);
 
 /* Set a shape; -1 for precision, kind or level selects all of them.
-   wg in {64, 128, 256}, no_remap in {0, 1}.  Errors: AFMG_ERR_ARG. */
+   wg in {64, 128, 256} holding whole boxes (wg >= box_n^(dim-1)),
+   no_remap in {0, 1}.  Errors: AFMG_ERR_ARG. */
 int afmg_tree_set_shape(afmg_tree *tree, int precision, int kind, int level, int wg, int no_remap);
 
 /* The same for a batch (its levels are those of the whole batch). */

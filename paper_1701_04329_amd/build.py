@@ -14,7 +14,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libafmg.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["afmg_tree.cpp", "afmg_kernels.hip", "afmg_solve.hip"]
+SOURCES = ["afmg_tree.cpp", "afmg_kernels.hip", "afmg_kernels_n16.hip", "afmg_solve.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [

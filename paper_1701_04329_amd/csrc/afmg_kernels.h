@@ -151,6 +151,10 @@ void launch_compact(const int *mask, const int64_t *ltoff, const int64_t *lvl_of
 // leaves the mask
 void launch_tree_stop(const double *norm, int *mask, TreeStop *state, double *hist, int n_trees, double tol,
                       int fixed, int nmax, hipStream_t st);
+// the one-tree coarse kernel holds levels <= 1 in LDS, and level 2 as well
+// where that fits a workgroup's LDS (all but 3D boxes of 16^3 cells); where
+// it does not, level 2 runs box by box and the kernel starts at level 1
+bool coarse_kernel_level2(int dim, int box_n);
 template <int D, int N, typename T>
 void launch_coarse(const CoarseArgs<T> &a, int n_trees, hipStream_t st);
 template <int D, int N, typename T>

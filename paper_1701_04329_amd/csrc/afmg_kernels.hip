@@ -10,7 +10,8 @@
 // No ghost layer is stored: side ghosts (paper §2.4, §3.3) are computed on
 // the fly from the neighbouring boxes.  Workgroups are 256 threads (four
 // wave64) and one thread owns one x-row of a box, so a workgroup holds four
-// boxes in 3D (one wave per box) and 32 in 2D.  Workgroup ids are
+// boxes of 8^3 cells in 3D (one wave per box) and 32 of 8^2 in 2D; a box of
+// 16^3 cells fills the workgroup, 16 boxes of 16^2 share one.  Workgroup ids are
 // remapped so that each of the eight XCDs processes a contiguous run of boxes:
 // Morton-ordered siblings and neighbours then share one L2.
 #include <hip/hip_runtime.h>
@@ -111,11 +112,12 @@ __device__ __forceinline__ int mort_nbr(int64_t b0, int m, int mask, bool hi) {
     return c != 0 ? (int)b0 + mort_dec(m, mask) : -1;
 }
 
-// Box record of box b.  With one box per wave (3D) the id is made
-// wave-uniform so that the record arrives through one scalar load.
+// Box record of box b.  When a box fills whole waves (3D: one wave per box
+// of 8^3 cells, four per box of 16^3) the id is made wave-uniform so that the
+// record arrives through one scalar load.
 template <int D, int N>
 __device__ __forceinline__ BoxInfo load_box(const BoxInfo *__restrict__ info, int64_t b) {
-    if (Geo<D, N>::TPB == 64) return info[__builtin_amdgcn_readfirstlane((int)b)];
+    if (Geo<D, N>::TPB % 64 == 0) return info[__builtin_amdgcn_readfirstlane((int)b)];
     return info[b];
 }
 
@@ -141,7 +143,7 @@ __device__ __forceinline__ Slot<D, N> slot_of(int64_t b0, int nb, bool remap = t
     r.slot = (int)threadIdx.x / G::TPB;
     r.t = (int)threadIdx.x % G::TPB;
     int bl = w * BPW + r.slot;
-    if (G::TPB == 64) bl = __builtin_amdgcn_readfirstlane(bl);  // one box per wave
+    if (G::TPB % 64 == 0) bl = __builtin_amdgcn_readfirstlane(bl);  // whole waves per box
     r.valid = bl < nb;
     r.b = b0 + (r.valid ? bl : 0);
     return r;
@@ -168,7 +170,7 @@ __device__ __forceinline__ Slot<D, N> slot_lvl(const LevelArgs<T> &a) {
     r.slot = (int)threadIdx.x / G::TPB;
     r.t = (int)threadIdx.x % G::TPB;
     int bl = w * BPW + r.slot;
-    if (G::TPB == 64) bl = __builtin_amdgcn_readfirstlane(bl);  // one box per wave
+    if (G::TPB % 64 == 0) bl = __builtin_amdgcn_readfirstlane(bl);  // whole waves per box
     r.valid = wb < g && bl < n;
     const int q = r.valid ? bl : 0;
     r.b = r.valid ? (int64_t)a.act[q] : a.b0;
@@ -1116,12 +1118,30 @@ __global__ __launch_bounds__(W) void k_final(LevelArgs<T> a, double *partial, in
             }
         }
     }
-    // reduce over the TPB threads of the box (one wave in 3D, 8 lanes in 2D)
-    for (int o = G::TPB / 2; o > 0; o >>= 1) {
+    // reduce over the TPB threads of the box (8 or 16 lanes in 2D, one wave
+    // in 3D with 8^3 cells), or over each wave of a box of several waves
+    constexpr int LW = G::TPB < 64 ? G::TPB : 64;
+    for (int o = LW / 2; o > 0; o >>= 1) {
         mx = fmax(mx, __shfl_xor(mx, o));
         ss += __shfl_xor(ss, o);
     }
     if (part0 < 0) {
+        if constexpr (G::TPB > 64) {
+            // the waves of the box through LDS, in wave order
+            constexpr int WPB = G::TPB / 64;
+            const int wave = (int)threadIdx.x / 64;
+            if ((threadIdx.x & 63) == 0) {
+                red_m[wave] = mx;
+                red_s[wave] = ss;
+            }
+            __syncthreads();
+            if (sl.t == 0) {
+                for (int q = 1; q < WPB; q++) {
+                    mx = fmax(mx, red_m[wave + q]);
+                    ss += red_s[wave + q];
+                }
+            }
+        }
         if (act && leaf && sl.t == 0) {
             partial[2 * sl.b + 0] = mx;
             partial[2 * sl.b + 1] = ss * hD;
@@ -1888,9 +1908,25 @@ __global__ __launch_bounds__(256) void k_box_flags(const BoxInfo *__restrict__ i
                     }
         }
     }
-    for (int o = G::TPB / 2; o > 0; o >>= 1) {
+    constexpr int LW = G::TPB < 64 ? G::TPB : 64;
+    for (int o = LW / 2; o > 0; o >>= 1) {
         w |= __shfl_xor(w, o);
         all_rm &= __shfl_xor(all_rm, o);
+    }
+    if constexpr (G::TPB > 64) {
+        // a box of several waves: its waves through LDS
+        __shared__ int red_w[4], red_a[4];
+        const int wave = (int)threadIdx.x / 64;
+        if ((threadIdx.x & 63) == 0) {
+            red_w[wave] = w;
+            red_a[wave] = all_rm;
+        }
+        __syncthreads();
+        if (sl.t == 0)
+            for (int q = 1; q < G::TPB / 64; q++) {
+                w |= red_w[wave + q];
+                all_rm &= red_a[wave + q];
+            }
     }
     if (sl.valid && sl.t == 0) words[sl.b] = leaf ? (w | (all_rm ? ADAPT_REMOVE : 0)) : 0;
 }
@@ -2018,6 +2054,7 @@ __global__ __launch_bounds__(256) void k_transfer_prolong(const BoxInfo *__restr
     }
 }
 
+#ifndef AFMG_INSTANTIATE_ONLY
 // One workgroup of 1024 threads: out[0] = max of the partial maxima, out[1] =
 // sqrt of the sum of the partial sums; the reduction order is fixed.
 __global__ __launch_bounds__(1024) void k_reduce(const double *__restrict__ partial, int64_t n, double *out,
@@ -2156,6 +2193,7 @@ __global__ __launch_bounds__(256) void k_tree_stop(const double *__restrict__ no
     state[t] = s;
     if (done) mask[t] = 0;
 }
+#endif  // AFMG_INSTANTIATE_ONLY
 
 // ---------------------------------------------------------------------------
 // small helpers
@@ -2261,6 +2299,7 @@ __global__ __launch_bounds__(256) void k_store_boxes(const int32_t *__restrict__
     }
 }
 
+#ifndef AFMG_INSTANTIATE_ONLY
 // Rows of F values: dst row r receives src row map[r].
 __global__ __launch_bounds__(256) void k_gather_rows(const int32_t *__restrict__ map, const double *__restrict__ src,
                                                      double *__restrict__ dst, int64_t n_rows, int F) {
@@ -2268,6 +2307,7 @@ __global__ __launch_bounds__(256) void k_gather_rows(const int32_t *__restrict__
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
         dst[i] = src[(int64_t)map[i / F] * F + i % F];
 }
+#endif  // AFMG_INSTANTIATE_ONLY
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_copy(const T *__restrict__ src, T *__restrict__ dst, int64_t n) {
@@ -2336,7 +2376,9 @@ struct CoarseGeo {
 template <int D, int N>
 struct CoarseState {
     using CG = CoarseGeo<D, N>;
-    double *u, *rho, *uold, *res, *bc;
+    // rho of a coarser grid receives the restricted residual, and then (in
+    // place) the FAS right-hand side: rbar + L u
+    double *u, *rho, *uold, *bc;
     int n_down, n_up, n_base;
 
     template <int G>
@@ -2456,7 +2498,7 @@ struct CoarseState {
             const int C = (int)threadIdx.x + it * nth<G>();
             if (C >= NC) continue;
             u[oc + C] = mu[it];
-            res[oc + C] = mr[it];
+            rho[oc + C] = mr[it];
         }
         sync<G>();
     }
@@ -2486,7 +2528,8 @@ struct CoarseState {
         }
         sync<G>();
     }
-    // copy v' of grid G, and the FAS right-hand side rho <- rbar + L u
+    // copy v' of grid G, and the FAS right-hand side rho <- rbar + L u (rho
+    // holds the restricted residual rbar)
     template <int G>
     __device__ __forceinline__ void uold_crhs() const {
         constexpr int o = CG::off(G), NC = CG::cells(G), IT = rounds<G, NC>();
@@ -2499,7 +2542,7 @@ struct CoarseState {
             int i, j, k;
             ijk<G>(c, i, j, k);
             uc[it] = u[o + c];
-            rc[it] = res[o + c] + (nbs<G>(u, i, j, k) - double(2 * D) * u[o + c]) * ih2;
+            rc[it] = rho[o + c] + (nbs<G>(u, i, j, k) - double(2 * D) * u[o + c]) * ih2;
         }
 #pragma unroll
         for (int it = 0; it < IT; it++) {
@@ -2775,14 +2818,33 @@ struct Level2 {
     }
 };
 
+// LDS of k_coarse: the FP64 chain (u, rho, v', Dirichlet rows) and the
+// padded level-2 grid with its rho and Dirichlet rows in T (FP64 counted)
+template <int D, int N>
+constexpr size_t coarse_lds_bytes(bool with_l2) {
+    using CG = CoarseGeo<D, N>;
+    using L2 = Level2<D, N, double>;
+    return sizeof(double) * (3 * (size_t)CG::TOT + CG::BTOT) +
+           (with_l2 ? sizeof(double) * ((size_t)L2::PCELLS + L2::CELLS + 2 * D * L2::F) : 0);
+}
+constexpr size_t LDS_PER_WORKGROUP = 160 * 1024;
+template <int D, int N>
+constexpr bool coarse_l2_fits() {
+    return coarse_lds_bytes<D, N>(true) <= LDS_PER_WORKGROUP;
+}
+static_assert(coarse_lds_bytes<3, 16>(false) <= LDS_PER_WORKGROUP, "levels <= 1 of 16^3 boxes fit");
+
 template <int D, int N, typename T>
 __global__ __launch_bounds__(COARSE_NT) void k_coarse(CoarseArgs<T> a) {
     using CG = CoarseGeo<D, N>;
     using G = Geo<D, N>;
     using L2 = Level2<D, N, T>;
-    __shared__ double f_u[CG::TOT], f_rho[CG::TOT], f_uold[CG::TOT], f_res[CG::TOT], f_bc[CG::BTOT];
-    __shared__ T l2_u[L2::PCELLS], l2_rho[L2::CELLS], l2_bc[2 * D * L2::F];
-    CoarseState<D, N> st{f_u, f_rho, f_uold, f_res, f_bc, a.n_down, a.n_up, a.n_base};
+    // level 2 in LDS where it fits (boxes of 8^D cells, 16^2); otherwise
+    // the scheduler runs level 2 box by box and asks for levels <= 1 only
+    constexpr bool HAS_L2 = coarse_l2_fits<D, N>();
+    __shared__ double f_u[CG::TOT], f_rho[CG::TOT], f_uold[CG::TOT], f_bc[CG::BTOT];
+    __shared__ T l2_u[HAS_L2 ? L2::PCELLS : 1], l2_rho[HAS_L2 ? L2::CELLS : 1], l2_bc[HAS_L2 ? 2 * D * L2::F : 1];
+    CoarseState<D, N> st{f_u, f_rho, f_uold, f_bc, a.n_down, a.n_up, a.n_base};
     // one workgroup per tree; the roots are boxes 0 .. n_trees-1
     const int64_t root = blockIdx.x;
     const BoxInfo *ri = a.info + root;
@@ -2803,7 +2865,7 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(CoarseArgs<T> a) {
     } else if (mode == COARSE_V_FROM_2 && root_leaf) {
         mode = COARSE_V_TOP1;
     }
-    const bool two = mode == COARSE_V2_FROM_3 || mode == COARSE_V2_TOP;
+    const bool two = HAS_L2 && (mode == COARSE_V2_FROM_3 || mode == COARSE_V2_TOP);
     T *gu = a.u + root * G::C;
     T *grho = a.rho + root * G::C;
     T *guold = a.uold ? a.uold + root * G::C : nullptr;
@@ -2827,7 +2889,7 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(CoarseArgs<T> a) {
         lb[q] = (g < 2 * D * G::F && !a.homog) ? a.bc[(size_t)ri->bcoff[g / G::F] * G::F + g % G::F] : 0.0;
     }
     const L2 lv2{l2_u, l2_rho, l2_bc, a.h2_2, a.ih2_2, parents};
-    if (two) {
+    if constexpr (HAS_L2) if (two) {
         // level 2: the children of the root into one grid, their Dirichlet
         // rows on the domain sides
         constexpr int C2 = (1 << D) * G::C, NE2 = (C2 + NT - 1) / NT;
@@ -2875,11 +2937,11 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(CoarseArgs<T> a) {
             lv2.resid_restrict(c, mu, mr);
             grho[e] = mr;
             f_u[c] = (double)mu;
-            f_rho[c] = 0.0;
-            f_res[c] = (double)mr;
+            f_rho[c] = (double)mr;
             f_uold[c] = 0.0;
         }
-    } else {
+    }
+    if (!two) {
 #pragma unroll
         for (int q = 0; q < NE; q++) {
             const int e = (int)threadIdx.x + q * NT;
@@ -2887,9 +2949,10 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(CoarseArgs<T> a) {
                 int i, j, k;
                 cell_of<D, N>(e, i, j, k);
                 const int c = i + N * (j + N * k);
+                // the right-hand side, or after a restriction from level 2
+                // the restricted residual
                 f_u[c] = lu[q];
-                f_rho[c] = mode == COARSE_V_FROM_2 ? 0.0 : lr[q];
-                f_res[c] = mode == COARSE_V_FROM_2 ? lr[q] : 0.0;
+                f_rho[c] = lr[q];
                 f_uold[c] = 0.0;
             }
         }
@@ -2898,7 +2961,6 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(CoarseArgs<T> a) {
         f_u[p] = 0.0;
         f_rho[p] = 0.0;
         f_uold[p] = 0.0;
-        f_res[p] = 0.0;
     }
 #pragma unroll
     for (int q = 0; q < NBC; q++) {
@@ -2941,17 +3003,19 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse(CoarseArgs<T> a) {
         gu[e] = (T)f_u[c];
         if (guold && mode != COARSE_V_TOP1) guold[e] = (T)f_uold[c];
     }
-    if (!two) return;
-    // back to level 2: correction from the root, smoothing, store
-    lv2.prolong(f_u, f_uold);
-    lv2.gsrb(a.n_up);
+    if constexpr (HAS_L2) {
+        if (!two) return;
+        // back to level 2: correction from the root, smoothing, store
+        lv2.prolong(f_u, f_uold);
+        lv2.gsrb(a.n_up);
 #pragma unroll 4
-    for (int e = threadIdx.x; e < (1 << D) * G::C; e += NT) {
-        const int o = e / G::C;
-        int i, j, k;
-        cell_of<D, N>(e % G::C, i, j, k);
-        const int c = L2::pad(i + (o & 1) * N, j + ((o >> 1) & 1) * N, D == 3 ? k + ((o >> 2) & 1) * N : 0);
-        a.u[(size_t)a.child[root * 8 + o] * G::C + e % G::C] = l2_u[c];
+        for (int e = threadIdx.x; e < (1 << D) * G::C; e += NT) {
+            const int o = e / G::C;
+            int i, j, k;
+            cell_of<D, N>(e % G::C, i, j, k);
+            const int c = L2::pad(i + (o & 1) * N, j + ((o >> 1) & 1) * N, D == 3 ? k + ((o >> 2) & 1) * N : 0);
+            a.u[(size_t)a.child[root * 8 + o] * G::C + e % G::C] = l2_u[c];
+        }
     }
 }
 
@@ -3679,6 +3743,7 @@ __global__ __launch_bounds__(256) void k_push_down(const BoxInfo *__restrict__ i
     }
 }
 
+#ifndef AFMG_INSTANTIATE_ONLY
 // per-workgroup (max |a|, sum a b) over n elements with a fixed grid, in a
 // fixed order; reduced by k_reduce
 __global__ __launch_bounds__(256) void k_dot(const double *__restrict__ a, const double *__restrict__ b,
@@ -3715,6 +3780,7 @@ __global__ __launch_bounds__(256) void k_lc3(double *out, double a, const double
         out[i] = v;
     }
 }
+#endif  // AFMG_INSTANTIATE_ONLY
 
 // dst = (h^D)^pw src on leaf boxes (pw in {-1, 0, 1}), 0 on parent boxes
 template <int D, int N>
@@ -3860,9 +3926,13 @@ void launch_level(Op op, const LevelArgs<T> &a, int colour, int wg, hipStream_t 
         launch_level_op<D, N, T>(op, a, colour, st);
         return;
     }
-    if (wg == 64) launch_level_w<D, N, T, 64>(op, a, colour, st);
-    else if (wg == 128) launch_level_w<D, N, T, 128>(op, a, colour, st);
-    else launch_level_w<D, N, T, 256>(op, a, colour, st);
+    // workgroups of 64 or 128 threads where they hold whole boxes
+    constexpr int TPB = Geo<D, N>::TPB;
+    if constexpr (TPB <= 64)
+        if (wg == 64) return launch_level_w<D, N, T, 64>(op, a, colour, st);
+    if constexpr (TPB <= 128)
+        if (wg == 128) return launch_level_w<D, N, T, 128>(op, a, colour, st);
+    launch_level_w<D, N, T, 256>(op, a, colour, st);
 }
 
 template <int D, int N, typename T, int W>
@@ -3881,9 +3951,12 @@ void launch_final(const LevelArgs<T> &a, double *partial, int64_t part0, double 
             AFMG_LAUNCH((k_vfinal<D, N, T>), (wg_count<D, N, 256>(a.nb)), st, a, partial, part0, hD);
         return;
     }
-    if (wg == 64) launch_final_w<D, N, T, 64>(a, partial, part0, hD, rout, st);
-    else if (wg == 128) launch_final_w<D, N, T, 128>(a, partial, part0, hD, rout, st);
-    else launch_final_w<D, N, T, 256>(a, partial, part0, hD, rout, st);
+    constexpr int TPB = Geo<D, N>::TPB;
+    if constexpr (TPB <= 64)
+        if (wg == 64) return launch_final_w<D, N, T, 64>(a, partial, part0, hD, rout, st);
+    if constexpr (TPB <= 128)
+        if (wg == 128) return launch_final_w<D, N, T, 128>(a, partial, part0, hD, rout, st);
+    launch_final_w<D, N, T, 256>(a, partial, part0, hD, rout, st);
 }
 
 template <int D, int N>
@@ -3895,9 +3968,15 @@ void launch_ir_update(const BoxInfo *info, double *u, float *e, int64_t nb, cons
 
 template <int D, int N>
 int final_wgs(int64_t nb, int wg) {
-    return wg == 64 ? wg_count<D, N, 64>(nb) : wg == 128 ? wg_count<D, N, 128>(nb) : wg_count<D, N, 256>(nb);
+    constexpr int TPB = Geo<D, N>::TPB;
+    if constexpr (TPB <= 64)
+        if (wg == 64) return wg_count<D, N, 64>(nb);
+    if constexpr (TPB <= 128)
+        if (wg == 128) return wg_count<D, N, 128>(nb);
+    return wg_count<D, N, 256>(nb);
 }
 
+#ifndef AFMG_INSTANTIATE_ONLY
 void launch_reduce(const double *partial, int64_t n, double *out, hipStream_t st) {
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, partial, n, out, 1);
 }
@@ -3922,6 +4001,7 @@ void launch_level_mask(const int *base, const int32_t *tree_lmax, int l, int *ou
     const int g = (n_trees + 255) / 256;
     AFMG_LAUNCH(k_level_mask, g, st, base, tree_lmax, l, out, n_trees);
 }
+#endif  // AFMG_INSTANTIATE_ONLY
 
 template <int D, int N, typename T>
 void launch_coarse(const CoarseArgs<T> &a, int n_trees, hipStream_t st) {
@@ -3981,12 +4061,14 @@ void launch_store_boxes(const int32_t *map, const T *src, T *dst, int64_t nb, hi
     AFMG_LAUNCH((k_store_boxes<D, N, T>), g, st, map, src, dst, (int)nb);
 }
 
+#ifndef AFMG_INSTANTIATE_ONLY
 void launch_gather_rows(const int32_t *map, const double *src, double *dst, int64_t n_rows, int F,
                         hipStream_t st) {
     int64_t g = (n_rows * F + 255) / 256;
     if (g > 65536) g = 65536;
     AFMG_LAUNCH(k_gather_rows, (int)g, st, map, src, dst, n_rows, F);
 }
+#endif  // AFMG_INSTANTIATE_ONLY
 
 template <int D, int N>
 void launch_bc_derive(const BoxInfo *info, int64_t b0, int64_t nb, double *bc, hipStream_t st) {
@@ -4049,6 +4131,7 @@ void launch_bc_grad(const BoxInfo *info, const double *lam, double *bc_bar, int6
     const int g = (int)((work + 255) / 256);
     AFMG_LAUNCH((k_bc_grad<D, N>), g, st, info, lam, bc_bar, (int)nb);
 }
+#ifndef AFMG_INSTANTIATE_ONLY
 void launch_dot(const double *a, const double *b, int64_t n, double *partial, double *out, hipStream_t st) {
     hipLaunchKernelGGL(k_dot, dim3(DOT_WGS), dim3(256), 0, st, a, b, n, partial);
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, partial, (int64_t)DOT_WGS, out, 0);
@@ -4059,6 +4142,7 @@ void launch_lc3(double *out, double a, const double *x, double b, const double *
     if (g > 65536) g = 65536;
     hipLaunchKernelGGL(k_lc3, dim3((unsigned)g), dim3(256), 0, st, out, a, x, b, y, c, z, n);
 }
+#endif  // AFMG_INSTANTIATE_ONLY
 
 #define AFMG_ADJ_INST(D, N)                                                                          \
     template void launch_apply_lt<D, N>(const BoxInfo *, const int *, const double *, double *, int64_t, \
@@ -4072,9 +4156,6 @@ void launch_lc3(double *out, double a, const double *x, double b, const double *
                                             hipStream_t);                                             \
     template void launch_bc_grad<D, N>(const BoxInfo *, const double *, double *, int64_t, hipStream_t);
 
-AFMG_ADJ_INST(2, 8)
-AFMG_ADJ_INST(3, 8)
-
 #define AFMG_INST(D, N, T)                                                                              \
     template void launch_level<D, N, T>(Op, const LevelArgs<T> &, int, int, hipStream_t);                \
     template void launch_final<D, N, T>(const LevelArgs<T> &, double *, int64_t, double, float *, int, \
@@ -4086,36 +4167,39 @@ AFMG_ADJ_INST(3, 8)
                                            hipStream_t);                                              \
     template void launch_store_boxes<D, N, T>(const int32_t *, const T *, T *, int64_t, hipStream_t);
 
-AFMG_INST(2, 8, double)
-AFMG_INST(3, 8, double)
-AFMG_INST(2, 8, float)
-AFMG_INST(3, 8, float)
-template void launch_ir_update<2, 8>(const BoxInfo *, double *, float *, int64_t, const int *, hipStream_t);
-template void launch_ir_update<3, 8>(const BoxInfo *, double *, float *, int64_t, const int *, hipStream_t);
+// every template the scheduler calls, for boxes of N^D cells
+#define AFMG_BOX_INST(D, N)                                                                                   \
+    AFMG_ADJ_INST(D, N)                                                                                       \
+    AFMG_INST(D, N, double)                                                                                   \
+    AFMG_INST(D, N, float)                                                                                    \
+    template void launch_ir_update<D, N>(const BoxInfo *, double *, float *, int64_t, const int *, hipStream_t); \
+    template size_t coarse_gen_doubles<D, N>(int);                                                           \
+    template void launch_restrict_field_op<D, N>(const BoxInfo *, double *, int64_t, int64_t, int,             \
+                                                 const int32_t *, double, hipStream_t);                        \
+    template void launch_check_positive<D, N>(const BoxInfo *, const double *, int64_t, int *, hipStream_t);  \
+    template void launch_box_flags<D, N>(const BoxInfo *, const int8_t *, int64_t, int, int32_t *, hipStream_t); \
+    template void launch_transfer<D, N>(const BoxInfo *, const BoxInfo *, const int32_t *, const int32_t *,    \
+                                        int64_t, const int32_t *, const int32_t *, int64_t, const double *,    \
+                                        const double *, int, double *, hipStream_t);                           \
+    template int final_wgs<D, N>(int64_t, int);                                                               \
+    template void launch_bc_derive<D, N>(const BoxInfo *, int64_t, int64_t, double *, hipStream_t);
+
+// Boxes of 8^D cells here; the boxes of 16^D cells are instantiated in a
+// translation unit of their own (afmg_kernels_n16.hip), which includes this
+// file with AFMG_INSTANTIATE_ONLY set.
+#ifndef AFMG_INSTANTIATE_ONLY
+AFMG_BOX_INST(2, 8)
+AFMG_BOX_INST(3, 8)
 template void launch_copy<float>(const float *, float *, int64_t, hipStream_t);
 template void launch_fill<float>(float *, int64_t, float, hipStream_t);
-template size_t coarse_gen_doubles<2, 8>(int);
-template void launch_restrict_field_op<2, 8>(const BoxInfo *, double *, int64_t, int64_t, int, const int32_t *,
-                                             double, hipStream_t);
-template void launch_restrict_field_op<3, 8>(const BoxInfo *, double *, int64_t, int64_t, int, const int32_t *,
-                                             double, hipStream_t);
-template void launch_check_positive<2, 8>(const BoxInfo *, const double *, int64_t, int *, hipStream_t);
-template void launch_box_flags<2, 8>(const BoxInfo *, const int8_t *, int64_t, int, int32_t *, hipStream_t);
-template void launch_box_flags<3, 8>(const BoxInfo *, const int8_t *, int64_t, int, int32_t *, hipStream_t);
-template void launch_transfer<2, 8>(const BoxInfo *, const BoxInfo *, const int32_t *, const int32_t *, int64_t,
-                                    const int32_t *, const int32_t *, int64_t, const double *, const double *, int,
-                                    double *, hipStream_t);
-template void launch_transfer<3, 8>(const BoxInfo *, const BoxInfo *, const int32_t *, const int32_t *, int64_t,
-                                    const int32_t *, const int32_t *, int64_t, const double *, const double *, int,
-                                    double *, hipStream_t);
-template void launch_check_positive<3, 8>(const BoxInfo *, const double *, int64_t, int *, hipStream_t);
-template size_t coarse_gen_doubles<3, 8>(int);
-template int final_wgs<2, 8>(int64_t, int);
-template int final_wgs<3, 8>(int64_t, int);
-template void launch_bc_derive<2, 8>(const BoxInfo *, int64_t, int64_t, double *, hipStream_t);
-template void launch_bc_derive<3, 8>(const BoxInfo *, int64_t, int64_t, double *, hipStream_t);
 template void launch_copy<double>(const double *, double *, int64_t, hipStream_t);
 template void launch_fill<double>(double *, int64_t, double, hipStream_t);
 template void launch_fill<int>(int *, int64_t, int, hipStream_t);
+
+bool coarse_kernel_level2(int dim, int box_n) {
+    if (dim == 3) return box_n == 8 ? coarse_l2_fits<3, 8>() : box_n == 16 ? coarse_l2_fits<3, 16>() : false;
+    return box_n == 8 ? coarse_l2_fits<2, 8>() : box_n == 16 ? coarse_l2_fits<2, 16>() : false;
+}
+#endif  // AFMG_INSTANTIATE_ONLY
 
 }  // namespace afmg

@@ -125,7 +125,21 @@ struct afmg_batch {
 
 namespace {
 
-constexpr int BOX_N = 8;
+// Boxes of 8^D or 16^D cells (paper §2.1: N is a parameter of the grid); the
+// kernels and the scheduler are instantiated for both: FN<dim, N> ARGS.
+#define AFMG_BOX_DISPATCH(h, FN, ARGS)                               \
+    do {                                                             \
+        if ((h).dim == 3) {                                          \
+            if ((h).N == 16) FN<3, 16> ARGS;                         \
+            else FN<3, 8> ARGS;                                      \
+        } else {                                                     \
+            if ((h).N == 16) FN<2, 16> ARGS;                         \
+            else FN<2, 8> ARGS;                                      \
+        }                                                            \
+    } while (0)
+#define AFMG_BOX_RETURN(h, FN, ARGS)                                      \
+    return (h).dim == 3 ? ((h).N == 16 ? FN<3, 16> ARGS : FN<3, 8> ARGS)  \
+                        : ((h).N == 16 ? FN<2, 16> ARGS : FN<2, 8> ARGS)
 
 int fail(int code, const std::string &msg) {
     set_error(msg);
@@ -136,9 +150,10 @@ int hip_fail(hipError_t e, const char *what) {
     return fail(AFMG_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-int64_t cells_per_box(int dim) { return dim == 3 ? BOX_N * BOX_N * BOX_N : BOX_N * BOX_N; }
-int64_t cells_per_face(int dim) { return dim == 3 ? BOX_N * BOX_N : BOX_N; }
-double level_h(int l) { return 1.0 / ((double)BOX_N * std::ldexp(1.0, l - 1)); }
+int64_t cells_per_box(int dim, int n) { return dim == 3 ? (int64_t)n * n * n : (int64_t)n * n; }
+int64_t cells_per_face(int dim, int n) { return dim == 3 ? (int64_t)n * n : n; }
+// cell size of level l (level-1 boxes are unit cubes, paper §2.2)
+double level_h(int l, int n) { return 1.0 / ((double)n * std::ldexp(1.0, l - 1)); }
 
 // x bits of the Morton key of level l when the level is complete (one tree,
 // all 2^(D (l-1)) boxes present, so that box index = key); 0 otherwise
@@ -158,17 +173,28 @@ struct WsLayout {
     size_t rho, uold, bc, partial, e, rho_e, uold_e, u, cg, total;
 };
 
-// doubles of the general coarse kernel's grids (0 unless the domain is general)
+// Levels <= 1 take the general coarse kernel (grids in global memory) on
+// general domains, the one-tree coarse kernel (LDS) otherwise.
+bool coarse_general(const HostTree &h) { return h.general; }
+
+// The coarsest level the box kernels run: 2 on general domains and where the
+// one-tree coarse kernel's LDS cannot hold level 2 as well (3D boxes of 16^3
+// cells), else 3 (level 2 inside the coarse kernel).
+int box_lo(const HostTree &h) { return (h.general || !coarse_kernel_level2(h.dim, h.N)) ? 2 : 3; }
+
+// bytes of the general coarse kernel's grids (0 where it is not used)
 size_t coarse_gen_bytes(const HostTree &h) {
-    if (!h.general) return 0;
-    return sizeof(double) * (h.dim == 3 ? coarse_gen_doubles<3, 8>(h.n_roots) : coarse_gen_doubles<2, 8>(h.n_roots));
+    if (!coarse_general(h)) return 0;
+    size_t n = 0;
+    AFMG_BOX_DISPATCH(h, n = coarse_gen_doubles, (h.n_roots));
+    return sizeof(double) * n;
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 WsLayout ws_layout(const afmg_tree *t, int precision) {
     const HostTree &h = t->h;
-    const size_t C = (size_t)cells_per_box(h.dim), F = (size_t)cells_per_face(h.dim);
+    const size_t C = (size_t)cells_per_box(h.dim, h.N), F = (size_t)cells_per_face(h.dim, h.N);
     const size_t nlt = (size_t)h.n_below_lmax(), nb = (size_t)h.n_boxes;
     const bool mixed = precision == AFMG_MIXED;
     const size_t np = t->forest ? nb : (size_t)std::max<int64_t>(1, t->n_parts_max);
@@ -194,7 +220,7 @@ struct TuneLayout {
 
 TuneLayout tune_layout(const afmg_tree *t) {
     const HostTree &h = t->h;
-    const size_t C = (size_t)cells_per_box(h.dim), F = (size_t)cells_per_face(h.dim);
+    const size_t C = (size_t)cells_per_box(h.dim, h.N), F = (size_t)cells_per_face(h.dim, h.N);
     const size_t nlt = (size_t)h.n_below_lmax(), nb = (size_t)h.n_boxes;
     TuneLayout L{};
     size_t off = 0;
@@ -210,8 +236,8 @@ TuneLayout tune_layout(const afmg_tree *t) {
     return L;
 }
 
-template <int D>
-int64_t final_wgs_d(int64_t nb, int wg) { return final_wgs<D, BOX_N>(nb, wg); }
+template <int D, int N>
+int64_t final_wgs_d(int64_t nb, int wg) { return final_wgs<D, N>(nb, wg); }
 
 
 // k_final partial offsets per level for the current shapes, and the count
@@ -227,8 +253,8 @@ void compute_partials(afmg_tree *t) {
         t->part_off[(size_t)l] = n;
         if (l >= 2 || h.level1_leaf) {
             const int wg = t->shapes[0][SK_FINAL][(size_t)l].wg;
-            n += h.dim == 3 ? final_wgs_d<3>(h.level_count(l), wg) : final_wgs_d<2>(h.level_count(l), wg);
-            nmax += h.dim == 3 ? final_wgs_d<3>(h.level_count(l), 64) : final_wgs_d<2>(h.level_count(l), 64);
+            AFMG_BOX_DISPATCH(h, n += final_wgs_d, (h.level_count(l), wg));
+            AFMG_BOX_DISPATCH(h, nmax += final_wgs_d, (h.level_count(l), 64));
         }
     }
     t->n_parts = n;
@@ -388,7 +414,7 @@ struct Prof {
 // ---------------------------------------------------------------------------
 // the FAS cycles (paper §3.2) on arrays of type T
 // ---------------------------------------------------------------------------
-template <int D, typename T>
+template <int D, int N, typename T>
 struct Cycler {
     const HostTree &h;
     hipStream_t st;
@@ -417,7 +443,7 @@ struct Cycler {
         a.b0 = h.lvl_off[(size_t)l];
         a.nb = (int)h.level_count(l);
         a.xmask = cube_xmask(h, l);
-        const double hh = level_h(l);
+        const double hh = level_h(l, N);
         a.h2 = (T)(hh * hh);
         a.ih2 = (T)(1.0 / (hh * hh));
         a.h = (T)hh;
@@ -442,7 +468,7 @@ struct Cycler {
         a.no_remap = sh.no_remap;
         a.add_to = add;
         a.own_zero = own_zero ? 1 : 0;
-        prof.timed(kind, l, [&] { launch_level<D, BOX_N, T>(op, a, colour, sh.wg, st); }, st);
+        prof.timed(kind, l, [&] { launch_level<D, N, T>(op, a, colour, sh.wg, st); }, st);
     }
     // n sweeps; their 2n half sweeps are timed as one group.  add: the last
     // half sweep adds the level's values to this FP64 array and clears its
@@ -467,14 +493,14 @@ struct Cycler {
     // top-level-1 path inside the kernel.  General domains: one workgroup for
     // all level-1 boxes and the grids below them.
     void coarse(int mode) {
-        if (h.general) {
+        if (coarse_general(h)) {
             CoarseGenArgs<T> c{base.info, base.u, base.rho, h.lmax >= 2 ? base.uold : nullptr, bc64, cg,
                                h.n_roots, mode, base.homog, o.n_down, o.n_up, o.n_base};
             c.eps = t->d_eps;
             c.bx = t->d_bx;
             c.opk = t->opk;
             c.dnbr = t->d_dnbr;
-            launch_coarse_gen<D, BOX_N, T>(c, st);
+            launch_coarse_gen<D, N, T>(c, st);
             return;
         }
         CoarseArgs<T> c{base.info, base.u, base.rho, base.uold, bc64, mode, base.homog,
@@ -486,7 +512,7 @@ struct Cycler {
             c.h2_2 = a2.h2;
             c.ih2_2 = a2.ih2;
         }
-        launch_coarse<D, BOX_N, T>(c, h.n_trees, st);
+        launch_coarse<D, N, T>(c, h.n_trees, st);
     }
     // V-cycle from level top: levels >= 3 box by box, levels <= 2 in the
     // coarse kernel (level 2, the 2^D children of the root, as one grid);
@@ -497,13 +523,13 @@ struct Cycler {
             coarse(COARSE_V_TOP1);
             return;
         }
-        const int lo = h.general ? 2 : 3;
+        const int lo = box_lo(h);
         for (int l = top; l >= lo; l--) {
             gsrb(l, o.n_down, nullptr, l == top && zero_start && fuses_update(top));
             level(Op::RESID_RESTRICT, l);
             if (l - 1 >= lo) level(Op::COARSE_RHS, l - 1);
         }
-        coarse(h.general ? COARSE_V_FROM_2 : top >= 3 ? COARSE_V2_FROM_3 : COARSE_V2_TOP);
+        coarse(lo == 2 ? COARSE_V_FROM_2 : top >= 3 ? COARSE_V2_FROM_3 : COARSE_V2_TOP);
         for (int l = lo; l <= top; l++) {
             level(Op::PROLONG, l);
             gsrb(l, o.n_up, l == top && fuses_update(top) ? add_to : nullptr);
@@ -514,10 +540,10 @@ struct Cycler {
     // the step at level l involves only the trees that reach level l.
     // zero_u = false: u is zero already.
     void fmg(bool zero_u = true) {
-        if (zero_u) launch_fill<T>(base.u, h.n_boxes * cells_per_box(D), T(0), st);
+        if (zero_u) launch_fill<T>(base.u, h.n_boxes * cells_per_box(D, N), T(0), st);
         for (int l = h.lmax; l >= 2; l--) level(Op::RESTRICT_RHO, l);
         coarse(COARSE_FMG);
-        const int64_t C = cells_per_box(D);
+        const int64_t C = cells_per_box(D, N);
         const LevelArgs<T> saved = base;
         for (int l = 2; l <= h.lmax; l++) {
             if (saved.active) {
@@ -543,7 +569,7 @@ struct Cycler {
 // ---------------------------------------------------------------------------
 // the solve
 // ---------------------------------------------------------------------------
-template <int D>
+template <int D, int N>
 struct Solver {
     afmg_tree *t;
     const HostTree &h;
@@ -567,7 +593,7 @@ struct Solver {
     void finalize_launch(float *rout, hipStream_t s, int lfirst = 1, double *norm_out = nullptr) {
         for (int l = h.lmax; l >= std::max(1, lfirst); l--) {
             if (l == 1 && !t->forest && !h.level1_leaf) continue;
-            const double hh = level_h(l);
+            const double hh = level_h(l, N);
             const double hD = D == 3 ? hh * hh * hh : hh * hh;
             LevelArgs<double> a = base;
             a.b0 = h.lvl_off[(size_t)l];
@@ -584,7 +610,7 @@ struct Solver {
             prof.timed(
                 AFMG_PROF_FINAL, l,
                 [&] {
-                    launch_final<D, BOX_N, double>(a, partial, t->forest ? -1 : t->part_off[(size_t)l], hD, rout,
+                    launch_final<D, N, double>(a, partial, t->forest ? -1 : t->part_off[(size_t)l], hD, rout,
                                                    sh.wg, s);
                 },
                 s);
@@ -600,10 +626,10 @@ struct Solver {
     void restrict_parents() {
         for (int l = h.lmin_leaf - 1; l >= 2; l--) {
             if (t->opk)
-                launch_restrict_field_op<D, BOX_N>(t->d_info, base.u, h.lvl_off[(size_t)l], h.level_count(l), t->opk,
-                                                   t->d_bx, level_h(l), st);
+                launch_restrict_field_op<D, N>(t->d_info, base.u, h.lvl_off[(size_t)l], h.level_count(l), t->opk,
+                                                   t->d_bx, level_h(l, N), st);
             else
-                launch_restrict_field<D, BOX_N>(t->d_info, base.u, h.lvl_off[(size_t)l], h.level_count(l), st);
+                launch_restrict_field<D, N>(t->d_info, base.u, h.lvl_off[(size_t)l], h.level_count(l), st);
         }
     }
     // the norms in t->h_norm (written there by the reduction kernels, no
@@ -714,8 +740,8 @@ struct Track {
 // applied, every check_every cycles (and after the last allowed cycle); the
 // history of the cycles in between holds NaN.  Running trees have run the
 // same number of cycles, so one m serves them all.
-template <int D, class Step>
-int iterate_trees(Solver<D> &s, afmg_stats *S, std::vector<Track> &tr, Step step) {
+template <int D, int N, class Step>
+int iterate_trees(Solver<D, N> &s, afmg_stats *S, std::vector<Track> &tr, Step step) {
     afmg_tree *t = s.t;
     const afmg_opts &o = s.o;
     const int n = t->h.n_trees;
@@ -786,8 +812,8 @@ int iterate_trees(Solver<D> &s, afmg_stats *S, std::vector<Track> &tr, Step step
 // no per-cycle synchronisation or mask upload.  cycle(stream, first)
 // enqueues one cycle, with the trees' norms into t->d_tnorm; first: the
 // mixed path's FMG step, run eagerly as the first cycle.
-template <int D, class Cycle>
-int iterate_forest(Solver<D> &s, afmg_stats *S, const std::vector<uintptr_t> &key, bool first_fmg, Cycle cycle) {
+template <int D, int N, class Cycle>
+int iterate_forest(Solver<D, N> &s, afmg_stats *S, const std::vector<uintptr_t> &key, bool first_fmg, Cycle cycle) {
     afmg_tree *t = s.t;
     const afmg_opts &o = s.o;
     const HostTree &h = t->h;
@@ -888,14 +914,14 @@ void take_norms(const afmg_tree *t, afmg_stats *S, bool initial) {
     }
 }
 
-template <int D>
+template <int D, int N>
 int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, double *u, char *ws,
           const afmg_opts &o, afmg_stats *S) {
     const HostTree &h = t->h;
     const int n = h.n_trees;
     const bool mixed = o.precision == AFMG_MIXED;
     const WsLayout L = ws_layout(t, o.precision);
-    Solver<D> s(t, st, o, &S[0]);
+    Solver<D, N> s(t, st, o, &S[0]);
     if (o.profile && t->events.empty()) {
         t->events.resize(2 * PROF_PAIRS);
         for (auto &ev : t->events)
@@ -911,7 +937,7 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
     s.base.bx = t->d_bx;
     s.base.opk = t->opk;
     s.base.dnbr = t->d_dnbr;
-    const int64_t F = cells_per_face(D), C = cells_per_box(D);
+    const int64_t F = cells_per_face(D, N), C = cells_per_box(D, N);
 
     hipEvent_t ev0 = t->span[0], ev1 = t->span[1];
     (void)hipEventRecord(ev0, st);
@@ -928,15 +954,15 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
         }
     }
     for (int l = h.lmax; l >= 2; l--)
-        launch_bc_derive<D, BOX_N>(t->d_info, h.lvl_off[(size_t)l], h.level_count(l), bc_w, st);
+        launch_bc_derive<D, N>(t->d_info, h.lvl_off[(size_t)l], h.level_count(l), bc_w, st);
     // working copies in the colour-split box layout: rho of the leaves, and
     // u (in place for one tree; a zero guess needs no conversion)
     const int32_t *map = t->forest ? t->d_box_map : nullptr;
-    launch_load_rho<D, BOX_N, double>(t->d_info, map, rho, rho_i, h.n_boxes, 1, st);
+    launch_load_rho<D, N, double>(t->d_info, map, rho, rho_i, h.n_boxes, 1, st);
     const bool guess = o.use_guess && (mixed || o.cycle == AFMG_CYCLE_V);
     if (!guess) launch_fill<double>(uw, h.n_boxes * C, 0.0, st);
-    else if (t->forest) launch_load_rho<D, BOX_N, double>(t->d_info, map, u, uw, h.n_boxes, 0, st);
-    else launch_permute<D, BOX_N, double>(t->d_info, u, 0, h.n_boxes, 1, 0, st);
+    else if (t->forest) launch_load_rho<D, N, double>(t->d_info, map, u, uw, h.n_boxes, 0, st);
+    else launch_permute<D, N, double>(t->d_info, u, 0, h.n_boxes, 1, 0, st);
 
     float *e32 = mixed ? (float *)(ws + L.e) : nullptr;
     float *rho32 = mixed ? (float *)(ws + L.rho_e) : nullptr;
@@ -961,7 +987,7 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
     if (!any) {
         // nothing to iterate
     } else if (!mixed) {
-        Cycler<D, double> cy{h, st, o, s.prof, s.base, bc_w, t};
+        Cycler<D, N, double> cy{h, st, o, s.prof, s.base, bc_w, t};
         cy.cg = (double *)(ws + L.cg);
         if (o.cycle == AFMG_CYCLE_FMG_V) {
             rc = s.upload_mask();
@@ -974,7 +1000,7 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
         }
         if (t->forest) {
             rc = iterate_forest(s, S, key, false, [&](hipStream_t cs, bool) {
-                Cycler<D, double> c2 = cy;
+                Cycler<D, N, double> c2 = cy;
                 c2.st = cs;
                 c2.vcycle(h.lmax);
                 s.finalize_launch(nullptr, cs, h.lmin_leaf, t->d_tnorm);
@@ -984,7 +1010,7 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
                 std::vector<uintptr_t> km = key;
                 km.push_back((uintptr_t)m);
                 const int q = s.run(km, [&](hipStream_t cs) {
-                    Cycler<D, double> c2 = cy;
+                    Cycler<D, N, double> c2 = cy;
                     c2.st = cs;
                     for (int c = 0; c < m; c++) c2.vcycle(h.lmax);
                     s.finalize_launch(nullptr, cs, h.lmin_leaf);
@@ -1004,12 +1030,12 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
         // takes the other colour's old values as zero.
         LevelArgs<float> b32{t->d_info, e32, rho32, (float *)(ws + L.uold_e), nullptr, 0, 0, 1, 0.f, 0.f,
                              t->d_active};
-        Cycler<D, float> cy{h, st, o, s.prof, b32, nullptr, t};
+        Cycler<D, N, float> cy{h, st, o, s.prof, b32, nullptr, t};
         cy.cg = (double *)(ws + L.cg);
         if (!t->forest && h.uniform && cube_xmask(h, h.lmax) != 0) cy.add_to = uw;
         if (o.cycle != AFMG_CYCLE_FMG_V) launch_fill<float>(e32, h.n_boxes * C, 0.f, st);
         auto refine = [&](hipStream_t cs, bool first_fmg) {
-            Cycler<D, float> c2 = cy;
+            Cycler<D, N, float> c2 = cy;
             c2.st = cs;
             if (first_fmg) {
                 c2.fmg();
@@ -1018,7 +1044,7 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
                 c2.vcycle(h.lmax);
             }
             if (!c2.fuses_update(h.lmax))
-                launch_ir_update<D, BOX_N>(t->d_info, uw, e32, h.n_boxes, t->d_active, cs);
+                launch_ir_update<D, N>(t->d_info, uw, e32, h.n_boxes, t->d_active, cs);
             s.finalize_launch(rho32, cs, h.lmin_leaf, t->forest ? t->d_tnorm : nullptr);
         };
         if (t->forest) {
@@ -1042,8 +1068,8 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
     }
     if (rc != AFMG_OK) return rc;
     if (any) s.restrict_parents();
-    if (t->forest) launch_store_boxes<D, BOX_N, double>(t->d_box_map, uw, u, h.n_boxes, st);
-    else launch_permute<D, BOX_N, double>(t->d_info, u, 0, h.n_boxes, 0, 0, st);
+    if (t->forest) launch_store_boxes<D, N, double>(t->d_box_map, uw, u, h.n_boxes, st);
+    else launch_permute<D, N, double>(t->d_info, u, 0, h.n_boxes, 0, 0, st);
     (void)hipEventRecord(ev1, st);
     (void)hipEventSynchronize(ev1);
     float ms = 0.f;
@@ -1074,7 +1100,7 @@ struct AdjLayout {
 
 AdjLayout adj_layout(const afmg_tree *t) {
     const HostTree &h = t->h;
-    const size_t C = (size_t)cells_per_box(h.dim), F = (size_t)cells_per_face(h.dim);
+    const size_t C = (size_t)cells_per_box(h.dim, h.N), F = (size_t)cells_per_face(h.dim, h.N);
     const size_t nb = (size_t)h.n_boxes, nlt = (size_t)h.n_below_lmax();
     AdjLayout L{};
     size_t off = 0;
@@ -1092,7 +1118,7 @@ AdjLayout adj_layout(const afmg_tree *t) {
     return L;
 }
 
-template <int D>
+template <int D, int N>
 struct Adj {
     afmg_tree *t;
     const HostTree &h;
@@ -1115,26 +1141,26 @@ struct Adj {
         return AFMG_OK;
     }
     void apply_lt(const double *y, double *out) {
-        launch_apply_lt<D, BOX_N>(t->d_info, t->d_child, y, out, h.n_boxes, st);
+        launch_apply_lt<D, N>(t->d_info, t->d_child, y, out, h.n_boxes, st);
     }
     // x must be zero on parents; its restriction is written there first
     void apply_l(double *x, double *out) {
         for (int l = h.lmax; l >= 2; l--)
-            launch_restrict_field<D, BOX_N>(t->d_info, x, h.lvl_off[(size_t)l], h.level_count(l), st);
-        launch_apply_l<D, BOX_N>(t->d_info, x, out, h.n_boxes, st);
+            launch_restrict_field<D, N>(t->d_info, x, h.lvl_off[(size_t)l], h.level_count(l), st);
+        launch_apply_l<D, N>(t->d_info, x, out, h.n_boxes, st);
     }
 };
 
-template <int D>
+template <int D, int N>
 int apply_op(afmg_tree *t, hipStream_t st, int op, const double *x, double *y, char *ws) {
     const HostTree &h = t->h;
-    Adj<D> A{t, h, st, ws, adj_layout(t), h.n_boxes * cells_per_box(D), nullptr, nullptr};
+    Adj<D, N> A{t, h, st, ws, adj_layout(t), h.n_boxes * cells_per_box(D, N), nullptr, nullptr};
     double *X = A.vec(AdjLayout::X), *Y = A.vec(AdjLayout::R);
     launch_fill<double>(X, A.n, 0.0, st);
-    launch_load_rho<D, BOX_N, double>(t->d_info, nullptr, x, X, h.n_boxes, 1, st);
+    launch_load_rho<D, N, double>(t->d_info, nullptr, x, X, h.n_boxes, 1, st);
     if (op == AFMG_OP_L) A.apply_l(X, Y);
     else A.apply_lt(X, Y);
-    launch_store_leaves<D, BOX_N>(t->d_info, Y, y, h.n_boxes, st);
+    launch_store_leaves<D, N>(t->d_info, Y, y, h.n_boxes, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "operator application");
     return AFMG_OK;
@@ -1142,35 +1168,35 @@ int apply_op(afmg_tree *t, hipStream_t st, int op, const double *x, double *y, c
 
 // lambda = L^-T ubar on the leaf cells; rho_bar = lambda, bc_bar = -2 lambda / h^2
 // on the leaf cells next to the Dirichlet rows.
-template <int D>
+template <int D, int N>
 int adjoint(afmg_tree *t, hipStream_t st, const double *ubar, double *rho_bar, double *bc_bar, char *ws,
             const afmg_opts &o, afmg_stats &S) {
     const HostTree &h = t->h;
-    Adj<D> A{t, h, st, ws, adj_layout(t), h.n_boxes * cells_per_box(D), nullptr, nullptr};
+    Adj<D, N> A{t, h, st, ws, adj_layout(t), h.n_boxes * cells_per_box(D, N), nullptr, nullptr};
     A.partial = (double *)(ws + A.L.partial);
     A.norm = (double *)(ws + A.L.norm);
     double *X = A.vec(AdjLayout::X), *B = A.vec(AdjLayout::B);
     double *bcz = (double *)(ws + A.L.bc);
-    const int64_t n = A.n, F = cells_per_face(D);
+    const int64_t n = A.n, F = cells_per_face(D, N);
     hipEvent_t ev0 = t->span[0], ev1 = t->span[1];
     (void)hipEventRecord(ev0, st);
     // u_bar in the working layout; values on parent boxes (the restriction of
     // the leaves) are pushed to the leaves through the transposed restriction
     launch_copy<double>(ubar, B, n, st);
-    launch_permute<D, BOX_N, double>(t->d_info, B, 0, h.n_boxes, 1, 0, st);
+    launch_permute<D, N, double>(t->d_info, B, 0, h.n_boxes, 1, 0, st);
     for (int l = 2; l <= h.lmax; l++)
-        launch_push_down<D, BOX_N>(t->d_info, B, h.lvl_off[(size_t)l], h.level_count(l), st);
-    launch_scale_leaves<D, BOX_N>(t->d_info, B, B, 0, h.n_boxes, st);
+        launch_push_down<D, N>(t->d_info, B, h.lvl_off[(size_t)l], h.level_count(l), st);
+    launch_scale_leaves<D, N>(t->d_info, B, B, 0, h.n_boxes, st);
     launch_fill<double>(bcz, std::max<int64_t>(1, h.n_bfaces_all) * F, 0.0, st);
     launch_fill<double>(X, n, 0.0, st);
-    Solver<D> s(t, st, o, &S);
+    Solver<D, N> s(t, st, o, &S);
     s.partial = A.partial;
     int status = AFMG_OK, rc;
     if (h.uniform) {
         // the operator is symmetric: lambda solves L lambda = ubar with zero
         // Dirichlet values, one more multigrid solve
         s.base = LevelArgs<double>{t->d_info, X, B, (double *)(ws + A.L.puold), bcz, 0, 0, 1, 0.0, 0.0};
-        Cycler<D, double> cy{h, st, o, s.prof, s.base, nullptr, t};
+        Cycler<D, N, double> cy{h, st, o, s.prof, s.base, nullptr, t};
         cy.cg = (double *)(ws + A.L.cg);
         rc = s.finalize(S.r0_max, S.r0_l2, nullptr);
         if (rc != AFMG_OK) return rc;
@@ -1189,13 +1215,13 @@ int adjoint(afmg_tree *t, hipStream_t st, const double *ubar, double *rho_bar, d
         double *PH = A.vec(AdjLayout::PH), *SH = A.vec(AdjLayout::SH);
         double *PU = A.vec(AdjLayout::PU), *PRHO = A.vec(AdjLayout::PRHO);
         LevelArgs<double> pb{t->d_info, PU, PRHO, (double *)(ws + A.L.puold), bcz, 0, 0, 1, 0.0, 0.0};
-        Cycler<D, double> cy{h, st, o, s.prof, pb, nullptr, t};
+        Cycler<D, N, double> cy{h, st, o, s.prof, pb, nullptr, t};
         cy.cg = (double *)(ws + A.L.cg);
         auto precond = [&](const double *in, double *out) {
-            launch_scale_leaves<D, BOX_N>(t->d_info, PRHO, in, -1, h.n_boxes, st);
+            launch_scale_leaves<D, N>(t->d_info, PRHO, in, -1, h.n_boxes, st);
             launch_fill<double>(PU, n, 0.0, st);
             cy.vcycle(h.lmax);
-            launch_scale_leaves<D, BOX_N>(t->d_info, out, PU, +1, h.n_boxes, st);
+            launch_scale_leaves<D, N>(t->d_info, out, PU, +1, h.n_boxes, st);
         };
         launch_copy<double>(B, R, n, st);
         double mx, sum;
@@ -1260,8 +1286,8 @@ int adjoint(afmg_tree *t, hipStream_t st, const double *ubar, double *rho_bar, d
         }
     }
     if (status < 0 && status != AFMG_ERR_NONFINITE && status != AFMG_ERR_DIVERGED) return status;
-    launch_store_leaves<D, BOX_N>(t->d_info, X, rho_bar, h.n_boxes, st);
-    if (bc_bar && h.n_bfaces_leaf > 0) launch_bc_grad<D, BOX_N>(t->d_info, X, bc_bar, h.n_boxes, st);
+    launch_store_leaves<D, N>(t->d_info, X, rho_bar, h.n_boxes, st);
+    if (bc_bar && h.n_bfaces_leaf > 0) launch_bc_grad<D, N>(t->d_info, X, bc_bar, h.n_boxes, st);
     (void)hipEventRecord(ev1, st);
     (void)hipEventSynchronize(ev1);
     float ms = 0.f;
@@ -1278,12 +1304,12 @@ int adjoint(afmg_tree *t, hipStream_t st, const double *ubar, double *rho_bar, d
 // ---------------------------------------------------------------------------
 // one step of the cycle on caller arrays (kernel-by-kernel checks)
 // ---------------------------------------------------------------------------
-template <int D>
+template <int D, int N>
 int step(afmg_tree *t, hipStream_t st, int op, int level, int colour, int homog, double *u, double *rho,
          double *uold, const double *bc, char *ws, const afmg_opts &o) {
     const HostTree &h = t->h;
     const WsLayout L = ws_layout(t, AFMG_FP64);
-    const int64_t F = cells_per_face(D);
+    const int64_t F = cells_per_face(D, N);
     double *bc_w = (double *)(ws + L.bc);
     if (h.n_bfaces_leaf > 0) {
         if (bc) {
@@ -1295,8 +1321,8 @@ int step(afmg_tree *t, hipStream_t st, int op, int level, int colour, int homog,
         }
     }
     for (int l = h.lmax; l >= 2; l--)
-        launch_bc_derive<D, BOX_N>(t->d_info, h.lvl_off[(size_t)l], h.level_count(l), bc_w, st);
-    for (double *f : {u, rho, uold}) launch_permute<D, BOX_N, double>(t->d_info, f, 0, h.n_boxes, 1, 0, st);
+        launch_bc_derive<D, N>(t->d_info, h.lvl_off[(size_t)l], h.level_count(l), bc_w, st);
+    for (double *f : {u, rho, uold}) launch_permute<D, N, double>(t->d_info, f, 0, h.n_boxes, 1, 0, st);
     LevelArgs<double> a{t->d_info, u, rho, uold, bc_w, h.lvl_off[(size_t)level], (int)h.level_count(level),
                         homog, 0.0, 0.0, nullptr, 0};
     a.xmask = cube_xmask(h, level);
@@ -1304,31 +1330,31 @@ int step(afmg_tree *t, hipStream_t st, int op, int level, int colour, int homog,
     a.bx = t->d_bx;
     a.opk = t->opk;
     a.dnbr = t->d_dnbr;
-    const double hh = level_h(level);
+    const double hh = level_h(level, N);
     a.h2 = hh * hh;
     a.ih2 = 1.0 / (hh * hh);
     a.h = hh;
     switch (op) {
-    case AFMG_STEP_HALF_SWEEP: launch_level<D, BOX_N, double>(Op::GSRB, a, colour, 256, st); break;
-    case AFMG_STEP_RESID_RESTRICT: launch_level<D, BOX_N, double>(Op::RESID_RESTRICT, a, 0, 256, st); break;
-    case AFMG_STEP_COARSE_RHS: launch_level<D, BOX_N, double>(Op::COARSE_RHS, a, 0, 256, st); break;
-    case AFMG_STEP_PROLONG: launch_level<D, BOX_N, double>(Op::PROLONG, a, 0, 256, st); break;
+    case AFMG_STEP_HALF_SWEEP: launch_level<D, N, double>(Op::GSRB, a, colour, 256, st); break;
+    case AFMG_STEP_RESID_RESTRICT: launch_level<D, N, double>(Op::RESID_RESTRICT, a, 0, 256, st); break;
+    case AFMG_STEP_COARSE_RHS: launch_level<D, N, double>(Op::COARSE_RHS, a, 0, 256, st); break;
+    case AFMG_STEP_PROLONG: launch_level<D, N, double>(Op::PROLONG, a, 0, 256, st); break;
     default:
-        if (h.general) {
+        if (coarse_general(h)) {
             CoarseGenArgs<double> c{t->d_info, u, rho, uold, homog ? nullptr : bc_w, (double *)(ws + L.cg),
                                     h.n_roots, COARSE_V_FROM_2, homog, o.n_down, o.n_up, o.n_base};
             c.eps = t->d_eps;
             c.bx = t->d_bx;
             c.opk = t->opk;
             c.dnbr = t->d_dnbr;
-            launch_coarse_gen<D, BOX_N, double>(c, st);
+            launch_coarse_gen<D, N, double>(c, st);
         } else {
             CoarseArgs<double> c{t->d_info, u, rho, uold, homog ? nullptr : bc_w, COARSE_V_FROM_2, homog,
                                  o.n_down, o.n_up, o.n_base, nullptr};
-            launch_coarse<D, BOX_N, double>(c, 1, st);
+            launch_coarse<D, N, double>(c, 1, st);
         }
     }
-    for (double *f : {u, rho, uold}) launch_permute<D, BOX_N, double>(t->d_info, f, 0, h.n_boxes, 0, 0, st);
+    for (double *f : {u, rho, uold}) launch_permute<D, N, double>(t->d_info, f, 0, h.n_boxes, 0, 0, st);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "step");
@@ -1363,7 +1389,7 @@ float time_launches(hipStream_t st, hipEvent_t a, hipEvent_t b, Fn fn) {
     return ms / TUNE_REPS;
 }
 
-template <int D, typename T>
+template <int D, int N, typename T>
 void tune_precision(afmg_tree *t, hipStream_t st, LevelArgs<T> base, double *partial, hipEvent_t e0, hipEvent_t e1) {
     const HostTree &h = t->h;
     const int pi = sizeof(T) == 4 ? 1 : 0;
@@ -1377,7 +1403,7 @@ void tune_precision(afmg_tree *t, hipStream_t st, LevelArgs<T> base, double *par
             a.b0 = h.lvl_off[(size_t)l];
             a.nb = (int)h.level_count(l);
             a.xmask = cube_xmask(h, l);
-            const double hh = level_h(l);
+            const double hh = level_h(l, N);
             a.h2 = (T)(hh * hh);
             a.ih2 = (T)(1.0 / (hh * hh));
             a.h = (T)hh;
@@ -1393,15 +1419,16 @@ void tune_precision(afmg_tree *t, hipStream_t st, LevelArgs<T> base, double *par
                 b.no_remap = sh.no_remap;
                 if (kind == SK_FINAL) {
                     const double hD = D == 3 ? hh * hh * hh : hh * hh;
-                    launch_final<D, BOX_N, T>(b, partial, t->forest ? -1 : 0, hD, nullptr, sh.wg, st);
+                    launch_final<D, N, T>(b, partial, t->forest ? -1 : 0, hD, nullptr, sh.wg, st);
                 } else {
-                    launch_level<D, BOX_N, T>(op, b, colour, sh.wg, st);
+                    launch_level<D, N, T>(op, b, colour, sh.wg, st);
                 }
             };
             Shape best{};
             float t_def = 0.f, t_best = 0.f;
             for (int round = 0; round < 2; round++) {
                 for (int wi = 0; wi < 3; wi++) {
+                    if (SHAPE_WGS[wi] < cells_per_face(D, N)) continue;  // a workgroup holds whole boxes
                     for (int nr = 0; nr < 2; nr++) {
                         const Shape sh{SHAPE_WGS[wi], nr};
                         const float ms = time_launches(st, e0, e1, [&](int c) { run(sh, c); });
@@ -1426,11 +1453,11 @@ void tune_precision(afmg_tree *t, hipStream_t st, LevelArgs<T> base, double *par
     }
 }
 
-template <int D>
+template <int D, int N>
 int autotune(afmg_tree *t, hipStream_t st, char *ws) {
     const HostTree &h = t->h;
     const TuneLayout L = tune_layout(t);
-    const int64_t C = cells_per_box(D), F = cells_per_face(D);
+    const int64_t C = cells_per_box(D, N), F = cells_per_face(D, N);
     const int64_t nb = h.n_boxes, nlt = std::max<int64_t>(1, h.n_below_lmax());
     double *u = (double *)(ws + L.u), *rho = (double *)(ws + L.rho), *uold = (double *)(ws + L.uold);
     double *bc = (double *)(ws + L.bc), *partial = (double *)(ws + L.partial);
@@ -1454,8 +1481,8 @@ int autotune(afmg_tree *t, hipStream_t st, char *ws) {
         b64.active = t->d_mask;
         b32.active = t->d_mask;
     }
-    tune_precision<D, double>(t, st, b64, partial, e0, e1);
-    tune_precision<D, float>(t, st, b32, partial, e0, e1);
+    tune_precision<D, N, double>(t, st, b64, partial, e0, e1);
+    tune_precision<D, N, float>(t, st, b32, partial, e0, e1);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     hipError_t err = hipStreamSynchronize(st);
@@ -1474,7 +1501,7 @@ int tree_autotune(afmg_tree *t, void *stream, void *workspace, size_t workspace_
     int rc = bind_device(t);
     if (rc != AFMG_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
-    return t->h.dim == 3 ? autotune<3>(t, st, (char *)workspace) : autotune<2>(t, st, (char *)workspace);
+    AFMG_BOX_RETURN(t->h, autotune, (t, st, (char *)workspace));
 }
 
 int get_shape(const afmg_tree *t, int precision, int kind, int level, int *wg, int *no_remap) {
@@ -1494,6 +1521,8 @@ int set_shape(afmg_tree *t, int precision, int kind, int level, int wg, int no_r
     if (precision < -1 || precision > 1 || kind < -1 || kind >= SK_KINDS || level < -1 || level == 0 ||
         level > t->h.lmax || (wg != 64 && wg != 128 && wg != 256) || (no_remap != 0 && no_remap != 1))
         return fail(AFMG_ERR_ARG, "shape out of range");
+    if (wg < cells_per_face(t->h.dim, t->h.N))
+        return fail(AFMG_ERR_ARG, "a workgroup must hold whole boxes (one thread per row of cells)");
     for (int p = 0; p < 2; p++)
         for (int k = 0; k < SK_KINDS; k++)
             for (int l = 1; l <= t->h.lmax; l++)
@@ -1525,15 +1554,15 @@ int scratch_address(int dev, void **out) {
 // The operator's coefficients: the caller's eps (leaf boxes) in the
 // colour-split layout, (volume) means into the parents, and a check that
 // every leaf value is positive and finite.
-template <int D>
+template <int D, int N>
 int load_eps(afmg_tree *t, hipStream_t st, const double *eps, int opk, int *flag) {
     const HostTree &h = t->h;
-    launch_load_rho<D, BOX_N, double>(t->d_info, nullptr, eps, t->d_eps, h.n_boxes, 1, st);
+    launch_load_rho<D, N, double>(t->d_info, nullptr, eps, t->d_eps, h.n_boxes, 1, st);
     for (int l = h.lmax; l >= 2; l--)
-        launch_restrict_field_op<D, BOX_N>(t->d_info, t->d_eps, h.lvl_off[(size_t)l], h.level_count(l), opk, t->d_bx,
-                                           level_h(l), st);
+        launch_restrict_field_op<D, N>(t->d_info, t->d_eps, h.lvl_off[(size_t)l], h.level_count(l), opk, t->d_bx,
+                                           level_h(l, N), st);
     launch_fill<int>(flag, 1, 0, st);
-    launch_check_positive<D, BOX_N>(t->d_info, t->d_eps, h.n_boxes, flag, st);
+    launch_check_positive<D, N>(t->d_info, t->d_eps, h.n_boxes, flag, st);
     int bad = 0;
     hipError_t e = hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -1549,7 +1578,7 @@ struct XferLayout {
     size_t u, bc, lists, total;
 };
 XferLayout xfer_layout(const afmg_tree *from, const afmg_tree *to) {
-    const size_t C = (size_t)cells_per_box(from->h.dim), F = (size_t)cells_per_face(from->h.dim);
+    const size_t C = (size_t)cells_per_box(from->h.dim, from->h.N), F = (size_t)cells_per_face(from->h.dim, from->h.N);
     XferLayout L{};
     size_t off = 0;
     L.u = off; off = align256(off + (size_t)from->h.n_boxes * C * sizeof(double));
@@ -1559,12 +1588,12 @@ XferLayout xfer_layout(const afmg_tree *from, const afmg_tree *to) {
     return L;
 }
 
-template <int D>
+template <int D, int N>
 int transfer(afmg_tree *from, afmg_tree *to, hipStream_t st, const double *u_from, const double *bc, double *u_to,
              char *ws) {
     const HostTree &hf = from->h, &ht = to->h;
     const XferLayout L = xfer_layout(from, to);
-    const int64_t C = cells_per_box(D), F = cells_per_face(D);
+    const int64_t C = cells_per_box(D, N), F = cells_per_face(D, N);
     // the box lists: a leaf of `to` that is a box of `from` takes its values
     // (the mean of its children if it was refined there); a new leaf is
     // prolonged from its parent, a leaf of `from`.  Both trees hold each level
@@ -1605,20 +1634,20 @@ int transfer(afmg_tree *from, afmg_tree *to, hipStream_t st, const double *u_fro
     const int64_t nc = (int64_t)cdst.size(), np = (int64_t)pdst.size();
     // the from-field with its parents, and its boundary rows
     double *uf = (double *)(ws + L.u), *bc_w = (double *)(ws + L.bc);
-    launch_load_rho<D, BOX_N, double>(from->d_info, nullptr, u_from, uf, hf.n_boxes, 1, st);
+    launch_load_rho<D, N, double>(from->d_info, nullptr, u_from, uf, hf.n_boxes, 1, st);
     for (int l = hf.lmax; l >= 2; l--)
-        launch_restrict_field<D, BOX_N>(from->d_info, uf, hf.lvl_off[(size_t)l], hf.level_count(l), st);
+        launch_restrict_field<D, N>(from->d_info, uf, hf.lvl_off[(size_t)l], hf.level_count(l), st);
     if (hf.n_bfaces_leaf > 0 && bc) {
         e = hipMemcpyAsync(bc_w, bc, (size_t)(hf.n_bfaces_leaf * F) * sizeof(double), hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return hip_fail(e, "copy of boundary values");
         for (int l = hf.lmax; l >= 2; l--)
-            launch_bc_derive<D, BOX_N>(from->d_info, hf.lvl_off[(size_t)l], hf.level_count(l), bc_w, st);
+            launch_bc_derive<D, N>(from->d_info, hf.lvl_off[(size_t)l], hf.level_count(l), bc_w, st);
     }
-    launch_transfer<D, BOX_N>(to->d_info, from->d_info, lists, lists + nc, nc, lists + 2 * nc, lists + 2 * nc + np, np,
+    launch_transfer<D, N>(to->d_info, from->d_info, lists, lists + nc, nc, lists + 2 * nc, lists + 2 * nc + np, np,
                               uf, bc_w, bc ? 0 : 1, u_to, st);
     for (int l = ht.lmax; l >= 2; l--)
-        launch_restrict_field<D, BOX_N>(to->d_info, u_to, ht.lvl_off[(size_t)l], ht.level_count(l), st);
-    launch_permute<D, BOX_N, double>(to->d_info, u_to, 0, ht.n_boxes, 0, 0, st);
+        launch_restrict_field<D, N>(to->d_info, u_to, ht.lvl_off[(size_t)l], ht.level_count(l), st);
+    launch_permute<D, N, double>(to->d_info, u_to, 0, ht.n_boxes, 0, 0, st);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(st);  // the host lists above must outlive their copy
     if (e != hipSuccess) return hip_fail(e, "transfer");
@@ -1726,8 +1755,8 @@ int afmg_tree_info(const afmg_tree *t, afmg_tree_desc *out) {
     out->n_bfaces = h.n_bfaces_leaf;
     out->lmin = h.lmin;
     out->lmax = h.lmax;
-    out->cells_per_box = cells_per_box(h.dim);
-    out->n_unknowns = h.n_leaves * cells_per_box(h.dim);
+    out->cells_per_box = cells_per_box(h.dim, h.N);
+    out->n_unknowns = h.n_leaves * cells_per_box(h.dim, h.N);
     out->n_roots = h.n_roots;
     for (int d = 0; d < 3; d++) out->ext[d] = h.ext[d];
     for (int s = 0; s < 6; s++) out->bc_type[s] = h.bc_type[s];
@@ -1765,11 +1794,11 @@ int afmg_tree_box(const afmg_tree *t, int64_t b, afmg_box_desc *out) {
     out->leaf = bi.flags & FLAG_LEAF;
     for (int s = 0; s < 6; s++) out->nbr[s] = s < 2 * t->h.dim ? bi.nbr[s] : -1;
     for (int c = 0; c < 8; c++) out->children[c] = c < (1 << t->h.dim) ? t->h.child[(size_t)b * 8 + c] : -1;
-    const double h = level_h(bi.level);
+    const double h = level_h(bi.level, t->h.N);
     out->h = h;
-    out->x_lo[0] = (out->idx[0] - 1) * BOX_N * h;
-    out->x_lo[1] = (out->idx[1] - 1) * BOX_N * h;
-    out->x_lo[2] = t->h.dim == 3 ? (out->idx[2] - 1) * BOX_N * h : 0.0;
+    out->x_lo[0] = (out->idx[0] - 1) * t->h.N * h;
+    out->x_lo[1] = (out->idx[1] - 1) * t->h.N * h;
+    out->x_lo[2] = t->h.dim == 3 ? (out->idx[2] - 1) * t->h.N * h : 0.0;
     return AFMG_OK;
 }
 
@@ -1806,8 +1835,7 @@ int afmg_tree_adapt(afmg_tree *t, void *stream, const int8_t *flags, int n_buf, 
         int32_t *d_words = nullptr;
         hipError_t e = hipMalloc(&d_words, sizeof(int32_t) * words.size());
         if (e != hipSuccess) return fail(AFMG_ERR_OOM, "hipMalloc of the box words failed");
-        if (h.dim == 3) launch_box_flags<3, BOX_N>(t->d_info, flags, h.n_boxes, n_buf, d_words, st);
-        else launch_box_flags<2, BOX_N>(t->d_info, flags, h.n_boxes, n_buf, d_words, st);
+        AFMG_BOX_DISPATCH(h, launch_box_flags, (t->d_info, flags, h.n_boxes, n_buf, d_words, st));
         e = hipGetLastError();
         if (e == hipSuccess) e = hipMemcpyAsync(words.data(), d_words, sizeof(int32_t) * words.size(),
                                                 hipMemcpyDeviceToHost, st);
@@ -1854,8 +1882,7 @@ int afmg_tree_transfer(afmg_tree *from, afmg_tree *to, void *stream, const doubl
     if (rc != AFMG_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     try {
-        if (a.dim == 3) return transfer<3>(from, to, st, u_from, bc_from, u_to, (char *)workspace);
-        return transfer<2>(from, to, st, u_from, bc_from, u_to, (char *)workspace);
+        AFMG_BOX_RETURN(a, transfer, (from, to, st, u_from, bc_from, u_to, (char *)workspace));
     } catch (const std::bad_alloc &) {
         return fail(AFMG_ERR_OOM, "host allocation failed");
     }
@@ -1879,7 +1906,7 @@ int afmg_tree_set_operator(afmg_tree *t, void *stream, int op, const double *eps
     t->op_kind = 0;
     t->op_prolong = 0;
     if ((rc = apply_schemes(t)) != AFMG_OK) return rc;
-    const size_t C = (size_t)cells_per_box(h.dim);
+    const size_t C = (size_t)cells_per_box(h.dim, h.N);
     if (opk && !t->d_bx && (rc = upload(t->d_bx, h.ix, "the box x indices")) != AFMG_OK) return rc;
     if (prolong == AFMG_PROLONG_LINEAR && !t->d_dnbr) {
         std::vector<int32_t> dn;
@@ -1897,7 +1924,7 @@ int afmg_tree_set_operator(afmg_tree *t, void *stream, int op, const double *eps
         }
         hipStream_t st = (hipStream_t)stream;
         int *flag = (int *)(t->d_eps + (size_t)h.n_boxes * C);
-        rc = h.dim == 3 ? load_eps<3>(t, st, eps, opk, flag) : load_eps<2>(t, st, eps, opk, flag);
+        AFMG_BOX_DISPATCH(h, rc = load_eps, (t, st, eps, opk, flag));
         if (rc != AFMG_OK) return rc;
     }
     t->op_kind = op;
@@ -1969,8 +1996,7 @@ int afmg_apply(afmg_tree *t, void *stream, int op, const double *x, double *y, v
     int rc = bind_device(t);
     if (rc != AFMG_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
-    if (t->h.dim == 3) return apply_op<3>(t, st, op, x, y, (char *)workspace);
-    return apply_op<2>(t, st, op, x, y, (char *)workspace);
+    AFMG_BOX_RETURN(t->h, apply_op, (t, st, op, x, y, (char *)workspace));
 }
 
 int afmg_adjoint(afmg_tree *t, void *stream, const double *u_bar, double *rho_bar, double *bc_bar,
@@ -1988,8 +2014,7 @@ int afmg_adjoint(afmg_tree *t, void *stream, const double *u_bar, double *rho_ba
     rc = bind_device(t);
     if (rc != AFMG_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
-    if (t->h.dim == 3) return adjoint<3>(t, st, u_bar, rho_bar, bc_bar, (char *)workspace, *opts, *stats);
-    return adjoint<2>(t, st, u_bar, rho_bar, bc_bar, (char *)workspace, *opts, *stats);
+    AFMG_BOX_RETURN(t->h, adjoint, (t, st, u_bar, rho_bar, bc_bar, (char *)workspace, *opts, *stats));
 }
 
 int afmg_solve(afmg_tree *t, void *stream, const double *rho, const double *bc, double *u,
@@ -2007,8 +2032,7 @@ int afmg_solve(afmg_tree *t, void *stream, const double *rho, const double *bc, 
     rc = bind_device(t);
     if (rc != AFMG_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
-    if (t->h.dim == 3) return solve<3>(t, st, rho, bc, u, (char *)workspace, *opts, stats);
-    return solve<2>(t, st, rho, bc, u, (char *)workspace, *opts, stats);
+    AFMG_BOX_RETURN(t->h, solve, (t, st, rho, bc, u, (char *)workspace, *opts, stats));
 }
 
 int afmg_solve_noalloc(afmg_tree *t, void *stream, const double *rho, const double *bc, double *u,
@@ -2036,8 +2060,7 @@ int afmg_solve_noalloc(afmg_tree *t, void *stream, const double *rho, const doub
     if ((rc = scratch_address(dev, &ws)) != AFMG_OK) return rc;
     std::memset(stats, 0, sizeof(*stats));
     hipStream_t st = (hipStream_t)stream;
-    if (t->h.dim == 3) return solve<3>(t, st, rho, bc, u, (char *)ws, *opts, stats);
-    return solve<2>(t, st, rho, bc, u, (char *)ws, *opts, stats);
+    AFMG_BOX_RETURN(t->h, solve, (t, st, rho, bc, u, (char *)ws, *opts, stats));
 }
 
 int afmg_batch_create(afmg_tree *const *trees, int n_trees, afmg_batch **out) {
@@ -2067,7 +2090,7 @@ int afmg_batch_create(afmg_tree *const *trees, int n_trees, afmg_batch **out) {
             row_base[(size_t)i] = f.user_rows;
             f.user_boxes += h.n_boxes;
             f.user_rows += h.n_bfaces_leaf;
-            f.user_unknowns += h.n_leaves * cells_per_box(dim);
+            f.user_unknowns += h.n_leaves * cells_per_box(dim, h.N);
         }
         if (f.user_boxes >= ((int64_t)1 << 30) || f.user_rows >= ((int64_t)1 << 31)) {
             delete b;
@@ -2171,8 +2194,7 @@ int afmg_batch_solve(afmg_batch *b, void *stream, const double *rho, const doubl
     rc = bind_device(f);
     if (rc != AFMG_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
-    if (f->h.dim == 3) return solve<3>(f, st, rho, bc, u, (char *)workspace, *opts, stats);
-    return solve<2>(f, st, rho, bc, u, (char *)workspace, *opts, stats);
+    AFMG_BOX_RETURN(f->h, solve, (f, st, rho, bc, u, (char *)workspace, *opts, stats));
 }
 
 int afmg_autotune_workspace_bytes(const afmg_tree *t, size_t *bytes) {
@@ -2240,8 +2262,7 @@ int afmg_step(afmg_tree *t, void *stream, int op, int level, int colour, int hom
     int rc = bind_device(t);
     if (rc != AFMG_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
-    if (t->h.dim == 3) return step<3>(t, st, op, level, colour, homog != 0, u, rho, uold, bc, (char *)workspace, o);
-    return step<2>(t, st, op, level, colour, homog != 0, u, rho, uold, bc, (char *)workspace, o);
+    AFMG_BOX_RETURN(t->h, step, (t, st, op, level, colour, homog != 0, u, rho, uold, bc, (char *)workspace, o));
 }
 
 }  // extern "C"

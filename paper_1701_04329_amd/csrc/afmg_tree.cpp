@@ -80,7 +80,7 @@ bool domain_position(const HostTree &t, int l, int q[3]) {
 int build_tree(int dim, int N, int n_trees, const int64_t *tree_off, const int32_t *level, const int32_t *idx,
                HostTree &t, std::string &msg, const int32_t *bc_type) {
     if (dim != 2 && dim != 3) { msg = "dim must be 2 or 3"; return AFMG_ERR_ARG; }
-    if (N != 8) { msg = "box_n must be 8"; return AFMG_ERR_ARG; }
+    if (N != 8 && N != 16) { msg = "box_n must be 8 or 16"; return AFMG_ERR_ARG; }
     if (n_trees <= 0 || !tree_off || !level || !idx) { msg = "empty or null leaf list"; return AFMG_ERR_ARG; }
     if (tree_off[0] != 0) { msg = "leaf offsets must start at 0"; return AFMG_ERR_ARG; }
     for (int tr = 0; tr < n_trees; tr++)

@@ -122,6 +122,9 @@ def test_tree_validation_codes():
     assert _create(2, lev, idx) == A.AFMG_OK
     assert _create(4, lev, idx) == A.AFMG_ERR_ARG
     assert _create(2, lev, idx, box_n=6) == A.AFMG_ERR_ARG
+    assert _create(2, lev, idx, box_n=16) == A.AFMG_OK
+    assert _create(3, *W.uniform_leaves(3, 2), box_n=16) == A.AFMG_OK
+    assert _create(3, *W.uniform_leaves(3, 2), box_n=32) == A.AFMG_ERR_ARG
     bad = idx.copy()
     bad[0, 0] = 3
     assert _create(2, lev, bad) == A.AFMG_ERR_ARG
@@ -294,8 +297,11 @@ def test_refine_balance_rules(dim):
         assert e.value.code == A.AFMG_ERR_ARG
 
 
-def test_level_lists_and_box_geometry():
-    t = A.Tree(3, *W.ball_leaves(3, 8, 4, (0.3, 0.62, 0.41), 0.0, 1))
+@pytest.mark.parametrize("N", [8, 16])
+def test_level_lists_and_box_geometry(N):
+    t = A.Tree(3, *W.ball_leaves(3, N, 4, (0.3, 0.62, 0.41), 0.0, 1), box_n=N)
+    assert t.box_n == N and t.cells_per_box == N ** 3
+    assert t.n_unknowns == t.n_leaves * N ** 3
     total = 0
     for l in range(1, t.lmax + 1):
         al, pa, le = t.level_list(l, "all"), t.level_list(l, "parent"), t.level_list(l, "leaf")
@@ -310,9 +316,9 @@ def test_level_lists_and_box_geometry():
         for b in le:
             d = t.box(int(b))
             assert d["leaf"] and all(c == -1 for c in d["children"])
-            h = 1.0 / (8 * 2 ** (d["level"] - 1))
+            h = 1.0 / (N * 2 ** (d["level"] - 1))
             assert d["h"] == h
-            assert d["x_lo"] == tuple((x - 1) * 8 * h for x in d["idx"])
+            assert d["x_lo"] == tuple((x - 1) * N * h for x in d["idx"])
     assert total == t.n_boxes
     assert sum(len(t.level_list(l, "leaf")) for l in range(1, t.lmax + 1)) == t.n_leaves
     with pytest.raises(A.AfmgError):

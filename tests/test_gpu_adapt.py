@@ -43,7 +43,14 @@ def grids():
                [P_, P_, D_, N_], (True, False)),
         "p3": (3, W.domain_leaves(3, 8, [(1, 1, 1), (2, 1, 1)], 4, (1.98, 0.4, 0.6), periodic=(True, True, True)),
                P_, (True, True, True)),
+        # boxes of 16^D cells
+        "a2x16": (2, W.ball_leaves(2, 16, 5, c, 0.0, 1), None, None),
+        "a3x16": (3, W.ball_leaves(3, 16, 3, c, 0.0, 1), None, None),
     }
+
+
+def box_n(name):
+    return 16 if name.endswith("x16") else 8
 
 
 _G = None
@@ -76,10 +83,10 @@ def keys_of(level, idx, dim):
 def gpu_tree(name):
     from paper_1701_04329_amd import afmg as A
     dim, (lev, idx), types, _ = grid(name)
-    return A.Tree(dim, lev, idx, bc_type=types)
+    return A.Tree(dim, lev, idx, box_n=box_n(name), bc_type=types)
 
 
-NAMES = ["a2", "a3", "L2", "p2", "p3"]
+NAMES = ["a2", "a3", "L2", "p2", "p3", "a2x16", "a3x16"]
 
 
 @pytest.mark.parametrize("name", NAMES)
@@ -89,11 +96,12 @@ def test_adapt_matches_oracle(name):
     t = gpu_tree(name)
     dev = torch.device("cuda", 0)
     rng = np.random.default_rng(sorted(NAMES).index(name) + 11)
+    n = box_n(name)
     for trial, n_buf in enumerate((2, 1, 0, 2)):
-        f = random_flags(len(lev), 8 ** dim, rng)
+        f = random_flags(len(lev), n ** dim, rng)
         announce(f"adapt {name} trial {trial} n_buf {n_buf}")
         nt, counts = A.adapt(t, t.leaf_to_boxes(torch.tensor(f, device=dev)).contiguous(), n_buf=n_buf)
-        ol, oi = AD.adapt(dim, 8, lev, idx, f, n_buf=n_buf, periodic=periodic)
+        ol, oi = AD.adapt(dim, n, lev, idx, f, n_buf=n_buf, periodic=periodic)
         gl, gi = nt.leaves()
         assert sorted(keys_of(gl, gi, dim)) == sorted(keys_of(ol, oi, dim)), (name, trial)
         assert nt.n_leaves == len(ol)
@@ -107,10 +115,11 @@ def test_transfer_matches_oracle(name):
     t = gpu_tree(name)
     dev = torch.device("cuda", 0)
     rng = np.random.default_rng(31 + sorted(NAMES).index(name))
-    f = random_flags(len(lev), 8 ** dim, rng)
+    n = box_n(name)
+    f = random_flags(len(lev), n ** dim, rng)
     nt, _ = A.adapt(t, t.leaf_to_boxes(torch.tensor(f, device=dev)).contiguous())
-    u = rng.standard_normal((len(lev), 8 ** dim))
-    bc = rng.standard_normal((len(lev), 2 * dim, 8 ** (dim - 1)))
+    u = rng.standard_normal((len(lev), n ** dim))
+    bc = rng.standard_normal((len(lev), 2 * dim, n ** (dim - 1)))
     bc *= W.domain_side_mask(dim, lev, idx, types)[:, :, None]
     for with_bc in (True, False):
         announce(f"transfer {name} bc {with_bc}")
@@ -119,8 +128,8 @@ def test_transfer_matches_oracle(name):
         torch.cuda.synchronize()
         gl, gi = nt.leaves()
         got = dict(zip(keys_of(gl, gi, dim), nt.boxes_to_leaf(ug).cpu().numpy()))
-        ol, oi = AD.adapt(dim, 8, lev, idx, f, periodic=periodic)
-        ot = O.Tree(dim, 8, lev, idx, bc_type=types)
+        ol, oi = AD.adapt(dim, n, lev, idx, f, periodic=periodic)
+        ot = O.Tree(dim, n, lev, idx, bc_type=types)
         uo = AD.transfer(ot, ol, oi, u, bc if with_bc else None)
         scale = np.abs(uo).max()
         old_keys = dict(zip(keys_of(lev, idx, dim), u))

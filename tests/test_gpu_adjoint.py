@@ -24,33 +24,36 @@ def dev():
     return DEV
 
 
-def grids():
+def grids(name):
+    """name -> (dim, box size, (level, idx))"""
     return {
-        "a2": W.ball_leaves(2, 8, 6, (0.71, 0.33), 0.0, 2),
-        "a3": W.ball_leaves(3, 8, 4, (0.3, 0.62, 0.41), 0.0, 1),
-        "u3": W.uniform_leaves(3, 3),
-        "u2": W.uniform_leaves(2, 4),
-        "b3": W.ball_leaves(3, 8, 5, (0.3, 0.62, 0.41), 0.0, 2),
-    }
+        "a2": lambda: (2, 8, W.ball_leaves(2, 8, 6, (0.71, 0.33), 0.0, 2)),
+        "a3": lambda: (3, 8, W.ball_leaves(3, 8, 4, (0.3, 0.62, 0.41), 0.0, 1)),
+        "u3": lambda: (3, 8, W.uniform_leaves(3, 3)),
+        "u2": lambda: (2, 8, W.uniform_leaves(2, 4)),
+        "b3": lambda: (3, 8, W.ball_leaves(3, 8, 5, (0.3, 0.62, 0.41), 0.0, 2)),
+        # boxes of 16^D cells
+        "a2x16": lambda: (2, 16, W.ball_leaves(2, 16, 5, (0.71, 0.33), 0.0, 2)),
+        "a3x16": lambda: (3, 16, W.ball_leaves(3, 16, 3, (0.3, 0.62, 0.41), 0.0, 1)),
+    }[name]()
 
 
 def setup(name, seed):
     from paper_1701_04329_amd import afmg as A
-    lev, idx = grids()[name]
-    dim = 2 if name.endswith("2") else 3
-    t = A.Tree(dim, lev, idx)
-    o = O.Tree(dim, 8, lev, idx)
+    dim, n, (lev, idx) = grids(name)
+    t = A.Tree(dim, lev, idx, box_n=n)
+    o = O.Tree(dim, n, lev, idx)
     rng = np.random.default_rng(seed)
     return dim, lev, idx, t, o, rng
 
 
-@pytest.mark.parametrize("name", ["a2", "a3", "u3", "b3"])
+@pytest.mark.parametrize("name", ["a2", "a3", "u3", "b3", "a2x16", "a3x16"])
 def test_apply_L_and_LT_match_oracle_matrix(name):
     dim, lev, idx, t, o, rng = setup(name, 11)
     print(f"[case] apply {name} leaves={len(lev)}", flush=True)
     A = O.assemble_L(o)
     from paper_1701_04329_amd import afmg as AF
-    x = rng.standard_normal((len(lev), 8 ** dim))
+    x = rng.standard_normal((len(lev), t.box_n ** dim))
     xd = t.leaf_to_boxes(torch.tensor(x, device=dev()))
     for op, M in (("L", A), ("LT", A.T.tocsr())):
         y = t.boxes_to_leaf(AF.apply(t, xd, op)).cpu().numpy().ravel()
@@ -72,12 +75,12 @@ def test_transpose_dot_product_on_a_larger_grid():
     assert a == pytest.approx(b, rel=1e-12)
 
 
-@pytest.mark.parametrize("name", ["a2", "a3", "u3", "u2"])
+@pytest.mark.parametrize("name", ["a2", "a3", "u3", "u2", "a2x16", "a3x16"])
 def test_adjoint_matches_oracle(name):
     from paper_1701_04329_amd import afmg as AF
     dim, lev, idx, t, o, rng = setup(name, 21)
     print(f"[case] adjoint {name} leaves={len(lev)}", flush=True)
-    ubar = rng.standard_normal((len(lev), 8 ** dim))
+    ubar = rng.standard_normal((len(lev), t.box_n ** dim))
     lam_o, gbc_o = O.adjoint(o, ubar)
     rb, bb, st = AF.adjoint(t, t.leaf_to_boxes(torch.tensor(ubar, device=dev())), tol=1e-12)
     lam = t.boxes_to_leaf(rb).cpu().numpy()

@@ -36,7 +36,7 @@ def announce(msg):
 
 def single(w, **kw):
     from paper_1701_04329_amd import afmg as A
-    t = A.Tree(w.dim, w.level, w.idx)
+    t = A.Tree(w.dim, w.level, w.idx, box_n=w.N)
     rho = t.leaf_to_boxes(torch.tensor(w.rho, device=dev()))
     bc = t.bc_rows(torch.tensor(w.bc, device=dev()))
     u0 = kw.pop("u0", None)
@@ -48,7 +48,7 @@ def single(w, **kw):
 
 def batched(ws, u0s=None, **kw):
     from paper_1701_04329_amd import afmg as A
-    trees = [A.Tree(w.dim, w.level, w.idx) for w in ws]
+    trees = [A.Tree(w.dim, w.level, w.idx, box_n=w.N) for w in ws]
     b = A.Batch(trees)
     rho = b.concat([t.leaf_to_boxes(torch.tensor(w.rho, device=dev())) for t, w in zip(trees, ws)])
     bc = b.concat_bc([t.bc_rows(torch.tensor(w.bc, device=dev())) for t, w in zip(trees, ws)])
@@ -132,6 +132,47 @@ def test_batch_matches_oracle(dim):
         assert_norms_close(s["hist_max"], so["hist_max"], floor, what=w.name)
         assert_norms_close(s["hist_l2"], so["hist_l2"], floor, what=w.name)
         assert s["cycles"] == so["cycles"] == 3
+
+
+def bag16(dim):
+    """Trees of 16^D-cell boxes (2D: forest kernels with 16 boxes per
+    workgroup; 3D: one box per workgroup, level 2 box by box and levels
+    <= 1 in the coarse kernel): the root alone, refinement boundaries at
+    several levels, Gaussian sources, zero data, a uniform two-level tree."""
+    c = (0.3, 0.62, 0.41)
+    ws = [
+        W.random_fields(dim, 16, *W.uniform_leaves(dim, 1), 21),
+        W.random_fields(dim, 16, *W.ball_leaves(dim, 16, 5 if dim == 2 else 3, c, 0.0, 1), 22),
+        W.adaptive_small(dim, 16, 6 if dim == 2 else 4, 1e-3, 6, n_src=2,
+                         sigma_range=(0.03, 0.06) if dim == 2 else (0.04, 0.08)),
+        W.random_fields(dim, 16, *W.uniform_leaves(dim, 2), 23),
+    ]
+    ws[3].rho[:] = 0.0
+    ws[3].bc[:] = 0.0
+    ws.append(W.random_fields(dim, 16, *W.uniform_leaves(dim, 2), 24))
+    return ws
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_batch_of_16_cell_boxes(dim, precision):
+    """Boxes of 16^D cells: each tree bitwise as solved alone, and FP64
+    against the oracle at a fixed cycle count."""
+    ws = bag16(dim)
+    announce(f"batch of 16^D-cell boxes dim={dim} {precision} trees={len(ws)}")
+    ub, sb = batched(ws, cycle="FMG", precision=precision, tol=1e-10)
+    for w, u, s in zip(ws, ub, sb):
+        us, ss = single(w, cycle="FMG", precision=precision, tol=1e-10)
+        assert_same(u, s, us, ss, w.name)
+    assert sb[3]["cycles"] == 0 and max(s["cycles"] for s in sb) >= 5
+    if precision == "fp64":
+        ub, sb = batched(ws, cycle="FMG", fixed_cycles=3)
+        for w, u, s in zip(ws, ub, sb):
+            uo, so = O.Tree(w.dim, w.N, w.level, w.idx).solve(w.rho, w.bc, cycle="FMG", fixed_cycles=3)
+            if np.linalg.norm(uo) == 0.0:
+                assert not u.any(), w.name
+                continue
+            assert_leaf_parity(u, uo, REL, w.name)
 
 
 def test_batch_use_guess_and_single_tree_batch():

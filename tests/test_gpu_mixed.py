@@ -26,7 +26,7 @@ BOUND = 1e-8
 
 def run_mixed(w, **kw):
     from paper_1701_04329_amd import afmg as A
-    t = A.Tree(w.dim, w.level, w.idx)
+    t = A.Tree(w.dim, w.level, w.idx, box_n=w.N)
     dev = torch.device("cuda", 0)
     rho = t.leaf_to_boxes(torch.tensor(w.rho, device=dev))
     bc = t.bc_rows(torch.tensor(w.bc, device=dev)) if t.n_bfaces else None
@@ -42,6 +42,11 @@ CASES = {
     "a2": lambda: W.adaptive_small(2, 8, 7, 1e-3, 5, n_src=2, sigma_range=(0.03, 0.06)),
     "b3_rand": lambda: W.random_fields(3, 8, *W.ball_leaves(3, 8, 5, (0.3, 0.62, 0.41), 0.0, 2), 77),
     "single_3d": lambda: W.random_fields(3, 8, *W.uniform_leaves(3, 1), 93),
+    # boxes of 16^D cells: a complete finest level (the fused refinement
+    # update), an adaptive octree (general coarse kernel), a quadtree
+    "u3x16_64": lambda: W.config2(N=16, res=64),
+    "a3x16": lambda: W.adaptive_small(3, 16, 4, 1e-3, 6, n_src=2, sigma_range=(0.04, 0.08)),
+    "a2x16": lambda: W.adaptive_small(2, 16, 6, 1e-3, 5, n_src=2, sigma_range=(0.03, 0.06)),
 }
 
 

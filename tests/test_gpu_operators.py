@@ -51,7 +51,14 @@ def cases():
                 "random"),
         "ep3": (3, W.domain_leaves(3, 8, [(1, 1, 1), (2, 1, 1)], 4, (1.98, 0.4, 0.6), periodic=(True, False, False)),
                 [P_, P_, N_, D_, D_, N_], "eps", "random"),
+        # boxes of 16^D cells
+        "e3x16": (3, W.ball_leaves(3, 16, 3, c, 0.0, 1), None, "eps", "random"),
+        "ce2x16": (2, W.ball_leaves(2, 16, 4, (0.25, 0.25), 0.02, 1), None, "cyl_eps", "jump"),
     }
+
+
+def box_n(name):
+    return 16 if name.endswith("x16") else 8
 
 
 _CASES = None
@@ -64,25 +71,25 @@ def get_case(name):
     return _CASES[name]
 
 
-def make_eps(recipe, dim, lev, idx, seed):
+def make_eps(recipe, dim, lev, idx, seed, n=8):
     if recipe is None:
         return None
     if recipe == "random":
-        return W.random_eps(len(lev), 8, dim, seed)
-    return W.eps_sampled(W.case2_eps, dim, 8, lev, idx)
+        return W.random_eps(len(lev), n, dim, seed)
+    return W.eps_sampled(W.case2_eps, dim, n, lev, idx)
 
 
-def gpu_tree(dim, lev, idx, types, kind, eps_leaf, prolong):
+def gpu_tree(dim, lev, idx, types, kind, eps_leaf, prolong, n=8):
     from paper_1701_04329_amd import afmg as A
-    t = A.Tree(dim, lev, idx, bc_type=types)
+    t = A.Tree(dim, lev, idx, box_n=n, bc_type=types)
     dev = torch.device("cuda", 0)
     e = None if eps_leaf is None else t.leaf_to_boxes(torch.tensor(eps_leaf, device=dev)).contiguous()
     t.set_operator(kind, e, prolong)
     return t
 
 
-def oracle_tree(dim, lev, idx, types, kind, eps_leaf, prolong):
-    o = O.Tree(dim, 8, lev, idx, bc_type=types)
+def oracle_tree(dim, lev, idx, types, kind, eps_leaf, prolong, n=8):
+    o = O.Tree(dim, n, lev, idx, bc_type=types)
     o.set_operator(kind, eps_leaf, prolong)
     return o
 
@@ -95,13 +102,14 @@ class Pair:
         from paper_1701_04329_amd import afmg as A
         self.A = A
         dim, (lev, idx), types, kind, recipe = get_case(name)
-        self.dim = dim
-        eps = make_eps(recipe, dim, lev, idx, 90 + seed)
+        self.dim, self.n = dim, box_n(name)
+        n = self.n
+        eps = make_eps(recipe, dim, lev, idx, 90 + seed, n)
         if eps is None and prolong == "eps":
             pytest.skip("the eps prolongation needs eps")
-        self.t = gpu_tree(dim, lev, idx, types, kind, eps, prolong)
-        self.o = oracle_tree(dim, lev, idx, types, kind, eps, prolong)
-        C = 8 ** dim
+        self.t = gpu_tree(dim, lev, idx, types, kind, eps, prolong, n)
+        self.o = oracle_tree(dim, lev, idx, types, kind, eps, prolong, n)
+        C = n ** dim
         key_o = {}
         for b in range(self.o.nbox):
             i = self.o.box_info(b)
@@ -114,7 +122,7 @@ class Pair:
         self.rho = rng.standard_normal((self.t.n_boxes, C))
         self.uold = rng.standard_normal((self.t.n_boxes, C))
         phys = W.domain_side_mask(dim, lev, idx, types)[:, :, None]
-        self.bc_leaf = rng.standard_normal((len(lev), 2 * dim, 8 ** (dim - 1))) * phys
+        self.bc_leaf = rng.standard_normal((len(lev), 2 * dim, n ** (dim - 1))) * phys
         self.levels = np.array([self.t.box(b)["level"] for b in range(self.t.n_boxes)])
         self.leaf = np.array([self.t.box(b)["leaf"] for b in range(self.t.n_boxes)])
 
@@ -129,7 +137,7 @@ class Pair:
         return u.cpu().numpy(), rho.cpu().numpy(), uold.cpu().numpy()
 
     def _set(self, field, arr):
-        n = 8
+        n = self.n
         inner = tuple(slice(1, -1) for _ in range(self.dim))
         for b in range(self.t.n_boxes):
             ob = int(self.o_of[b])
@@ -162,7 +170,7 @@ def close(what, got, ref, rel=STEP_REL):
     assert err <= rel, (what, err)
 
 
-STEP_NAMES = ["e2", "e3", "c2", "ce2", "eL2", "ep3"]
+STEP_NAMES = ["e2", "e3", "c2", "ce2", "eL2", "ep3", "e3x16", "ce2x16"]
 
 
 @pytest.mark.parametrize("name", STEP_NAMES)
@@ -206,7 +214,7 @@ def test_operator_steps(name):
 
 
 @pytest.mark.parametrize("prolong", ["default", "eps"])
-@pytest.mark.parametrize("name", ["e2", "e3", "ce2", "eL2"])
+@pytest.mark.parametrize("name", ["e2", "e3", "ce2", "eL2", "e3x16"])
 def test_operator_prolong_steps(name, prolong):
     P = Pair(name, 4, prolong)
     for level in range(2, P.t.lmax + 1):
@@ -226,20 +234,21 @@ def test_operator_prolong_steps(name, prolong):
 # ---------------------------------------------------------------------------
 # solves
 # ---------------------------------------------------------------------------
-def inputs(dim, lev, idx, types, seed, singular=False):
+def inputs(dim, lev, idx, types, seed, singular=False, n=8):
     rng = np.random.default_rng(seed)
-    rho = rng.standard_normal((len(lev), 8 ** dim))
-    bc = rng.standard_normal((len(lev), 2 * dim, 8 ** (dim - 1)))
+    rho = rng.standard_normal((len(lev), n ** dim))
+    bc = rng.standard_normal((len(lev), 2 * dim, n ** (dim - 1)))
     bc *= W.domain_side_mask(dim, lev, idx, types)[:, :, None]
     return rho, bc
 
 
 def solve_pair(name, prolong, seed, **kw):
     dim, (lev, idx), types, kind, recipe = get_case(name)
-    eps = make_eps(recipe, dim, lev, idx, seed + 1)
-    rho, bc = inputs(dim, lev, idx, types, seed)
-    t = gpu_tree(dim, lev, idx, types, kind, eps, prolong)
-    o = oracle_tree(dim, lev, idx, types, kind, eps, prolong)
+    n = box_n(name)
+    eps = make_eps(recipe, dim, lev, idx, seed + 1, n)
+    rho, bc = inputs(dim, lev, idx, types, seed, n=n)
+    t = gpu_tree(dim, lev, idx, types, kind, eps, prolong, n)
+    o = oracle_tree(dim, lev, idx, types, kind, eps, prolong, n)
     from paper_1701_04329_amd import afmg as A
     dev = torch.device("cuda", 0)
     announce(f"op solve {name} {kind} {prolong} {kw}")
@@ -264,7 +273,7 @@ def test_operator_fixed_cycles_match_oracle(name, prolong):
         assert_norms_close(sg["hist_l2"], so["hist_l2"], 1e-12 * so["r0_l2"], what=(name, "history L2"))
 
 
-@pytest.mark.parametrize("name", ["e3", "ce2", "eL2"])
+@pytest.mark.parametrize("name", ["e3", "ce2", "eL2", "e3x16", "ce2x16"])
 def test_operator_solve_to_tolerance_matches_oracle(name):
     ug, sg, uo, so = solve_pair(name, "default", 51, cycle="FMG", tol=1e-10, n_base=16, max_cycles=80)
     assert sg["status"] == 0 and so["status"] == 0, (sg["status"], so["status"])

@@ -27,7 +27,7 @@ def announce(msg):
 
 def gpu_solve(w, **kw):
     from paper_1701_04329_amd import afmg as A
-    t = A.Tree(w.dim, w.level, w.idx)
+    t = A.Tree(w.dim, w.level, w.idx, box_n=w.N)
     dev = torch.device("cuda", 0)
     rho = t.leaf_to_boxes(torch.tensor(w.rho, device=dev))
     bc = t.bc_rows(torch.tensor(w.bc, device=dev)) if t.n_bfaces else None
@@ -91,6 +91,14 @@ def cases():
         for l in (1, 2):
             lev, idx = W.uniform_leaves(dim, l)
             out[f"single_{dim}d_l{l}"] = W.random_fields(dim, 8, lev, idx, 90 + 10 * dim + l)
+    # boxes of 16^D cells (paper §2.1, §4.2): 3D trees take the general
+    # coarse kernel for levels <= 1 and the box kernels from level 2 on
+    out["u3x16_64"] = W.config2(N=16, res=64)
+    out["a2x16"] = W.adaptive_small(2, 16, 6, 1e-3, 5, n_src=2, sigma_range=(0.03, 0.06))
+    out["a3x16"] = W.adaptive_small(3, 16, 4, 1e-3, 6, n_src=2, sigma_range=(0.04, 0.08))
+    for dim in (2, 3):
+        lev, idx = W.uniform_leaves(dim, 1)
+        out[f"single_{dim}d_l1x16"] = W.random_fields(dim, 16, lev, idx, 190 + dim)
     return out
 
 
@@ -105,21 +113,45 @@ def get(name):
 
 
 @pytest.mark.parametrize("name", ["c1", "u3_32", "a2", "a3", "b3_rand", "b2_rand",
-                                  "single_2d_l1", "single_2d_l2", "single_3d_l1", "single_3d_l2"])
+                                  "single_2d_l1", "single_2d_l2", "single_3d_l1", "single_3d_l2",
+                                  "u3x16_64", "a2x16", "a3x16", "single_2d_l1x16", "single_3d_l1x16"])
 @pytest.mark.parametrize("fixed", [1, 3])
 def test_fixed_cycles_match_oracle(name, fixed):
     check_pair(get(name), fixed_cycles=fixed)
 
 
-@pytest.mark.parametrize("name", ["c1", "u3_64", "a2", "a3", "b3_rand", "single_3d_l1"])
+@pytest.mark.parametrize("name", ["c1", "u3_64", "a2", "a3", "b3_rand", "single_3d_l1", "u3x16_64", "a2x16",
+                                  "a3x16"])
 def test_solve_to_tolerance_matches_oracle(name):
     check_pair(get(name), tol=1e-10)
 
 
-@pytest.mark.parametrize("name", ["c1", "u3_32", "a2", "a3", "single_2d_l1", "single_3d_l2"])
+@pytest.mark.parametrize("name", ["c1", "u3_32", "a2", "a3", "single_2d_l1", "single_3d_l2", "u3x16_64", "a2x16",
+                                  "a3x16", "single_3d_l1x16"])
 def test_fmg_then_v_matches_oracle(name):
     check_pair(get(name), cycle="FMG", fixed_cycles=2)
     check_pair(get(name), cycle="FMG", tol=1e-10)
+
+
+def test_box_sizes_give_the_same_uniform_solve():
+    """On a uniform grid boxes of 8^3 and of 16^3 cells carry the same grids
+    (64^3 down to 2^3), ghosts and red-black order: the two GPU solves agree
+    cell by cell to rounding, with the same cycle counts."""
+    w8, w16 = get("u3_64"), get("u3x16_64")
+    out = []
+    for w in (w8, w16):
+        announce(f"uniform 64^3 with boxes of {w.N}^3")
+        u, st = gpu_solve(w, cycle="FMG", tol=1e-10)
+        n = w.N
+        g = np.zeros((64, 64, 64))
+        ub = u.reshape(-1, n, n, n)
+        o = (w.idx[:, :3] - 1) * n
+        for q in range(len(w.level)):
+            g[o[q, 2]:o[q, 2] + n, o[q, 1]:o[q, 1] + n, o[q, 0]:o[q, 0] + n] = ub[q]
+        out.append((g, st))
+    (g8, s8), (g16, s16) = out
+    assert s8["cycles"] == s16["cycles"]
+    assert np.abs(g16 - g8).max() <= 1e-12 * np.abs(g8).max()
 
 
 def test_warm_start_matches_oracle():

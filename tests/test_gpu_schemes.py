@@ -43,7 +43,14 @@ def cases():
                 False, "linear", "bilinear"),
         "lp3": (3, W.domain_leaves(3, 8, [(1, 1, 1), (2, 1, 1)], 4, (1.98, 0.4, 0.6), periodic=(True, False, False)),
                 [P_, P_, N_, D_, D_, N_], "eps", True, "linear", "bilinear"),
+        # boxes of 16^D cells
+        "bl3x16": (3, W.ball_leaves(3, 16, 3, c, 0.0, 1), None, "laplacian", False, "linear", "bilinear"),
+        "bl2x16": (2, W.ball_leaves(2, 16, 4, c, 0.0, 1), None, "laplacian", False, "linear", "bilinear"),
     }
+
+
+def box_n(name):
+    return 16 if name.endswith("x16") else 8
 
 
 _C = None
@@ -56,21 +63,22 @@ def case(name):
     return _C[name]
 
 
-NAMES = ["b2", "b3", "l2", "l3", "lL2", "lp3"]
+NAMES = ["b2", "b3", "l2", "l3", "lL2", "lp3", "bl3x16", "bl2x16"]
 
 
 def build(name, seed):
     from paper_1701_04329_amd import afmg as A
     dim, (lev, idx), types, kind, has_eps, prolong, ghost = case(name)
+    n = box_n(name)
     # eps jumps on a coarse-grid face (between the two level-1 boxes), the
     # setting the ghost schemes are made for (paper §3.4)
-    eps = W.eps_sampled(lambda x: np.where(x[..., 0] < 1.0, 4.0, 1.0), dim, 8, lev, idx) if has_eps else None
-    t = A.Tree(dim, lev, idx, bc_type=types)
+    eps = W.eps_sampled(lambda x: np.where(x[..., 0] < 1.0, 4.0, 1.0), dim, n, lev, idx) if has_eps else None
+    t = A.Tree(dim, lev, idx, box_n=n, bc_type=types)
     dev = torch.device("cuda", 0)
     t.set_operator(kind, None if eps is None else t.leaf_to_boxes(torch.tensor(eps, device=dev)).contiguous(),
                    prolong)
     t.set_ghost_scheme(ghost)
-    o = O.Tree(dim, 8, lev, idx, bc_type=types)
+    o = O.Tree(dim, n, lev, idx, bc_type=types)
     o.set_operator(kind, eps, prolong)
     o.set_ghost_scheme(ghost)
     return t, o
@@ -81,7 +89,7 @@ class Pair:
         from paper_1701_04329_amd import afmg as A
         self.A = A
         dim, (lev, idx), types, *_ = case(name)
-        self.dim = dim
+        self.dim, self.n = dim, box_n(name)
         self.t, self.o = build(name, 70 + seed)
         key_o = {}
         for b in range(self.o.nbox):
@@ -90,12 +98,12 @@ class Pair:
                 key_o[(i["level"], i["ix"], i["iy"], i["iz"])] = b
         self.o_of = np.array([key_o[(self.t.box(b)["level"],) + self.t.box(b)["idx"]] for b in range(self.t.n_boxes)])
         rng = np.random.default_rng(seed)
-        C = 8 ** dim
+        C = self.n ** dim
         self.u = rng.standard_normal((self.t.n_boxes, C))
         self.rho = rng.standard_normal((self.t.n_boxes, C))
         self.uold = rng.standard_normal((self.t.n_boxes, C))
         phys = W.domain_side_mask(dim, lev, idx, types)[:, :, None]
-        self.bc_leaf = rng.standard_normal((len(lev), 2 * dim, 8 ** (dim - 1))) * phys
+        self.bc_leaf = rng.standard_normal((len(lev), 2 * dim, self.n ** (dim - 1))) * phys
         self.levels = np.array([self.t.box(b)["level"] for b in range(self.t.n_boxes)])
         self.leaf = np.array([self.t.box(b)["leaf"] for b in range(self.t.n_boxes)])
 
@@ -114,7 +122,7 @@ class Pair:
         for b in range(self.t.n_boxes):
             ob = int(self.o_of[b])
             p = self.o.box_padded(ob, field)
-            p[inner] = arr[b].reshape((8,) * self.dim)
+            p[inner] = arr[b].reshape((self.n,) * self.dim)
             self.o.set_box_padded(ob, p, field)
 
     def _get(self, field):
@@ -183,10 +191,10 @@ def test_scheme_steps(name):
         close("level-1 u", u[root], P._get("u")[root])
 
 
-def inputs(dim, lev, idx, types, seed):
+def inputs(dim, lev, idx, types, seed, n=8):
     rng = np.random.default_rng(seed)
-    rho = rng.standard_normal((len(lev), 8 ** dim))
-    bc = rng.standard_normal((len(lev), 2 * dim, 8 ** (dim - 1)))
+    rho = rng.standard_normal((len(lev), n ** dim))
+    bc = rng.standard_normal((len(lev), 2 * dim, n ** (dim - 1)))
     bc *= W.domain_side_mask(dim, lev, idx, types)[:, :, None]
     return rho, bc
 
@@ -196,7 +204,7 @@ def test_scheme_solves_match_oracle(name):
     from paper_1701_04329_amd import afmg as A
     dim, (lev, idx), types, *_ = case(name)
     t, o = build(name, 5)
-    rho, bc = inputs(dim, lev, idx, types, 17)
+    rho, bc = inputs(dim, lev, idx, types, 17, box_n(name))
     dev = torch.device("cuda", 0)
     rho_d = t.leaf_to_boxes(torch.tensor(rho, device=dev))
     bc_d = t.bc_rows(torch.tensor(bc, device=dev)) if t.n_bfaces else None

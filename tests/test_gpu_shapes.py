@@ -55,6 +55,39 @@ def test_every_shape_gives_identical_solves(dim, precision):
 
 
 @pytest.mark.parametrize("dim", [2, 3])
+def test_shapes_of_16_cell_boxes(dim):
+    """Boxes of 16^D cells: in 2D (16 threads per box) every shape gives the
+    default solve bitwise; in 3D a box fills a 256-thread workgroup, so the
+    smaller workgroups are refused and the autotuner keeps 256."""
+    from paper_1701_04329_amd import afmg as A
+    c = (0.3, 0.62, 0.41)
+    w = W.random_fields(dim, 16, *W.ball_leaves(dim, 16, 4 if dim == 3 else 6, c, 0.0, 1), 25)
+    t = A.Tree(w.dim, w.level, w.idx, box_n=16)
+    announce(f"16-cell boxes shapes dim={dim} default")
+    ref = {p: solve(t, w, cycle="FMG", precision=p, tol=1e-10) for p in ("fp64", "mixed")}
+    wgs = (64, 128, 256) if dim == 2 else (256,)
+    for p in ("fp64", "mixed"):
+        for wg in wgs:
+            for nr in (0, 1):
+                announce(f"16-cell boxes dim={dim} {p} wg={wg} no_remap={nr}")
+                t.set_shape(wg, nr)
+                u, s = solve(t, w, cycle="FMG", precision=p, tol=1e-10)
+                assert torch.equal(u, ref[p][0]), (p, wg, nr)
+                assert np.array_equal(s["hist_max"], ref[p][1]["hist_max"])
+    if dim == 3:
+        for wg in (64, 128):
+            with pytest.raises(A.AfmgError):
+                t.set_shape(wg, 0)
+    t.set_shape(256, 0)
+    shapes = t.autotune()
+    for vals in shapes.values():
+        assert all(wg in wgs and nr in (0, 1) for wg, nr in vals)
+    for p in ("fp64", "mixed"):
+        u, s = solve(t, w, cycle="FMG", precision=p, tol=1e-10, graph=True)
+        assert torch.equal(u, ref[p][0]), p
+
+
+@pytest.mark.parametrize("dim", [2, 3])
 def test_autotuned_tree_and_batch_reproduce_default(dim):
     from paper_1701_04329_amd import afmg as A
     w = grid(dim)

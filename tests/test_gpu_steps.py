@@ -25,25 +25,39 @@ pytestmark = pytest.mark.gpu
 REL = 1e-14
 
 
-def grids():
-    """name -> (dim, (level, idx), side types or None)"""
+_G = {}
+
+
+def grids(name):
+    """name -> (dim, box size N, (level, idx), side types or None)"""
+    if name in _G:
+        return _G[name]
     c = (0.3, 0.62, 0.41)
     D_, N_, P_ = "dirichlet", "neumann", "periodic"
-    return {
-        "a3": (3, W.ball_leaves(3, 8, 5, c, 0.0, 1), None),
-        "a2": (2, W.ball_leaves(2, 8, 6, c, 0.0, 1), None),
-        "u3": (3, W.uniform_leaves(3, 3), None),
+    make = {
+        "a3": lambda: (3, 8, W.ball_leaves(3, 8, 5, c, 0.0, 1), None),
+        "a2": lambda: (2, 8, W.ball_leaves(2, 8, 6, c, 0.0, 1), None),
+        "u3": lambda: (3, 8, W.uniform_leaves(3, 3), None),
         # L-shaped coarse grid, refinement at the re-entrant corner, mixed sides
-        "L2": (2, W.domain_leaves(2, 8, [(1, 1), (2, 1), (1, 2)], 5, (0.97, 0.97)), [D_, N_, N_, D_]),
+        "L2": lambda: (2, 8, W.domain_leaves(2, 8, [(1, 1), (2, 1), (1, 2)], 5, (0.97, 0.97)), [D_, N_, N_, D_]),
         # 2x1 coarse grid periodic in x, refinement across the periodic side
-        "p3": (3, W.domain_leaves(3, 8, [(1, 1, 1), (2, 1, 1)], 4, (1.98, 0.4, 0.6), periodic=(True, False, False)),
-               [P_, P_, N_, D_, D_, N_]),
+        "p3": lambda: (3, 8, W.domain_leaves(3, 8, [(1, 1, 1), (2, 1, 1)], 4, (1.98, 0.4, 0.6),
+                                             periodic=(True, False, False)), [P_, P_, N_, D_, D_, N_]),
         # one level-1 box, Neumann sides along x and y
-        "n3": (3, W.ball_leaves(3, 8, 4, c, 0.0, 1), [N_, N_, N_, N_, D_, D_]),
+        "n3": lambda: (3, 8, W.ball_leaves(3, 8, 4, c, 0.0, 1), [N_, N_, N_, N_, D_, D_]),
+        # boxes of 16^D cells (paper §2.1: N is a parameter): 3D trees take
+        # the general coarse kernel, 2D trees the one-tree coarse kernel
+        "a3x16": lambda: (3, 16, W.ball_leaves(3, 16, 4, c, 0.0, 1), None),
+        "a2x16": lambda: (2, 16, W.ball_leaves(2, 16, 5, c, 0.0, 1), None),
+        "u3x16": lambda: (3, 16, W.uniform_leaves(3, 2), None),
+        "p3x16": lambda: (3, 16, W.domain_leaves(3, 16, [(1, 1, 1), (2, 1, 1)], 3, (1.98, 0.4, 0.6),
+                                                 periodic=(True, False, False)), [P_, P_, N_, D_, D_, N_]),
     }
+    _G[name] = make[name]()
+    return _G[name]
 
 
-NAMES = ["a3", "a2", "u3", "L2", "p3", "n3"]
+NAMES = ["a3", "a2", "u3", "L2", "p3", "n3", "a3x16", "a2x16", "u3x16", "p3x16"]
 
 
 class Pair:
@@ -52,11 +66,11 @@ class Pair:
     def __init__(self, name, seed):
         from paper_1701_04329_amd import afmg as A
         self.A = A
-        dim, (lev, idx), types = grids()[name]
-        self.dim, self.N = dim, 8
-        self.t = A.Tree(dim, lev, idx, bc_type=types)
-        self.o = O.Tree(dim, 8, lev, idx, bc_type=types)
-        C = 8 ** dim
+        dim, n, (lev, idx), types = grids(name)
+        self.dim, self.N = dim, n
+        self.t = A.Tree(dim, lev, idx, box_n=n, bc_type=types)
+        self.o = O.Tree(dim, n, lev, idx, bc_type=types)
+        C = n ** dim
         key_o = {}
         for b in range(self.o.nbox):
             i = self.o.box_info(b)
@@ -69,7 +83,7 @@ class Pair:
         self.rho = rng.standard_normal((self.t.n_boxes, C))
         self.uold = rng.standard_normal((self.t.n_boxes, C))
         phys = W.domain_side_mask(dim, lev, idx, types)[:, :, None]
-        self.bc_leaf = rng.standard_normal((len(lev), 2 * dim, 8 ** (dim - 1))) * phys
+        self.bc_leaf = rng.standard_normal((len(lev), 2 * dim, n ** (dim - 1))) * phys
         self.lev, self.idx = lev, idx
 
     def gpu(self, op, level, colour=0, homog=False):

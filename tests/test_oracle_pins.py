@@ -438,9 +438,8 @@ def bc_term(dim, N, lev, idx, bc):
     return out.reshape(len(lev), -1)
 
 
-@pytest.mark.parametrize("dim,res", [(2, 128), (3, 32)])
-def test_uniform_solution_equals_dst(dim, res):
-    N = 8
+@pytest.mark.parametrize("dim,res,N", [(2, 128, 8), (3, 32, 8), (2, 128, 16), (3, 32, 16)])
+def test_uniform_solution_equals_dst(dim, res, N):
     mix = W.gauss_mix_seeded(dim, 2, 21, 0.1, 0.9, (0.05, 0.1))
     lmax = 1 + int(np.log2(res // N))
     lev, idx = W.uniform_leaves(dim, lmax)
@@ -515,6 +514,25 @@ def test_fmg_reaches_discretisation_error_and_v_cycle_rate():
     u_fmg, st = t.solve(w.rho, w.bc, cycle="FMG", fixed_cycles=0, max_cycles=0)
     assert np.abs(u_fmg - w.u_exact).max() <= 2.0 * disc
     _, st = t.solve(w.rho, w.bc, fixed_cycles=12)
+    rates = st["hist_max"][1:] / st["hist_max"][:-1]
+    assert np.all((rates > 0.02) & (rates < 0.2)), rates
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_coarse_grids_below_the_root_follow_box_size(dim):
+    """§3.2: coarse grids are added below the coarsest tree level down to
+    2^D cells; with 16^D-cell boxes these are three levels of 8, 4 and 2
+    cells per side (the paper's example), with 8^D-cell boxes two.  The
+    V-cycle rate with 16^D-cell boxes is that of the method (§4.1: a
+    roughly constant factor, about 0.07 in the paper)."""
+    for N, lmin in ((8, -1), (16, -2)):
+        lev, idx = W.uniform_leaves(dim, 2)
+        t = O.Tree(dim, N, lev, idx)
+        assert t.lmin == lmin, (N, t.lmin)
+    mix = W.gauss_mix_seeded(dim, 2, 31, 0.2, 0.8, (0.08, 0.12))
+    lev, idx = W.uniform_leaves(dim, 3 if dim == 3 else 4)
+    w = W.sample_workload("rate16", dim, 16, lev, idx, mix)
+    _, st = O.Tree(dim, 16, lev, idx).solve(w.rho, w.bc, fixed_cycles=8)
     rates = st["hist_max"][1:] / st["hist_max"][:-1]
     assert np.all((rates > 0.02) & (rates < 0.2)), rates
 
