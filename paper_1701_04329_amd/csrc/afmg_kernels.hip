@@ -431,6 +431,24 @@ __device__ __forceinline__ T gs_finish(const T *s, T raw, int v, T own, int homo
     return T(0.5) * raw + T(1.25) * own - T(0.25) * ((u2 + u1p) + u1pp);
 }
 
+// Slot of this workgroup holding the same-level neighbour across side s of
+// box sl.b (one tree: slot q holds box sl.b + q - sl.slot), or -1.  Only the
+// slot that differs in the side's axis bit can be a sibling; the box table
+// decides (any box order stays correct).
+// (v: the box record's neighbour entry of that side, selected with a
+// compile-time index so that the record stays in registers)
+template <int D, int N, int W, int AXIS>
+__device__ __forceinline__ int sib_slot(int v, const Slot<D, N> &sl, int64_t b0, int nb) {
+    constexpr int BPW = W / Geo<D, N>::TPB, BIT = 1 << AXIS;
+    if constexpr (BIT >= BPW) {
+        return -1;
+    } else {
+        const int q = sl.slot ^ BIT;
+        const int64_t cand = sl.b + (q - sl.slot);
+        return (v >= 0 && (int64_t)v == cand && cand - b0 < nb) ? q : -1;
+    }
+}
+
 template <int D, int N, typename T, int W, bool F>
 __global__ __launch_bounds__(W) void k_gsrb(LevelArgs<T> a, int colour) {
     using G = Geo<D, N>;
@@ -458,6 +476,14 @@ __global__ __launch_bounds__(W) void k_gsrb(LevelArgs<T> a, int colour) {
     // (sl.b is clamped), so that no branch separates the loads from the
     // kernel start
     const bool act = sl.valid;
+    // Siblings in the workgroup: the 2^D children of a parent are consecutive
+    // in a level's box order, so slot ^ (axis bit) is often the same-level
+    // neighbour across a side.  Its other colour is staged in LDS by its own
+    // threads, and ghosts across such a side are read there after the
+    // barrier (the same values as from global memory).  qx, qy, qz: the slot
+    // across the side this thread's ghosts need, or -1.
+    // (decided after the box's own loads are issued: it needs the box record)
+    int qx = -1, qy = -1, qz = -1;
     if (!F || act) {
         T ot[HN];
         const int oth0 = (1 - colour) * G::HALF + r * HN;
@@ -466,9 +492,16 @@ __global__ __launch_bounds__(W) void k_gsrb(LevelArgs<T> a, int colour) {
         const T *rb = a.rho + (size_t)sl.b * G::C + own0;
 #pragma unroll
         for (int m = 0; m < HN; m++) rr[m] = rb[m];
+        if (!F) {
+            qx = sib_slot<D, N, W, 0>(p == 0 ? bi.nbr[0] : bi.nbr[1], sl, a.b0, a.nb);
+            qy = sib_slot<D, N, W, 1>(j == 0 ? bi.nbr[2] : bi.nbr[3], sl, a.b0, a.nb);
+            if (D == 3) qz = sib_slot<D, N, W, 2>(k == 0 ? bi.nbr[4] : bi.nbr[5], sl, a.b0, a.nb);
+        }
         // x ghost of the row end cell (side 0 when the row starts with this colour)
-        if (p == 0) gx = ghost_raw<D, N, 0, T>(bi, r, a.u, a.bc, a.homog, vx);
-        else gx = ghost_raw<D, N, 1, T>(bi, r, a.u, a.bc, a.homog, vx);
+        if (qx < 0) {
+            if (p == 0) gx = ghost_raw<D, N, 0, T>(bi, r, a.u, a.bc, a.homog, vx);
+            else gx = ghost_raw<D, N, 1, T>(bi, r, a.u, a.bc, a.homog, vx);
+        }
         bool need_own = vx < 0;
         // y / z ghosts.  Across a same-level side they are the other-colour
         // cells of one row of the neighbour (row j' = N-1-j, resp. k' =
@@ -476,7 +509,7 @@ __global__ __launch_bounds__(W) void k_gsrb(LevelArgs<T> a, int colour) {
         // with both sides of an axis at the same level take this form, the
         // others the general one, which comes later in the program so that
         // the common form's loads never wait for its loads.
-        const bool yrow = j == 0 || j == N - 1, zrow = D == 3 && (k == 0 || k == N - 1);
+        const bool yrow = (j == 0 || j == N - 1) && qy < 0, zrow = D == 3 && (k == 0 || k == N - 1) && qz < 0;
         const bool yfast = bi.nbr[2] >= 0 && bi.nbr[3] >= 0;
         const bool zfast = D == 3 && bi.nbr[4] >= 0 && bi.nbr[5] >= 0;
         if (yfast && yrow) {
@@ -525,6 +558,16 @@ __global__ __launch_bounds__(W) void k_gsrb(LevelArgs<T> a, int colour) {
     }
     __syncthreads();
     if (!act) return;
+    // ghosts from a sibling's staged other colour: its face cell across the side
+    if (qx >= 0) gx = so[qx * oblock<D, N>() + oslot<D, N>(p == 0 ? N - 1 : 0, j, k)];
+    if (qy >= 0 && (j == 0 || j == N - 1)) {
+#pragma unroll
+        for (int m = 0; m < HN; m++) gy[m] = so[qy * oblock<D, N>() + oslot<D, N>(2 * m + p, j == 0 ? N - 1 : 0, k)];
+    }
+    if (D == 3 && qz >= 0 && (k == 0 || k == N - 1)) {
+#pragma unroll
+        for (int m = 0; m < HN; m++) gz[m] = so[qz * oblock<D, N>() + oslot<D, N>(2 * m + p, j, k == 0 ? N - 1 : 0)];
+    }
 #pragma unroll
     for (int m = 0; m < HN; m++) {
         const int i = 2 * m + p;
@@ -591,6 +634,13 @@ __global__ __launch_bounds__(W) void k_gsrb_cube(LevelArgs<T> a, int colour) {
     const int vx = mort_nbr(a.b0, mb, xm, p != 0);
     const int vy = yrow ? mort_nbr(a.b0, mb, xm << 1, j != 0) : 0;
     const int vz = zrow ? mort_nbr(a.b0, mb, xm << 2, k != 0) : 0;
+    // the neighbour is a sibling in this workgroup (slot ^ axis bit, box
+    // key ^ axis bit): its ghost comes from its staged other colour
+    constexpr int BPW = W / G::TPB;
+    const int rx = vx - (int)a.b0, ry = vy - (int)a.b0, rz = vz - (int)a.b0;
+    const int qx = (BPW > 1 && vx >= 0 && rx == (mb ^ 1)) ? (sl.slot ^ 1) : -1;
+    const int qy = (BPW > 2 && yrow && vy >= 0 && ry == (mb ^ 2)) ? (sl.slot ^ 2) : -1;
+    const int qz = (D == 3 && BPW > 4 && zrow && vz >= 0 && rz == (mb ^ 4)) ? (sl.slot ^ 4) : -1;
     T rr[HN], ot[HN], gy[HN], gz[HN];
     T gx = T(0);
 #pragma unroll
@@ -604,13 +654,13 @@ __global__ __launch_bounds__(W) void k_gsrb_cube(LevelArgs<T> a, int colour) {
     const T *rb = a.rho + (size_t)sl.b * G::C + own0;
 #pragma unroll
     for (int m = 0; m < HN; m++) rr[m] = rb[m];
-    if (vx >= 0) gx = a.u[(size_t)vx * G::C + cpos<D, N>(p == 0 ? N - 1 : 0, j, k)];
-    if (yrow && vy >= 0) {
+    if (vx >= 0 && qx < 0) gx = a.u[(size_t)vx * G::C + cpos<D, N>(p == 0 ? N - 1 : 0, j, k)];
+    if (yrow && vy >= 0 && qy < 0) {
         const T *nr = a.u + (size_t)vy * G::C + oth0 + ((D == 3 ? N * k : 0) + (N - 1 - j) - r) * HN;
 #pragma unroll
         for (int m = 0; m < HN; m++) gy[m] = nr[m];
     }
-    if (zrow && vz >= 0) {
+    if (zrow && vz >= 0 && qz < 0) {
         const T *nr = a.u + (size_t)vz * G::C + oth0 + ((N - 1 - k) * N + j - r) * HN;
 #pragma unroll
         for (int m = 0; m < HN; m++) gz[m] = nr[m];
@@ -628,6 +678,15 @@ __global__ __launch_bounds__(W) void k_gsrb_cube(LevelArgs<T> a, int colour) {
     for (int m = 0; m < HN; m++) s[m * G::TPB + r] = ot[m];
     __syncthreads();
     if (!sl.valid) return;
+    if (qx >= 0) gx = so[qx * oblock<D, N>() + oslot<D, N>(p == 0 ? N - 1 : 0, j, k)];
+    if (qy >= 0) {
+#pragma unroll
+        for (int m = 0; m < HN; m++) gy[m] = so[qy * oblock<D, N>() + oslot<D, N>(2 * m + p, j == 0 ? N - 1 : 0, k)];
+    }
+    if (qz >= 0) {
+#pragma unroll
+        for (int m = 0; m < HN; m++) gz[m] = so[qz * oblock<D, N>() + oslot<D, N>(2 * m + p, j, k == 0 ? N - 1 : 0)];
+    }
     // Dirichlet sides: ghost 2 b - u1 (b = 0 when homogeneous)
     const bool dx = vx < 0, dy = yrow && vy < 0, dz = zrow && vz < 0;
     T ow[HN], bx = T(0), by[HN], bz[HN];

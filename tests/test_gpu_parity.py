@@ -190,7 +190,8 @@ def test_deep_point_refinement_matches_oracle(dim, lmax):
     check_pair(w, cycle="V", tol=1e-10)
 
 
-def test_maximum_size_uniform_512_residual():
+@pytest.mark.parametrize("n", [8, 16])
+def test_maximum_size_uniform_512_residual(n):
     """The largest uniform grid the benchmark runs (512^3 = 134,217,728
     unknowns, lap(phi) = 1, phi = 0 on the boundary), solved to a 1e-8
     residual reduction (the FP64 rounding floor of this residual is about
@@ -199,11 +200,12 @@ def test_maximum_size_uniform_512_residual():
     check is a property that holds at any size: the residual of the returned
     solution, recomputed here from the 7-point stencil with the Dirichlet
     ghost -u1 (plain numpy on the whole grid), is below 1e-8 of the initial
-    one (max |rho| = 1), up to the rounding floor."""
+    one (max |rho| = 1), up to the rounding floor.  Boxes of 8^3 and of
+    16^3 cells."""
     from paper_1701_04329_amd import afmg as A
-    w = W.uniform_const_rhs(3, 8, 512)
-    announce(f"maximum size {w.name} unknowns={w.n_unknowns}")
-    t = A.Tree(3, w.level, w.idx)
+    w = W.uniform_const_rhs(3, n, 512)
+    announce(f"maximum size {w.name} box {n}^3 unknowns={w.n_unknowns}")
+    t = A.Tree(3, w.level, w.idx, box_n=n)
     dev = torch.device("cuda", 0)
     rho = t.leaf_to_boxes(torch.tensor(w.rho, device=dev))
     u, st = A.solve(t, rho, None, cycle="FMG", tol=1e-8)
@@ -214,11 +216,11 @@ def test_maximum_size_uniform_512_residual():
     # leaves in box order -> one 512^3 array (z, y, x)
     lev, idx = w.level, w.idx
     g = np.zeros((512, 512, 512))
-    ulh = ul.cpu().numpy().reshape(-1, 8, 8, 8)
+    ulh = ul.cpu().numpy().reshape(-1, n, n, n)
     del ul
-    i0, j0, k0 = (idx[:, 0] - 1) * 8, (idx[:, 1] - 1) * 8, (idx[:, 2] - 1) * 8
+    i0, j0, k0 = (idx[:, 0] - 1) * n, (idx[:, 1] - 1) * n, (idx[:, 2] - 1) * n
     for q in range(len(lev)):
-        g[k0[q]:k0[q] + 8, j0[q]:j0[q] + 8, i0[q]:i0[q] + 8] = ulh[q]
+        g[k0[q]:k0[q] + n, j0[q]:j0[q] + n, i0[q]:i0[q] + n] = ulh[q]
     del ulh
     p = np.pad(g, 1)
     for ax in range(3):  # Dirichlet ghosts 2b - u1 with b = 0
