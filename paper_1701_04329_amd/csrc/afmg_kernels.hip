@@ -96,6 +96,15 @@ __device__ __forceinline__ int xcd_remap(int w, int G) {
     // x < r: x (q + 1) + p; else r (q + 1) + (x - r) q + p (no branch)
     return x * q + min(x, r) + p;
 }
+// The same runs, each XCD taking its run from the end: a launch that follows
+// one in the forward order starts on the boxes whose data the previous
+// launch touched last (still in that XCD's L2)
+__device__ __forceinline__ int xcd_remap_rev(int w, int G) {
+    const int q = G >> 3, r = G & 7;
+    const int x = w & 7, p = w >> 3;
+    const int len = q + (x < r ? 1 : 0);
+    return x * q + min(x, r) + (len - 1 - p);
+}
 
 // Morton neighbours on a complete level (every box of one tree's level
 // present, in Morton order, so that box index = Morton key): the x bits of a
@@ -133,13 +142,14 @@ struct Slot {
 // rather than read from the dispatch, which saves the kernel one dependent
 // argument load before its first memory access.
 template <int D, int N, int W = 256>
-__device__ __forceinline__ Slot<D, N> slot_of(int64_t b0, int nb, bool remap = true) {
+__device__ __forceinline__ Slot<D, N> slot_of(int64_t b0, int nb, bool remap = true, bool rev = false) {
     using G = Geo<D, N>;
     constexpr int BPW = W / G::TPB;
     static_assert(BPW >= 1 && W % G::TPB == 0, "workgroup must hold whole boxes");
     Slot<D, N> r;
-    const int wr = xcd_remap((int)blockIdx.x, (nb + BPW - 1) / BPW);
-    const int w = remap ? wr : (int)blockIdx.x;
+    const int ng = (nb + BPW - 1) / BPW;
+    const int wr = rev ? xcd_remap_rev((int)blockIdx.x, ng) : xcd_remap((int)blockIdx.x, ng);
+    const int w = remap ? wr : (rev ? ng - 1 - (int)blockIdx.x : (int)blockIdx.x);
     r.slot = (int)threadIdx.x / G::TPB;
     r.t = (int)threadIdx.x % G::TPB;
     int bl = w * BPW + r.slot;
@@ -158,8 +168,8 @@ __device__ __forceinline__ Slot<D, N> slot_of(int64_t b0, int nb, bool remap = t
 // grid (sized for the whole level) find no box and exit, so that stopped
 // trees cost neither memory traffic nor more than an empty workgroup.
 template <int D, int N, int W, bool F, typename T>
-__device__ __forceinline__ Slot<D, N> slot_lvl(const LevelArgs<T> &a) {
-    if (!F) return slot_of<D, N, W>(a.b0, a.nb, a.no_remap == 0);
+__device__ __forceinline__ Slot<D, N> slot_lvl(const LevelArgs<T> &a, bool rev = false) {
+    if (!F) return slot_of<D, N, W>(a.b0, a.nb, a.no_remap == 0, rev);
     using G = Geo<D, N>;
     constexpr int BPW = W / G::TPB;
     Slot<D, N> r;
@@ -454,7 +464,9 @@ __global__ __launch_bounds__(W) void k_gsrb(LevelArgs<T> a, int colour) {
     using G = Geo<D, N>;
     constexpr int HN = G::HN;
     __shared__ T so[(W / G::TPB) * oblock<D, N>()];
-    const Slot<D, N> sl = slot_lvl<D, N, W, F>(a);
+    // the black half sweep takes each XCD's run of boxes from the end, so
+    // that it starts where the red one ended (and the other way round)
+    const Slot<D, N> sl = slot_lvl<D, N, W, F>(a, colour == 1);
     T *s = so + sl.slot * oblock<D, N>();
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     T *ub = a.u + (size_t)sl.b * G::C;
@@ -619,7 +631,7 @@ __global__ __launch_bounds__(W) void k_gsrb_cube(LevelArgs<T> a, int colour) {
     __asm__ volatile("" ::"s"(a.u), "s"(a.rho), "s"(a.b0), "s"(a.nb), "s"(a.no_remap), "s"(a.xmask),
                      "s"(colour));
     if (ADD) __asm__ volatile("" ::"s"(a.add_to));
-    const Slot<D, N> sl = slot_lvl<D, N, W, false>(a);
+    const Slot<D, N> sl = slot_lvl<D, N, W, false>(a, colour == 1);
     T *s = so + sl.slot * oblock<D, N>();
     T *ub = a.u + (size_t)sl.b * G::C;
     const int r = sl.t;
@@ -997,7 +1009,8 @@ __global__ __launch_bounds__(W) void k_prolong(LevelArgs<T> a) {
     constexpr int NO = G::HC / G::TPB;                           // octant cells per thread
     constexpr int NE = G::C / G::TPB;                            // fine cells per thread
     __shared__ T qs[(W / G::TPB) * G::QC];
-    const Slot<D, N> sl = slot_lvl<D, N, W, F>(a);
+    // reversed order: the first half sweep that follows runs forward
+    const Slot<D, N> sl = slot_lvl<D, N, W, F>(a, true);
     T *q = qs + sl.slot * G::QC;
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
