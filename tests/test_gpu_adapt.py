@@ -194,6 +194,55 @@ def test_adapted_tree_solves_from_transferred_guess():
     assert s_guess["r0_max"] < s_zero["r0_max"]
 
 
+def test_full_size_adaptation():
+    """The benchmark's adaptation at full size (the adaptive octree of about
+    2.3e7 unknowns, sources moved by 0.02, refine above 1e-4 and derefine
+    below 1e-6 of |lap u| h^2): the adapted leaves equal the oracle's, bit
+    for bit; the transferred field keeps every surviving leaf bitwise, and a
+    leaf whose children were removed holds their mean (restriction, §2.5)."""
+    from paper_1701_04329_amd import afmg as A
+    dev = torch.device("cuda", 0)
+    w = W.config3()
+    moved = W.GaussMix(w.mix.centres + np.array([0.02, 0.0, 0.0]), w.mix.sigmas, w.mix.amps)
+    crit = np.abs(moved.laplacian(W.cell_centres(w.dim, w.N, w.level, w.idx))) * (W.box_h(w.level, w.N)[:, None] ** 2)
+    fine = (w.level < w.lmax)[:, None]
+    flags = np.where((crit > 1e-4) & fine, 1, np.where(crit < 1e-6, -1, 0)).astype(np.int8)
+    del crit
+    t = A.Tree(w.dim, w.level, w.idx)
+    announce(f"full-size adaptation leaves={w.n_leaves}")
+    nt, counts = A.adapt(t, t.leaf_to_boxes(torch.tensor(flags, device=dev)).contiguous(), n_buf=2)
+    ol, oi = AD.adapt(3, 8, w.level, w.idx, flags, n_buf=2)
+    gl, gi = nt.leaves()
+    assert sorted(keys_of(gl, gi, 3)) == sorted(keys_of(ol, oi, 3))
+    assert counts[0] > 0 and counts[1] > 0
+    # a field with distinct values per cell, carried over
+    rng = np.random.default_rng(7)
+    u = rng.standard_normal((w.n_leaves, 512))
+    ug = nt.boxes_to_leaf(A.transfer(t, nt, t.leaf_to_boxes(torch.tensor(u, device=dev)))).cpu().numpy()
+    old = {k: q for q, k in enumerate(keys_of(w.level, w.idx, 3))}
+    new_keys = keys_of(gl, gi, 3)
+    n_same = n_coarse = 0
+    for q, k in enumerate(new_keys):
+        if k in old:
+            assert np.array_equal(ug[q], u[old[k]]), k
+            n_same += 1
+            continue
+        kids = [(k[0] + 1, 2 * k[1] - 1 + a, 2 * k[2] - 1 + b, 2 * k[3] - 1 + c)
+                for c in (0, 1) for b in (0, 1) for a in (0, 1)]
+        if all(c in old for c in kids):
+            # the parent's cell (I, J, K) is the mean of the 2x2x2 block of its child's cells
+            want = np.zeros((8, 8, 8))
+            for kid in kids:
+                v = u[old[kid]].reshape(8, 8, 8)  # (z, y, x)
+                blk = v.reshape(4, 2, 4, 2, 4, 2).mean(axis=(1, 3, 5))
+                ox, oy, oz = (kid[1] - 1) % 2 * 4, (kid[2] - 1) % 2 * 4, (kid[3] - 1) % 2 * 4
+                want[oz:oz + 4, oy:oy + 4, ox:ox + 4] = blk
+            np.testing.assert_allclose(ug[q].reshape(8, 8, 8), want, rtol=0, atol=1e-14 * np.abs(u).max())
+            n_coarse += 1
+    print(f"kept {n_same}, coarsened {n_coarse}, refined {len(new_keys) - n_same - n_coarse}", flush=True)
+    assert n_coarse == counts[1]
+
+
 def test_adapt_and_transfer_checks():
     from paper_1701_04329_amd import afmg as A
     dev = torch.device("cuda", 0)

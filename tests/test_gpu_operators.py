@@ -311,6 +311,30 @@ def test_case2_paper_configuration():
     assert np.all(h[1:] < 0.5 * h[:-1]), h
 
 
+def test_full_size_eps_jump_matches_oracle():
+    """The benchmark's variable-coefficient workload at its full size: the
+    uniform 256^3 octree with eps = 100 in [0, 1/2)^3 and 1 elsewhere (a jump
+    across three coarse-grid faces), FMG + 2 V-cycles on the GPU and in the
+    oracle; every leaf cell to 1e-12 of the largest value, residual history
+    to 1e-12 of the initial residual."""
+    from paper_1701_04329_amd import afmg as A
+    w = W.config2()
+    eps = W.eps_sampled(lambda x: np.where(np.all(x < 0.5, axis=-1), 100.0, 1.0), w.dim, w.N, w.level, w.idx)
+    dev = torch.device("cuda", 0)
+    t = A.Tree(w.dim, w.level, w.idx)
+    t.set_operator("eps", t.leaf_to_boxes(torch.tensor(eps, device=dev)).contiguous())
+    announce(f"full-size eps jump unknowns={w.n_unknowns}")
+    u, sg = A.solve(t, t.leaf_to_boxes(torch.tensor(w.rho, device=dev)), t.bc_rows(torch.tensor(w.bc, device=dev)),
+                    None, cycle="FMG", fixed_cycles=2)
+    ug = t.boxes_to_leaf(u).cpu().numpy()
+    del u
+    o = O.Tree(w.dim, w.N, w.level, w.idx)
+    o.set_operator("eps", eps)
+    uo, so = o.solve(w.rho, w.bc, cycle="FMG", fixed_cycles=2)
+    assert_leaf_parity(ug, uo, REL, "eps3d full size")
+    assert_norms_close(sg["hist_max"], so["hist_max"], 1e-12 * so["r0_max"], what="eps3d history")
+
+
 # ---------------------------------------------------------------------------
 # the entry point's checks
 # ---------------------------------------------------------------------------
