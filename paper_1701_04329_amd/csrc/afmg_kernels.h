@@ -121,6 +121,7 @@ struct CoarseGenArgs {
     const int32_t *bx;
     int opk;
     const int32_t *dnbr;  // OPK_PROLONG_LIN: as in LevelArgs (the roots' rows)
+    int in_lds;           // set by launch_coarse_gen: the grids live in LDS, not in ws
 };
 
 // wg: workgroup size of the launch (64, 128 or 256 threads; W / N^(D-1)

@@ -1360,13 +1360,21 @@ struct EpsStager {
 // of the old state, u_c = (sum w_s u_s - h^2 rho_c) / sum w_s.  The whole
 // box is staged; the cells written are the updated colour, which no ghost of
 // an updated cell reads (its neighbours across sides are the other colour).
+// Workgroup size of the operator kernels: 128 threads (two 8^3 boxes in 3D,
+// sixteen 8^2 boxes in 2D), or one box where a box needs more threads.  They
+// stage padded boxes of u and eps (16 KB per 8^3 box); 128-thread workgroups
+// leave more of them resident per CU than 256-thread ones (the half sweep on
+// 256^3: 106 against 128 us per launch).
+template <int D, int N>
+constexpr int opw() { return Geo<D, N>::TPB > 128 ? Geo<D, N>::TPB : 128; }
+
 template <int D, int N, typename T>
-__global__ __launch_bounds__(256) void k_vgsrb(LevelArgs<T> a, int colour) {
+__global__ __launch_bounds__((opw<D, N>())) void k_vgsrb(LevelArgs<T> a, int colour) {
     using G = Geo<D, N>;
     constexpr int HN = G::HN;
-    __shared__ T sm[G::BPW * G::PC];
-    __shared__ T sme[G::BPW * G::PC];
-    const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb, a.no_remap == 0);
+    __shared__ T sm[opw<D, N>() / G::TPB * G::PC];
+    __shared__ T sme[opw<D, N>() / G::TPB * G::PC];
+    const Slot<D, N> sl = slot_of<D, N, opw<D, N>()>(a.b0, a.nb, a.no_remap == 0);
     T *s = sm + sl.slot * G::PC, *se = sme + sl.slot * G::PC;
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
@@ -1409,11 +1417,11 @@ __global__ __launch_bounds__(256) void k_vgsrb(LevelArgs<T> a, int colour) {
 // residual r = rho - L u on the boxes of level l; the parent's octant
 // receives the means of u and of r (volume means in the cylindrical form)
 template <int D, int N, typename T>
-__global__ __launch_bounds__(256) void k_vresid_restrict(LevelArgs<T> a) {
+__global__ __launch_bounds__((opw<D, N>())) void k_vresid_restrict(LevelArgs<T> a) {
     using G = Geo<D, N>;
-    __shared__ T sm[G::BPW * G::PC];
-    __shared__ T sme[G::BPW * G::PC];
-    const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb, a.no_remap == 0);
+    __shared__ T sm[opw<D, N>() / G::TPB * G::PC];
+    __shared__ T sme[opw<D, N>() / G::TPB * G::PC];
+    const Slot<D, N> sl = slot_of<D, N, opw<D, N>()>(a.b0, a.nb, a.no_remap == 0);
     T *s = sm + sl.slot * G::PC, *se = sme + sl.slot * G::PC;
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
@@ -1472,11 +1480,11 @@ __global__ __launch_bounds__(256) void k_vresid_restrict(LevelArgs<T> a) {
 
 // boxes of level l-1: uold <- u; on parents rho <- rbar + L_H u
 template <int D, int N, typename T>
-__global__ __launch_bounds__(256) void k_vcoarse_rhs(LevelArgs<T> a) {
+__global__ __launch_bounds__((opw<D, N>())) void k_vcoarse_rhs(LevelArgs<T> a) {
     using G = Geo<D, N>;
-    __shared__ T sm[G::BPW * G::PC];
-    __shared__ T sme[G::BPW * G::PC];
-    const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb, a.no_remap == 0);
+    __shared__ T sm[opw<D, N>() / G::TPB * G::PC];
+    __shared__ T sme[opw<D, N>() / G::TPB * G::PC];
+    const Slot<D, N> sl = slot_of<D, N, opw<D, N>()>(a.b0, a.nb, a.no_remap == 0);
     T *s = sm + sl.slot * G::PC, *se = sme + sl.slot * G::PC;
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
@@ -1623,14 +1631,14 @@ __global__ __launch_bounds__(256) void k_vfinal(LevelArgs<T> a, double *partial,
 // interpolation.  The coefficients of the parent's octant and its halo are
 // staged beside the deltas, with the copy rules of the coefficient ghosts.
 template <int D, int N, typename T>
-__global__ __launch_bounds__(256) void k_vprolong(LevelArgs<T> a) {
+__global__ __launch_bounds__((opw<D, N>())) void k_vprolong(LevelArgs<T> a) {
     using G = Geo<D, N>;
     constexpr int NH = (2 * D * G::HF + G::TPB - 1) / G::TPB;
     constexpr int NO = G::HC / G::TPB;
     constexpr int NE = G::C / G::TPB;
-    __shared__ T qs[G::BPW * G::QC];
-    __shared__ T qes[G::BPW * G::QC];
-    const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb, a.no_remap == 0);
+    __shared__ T qs[opw<D, N>() / G::TPB * G::QC];
+    __shared__ T qes[opw<D, N>() / G::TPB * G::QC];
+    const Slot<D, N> sl = slot_of<D, N, opw<D, N>()>(a.b0, a.nb, a.no_remap == 0);
     T *q = qs + sl.slot * G::QC, *qe = qes + sl.slot * G::QC;
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
@@ -1753,11 +1761,11 @@ __global__ __launch_bounds__(256) void k_vprolong(LevelArgs<T> a) {
 // inner cell).  A fine cell takes weights 3/4 and 1/4 per axis over the 2^D
 // coarse cells nearest to it.
 template <int D, int N, typename T>
-__global__ __launch_bounds__(256) void k_vprolong_lin(LevelArgs<T> a) {
+__global__ __launch_bounds__((opw<D, N>())) void k_vprolong_lin(LevelArgs<T> a) {
     using G = Geo<D, N>;
     constexpr int NE = G::C / G::TPB;
-    __shared__ T sm[G::BPW * G::PC];
-    const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb, a.no_remap == 0);
+    __shared__ T sm[opw<D, N>() / G::TPB * G::PC];
+    const Slot<D, N> sl = slot_of<D, N, opw<D, N>()>(a.b0, a.nb, a.no_remap == 0);
     T *s = sm + sl.slot * G::PC;
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const bool act = sl.valid;
@@ -3507,7 +3515,11 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse_gen(CoarseGenArgs<T> a) {
     using GG = GenGeo<D, N>;
     using G = Geo<D, N>;
     const int R = a.n_roots;
-    double *ws = a.ws;
+    // the grids in LDS where they fit (the kernel fills them from the boxes
+    // and writes its results back, so the scratch holds nothing between
+    // calls), else in the caller's scratch
+    extern __shared__ double gen_lds[];
+    double *ws = a.in_lds ? gen_lds : a.ws;
     GenState<D, N> st{a.info, ws, ws + (size_t)R * GG::TOT, ws + (size_t)2 * R * GG::TOT,
                       ws + (size_t)3 * R * GG::TOT, ws + (size_t)4 * R * GG::TOT, R, a.homog,
                       a.n_down, a.n_up, a.n_base,
@@ -3976,13 +3988,15 @@ template <int D, int N, typename T>
 static void launch_level_op(Op op, const LevelArgs<T> &a, int colour, hipStream_t st) {
     if constexpr (sizeof(T) == 8) {
         const int g = wg_count<D, N, 256>(a.nb);
+        constexpr int OW = opw<D, N>();
+        const int go = wg_count<D, N, OW>(a.nb);
         switch (op) {
-        case Op::GSRB: AFMG_LAUNCH((k_vgsrb<D, N, T>), g, st, a, colour); break;
-        case Op::RESID_RESTRICT: AFMG_LAUNCH((k_vresid_restrict<D, N, T>), g, st, a); break;
-        case Op::COARSE_RHS: AFMG_LAUNCH((k_vcoarse_rhs<D, N, T>), g, st, a); break;
+        case Op::GSRB: AFMG_LAUNCH_W((k_vgsrb<D, N, T>), go, OW, st, a, colour); break;
+        case Op::RESID_RESTRICT: AFMG_LAUNCH_W((k_vresid_restrict<D, N, T>), go, OW, st, a); break;
+        case Op::COARSE_RHS: AFMG_LAUNCH_W((k_vcoarse_rhs<D, N, T>), go, OW, st, a); break;
         case Op::PROLONG:
-            if (a.opk & OPK_PROLONG_LIN) AFMG_LAUNCH((k_vprolong_lin<D, N, T>), g, st, a);
-            else if (a.opk & (OPK_PROLONG_EPS | OPK_GHOST_BIL)) AFMG_LAUNCH((k_vprolong<D, N, T>), g, st, a);
+            if (a.opk & OPK_PROLONG_LIN) AFMG_LAUNCH_W((k_vprolong_lin<D, N, T>), go, OW, st, a);
+            else if (a.opk & (OPK_PROLONG_EPS | OPK_GHOST_BIL)) AFMG_LAUNCH_W((k_vprolong<D, N, T>), go, OW, st, a);
             else AFMG_LAUNCH((k_prolong<D, N, T, 256, false>), g, st, a);
             break;
         case Op::RESTRICT_RHO:
@@ -4082,7 +4096,14 @@ void launch_coarse(const CoarseArgs<T> &a, int n_trees, hipStream_t st) {
 
 template <int D, int N, typename T>
 void launch_coarse_gen(const CoarseGenArgs<T> &a, hipStream_t st) {
-    hipLaunchKernelGGL((k_coarse_gen<D, N, T>), dim3(1), dim3(COARSE_NT), 0, st, a);
+    // up to 64 KB of dynamic LDS (a level-1 box with its chain: 27 KB in 3D
+    // with 8^3 cells, 3.8 KB in 2D); on the 3D eps-jump solve 162 against
+    // 192 us per call with the grids in global memory
+    constexpr size_t LDS_GEN_MAX = 64 * 1024;
+    const size_t bytes = sizeof(double) * coarse_gen_doubles<D, N>(a.n_roots);
+    CoarseGenArgs<T> b = a;
+    b.in_lds = bytes <= LDS_GEN_MAX ? 1 : 0;
+    hipLaunchKernelGGL((k_coarse_gen<D, N, T>), dim3(1), dim3(COARSE_NT), b.in_lds ? bytes : 0, st, b);
 }
 template <int D, int N>
 void launch_restrict_field_op(const BoxInfo *info, double *f, int64_t b0, int64_t nb, int opk, const int32_t *bx,
