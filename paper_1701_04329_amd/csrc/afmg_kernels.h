@@ -124,6 +124,10 @@ struct CoarseGenArgs {
     int in_lds;           // set by launch_coarse_gen: the grids live in LDS, not in ws
 };
 
+// Workgroup size of the kernels of a tree with an operator: 128 threads, or
+// one box where a box has more rows (N^(D-1) threads per box)
+constexpr int op_wg(int dim, int n) { return (dim == 3 ? n * n : n) > 128 ? (dim == 3 ? n * n : n) : 128; }
+
 // wg: workgroup size of the launch (64, 128 or 256 threads; W / N^(D-1)
 // boxes per workgroup); every size gives bitwise the same results
 template <int D, int N, typename T>

@@ -1366,7 +1366,7 @@ struct EpsStager {
 // leave more of them resident per CU than 256-thread ones (the half sweep on
 // 256^3: 106 against 128 us per launch).
 template <int D, int N>
-constexpr int opw() { return Geo<D, N>::TPB > 128 ? Geo<D, N>::TPB : 128; }
+constexpr int opw() { return op_wg(D, N); }
 
 template <int D, int N, typename T>
 __global__ __launch_bounds__((opw<D, N>())) void k_vgsrb(LevelArgs<T> a, int colour) {
@@ -1459,7 +1459,8 @@ __global__ __launch_bounds__((opw<D, N>())) void k_vresid_restrict(LevelArgs<T> 
         const int pc = sl.t + it * G::TPB;
         const int I = pc % G::H, J = (pc / G::H) % G::H, K = D == 3 ? pc / (G::H * G::H) : 0;
         T su = T(0), sr = T(0), vol = T(0);
-#pragma unroll
+        // two fine cells at a time: the full unroll needs 220 VGPRs
+#pragma unroll 2
         for (int q = 0; q < NB; q++) {
             int i, j, k;
             block_cell<D, N>(pc, q, i, j, k);
@@ -1531,13 +1532,13 @@ __global__ __launch_bounds__((opw<D, N>())) void k_vcoarse_rhs(LevelArgs<T> a) {
 // u (volume mean in the cylindrical form); on leaves r = rho - L u and its
 // (max |r|, sum r^2 h^D) per workgroup at partial[part0 + workgroup]
 template <int D, int N, typename T>
-__global__ __launch_bounds__(256) void k_vfinal(LevelArgs<T> a, double *partial, int64_t part0, double hD) {
+__global__ __launch_bounds__((opw<D, N>())) void k_vfinal(LevelArgs<T> a, double *partial, int64_t part0, double hD) {
     using G = Geo<D, N>;
-    constexpr int NW = 256 / 64;
-    __shared__ T sm[G::BPW * G::PC];
-    __shared__ T sme[G::BPW * G::PC];
+    constexpr int NW = opw<D, N>() / 64;
+    __shared__ T sm[opw<D, N>() / G::TPB * G::PC];
+    __shared__ T sme[opw<D, N>() / G::TPB * G::PC];
     __shared__ double red_m[NW], red_s[NW];
-    const Slot<D, N> sl = slot_of<D, N>(a.b0, a.nb, a.no_remap == 0);
+    const Slot<D, N> sl = slot_of<D, N, opw<D, N>()>(a.b0, a.nb, a.no_remap == 0);
     T *s = sm + sl.slot * G::PC, *se = sme + sl.slot * G::PC;
     const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const size_t bo = (size_t)sl.b * G::C;
@@ -4033,8 +4034,9 @@ template <int D, int N, typename T>
 void launch_final(const LevelArgs<T> &a, double *partial, int64_t part0, double hD, float *rout, int wg,
                   hipStream_t st) {
     if (a.opk) {
+        constexpr int OW = opw<D, N>();
         if constexpr (sizeof(T) == 8)
-            AFMG_LAUNCH((k_vfinal<D, N, T>), (wg_count<D, N, 256>(a.nb)), st, a, partial, part0, hD);
+            AFMG_LAUNCH_W((k_vfinal<D, N, T>), (wg_count<D, N, OW>(a.nb)), OW, st, a, partial, part0, hD);
         return;
     }
     constexpr int TPB = Geo<D, N>::TPB;

@@ -252,7 +252,8 @@ void compute_partials(afmg_tree *t) {
     for (int l = h.lmax; l >= 1; l--) {
         t->part_off[(size_t)l] = n;
         if (l >= 2 || h.level1_leaf) {
-            const int wg = t->shapes[0][SK_FINAL][(size_t)l].wg;
+            // (trees with an operator: the operator kernels' workgroups)
+            const int wg = t->opk ? op_wg(h.dim, h.N) : t->shapes[0][SK_FINAL][(size_t)l].wg;
             AFMG_BOX_DISPATCH(h, n += final_wgs_d, (h.level_count(l), wg));
             AFMG_BOX_DISPATCH(h, nmax += final_wgs_d, (h.level_count(l), 64));
         }
@@ -1672,9 +1673,9 @@ int apply_schemes(afmg_tree *t) {
     if (opk) {
         for (auto &pk : t->shapes)
             for (auto &v : pk) v.assign((size_t)h.lmax + 2, Shape{});
-        compute_partials(t);
         t->tune_epoch++;
     }
+    compute_partials(t);  // the norm partials follow the final kernel's workgroups
     return AFMG_OK;
 }
 
