@@ -77,10 +77,11 @@ enum class Op { GSRB, RESID_RESTRICT, COARSE_RHS, PROLONG, RESTRICT_RHO };
 
 // Modes of the coarse kernel.  Levels <= 1: V_FROM_2 (level 1 right after
 // the restriction from level 2), V_TOP1 (V-cycle from level 1), FMG.
-// Levels <= 2 (the 2^D boxes of level 2 as one grid): V2_FROM_3 (level 2
-// right after the restriction from level 3: FAS right-hand side, then the
-// V-cycle from level 2), V2_TOP (V-cycle from level 2).  A tree without the
-// levels a mode assumes takes the mode that fits it.
+// Levels <= 2 (the 2^D boxes of level 2 as one grid; only where
+// coarse_kernel_level2() holds): V2_FROM_3 (level 2 right after the
+// restriction from level 3: FAS right-hand side, then the V-cycle from level
+// 2), V2_TOP (V-cycle from level 2).  A tree without the levels a mode
+// assumes takes the mode that fits it.
 enum { COARSE_V_FROM_2 = 0, COARSE_V_TOP1 = 1, COARSE_FMG = 2, COARSE_V2_FROM_3 = 3, COARSE_V2_TOP = 4 };
 
 // Arguments of the coarse kernel: one workgroup per tree, whose root is box

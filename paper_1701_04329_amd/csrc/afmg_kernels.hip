@@ -3521,10 +3521,25 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse_gen(CoarseGenArgs<T> a) {
     // calls), else in the caller's scratch
     extern __shared__ double gen_lds[];
     double *ws = a.in_lds ? gen_lds : a.ws;
-    GenState<D, N> st{a.info, ws, ws + (size_t)R * GG::TOT, ws + (size_t)2 * R * GG::TOT,
+    // with the grids in LDS, the roots' box records and x indices follow
+    // them there (every cell's neighbour lookup reads them)
+    const BoxInfo *info = a.info;
+    const int32_t *bx = a.bx;
+    if (a.in_lds) {
+        BoxInfo *li = reinterpret_cast<BoxInfo *>(gen_lds + (size_t)R * (5 * GG::TOT + GG::BTOT));
+        int32_t *lx = reinterpret_cast<int32_t *>(li + R);
+        for (int e = threadIdx.x; e < R; e += blockDim.x) {
+            li[e] = a.info[e];
+            if (a.bx) lx[e] = a.bx[e];
+        }
+        info = li;
+        if (a.bx) bx = lx;
+        __syncthreads();
+    }
+    GenState<D, N> st{info, ws, ws + (size_t)R * GG::TOT, ws + (size_t)2 * R * GG::TOT,
                       ws + (size_t)3 * R * GG::TOT, ws + (size_t)4 * R * GG::TOT, R, a.homog,
                       a.n_down, a.n_up, a.n_base,
-                      ws + (size_t)4 * R * GG::TOT + (size_t)R * GG::BTOT, a.bx, a.opk, a.dnbr};
+                      ws + (size_t)4 * R * GG::TOT + (size_t)R * GG::BTOT, bx, a.opk, a.dnbr};
     const int mode = a.mode;
     // level 1 from the roots' boxes (colour-split in the tree's arrays), the
     // coarser grids start at zero
@@ -4102,7 +4117,8 @@ void launch_coarse_gen(const CoarseGenArgs<T> &a, hipStream_t st) {
     // with 8^3 cells, 3.8 KB in 2D); on the 3D eps-jump solve 162 against
     // 192 us per call with the grids in global memory
     constexpr size_t LDS_GEN_MAX = 64 * 1024;
-    const size_t bytes = sizeof(double) * coarse_gen_doubles<D, N>(a.n_roots);
+    const size_t bytes = sizeof(double) * coarse_gen_doubles<D, N>(a.n_roots) +
+                         (sizeof(BoxInfo) + sizeof(int32_t)) * (size_t)a.n_roots;
     CoarseGenArgs<T> b = a;
     b.in_lds = bytes <= LDS_GEN_MAX ? 1 : 0;
     hipLaunchKernelGGL((k_coarse_gen<D, N, T>), dim3(1), dim3(COARSE_NT), b.in_lds ? bytes : 0, st, b);
