@@ -1112,6 +1112,7 @@ def main():
     solve_level = {
         "v_cycles": int(np.median(cycles)),
         "byte_model_bytes": bm,
+        "library_bytes_model": st64.get("bytes_model"),
         "byte_model_GBs": round(bm / (ms * 1e-3) / 1e9, 1),
         "byte_model_frac": round(bm / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
         "hbm_bytes_measured": hbm,

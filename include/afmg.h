@@ -126,6 +126,9 @@ typedef struct {
     double t_ms;      /* device time from first kernel to last norm */
     double prof_ms[AFMG_PROF_KINDS]; /* summed kernel time per class */
     int prof_n[AFMG_PROF_KINDS];     /* launches per class */
+    double bytes_model;  /* algorithmic HBM bytes of the solve (afmg_solve_bytes_model
+                            with the cycles run); FP64 solves of one tree with
+                            the Laplacian, else 0 */
 } afmg_stats;
 
 typedef struct {
@@ -383,6 +386,21 @@ int afmg_tree_box(const afmg_tree *tree, int64_t box, afmg_box_desc *out);
 
 /* Device workspace bytes afmg_solve needs for these options. */
 int afmg_workspace_bytes(const afmg_tree *tree, const afmg_opts *opts, size_t *bytes);
+
+/* Algorithmic HBM bytes of an FP64 solve of this tree with the Laplacian
+   (paper §3.2's cycle): every array a kernel of the solve reads or writes,
+   counted once per launch over the scheduler's launch sequence, with
+   v_cycles V-cycles after the FMG cycle (opts->cycle FMG) or from the
+   initial guess.  Per cell of a level (s = 8 B, D the dimension): half sweep
+   1.5 s; residual + restriction 2 s + 2 s / 2^D; FAS right-hand side + copy
+   4 s (parents' level); prolongation + correction 2 s + 2 s / 2^D; the
+   end-of-cycle pass 2 s + s / 2^D on leaves, s + s / 2^D on parents; the
+   coarse kernel 4 s per cell of the coarsest level it loads (2, or 1 where
+   level 2 runs box by box); layout conversions 2 s and fills s; the ghosts
+   read from neighbouring boxes are not counted.  stats.bytes_model reports it
+   for the solve's cycle count.  Host-only.  Errors: AFMG_ERR_ARG (null, a
+   tree with an operator or a batch's forest, v_cycles < 0). */
+int afmg_solve_bytes_model(const afmg_tree *tree, const afmg_opts *opts, int v_cycles, double *bytes);
 
 /*
  * Solve lap_h(u) = rho (paper §3, eq. mg-discr-equation) on the tree.

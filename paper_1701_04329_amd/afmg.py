@@ -62,6 +62,7 @@ class Stats(C.Structure):
         ("t_ms", C.c_double),
         ("prof_ms", C.c_double * 4),
         ("prof_n", C.c_int * 4),
+        ("bytes_model", C.c_double),
     ]
 
     def to_dict(self):
@@ -69,7 +70,7 @@ class Stats(C.Structure):
         return dict(status=self.status, cycles=self.cycles, r0_max=self.r0_max, r0_l2=self.r0_l2,
                     r_max=self.r_max, r_l2=self.r_l2, hist_max=np.array(self.hist_max[:n]),
                     hist_l2=np.array(self.hist_l2[:n]), t_ms=self.t_ms,
-                    prof_ms=list(self.prof_ms), prof_n=list(self.prof_n))
+                    prof_ms=list(self.prof_ms), prof_n=list(self.prof_n), bytes_model=self.bytes_model)
 
 
 class TreeDesc(C.Structure):
@@ -144,6 +145,7 @@ EXPORTS = [
     "afmg_batch_set_shape", "afmg_tree_refine", "afmg_tree_finalize", "afmg_tree_level_list", "afmg_step",
     "afmg_solve_noalloc", "afmg_tree_create_domain", "afmg_tree_set_operator", "afmg_tree_adapt",
     "afmg_transfer_workspace_bytes", "afmg_tree_transfer", "afmg_tree_set_ghost_scheme",
+    "afmg_solve_bytes_model",
 ]
 # operators (paper §3.4, §3.5) and prolongations of afmg_tree_set_operator
 OPERATORS = {"laplacian": 0, "eps": 1, "cyl": 2, "cyl_eps": 3}
@@ -185,6 +187,7 @@ def lib():
         L.afmg_tree_bfaces.argtypes = [vp, i32p]
         L.afmg_tree_box.argtypes = [vp, i64, C.POINTER(BoxDesc)]
         L.afmg_workspace_bytes.argtypes = [vp, C.POINTER(Opts), C.POINTER(C.c_size_t)]
+        L.afmg_solve_bytes_model.argtypes = [vp, C.POINTER(Opts), C.c_int, C.POINTER(C.c_double)]
         L.afmg_solve.argtypes = [vp, vp, vp, vp, vp, vp, C.c_size_t, C.POINTER(Opts), C.POINTER(Stats)]
         L.afmg_solve_noalloc.argtypes = [vp, vp, vp, vp, vp, C.POINTER(Opts), C.POINTER(Stats)]
         L.afmg_last_error.restype = C.c_char_p
@@ -409,6 +412,14 @@ class Tree(_Shapes):
         n = C.c_size_t()
         _check(lib().afmg_workspace_bytes(self._h, C.byref(opts) if opts is not None else None, C.byref(n)))
         return n.value
+
+    def bytes_model(self, v_cycles, opts=None):
+        """Algorithmic HBM bytes of an FP64 solve with v_cycles V-cycles
+        (after the FMG cycle when opts.cycle is FMG); host-only."""
+        b = C.c_double()
+        _check(lib().afmg_solve_bytes_model(self._h, C.byref(opts) if opts is not None else None, v_cycles,
+                                            C.byref(b)))
+        return b.value
 
     # ---- marshalling between the caller's leaf order and box order ---------
     def leaf_to_boxes(self, leaf_field):

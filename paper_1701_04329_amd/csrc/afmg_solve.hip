@@ -182,6 +182,60 @@ bool coarse_general(const HostTree &h) { return h.general; }
 // cells), else 3 (level 2 inside the coarse kernel).
 int box_lo(const HostTree &h) { return (h.general || !coarse_kernel_level2(h.dim, h.N)) ? 2 : 3; }
 
+// The byte model of one FP64 solve with the Laplacian (see
+// afmg_solve_bytes_model): every array a kernel touches, once per launch,
+// over the launch sequence of Cycler::fmg / vcycle and Solver.
+double solve_bytes_model(const HostTree &h, int v_cycles, bool fmg, int n_down, int n_up) {
+    const double s = 8.0, r = 1.0 / (double)(1 << h.dim), C = (double)cells_per_box(h.dim, h.N);
+    std::vector<double> all((size_t)h.lmax + 2, 0.0), leaf((size_t)h.lmax + 2, 0.0);
+    for (const BoxInfo &bi : h.info) {
+        if (bi.level < 1) continue;
+        all[(size_t)bi.level] += C;
+        if (bi.flags & FLAG_LEAF) leaf[(size_t)bi.level] += C;
+    }
+    double n_all = 0.0, n_leaf = 0.0;
+    int lmin_leaf = h.lmax;
+    for (int l = 1; l <= h.lmax; l++) {
+        n_all += all[(size_t)l];
+        n_leaf += leaf[(size_t)l];
+        if (leaf[(size_t)l] > 0.0 && l < lmin_leaf) lmin_leaf = l;
+    }
+    const int lo = box_lo(h);
+    auto finalize = [&](int lfirst) {
+        double b = 0.0;
+        for (int l = std::max(1, lfirst); l <= h.lmax; l++) {
+            if (l == 1 && leaf[1] == 0.0) continue;
+            b += leaf[(size_t)l] * (2 * s + s * r) + (all[(size_t)l] - leaf[(size_t)l]) * (s + s * r);
+        }
+        return b;
+    };
+    const double coarse = 4 * s * all[(size_t)(lo == 3 && h.lmax >= 2 ? 2 : 1)];
+    auto vcycle = [&](int top) {
+        if (top < lo) return coarse;
+        double b = 0.0;
+        for (int l = top; l >= lo; l--) {
+            b += 2 * n_down * 1.5 * s * all[(size_t)l] + (2 * s + 2 * s * r) * all[(size_t)l];
+            if (l - 1 >= lo) b += 4 * s * all[(size_t)l - 1];
+        }
+        b += coarse;
+        for (int l = lo; l <= top; l++) b += (2 * s + 2 * s * r) * all[(size_t)l] + 2 * n_up * 1.5 * s * all[(size_t)l];
+        return b;
+    };
+    double b = 2 * s * n_leaf + s * n_all + finalize(1);  // rho layout, u = 0, initial residual
+    if (fmg) {
+        for (int l = 2; l <= h.lmax; l++) b += (s + s * r) * all[(size_t)l];  // rho restricted down
+        b += coarse;
+        for (int l = 2; l <= h.lmax; l++) {
+            if (l < h.lmax) b += 2 * s * all[(size_t)l];  // the copy v'
+            b += (2 * s + 2 * s * r) * all[(size_t)l] + vcycle(l);
+        }
+        b += finalize(lmin_leaf);
+    }
+    b += v_cycles * (vcycle(h.lmax) + finalize(lmin_leaf));
+    b += 2 * s * n_all;  // layout conversion of u on return
+    return b;
+}
+
 // bytes of the general coarse kernel's grids (0 where it is not used)
 size_t coarse_gen_bytes(const HostTree &h) {
     if (!coarse_general(h)) return 0;
@@ -1080,6 +1134,9 @@ int solve(afmg_tree *t, hipStream_t st, const double *rho, const double *bc, dou
     int status = AFMG_OK;
     for (int i = 0; i < n; i++) {
         S[i].t_ms = ms;
+        S[i].bytes_model = (!t->forest && !t->opk && !mixed)
+                               ? solve_bytes_model(h, S[i].cycles, o.cycle == AFMG_CYCLE_FMG_V, o.n_down, o.n_up)
+                               : 0.0;
         if (S[i].status < 0 && status >= 0) status = S[i].status;
         if (S[i].status == AFMG_NOT_CONVERGED && status == AFMG_OK) status = AFMG_NOT_CONVERGED;
     }
@@ -1974,6 +2031,16 @@ int afmg_workspace_bytes(const afmg_tree *t, const afmg_opts *o, size_t *bytes) 
         if (rc != AFMG_OK) return rc;
     }
     *bytes = ws_layout(t, o ? o->precision : AFMG_FP64).total;
+    return AFMG_OK;
+}
+
+int afmg_solve_bytes_model(const afmg_tree *t, const afmg_opts *opts, int v_cycles, double *bytes) {
+    if (!t || !bytes || v_cycles < 0) return fail(AFMG_ERR_ARG, "null argument or negative cycle count");
+    if (t->forest || t->opk) return fail(AFMG_ERR_ARG, "the byte model covers one tree with the Laplacian");
+    afmg_opts o;
+    afmg_default_opts(&o);
+    if (opts) o = *opts;
+    *bytes = solve_bytes_model(t->h, v_cycles, o.cycle == AFMG_CYCLE_FMG_V, o.n_down, o.n_up);
     return AFMG_OK;
 }
 

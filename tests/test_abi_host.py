@@ -427,3 +427,33 @@ def test_general_domain_validation():
     # the plain constructor keeps one level-1 box
     with pytest.raises(A.AfmgError):
         A.Tree(2, level, idx)
+
+
+def test_solve_bytes_model_matches_the_documented_model():
+    """afmg_solve_bytes_model (host-only) equals the byte model bench.py
+    documents (every array a kernel touches once per launch, the scheduler's
+    launch sequence) on uniform and adaptive trees, FMG and V cycles; with
+    16^3-cell boxes level 2 runs box by box, which the model follows."""
+    import bench
+    cases = [W.config2(res=64), W.config1(),
+             W.adaptive_small(3, 8, 5, 1e-3, 6, n_src=2, sigma_range=(0.04, 0.08)),
+             W.adaptive_small(2, 8, 7, 1e-3, 5, n_src=2, sigma_range=(0.03, 0.06))]
+    for w in cases:
+        t = A.Tree(w.dim, w.level, w.idx)
+        for cyc, fmg in (("FMG", True), ("V", False)):
+            for n in (0, 3, 8):
+                assert t.bytes_model(n, A.make_opts(cycle=cyc)) == bench.solve_byte_model(t, n, fmg), (w.name, cyc, n)
+    # every V-cycle adds the same amount
+    t = A.Tree(3, *W.uniform_leaves(3, 4))
+    b = [t.bytes_model(n) for n in range(4)]
+    assert b[1] - b[0] == b[2] - b[1] == b[3] - b[2] > 0
+    # the same uniform grid on 16^3-cell boxes: the same grids and kernels per
+    # V-cycle (level 2 of the 16^3 tree runs box by box like level 3 of the
+    # 8^3 one), so the same bytes per cycle
+    t16 = A.Tree(3, *W.uniform_leaves(3, 3), box_n=16)
+    t8 = A.Tree(3, *W.uniform_leaves(3, 4))
+    assert t16.n_unknowns == t8.n_unknowns
+    assert t16.bytes_model(1) - t16.bytes_model(0) == t8.bytes_model(1) - t8.bytes_model(0)
+    with pytest.raises(A.AfmgError):
+        t.bytes_model(-1)
+

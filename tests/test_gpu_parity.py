@@ -154,6 +154,23 @@ def test_box_sizes_give_the_same_uniform_solve():
     assert np.abs(g16 - g8).max() <= 1e-12 * np.abs(g8).max()
 
 
+def test_stats_report_the_byte_model():
+    """stats.bytes_model of an FP64 solve equals afmg_solve_bytes_model with
+    the cycles run; mixed-precision solves report 0 (not modelled)."""
+    from paper_1701_04329_amd import afmg as A
+    w = get("a3")
+    t = A.Tree(w.dim, w.level, w.idx)
+    dev = torch.device("cuda", 0)
+    rho = t.leaf_to_boxes(torch.tensor(w.rho, device=dev))
+    bc = t.bc_rows(torch.tensor(w.bc, device=dev))
+    for cyc in ("FMG", "V"):
+        announce(f"byte model {cyc}")
+        _, st = A.solve(t, rho, bc, None, cycle=cyc, tol=1e-10)
+        assert st["bytes_model"] == t.bytes_model(st["cycles"], A.make_opts(cycle=cyc)) > 0
+    _, st = A.solve(t, rho, bc, None, cycle="FMG", tol=1e-10, precision="mixed")
+    assert st["bytes_model"] == 0.0
+
+
 def test_warm_start_matches_oracle():
     w = get("a3")
     rng = np.random.default_rng(5)
