@@ -98,3 +98,33 @@ def test_noalloc_argument_errors():
     u_ref, _ = A.solve(t, rho, bc, fixed_cycles=2)
     rc, _ = A.solve_noalloc(t, rho, bc, u, fixed_cycles=2)
     assert rc == A.AFMG_OK and torch.equal(u, u_ref)
+
+
+def test_noalloc_box16_and_operator_trees():
+    """Boxes of 16^D cells, then a smaller tree with the paper's cylindrical
+    variable-coefficient operator (§3.4, §3.5; its general coarse kernel keeps
+    its grids in the workspace when they leave LDS) through the scratch
+    array: bitwise afmg_solve's solution and statistics on both calls."""
+    from paper_1701_04329_amd import afmg as A
+    dev = torch.device("cuda", 0)
+    a = W.adaptive_small(3, 16, 4, 1e-3, 6, n_src=2, sigma_range=(0.04, 0.08))
+    c = W.case2_workload(lmax=7)
+    assert c.n_unknowns < a.n_unknowns
+    t1 = A.Tree(3, a.level, a.idx, box_n=16)
+    t2 = A.Tree(2, c.level, c.idx)
+    t2.set_operator("cyl_eps", t2.leaf_to_boxes(torch.tensor(c.eps, device=dev)).contiguous())
+    for call, (t, w) in enumerate(((t1, a), (t2, c))):
+        announce(f"noalloc call {call} {w.name} box_n={t.box_n} unknowns={w.n_unknowns}")
+        t.finalize()
+        assert t.workspace_bytes(A.make_opts()) <= A.SCRATCH_BYTES
+        rho = t.leaf_to_boxes(torch.tensor(w.rho, device=dev))
+        bc = t.bc_rows(torch.tensor(w.bc, device=dev)) if t.n_bfaces else None
+        u_ref, s_ref = A.solve(t, rho, bc, cycle="FMG", tol=1e-10)
+        u = torch.full_like(rho, float("nan"))
+        rc, st = A.solve_noalloc(t, rho, bc, u, cycle="FMG", tol=1e-10)
+        torch.cuda.synchronize()
+        assert rc == s_ref["rc"] == A.AFMG_OK
+        assert torch.equal(u, u_ref), float((u - u_ref).abs().max())
+        assert st["cycles"] == s_ref["cycles"] and st["status"] == s_ref["status"]
+        assert np.array_equal(st["hist_max"], s_ref["hist_max"])
+        assert st["r0_max"] == s_ref["r0_max"] and st["r_max"] == s_ref["r_max"]
