@@ -1414,6 +1414,186 @@ __global__ __launch_bounds__((opw<D, N>())) void k_vgsrb(LevelArgs<T> a, int col
     for (int m = 0; m < HN; m++) a.u[bo + own0 + m] = out[m];
 }
 
+// The same half sweep with one row of a box per thread, in the Laplacian
+// half sweep's form: only the other colour of u and of eps is staged in LDS
+// (the cells of one colour have only the other colour as neighbours), the
+// updated colour's eps, right-hand side and, next to physical or refinement
+// sides, old values stay in registers, and each thread fetches the ghosts
+// of u and of eps across the sides of its own cells.  Face weights, the
+// cylindrical factors and the order of the sum over sides (-x, +x, -y, +y,
+// -z, +z) are those of op_sum, and the ghosts those of the staging helpers
+// (eps across a physical side: the face cell's own).  Default refinement
+// ghosts only: the bilinear scheme reads cells of both colours and runs
+// k_vgsrb.
+template <int D, int N, typename T, int W>
+__global__ __launch_bounds__(W) void k_vgsrb_row(LevelArgs<T> a, int colour) {
+    using G = Geo<D, N>;
+    constexpr int HN = G::HN;
+    __shared__ T so[(W / G::TPB) * oblock<D, N>()];
+    __shared__ T soe[(W / G::TPB) * oblock<D, N>()];
+    const Slot<D, N> sl = slot_of<D, N, W>(a.b0, a.nb, a.no_remap == 0, colour == 1);
+    T *s = so + sl.slot * oblock<D, N>();
+    T *se = soe + sl.slot * oblock<D, N>();
+    const BoxInfo bi = load_box<D, N>(a.info, sl.b);
+    const size_t bo = (size_t)sl.b * G::C;
+    const int r = sl.t;
+    int j, k;
+    row_of<D, N>(r, j, k);
+    const int p = (colour + D + j + k) & 1;  // x parity of the updated cells in this row
+    const int own0 = colour * G::HALF + r * HN, oth0 = (1 - colour) * G::HALF + r * HN;
+    const bool eps = a.opk & OPK_EPS, cyl = a.opk & OPK_CYL;
+    T rr[HN], ow[HN], eo[HN], gy[HN], gz[HN], ey[HN], ez[HN];
+    T gx = T(0), ex = T(0);
+    int vx = 0, vy = 0, vz = 0;
+#pragma unroll
+    for (int m = 0; m < HN; m++) {
+        ow[m] = T(0);
+        eo[m] = T(1);
+        gy[m] = gz[m] = ey[m] = ez[m] = T(0);
+    }
+    // padding slots (sl.b clamped to a valid box) load too
+    {
+        T ot[HN], et[HN];
+#pragma unroll
+        for (int m = 0; m < HN; m++) ot[m] = a.u[bo + oth0 + m];
+#pragma unroll
+        for (int m = 0; m < HN; m++) rr[m] = a.rho[bo + own0 + m];
+        if (eps) {
+#pragma unroll
+            for (int m = 0; m < HN; m++) eo[m] = a.eps[bo + own0 + m];
+#pragma unroll
+            for (int m = 0; m < HN; m++) et[m] = a.eps[bo + oth0 + m];
+        }
+        // x ghost of the row end cell (side 0 when the row starts with this colour)
+        int dv;
+        if (p == 0) {
+            gx = ghost_raw<D, N, 0, T>(bi, r, a.u, a.bc, a.homog, vx);
+            if (eps) ex = ghost_raw<D, N, 0, T>(bi, r, a.eps, nullptr, 1, dv);
+        } else {
+            gx = ghost_raw<D, N, 1, T>(bi, r, a.u, a.bc, a.homog, vx);
+            if (eps) ex = ghost_raw<D, N, 1, T>(bi, r, a.eps, nullptr, 1, dv);
+        }
+        bool need_own = vx < 0;
+        // y / z ghosts: across a same-level side, one row of the neighbour's
+        // other colour (row j' = N-1-j, resp. k' = N-1-k); else per cell
+        const bool yrow = j == 0 || j == N - 1, zrow = D == 3 && (k == 0 || k == N - 1);
+        const bool yfast = bi.nbr[2] >= 0 && bi.nbr[3] >= 0;
+        const bool zfast = D == 3 && bi.nbr[4] >= 0 && bi.nbr[5] >= 0;
+        if (yfast && yrow) {
+            vy = bi.nbr[j == 0 ? 2 : 3];
+            const size_t o = (size_t)vy * G::C + oth0 + ((D == 3 ? N * k : 0) + (N - 1 - j) - r) * HN;
+#pragma unroll
+            for (int m = 0; m < HN; m++) gy[m] = a.u[o + m];
+            if (eps) {
+#pragma unroll
+                for (int m = 0; m < HN; m++) ey[m] = a.eps[o + m];
+            }
+        }
+        if (zfast && zrow) {
+            vz = bi.nbr[k == 0 ? 4 : 5];
+            const size_t o = (size_t)vz * G::C + oth0 + ((N - 1 - k) * N + j - r) * HN;
+#pragma unroll
+            for (int m = 0; m < HN; m++) gz[m] = a.u[o + m];
+            if (eps) {
+#pragma unroll
+                for (int m = 0; m < HN; m++) ez[m] = a.eps[o + m];
+            }
+        }
+        __asm__ volatile("" ::: "memory");
+        // (the coefficient ghost is the u ghost's cell in eps: a physical
+        // side reads an in-range value of box 0 and ignores it)
+        if (!yfast && yrow) {
+#pragma unroll
+            for (int m = 0; m < HN; m++) {
+                const int fm = (2 * m + p) + (D == 3 ? N * k : 0);
+                const T *pu, *pe;
+                if (j == 0) {
+                    pu = ghost_ptr<D, N, 2, T>(bi, fm, a.u, a.bc, a.homog, vy);
+                    pe = ghost_ptr<D, N, 2, T>(bi, fm, a.eps, nullptr, 1, vy);
+                } else {
+                    pu = ghost_ptr<D, N, 3, T>(bi, fm, a.u, a.bc, a.homog, vy);
+                    pe = ghost_ptr<D, N, 3, T>(bi, fm, a.eps, nullptr, 1, vy);
+                }
+                gy[m] = *pu;
+                if (eps) ey[m] = *pe;
+            }
+            need_own |= vy < 0;
+        }
+        if (D == 3 && !zfast && zrow) {
+#pragma unroll
+            for (int m = 0; m < HN; m++) {
+                const int fm = (2 * m + p) + N * j;
+                const T *pu, *pe;
+                if (k == 0) {
+                    pu = ghost_ptr<D, N, 4, T>(bi, fm, a.u, a.bc, a.homog, vz);
+                    pe = ghost_ptr<D, N, 4, T>(bi, fm, a.eps, nullptr, 1, vz);
+                } else {
+                    pu = ghost_ptr<D, N, 5, T>(bi, fm, a.u, a.bc, a.homog, vz);
+                    pe = ghost_ptr<D, N, 5, T>(bi, fm, a.eps, nullptr, 1, vz);
+                }
+                gz[m] = *pu;
+                if (eps) ez[m] = *pe;
+            }
+            need_own |= vz < 0;
+        }
+        if (need_own) {
+#pragma unroll
+            for (int m = 0; m < HN; m++) ow[m] = a.u[bo + own0 + m];
+        }
+#pragma unroll
+        for (int m = 0; m < HN; m++) s[m * G::TPB + r] = ot[m];
+        if (eps) {
+#pragma unroll
+            for (int m = 0; m < HN; m++) se[m * G::TPB + r] = et[m];
+        }
+    }
+    __syncthreads();
+    if (!sl.valid) return;
+    const T x0 = cyl ? box_x0<N, T>(a.bx, sl.b, a.h) : T(0);
+    const int fl = bi.flags;
+    const T h = a.h;
+    T out[HN];
+#pragma unroll
+    for (int m = 0; m < HN; m++) {
+        const int i = 2 * m + p;
+        T un[6], en[6];
+        un[0] = i > 0 ? s[oslot<D, N>(i - 1, j, k)] : gs_finish<D, N, 0, T>(s, gx, vx, ow[m], a.homog, i, j, k, fl, h);
+        un[1] = i < N - 1 ? s[oslot<D, N>(i + 1, j, k)] : gs_finish<D, N, 1, T>(s, gx, vx, ow[m], a.homog, i, j, k, fl, h);
+        un[2] = j > 0 ? s[oslot<D, N>(i, j - 1, k)] : gs_finish<D, N, 2, T>(s, gy[m], vy, ow[m], a.homog, i, j, k, fl, h);
+        un[3] = j < N - 1 ? s[oslot<D, N>(i, j + 1, k)] : gs_finish<D, N, 3, T>(s, gy[m], vy, ow[m], a.homog, i, j, k, fl, h);
+        if (D == 3) {
+            un[4] = k > 0 ? s[oslot<D, N>(i, j, k - 1)] : gs_finish<D, N, 4, T>(s, gz[m], vz, ow[m], a.homog, i, j, k, fl, h);
+            un[5] = k < N - 1 ? s[oslot<D, N>(i, j, k + 1)] : gs_finish<D, N, 5, T>(s, gz[m], vz, ow[m], a.homog, i, j, k, fl, h);
+        }
+        const T ec = eo[m];
+        if (eps) {
+            en[0] = i > 0 ? se[oslot<D, N>(i - 1, j, k)] : (vx == -1 ? ec : ex);
+            en[1] = i < N - 1 ? se[oslot<D, N>(i + 1, j, k)] : (vx == -1 ? ec : ex);
+            en[2] = j > 0 ? se[oslot<D, N>(i, j - 1, k)] : (vy == -1 ? ec : ey[m]);
+            en[3] = j < N - 1 ? se[oslot<D, N>(i, j + 1, k)] : (vy == -1 ? ec : ey[m]);
+            if (D == 3) {
+                en[4] = k > 0 ? se[oslot<D, N>(i, j, k - 1)] : (vz == -1 ? ec : ez[m]);
+                en[5] = k < N - 1 ? se[oslot<D, N>(i, j, k + 1)] : (vz == -1 ? ec : ez[m]);
+            }
+        }
+        const T rc = x0 + (T(i) + T(0.5)) * h;
+        T sum = T(0), d = T(0);
+#pragma unroll
+        for (int q = 0; q < 2 * D; q++) {
+            T w = T(1);
+            if (eps) w = T(2) * ec * en[q] / (ec + en[q]);
+            if (cyl && q < 2) w *= (x0 + T(i + q) * h) / rc;
+            sum += w * un[q];
+            d += w;
+        }
+        out[m] = (sum - a.h2 * rr[m]) / d;
+        // one cell's neighbours in registers at a time
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int m = 0; m < HN; m++) a.u[bo + own0 + m] = out[m];
+}
+
 // residual r = rho - L u on the boxes of level l; the parent's octant
 // receives the means of u and of r (volume means in the cylindrical form)
 template <int D, int N, typename T>
@@ -4007,7 +4187,10 @@ static void launch_level_op(Op op, const LevelArgs<T> &a, int colour, hipStream_
         constexpr int OW = opw<D, N>();
         const int go = wg_count<D, N, OW>(a.nb);
         switch (op) {
-        case Op::GSRB: AFMG_LAUNCH_W((k_vgsrb<D, N, T>), go, OW, st, a, colour); break;
+        case Op::GSRB:
+            if (a.opk & OPK_GHOST_BIL) AFMG_LAUNCH_W((k_vgsrb<D, N, T>), go, OW, st, a, colour);
+            else AFMG_LAUNCH((k_vgsrb_row<D, N, T, 256>), g, st, a, colour);
+            break;
         case Op::RESID_RESTRICT: AFMG_LAUNCH_W((k_vresid_restrict<D, N, T>), go, OW, st, a); break;
         case Op::COARSE_RHS: AFMG_LAUNCH_W((k_vcoarse_rhs<D, N, T>), go, OW, st, a); break;
         case Op::PROLONG:
