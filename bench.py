@@ -691,7 +691,7 @@ def operators_bench(args, A, torch, dev, stream):
     * eps3d: the 256^3 uniform octree of the headline workload with eps =
       100 in the octant [0, 1/2)^3 (a jump on a coarse-grid face on every
       level), FMG + V(2,2) to 1e-10 in FP64; roofline of the finest-level
-      half sweep k_vgsrb: 20 B per cell of the level algorithmically (other
+      half sweep k_vgsrb_row: 20 B per cell of the level algorithmically (other
       colour s/2, own rho s/2, own colour written s/2, eps of every cell s;
       s = 8 B)."""
     from oracle import oracle as O
@@ -766,7 +766,7 @@ def operators_bench(args, A, torch, dev, stream):
     ach = 20.0 * n_fine / (avg * 1e-3) / 1e9
     e3["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                       "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                      "kernel": "k_vgsrb<3,8,double> (finest level, one half sweep)",
+                      "kernel": "k_vgsrb_row<3,8,double,256> (finest level, one half sweep)",
                       "algorithmic_bytes_per_launch": 20.0 * n_fine, "avg_launch_ms": round(avg, 5),
                       "launches_timed": int(stp["prof_n"][0])}
     out["eps3d"] = e3

@@ -111,7 +111,7 @@ struct CoarseGenArgs {
     T *rho;
     T *uold;            // null when the tree has one level
     const double *bc;
-    double *ws;         // scratch of coarse_gen_doubles(n_roots) doubles
+    double *ws;         // scratch of coarse_gen_doubles(n_roots, opk) doubles
     int n_roots;
     int mode;           // COARSE_V_FROM_2, COARSE_V_TOP1 or COARSE_FMG
     int homog;
@@ -166,7 +166,7 @@ void launch_coarse(const CoarseArgs<T> &a, int n_trees, hipStream_t st);
 template <int D, int N, typename T>
 void launch_coarse_gen(const CoarseGenArgs<T> &a, hipStream_t st);
 template <int D, int N>
-size_t coarse_gen_doubles(int n_roots);
+size_t coarse_gen_doubles(int n_roots, int opk);
 template <int D, int N, typename T>
 void launch_permute(const BoxInfo *info, T *f, int64_t b0, int64_t nb, int to_split, int leaves_only,
                     hipStream_t st);

@@ -3321,6 +3321,8 @@ struct GenState {
     const int32_t *bx;     // x index of the boxes (roots first)
     int opk;               // operator (OPK_* bits)
     const int32_t *dnbr;   // OPK_PROLONG_LIN: roots' same-level boxes across edges and corners
+    double *WT;            // with an operator: the 2D side weights of every cell and their
+                           // sum, [2D + 1][root][TOT] (prep_weights)
 
     __device__ static double hgrid(int g) { return (double)(1 << g) / (double)N; }
     __device__ double *at(double *f, int r, int g) const { return f + (size_t)r * GG::TOT + GG::off(g); }
@@ -3372,25 +3374,45 @@ struct GenState {
     }
     // left edge (x = r) of root r's box on grid g (its grids cover one unit)
     __device__ double x0(int r, int g) const { return (double)(bx[r] - 1) * (double)GG::n(g) * hgrid(g); }
+    __device__ double *wt(int q, int r, int g) const { return WT + ((size_t)q * R + r) * GG::TOT + GG::off(g); }
+    // The side weights of the operator at every cell of every grid, and their
+    // sum, formed once per call (the coefficients do not change during it):
+    // w_s = 2 ec en / (ec + en) with eps, times (x of the face) / (x of the
+    // centre) on the x sides in the cylindrical form
+    __device__ void prep_weights() const {
+        for (int g = 0; g < GG::NG; g++) {
+            const int n = GG::n(g), NC = GG::cells(g);
+            const double h = hgrid(g);
+            const bool eps = opk & OPK_EPS, cyl = opk & OPK_CYL;
+            for (int e = threadIdx.x; e < R * NC; e += blockDim.x) {
+                const int r = e / NC, c = e % NC;
+                int i, j, k;
+                ijk(n, c, i, j, k);
+                const double ec = eps ? at(E, r, g)[c] : 1.0;
+                const double xl = cyl ? x0(r, g) : 0.0;
+                const double rc = xl + (i + 0.5) * h;
+                double d = 0.0;
+                for (int s = 0; s < 2 * D; s++) {
+                    double w = 1.0;
+                    if (eps) {
+                        const double en = eacross(r, g, s, i, j, k);
+                        w = 2.0 * ec * en / (ec + en);
+                    }
+                    if (cyl && s < 2) w *= (xl + (i + s) * h) / rc;
+                    wt(s, r, g)[c] = w;
+                    d += w;
+                }
+                wt(2 * D, r, g)[c] = d;
+            }
+        }
+        __syncthreads();
+    }
     // with the operator: sum over the sides of w_s f_s, dg = sum of w_s
     __device__ double osum(const double *f, int r, int g, int i, int j, int k, double &dg) const {
-        const double h = hgrid(g);
-        const bool eps = opk & OPK_EPS, cyl = opk & OPK_CYL;
-        const double ec = eps ? at(E, r, g)[cidx(GG::n(g), i, j, k)] : 1.0;
-        const double xl = cyl ? x0(r, g) : 0.0;
-        const double rc = xl + (i + 0.5) * h;
-        double sum = 0.0, d = 0.0;
-        for (int s = 0; s < 2 * D; s++) {
-            double w = 1.0;
-            if (eps) {
-                const double en = eacross(r, g, s, i, j, k);
-                w = 2.0 * ec * en / (ec + en);
-            }
-            if (cyl && s < 2) w *= (xl + (i + s) * h) / rc;
-            sum += w * across(f, r, g, s, i, j, k);
-            d += w;
-        }
-        dg = d;
+        const int c = cidx(GG::n(g), i, j, k);
+        double sum = 0.0;
+        for (int s = 0; s < 2 * D; s++) sum += wt(s, r, g)[c] * across(f, r, g, s, i, j, k);
+        dg = wt(2 * D, r, g)[c];
         return sum;
     }
     // h^2 (L f) at cell (i, j, k) of grid g
@@ -3705,8 +3727,12 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse_gen(CoarseGenArgs<T> a) {
     // them there (every cell's neighbour lookup reads them)
     const BoxInfo *info = a.info;
     const int32_t *bx = a.bx;
+    // grids, then (with an operator) the side weights: the layout of
+    // coarse_gen_doubles
+    const size_t ngrid = (size_t)R * (5 * GG::TOT + GG::BTOT);
+    const size_t nwt = a.opk ? (size_t)(2 * D + 1) * R * GG::TOT : 0;
     if (a.in_lds) {
-        BoxInfo *li = reinterpret_cast<BoxInfo *>(gen_lds + (size_t)R * (5 * GG::TOT + GG::BTOT));
+        BoxInfo *li = reinterpret_cast<BoxInfo *>(gen_lds + ngrid + nwt);
         int32_t *lx = reinterpret_cast<int32_t *>(li + R);
         for (int e = threadIdx.x; e < R; e += blockDim.x) {
             li[e] = a.info[e];
@@ -3719,7 +3745,7 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse_gen(CoarseGenArgs<T> a) {
     GenState<D, N> st{info, ws, ws + (size_t)R * GG::TOT, ws + (size_t)2 * R * GG::TOT,
                       ws + (size_t)3 * R * GG::TOT, ws + (size_t)4 * R * GG::TOT, R, a.homog,
                       a.n_down, a.n_up, a.n_base,
-                      ws + (size_t)4 * R * GG::TOT + (size_t)R * GG::BTOT, bx, a.opk, a.dnbr};
+                      ws + (size_t)4 * R * GG::TOT + (size_t)R * GG::BTOT, bx, a.opk, a.dnbr, ws + ngrid};
     const int mode = a.mode;
     // level 1 from the roots' boxes (colour-split in the tree's arrays), the
     // coarser grids start at zero
@@ -3782,6 +3808,7 @@ __global__ __launch_bounds__(COARSE_NT) void k_coarse_gen(CoarseGenArgs<T> a) {
         }
         __syncthreads();
     }
+    if (a.opk) st.prep_weights();
     if (mode == COARSE_V_FROM_2) {
         st.uold_crhs(0, false);
         st.vcycle(0);
@@ -4300,7 +4327,7 @@ void launch_coarse_gen(const CoarseGenArgs<T> &a, hipStream_t st) {
     // with 8^3 cells, 3.8 KB in 2D); on the 3D eps-jump solve 162 against
     // 192 us per call with the grids in global memory
     constexpr size_t LDS_GEN_MAX = 64 * 1024;
-    const size_t bytes = sizeof(double) * coarse_gen_doubles<D, N>(a.n_roots) +
+    const size_t bytes = sizeof(double) * coarse_gen_doubles<D, N>(a.n_roots, a.opk) +
                          (sizeof(BoxInfo) + sizeof(int32_t)) * (size_t)a.n_roots;
     CoarseGenArgs<T> b = a;
     b.in_lds = bytes <= LDS_GEN_MAX ? 1 : 0;
@@ -4331,8 +4358,9 @@ void launch_transfer(const BoxInfo *to_info, const BoxInfo *from_info, const int
 }
 
 template <int D, int N>
-size_t coarse_gen_doubles(int n_roots) {
-    return (size_t)n_roots * (5 * GenGeo<D, N>::TOT + GenGeo<D, N>::BTOT);
+size_t coarse_gen_doubles(int n_roots, int opk) {
+    using GG = GenGeo<D, N>;
+    return (size_t)n_roots * (5 * GG::TOT + GG::BTOT) + (opk ? (size_t)(2 * D + 1) * n_roots * GG::TOT : 0);
 }
 
 template <int D, int N, typename T>
@@ -4467,7 +4495,7 @@ void launch_lc3(double *out, double a, const double *x, double b, const double *
     AFMG_INST(D, N, double)                                                                                   \
     AFMG_INST(D, N, float)                                                                                    \
     template void launch_ir_update<D, N>(const BoxInfo *, double *, float *, int64_t, const int *, hipStream_t); \
-    template size_t coarse_gen_doubles<D, N>(int);                                                           \
+    template size_t coarse_gen_doubles<D, N>(int, int);                                                             \
     template void launch_restrict_field_op<D, N>(const BoxInfo *, double *, int64_t, int64_t, int,             \
                                                  const int32_t *, double, hipStream_t);                        \
     template void launch_check_positive<D, N>(const BoxInfo *, const double *, int64_t, int *, hipStream_t);  \

@@ -237,10 +237,10 @@ double solve_bytes_model(const HostTree &h, int v_cycles, bool fmg, int n_down, 
 }
 
 // bytes of the general coarse kernel's grids (0 where it is not used)
-size_t coarse_gen_bytes(const HostTree &h) {
+size_t coarse_gen_bytes(const HostTree &h, int opk) {
     if (!coarse_general(h)) return 0;
     size_t n = 0;
-    AFMG_BOX_DISPATCH(h, n = coarse_gen_doubles, (h.n_roots));
+    AFMG_BOX_DISPATCH(h, n = coarse_gen_doubles, (h.n_roots, opk));
     return sizeof(double) * n;
 }
 
@@ -262,7 +262,7 @@ WsLayout ws_layout(const afmg_tree *t, int precision) {
     L.rho_e = off; off = align256(off + (mixed ? nb * C * sizeof(float) : 0));
     L.uold_e = off; off = align256(off + (mixed ? nlt * C * sizeof(float) : 0));
     L.u = off; off = align256(off + (t->forest ? nb * C * sizeof(double) : 0));
-    L.cg = off; off = align256(off + coarse_gen_bytes(h));
+    L.cg = off; off = align256(off + coarse_gen_bytes(h, t->opk));
     L.total = off;
     return L;
 }
@@ -1171,7 +1171,7 @@ AdjLayout adj_layout(const afmg_tree *t) {
     const size_t np = (size_t)std::max<int64_t>(t->n_parts_max, DOT_WGS);
     L.partial = off; off = align256(off + np * 2 * sizeof(double));
     L.norm = off; off = align256(off + 2 * sizeof(double));
-    L.cg = off; off = align256(off + coarse_gen_bytes(h));
+    L.cg = off; off = align256(off + coarse_gen_bytes(h, t->opk));
     L.total = off;
     return L;
 }
