@@ -606,8 +606,9 @@ __global__ __launch_bounds__(W) void k_gsrb(LevelArgs<T> a, int colour) {
 // side is same-level or physical, and the neighbour ids come from the Morton
 // index, so that the ghost loads leave with the box's own loads instead of
 // waiting for the box table.  Boxes on the domain boundary fetch their
-// Dirichlet values b and the old values u1 of their own cells after the
-// barrier (ghost 2 b - u1).  Same arithmetic and order as k_gsrb.
+// Dirichlet values b (rows named by the box record, a scalar load issued
+// first) and the old values u1 of their own cells before the barrier as
+// well (ghost 2 b - u1).  Same arithmetic and order as k_gsrb.
 // Modes for a mixed-precision correction on a tree whose leaves all lie on
 // this level.  CUBE_ADD (its last half sweep): instead of storing the new
 // values, add e (the new values and the other colour's) to the FP64
@@ -634,6 +635,8 @@ __global__ __launch_bounds__(W) void k_gsrb_cube(LevelArgs<T> a, int colour) {
     const Slot<D, N> sl = slot_lvl<D, N, W, false>(a, colour == 1);
     T *s = so + sl.slot * oblock<D, N>();
     T *ub = a.u + (size_t)sl.b * G::C;
+    // the box record (boundary rows of Dirichlet sides), issued first
+    const BoxInfo bi = load_box<D, N>(a.info, sl.b);
     const int r = sl.t;
     int j, k;
     row_of<D, N>(r, j, k);
@@ -686,20 +689,10 @@ __global__ __launch_bounds__(W) void k_gsrb_cube(LevelArgs<T> a, int colour) {
             ft[m] = fb[oth0 + m];
         }
     }
-#pragma unroll
-    for (int m = 0; m < HN; m++) s[m * G::TPB + r] = ot[m];
-    __syncthreads();
-    if (!sl.valid) return;
-    if (qx >= 0) gx = so[qx * oblock<D, N>() + oslot<D, N>(p == 0 ? N - 1 : 0, j, k)];
-    if (qy >= 0) {
-#pragma unroll
-        for (int m = 0; m < HN; m++) gy[m] = so[qy * oblock<D, N>() + oslot<D, N>(2 * m + p, j == 0 ? N - 1 : 0, k)];
-    }
-    if (qz >= 0) {
-#pragma unroll
-        for (int m = 0; m < HN; m++) gz[m] = so[qz * oblock<D, N>() + oslot<D, N>(2 * m + p, j, k == 0 ? N - 1 : 0)];
-    }
-    // Dirichlet sides: ghost 2 b - u1 (b = 0 when homogeneous)
+    // Dirichlet sides: ghost 2 b - u1 (b = 0 when homogeneous).  The old
+    // values and the boundary values leave before the barrier; the box record
+    // they need is a scalar load, so its wait holds back none of the loads
+    // above
     const bool dx = vx < 0, dy = yrow && vy < 0, dz = zrow && vz < 0;
     T ow[HN], bx = T(0), by[HN], bz[HN];
 #pragma unroll
@@ -709,7 +702,6 @@ __global__ __launch_bounds__(W) void k_gsrb_cube(LevelArgs<T> a, int colour) {
         bz[m] = T(0);
     }
     if (dx || dy || dz) {
-        const BoxInfo bi = load_box<D, N>(a.info, sl.b);
         if (MODE != CUBE_OWN_ZERO) {
 #pragma unroll
             for (int m = 0; m < HN; m++) ow[m] = ub[own0 + m];
@@ -727,6 +719,19 @@ __global__ __launch_bounds__(W) void k_gsrb_cube(LevelArgs<T> a, int colour) {
                 for (int m = 0; m < HN; m++) bz[m] = br[2 * m];
             }
         }
+    }
+#pragma unroll
+    for (int m = 0; m < HN; m++) s[m * G::TPB + r] = ot[m];
+    __syncthreads();
+    if (!sl.valid) return;
+    if (qx >= 0) gx = so[qx * oblock<D, N>() + oslot<D, N>(p == 0 ? N - 1 : 0, j, k)];
+    if (qy >= 0) {
+#pragma unroll
+        for (int m = 0; m < HN; m++) gy[m] = so[qy * oblock<D, N>() + oslot<D, N>(2 * m + p, j == 0 ? N - 1 : 0, k)];
+    }
+    if (qz >= 0) {
+#pragma unroll
+        for (int m = 0; m < HN; m++) gz[m] = so[qz * oblock<D, N>() + oslot<D, N>(2 * m + p, j, k == 0 ? N - 1 : 0)];
     }
 #pragma unroll
     for (int m = 0; m < HN; m++) {
@@ -4177,10 +4182,9 @@ static void launch_level_wf(Op op, const LevelArgs<T> &a, int colour, hipStream_
         // the complete-level variant pays off where the level fits the GPU in
         // about one round of waves (latency-bound), and on every level in
         // FP32 (3D), where a box's loads are half as long; on larger FP64
-        // levels the post-barrier Dirichlet loads of its boundary boxes cost
-        // more than the shorter load chain saves (measured on 256^3: levels
-        // of 512 and 4096 boxes 4-10% faster; 32768 boxes 5% slower in FP64,
-        // 15% faster in FP32)
+        // levels it is no faster (measured on 256^3: levels of 512 and 4096
+        // boxes 4-10% faster; 32768 boxes 1-2% slower in FP64, 15% faster in
+        // FP32)
         // (the modes of a correction: the caller checked that the level is
         // complete and holds every leaf of the one tree)
         if (a.add_to)
