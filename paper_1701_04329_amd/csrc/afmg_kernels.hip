@@ -2663,21 +2663,30 @@ struct CoarseState {
         const int m = d == 0 ? j + n * k : d == 1 ? i + n * k : i + n * j;
         return bc[CG::boff(G) + side * F + m];
     }
-    // sum of the 2D neighbours of cell (i, j, k) of f on grid G
+    // sum of the 2D neighbours of cell (i, j, k) of f on grid G.  Every
+    // operand is fetched (a neighbour outside the grid at the cell's own
+    // index, the boundary value of each side) before one is selected, so
+    // that the LDS reads leave together instead of one branch at a time.
     template <int G>
     __device__ __forceinline__ double nbs(const double *f, int i, int j, int k) const {
         constexpr int n = CG::n(G);
         const double *g = f + CG::off(G);
         const int c = i + n * (j + n * k);
         const double uc = g[c];
-        const double xm = i > 0 ? g[c - 1] : 2.0 * bval<G>(0, i, j, k) - uc;
-        const double xp = i < n - 1 ? g[c + 1] : 2.0 * bval<G>(1, i, j, k) - uc;
-        const double ym = j > 0 ? g[c - n] : 2.0 * bval<G>(2, i, j, k) - uc;
-        const double yp = j < n - 1 ? g[c + n] : 2.0 * bval<G>(3, i, j, k) - uc;
+        const double vxm = g[i > 0 ? c - 1 : c], vxp = g[i < n - 1 ? c + 1 : c];
+        const double vym = g[j > 0 ? c - n : c], vyp = g[j < n - 1 ? c + n : c];
+        const double bxm = bval<G>(0, i, j, k), bxp = bval<G>(1, i, j, k);
+        const double bym = bval<G>(2, i, j, k), byp = bval<G>(3, i, j, k);
+        const double xm = i > 0 ? vxm : 2.0 * bxm - uc;
+        const double xp = i < n - 1 ? vxp : 2.0 * bxp - uc;
+        const double ym = j > 0 ? vym : 2.0 * bym - uc;
+        const double yp = j < n - 1 ? vyp : 2.0 * byp - uc;
         double s = (xm + xp) + (ym + yp);
         if (D == 3) {
-            const double zm = k > 0 ? g[c - n * n] : 2.0 * bval<G>(4, i, j, k) - uc;
-            const double zp = k < n - 1 ? g[c + n * n] : 2.0 * bval<G>(5, i, j, k) - uc;
+            const double vzm = g[k > 0 ? c - n * n : c], vzp = g[k < n - 1 ? c + n * n : c];
+            const double bzm = bval<G>(4, i, j, k), bzp = bval<G>(5, i, j, k);
+            const double zm = k > 0 ? vzm : 2.0 * bzm - uc;
+            const double zp = k < n - 1 ? vzp : 2.0 * bzp - uc;
             s = s + (zm + zp);
         }
         return s;
@@ -2821,18 +2830,17 @@ struct CoarseState {
     }
     // u - v' on grid G at (I, J, K) + s e_axis; outside the grid the ghost of
     // u minus the ghost of v' (the Dirichlet value cancels up to rounding)
+    // (the operands are fetched before the selection, as in nbs)
     template <int G>
     __device__ __forceinline__ double delta(int axis, int I, int J, int K, int s) const {
         constexpr int n = CG::n(G), o = CG::off(G);
         int a[3] = {I, J, K};
         a[axis] += s;
-        if (a[axis] >= 0 && a[axis] < n) {
-            const int c = a[0] + n * (a[1] + n * a[2]);
-            return u[o + c] - uold[o + c];
-        }
-        const int c = I + n * (J + n * K);
+        const bool in = a[axis] >= 0 && a[axis] < n;
+        const int c = in ? a[0] + n * (a[1] + n * a[2]) : I + n * (J + n * K);
+        const double uu = u[o + c], uo = uold[o + c];
         const double b = bval<G>(2 * axis + (s > 0 ? 1 : 0), I, J, K);
-        return (2.0 * b - u[o + c]) - (2.0 * b - uold[o + c]);
+        return in ? uu - uo : (2.0 * b - uu) - (2.0 * b - uo);
     }
     // u of grid G += P211(u - v' of grid G+1); with store_old, v' of grid G
     // first receives u (FMG)
@@ -3059,14 +3067,20 @@ struct Level2 {
             ijk(c, i, j, k);
             const int I = i >> 1, J = j >> 1, K = k >> 1;
             const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
+            // neighbours outside the root at the cell's own index, fetched
+            // before the selection (the reads leave together)
+            const bool ix = I + sx >= 0 && I + sx < N, iy = J + sy >= 0 && J + sy < N;
             const T dP = delta(fu, fo, I, J, K);
-            const T dx = (I + sx >= 0 && I + sx < N) ? delta(fu, fo, I + sx, J, K) : -dP;
-            const T dy = (J + sy >= 0 && J + sy < N) ? delta(fu, fo, I, J + sy, K) : -dP;
+            const T ex = delta(fu, fo, ix ? I + sx : I, J, K), ey = delta(fu, fo, I, iy ? J + sy : J, K);
+            const T dx = ix ? ex : -dP;
+            const T dy = iy ? ey : -dP;
             T v;
             if (D == 2) {
                 v = T(0.5) * dP + T(0.25) * dx + T(0.25) * dy;
             } else {
-                const T dz = (K + sz >= 0 && K + sz < N) ? delta(fu, fo, I, J, K + sz) : -dP;
+                const bool iz = K + sz >= 0 && K + sz < N;
+                const T ez = delta(fu, fo, I, J, iz ? K + sz : K);
+                const T dz = iz ? ez : -dP;
                 v = T(0.25) * (((dP + dx) + dy) + dz);
             }
             res[it] = val(i, j, k) + v;
