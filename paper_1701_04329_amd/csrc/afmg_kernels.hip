@@ -4233,8 +4233,15 @@ static void launch_level_op(Op op, const LevelArgs<T> &a, int colour, hipStream_
         const int go = wg_count<D, N, OW>(a.nb);
         switch (op) {
         case Op::GSRB:
-            if (a.opk & OPK_GHOST_BIL) AFMG_LAUNCH_W((k_vgsrb<D, N, T>), go, OW, st, a, colour);
-            else AFMG_LAUNCH((k_vgsrb_row<D, N, T, 256>), g, st, a, colour);
+            if (a.opk & OPK_GHOST_BIL) {
+                AFMG_LAUNCH_W((k_vgsrb<D, N, T>), go, OW, st, a, colour);
+            } else if constexpr (D == 2) {
+                // 2D levels are small and latency-bound: more, smaller
+                // workgroups (paper case 2: 6.39 against 6.57 ms with 256)
+                AFMG_LAUNCH_W((k_vgsrb_row<D, N, T, 64>), (wg_count<D, N, 64>(a.nb)), 64, st, a, colour);
+            } else {
+                AFMG_LAUNCH((k_vgsrb_row<D, N, T, 256>), g, st, a, colour);
+            }
             break;
         case Op::RESID_RESTRICT: AFMG_LAUNCH_W((k_vresid_restrict<D, N, T>), go, OW, st, a); break;
         case Op::COARSE_RHS: AFMG_LAUNCH_W((k_vcoarse_rhs<D, N, T>), go, OW, st, a); break;
