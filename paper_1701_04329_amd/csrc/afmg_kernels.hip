@@ -4233,15 +4233,18 @@ static void launch_level_op(Op op, const LevelArgs<T> &a, int colour, hipStream_
         const int go = wg_count<D, N, OW>(a.nb);
         switch (op) {
         case Op::GSRB:
-            if (a.opk & OPK_GHOST_BIL) {
-                AFMG_LAUNCH_W((k_vgsrb<D, N, T>), go, OW, st, a, colour);
-            } else if constexpr (D == 2) {
-                // 2D levels are small and latency-bound: more, smaller
-                // workgroups (paper case 2: 6.39 against 6.57 ms with 256)
-                AFMG_LAUNCH_W((k_vgsrb_row<D, N, T, 64>), (wg_count<D, N, 64>(a.nb)), 64, st, a, colour);
-            } else {
-                AFMG_LAUNCH((k_vgsrb_row<D, N, T, 256>), g, st, a, colour);
+            // the row form on large 3D levels; small levels are
+            // latency-bound, and there the staged box is faster (its LDS
+            // reads do not wait behind the ghost selection): 3D levels of 8
+            // to 512 boxes 5.6-6.0 against 7.3-7.6 us per launch, paper case
+            // 2 (2D) 6.07-6.13 against 6.53-6.63 ms
+            if constexpr (D == 3) {
+                if (!(a.opk & OPK_GHOST_BIL) && a.nb > 1024) {
+                    AFMG_LAUNCH((k_vgsrb_row<D, N, T, 256>), g, st, a, colour);
+                    break;
+                }
             }
+            AFMG_LAUNCH_W((k_vgsrb<D, N, T>), go, OW, st, a, colour);
             break;
         case Op::RESID_RESTRICT: AFMG_LAUNCH_W((k_vresid_restrict<D, N, T>), go, OW, st, a); break;
         case Op::COARSE_RHS: AFMG_LAUNCH_W((k_vcoarse_rhs<D, N, T>), go, OW, st, a); break;
