@@ -51,6 +51,11 @@ def cases():
                 "random"),
         "ep3": (3, W.domain_leaves(3, 8, [(1, 1, 1), (2, 1, 1)], 4, (1.98, 0.4, 0.6), periodic=(True, False, False)),
                 [P_, P_, N_, D_, D_, N_], "eps", "random"),
+        # a level of more than 1024 boxes (2048 at level 5), where the half
+        # sweep takes its row form, with refinement, Neumann and periodic sides
+        "ep3big": (3, W.domain_leaves(3, 8, [(1, 1, 1), (2, 1, 1)], 5, (1.0, 0.45, 0.55), 0.4,
+                                      periodic=(True, False, False)),
+                   [P_, P_, N_, D_, D_, N_], "eps", "random"),
         # boxes of 16^D cells
         "e3x16": (3, W.ball_leaves(3, 16, 3, c, 0.0, 1), None, "eps", "random"),
         "ce2x16": (2, W.ball_leaves(2, 16, 4, (0.25, 0.25), 0.02, 1), None, "cyl_eps", "jump"),
@@ -170,7 +175,7 @@ def close(what, got, ref, rel=STEP_REL):
     assert err <= rel, (what, err)
 
 
-STEP_NAMES = ["e2", "e3", "c2", "ce2", "eL2", "ep3", "e3x16", "ce2x16"]
+STEP_NAMES = ["e2", "e3", "c2", "ce2", "eL2", "ep3", "ep3big", "e3x16", "ce2x16"]
 
 
 @pytest.mark.parametrize("name", STEP_NAMES)
@@ -273,7 +278,7 @@ def test_operator_fixed_cycles_match_oracle(name, prolong):
         assert_norms_close(sg["hist_l2"], so["hist_l2"], 1e-12 * so["r0_l2"], what=(name, "history L2"))
 
 
-@pytest.mark.parametrize("name", ["e3", "ce2", "eL2", "e3x16", "ce2x16"])
+@pytest.mark.parametrize("name", ["e3", "ce2", "eL2", "ep3big", "e3x16", "ce2x16"])
 def test_operator_solve_to_tolerance_matches_oracle(name):
     ug, sg, uo, so = solve_pair(name, "default", 51, cycle="FMG", tol=1e-10, n_base=16, max_cycles=80)
     assert sg["status"] == 0 and so["status"] == 0, (sg["status"], so["status"])
