@@ -1456,6 +1456,10 @@ __global__ __launch_bounds__(W) void k_vgsrb_row(LevelArgs<T> a, int colour) {
         eo[m] = T(1);
         gy[m] = gz[m] = ey[m] = ez[m] = T(0);
     }
+    // ghosts across a side whose neighbour is a sibling in this workgroup
+    // come from its staged other colour of u and eps (as in k_gsrb; decided
+    // after the box's own loads are issued: it needs the box record)
+    int qx = -1, qy = -1, qz = -1;
     // padding slots (sl.b clamped to a valid box) load too
     {
         T ot[HN], et[HN];
@@ -1469,19 +1473,24 @@ __global__ __launch_bounds__(W) void k_vgsrb_row(LevelArgs<T> a, int colour) {
 #pragma unroll
             for (int m = 0; m < HN; m++) et[m] = a.eps[bo + oth0 + m];
         }
+        qx = sib_slot<D, N, W, 0>(p == 0 ? bi.nbr[0] : bi.nbr[1], sl, a.b0, a.nb);
+        qy = sib_slot<D, N, W, 1>(j == 0 ? bi.nbr[2] : bi.nbr[3], sl, a.b0, a.nb);
+        if (D == 3) qz = sib_slot<D, N, W, 2>(k == 0 ? bi.nbr[4] : bi.nbr[5], sl, a.b0, a.nb);
         // x ghost of the row end cell (side 0 when the row starts with this colour)
         int dv;
-        if (p == 0) {
-            gx = ghost_raw<D, N, 0, T>(bi, r, a.u, a.bc, a.homog, vx);
-            if (eps) ex = ghost_raw<D, N, 0, T>(bi, r, a.eps, nullptr, 1, dv);
-        } else {
-            gx = ghost_raw<D, N, 1, T>(bi, r, a.u, a.bc, a.homog, vx);
-            if (eps) ex = ghost_raw<D, N, 1, T>(bi, r, a.eps, nullptr, 1, dv);
+        if (qx < 0) {
+            if (p == 0) {
+                gx = ghost_raw<D, N, 0, T>(bi, r, a.u, a.bc, a.homog, vx);
+                if (eps) ex = ghost_raw<D, N, 0, T>(bi, r, a.eps, nullptr, 1, dv);
+            } else {
+                gx = ghost_raw<D, N, 1, T>(bi, r, a.u, a.bc, a.homog, vx);
+                if (eps) ex = ghost_raw<D, N, 1, T>(bi, r, a.eps, nullptr, 1, dv);
+            }
         }
         bool need_own = vx < 0;
         // y / z ghosts: across a same-level side, one row of the neighbour's
         // other colour (row j' = N-1-j, resp. k' = N-1-k); else per cell
-        const bool yrow = j == 0 || j == N - 1, zrow = D == 3 && (k == 0 || k == N - 1);
+        const bool yrow = (j == 0 || j == N - 1) && qy < 0, zrow = D == 3 && (k == 0 || k == N - 1) && qz < 0;
         const bool yfast = bi.nbr[2] >= 0 && bi.nbr[3] >= 0;
         const bool zfast = D == 3 && bi.nbr[4] >= 0 && bi.nbr[5] >= 0;
         if (yfast && yrow) {
@@ -1554,6 +1563,26 @@ __global__ __launch_bounds__(W) void k_vgsrb_row(LevelArgs<T> a, int colour) {
     }
     __syncthreads();
     if (!sl.valid) return;
+    if (qx >= 0) {
+        gx = so[qx * oblock<D, N>() + oslot<D, N>(p == 0 ? N - 1 : 0, j, k)];
+        if (eps) ex = soe[qx * oblock<D, N>() + oslot<D, N>(p == 0 ? N - 1 : 0, j, k)];
+    }
+    if (qy >= 0 && (j == 0 || j == N - 1)) {
+#pragma unroll
+        for (int m = 0; m < HN; m++) {
+            const int o = qy * oblock<D, N>() + oslot<D, N>(2 * m + p, j == 0 ? N - 1 : 0, k);
+            gy[m] = so[o];
+            if (eps) ey[m] = soe[o];
+        }
+    }
+    if (D == 3 && qz >= 0 && (k == 0 || k == N - 1)) {
+#pragma unroll
+        for (int m = 0; m < HN; m++) {
+            const int o = qz * oblock<D, N>() + oslot<D, N>(2 * m + p, j, k == 0 ? N - 1 : 0);
+            gz[m] = so[o];
+            if (eps) ez[m] = soe[o];
+        }
+    }
     const T x0 = cyl ? box_x0<N, T>(a.bx, sl.b, a.h) : T(0);
     const int fl = bi.flags;
     const T h = a.h;
